@@ -1,0 +1,21 @@
+"""Seeded synthetic gate-stack devices: the inputs both the solver and its checker consume.
+
+This package only lays out meshes, materials, doping, gate rectangles and
+contact voltages.  It holds none of the solver's arithmetic (no charge
+statistics, no discretisation, no physical constants).
+"""
+from .devices import (  # noqa: F401
+    Device,
+    stack_z,
+    make_stack_device,
+    double_dot_gates,
+    double_dot_device,
+    config1,
+    config2,
+    config3_spec,
+    config3_instance,
+    config4,
+    config5,
+    DOT_BOX_D1,
+    DOT_BOX_D2,
+)

@@ -1,0 +1,266 @@
+"""Seeded Si/SiO2 gate-stack devices on rectilinear Q1 hexahedral meshes.
+
+Layout conventions shared by every consumer:
+
+* nodes are numbered ``i + nx*(j + ny*k)`` (x fastest), elements
+  ``i + (nx-1)*(j + (ny-1)*k)``; coordinates are in nm;
+* z = 0 is the bottom (grounded substrate contact), z = z_max the top face
+  where the metal gates sit on the oxide;
+* per element: relative permittivity, a semiconductor flag and the net doping
+  N_D - N_A in nm^-3 (1 cm^-3 = 1e-21 nm^-3);
+* Dirichlet data: ``dir_id[node]`` is -1 for a free node, otherwise an index
+  into ``dir_val`` (volts); gates come first, the bottom contact last.
+
+The workloads mirror the paper's devices (a Si substrate under a 10 nm gate
+oxide with top depletion gates, Sec. III and IV); the real device layouts are
+not available, so every geometry here is synthetic and drawn from a seed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+EPS_SI = 11.7
+EPS_OX = 3.9
+BOX_XY_NM = 200.0
+SI_NM = 90.0
+OX_NM = 10.0
+NA_BULK_NM3 = 1e15 * 1e-21          # 1e15 cm^-3 acceptors, fully ionised
+SEED_BASE = 7561
+
+# Dot regions of the double-dot stack (x0, x1, y0, y1, z0, z1) in nm.
+DOT_BOX_D1 = (0.0, 60.0, 70.0, 130.0, 70.0, 90.0)
+DOT_BOX_D2 = (140.0, 200.0, 70.0, 130.0, 70.0, 90.0)
+
+
+@dataclass
+class Device:
+    name: str
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    eps_r: np.ndarray          # [E] float64
+    semi: np.ndarray           # [E] uint8
+    net_doping: np.ndarray     # [E] float64, nm^-3
+    dir_id: np.ndarray         # [N] int32
+    dir_val: np.ndarray        # [G] float64, V
+    contacts: list = field(default_factory=list)
+    stat: str = "fd"           # "linear" | "tf" | "fd"
+    T_K: float = 4.0
+    m_eff: float = 1.08
+    Ec0_eV: float = 0.56
+    boxes: dict = field(default_factory=dict)
+
+    @property
+    def nx(self):
+        return int(self.x.size)
+
+    @property
+    def ny(self):
+        return int(self.y.size)
+
+    @property
+    def nz(self):
+        return int(self.z.size)
+
+    @property
+    def n_nodes(self):
+        return self.nx * self.ny * self.nz
+
+    @property
+    def n_elems(self):
+        return (self.nx - 1) * (self.ny - 1) * (self.nz - 1)
+
+    def contact_index(self, name):
+        return self.contacts.index(name)
+
+
+def stack_z(n_ez, si_nm=SI_NM, ox_nm=OX_NM):
+    """Node z coordinates for ``n_ez`` element layers that put a node plane
+    exactly on the Si/SiO2 interface: the oxide gets max(1, round(n_ez*ox/total))
+    uniform layers, the silicon the rest."""
+    n_ox = max(1, int(round(n_ez * ox_nm / (si_nm + ox_nm))))
+    n_si = n_ez - n_ox
+    if n_si < 1:
+        raise ValueError("need at least two element layers")
+    z_si = np.linspace(0.0, si_nm, n_si + 1)
+    z_ox = np.linspace(si_nm, si_nm + ox_nm, n_ox + 1)[1:]
+    return np.concatenate([z_si, z_ox])
+
+
+def _bilinear(ctrl, pitch, xq, yq):
+    """Bilinear interpolation of a control grid with uniform pitch starting at 0."""
+    n = ctrl.shape[0]
+    fx = np.clip(xq / pitch, 0.0, n - 1 - 1e-12)
+    fy = np.clip(yq / pitch, 0.0, n - 1 - 1e-12)
+    i = np.floor(fx).astype(np.int64)
+    j = np.floor(fy).astype(np.int64)
+    tx = fx - i
+    ty = fy - j
+    # ctrl indexed [ix, iy]
+    return ((1 - tx) * (1 - ty) * ctrl[i, j] + tx * (1 - ty) * ctrl[i + 1, j]
+            + (1 - tx) * ty * ctrl[i, j + 1] + tx * ty * ctrl[i + 1, j + 1])
+
+
+def make_stack_device(name, x, y, z, gates, volts, stat="fd", T_K=4.0,
+                      m_eff=1.08, Ec0_eV=0.56, interface=None,
+                      net_doping_si=-NA_BULK_NM3, boxes=None,
+                      bottom_contact=True, gate_tol=1e-9):
+    """Lay out a Si substrate under an oxide with rectangular top gates.
+
+    gates:  list of (name, (x0, x1, y0, y1)) on the top face (closed rectangles)
+    volts:  gate voltages in the same order
+    interface: None for a flat interface at z = 90 nm, else a callable
+        (xc, yc) -> z_int; an element is oxide iff its centroid lies above it.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    nx, ny, nz = x.size, y.size, z.size
+    xc = 0.5 * (x[1:] + x[:-1])
+    yc = 0.5 * (y[1:] + y[:-1])
+    zc = 0.5 * (z[1:] + z[:-1])
+    ZC, YC, XC = np.meshgrid(zc, yc, xc, indexing="ij")     # [ez, ey, ex]
+    if interface is None:
+        zint = np.full_like(XC, SI_NM)
+    else:
+        zint = interface(XC, YC)
+    oxide = ZC > zint
+    semi = (~oxide).astype(np.uint8).ravel()
+    eps_r = np.where(oxide, EPS_OX, EPS_SI).ravel().astype(np.float64)
+    net = np.where(oxide, 0.0, net_doping_si).ravel().astype(np.float64)
+
+    dir_id = np.full(nx * ny * nz, -1, dtype=np.int32)
+    contacts = []
+    dir_val = []
+    top = nz - 1
+    Y2, X2 = np.meshgrid(y, x, indexing="ij")           # [j, i]
+    for g, (gname, (x0, x1, y0, y1)) in enumerate(gates):
+        inside = ((X2 >= x0 - gate_tol) & (X2 <= x1 + gate_tol)
+                  & (Y2 >= y0 - gate_tol) & (Y2 <= y1 + gate_tol))
+        jj, ii = np.nonzero(inside)
+        dir_id[ii + nx * (jj + ny * top)] = len(contacts)
+        contacts.append(gname)
+        dir_val.append(float(volts[g]))
+    if bottom_contact:
+        dir_id[: nx * ny] = len(contacts)
+        contacts.append("bottom")
+        dir_val.append(0.0)
+    return Device(name=name, x=x, y=y, z=z, eps_r=eps_r, semi=semi,
+                  net_doping=net, dir_id=dir_id,
+                  dir_val=np.asarray(dir_val, dtype=np.float64),
+                  contacts=contacts, stat=stat, T_K=T_K, m_eff=m_eff,
+                  Ec0_eV=Ec0_eV, boxes=dict(boxes or {}))
+
+
+def double_dot_gates():
+    """Five 40 nm wide gates with 30 nm gaps in a 200x200 nm footprint:
+    two plungers (P1, P2), a middle barrier (B2) between them and two long
+    barriers (B1 above, B3 below).  Voltages are drawn in the order
+    P1, P2, B1, B2, B3."""
+    return [
+        ("P1", (10.0, 50.0, 80.0, 120.0)),
+        ("P2", (150.0, 190.0, 80.0, 120.0)),
+        ("B1", (10.0, 190.0, 150.0, 190.0)),
+        ("B2", (80.0, 120.0, 80.0, 120.0)),
+        ("B3", (10.0, 190.0, 10.0, 50.0)),
+    ]
+
+
+def _uniform_xy(n):
+    return np.linspace(0.0, BOX_XY_NM, n)
+
+
+def config1():
+    """17x17x9 nodes, two top gates, Thomas-Fermi electrons at 0 K."""
+    rng = np.random.default_rng(SEED_BASE + 1)
+    volts = rng.uniform(0.5, 1.5, 2)
+    gates = [("G1", (30.0, 90.0, 50.0, 150.0)), ("G2", (110.0, 170.0, 50.0, 150.0))]
+    return make_stack_device("c1", _uniform_xy(17), _uniform_xy(17), stack_z(8),
+                             gates, volts, stat="tf", T_K=0.0,
+                             boxes={"D1": DOT_BOX_D1, "D2": DOT_BOX_D2})
+
+
+def double_dot_device(name, nx, ny, nz, volts, stat="fd", T_K=4.0):
+    """The five-gate double-dot stack at an arbitrary node count."""
+    return make_stack_device(name, _uniform_xy(nx), _uniform_xy(ny), stack_z(nz - 1),
+                             double_dot_gates(), volts, stat=stat, T_K=T_K,
+                             boxes={"D1": DOT_BOX_D1, "D2": DOT_BOX_D2})
+
+
+def config2(nx=129, ny=129, nz=65):
+    """Five-gate double-dot stack, Fermi-Dirac electrons at 4 K."""
+    rng = np.random.default_rng(SEED_BASE + 2)
+    volts = rng.uniform(0.0, 2.0, 5)
+    return double_dot_device("c2", nx, ny, nz, volts)
+
+
+PLUNGER_GRID = np.linspace(0.8, 1.6, 16)
+
+
+def config3_spec(n_inst=256):
+    """Mesh sizes and gate voltages of the batched plunger sweep.
+
+    Returns (m[n_inst], volts[n_inst][5]); instance k has
+    (m+1) x (m+1) x (m//2 + 1) nodes and plunger voltages on the 16x16 grid."""
+    rng = np.random.default_rng(SEED_BASE + 3)
+    ms = rng.integers(32, 65, size=n_inst)
+    vb = rng.uniform(0.0, 2.0, 3)            # B1, B2, B3, shared by the sweep
+    volts = np.empty((n_inst, 5))
+    for k in range(n_inst):
+        vp1 = PLUNGER_GRID[(k // 16) % 16]
+        vp2 = PLUNGER_GRID[k % 16]
+        volts[k] = (vp1, vp2, vb[0], vb[1], vb[2])
+    return ms, volts
+
+
+def config3_instance(k, spec=None):
+    ms, volts = spec if spec is not None else config3_spec()
+    m = int(ms[k])
+    return double_dot_device(f"c3[{k}]", m + 1, m + 1, m // 2 + 1, volts[k])
+
+
+def config4(nx=129, ny=129, nz=65):
+    """The five-gate stack used for dot-charge gradients."""
+    rng = np.random.default_rng(SEED_BASE + 4)
+    volts = rng.uniform(0.0, 2.0, 5)
+    return double_dot_device("c4", nx, ny, nz, volts)
+
+
+def _random_gates(rng, n=8, min_gap=10.0, max_tries=10000):
+    acc = []
+    tries = 0
+    while len(acc) < n and tries < max_tries:
+        tries += 1
+        w = rng.uniform(20.0, 60.0)
+        l = rng.uniform(20.0, 60.0)
+        x0 = rng.uniform(0.0, BOX_XY_NM - w)
+        y0 = rng.uniform(0.0, BOX_XY_NM - l)
+        r = (x0, x0 + w, y0, y0 + l)
+        ok = True
+        for a in acc:
+            gx = max(0.0, max(r[0] - a[1], a[0] - r[1]))
+            gy = max(0.0, max(r[2] - a[3], a[2] - r[3]))
+            if max(gx, gy) < min_gap:
+                ok = False
+                break
+        if ok:
+            acc.append(r)
+    return acc
+
+
+def config5(nx=257, ny=257, nz=129):
+    """Eight random top gates over an oxide with +-1 nm thickness roughness."""
+    rng = np.random.default_rng(SEED_BASE + 5)
+    ctrl = rng.uniform(-1.0, 1.0, (11, 11))
+    rects = _random_gates(rng)
+    volts = rng.uniform(0.0, 2.0, len(rects))
+    gates = [(f"G{g + 1}", r) for g, r in enumerate(rects)]
+
+    def interface(xq, yq):
+        return SI_NM + _bilinear(ctrl, 20.0, xq, yq)
+
+    return make_stack_device("c5", _uniform_xy(nx), _uniform_xy(ny), stack_z(nz - 1),
+                             gates, volts, stat="fd", T_K=4.0, interface=interface,
+                             boxes={"D1": DOT_BOX_D1, "D2": DOT_BOX_D2})
