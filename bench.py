@@ -1,0 +1,162 @@
+"""Benchmark of the nonlinear-Poisson Newton-Krylov path on one MI355X.
+
+A step is one full FP64 solve of the five-gate double-dot stack
+(129 x 129 x 65 nodes, Fermi-Dirac electrons at 4 K) from the default
+(charge-free) initial guess to ||F|| < 1e-8, plus the electron counts in the
+two dot boxes.  ``value`` is solves per second over the timed steps.  Also
+reported: the J.v kernel rate (GDOF/s, FP64 and FP32) with its HBM roofline,
+the adjoint/forward time ratio, and the CPU oracle timed on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GDOF/s of nonlinear-Poisson J·v; solves/s at ‖F‖<1e-8; adjoint/forward time"
+
+
+def jv_bytes(dev, elem_bytes, node_bytes, coef_bytes):
+    """Algorithmic bytes of one masked J.v launch: read v, mask; write y (per
+    node); read eps, semi (per element); read the 8 Gauss-point coefficients
+    of every semiconductor element."""
+    n_semi = int(dev.semi.sum())
+    return dev.n_nodes * (2 * node_bytes + 1) + dev.n_elems * (elem_bytes + 1) + n_semi * 8 * coef_bytes
+
+
+def cpu_baseline(dev, gpu_newton, budget_s=25.0):
+    """The oracle on the host: linear initial guess plus as many Newton steps
+    as fit in the budget (at least one), extrapolated to a full solve with the
+    GPU run's Newton step count."""
+    import numpy as np
+    from oracle import solver
+    t0 = time.perf_counter()
+    prob = solver.make_problem(dev)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    phi = solver.initial_guess(prob, method="cg")
+    t_init = time.perf_counter() - t0
+    steps, t_steps = 0, 0.0
+    phi_k = phi
+    while steps < max(gpu_newton, 1):
+        t0 = time.perf_counter()
+        r = solver.newton(prob, phi0=phi_k, atol=1e-8, maxit=1, method="cg")
+        t_steps += time.perf_counter() - t0
+        phi_k = r.phi
+        steps += 1
+        if t_init + t_steps > budget_s:
+            break
+    est = t_setup + t_init + t_steps / steps * max(gpu_newton, 1)
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"c2 device: assembly + linear initial guess + {steps} Newton step(s) timed "
+                      f"({t_setup + t_init + t_steps:.1f} s), full solve extrapolated to "
+                      f"{gpu_newton} Newton steps = {est:.1f} s (scipy CSR/CG, single-threaded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--jv-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "slab decomposition is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1403_7561_amd import qe
+
+    torch.cuda.set_device(0)
+    dev = synth.config2()
+    P = qe.Problem(dev)
+    opts = qe.qe_default_options(newton_atol=1e-8)
+    ws = qe.workspace_for(P, opts)
+    boxes = [dev.boxes["D1"], dev.boxes["D2"]]
+    phi = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+
+    def step():
+        ph, _, rep = qe.qe_solve(P, opts=opts, phi=phi, want_density=True, ws=ws)
+        c = qe.qe_count_electrons(P, ph, boxes, ws=ws)
+        return rep, c
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(args.steps):
+        rep, counts = step()
+        reps.append(rep)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = args.steps / (t1 - t0)
+
+    # J.v kernel alone (HIP events on the library's stream)
+    v = torch.randn(P.N, dtype=torch.float64, device="cuda")
+    ms64 = qe.qe_time_jv(P, phi, v, "fp64", args.jv_reps, ws=ws)
+    ms32 = qe.qe_time_jv(P, phi, v, "mixed", args.jv_reps, ws=ws)
+    b64 = jv_bytes(dev, 8, 8, 8)
+    b32 = jv_bytes(dev, 4, 4, 4)
+    ach = b64 / (ms64 * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "double-dot Si/SiO2 stack 129x129x65 nodes (1081665 DOF), 5 gates, "
+                               "Fermi-Dirac 4 K, FP64 Newton + Jacobi-PCG to ||F||<1e-8",
+                   "global_batch": 1, "parallelism": "single GPU"},
+        "newton_iters": reps[-1]["newton_iters"],
+        "krylov_iters": reps[-1]["krylov_iters"],
+        "res_final": reps[-1]["res_final"],
+        "dot_electrons": [float(c) for c in counts],
+        "jv_gdof_s": {"fp64": P.N / (ms64 * 1e-3) / 1e9, "fp32": P.N / (ms32 * 1e-3) / 1e9,
+                      "ms_fp64": ms64, "ms_fp32": ms32},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_jv<double,false> (FP64 masked J.v)",
+                     "bytes_per_launch": b64},
+        "roofline_fp32": {"achieved": b32 / (ms32 * 1e-3) / 1e9, "bytes_per_launch": b32},
+    }
+    if not args.no_adjoint:
+        dev4 = synth.config4()
+        P4 = qe.Problem(dev4)
+        ws4 = qe.workspace_for(P4, opts)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ph4, _, rep4 = qe.qe_solve(P4, opts=opts, ws=ws4, want_density=False)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        Q, dV, deps, _, arep = qe.qe_adjoint(P4, ph4, dev4.boxes["D1"], opts=opts, ws=ws4)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        out["adjoint"] = {"forward_ms": (tb - ta) * 1e3, "adjoint_ms": (tc - tb) * 1e3,
+                          "ratio": (tc - tb) / (tb - ta), "Q_D1": Q, "dQ_dV": [float(x) for x in dV],
+                          "adjoint_cg_iters": arep["krylov_iters"]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(dev, reps[-1]["newton_iters"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

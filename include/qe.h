@@ -1,0 +1,217 @@
+/*
+ * qe.h -- C ABI of the MI355X semiclassical nonlinear-Poisson library.
+ *
+ * The library solves the discrete Galerkin form (Eq. PoissonWeakForm, Sec.
+ * II.A) of
+ *
+ *     -div(eps_r grad phi) = KAPPA * (N_D - N_A - n(phi)),   KAPPA = q/eps0
+ *
+ * on a rectilinear Q1 hexahedral mesh of a Si/SiO2 gate stack.  Electrons
+ * follow Thomas-Fermi (T = 0) or Fermi-Dirac statistics with the Bednarczyk
+ * F_1/2 form (Eqs. FDstatistics, EffectiveDOS, FDIntApprox, with exp(x) below
+ * x = -50); holes are absent and dopants fully ionised.  Gate electrodes and
+ * the substrate contact are Dirichlet nodes (Eq. ContOnIns with a mid-gap
+ * work function, so a gate node carries its applied voltage); every other
+ * outer face is the default zero-flux Neumann boundary (Sec. II.A.5).
+ * Newton's method with the exact Jacobian (Sec. II.A.4, II.C) is globalised
+ * by backtracking; the linear systems are solved by Jacobi-preconditioned
+ * conjugate gradients, all on the GPU.
+ *
+ * Units: lengths nm, potentials V, energies eV, densities nm^-3
+ * (1 cm^-3 = 1e-21 nm^-3), temperatures K.  The residual is in V*nm.
+ *
+ * Layout: node (i, j, k) is i + nx*(j + ny*k) (x fastest); element (i, j, k),
+ * whose lowest corner is node (i, j, k), is i + (nx-1)*(j + (ny-1)*k).
+ * E_F = 0 (grounded substrate, Sec. II.A.2), and E_F - E_C = phi - Ec0.
+ *
+ * Conventions shared by every entry point:
+ *  - Every array pointer in qe_problem and every "device" argument is DEVICE
+ *    memory allocated and owned by the caller; "host" arguments are host
+ *    memory.  The library never frees caller memory.
+ *  - `ws` is caller-owned device scratch of at least qe_workspace_bytes()
+ *    bytes, 256-byte aligned; its contents on entry are irrelevant and on
+ *    return unspecified.  Concurrent calls must not share a workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    device work is enqueued on it; every entry point returns after
+ *    synchronising that stream (the Newton decisions are taken on the host).
+ *  - Errors never abort: a negative qe_status is returned and
+ *    qe_last_error() describes it.  Invalid arguments are detected before any
+ *    device work is enqueued, except the device-array checks (eps_r > 0,
+ *    finiteness, dir_id range), which a validation kernel performs first.
+ *    On QE_ERR_NOT_CONVERGED / QE_ERR_LINESEARCH / QE_ERR_KRYLOV_* the last
+ *    iterate is still written to phi and the report.
+ */
+#ifndef QE_H
+#define QE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QE_OK = 0,
+  QE_ERR_INVALID_ARG = -1,       /* bad sizes, NULL pointers, options out of range */
+  QE_ERR_HIP = -2,               /* a HIP runtime call failed */
+  QE_ERR_WORKSPACE = -3,         /* ws NULL, misaligned or smaller than required */
+  QE_ERR_NOT_CONVERGED = -4,     /* Newton hit newton_maxit above newton_atol */
+  QE_ERR_LINESEARCH = -5,        /* no sufficient decrease after ls_max_halvings */
+  QE_ERR_KRYLOV_BREAKDOWN = -6,  /* p^T J p <= 0 or non-finite inside CG */
+  QE_ERR_NONFINITE = -7,         /* NaN/Inf in inputs or in the residual */
+  QE_ERR_KRYLOV_MAXIT = -8       /* a linear solve hit krylov_maxit (adjoint only) */
+} qe_status;
+
+typedef enum {
+  QE_STAT_LINEAR = 0,            /* no mobile charge (doping only) */
+  QE_STAT_TF = 1,                /* Thomas-Fermi: n = C_TF max(0, phi-Ec0)^(3/2) */
+  QE_STAT_FD12 = 2               /* n = N_C F_1/2((phi-Ec0)/kT), Eq. FDIntApprox */
+} qe_statistics;
+
+typedef enum {
+  QE_PREC_FP64 = 0,              /* everything in FP64 */
+  QE_PREC_MIXED = 1              /* J.v and CG in FP32; residual, charge, line search,
+                                    Newton update in FP64 */
+} qe_precision;
+
+/* One device.  All pointers are DEVICE memory, read only. */
+typedef struct {
+  int32_t nx, ny, nz;            /* nodes per axis, each >= 2 */
+  const double* x;               /* [nx] nm, strictly increasing */
+  const double* y;               /* [ny] */
+  const double* z;               /* [nz] */
+  const double* eps_r;           /* [E] relative permittivity, finite, > 0 */
+  const uint8_t* semi;           /* [E] 1 = semiconductor (carries electrons and
+                                    doping), 0 = insulator */
+  const double* net_doping;      /* [E] N_D - N_A in nm^-3; NULL means 0 */
+  const int32_t* dir_id;         /* [N] -1 = free node, else index < n_dir */
+  const double* dir_val;         /* [n_dir] Dirichlet potential in V */
+  int32_t n_dir;                 /* >= 0; a problem with no Dirichlet node needs
+                                    n'(phi) > 0 somewhere to be solvable */
+} qe_problem;
+
+typedef struct {
+  int32_t stat;                  /* qe_statistics */
+  double T_K;                    /* > 0 for QE_STAT_FD12, ignored otherwise */
+  double m_eff;                  /* DOS effective mass / m0 (Eq. EffectiveMass), > 0 */
+  double Ec0_eV;                 /* E_C - E_F at phi = 0 */
+} qe_physics;
+
+typedef struct {
+  double newton_atol;            /* stop when ||F_free||_2 <= atol (V nm), > 0 */
+  int32_t newton_maxit;          /* >= 0 */
+  int32_t ls_max_halvings;       /* >= 0 */
+  double krylov_rtol_max;        /* cap of the inexact-Newton forcing term, (0, 1) */
+  int32_t krylov_maxit;          /* CG iterations per linear solve, >= 1 */
+  int32_t precision;             /* qe_precision */
+  int32_t init_guess;            /* 0: linear (charge-free) Poisson solve;
+                                    1: start from the phi passed in */
+  int32_t check_every;           /* CG iterations between host convergence checks
+                                    (0 = library default) */
+} qe_options;
+
+typedef struct {
+  int32_t status;                /* qe_status of the call */
+  int32_t newton_iters;
+  int32_t krylov_iters;          /* total CG iterations incl. the initial guess */
+  int32_t ls_halvings;
+  int32_t init_krylov_iters;
+  int32_t n_residual_evals;
+  double res0;                   /* ||F_free|| at the first Newton iterate */
+  double res_final;              /* ||F_free|| at the returned phi */
+} qe_report;
+
+/* Fill `o` with defaults (atol 1e-8, 100 Newton steps, 30 halvings, forcing
+ * cap 1e-2, 20000 CG iterations, FP64, linear initial guess). */
+void qe_default_options(qe_options* o);
+
+/* Bytes of workspace any entry point below needs for this problem. */
+size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o);
+
+/* Nonlinear solve (Sec. II.A; initial guess, residual, Jacobian, CG, line
+ * search, Newton update).  phi: device [N]; on entry the guess when
+ * init_guess = 1 (its Dirichlet entries are overwritten), on return the
+ * solution.  n_nodal: device [N] or NULL; receives n(phi_i) at nodes that
+ * touch a semiconductor element, 0 elsewhere.  rep: host, may be NULL. */
+qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* o,
+                   double* phi, double* n_nodal, void* ws, size_t ws_bytes,
+                   void* stream, qe_report* rep);
+
+/* Residual of Eq. PoissonWeakForm at phi (device [N], used as given, Dirichlet
+ * entries included): F device [N] (free rows; 0 on Dirichlet rows).
+ * diag: device [N] or NULL, the Jacobian diagonal (1 on Dirichlet rows).
+ * norm2: host scalar or NULL, ||F_free||_2^2. */
+qe_status qe_residual(const qe_problem* p, const qe_physics* ph, const double* phi,
+                      double* F, double* diag, double* norm2,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Jacobian-vector product at phi (exact derivative of the coded residual):
+ * y = J(phi) v with v masked to 0 on Dirichlet nodes, and y_i = v_i on
+ * Dirichlet rows.  phi, v, y: device [N]. */
+qe_status qe_jv(const qe_problem* p, const qe_physics* ph, const double* phi,
+                const double* v, double* y, void* ws, size_t ws_bytes, void* stream);
+
+/* The same product computed in FP32 (the mixed-precision inner operator):
+ * the linearisation is formed in FP64 at phi, then rounded to FP32. */
+qe_status qe_jv_f32(const qe_problem* p, const qe_physics* ph, const double* phi,
+                    const float* v, float* y, void* ws, size_t ws_bytes, void* stream);
+
+/* Electron count in boxes (Sec. III: N = integral of n over the dot region):
+ * sum over semiconductor elements whose centroid lies in the closed box of
+ * sum_q W_q n(phi_q).  boxes: host [n_boxes][6] = x0,x1,y0,y1,z0,z1 (nm);
+ * counts: host [n_boxes].  1 <= n_boxes <= 16. */
+qe_status qe_count_electrons(const qe_problem* p, const qe_physics* ph, const double* phi,
+                             int32_t n_boxes, const double* boxes, double* counts,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Nodal electron density (as qe_solve's n_nodal) at phi.  n: device [N]. */
+qe_status qe_density(const qe_problem* p, const qe_physics* ph, const double* phi,
+                     double* n, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint gradient of Q = electrons in `box` (host [6]) at a converged phi
+ * (device [N]), for the capacitance C_g = q dQ/dV_g of Sec. III and gate
+ * design loops (Sec. IV):
+ *   J_ff lam = dQ/dphi_f (same CG, J symmetric),
+ *   dQ/dV_c   = sum_{i in contact c} (dQ/dphi_i - (J lam)_i),
+ *   dQ/deps_e = -lam_e^T Khat_e phi_e.
+ * Q: host scalar or NULL.  dQ_ddir: host [n_dir] (per Dirichlet value).
+ * dQ_deps: device [E] or NULL.  lam: device [N] or NULL (adjoint state).
+ * opts: krylov_maxit and precision (must be FP64) are used; the adjoint CG
+ * runs to a relative residual of 1e-12.  rep: host or NULL. */
+qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options* o,
+                     const double* phi, const double* box, double* Q, double* dQ_ddir,
+                     double* dQ_deps, double* lam, void* ws, size_t ws_bytes,
+                     void* stream, qe_report* rep);
+
+/* Batched solve of many independent devices (a gate-voltage sweep over
+ * uneven meshes) in one persistent launch: Newton, line search and CG run
+ * on the device for every instance.
+ *   probs: host [n_inst] of qe_problem (device arrays inside);
+ *   phi: host [n_inst] of device pointers, each [N_k]; out: solutions;
+ *   boxes: host [n_boxes][6]; counts: host [n_inst][n_boxes] (may be NULL
+ *     when n_boxes = 0);
+ *   tune_cache: path of the autotuner's cache file (NULL = no cache);
+ *   reps: host [n_inst] or NULL.
+ * All instances share ph and o; o->precision must be FP64. */
+size_t qe_batch_workspace_bytes(int32_t n_inst, const qe_problem* probs, const qe_options* o);
+qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physics* ph,
+                         const qe_options* o, double* const* phi, int32_t n_boxes,
+                         const double* boxes, double* counts, const char* tune_cache,
+                         void* ws, size_t ws_bytes, void* stream, qe_report* reps);
+
+/* Benchmark helper: forms the linearisation at phi (device [N]), then applies
+ * J.v `reps` times (FP64 or, with QE_PREC_MIXED, FP32) to the vector v
+ * (device [N], FP64; converted once for FP32) between two HIP events on
+ * `stream`.  ms_per_apply: host, mean kernel time per product. */
+qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* phi, const double* v,
+                     int32_t precision, int32_t reps, double* ms_per_apply, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* qe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QE_H */

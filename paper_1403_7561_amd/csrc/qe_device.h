@@ -1,0 +1,245 @@
+// Device-side building blocks of the Q1 nonlinear-Poisson kernels (gfx950).
+//
+// Element-local algebra uses the local corner index a + 2b + 4c (x fastest).
+// On a box element (hx, hy, hz) the unit-permittivity stiffness is
+//   Khat = (hy hz/hx) A(x)M(y)M(z) + (hx hz/hy) M(x)A(y)M(z) + (hx hy/hz) M(x)M(y)A(z)
+// with the unit 1D stiffness A = [[1,-1],[-1,1]] and mass M = [[2,1],[1,2]]/6;
+// it is applied axis by axis (sum factorisation), never formed.  Gauss-point
+// interpolation with the 2-point rule is the tensor product of the symmetric
+// 1D matrix B = [[g1, g0], [g0, g1]], g1,0 = (1 +- 1/sqrt(3))/2, so the same
+// routine also performs the projection back to the corners.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qe {
+
+constexpr int kTX = 16;               // owned node columns per tile in x
+constexpr int kTY = 16;               // ... in y
+constexpr int kEX = kTX + 1;          // element columns per tile (one halo column)
+constexpr int kEY = kTY + 1;
+constexpr int kNXL = kTX + 2;         // staged node columns
+constexpr int kNYL = kTY + 2;
+constexpr int kNEL = kEX * kEY;       // elements per tile layer (289)
+constexpr int kNNL = kNXL * kNYL;     // staged nodes per plane (324)
+constexpr int kThreads = 256;         // 4 waves of 64
+constexpr int kVecThreads = 256;
+
+constexpr double kG1 = 0.78867513459481288225;   // (1 + 1/sqrt(3)) / 2
+constexpr double kG0 = 0.21132486540518711775;   // (1 - 1/sqrt(3)) / 2
+
+enum Stat : int { STAT_LINEAR = 0, STAT_TF = 1, STAT_FD = 2 };
+
+// Mesh geometry (device pointers to the caller's coordinate arrays).
+struct Geom {
+  int nx, ny, nz;
+  const double* x;
+  const double* y;
+  const double* z;
+};
+
+// Electron statistics constants (derived on the host from CODATA values).
+struct Charge {
+  int stat;
+  double Ec0;      // eV
+  double inv_kT;   // 1/eV
+  double Nc;       // nm^-3
+  double Ctf;      // nm^-3 eV^-3/2
+  double kappa;    // q/eps0 in V nm
+};
+
+// Tile decomposition of the node grid: gx*gy tiles of kTX x kTY node columns,
+// gz chunks of kz node planes.
+struct TileMap {
+  int gx, gy, gz, kz;
+  int nblocks;
+};
+
+// Block b is dispatched to XCD b % 8; hand each XCD a contiguous run of tiles
+// so that neighbouring tiles (which re-read each other's halo) share an L2.
+__device__ __forceinline__ void tile_of_block(int b, const TileMap& tm, int& tx, int& ty, int& tz) {
+  const int per = tm.nblocks >> 3, rem = tm.nblocks & 7;
+  const int xcd = b & 7, loc = b >> 3;
+  int t = (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
+  tx = t % tm.gx;
+  t /= tm.gx;
+  ty = t % tm.gy;
+  tz = t / tm.gy;
+}
+
+__device__ __forceinline__ int ci(int a, int b, int c) { return a + 2 * b + 4 * c; }
+
+// ---- 1D operators -------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void mass1(T u0, T u1, T& o0, T& o1) {
+  const T s = T(1) / T(6);
+  o0 = (T(2) * u0 + u1) * s;
+  o1 = (u0 + T(2) * u1) * s;
+}
+
+// out = (sx A(x)M(y)M(z) + sy M(x)A(y)M(z) + sz M(x)M(y)A(z)) v
+template <typename T>
+__device__ __forceinline__ void stiff_apply(const T v[8], T sx, T sy, T sz, T out[8]) {
+  T mz[8], dz[8];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const T u0 = v[ci(a, b, 0)], u1 = v[ci(a, b, 1)];
+      mass1(u0, u1, mz[ci(a, b, 0)], mz[ci(a, b, 1)]);
+      const T d = u0 - u1;
+      dz[ci(a, b, 0)] = d;
+      dz[ci(a, b, 1)] = -d;
+    }
+  T myz[8], t[8];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const T m0 = mz[ci(a, 0, c)], m1 = mz[ci(a, 1, c)];
+      mass1(m0, m1, myz[ci(a, 0, c)], myz[ci(a, 1, c)]);
+      const T d = m0 - m1;
+      T e0, e1;
+      mass1(dz[ci(a, 0, c)], dz[ci(a, 1, c)], e0, e1);
+      t[ci(a, 0, c)] = sy * d + sz * e0;
+      t[ci(a, 1, c)] = -sy * d + sz * e1;
+    }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const T d = sx * (myz[ci(0, b, c)] - myz[ci(1, b, c)]);
+      T o0, o1;
+      mass1(t[ci(0, b, c)], t[ci(1, b, c)], o0, o1);
+      out[ci(0, b, c)] = d + o0;
+      out[ci(1, b, c)] = -d + o1;
+    }
+}
+
+// Tensor-product application of [[p, q], [q, p]] along x, y and z (in place).
+template <typename T>
+__device__ __forceinline__ void tensor_sym(T u[8], T p, T q) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const T u0 = u[ci(0, b, c)], u1 = u[ci(1, b, c)];
+      u[ci(0, b, c)] = p * u0 + q * u1;
+      u[ci(1, b, c)] = q * u0 + p * u1;
+    }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const T u0 = u[ci(a, 0, c)], u1 = u[ci(a, 1, c)];
+      u[ci(a, 0, c)] = p * u0 + q * u1;
+      u[ci(a, 1, c)] = q * u0 + p * u1;
+    }
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const T u0 = u[ci(a, b, 0)], u1 = u[ci(a, b, 1)];
+      u[ci(a, b, 0)] = p * u0 + q * u1;
+      u[ci(a, b, 1)] = q * u0 + p * u1;
+    }
+}
+
+// Corner values -> Gauss-point values (and, being symmetric, the projection
+// sum_q f_q w_a(q) back to the corners).
+template <typename T>
+__device__ __forceinline__ void gauss_interp(T u[8]) { tensor_sym(u, T(kG1), T(kG0)); }
+
+// sum_q f_q w_a(q)^2 : the Gauss-point weights of the mass diagonal.
+template <typename T>
+__device__ __forceinline__ void gauss_sq_project(T u[8]) { tensor_sym(u, T(kG1 * kG1), T(kG0 * kG0)); }
+
+// ---- charge statistics ----------------------------------------------------
+// n(phi) and dn/dphi.  Fermi-Dirac uses Bednarczyk's F_1/2 with its exact
+// derivative, and exp(eta) below eta = -50; Thomas-Fermi is its T -> 0 limit.
+__device__ __forceinline__ void electron_density(const Charge& ch, double phi, double& n, double& dn) {
+  const double u = phi - ch.Ec0;
+  if (ch.stat == STAT_TF) {
+    const double up = fmax(u, 0.0);
+    const double s = sqrt(up);
+    n = ch.Ctf * up * s;
+    dn = 1.5 * ch.Ctf * s;
+  } else if (ch.stat == STAT_FD) {
+    const double eta = u * ch.inv_kT;
+    if (eta < -50.0) {
+      const double e = exp(eta);
+      n = ch.Nc * e;
+      dn = ch.Nc * e * ch.inv_kT;
+    } else {
+      const double a = 1.3293403881791355;          // 3 sqrt(pi) / 4
+      const double xp1 = eta + 1.0;
+      const double g = exp(-0.17 * xp1 * xp1);
+      const double eta2 = eta * eta;
+      const double v = eta2 * eta2 + 50.0 + 33.6 * eta * (1.0 - 0.68 * g);
+      const double dv = 4.0 * eta2 * eta + 33.6 * (1.0 - 0.68 * g) + 7.76832 * eta * xp1 * g;
+      const double em = exp(-eta);
+      const double vp = exp(-0.375 * log(v));          // v^(-3/8)
+      const double F = 1.0 / (em + a * vp);
+      const double Fp = (em + 0.375 * a * (vp / v) * dv) * F * F;
+      n = ch.Nc * F;
+      dn = ch.Nc * Fp * ch.inv_kT;
+    }
+  } else {
+    n = 0.0;
+    dn = 0.0;
+  }
+}
+
+__device__ __forceinline__ double electron_density_only(const Charge& ch, double phi) {
+  double n, dn;
+  electron_density(ch, phi, n, dn);
+  return n;
+}
+
+// ---- reductions -------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Sum over the block (fixed order); the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sred) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sred[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) r += sred[w];
+  }
+  __syncthreads();
+  return r;
+}
+
+// Publishes partial[blockIdx] (already written by thread 0) and reports
+// whether this block is the last to finish; the last block then sees every
+// partial.  The counter is reset by the caller's last block.
+__device__ __forceinline__ bool last_block_done(unsigned int* counter) {
+  __shared__ int am_last;
+  __threadfence();
+  if (threadIdx.x == 0) {
+    const unsigned int prev = atomicAdd(counter, 1u);
+    am_last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (am_last) __threadfence();
+  return am_last != 0;
+}
+
+// Sum of partial[0..n) in a fixed order by one block; valid in thread 0.
+__device__ __forceinline__ double reduce_partials(const double* partial, int n, double* sred) {
+  double v = 0.0;
+  const volatile double* p = partial;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+  return block_sum(v, sred);
+}
+
+}  // namespace qe

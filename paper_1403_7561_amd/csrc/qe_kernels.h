@@ -1,0 +1,76 @@
+// Kernel-side types and host launchers of the Q1 nonlinear-Poisson path.
+#pragma once
+
+#include "qe_device.h"
+
+namespace qe {
+
+constexpr int kMaxBoxes = 16;
+
+// Closed axis-aligned box (nm); an element belongs to it when its centroid does.
+struct Box {
+  double x0, x1, y0, y1, z0, z1;
+  __host__ __device__ bool contains(double x, double y, double z) const {
+    return x >= x0 && x <= x1 && y >= y0 && y <= y1 && z >= z0 && z <= z1;
+  }
+};
+
+struct BoxSet {
+  int n;
+  Box b[kMaxBoxes];
+};
+
+enum PcgStatus : int { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_BREAKDOWN = 2, PCG_MAXIT = 3, PCG_NONFINITE = 4 };
+
+// Conjugate-gradient scalars, kept on the device between kernels.  Counters
+// serve the last-block reductions and are reset by the block that uses them.
+struct PcgCtx {
+  double rz, pAp, alpha, beta, rr, rr0, tol2, pad;
+  int iters, maxit, done, status;
+  unsigned int cnt_jv, cnt_upd, cnt_init, cnt_misc;
+};
+
+void launch_residual(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const double* eps,
+                     const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
+                     const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
+                     double* diag_out, double* cq, float* cq32, float* invdiag32, double* partial,
+                     unsigned int* counter, double* norm2);
+void launch_jv64(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
+                 const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows, PcgCtx* ctx,
+                 double* partial);
+void launch_jv32(hipStream_t s, const Geom& g, const TileMap& tm, const float* eps, const uint8_t* semi,
+                 const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows, PcgCtx* ctx,
+                 double* partial);
+void launch_adj_rhs(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const Box& box,
+                    const uint8_t* semi, const double* phi, double* gvec, double* partial, unsigned int* counter,
+                    double* Q);
+void launch_adj_grad(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
+                     const double* cq, const uint8_t* mask, const double* lam, const double* phi,
+                     const double* gvec, double* dQdeps, double* tcon);
+void launch_contact_sum(hipStream_t s, int nblocks, long N, int n_dir, const int32_t* dir_id, const double* tcon,
+                        double* partial, unsigned int* counter, double* out);
+void launch_count(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, const BoxSet& boxes,
+                  const uint8_t* semi, const double* phi, double* partial, unsigned int* counter, double* out);
+void launch_density(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, const uint8_t* semi,
+                    const double* phi, double* nout);
+void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const double* netdop,
+                     const int32_t* dir_id, const double* phi, int* flags);
+void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, const double* dir_val, uint8_t* mask,
+                  double* phi, int apply, int zero_free);
+void launch_cast_d2f(hipStream_t s, int nblocks, long n, const double* a, float* b);
+void launch_axpy_phi(hipStream_t s, int nblocks, long N, double* phi, const double* d64, const float* d32,
+                     double lam);
+void launch_pcg_init64(hipStream_t s, int nblocks, long N, double sign, const double* b, const uint8_t* mask,
+                       const double* invdiag, double* x, double* r, double* p, PcgCtx* ctx, double* partial,
+                       double rtol);
+void launch_pcg_init32(hipStream_t s, int nblocks, long N, double sign, const double* b, const uint8_t* mask,
+                       const float* invdiag, float* x, float* r, float* p, PcgCtx* ctx, double* partial,
+                       double rtol);
+void launch_pcg_iter64(hipStream_t s, const Geom& g, const TileMap& tm, int vblocks, long N, const double* eps,
+                       const uint8_t* semi, const double* cq, const uint8_t* mask, const double* invdiag, double* x,
+                       double* r, double* p, double* y, PcgCtx* ctx, double* partial);
+void launch_pcg_iter32(hipStream_t s, const Geom& g, const TileMap& tm, int vblocks, long N, const float* eps,
+                       const uint8_t* semi, const float* cq, const uint8_t* mask, const float* invdiag, float* x,
+                       float* r, float* p, float* y, PcgCtx* ctx, double* partial);
+
+}  // namespace qe

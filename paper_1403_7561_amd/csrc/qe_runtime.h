@@ -1,0 +1,53 @@
+// Host-side context shared by the entry points of the nonlinear-Poisson library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/qe.h"
+#include "qe_kernels.h"
+
+namespace qe {
+
+qe_status fail(qe_status st, const char* fmt, ...);
+void clear_error();
+qe_status make_charge(const qe_physics* ph, Charge& ch);
+qe_status check_problem(const qe_problem* p);
+qe_status check_options(const qe_options* o);
+int vec_blocks(long N);
+TileMap make_tilemap(int nx, int ny, int nz, int kz);
+
+// Byte offsets of the workspace carve-out.
+struct Layout {
+  size_t F, x, r, p, y, invdiag, gvec, c, mask;
+  size_t x32, r32, p32, y32, invdiag32, c32, eps32;
+  size_t partial, ctx, scal, counters, flags;
+  long n_partial;
+  size_t total;
+};
+Layout make_layout(long N, long E, int nblocks_tile, int vblocks, int n_dir);
+
+// One call's view of a problem, its workspace and its stream.
+struct Context {
+  qe_problem prob;
+  Geom g;
+  TileMap tm;
+  long N = 0, E = 0;
+  int vblocks = 0;
+  Layout lay;
+  char* ws = nullptr;
+  hipStream_t s = nullptr;
+
+  double* f64(size_t off) const { return reinterpret_cast<double*>(ws + off); }
+  float* f32(size_t off) const { return reinterpret_cast<float*>(ws + off); }
+  uint8_t* u8(size_t off) const { return reinterpret_cast<uint8_t*>(ws + off); }
+
+  qe_status init(const qe_problem* p, void* ws, size_t ws_bytes, void* stream, int kz = 0);
+  qe_status validate(const double* phi);
+  qe_status stage(double* phi, int apply, int zero_free);
+  qe_status residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam, bool mixed,
+                     double* diag_out, double* norm2_host);
+  qe_status pcg(bool mixed, const double* b, double sign, double rtol, int maxit, int check_every, int* pcg_status,
+                int* iters);
+};
+
+}  // namespace qe

@@ -1,0 +1,664 @@
+// Host runtime and C ABI of the Q1 nonlinear-Poisson library (see qe.h).
+//
+// The Newton iteration is driven from the host: one scalar read per residual
+// evaluation and one per block of CG iterations.  Inside a linear solve every
+// scalar (alpha, beta, residual norms, the stop flag) lives on the device, so
+// a block of CG iterations is a plain sequence of kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qe.h"
+#include "qe_kernels.h"
+#include "qe_runtime.h"
+
+namespace qe {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+qe_status fail(qe_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+#define QE_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(QE_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+#define QE_TRY(expr)              \
+  do {                            \
+    qe_status s_ = (expr);        \
+    if (s_ != QE_OK) return s_;   \
+  } while (0)
+
+// ------------------------------------------------------------------ physics
+// CODATA 2018 values (q, hbar, kB exact).
+static const double kQ = 1.602176634e-19, kEps0 = 8.8541878128e-12, kHbar = 1.054571817e-34,
+                    kM0 = 9.1093837015e-31, kKB = 1.380649e-23, kPi = 3.14159265358979323846;
+
+qe_status make_charge(const qe_physics* ph, Charge& ch) {
+  if (!ph) return fail(QE_ERR_INVALID_ARG, "physics is NULL");
+  std::memset(&ch, 0, sizeof(ch));
+  ch.kappa = kQ / kEps0 * 1e9;  // V nm: Poisson divided by eps0, nm units
+  ch.Ec0 = ph->Ec0_eV;
+  if (!std::isfinite(ph->Ec0_eV)) return fail(QE_ERR_INVALID_ARG, "Ec0_eV not finite");
+  switch (ph->stat) {
+    case QE_STAT_LINEAR:
+      ch.stat = STAT_LINEAR;
+      break;
+    case QE_STAT_TF: {
+      if (!(ph->m_eff > 0) || !std::isfinite(ph->m_eff)) return fail(QE_ERR_INVALID_ARG, "m_eff must be > 0");
+      ch.stat = STAT_TF;
+      // T = 0 limit of the 3D density of states integral: n = (2 m* E)^(3/2) / (3 pi^2 hbar^3)
+      const double m = ph->m_eff * kM0;
+      ch.Ctf = std::pow(2.0 * m * kQ, 1.5) / (3.0 * kPi * kPi * kHbar * kHbar * kHbar) * 1e-27;
+      break;
+    }
+    case QE_STAT_FD12: {
+      if (!(ph->m_eff > 0) || !std::isfinite(ph->m_eff)) return fail(QE_ERR_INVALID_ARG, "m_eff must be > 0");
+      if (!(ph->T_K > 0) || !std::isfinite(ph->T_K))
+        return fail(QE_ERR_INVALID_ARG, "Fermi-Dirac statistics need T_K > 0");
+      ch.stat = STAT_FD;
+      const double m = ph->m_eff * kM0;
+      const double kT_J = kKB * ph->T_K;
+      ch.inv_kT = kQ / kT_J;  // 1/eV
+      ch.Nc = 2.0 * std::pow(m * kT_J / (2.0 * kPi * kHbar * kHbar), 1.5) * 1e-27;
+      break;
+    }
+    default:
+      return fail(QE_ERR_INVALID_ARG, "unknown statistics %d", ph->stat);
+  }
+  return QE_OK;
+}
+
+// ------------------------------------------------------------------ sizes
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int vec_blocks(long N) {
+  long b = (N + (long)kVecThreads * 4 - 1) / ((long)kVecThreads * 4);
+  return (int)std::max(1L, std::min(b, 2048L));
+}
+
+TileMap make_tilemap(int nx, int ny, int nz, int kz) {
+  TileMap tm;
+  tm.gx = (nx + kTX - 1) / kTX;
+  tm.gy = (ny + kTY - 1) / kTY;
+  if (kz <= 0) {
+    // enough blocks to cover the chip a few times, but chunks long enough that
+    // the recomputed halo layer stays a small fraction
+    kz = 8;
+    while (kz > 4 && (long)tm.gx * tm.gy * ((nz + kz - 1) / kz) < 512) kz >>= 1;
+  }
+  tm.kz = kz;
+  tm.gz = (nz + kz - 1) / kz;
+  tm.nblocks = tm.gx * tm.gy * tm.gz;
+  return tm;
+}
+
+static const int kCountBlocks = 256;
+static const int kContactBlocks = 256;
+
+Layout make_layout(long N, long E, int nblocks_tile, int vblocks, int n_dir) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.F = take(N * 8);
+  L.x = take(N * 8);
+  L.r = take(N * 8);
+  L.p = take(N * 8);
+  L.y = take(N * 8);
+  L.invdiag = take(N * 8);
+  L.gvec = take(N * 8);
+  L.c = take(E * 64);
+  L.mask = take(N);
+  L.x32 = take(N * 4);
+  L.r32 = take(N * 4);
+  L.p32 = take(N * 4);
+  L.y32 = take(N * 4);
+  L.invdiag32 = take(N * 4);
+  L.c32 = take(E * 32);
+  L.eps32 = take(E * 4);
+  long np = std::max<long>(nblocks_tile, 2L * vblocks);
+  np = std::max<long>(np, (long)kCountBlocks * kMaxBoxes);
+  np = std::max<long>(np, (long)kContactBlocks * std::max(1, n_dir));
+  L.n_partial = np;
+  L.partial = take(np * 8);
+  L.ctx = take(sizeof(PcgCtx));
+  L.scal = take(64 * 8);
+  L.counters = take(16 * sizeof(unsigned int));
+  L.flags = take(16);
+  L.total = off;
+  return L;
+}
+
+// ------------------------------------------------------------------ problem
+qe_status check_problem(const qe_problem* p) {
+  if (!p) return fail(QE_ERR_INVALID_ARG, "problem is NULL");
+  if (p->nx < 2 || p->ny < 2 || p->nz < 2) return fail(QE_ERR_INVALID_ARG, "need nx, ny, nz >= 2");
+  const long N = (long)p->nx * p->ny * p->nz;
+  if (N > (1L << 31) - 1) return fail(QE_ERR_INVALID_ARG, "mesh too large");
+  if (!p->x || !p->y || !p->z || !p->eps_r || !p->semi || !p->dir_id)
+    return fail(QE_ERR_INVALID_ARG, "NULL array in problem");
+  if (p->n_dir < 0) return fail(QE_ERR_INVALID_ARG, "n_dir < 0");
+  if (p->n_dir > 0 && !p->dir_val) return fail(QE_ERR_INVALID_ARG, "dir_val is NULL");
+  return QE_OK;
+}
+
+qe_status check_options(const qe_options* o) {
+  if (!o) return fail(QE_ERR_INVALID_ARG, "options are NULL");
+  if (!(o->newton_atol > 0) || !std::isfinite(o->newton_atol)) return fail(QE_ERR_INVALID_ARG, "newton_atol must be > 0");
+  if (o->newton_maxit < 0) return fail(QE_ERR_INVALID_ARG, "newton_maxit < 0");
+  if (o->ls_max_halvings < 0 || o->ls_max_halvings > 60) return fail(QE_ERR_INVALID_ARG, "ls_max_halvings out of range");
+  if (!(o->krylov_rtol_max > 0 && o->krylov_rtol_max < 1)) return fail(QE_ERR_INVALID_ARG, "krylov_rtol_max not in (0,1)");
+  if (o->krylov_maxit < 1) return fail(QE_ERR_INVALID_ARG, "krylov_maxit < 1");
+  if (o->precision != QE_PREC_FP64 && o->precision != QE_PREC_MIXED) return fail(QE_ERR_INVALID_ARG, "bad precision");
+  if (o->init_guess != 0 && o->init_guess != 1) return fail(QE_ERR_INVALID_ARG, "bad init_guess");
+  if (o->check_every < 0) return fail(QE_ERR_INVALID_ARG, "check_every < 0");
+  return QE_OK;
+}
+
+// Pinned host mirror for scalar read-backs (one per thread).
+struct HostMirror {
+  PcgCtx* ctx = nullptr;
+  double* scal = nullptr;
+  int* flags = nullptr;
+  bool ok = false;
+  HostMirror() {
+    void* a = nullptr;
+    if (hipHostMalloc(&a, 4096, hipHostMallocDefault) == hipSuccess) {
+      ctx = reinterpret_cast<PcgCtx*>(a);
+      scal = reinterpret_cast<double*>(reinterpret_cast<char*>(a) + 1024);
+      flags = reinterpret_cast<int*>(reinterpret_cast<char*>(a) + 3072);
+      ok = true;
+    }
+  }
+  // never freed: thread-exit destructors may run after the HIP runtime is gone
+};
+
+HostMirror& mirror() {
+  static thread_local HostMirror m;
+  return m;
+}
+
+qe_status Context::init(const qe_problem* p, void* ws_, size_t ws_bytes, void* stream_, int kz) {
+  QE_TRY(check_problem(p));
+  prob = *p;
+  s = (hipStream_t)stream_;
+  N = (long)p->nx * p->ny * p->nz;
+  E = (long)(p->nx - 1) * (p->ny - 1) * (p->nz - 1);
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.nz = p->nz;
+  g.x = p->x;
+  g.y = p->y;
+  g.z = p->z;
+  tm = make_tilemap(p->nx, p->ny, p->nz, kz);
+  vblocks = vec_blocks(N);
+  lay = make_layout(N, E, tm.nblocks, vblocks, p->n_dir);
+  if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < lay.total)
+    return fail(QE_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total);
+  ws = reinterpret_cast<char*>(ws_);
+  if (!mirror().ok) return fail(QE_ERR_HIP, "pinned host buffer allocation failed");
+  // coordinates: strictly increasing (host copy; a few KB)
+  std::vector<double> c(std::max({p->nx, p->ny, p->nz}));
+  const double* arrs[3] = {p->x, p->y, p->z};
+  const int lens[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a) {
+    QE_HIP(hipMemcpyAsync(c.data(), arrs[a], lens[a] * sizeof(double), hipMemcpyDeviceToHost, s));
+    QE_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < lens[a]; ++i)
+      if (!std::isfinite(c[i])) return fail(QE_ERR_INVALID_ARG, "coordinate %c[%d] not finite", "xyz"[a], i);
+    for (int i = 1; i < lens[a]; ++i)
+      if (!(c[i] > c[i - 1])) return fail(QE_ERR_INVALID_ARG, "coordinates %c not strictly increasing at %d", "xyz"[a], i);
+  }
+  if (p->n_dir > 0) {
+    std::vector<double> dv(p->n_dir);
+    QE_HIP(hipMemcpyAsync(dv.data(), p->dir_val, p->n_dir * sizeof(double), hipMemcpyDeviceToHost, s));
+    QE_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < p->n_dir; ++i)
+      if (!std::isfinite(dv[i])) return fail(QE_ERR_NONFINITE, "dir_val[%d] not finite", i);
+  }
+  // reset device scalars and reduction counters
+  QE_HIP(hipMemsetAsync(ws + lay.ctx, 0, sizeof(PcgCtx), s));
+  QE_HIP(hipMemsetAsync(ws + lay.counters, 0, 16 * sizeof(unsigned int), s));
+  QE_HIP(hipMemsetAsync(ws + lay.flags, 0, 16, s));
+  return QE_OK;
+}
+
+// Device-side checks of eps_r, net doping, dir_id and (optionally) phi.
+qe_status Context::validate(const double* phi) {
+  int* dflags = reinterpret_cast<int*>(ws + lay.flags);
+  launch_validate(s, vblocks, N, E, prob.n_dir, prob.eps_r, prob.net_doping, prob.dir_id, phi, dflags);
+  QE_HIP(hipGetLastError());
+  QE_HIP(hipMemcpyAsync(mirror().flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+  QE_HIP(hipStreamSynchronize(s));
+  const int f = *mirror().flags;
+  if (f & 1) return fail(QE_ERR_INVALID_ARG, "eps_r must be finite and > 0");
+  if (f & 2) return fail(QE_ERR_NONFINITE, "net_doping not finite");
+  if (f & 4) return fail(QE_ERR_INVALID_ARG, "dir_id outside [-1, n_dir)");
+  if (f & 8) return fail(QE_ERR_NONFINITE, "phi not finite");
+  return QE_OK;
+}
+
+qe_status Context::stage(double* phi, int apply, int zero_free) {
+  launch_stage(s, vblocks, N, prob.dir_id, prob.dir_val, u8(lay.mask), phi, apply, zero_free);
+  QE_HIP(hipGetLastError());
+  return QE_OK;
+}
+
+qe_status Context::residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam,
+                            bool mixed, double* diag_out, double* norm2_host) {
+  launch_residual(s, g, tm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
+                  f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
+                  mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial),
+                  reinterpret_cast<unsigned int*>(ws + lay.counters), f64(lay.scal));
+  QE_HIP(hipGetLastError());
+  if (norm2_host) {
+    QE_HIP(hipMemcpyAsync(mirror().scal, ws + lay.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    QE_HIP(hipStreamSynchronize(s));
+    *norm2_host = mirror().scal[0];
+  }
+  return QE_OK;
+}
+
+// Jacobi-PCG on J x = sign*b (free rows).  Returns the CG status through
+// *pcg_status and the iteration count through *iters.
+qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, int maxit, int check_every,
+                       int* pcg_status, int* iters) {
+  PcgCtx* dctx = reinterpret_cast<PcgCtx*>(ws + lay.ctx);
+  PcgCtx& h = *mirror().ctx;
+  // maxit goes into the device context before the first iteration
+  h = PcgCtx{};
+  h.maxit = maxit;
+  QE_HIP(hipMemcpyAsync(&dctx->maxit, &h.maxit, sizeof(int), hipMemcpyHostToDevice, s));
+  if (mixed)
+    launch_pcg_init32(s, vblocks, N, sign, b, u8(lay.mask), f32(lay.invdiag32), f32(lay.x32), f32(lay.r32),
+                      f32(lay.p32), dctx, f64(lay.partial), rtol);
+  else
+    launch_pcg_init64(s, vblocks, N, sign, b, u8(lay.mask), f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.p),
+                      dctx, f64(lay.partial), rtol);
+  QE_HIP(hipGetLastError());
+  const int chunk = check_every > 0 ? check_every : 16;
+  int launched = 0;
+  for (;;) {
+    QE_HIP(hipMemcpyAsync(&h, dctx, sizeof(PcgCtx), hipMemcpyDeviceToHost, s));
+    QE_HIP(hipStreamSynchronize(s));
+    if (h.done || launched >= maxit) break;
+    const int nb = std::min(chunk, maxit - launched);
+    for (int k = 0; k < nb; ++k) {
+      if (mixed)
+        launch_pcg_iter32(s, g, tm, vblocks, N, f32(lay.eps32), prob.semi, f32(lay.c32), u8(lay.mask),
+                          f32(lay.invdiag32), f32(lay.x32), f32(lay.r32), f32(lay.p32), f32(lay.y32), dctx,
+                          f64(lay.partial));
+      else
+        launch_pcg_iter64(s, g, tm, vblocks, N, prob.eps_r, prob.semi, f64(lay.c), u8(lay.mask), f64(lay.invdiag),
+                          f64(lay.x), f64(lay.r), f64(lay.p), f64(lay.y), dctx, f64(lay.partial));
+    }
+    QE_HIP(hipGetLastError());
+    launched += nb;
+  }
+  *pcg_status = h.done ? h.status : PCG_MAXIT;
+  *iters = h.iters;
+  return QE_OK;
+}
+
+}  // namespace qe
+
+using namespace qe;
+
+// ====================================================================== C ABI
+extern "C" {
+
+void qe_default_options(qe_options* o) {
+  if (!o) return;
+  o->newton_atol = 1e-8;
+  o->newton_maxit = 100;
+  o->ls_max_halvings = 30;
+  o->krylov_rtol_max = 1e-2;
+  o->krylov_maxit = 20000;
+  o->precision = QE_PREC_FP64;
+  o->init_guess = 0;
+  o->check_every = 0;
+}
+
+size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
+  (void)o;
+  if (check_problem(p) != QE_OK) return 0;
+  const long N = (long)p->nx * p->ny * p->nz;
+  const long E = (long)(p->nx - 1) * (p->ny - 1) * (p->nz - 1);
+  // the tile map with the smallest chunk height has the most blocks
+  TileMap tm = make_tilemap(p->nx, p->ny, p->nz, 1);
+  return make_layout(N, E, tm.nblocks, vec_blocks(N), p->n_dir).total;
+}
+
+const char* qe_last_error(void) { return g_last_error.c_str(); }
+
+static void fill_report(qe_report* rep, const qe_report& r) {
+  if (rep) *rep = r;
+}
+
+static qe_status finish(qe_status st, qe_report& r, qe_report* rep) {
+  r.status = st;
+  fill_report(rep, r);
+  return st;
+}
+
+qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* o, double* phi, double* n_nodal,
+                   void* ws, size_t ws_bytes, void* stream, qe_report* rep) {
+  clear_error();
+  qe_report r;
+  std::memset(&r, 0, sizeof(r));
+  Charge ch, lin;
+  qe_status st;
+  if ((st = check_options(o)) != QE_OK) return finish(st, r, rep);
+  if ((st = make_charge(ph, ch)) != QE_OK) return finish(st, r, rep);
+  if (!phi) return finish(fail(QE_ERR_INVALID_ARG, "phi is NULL"), r, rep);
+  Context cx;
+  if ((st = cx.init(p, ws, ws_bytes, stream)) != QE_OK) return finish(st, r, rep);
+  const bool mixed = o->precision == QE_PREC_MIXED;
+  if ((st = cx.validate(o->init_guess == 1 ? phi : nullptr)) != QE_OK) return finish(st, r, rep);
+  if ((st = cx.stage(phi, 1, o->init_guess == 0 ? 1 : 0)) != QE_OK) return finish(st, r, rep);
+  if (mixed) {
+    launch_cast_d2f(cx.s, cx.vblocks, cx.E, p->eps_r, cx.f32(cx.lay.eps32));
+    if (hipGetLastError() != hipSuccess) return finish(fail(QE_ERR_HIP, "cast launch failed"), r, rep);
+  }
+  const int check = o->check_every;
+  int pst = 0, its = 0;
+  if (o->init_guess == 0) {
+    // charge-free linear Poisson with the doping kept: one Newton step from
+    // phi = (Dirichlet values, 0) on the linear problem
+    lin = ch;
+    lin.stat = STAT_LINEAR;
+    double n2;
+    if ((st = cx.residual(lin, phi, nullptr, nullptr, 0.0, mixed, nullptr, &n2)) != QE_OK) return finish(st, r, rep);
+    if (!std::isfinite(n2)) return finish(fail(QE_ERR_NONFINITE, "initial residual not finite"), r, rep);
+    if (n2 > 0) {
+      if ((st = cx.pcg(mixed, cx.f64(cx.lay.F), -1.0, mixed ? 1e-6 : 1e-8, o->krylov_maxit, check, &pst, &its)) != QE_OK)
+        return finish(st, r, rep);
+      r.init_krylov_iters = its;
+      r.krylov_iters += its;
+      if (pst == PCG_BREAKDOWN || pst == PCG_NONFINITE)
+        return finish(fail(pst == PCG_BREAKDOWN ? QE_ERR_KRYLOV_BREAKDOWN : QE_ERR_NONFINITE,
+                           "linear initial guess: CG failed (status %d)", pst), r, rep);
+      launch_axpy_phi(cx.s, cx.vblocks, cx.N, phi, mixed ? nullptr : cx.f64(cx.lay.x),
+                      mixed ? cx.f32(cx.lay.x32) : nullptr, 1.0);
+    }
+  }
+  double n2;
+  if ((st = cx.residual(ch, phi, nullptr, nullptr, 0.0, mixed, nullptr, &n2)) != QE_OK) return finish(st, r, rep);
+  r.n_residual_evals++;
+  double nrm = std::sqrt(n2), prev = -1.0;
+  r.res0 = nrm;
+  r.res_final = nrm;
+  if (!std::isfinite(nrm)) return finish(fail(QE_ERR_NONFINITE, "residual not finite at the initial guess"), r, rep);
+  st = QE_ERR_NOT_CONVERGED;
+  for (int it = 0; it <= o->newton_maxit; ++it) {
+    if (nrm <= o->newton_atol) {
+      st = QE_OK;
+      break;
+    }
+    if (it == o->newton_maxit) break;
+    double eta = prev < 0 ? o->krylov_rtol_max : std::min(o->krylov_rtol_max, 0.1 * (nrm / prev) * (nrm / prev));
+    eta = std::max(eta, 0.5 * o->newton_atol / nrm);
+    eta = std::min(eta, o->krylov_rtol_max);
+    eta = std::max(eta, mixed ? 1e-6 : 1e-13);
+    qe_status s2 = cx.pcg(mixed, cx.f64(cx.lay.F), -1.0, eta, o->krylov_maxit, check, &pst, &its);
+    if (s2 != QE_OK) return finish(s2, r, rep);
+    r.krylov_iters += its;
+    if (pst == PCG_BREAKDOWN || pst == PCG_NONFINITE) {
+      st = fail(pst == PCG_BREAKDOWN ? QE_ERR_KRYLOV_BREAKDOWN : QE_ERR_NONFINITE, "Newton step %d: CG failed (status %d)",
+                it, pst);
+      break;
+    }
+    double lam = 1.0, nt = 0.0;
+    bool ok = false;
+    for (int hv = 0; hv <= o->ls_max_halvings; ++hv) {
+      if ((s2 = cx.residual(ch, phi, mixed ? nullptr : cx.f64(cx.lay.x), mixed ? cx.f32(cx.lay.x32) : nullptr, lam,
+                            mixed, nullptr, &n2)) != QE_OK)
+        return finish(s2, r, rep);
+      r.n_residual_evals++;
+      nt = std::sqrt(n2);
+      if (std::isfinite(nt) && nt <= (1.0 - 1e-4 * lam) * nrm) {
+        ok = true;
+        break;
+      }
+      lam *= 0.5;
+      r.ls_halvings++;
+    }
+    if (!ok) {
+      st = fail(QE_ERR_LINESEARCH, "line search failed at Newton step %d (||F|| = %.3e)", it, nrm);
+      break;
+    }
+    launch_axpy_phi(cx.s, cx.vblocks, cx.N, phi, mixed ? nullptr : cx.f64(cx.lay.x),
+                    mixed ? cx.f32(cx.lay.x32) : nullptr, lam);
+    prev = nrm;
+    nrm = nt;
+    r.newton_iters = it + 1;
+    r.res_final = nrm;
+  }
+  if (st == QE_ERR_NOT_CONVERGED)
+    fail(st, "Newton did not reach atol %.3e in %d steps (||F|| = %.3e)", o->newton_atol, o->newton_maxit, nrm);
+  if (n_nodal) launch_density(cx.s, cx.vblocks, cx.g, ch, p->semi, phi, n_nodal);
+  if (hipStreamSynchronize(cx.s) != hipSuccess || hipGetLastError() != hipSuccess)
+    return finish(fail(QE_ERR_HIP, "stream error at the end of the solve"), r, rep);
+  return finish(st, r, rep);
+}
+
+qe_status qe_residual(const qe_problem* p, const qe_physics* ph, const double* phi, double* F, double* diag,
+                      double* norm2, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  Charge ch;
+  QE_TRY(make_charge(ph, ch));
+  if (!phi || !F) return fail(QE_ERR_INVALID_ARG, "phi/F is NULL");
+  Context cx;
+  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.validate(phi));
+  QE_TRY(cx.stage(nullptr, 0, 0));
+  double n2;
+  QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, false, diag, &n2));
+  QE_HIP(hipMemcpyAsync(F, cx.ws + cx.lay.F, cx.N * sizeof(double), hipMemcpyDeviceToDevice, cx.s));
+  QE_HIP(hipStreamSynchronize(cx.s));
+  if (norm2) *norm2 = n2;
+  return QE_OK;
+}
+
+qe_status qe_jv(const qe_problem* p, const qe_physics* ph, const double* phi, const double* v, double* y, void* ws,
+                size_t ws_bytes, void* stream) {
+  clear_error();
+  Charge ch;
+  QE_TRY(make_charge(ph, ch));
+  if (!phi || !v || !y) return fail(QE_ERR_INVALID_ARG, "phi/v/y is NULL");
+  Context cx;
+  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.validate(phi));
+  QE_TRY(cx.stage(nullptr, 0, 0));
+  QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, false, nullptr, nullptr));
+  launch_jv64(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, y, 1, nullptr, nullptr);
+  QE_HIP(hipGetLastError());
+  QE_HIP(hipStreamSynchronize(cx.s));
+  return QE_OK;
+}
+
+qe_status qe_jv_f32(const qe_problem* p, const qe_physics* ph, const double* phi, const float* v, float* y, void* ws,
+                    size_t ws_bytes, void* stream) {
+  clear_error();
+  Charge ch;
+  QE_TRY(make_charge(ph, ch));
+  if (!phi || !v || !y) return fail(QE_ERR_INVALID_ARG, "phi/v/y is NULL");
+  Context cx;
+  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.validate(phi));
+  QE_TRY(cx.stage(nullptr, 0, 0));
+  QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, true, nullptr, nullptr));
+  launch_cast_d2f(cx.s, cx.vblocks, cx.E, p->eps_r, cx.f32(cx.lay.eps32));
+  launch_jv32(cx.s, cx.g, cx.tm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v, y, 1,
+              nullptr, nullptr);
+  QE_HIP(hipGetLastError());
+  QE_HIP(hipStreamSynchronize(cx.s));
+  return QE_OK;
+}
+
+qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* phi, const double* v,
+                     int32_t precision, int32_t reps, double* ms_per_apply, void* ws, size_t ws_bytes,
+                     void* stream) {
+  clear_error();
+  Charge ch;
+  QE_TRY(make_charge(ph, ch));
+  if (!phi || !v || !ms_per_apply) return fail(QE_ERR_INVALID_ARG, "phi/v/ms_per_apply is NULL");
+  if (reps < 1) return fail(QE_ERR_INVALID_ARG, "reps < 1");
+  if (precision != QE_PREC_FP64 && precision != QE_PREC_MIXED) return fail(QE_ERR_INVALID_ARG, "bad precision");
+  const bool mixed = precision == QE_PREC_MIXED;
+  Context cx;
+  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.validate(phi));
+  QE_TRY(cx.stage(nullptr, 0, 0));
+  QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, mixed, nullptr, nullptr));
+  if (mixed) {
+    launch_cast_d2f(cx.s, cx.vblocks, cx.E, p->eps_r, cx.f32(cx.lay.eps32));
+    launch_cast_d2f(cx.s, cx.vblocks, cx.N, v, cx.f32(cx.lay.p32));
+  }
+  hipEvent_t e0, e1;
+  QE_HIP(hipEventCreate(&e0));
+  QE_HIP(hipEventCreate(&e1));
+  auto once = [&]() {
+    if (mixed)
+      launch_jv32(cx.s, cx.g, cx.tm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask),
+                  cx.f32(cx.lay.p32), cx.f32(cx.lay.y32), 1, nullptr, nullptr);
+    else
+      launch_jv64(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, cx.f64(cx.lay.y), 1,
+                  nullptr, nullptr);
+  };
+  once();  // warm-up
+  hipError_t e = hipEventRecord(e0, cx.s);
+  for (int k = 0; k < reps && e == hipSuccess; ++k) once();
+  if (e == hipSuccess) e = hipEventRecord(e1, cx.s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(QE_ERR_HIP, "timing failed: %s", hipGetErrorString(e));
+  *ms_per_apply = (double)ms / reps;
+  return QE_OK;
+}
+
+qe_status qe_count_electrons(const qe_problem* p, const qe_physics* ph, const double* phi, int32_t n_boxes,
+                             const double* boxes, double* counts, void* ws, size_t ws_bytes, void* stream) {
+  clear_error();
+  Charge ch;
+  QE_TRY(make_charge(ph, ch));
+  if (!phi || !boxes || !counts) return fail(QE_ERR_INVALID_ARG, "phi/boxes/counts is NULL");
+  if (n_boxes < 1 || n_boxes > kMaxBoxes) return fail(QE_ERR_INVALID_ARG, "n_boxes must be in [1, %d]", kMaxBoxes);
+  BoxSet bs;
+  bs.n = n_boxes;
+  for (int r = 0; r < n_boxes; ++r) {
+    const double* b = boxes + 6 * r;
+    for (int k = 0; k < 6; ++k)
+      if (std::isnan(b[k])) return fail(QE_ERR_INVALID_ARG, "box %d has NaN", r);
+    bs.b[r] = Box{b[0], b[1], b[2], b[3], b[4], b[5]};
+  }
+  Context cx;
+  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.validate(phi));
+  launch_count(cx.s, kCountBlocks, cx.g, ch, bs, p->semi, phi, cx.f64(cx.lay.partial),
+               reinterpret_cast<unsigned int*>(cx.ws + cx.lay.counters) + 1, cx.f64(cx.lay.scal));
+  QE_HIP(hipGetLastError());
+  QE_HIP(hipMemcpyAsync(mirror().scal, cx.ws + cx.lay.scal, n_boxes * sizeof(double), hipMemcpyDeviceToHost, cx.s));
+  QE_HIP(hipStreamSynchronize(cx.s));
+  for (int r = 0; r < n_boxes; ++r) counts[r] = mirror().scal[r];
+  return QE_OK;
+}
+
+qe_status qe_density(const qe_problem* p, const qe_physics* ph, const double* phi, double* n, void* ws,
+                     size_t ws_bytes, void* stream) {
+  clear_error();
+  Charge ch;
+  QE_TRY(make_charge(ph, ch));
+  if (!phi || !n) return fail(QE_ERR_INVALID_ARG, "phi/n is NULL");
+  Context cx;
+  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.validate(phi));
+  launch_density(cx.s, cx.vblocks, cx.g, ch, p->semi, phi, n);
+  QE_HIP(hipGetLastError());
+  QE_HIP(hipStreamSynchronize(cx.s));
+  return QE_OK;
+}
+
+qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options* o, const double* phi,
+                     const double* box, double* Q, double* dQ_ddir, double* dQ_deps, double* lam, void* ws,
+                     size_t ws_bytes, void* stream, qe_report* rep) {
+  clear_error();
+  qe_report r;
+  std::memset(&r, 0, sizeof(r));
+  Charge ch;
+  qe_status st;
+  if ((st = check_options(o)) != QE_OK) return finish(st, r, rep);
+  if (o->precision != QE_PREC_FP64) return finish(fail(QE_ERR_INVALID_ARG, "the adjoint runs in FP64"), r, rep);
+  if ((st = make_charge(ph, ch)) != QE_OK) return finish(st, r, rep);
+  if (!phi || !box || !dQ_ddir) return finish(fail(QE_ERR_INVALID_ARG, "phi/box/dQ_ddir is NULL"), r, rep);
+  for (int k = 0; k < 6; ++k)
+    if (std::isnan(box[k])) return finish(fail(QE_ERR_INVALID_ARG, "box has NaN"), r, rep);
+  Context cx;
+  if ((st = cx.init(p, ws, ws_bytes, stream)) != QE_OK) return finish(st, r, rep);
+  if ((st = cx.validate(phi)) != QE_OK) return finish(st, r, rep);
+  if (p->n_dir > 56) return finish(fail(QE_ERR_INVALID_ARG, "the adjoint supports at most 56 contacts"), r, rep);
+  if ((st = cx.stage(nullptr, 0, 0)) != QE_OK) return finish(st, r, rep);
+  double n2;
+  if ((st = cx.residual(ch, phi, nullptr, nullptr, 0.0, false, nullptr, &n2)) != QE_OK) return finish(st, r, rep);
+  r.res0 = r.res_final = std::sqrt(n2);
+  unsigned int* counters = reinterpret_cast<unsigned int*>(cx.ws + cx.lay.counters);
+  const Box bx{box[0], box[1], box[2], box[3], box[4], box[5]};
+  launch_adj_rhs(cx.s, cx.g, cx.tm, ch, bx, p->semi, phi, cx.f64(cx.lay.gvec), cx.f64(cx.lay.partial), counters + 2,
+                 cx.f64(cx.lay.scal) + 1);
+  int pst = 0, its = 0;
+  if ((st = cx.pcg(false, cx.f64(cx.lay.gvec), 1.0, 1e-11, o->krylov_maxit, o->check_every, &pst, &its)) != QE_OK)
+    return finish(st, r, rep);
+  r.krylov_iters = its;
+  if (pst == PCG_BREAKDOWN || pst == PCG_NONFINITE)
+    return finish(fail(pst == PCG_BREAKDOWN ? QE_ERR_KRYLOV_BREAKDOWN : QE_ERR_NONFINITE, "adjoint CG failed (status %d)",
+                       pst), r, rep);
+  // dQ/deps goes to the caller's buffer or to scratch (the y vector; E < N)
+  double* deps_buf = dQ_deps ? dQ_deps : cx.f64(cx.lay.y);
+  launch_adj_grad(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), cx.f64(cx.lay.x), phi,
+                  cx.f64(cx.lay.gvec), deps_buf, cx.f64(cx.lay.r));
+  if (p->n_dir > 0)
+    launch_contact_sum(cx.s, kContactBlocks, cx.N, p->n_dir, p->dir_id, cx.f64(cx.lay.r), cx.f64(cx.lay.partial),
+                       counters + 3, cx.f64(cx.lay.scal) + 8);
+  if (hipGetLastError() != hipSuccess) return finish(fail(QE_ERR_HIP, "adjoint launch failed"), r, rep);
+  if (lam && hipMemcpyAsync(lam, cx.ws + cx.lay.x, cx.N * sizeof(double), hipMemcpyDeviceToDevice, cx.s) != hipSuccess)
+    return finish(fail(QE_ERR_HIP, "copy of lam failed"), r, rep);
+  const int nd = p->n_dir;
+  if (hipMemcpyAsync(mirror().scal, cx.ws + cx.lay.scal, 64 * sizeof(double), hipMemcpyDeviceToHost, cx.s) != hipSuccess ||
+      hipStreamSynchronize(cx.s) != hipSuccess)
+    return finish(fail(QE_ERR_HIP, "adjoint read-back failed"), r, rep);
+  if (Q) *Q = mirror().scal[1];
+  for (int c = 0; c < nd; ++c) dQ_ddir[c] = mirror().scal[8 + c];
+  st = (pst == PCG_MAXIT) ? fail(QE_ERR_KRYLOV_MAXIT, "adjoint CG hit krylov_maxit (%d)", its) : QE_OK;
+  return finish(st, r, rep);
+}
+
+}  // extern "C"

@@ -1,0 +1,352 @@
+"""Thin ctypes binding of the C ABI in include/qe.h.
+
+Each ``qe_*`` function here marshals torch device tensors into the C structs
+and calls the function of the same name in ``libqe.so``; every step of the
+computation runs in the HIP kernels behind it.  PyTorch only provides device
+memory and the current stream.  There is no fallback: if the library or a
+GPU is missing, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqe.so")
+
+QE_OK = 0
+STATUS_NAMES = {
+    0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "WORKSPACE", -4: "NOT_CONVERGED",
+    -5: "LINESEARCH", -6: "KRYLOV_BREAKDOWN", -7: "NONFINITE", -8: "KRYLOV_MAXIT",
+}
+STAT = {"linear": 0, "tf": 1, "fd": 2}
+PREC = {"fp64": 0, "mixed": 1}
+
+EXPORTED = [
+    "qe_default_options", "qe_workspace_bytes", "qe_solve", "qe_residual", "qe_jv",
+    "qe_jv_f32", "qe_count_electrons", "qe_density", "qe_adjoint",
+    "qe_batch_workspace_bytes", "qe_solve_batch", "qe_time_jv", "qe_last_error",
+]
+
+
+class QeError(RuntimeError):
+    def __init__(self, status, msg, report=None):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.report = report
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("eps_r", ctypes.c_void_p), ("semi", ctypes.c_void_p),
+                ("net_doping", ctypes.c_void_p), ("dir_id", ctypes.c_void_p),
+                ("dir_val", ctypes.c_void_p), ("n_dir", ctypes.c_int32)]
+
+
+class CPhysics(ctypes.Structure):
+    _fields_ = [("stat", ctypes.c_int32), ("T_K", ctypes.c_double),
+                ("m_eff", ctypes.c_double), ("Ec0_eV", ctypes.c_double)]
+
+
+class COptions(ctypes.Structure):
+    _fields_ = [("newton_atol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
+                ("ls_max_halvings", ctypes.c_int32), ("krylov_rtol_max", ctypes.c_double),
+                ("krylov_maxit", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("init_guess", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class CReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
+                ("krylov_iters", ctypes.c_int32), ("ls_halvings", ctypes.c_int32),
+                ("init_krylov_iters", ctypes.c_int32), ("n_residual_evals", ctypes.c_int32),
+                ("res0", ctypes.c_double), ("res_final", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libqe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1403_7561_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, V, S, D, I32 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double, ctypes.c_int32
+    pp, pph, po, pr = P(CProblem), P(CPhysics), P(COptions), P(CReport)
+    sig = {
+        "qe_default_options": (None, [po]),
+        "qe_workspace_bytes": (S, [pp, po]),
+        "qe_solve": (I32, [pp, pph, po, V, V, V, S, V, pr]),
+        "qe_residual": (I32, [pp, pph, V, V, V, P(D), V, S, V]),
+        "qe_jv": (I32, [pp, pph, V, V, V, V, S, V]),
+        "qe_jv_f32": (I32, [pp, pph, V, V, V, V, S, V]),
+        "qe_count_electrons": (I32, [pp, pph, V, I32, P(D), P(D), V, S, V]),
+        "qe_density": (I32, [pp, pph, V, V, V, S, V]),
+        "qe_adjoint": (I32, [pp, pph, po, V, P(D), P(D), P(D), V, V, V, S, V, pr]),
+        "qe_batch_workspace_bytes": (S, [I32, pp, po]),
+        "qe_solve_batch": (I32, [I32, pp, pph, po, P(V), I32, P(D), P(D), ctypes.c_char_p,
+                                 V, S, V, pr]),
+        "qe_time_jv": (I32, [pp, pph, V, V, I32, I32, P(D), V, S, V]),
+        "qe_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def qe_last_error():
+    return load_library().qe_last_error().decode()
+
+
+def _check(status, report=None):
+    if status != QE_OK:
+        raise QeError(status, qe_last_error(), report)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP library needs a GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@dataclass
+class Physics:
+    stat: str = "fd"
+    T_K: float = 4.0
+    m_eff: float = 1.08
+    Ec0_eV: float = 0.56
+
+    def c(self):
+        return CPhysics(STAT[self.stat], float(self.T_K), float(self.m_eff), float(self.Ec0_eV))
+
+    @classmethod
+    def of(cls, dev):
+        return cls(dev.stat, dev.T_K, dev.m_eff, dev.Ec0_eV)
+
+
+def qe_default_options(**over):
+    o = COptions()
+    load_library().qe_default_options(ctypes.byref(o))
+    for k, v in over.items():
+        if k == "precision" and isinstance(v, str):
+            v = PREC[v]
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """Device copies of one device's arrays plus the C struct pointing at them."""
+
+    def __init__(self, dev, device="cuda"):
+        torch = _torch()
+        f64 = dict(dtype=torch.float64, device=device)
+        self.nx, self.ny, self.nz = dev.nx, dev.ny, dev.nz
+        self.N, self.E = dev.n_nodes, dev.n_elems
+        self.x = torch.as_tensor(np.ascontiguousarray(dev.x), **f64)
+        self.y = torch.as_tensor(np.ascontiguousarray(dev.y), **f64)
+        self.z = torch.as_tensor(np.ascontiguousarray(dev.z), **f64)
+        self.eps_r = torch.as_tensor(np.ascontiguousarray(dev.eps_r), **f64)
+        self.semi = torch.as_tensor(np.ascontiguousarray(dev.semi, dtype=np.uint8), device=device)
+        self.net_doping = torch.as_tensor(np.ascontiguousarray(dev.net_doping), **f64)
+        self.dir_id = torch.as_tensor(np.ascontiguousarray(dev.dir_id, dtype=np.int32), device=device)
+        dv = np.ascontiguousarray(dev.dir_val, dtype=np.float64)
+        self.dir_val = torch.as_tensor(dv if dv.size else np.zeros(1), **f64)
+        self.n_dir = int(dv.size)
+        self.physics = Physics.of(dev) if hasattr(dev, "stat") else Physics()
+        self.device = device
+
+    def c(self):
+        return CProblem(self.nx, self.ny, self.nz, self.x.data_ptr(), self.y.data_ptr(),
+                        self.z.data_ptr(), self.eps_r.data_ptr(), self.semi.data_ptr(),
+                        self.net_doping.data_ptr(), self.dir_id.data_ptr(),
+                        self.dir_val.data_ptr(), self.n_dir)
+
+
+class Workspace:
+    """Caller-owned device scratch sized by qe_workspace_bytes."""
+
+    def __init__(self, nbytes, device="cuda"):
+        torch = _torch()
+        self.t = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+        base = self.t.data_ptr()
+        self.off = (-base) % 256
+        self.ptr = ctypes.c_void_p(base + self.off)
+        self.nbytes = int(nbytes)
+
+
+def qe_workspace_bytes(prob, opts=None):
+    o = opts if opts is not None else qe_default_options()
+    cp = prob.c()
+    return int(load_library().qe_workspace_bytes(ctypes.byref(cp), ctypes.byref(o)))
+
+
+def workspace_for(prob, opts=None):
+    return Workspace(qe_workspace_bytes(prob, opts), prob.device)
+
+
+def qe_solve(prob, phys=None, opts=None, phi=None, want_density=True, ws=None, check=True):
+    """Solve; returns (phi, n_nodal or None, report dict)."""
+    torch = _torch()
+    lib = load_library()
+    phys = phys or prob.physics
+    o = opts if opts is not None else qe_default_options()
+    if phi is None:
+        phi = torch.zeros(prob.N, dtype=torch.float64, device=prob.device)
+    n = torch.empty(prob.N, dtype=torch.float64, device=prob.device) if want_density else None
+    ws = ws or workspace_for(prob, o)
+    cp, cph, rep = prob.c(), phys.c(), CReport()
+    st = lib.qe_solve(ctypes.byref(cp), ctypes.byref(cph), ctypes.byref(o), _ptr(phi), _ptr(n),
+                      ws.ptr, ws.nbytes, _stream(), ctypes.byref(rep))
+    if check:
+        _check(st, rep.as_dict())
+    return phi, n, rep.as_dict()
+
+
+def qe_residual(prob, phi, phys=None, ws=None, want_diag=True):
+    torch = _torch()
+    lib = load_library()
+    phys = phys or prob.physics
+    F = torch.empty(prob.N, dtype=torch.float64, device=prob.device)
+    d = torch.empty_like(F) if want_diag else None
+    n2 = ctypes.c_double(0.0)
+    ws = ws or workspace_for(prob)
+    cp, cph = prob.c(), phys.c()
+    _check(lib.qe_residual(ctypes.byref(cp), ctypes.byref(cph), _ptr(phi), _ptr(F), _ptr(d),
+                           ctypes.byref(n2), ws.ptr, ws.nbytes, _stream()))
+    return F, d, n2.value
+
+
+def qe_jv(prob, phi, v, phys=None, ws=None):
+    torch = _torch()
+    lib = load_library()
+    phys = phys or prob.physics
+    y = torch.empty_like(v)
+    ws = ws or workspace_for(prob)
+    cp, cph = prob.c(), phys.c()
+    fn = lib.qe_jv if v.dtype == torch.float64 else lib.qe_jv_f32
+    _check(fn(ctypes.byref(cp), ctypes.byref(cph), _ptr(phi), _ptr(v), _ptr(y), ws.ptr,
+              ws.nbytes, _stream()))
+    return y
+
+
+def qe_jv_f32(prob, phi, v32, phys=None, ws=None):
+    return qe_jv(prob, phi, v32, phys, ws)
+
+
+def qe_count_electrons(prob, phi, boxes, phys=None, ws=None):
+    lib = load_library()
+    phys = phys or prob.physics
+    b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 6))
+    out = np.zeros(b.shape[0])
+    ws = ws or workspace_for(prob)
+    cp, cph = prob.c(), phys.c()
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(lib.qe_count_electrons(ctypes.byref(cp), ctypes.byref(cph), _ptr(phi), b.shape[0],
+                                  b.ctypes.data_as(P), out.ctypes.data_as(P), ws.ptr, ws.nbytes,
+                                  _stream()))
+    return out
+
+
+def qe_density(prob, phi, phys=None, ws=None):
+    torch = _torch()
+    lib = load_library()
+    phys = phys or prob.physics
+    n = torch.empty(prob.N, dtype=torch.float64, device=prob.device)
+    ws = ws or workspace_for(prob)
+    cp, cph = prob.c(), phys.c()
+    _check(lib.qe_density(ctypes.byref(cp), ctypes.byref(cph), _ptr(phi), _ptr(n), ws.ptr,
+                          ws.nbytes, _stream()))
+    return n
+
+
+def qe_adjoint(prob, phi, box, phys=None, opts=None, ws=None, want_eps=True, want_lam=False,
+               check=True):
+    """Returns (Q, dQ/dV per Dirichlet value [numpy], dQ/deps [device] or None,
+    lam [device] or None, report)."""
+    torch = _torch()
+    lib = load_library()
+    phys = phys or prob.physics
+    o = opts if opts is not None else qe_default_options()
+    b = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(6))
+    dV = np.zeros(max(prob.n_dir, 1))
+    Q = ctypes.c_double(0.0)
+    deps = torch.empty(prob.E, dtype=torch.float64, device=prob.device) if want_eps else None
+    lam = torch.empty(prob.N, dtype=torch.float64, device=prob.device) if want_lam else None
+    ws = ws or workspace_for(prob, o)
+    cp, cph, rep = prob.c(), phys.c(), CReport()
+    P = ctypes.POINTER(ctypes.c_double)
+    st = lib.qe_adjoint(ctypes.byref(cp), ctypes.byref(cph), ctypes.byref(o), _ptr(phi),
+                        b.ctypes.data_as(P), ctypes.byref(Q), dV.ctypes.data_as(P), _ptr(deps),
+                        _ptr(lam), ws.ptr, ws.nbytes, _stream(), ctypes.byref(rep))
+    if check:
+        _check(st, rep.as_dict())
+    return Q.value, dV[:prob.n_dir], deps, lam, rep.as_dict()
+
+
+def qe_time_jv(prob, phi, v, precision="fp64", reps=200, phys=None, ws=None):
+    """Mean time (ms) of one J.v kernel launch, measured with HIP events."""
+    lib = load_library()
+    phys = phys or prob.physics
+    ms = ctypes.c_double(0.0)
+    ws = ws or workspace_for(prob)
+    cp, cph = prob.c(), phys.c()
+    _check(lib.qe_time_jv(ctypes.byref(cp), ctypes.byref(cph), _ptr(phi), _ptr(v), PREC[precision],
+                          int(reps), ctypes.byref(ms), ws.ptr, ws.nbytes, _stream()))
+    return ms.value
+
+
+def qe_batch_workspace_bytes(probs, opts=None):
+    o = opts if opts is not None else qe_default_options()
+    arr = (CProblem * len(probs))(*[p.c() for p in probs])
+    return int(load_library().qe_batch_workspace_bytes(len(probs), arr, ctypes.byref(o)))
+
+
+def qe_solve_batch(probs, phys=None, opts=None, phis=None, boxes=(), tune_cache=None, ws=None,
+                   check=True):
+    """Solve many devices in one persistent launch.  Returns (phis, counts
+    [n_inst, n_boxes], reports)."""
+    torch = _torch()
+    lib = load_library()
+    phys = phys or probs[0].physics
+    o = opts if opts is not None else qe_default_options()
+    n = len(probs)
+    if phis is None:
+        phis = [torch.zeros(p.N, dtype=torch.float64, device=p.device) for p in probs]
+    arr = (CProblem * n)(*[p.c() for p in probs])
+    ptrs = (ctypes.c_void_p * n)(*[ph.data_ptr() for ph in phis])
+    b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 6))
+    counts = np.zeros((n, max(b.shape[0], 1)))
+    reps = (CReport * n)()
+    if ws is None:
+        ws = Workspace(qe_batch_workspace_bytes(probs, o), probs[0].device)
+    P = ctypes.POINTER(ctypes.c_double)
+    cph = phys.c()
+    path = tune_cache.encode() if tune_cache else None
+    st = lib.qe_solve_batch(n, arr, ctypes.byref(cph), ctypes.byref(o), ptrs, b.shape[0],
+                            b.ctypes.data_as(P), counts.ctypes.data_as(P), path, ws.ptr,
+                            ws.nbytes, _stream(), reps)
+    rlist = [reps[i].as_dict() for i in range(n)]
+    if check:
+        _check(st, rlist)
+    return phis, counts[:, : b.shape[0]], rlist

@@ -1,0 +1,144 @@
+"""Host-side checks of the C ABI (no kernel is launched): the library loads,
+exports every function include/qe.h declares, and rejects bad arguments with
+the documented status codes before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1403_7561_amd import qe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "qe.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qe_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = qe.load_library()
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(qe.EXPORTED) == names
+
+
+def test_default_options():
+    o = qe.qe_default_options()
+    assert o.newton_atol == 1e-8 and o.newton_maxit == 100 and o.ls_max_halvings == 30
+    assert o.precision == 0 and o.init_guess == 0
+
+
+def fake_problem(nx=4, ny=3, nz=2, n_dir=1):
+    # pointers are never dereferenced: every call below fails host-side validation first
+    return qe.CProblem(nx, ny, nz, 16, 16, 16, 16, 16, 16, 16, 16 if n_dir else 0, n_dir)
+
+
+@pytest.mark.parametrize("mut,needle", [
+    (dict(nx=1), "nx, ny, nz >= 2"),
+    (dict(nz=0), "nx, ny, nz >= 2"),
+    (dict(eps_r=0), "NULL array"),
+    (dict(dir_id=0), "NULL array"),
+    (dict(n_dir=-1), "n_dir < 0"),
+    (dict(dir_val=0), "dir_val is NULL"),
+])
+def test_invalid_problem_rejected(mut, needle):
+    lib = qe.load_library()
+    p = fake_problem()
+    for k, v in mut.items():
+        setattr(p, k, v)
+    o = qe.qe_default_options()
+    ph = qe.CPhysics(2, 4.0, 1.08, 0.56)
+    rep = qe.CReport()
+    st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                      None, ctypes.c_void_p(256), 1 << 40, None, ctypes.byref(rep))
+    assert st == -1 and rep.status == -1
+    assert needle in qe.qe_last_error()
+    assert lib.qe_workspace_bytes(ctypes.byref(p), ctypes.byref(o)) == 0
+
+
+@pytest.mark.parametrize("field,val,needle", [
+    ("newton_atol", 0.0, "newton_atol"),
+    ("newton_atol", float("nan"), "newton_atol"),
+    ("newton_maxit", -1, "newton_maxit"),
+    ("ls_max_halvings", 99, "ls_max_halvings"),
+    ("krylov_rtol_max", 1.5, "krylov_rtol_max"),
+    ("krylov_maxit", 0, "krylov_maxit"),
+    ("precision", 7, "precision"),
+    ("init_guess", 3, "init_guess"),
+])
+def test_invalid_options_rejected(field, val, needle):
+    lib = qe.load_library()
+    p = fake_problem()
+    o = qe.qe_default_options()
+    setattr(o, field, val)
+    ph = qe.CPhysics(2, 4.0, 1.08, 0.56)
+    st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                      None, ctypes.c_void_p(256), 1 << 40, None, None)
+    assert st == -1 and needle in qe.qe_last_error()
+
+
+@pytest.mark.parametrize("phys,needle", [
+    ((2, 0.0, 1.08, 0.56), "T_K > 0"),
+    ((2, float("inf"), 1.08, 0.56), "T_K > 0"),
+    ((1, 0.0, -1.0, 0.56), "m_eff"),
+    ((9, 4.0, 1.08, 0.56), "unknown statistics"),
+    ((1, 0.0, 1.08, float("nan")), "Ec0_eV"),
+])
+def test_invalid_physics_rejected(phys, needle):
+    lib = qe.load_library()
+    p = fake_problem()
+    o = qe.qe_default_options()
+    ph = qe.CPhysics(*phys)
+    st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                      None, ctypes.c_void_p(256), 1 << 40, None, None)
+    assert st == -1 and needle in qe.qe_last_error()
+
+
+def test_workspace_checks():
+    lib = qe.load_library()
+    p = fake_problem()
+    o = qe.qe_default_options()
+    ph = qe.CPhysics(2, 4.0, 1.08, 0.56)
+    need = lib.qe_workspace_bytes(ctypes.byref(p), ctypes.byref(o))
+    assert need > 0 and need % 256 == 0
+    # NULL, misaligned and short workspaces are rejected before any device work
+    for ws, nb, msg in ((None, need, "NULL"), (ctypes.c_void_p(257), need, "aligned"),
+                        (ctypes.c_void_p(256), need - 1, "too small")):
+        st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                          None, ws, nb, None, None)
+        assert st == -3 and msg in qe.qe_last_error()
+
+
+def test_workspace_scales_with_mesh():
+    lib = qe.load_library()
+    o = qe.qe_default_options()
+    small = lib.qe_workspace_bytes(ctypes.byref(fake_problem(17, 17, 9)), ctypes.byref(o))
+    big = lib.qe_workspace_bytes(ctypes.byref(fake_problem(129, 129, 65)), ctypes.byref(o))
+    N = 129 * 129 * 65
+    assert big > small
+    # about 7 FP64 + 5 FP32 nodal vectors, FP64 + FP32 Gauss-point coefficients
+    assert 150 * N < big < 230 * N
+
+
+def test_count_and_adjoint_argument_checks():
+    lib = qe.load_library()
+    p = fake_problem()
+    ph = qe.CPhysics(1, 0.0, 1.08, 0.56)
+    P = ctypes.POINTER(ctypes.c_double)
+    boxes = np.zeros(6 * 17)
+    out = np.zeros(17)
+    st = lib.qe_count_electrons(ctypes.byref(p), ctypes.byref(ph), ctypes.c_void_p(16), 17,
+                                boxes.ctypes.data_as(P), out.ctypes.data_as(P),
+                                ctypes.c_void_p(256), 1 << 40, None)
+    assert st == -1 and "n_boxes" in qe.qe_last_error()
+    o = qe.qe_default_options(precision=1)
+    st = lib.qe_adjoint(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                        boxes.ctypes.data_as(P), None, out.ctypes.data_as(P), None, None,
+                        ctypes.c_void_p(256), 1 << 40, None, None)
+    assert st == -1 and "FP64" in qe.qe_last_error()
