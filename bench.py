@@ -45,6 +45,8 @@ def cpu_baseline(dev, gpu_newton, budget_s=25.0):
     while steps < max(gpu_newton, 1):
         t0 = time.perf_counter()
         r = solver.newton(prob, phi0=phi_k, atol=1e-8, maxit=1, method="cg")
+        print(f"[bench] oracle Newton step {steps + 1}: {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
         t_steps += time.perf_counter() - t0
         phi_k = r.phi
         steps += 1
@@ -55,6 +57,10 @@ def cpu_baseline(dev, gpu_newton, budget_s=25.0):
             "sample": f"c2 device: assembly + linear initial guess + {steps} Newton step(s) timed "
                       f"({t_setup + t_init + t_steps:.1f} s), full solve extrapolated to "
                       f"{gpu_newton} Newton steps = {est:.1f} s (scipy CSR/CG, single-threaded)"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -90,8 +96,10 @@ def main():
         c = qe.qe_count_electrons(P, ph, boxes, ws=ws)
         return rep, c
 
+    log("warmup")
     for _ in range(args.warmup):
         step()
+    log("timed steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
@@ -103,6 +111,7 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = args.steps / (t1 - t0)
 
+    log(f"{value:.3f} solves/s; timing J.v")
     # J.v kernel alone (HIP events on the library's stream)
     v = torch.randn(P.N, dtype=torch.float64, device="cuda")
     ms64 = qe.qe_time_jv(P, phi, v, "fp64", args.jv_reps, ws=ws)
@@ -138,6 +147,7 @@ def main():
                      "bytes_per_launch": b64},
         "roofline_fp32": {"achieved": b32 / (ms32 * 1e-3) / 1e9, "bytes_per_launch": b32},
     }
+    log("adjoint")
     if not args.no_adjoint:
         dev4 = synth.config4()
         P4 = qe.Problem(dev4)
@@ -153,6 +163,7 @@ def main():
         out["adjoint"] = {"forward_ms": (tb - ta) * 1e3, "adjoint_ms": (tc - tb) * 1e3,
                           "ratio": (tc - tb) / (tb - ta), "Q_D1": Q, "dQ_dV": [float(x) for x in dV],
                           "adjoint_cg_iters": arep["krylov_iters"]}
+    log("cpu baseline")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dev, reps[-1]["newton_iters"])
     print(json.dumps(out), flush=True)

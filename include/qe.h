@@ -200,10 +200,11 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
                          const double* boxes, double* counts, const char* tune_cache,
                          void* ws, size_t ws_bytes, void* stream, qe_report* reps);
 
-/* Benchmark helper: forms the linearisation at phi (device [N]), then applies
- * J.v `reps` times (FP64 or, with QE_PREC_MIXED, FP32) to the vector v
- * (device [N], FP64; converted once for FP32) between two HIP events on
- * `stream`.  ms_per_apply: host, mean kernel time per product. */
+/* Benchmark helper: forms the linearisation at phi (device [N]), zeroes the
+ * Dirichlet entries of v (device [N], FP64; rounded once to FP32 with
+ * QE_PREC_MIXED) as the CG iteration keeps them, then launches the CG J.v
+ * kernel `reps` times between two HIP events on `stream`.
+ * ms_per_apply: host, mean kernel time per product. */
 qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* phi, const double* v,
                      int32_t precision, int32_t reps, double* ms_per_apply, void* ws, size_t ws_bytes,
                      void* stream);

@@ -24,6 +24,8 @@ constexpr int kNYL = kTY + 2;
 constexpr int kNEL = kEX * kEY;       // elements per tile layer (289)
 constexpr int kNNL = kNXL * kNYL;     // staged nodes per plane (324)
 constexpr int kThreads = 256;         // 4 waves of 64
+constexpr int kJvThreads = 320;       // 5 waves: one thread per tile element (289)
+constexpr int kMaxKz = 16;            // node planes per chunk, at most
 constexpr int kVecThreads = 256;
 
 constexpr double kG1 = 0.78867513459481288225;   // (1 + 1/sqrt(3)) / 2
@@ -66,6 +68,20 @@ __device__ __forceinline__ void tile_of_block(int b, const TileMap& tm, int& tx,
   t /= tm.gx;
   ty = t % tm.gy;
   tz = t / tm.gy;
+}
+
+// Wave tiles of the J.v kernel: gx*gy tiles of 7 x 7 owned node columns,
+// gz chunks of kz node planes, four waves per block.
+struct WaveMap {
+  int gx, gy, gz, kz;
+  int nwaves, nblocks;
+};
+
+// XCD-aware block order (see tile_of_block) for the wave-tiled kernels.
+__device__ __forceinline__ int wave_of_block(int b, const WaveMap& wm) {
+  const int per = wm.nblocks >> 3, rem = wm.nblocks & 7;
+  const int xcd = b & 7, loc = b >> 3;
+  return (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
 }
 
 __device__ __forceinline__ int ci(int a, int b, int c) { return a + 2 * b + 4 * c; }
@@ -155,6 +171,76 @@ __device__ __forceinline__ void gauss_interp(T u[8]) { tensor_sym(u, T(kG1), T(k
 template <typename T>
 __device__ __forceinline__ void gauss_sq_project(T u[8]) { tensor_sym(u, T(kG1 * kG1), T(kG0 * kG0)); }
 
+// ---- sum/difference (Haar) form of the element Jacobian ---------------------
+// With H = [[1, 1], [1, -1]] along each axis (H^-1 = H/2):
+//   A = H^-1 diag(0, 2) H,  M = H^-1 diag(1/2, 1/6) H,  B = H^-1 diag(1, 1/sqrt(3)) H,
+// so in the basis H3 = H(x)H(y)H(z) the box-element stiffness is diagonal and
+// the Gauss-point interpolation is diagonal too.  J_e v = Khat v + B3 (c . B3 v)
+// then costs four 8-point transforms, a few scalings and the 8 coefficient
+// products, instead of the axis-by-axis matrices above.
+template <typename T>
+__device__ __forceinline__ void haar3(T u[8]) {
+#pragma unroll
+  for (int p = 0; p < 8; p += 2) {
+    const T a = u[p], b = u[p + 1];
+    u[p] = a + b;
+    u[p + 1] = a - b;
+  }
+#pragma unroll
+  for (int p = 0; p < 8; p += 4)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const T a = u[p + q], b = u[p + q + 2];
+      u[p + q] = a + b;
+      u[p + q + 2] = a - b;
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const T a = u[q], b = u[q + 4];
+    u[q] = a + b;
+    u[q + 4] = a - b;
+  }
+}
+
+// out = (eps Khat + B3 diag(c) B3) v on one box element; sx = eps hy hz / hx,
+// sy = eps hx hz / hy, sz = eps hx hy / hz; c may be skipped (insulator).
+template <typename T>
+__device__ __forceinline__ void jv_element(const T v[8], T sx, T sy, T sz, const T c[8], bool have_c, T out[8]) {
+  // Khat diagonal in the Haar basis, times the 1/8 of the final inverse transform
+  const T k2 = T(1.0 / 16.0), k6 = T(1.0 / 48.0), k18 = T(1.0 / 144.0);
+  T dk[8];
+  dk[0] = T(0);
+  dk[1] = sx * k2;
+  dk[2] = sy * k2;
+  dk[3] = (sx + sy) * k6;
+  dk[4] = sz * k2;
+  dk[5] = (sx + sz) * k6;
+  dk[6] = (sy + sz) * k6;
+  dk[7] = (sx + sy + sz) * k18;
+  T vt[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) vt[k] = v[k];
+  haar3(vt);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) out[k] = dk[k] * vt[k];
+  if (have_c) {
+    // D_B / 8 : (1/sqrt3)^(number of difference axes) / 8
+    const T b0 = T(0.125), b1 = T(0.07216878364870322), b2 = T(0.041666666666666664),
+            b3 = T(0.024056261216234407);
+    const T db[8] = {b0, b1, b1, b2, b1, b2, b2, b3};
+    T q[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = db[k] * vt[k];
+    haar3(q);  // Gauss-point values
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] *= c[k];
+    haar3(q);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] += db[k] * q[k];
+  }
+  haar3(out);
+}
+
 // ---- charge statistics ----------------------------------------------------
 // n(phi) and dn/dphi.  Fermi-Dirac uses Bednarczyk's F_1/2 with its exact
 // derivative, and exp(eta) below eta = -50; Thomas-Fermi is its T -> 0 limit.
@@ -195,6 +281,14 @@ __device__ __forceinline__ double electron_density_only(const Charge& ch, double
   double n, dn;
   electron_density(ch, phi, n, dn);
   return n;
+}
+
+// Block barrier that orders LDS only: unlike __syncthreads() it does not wait
+// for outstanding global loads, so prefetches stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // ---- reductions -------------------------------------------------------------

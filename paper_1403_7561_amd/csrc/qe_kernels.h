@@ -22,25 +22,21 @@ struct BoxSet {
 
 enum PcgStatus : int { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_BREAKDOWN = 2, PCG_MAXIT = 3, PCG_NONFINITE = 4 };
 
-// Conjugate-gradient scalars, kept on the device between kernels.  Counters
-// serve the last-block reductions and are reset by the block that uses them.
+// Conjugate-gradient scalars, kept on the device between kernels.
 struct PcgCtx {
-  double rz, pAp, alpha, beta, rr, rr0, tol2, pad;
+  double rzs[2], pAp, alpha, beta, rr, rr0, tol2;
   int iters, maxit, done, status;
-  unsigned int cnt_jv, cnt_upd, cnt_init, cnt_misc;
 };
 
 void launch_residual(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const double* eps,
                      const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
                      const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
                      double* diag_out, double* cq, float* cq32, float* invdiag32, double* partial,
-                     unsigned int* counter, double* norm2);
+                     double* norm2);
 void launch_jv64(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
-                 const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows, PcgCtx* ctx,
-                 double* partial);
+                 const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows);
 void launch_jv32(hipStream_t s, const Geom& g, const TileMap& tm, const float* eps, const uint8_t* semi,
-                 const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows, PcgCtx* ctx,
-                 double* partial);
+                 const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows);
 void launch_adj_rhs(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const Box& box,
                     const uint8_t* semi, const double* phi, double* gvec, double* partial, unsigned int* counter,
                     double* Q);
@@ -58,19 +54,44 @@ void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, cons
 void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, const double* dir_val, uint8_t* mask,
                   double* phi, int apply, int zero_free);
 void launch_cast_d2f(hipStream_t s, int nblocks, long n, const double* a, float* b);
+void launch_masked_copy_d2d(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, double* b);
+void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, float* b);
+// The J.v kernel exactly as CG launches it (p must vanish on Dirichlet nodes).
+void launch_jv_pcg64(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
+                     const double* cq, const uint8_t* mask, const double* p, double* y, const PcgCtx* ctx,
+                     double* part);
+void launch_jv_pcg32(hipStream_t s, const Geom& g, const TileMap& tm, const float* eps, const uint8_t* semi,
+                     const float* cq, const uint8_t* mask, const float* p, float* y, const PcgCtx* ctx,
+                     double* part);
+WaveMap make_wavemap(int nx, int ny, int nz, int kz);
+void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
+                          const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
+                          const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
+                          double* diag_out, double* cq, float* cq32, float* invdiag32, double* partial,
+                          double* norm2);
+void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const uint8_t* semi,
+                      const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows,
+                      const PcgCtx* ctx, double* part);
+void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const uint8_t* semi,
+                      const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows,
+                      const PcgCtx* ctx, double* part);
 void launch_axpy_phi(hipStream_t s, int nblocks, long N, double* phi, const double* d64, const float* d32,
                      double lam);
-void launch_pcg_init64(hipStream_t s, int nblocks, long N, double sign, const double* b, const uint8_t* mask,
-                       const double* invdiag, double* x, double* r, double* p, PcgCtx* ctx, double* partial,
-                       double rtol);
-void launch_pcg_init32(hipStream_t s, int nblocks, long N, double sign, const double* b, const uint8_t* mask,
-                       const float* invdiag, float* x, float* r, float* p, PcgCtx* ctx, double* partial,
-                       double rtol);
-void launch_pcg_iter64(hipStream_t s, const Geom& g, const TileMap& tm, int vblocks, long N, const double* eps,
-                       const uint8_t* semi, const double* cq, const uint8_t* mask, const double* invdiag, double* x,
-                       double* r, double* p, double* y, PcgCtx* ctx, double* partial);
-void launch_pcg_iter32(hipStream_t s, const Geom& g, const TileMap& tm, int vblocks, long N, const float* eps,
-                       const uint8_t* semi, const float* cq, const uint8_t* mask, const float* invdiag, float* x,
-                       float* r, float* p, float* y, PcgCtx* ctx, double* partial);
+// CG start: x = 0, r = sign*b (free rows), p = D^-1 r, then the scalars.
+void launch_pcg_start64(hipStream_t s, int vblocks, long N, double sign, const double* b, const uint8_t* mask,
+                        const double* invdiag, double* x, double* r, double* p, PcgCtx* ctx, double* part2,
+                        double rtol, int maxit);
+void launch_pcg_start32(hipStream_t s, int vblocks, long N, double sign, const double* b, const uint8_t* mask,
+                        const float* invdiag, float* x, float* r, float* p, PcgCtx* ctx, double* part2,
+                        double rtol, int maxit);
+// CG iteration k: J.v, update, direction (three launches).
+void launch_pcg_iter64(hipStream_t s, const Geom& g, const TileMap& tm, const WaveMap* wm, int vblocks, long N, int k,
+                       const double* eps, const uint8_t* semi, const double* cq, const uint8_t* mask,
+                       const double* invdiag, double* x, double* r, double* p, double* y, PcgCtx* ctx,
+                       double* part_pap, double* part2);
+void launch_pcg_iter32(hipStream_t s, const Geom& g, const TileMap& tm, const WaveMap* wm, int vblocks, long N, int k,
+                       const float* eps, const uint8_t* semi, const float* cq, const uint8_t* mask,
+                       const float* invdiag, float* x, float* r, float* p, float* y, PcgCtx* ctx,
+                       double* part_pap, double* part2);
 
 }  // namespace qe

@@ -10,6 +10,7 @@
 // below and above it.  There are no atomics: every nodal sum is formed in a
 // fixed order, so results are bitwise reproducible.
 #include "qe_kernels.h"
+#include "qe_tiles.h"
 
 namespace qe {
 
@@ -19,6 +20,19 @@ template <typename T, typename Load>
 __device__ __forceinline__ void stage_plane(T* dst, int P, int i0, int j0, const Geom& g, Load load) {
   if (P < 0 || P >= g.nz) return;
   for (int s = threadIdx.x; s < kNNL; s += kThreads) {
+    const int la = s % kNXL, lb = s / kNXL;
+    const int gi = i0 - 1 + la, gj = j0 - 1 + lb;
+    T val = T(0);
+    if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)
+      val = load((long)gi + (long)g.nx * ((long)gj + (long)g.ny * P));
+    dst[s] = val;
+  }
+}
+
+template <int NT, typename T, typename Load>
+__device__ __forceinline__ void stage_plane_n(T* dst, int P, int i0, int j0, const Geom& g, Load load) {
+  if (P < 0 || P >= g.nz) return;
+  for (int s = threadIdx.x; s < kNNL; s += NT) {
     const int la = s % kNXL, lb = s / kNXL;
     const int gi = i0 - 1 + la, gj = j0 - 1 + lb;
     T val = T(0);
@@ -50,46 +64,6 @@ __device__ __forceinline__ void gather4(T (*so)[kNEL], int na, int nb, T& bot, T
   top = so[7][e] + so[6][e + 1] + so[5][e + kEX] + so[4][e + kEX + 1];
 }
 
-template <typename T>
-__device__ __forceinline__ void load8(const T* __restrict__ p, T out[8]);
-
-template <>
-__device__ __forceinline__ void load8<double>(const double* __restrict__ p, double out[8]) {
-  const double2* q = reinterpret_cast<const double2*>(p);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const double2 v = q[i];
-    out[2 * i] = v.x;
-    out[2 * i + 1] = v.y;
-  }
-}
-
-template <>
-__device__ __forceinline__ void load8<float>(const float* __restrict__ p, float out[8]) {
-  const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const float4 v = q[i];
-    out[4 * i] = v.x;
-    out[4 * i + 1] = v.y;
-    out[4 * i + 2] = v.z;
-    out[4 * i + 3] = v.w;
-  }
-}
-
-__device__ __forceinline__ void store8(double* p, const double v[8]) {
-  double2* q = reinterpret_cast<double2*>(p);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
-}
-
-__device__ __forceinline__ void store8(float* p, const double v[8]) {
-  float4* q = reinterpret_cast<float4*>(p);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-    q[i] = make_float4((float)v[4 * i], (float)v[4 * i + 1], (float)v[4 * i + 2], (float)v[4 * i + 3]);
-}
-
 __device__ __forceinline__ long elem_index(const Geom& g, int ex, int ey, int ez) {
   return (long)ex + (long)(g.nx - 1) * ((long)ey + (long)(g.ny - 1) * ez);
 }
@@ -104,8 +78,7 @@ __global__ __launch_bounds__(kThreads) void k_residual(
     const double* __restrict__ netdop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
     const TD* __restrict__ delta, double lam, double* __restrict__ F, double* __restrict__ invdiag,
     double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
-    float* __restrict__ invdiag32, double* __restrict__ partial, unsigned int* counter,
-    double* __restrict__ norm2) {
+    float* __restrict__ invdiag32, double* __restrict__ partial) {
   __shared__ double sv[2][kNNL];
   __shared__ double sF[8][kNEL];
   __shared__ double sD[8][kNEL];
@@ -211,110 +184,292 @@ __global__ __launch_bounds__(kThreads) void k_residual(
   }
   const double s = block_sum(acc, sred);
   if (t == 0) partial[blockIdx.x] = s;
-  if (last_block_done(counter)) {
-    const double tot = reduce_partials(partial, gridDim.x, sred);
-    if (t == 0) {
-      *norm2 = tot;
-      *counter = 0;
+}
+
+// ---------------------------------------------------------------------------
+// y = J v (masked: v is read as 0 on Dirichlet nodes).  Dirichlet rows return
+// v_i when identity_rows is set; with kPcg the CG vectors vanish on Dirichlet
+// nodes, so those rows are written as 0 without reading v.
+//
+// One element per thread and one LDS-only barrier per element layer.  Loads
+// are issued in the order they are needed and never waited on early: at layer
+// L the block first fetches node plane L+2 (value and Dirichlet flag), then
+// the Gauss-point coefficients and permittivity of layer L+1, then computes
+// layer L from LDS and registers.  Three LDS plane buffers, two output
+// buffers; the loop is unrolled by two so the coefficient registers
+// ping-pong instead of being copied.  With kPcg the block also writes its
+// share of p^T J p, formed element by element (each element once, by the
+// tile that owns it).
+template <typename T>
+struct JvTile {
+  T sv[3][kNNL];           // node planes (Dirichlet entries zeroed)
+  uint8_t sm[3][kNNL];     // Dirichlet flags of those planes
+  T so[2][8][kNEL];        // per-element corner contributions
+  uint8_t ssemi[kMaxKz + 1][kNEL];
+  double sred[kJvThreads / 64];
+};
+
+template <typename T, bool kPcg>
+struct JvCtx {
+  const Geom& g;
+  const T* __restrict__ eps;
+  const T* __restrict__ cq;
+  const uint8_t* __restrict__ mask;
+  const T* __restrict__ v;
+  T* __restrict__ y;
+  JvTile<T>& sh;
+  int i0, j0, k0, Lbeg, Lend, t, ea, eb, na, nb, gi, gj;
+  long ecol, elayer;
+  bool col_ok, owned_col, node_ok;
+  double hx, hy;
+  int identity_rows;
+};
+
+__device__ __forceinline__ int plane_slot(int P) { return (P + 3) % 3; }
+
+template <typename T, bool kPcg>
+__device__ __forceinline__ void jv_layer(JvCtx<T, kPcg>& c, int L, T (&cc)[8], T& ee, bool& c_ok, T (&cn)[8],
+                                         T& en, bool& cn_ok, T& carry, double& dot) {
+  const Geom& g = c.g;
+  const int t = c.t;
+  const bool layer_ok = (L >= 0 && L <= g.nz - 2);
+  // 1. node plane L+2 (value and flag, independent loads)
+  const int L1 = L + 1, P2 = L + 2;
+  const bool stage2 = (L1 <= c.Lend && P2 <= g.nz - 1);
+  T st0 = T(0), st1 = T(0);
+  uint8_t m0 = 0, m1 = 0;
+  if (stage2) {
+    {
+      const int gi2 = c.i0 - 1 + t % kNXL, gj2 = c.j0 - 1 + t / kNXL;
+      if (gi2 >= 0 && gi2 < g.nx && gj2 >= 0 && gj2 < g.ny) {
+        const long n = (long)gi2 + (long)g.nx * ((long)gj2 + (long)g.ny * P2);
+        st0 = c.v[n];
+        m0 = c.mask[n];
+      }
     }
+    const int s1 = t + kJvThreads;
+    if (s1 < kNNL) {
+      const int gi2 = c.i0 - 1 + s1 % kNXL, gj2 = c.j0 - 1 + s1 / kNXL;
+      if (gi2 >= 0 && gi2 < g.nx && gj2 >= 0 && gj2 < g.ny) {
+        const long n = (long)gi2 + (long)g.nx * ((long)gj2 + (long)g.ny * P2);
+        st1 = c.v[n];
+        m1 = c.mask[n];
+      }
+    }
+  }
+  // 2. coefficients of layer L+1
+  cn_ok = false;
+  en = T(0);
+  if (c.col_ok && L1 <= c.Lend && L1 <= g.nz - 2) {
+    const long el = c.ecol + c.elayer * L1;
+    en = c.eps[el];
+    if (c.sh.ssemi[L1 - c.Lbeg][t]) {
+      load8(c.cq + 8 * el, cn);
+      cn_ok = true;
+    }
+  }
+  // 3. layer L
+  if (t < kNEL) {
+    T out[8];
+    if (c.col_ok && layer_ok) {
+      const double hz = g.z[L + 1] - g.z[L];
+      const T sx = ee * T(c.hy * hz / c.hx), sy = ee * T(c.hx * hz / c.hy), sz = ee * T(c.hx * c.hy / hz);
+      T ve[8];
+      corners(c.sh.sv[plane_slot(L)], c.sh.sv[plane_slot(L + 1)], c.ea, c.eb, ve);
+      jv_element(ve, sx, sy, sz, cc, c_ok, out);
+      if (kPcg && c.owned_col && L >= c.k0) {
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d += (double)ve[k] * (double)out[k];
+        dot += d;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) out[k] = T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c.sh.so[L & 1][k][t] = out[k];
+  }
+  // 4. publish plane L+2
+  if (stage2) {
+    const int sl = plane_slot(P2);
+    c.sh.sv[sl][t] = m0 ? T(0) : st0;
+    c.sh.sm[sl][t] = m0;
+    if (t + kJvThreads < kNNL) {
+      c.sh.sv[sl][t + kJvThreads] = m1 ? T(0) : st1;
+      c.sh.sm[sl][t + kJvThreads] = m1;
+    }
+  }
+  lds_barrier();
+  // 5. nodes of plane L
+  if (c.node_ok) {
+    T bot = T(0), top = T(0);
+    if (layer_ok) gather4(c.sh.so[L & 1], c.na, c.nb, bot, top);
+    if (L >= c.k0) {
+      const long n = (long)c.gi + (long)g.nx * ((long)c.gj + (long)g.ny * L);
+      T val = carry + bot;
+      if (c.sh.sm[plane_slot(L)][(c.nb + 1) * kNXL + c.na + 1]) {
+        if (kPcg)
+          val = T(0);
+        else if (c.identity_rows)
+          val = c.v[n];
+      }
+      c.y[n] = val;
+    }
+    carry = top;
+  }
+}
+
+template <typename T, bool kPcg>
+__global__ __launch_bounds__(kJvThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_jv(
+    Geom g, TileMap tm, const T* __restrict__ eps, const uint8_t* __restrict__ semi,
+    const T* __restrict__ cq, const uint8_t* __restrict__ mask, const T* __restrict__ v,
+    T* __restrict__ y, int identity_rows, const PcgCtx* ctx, double* __restrict__ part) {
+  if (kPcg && ctx->done) return;
+  __shared__ JvTile<T> sh;
+  int tx, ty, tz;
+  tile_of_block(blockIdx.x, tm, tx, ty, tz);
+  const int t = threadIdx.x;
+  JvCtx<T, kPcg> c{g, eps, cq, mask, v, y, sh};
+  c.i0 = tx * kTX;
+  c.j0 = ty * kTY;
+  c.k0 = tz * tm.kz;
+  c.t = t;
+  c.Lbeg = c.k0 - 1;
+  c.Lend = min(c.k0 + tm.kz - 1, g.nz - 1);
+  c.ea = t % kEX;
+  c.eb = t / kEX;
+  const int ex = c.i0 - 1 + c.ea, ey = c.j0 - 1 + c.eb;
+  c.col_ok = t < kNEL && ex >= 0 && ex < g.nx - 1 && ey >= 0 && ey < g.ny - 1;
+  c.owned_col = c.col_ok && c.ea >= 1 && c.eb >= 1;
+  c.na = t % kTX;
+  c.nb = t / kTX;
+  c.gi = c.i0 + c.na;
+  c.gj = c.j0 + c.nb;
+  c.node_ok = t < kTX * kTY && c.gi < g.nx && c.gj < g.ny;
+  c.hx = c.hy = 1.0;
+  if (c.col_ok) {
+    c.hx = g.x[ex + 1] - g.x[ex];
+    c.hy = g.y[ey + 1] - g.y[ey];
+  }
+  c.ecol = c.col_ok ? (long)ex + (long)(g.nx - 1) * ey : 0;
+  c.elayer = (long)(g.nx - 1) * (g.ny - 1);
+  c.identity_rows = identity_rows;
+  const int nlay = c.Lend - c.Lbeg + 1;
+  // prologue: flags of the chunk, node planes Lbeg and Lbeg+1, layer Lbeg data
+  for (int s = t; s < nlay * kNEL; s += kJvThreads) {
+    const int li = s / kNEL, e = s % kNEL;
+    const int L = c.Lbeg + li;
+    const int xe = c.i0 - 1 + e % kEX, ye = c.j0 - 1 + e / kEX;
+    uint8_t f = 0;
+    if (L >= 0 && L <= g.nz - 2 && xe >= 0 && xe < g.nx - 1 && ye >= 0 && ye < g.ny - 1)
+      f = semi[elem_index(g, xe, ye, L)];
+    sh.ssemi[li][e] = f;
+  }
+  for (int P = c.Lbeg; P <= c.Lbeg + 1; ++P) {
+    if (P < 0 || P >= g.nz) continue;
+    const int sl = plane_slot(P);
+    for (int s = t; s < kNNL; s += kJvThreads) {
+      const int gi2 = c.i0 - 1 + s % kNXL, gj2 = c.j0 - 1 + s / kNXL;
+      T val = T(0);
+      uint8_t m = 0;
+      if (gi2 >= 0 && gi2 < g.nx && gj2 >= 0 && gj2 < g.ny) {
+        const long n = (long)gi2 + (long)g.nx * ((long)gj2 + (long)g.ny * P);
+        m = mask[n];
+        val = m ? T(0) : v[n];
+      }
+      sh.sv[sl][s] = val;
+      sh.sm[sl][s] = m;
+    }
+  }
+  T ca[8], cb[8], ea_ = T(0), eb_ = T(0);
+  bool oka = false, okb = false;
+  __syncthreads();
+  if (c.col_ok && c.Lbeg >= 0 && c.Lbeg <= g.nz - 2) {
+    const long el = c.ecol + c.elayer * c.Lbeg;
+    ea_ = eps[el];
+    if (sh.ssemi[0][t]) {
+      load8(cq + 8 * el, ca);
+      oka = true;
+    }
+  }
+  T carry = T(0);
+  double dot = 0.0;
+  int L = c.Lbeg;
+  if (sizeof(T) == 4) {
+    // ping-pong coefficient registers (fits the register budget in FP32)
+    for (; L + 1 <= c.Lend; L += 2) {
+      jv_layer(c, L, ca, ea_, oka, cb, eb_, okb, carry, dot);
+      jv_layer(c, L + 1, cb, eb_, okb, ca, ea_, oka, carry, dot);
+    }
+    if (L <= c.Lend) jv_layer(c, L, ca, ea_, oka, cb, eb_, okb, carry, dot);
+  } else {
+    for (; L <= c.Lend; ++L) {
+      jv_layer(c, L, ca, ea_, oka, cb, eb_, okb, carry, dot);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ca[k] = cb[k];
+      ea_ = eb_;
+      oka = okb;
+    }
+  }
+  if (kPcg) {
+    const double s = block_sum(dot, sh.sred);
+    if (t == 0) part[blockIdx.x] = s;
   }
 }
 
 // ---------------------------------------------------------------------------
-// y = J v (masked).  With kPcg the block also forms p^T J p and the last
-// block sets alpha = r^T z / p^T J p (or flags a breakdown).
+// Wave-tiled kernels: four independent waves per block, one wave tile each
+// (see qe_tiles.h).  No LDS and no block barrier in the sweep, so memory
+// latency is hidden by the other waves on the SIMD.
+__device__ __forceinline__ void wave_coords(const WaveMap& wm, int& wx, int& wy, int& wz, bool& active) {
+  const int w = wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6);
+  active = w < wm.nwaves;
+  wx = w % wm.gx;
+  wy = (w / wm.gx) % wm.gy;
+  wz = w / (wm.gx * wm.gy);
+}
+
 template <typename T, bool kPcg>
-__global__ __launch_bounds__(kThreads) void k_jv(
-    Geom g, TileMap tm, const T* __restrict__ eps, const uint8_t* __restrict__ semi,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_jv_wave(
+    Geom g, WaveMap wm, const T* __restrict__ eps, const uint8_t* __restrict__ semi,
     const T* __restrict__ cq, const uint8_t* __restrict__ mask, const T* __restrict__ v,
-    T* __restrict__ y, int identity_rows, PcgCtx* ctx, double* __restrict__ partial) {
+    T* __restrict__ y, int identity_rows, const PcgCtx* ctx, double* __restrict__ part) {
   if (kPcg && ctx->done) return;
-  __shared__ T sv[2][kNNL];
-  __shared__ T so[8][kNEL];
-  __shared__ double sred[kThreads / 64];
-  int tx, ty, tz;
-  tile_of_block(blockIdx.x, tm, tx, ty, tz);
-  const int i0 = tx * kTX, j0 = ty * kTY, k0 = tz * tm.kz;
-  const int t = threadIdx.x;
-  const int na = t % kTX, nb = t / kTX;
-  const int gi = i0 + na, gj = j0 + nb;
-  const bool node_ok = gi < g.nx && gj < g.ny;
-  auto ld = [&](long n) -> T { return mask[n] ? T(0) : v[n]; };
-  T carry = T(0);
+  __shared__ double sred[4];
+  int wx, wy, wz;
+  bool active;
+  wave_coords(wm, wx, wy, wz, active);
+  const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   double dot = 0.0;
-  const int Lend = min(k0 + tm.kz - 1, g.nz - 1);
-  stage_plane(sv[(k0 - 1) & 1], k0 - 1, i0, j0, g, ld);
-  for (int L = k0 - 1; L <= Lend; ++L) {
-    stage_plane(sv[(L + 1) & 1], L + 1, i0, j0, g, ld);
-    __syncthreads();
-    const bool layer_ok = (L >= 0 && L <= g.nz - 2);
-    if (layer_ok) {
-      const double hz = g.z[L + 1] - g.z[L];
-      for (int e = t; e < kNEL; e += kThreads) {
-        const int ea = e % kEX, eb = e / kEX;
-        const int ex = i0 - 1 + ea, ey = j0 - 1 + eb;
-        T out[8];
-        if (ex >= 0 && ex < g.nx - 1 && ey >= 0 && ey < g.ny - 1) {
-          const long el = elem_index(g, ex, ey, L);
-          const double hx = g.x[ex + 1] - g.x[ex], hy = g.y[ey + 1] - g.y[ey];
-          const T ee = eps[el];
-          const T sx = ee * T(hy * hz / hx), sy = ee * T(hx * hz / hy), sz = ee * T(hx * hy / hz);
-          T ve[8];
-          corners(sv[L & 1], sv[(L + 1) & 1], ea, eb, ve);
-          stiff_apply(ve, sx, sy, sz, out);
-          if (semi[el]) {
-            T c8[8];
-            load8(cq + 8 * el, c8);
-            gauss_interp(ve);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) ve[q] *= c8[q];
-            gauss_interp(ve);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) out[k] += ve[k];
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) out[k] = T(0);
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) so[k][e] = out[k];
-      }
-    }
-    __syncthreads();
-    if (node_ok) {
-      T bot = T(0), top = T(0);
-      if (layer_ok) gather4(so, na, nb, bot, top);
-      if (L >= k0) {
-        const long n = (long)gi + (long)g.nx * ((long)gj + (long)g.ny * L);
-        T val = carry + bot;
-        if (mask[n]) {
-          if (identity_rows) val = v[n];
-        } else if (kPcg) {
-          dot += (double)sv[L & 1][(nb + 1) * kNXL + na + 1] * (double)val;
-        }
-        y[n] = val;
-      }
-      carry = top;
-    }
-  }
+  jv_tile<T, kPcg>(g, w, eps, semi, cq, mask, v, y, identity_rows, dot);
   if (kPcg) {
-    const double s = block_sum(dot, sred);
-    if (t == 0) partial[blockIdx.x] = s;
-    if (last_block_done(&ctx->cnt_jv)) {
-      const double pAp = reduce_partials(partial, gridDim.x, sred);
-      if (t == 0) {
-        ctx->pAp = pAp;
-        if (!(pAp > 0.0) || !isfinite(pAp)) {
-          ctx->done = 1;
-          ctx->status = PCG_BREAKDOWN;
-          ctx->alpha = 0.0;
-        } else {
-          ctx->alpha = ctx->rz / pAp;
-        }
-        ctx->cnt_jv = 0;
-      }
-    }
+    const double d = wave_sum(dot);
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
   }
+}
+
+template <typename TD>
+__global__ __launch_bounds__(256) void k_residual_wave(
+    Geom g, WaveMap wm, Charge ch, const double* __restrict__ eps, const uint8_t* __restrict__ semi,
+    const double* __restrict__ netdop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
+    const TD* __restrict__ delta, double lam, double* __restrict__ F, double* __restrict__ invdiag,
+    double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
+    float* __restrict__ invdiag32, double* __restrict__ part) {
+  __shared__ double sred[4];
+  int wx, wy, wz;
+  bool active;
+  wave_coords(wm, wx, wy, wz, active);
+  const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
+  double acc = 0.0;
+  residual_tile<TD>(g, w, ch, eps, semi, netdop, mask, phi, delta, lam, F, invdiag, diag_out, cq, cq32, invdiag32,
+                    acc);
+  const double d = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -618,6 +773,14 @@ __global__ __launch_bounds__(kVecThreads) void k_cast(long n, const TS* __restri
     b[i] = (TD)a[i];
 }
 
+// b = a with Dirichlet entries zeroed (converted to TD)
+template <typename TS, typename TD>
+__global__ __launch_bounds__(kVecThreads) void k_masked_copy(long n, const uint8_t* __restrict__ mask,
+                                                            const TS* __restrict__ a, TD* __restrict__ b) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    b[i] = mask[i] ? TD(0) : (TD)a[i];
+}
+
 // phi += lam * delta
 template <typename TD>
 __global__ __launch_bounds__(kVecThreads) void k_axpy_phi(long N, double* __restrict__ phi,
@@ -627,14 +790,33 @@ __global__ __launch_bounds__(kVecThreads) void k_axpy_phi(long N, double* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Jacobi-preconditioned CG, scalars kept on the device in PcgCtx.
-// init: x = 0, r = sign*b on free nodes, p = z = D^-1 r; rz, rr0, tol2.
+// Jacobi-preconditioned CG with its scalars on the device.  No kernel of the
+// loop ends with a grid-wide reduction: each block publishes a partial sum and
+// every block of the *next* kernel re-adds all partials in the same fixed
+// order, so all blocks agree on alpha / beta bit for bit.  Iteration k keeps
+// r^T z in ctx->rzs[k & 1]; the host passes k with every launch.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, int stride, int off,
+                                               double* sred) {
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[(long)i * stride + off];
+  a = wave_sum(a);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sred[wid] = a;
+  __syncthreads();
+  double r = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int w = 0; w < nw; ++w) r += sred[w];
+  return r;  // identical in every thread
+}
+
+// x = 0, r = sign*b on free nodes, p = D^-1 r; partials of r^T z and r^T r.
 template <typename T, typename TB>
 __global__ __launch_bounds__(kVecThreads) void k_pcg_init(long N, double sign, const TB* __restrict__ b,
                                                          const uint8_t* __restrict__ mask,
                                                          const T* __restrict__ invdiag, T* __restrict__ x,
-                                                         T* __restrict__ r, T* __restrict__ p, PcgCtx* ctx,
-                                                         double* __restrict__ partial, double rtol) {
+                                                         T* __restrict__ r, T* __restrict__ p,
+                                                         double* __restrict__ part2) {
   __shared__ double sred[kVecThreads / 64];
   double rz = 0.0, rr = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
@@ -649,50 +831,65 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_init(long N, double sign, c
   const double s1 = block_sum(rz, sred);
   const double s2 = block_sum(rr, sred);
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = s1;
-    partial[2 * blockIdx.x + 1] = s2;
+    part2[2 * blockIdx.x] = s1;
+    part2[2 * blockIdx.x + 1] = s2;
   }
-  if (last_block_done(&ctx->cnt_init)) {
-    double a = 0.0, c = 0.0;
-    const volatile double* pp = partial;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) {
-      a += pp[2 * k];
-      c += pp[2 * k + 1];
-    }
-    const double RZ = block_sum(a, sred);
-    const double RR = block_sum(c, sred);
-    if (threadIdx.x == 0) {
-      ctx->rz = RZ;
-      ctx->rr = RR;
-      ctx->rr0 = RR;
-      ctx->tol2 = rtol * rtol * RR;
-      ctx->iters = 0;
-      ctx->alpha = ctx->beta = 0.0;
-      if (!isfinite(RR) || !isfinite(RZ)) {
-        ctx->done = 1;
-        ctx->status = PCG_NONFINITE;
-      } else if (RR == 0.0) {
-        ctx->done = 1;
-        ctx->status = PCG_CONVERGED;
-      } else {
-        ctx->done = 0;
-        ctx->status = PCG_RUNNING;
-      }
-      ctx->cnt_init = 0;
+}
+
+// One block: the starting scalars of a solve.
+__global__ __launch_bounds__(kVecThreads) void k_pcg_init_fin(PcgCtx* ctx, const double* __restrict__ part2, int n,
+                                                             double rtol, int maxit) {
+  __shared__ double sred[kVecThreads / 64];
+  const double RZ = sum_partials(part2, n, 2, 0, sred);
+  const double RR = sum_partials(part2, n, 2, 1, sred);
+  if (threadIdx.x == 0) {
+    ctx->rzs[0] = RZ;
+    ctx->rzs[1] = 0.0;
+    ctx->rr = RR;
+    ctx->rr0 = RR;
+    ctx->tol2 = rtol * rtol * RR;
+    ctx->iters = 0;
+    ctx->maxit = maxit;
+    ctx->alpha = ctx->beta = ctx->pAp = 0.0;
+    if (!isfinite(RR) || !isfinite(RZ)) {
+      ctx->done = 1;
+      ctx->status = PCG_NONFINITE;
+    } else if (RR == 0.0) {
+      ctx->done = 1;
+      ctx->status = PCG_CONVERGED;
+    } else {
+      ctx->done = 0;
+      ctx->status = PCG_RUNNING;
     }
   }
 }
 
-// x += alpha p; r -= alpha y; then rz_new = r^T D^-1 r, rr = r^T r; the last
-// block sets beta and decides convergence.
+// alpha = rz_k / p^T J p (from the J.v partials); x += alpha p; r -= alpha y;
+// partials of r^T D^-1 r and r^T r.
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_pcg_update(long N, T* __restrict__ x, T* __restrict__ r,
+__global__ __launch_bounds__(kVecThreads) void k_pcg_update(long N, int k, T* __restrict__ x, T* __restrict__ r,
                                                            const T* __restrict__ p, const T* __restrict__ y,
                                                            const T* __restrict__ invdiag, PcgCtx* ctx,
-                                                           double* __restrict__ partial) {
+                                                           const double* __restrict__ part_pap, int n_pap,
+                                                           double* __restrict__ part2) {
   if (ctx->done) return;
   __shared__ double sred[kVecThreads / 64];
-  const T alpha = (T)ctx->alpha;
+  const double pAp = sum_partials(part_pap, n_pap, 1, 0, sred);
+  const double rzk = ctx->rzs[k & 1];
+  if (!(pAp > 0.0) || !isfinite(pAp)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctx->pAp = pAp;
+      ctx->done = 1;
+      ctx->status = PCG_BREAKDOWN;
+    }
+    return;
+  }
+  const double a = rzk / pAp;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctx->pAp = pAp;
+    ctx->alpha = a;
+  }
+  const T alpha = (T)a;
   double rz = 0.0, rr = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
     x[i] += alpha * p[i];
@@ -705,47 +902,50 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_update(long N, T* __restric
   const double s1 = block_sum(rz, sred);
   const double s2 = block_sum(rr, sred);
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = s1;
-    partial[2 * blockIdx.x + 1] = s2;
-  }
-  if (last_block_done(&ctx->cnt_upd)) {
-    double a = 0.0, c = 0.0;
-    const volatile double* pp = partial;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) {
-      a += pp[2 * k];
-      c += pp[2 * k + 1];
-    }
-    const double RZ = block_sum(a, sred);
-    const double RR = block_sum(c, sred);
-    if (threadIdx.x == 0) {
-      ctx->beta = RZ / ctx->rz;
-      ctx->rz = RZ;
-      ctx->rr = RR;
-      ctx->iters += 1;
-      if (!isfinite(RR) || !isfinite(RZ)) {
-        ctx->done = 1;
-        ctx->status = PCG_NONFINITE;
-      } else if (RR <= ctx->tol2) {
-        ctx->done = 1;
-        ctx->status = PCG_CONVERGED;
-      } else if (ctx->iters >= ctx->maxit) {
-        ctx->done = 1;
-        ctx->status = PCG_MAXIT;
-      }
-      ctx->cnt_upd = 0;
-    }
+    part2[2 * blockIdx.x] = s1;
+    part2[2 * blockIdx.x + 1] = s2;
   }
 }
 
-// p = D^-1 r + beta p
+// beta = rz_{k+1} / rz_k, convergence test, p = D^-1 r + beta p.  Block 0
+// records the new scalars (rz_{k+1} goes to the other slot, so no block of
+// this kernel can read a value written by it).
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_pcg_dir(long N, const T* __restrict__ r,
-                                                        const T* __restrict__ invdiag, T* __restrict__ p,
-                                                        const PcgCtx* ctx) {
+__global__ __launch_bounds__(kVecThreads) void k_pcg_dir(long N, int k, const T* __restrict__ r,
+                                                        const T* __restrict__ invdiag, T* __restrict__ p, PcgCtx* ctx,
+                                                        const double* __restrict__ part2, int n2) {
   if (ctx->done) return;
-  const T beta = (T)ctx->beta;
+  __shared__ double sred[kVecThreads / 64];
+  const double RZ = sum_partials(part2, n2, 2, 0, sred);
+  const double RR = sum_partials(part2, n2, 2, 1, sred);
+  const double rzk = ctx->rzs[k & 1];
+  const bool bad = !isfinite(RR) || !isfinite(RZ);
+  const bool conv = !bad && RR <= ctx->tol2;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctx->rzs[(k + 1) & 1] = RZ;
+    ctx->rr = RR;
+    ctx->iters = k + 1;
+    ctx->beta = RZ / rzk;
+    if (bad) {
+      ctx->done = 1;
+      ctx->status = PCG_NONFINITE;
+    } else if (conv) {
+      ctx->done = 1;
+      ctx->status = PCG_CONVERGED;
+    }
+  }
+  if (bad || conv) return;
+  const T beta = (T)(RZ / rzk);
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
     p[i] = invdiag[i] * r[i] + beta * p[i];
+}
+
+// One block: sum of n partials (fixed order) into *out.
+__global__ __launch_bounds__(kVecThreads) void k_sum_partials(const double* __restrict__ part, int n,
+                                                             double* __restrict__ out) {
+  __shared__ double sred[kVecThreads / 64];
+  const double s = sum_partials(part, n, 1, 0, sred);
+  if (threadIdx.x == 0) *out = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -757,35 +957,26 @@ void launch_residual(hipStream_t s, const Geom& g, const TileMap& tm, const Char
                      const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
                      const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
                      double* diag_out, double* cq, float* cq32, float* invdiag32, double* partial,
-                     unsigned int* counter, double* norm2) {
+                     double* norm2) {
   if (delta32)
     QE_LAUNCH(k_residual<float>, tm.nblocks, kThreads, s, g, tm, ch, eps, semi, netdop, mask, phi, delta32, lam, F,
-              invdiag, diag_out, cq, cq32, invdiag32, partial, counter, norm2);
+              invdiag, diag_out, cq, cq32, invdiag32, partial);
   else
     QE_LAUNCH(k_residual<double>, tm.nblocks, kThreads, s, g, tm, ch, eps, semi, netdop, mask, phi, delta64, lam, F,
-              invdiag, diag_out, cq, cq32, invdiag32, partial, counter, norm2);
+              invdiag, diag_out, cq, cq32, invdiag32, partial);
+  QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, tm.nblocks, norm2);
 }
 
 void launch_jv64(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
-                 const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows, PcgCtx* ctx,
-                 double* partial) {
-  if (ctx)
-    QE_LAUNCH((k_jv<double, true>), tm.nblocks, kThreads, s, g, tm, eps, semi, cq, mask, v, y, identity_rows, ctx,
-              partial);
-  else
-    QE_LAUNCH((k_jv<double, false>), tm.nblocks, kThreads, s, g, tm, eps, semi, cq, mask, v, y, identity_rows, ctx,
-              partial);
+                 const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows) {
+  QE_LAUNCH((k_jv<double, false>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, v, y, identity_rows,
+            (const PcgCtx*)nullptr, (double*)nullptr);
 }
 
 void launch_jv32(hipStream_t s, const Geom& g, const TileMap& tm, const float* eps, const uint8_t* semi,
-                 const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows, PcgCtx* ctx,
-                 double* partial) {
-  if (ctx)
-    QE_LAUNCH((k_jv<float, true>), tm.nblocks, kThreads, s, g, tm, eps, semi, cq, mask, v, y, identity_rows, ctx,
-              partial);
-  else
-    QE_LAUNCH((k_jv<float, false>), tm.nblocks, kThreads, s, g, tm, eps, semi, cq, mask, v, y, identity_rows, ctx,
-              partial);
+                 const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows) {
+  QE_LAUNCH((k_jv<float, false>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, v, y, identity_rows,
+            (const PcgCtx*)nullptr, (double*)nullptr);
 }
 
 void launch_adj_rhs(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const Box& box,
@@ -829,6 +1020,62 @@ void launch_cast_d2f(hipStream_t s, int nblocks, long n, const double* a, float*
   QE_LAUNCH((k_cast<double, float>), nblocks, kVecThreads, s, n, a, b);
 }
 
+void launch_masked_copy_d2d(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, double* b) {
+  QE_LAUNCH((k_masked_copy<double, double>), nblocks, kVecThreads, s, n, mask, a, b);
+}
+
+void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, float* b) {
+  QE_LAUNCH((k_masked_copy<double, float>), nblocks, kVecThreads, s, n, mask, a, b);
+}
+
+void launch_jv_pcg64(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
+                     const double* cq, const uint8_t* mask, const double* p, double* y, const PcgCtx* ctx,
+                     double* part) {
+  QE_LAUNCH((k_jv<double, true>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, p, y, 1, ctx, part);
+}
+
+void launch_jv_pcg32(hipStream_t s, const Geom& g, const TileMap& tm, const float* eps, const uint8_t* semi,
+                     const float* cq, const uint8_t* mask, const float* p, float* y, const PcgCtx* ctx,
+                     double* part) {
+  QE_LAUNCH((k_jv<float, true>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, p, y, 1, ctx, part);
+}
+
+void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
+                          const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
+                          const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
+                          double* diag_out, double* cq, float* cq32, float* invdiag32, double* partial,
+                          double* norm2) {
+  if (delta32)
+    QE_LAUNCH(k_residual_wave<float>, wm.nblocks, 256, s, g, wm, ch, eps, semi, netdop, mask, phi, delta32, lam, F,
+              invdiag, diag_out, cq, cq32, invdiag32, partial);
+  else
+    QE_LAUNCH(k_residual_wave<double>, wm.nblocks, 256, s, g, wm, ch, eps, semi, netdop, mask, phi, delta64, lam, F,
+              invdiag, diag_out, cq, cq32, invdiag32, partial);
+  QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, wm.nblocks, norm2);
+}
+
+void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const uint8_t* semi,
+                      const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows,
+                      const PcgCtx* ctx, double* part) {
+  if (ctx)
+    QE_LAUNCH((k_jv_wave<double, true>), wm.nblocks, 256, s, g, wm, eps, semi, cq, mask, v, y, identity_rows, ctx,
+              part);
+  else
+    QE_LAUNCH((k_jv_wave<double, false>), wm.nblocks, 256, s, g, wm, eps, semi, cq, mask, v, y, identity_rows, ctx,
+              part);
+}
+
+void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const uint8_t* semi,
+                      const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows,
+                      const PcgCtx* ctx, double* part) {
+  if (ctx)
+    QE_LAUNCH((k_jv_wave<float, true>), wm.nblocks, 256, s, g, wm, eps, semi, cq, mask, v, y, identity_rows, ctx,
+              part);
+  else
+    QE_LAUNCH((k_jv_wave<float, false>), wm.nblocks, 256, s, g, wm, eps, semi, cq, mask, v, y, identity_rows, ctx,
+              part);
+}
+
 void launch_axpy_phi(hipStream_t s, int nblocks, long N, double* phi, const double* d64, const float* d32,
                      double lam) {
   if (d32)
@@ -837,34 +1084,52 @@ void launch_axpy_phi(hipStream_t s, int nblocks, long N, double* phi, const doub
     QE_LAUNCH(k_axpy_phi<double>, nblocks, kVecThreads, s, N, phi, d64, lam);
 }
 
-void launch_pcg_init64(hipStream_t s, int nblocks, long N, double sign, const double* b, const uint8_t* mask,
-                       const double* invdiag, double* x, double* r, double* p, PcgCtx* ctx, double* partial,
-                       double rtol) {
-  QE_LAUNCH((k_pcg_init<double, double>), nblocks, kVecThreads, s, N, sign, b, mask, invdiag, x, r, p, ctx, partial,
-            rtol);
+void launch_pcg_start64(hipStream_t s, int vblocks, long N, double sign, const double* b, const uint8_t* mask,
+                        const double* invdiag, double* x, double* r, double* p, PcgCtx* ctx, double* part2,
+                        double rtol, int maxit) {
+  QE_LAUNCH((k_pcg_init<double, double>), vblocks, kVecThreads, s, N, sign, b, mask, invdiag, x, r, p, part2);
+  QE_LAUNCH(k_pcg_init_fin, 1, kVecThreads, s, ctx, part2, vblocks, rtol, maxit);
 }
 
-void launch_pcg_init32(hipStream_t s, int nblocks, long N, double sign, const double* b, const uint8_t* mask,
-                       const float* invdiag, float* x, float* r, float* p, PcgCtx* ctx, double* partial,
-                       double rtol) {
-  QE_LAUNCH((k_pcg_init<float, double>), nblocks, kVecThreads, s, N, sign, b, mask, invdiag, x, r, p, ctx, partial,
-            rtol);
+void launch_pcg_start32(hipStream_t s, int vblocks, long N, double sign, const double* b, const uint8_t* mask,
+                        const float* invdiag, float* x, float* r, float* p, PcgCtx* ctx, double* part2,
+                        double rtol, int maxit) {
+  QE_LAUNCH((k_pcg_init<float, double>), vblocks, kVecThreads, s, N, sign, b, mask, invdiag, x, r, p, part2);
+  QE_LAUNCH(k_pcg_init_fin, 1, kVecThreads, s, ctx, part2, vblocks, rtol, maxit);
 }
 
-void launch_pcg_iter64(hipStream_t s, const Geom& g, const TileMap& tm, int vblocks, long N, const double* eps,
-                       const uint8_t* semi, const double* cq, const uint8_t* mask, const double* invdiag, double* x,
-                       double* r, double* p, double* y, PcgCtx* ctx, double* partial) {
-  QE_LAUNCH((k_jv<double, true>), tm.nblocks, kThreads, s, g, tm, eps, semi, cq, mask, p, y, 1, ctx, partial);
-  QE_LAUNCH(k_pcg_update<double>, vblocks, kVecThreads, s, N, x, r, p, y, invdiag, ctx, partial);
-  QE_LAUNCH(k_pcg_dir<double>, vblocks, kVecThreads, s, N, r, invdiag, p, ctx);
+void launch_pcg_iter64(hipStream_t s, const Geom& g, const TileMap& tm, const WaveMap* wm, int vblocks, long N, int k,
+                       const double* eps, const uint8_t* semi, const double* cq, const uint8_t* mask,
+                       const double* invdiag, double* x, double* r, double* p, double* y, PcgCtx* ctx,
+                       double* part_pap, double* part2) {
+  int npap = tm.nblocks;
+  if (wm) {
+    QE_LAUNCH((k_jv_wave<double, true>), wm->nblocks, 256, s, g, *wm, eps, semi, cq, mask, p, y, 1, (const PcgCtx*)ctx,
+              part_pap);
+    npap = wm->nblocks;
+  } else {
+    QE_LAUNCH((k_jv<double, true>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, p, y, 1,
+              (const PcgCtx*)ctx, part_pap);
+  }
+  QE_LAUNCH(k_pcg_update<double>, vblocks, kVecThreads, s, N, k, x, r, p, y, invdiag, ctx, part_pap, npap, part2);
+  QE_LAUNCH(k_pcg_dir<double>, vblocks, kVecThreads, s, N, k, r, invdiag, p, ctx, part2, vblocks);
 }
 
-void launch_pcg_iter32(hipStream_t s, const Geom& g, const TileMap& tm, int vblocks, long N, const float* eps,
-                       const uint8_t* semi, const float* cq, const uint8_t* mask, const float* invdiag, float* x,
-                       float* r, float* p, float* y, PcgCtx* ctx, double* partial) {
-  QE_LAUNCH((k_jv<float, true>), tm.nblocks, kThreads, s, g, tm, eps, semi, cq, mask, p, y, 1, ctx, partial);
-  QE_LAUNCH(k_pcg_update<float>, vblocks, kVecThreads, s, N, x, r, p, y, invdiag, ctx, partial);
-  QE_LAUNCH(k_pcg_dir<float>, vblocks, kVecThreads, s, N, r, invdiag, p, ctx);
+void launch_pcg_iter32(hipStream_t s, const Geom& g, const TileMap& tm, const WaveMap* wm, int vblocks, long N, int k,
+                       const float* eps, const uint8_t* semi, const float* cq, const uint8_t* mask,
+                       const float* invdiag, float* x, float* r, float* p, float* y, PcgCtx* ctx,
+                       double* part_pap, double* part2) {
+  int npap = tm.nblocks;
+  if (wm) {
+    QE_LAUNCH((k_jv_wave<float, true>), wm->nblocks, 256, s, g, *wm, eps, semi, cq, mask, p, y, 1, (const PcgCtx*)ctx,
+              part_pap);
+    npap = wm->nblocks;
+  } else {
+    QE_LAUNCH((k_jv<float, true>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, p, y, 1,
+              (const PcgCtx*)ctx, part_pap);
+  }
+  QE_LAUNCH(k_pcg_update<float>, vblocks, kVecThreads, s, N, k, x, r, p, y, invdiag, ctx, part_pap, npap, part2);
+  QE_LAUNCH(k_pcg_dir<float>, vblocks, kVecThreads, s, N, k, r, invdiag, p, ctx, part2, vblocks);
 }
 
 }  // namespace qe

@@ -20,7 +20,7 @@ TileMap make_tilemap(int nx, int ny, int nz, int kz);
 struct Layout {
   size_t F, x, r, p, y, invdiag, gvec, c, mask;
   size_t x32, r32, p32, y32, invdiag32, c32, eps32;
-  size_t partial, ctx, scal, counters, flags;
+  size_t partial, partial2, ctx, scal, counters, flags;
   long n_partial;
   size_t total;
 };
@@ -31,6 +31,8 @@ struct Context {
   qe_problem prob;
   Geom g;
   TileMap tm;
+  WaveMap wm;
+  int jv_impl = 1;
   long N = 0, E = 0;
   int vblocks = 0;
   Layout lay;

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -93,8 +94,8 @@ qe_status make_charge(const qe_physics* ph, Charge& ch) {
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 int vec_blocks(long N) {
-  long b = (N + (long)kVecThreads * 4 - 1) / ((long)kVecThreads * 4);
-  return (int)std::max(1L, std::min(b, 2048L));
+  long b = (N + (long)kVecThreads * 8 - 1) / ((long)kVecThreads * 8);
+  return (int)std::max(1L, std::min(b, 1024L));
 }
 
 TileMap make_tilemap(int nx, int ny, int nz, int kz) {
@@ -107,10 +108,31 @@ TileMap make_tilemap(int nx, int ny, int nz, int kz) {
     kz = 8;
     while (kz > 4 && (long)tm.gx * tm.gy * ((nz + kz - 1) / kz) < 512) kz >>= 1;
   }
-  tm.kz = kz;
+  tm.kz = std::max(1, std::min(kz, kMaxKz));
+  kz = tm.kz;
   tm.gz = (nz + kz - 1) / kz;
   tm.nblocks = tm.gx * tm.gy * tm.gz;
   return tm;
+}
+
+WaveMap make_wavemap(int nx, int ny, int nz, int kz) {
+  WaveMap wm;
+  wm.gx = (nx + 6) / 7;
+  wm.gy = (ny + 6) / 7;
+  if (kz <= 0) {
+    kz = 16;
+    while (kz > 4 && (long)wm.gx * wm.gy * ((nz + kz - 1) / kz) < 4096) kz >>= 1;
+  }
+  wm.kz = std::max(1, std::min(kz, 31));
+  wm.gz = (nz + wm.kz - 1) / wm.kz;
+  wm.nwaves = wm.gx * wm.gy * wm.gz;
+  wm.nblocks = (wm.nwaves + 3) / 4;
+  return wm;
+}
+
+static int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : dflt;
 }
 
 static const int kCountBlocks = 256;
@@ -141,10 +163,12 @@ Layout make_layout(long N, long E, int nblocks_tile, int vblocks, int n_dir) {
   L.c32 = take(E * 32);
   L.eps32 = take(E * 4);
   long np = std::max<long>(nblocks_tile, 2L * vblocks);
+  np = std::max<long>(np, (long)N / 64 + 64);   // wave-tiled J.v: one partial per block
   np = std::max<long>(np, (long)kCountBlocks * kMaxBoxes);
   np = std::max<long>(np, (long)kContactBlocks * std::max(1, n_dir));
   L.n_partial = np;
   L.partial = take(np * 8);
+  L.partial2 = take(2L * vblocks * 8);
   L.ctx = take(sizeof(PcgCtx));
   L.scal = take(64 * 8);
   L.counters = take(16 * sizeof(unsigned int));
@@ -215,6 +239,8 @@ qe_status Context::init(const qe_problem* p, void* ws_, size_t ws_bytes, void* s
   g.y = p->y;
   g.z = p->z;
   tm = make_tilemap(p->nx, p->ny, p->nz, kz);
+  jv_impl = env_int("QE_JV_IMPL", 1);
+  wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
   vblocks = vec_blocks(N);
   lay = make_layout(N, E, tm.nblocks, vblocks, p->n_dir);
   if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
@@ -272,10 +298,14 @@ qe_status Context::stage(double* phi, int apply, int zero_free) {
 
 qe_status Context::residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam,
                             bool mixed, double* diag_out, double* norm2_host) {
-  launch_residual(s, g, tm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
-                  f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
-                  mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial),
-                  reinterpret_cast<unsigned int*>(ws + lay.counters), f64(lay.scal));
+  if (jv_impl)
+    launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
+                         f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
+                         mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial), f64(lay.scal));
+  else
+    launch_residual(s, g, tm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
+                    f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
+                    mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial), f64(lay.scal));
   QE_HIP(hipGetLastError());
   if (norm2_host) {
     QE_HIP(hipMemcpyAsync(mirror().scal, ws + lay.scal, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -291,16 +321,12 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
                        int* pcg_status, int* iters) {
   PcgCtx* dctx = reinterpret_cast<PcgCtx*>(ws + lay.ctx);
   PcgCtx& h = *mirror().ctx;
-  // maxit goes into the device context before the first iteration
-  h = PcgCtx{};
-  h.maxit = maxit;
-  QE_HIP(hipMemcpyAsync(&dctx->maxit, &h.maxit, sizeof(int), hipMemcpyHostToDevice, s));
   if (mixed)
-    launch_pcg_init32(s, vblocks, N, sign, b, u8(lay.mask), f32(lay.invdiag32), f32(lay.x32), f32(lay.r32),
-                      f32(lay.p32), dctx, f64(lay.partial), rtol);
+    launch_pcg_start32(s, vblocks, N, sign, b, u8(lay.mask), f32(lay.invdiag32), f32(lay.x32), f32(lay.r32),
+                       f32(lay.p32), dctx, f64(lay.partial2), rtol, maxit);
   else
-    launch_pcg_init64(s, vblocks, N, sign, b, u8(lay.mask), f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.p),
-                      dctx, f64(lay.partial), rtol);
+    launch_pcg_start64(s, vblocks, N, sign, b, u8(lay.mask), f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.p),
+                       dctx, f64(lay.partial2), rtol, maxit);
   QE_HIP(hipGetLastError());
   const int chunk = check_every > 0 ? check_every : 16;
   int launched = 0;
@@ -310,13 +336,16 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
     if (h.done || launched >= maxit) break;
     const int nb = std::min(chunk, maxit - launched);
     for (int k = 0; k < nb; ++k) {
+      const int it = launched + k;
+      const WaveMap* w = jv_impl ? &wm : nullptr;
       if (mixed)
-        launch_pcg_iter32(s, g, tm, vblocks, N, f32(lay.eps32), prob.semi, f32(lay.c32), u8(lay.mask),
+        launch_pcg_iter32(s, g, tm, w, vblocks, N, it, f32(lay.eps32), prob.semi, f32(lay.c32), u8(lay.mask),
                           f32(lay.invdiag32), f32(lay.x32), f32(lay.r32), f32(lay.p32), f32(lay.y32), dctx,
-                          f64(lay.partial));
+                          f64(lay.partial), f64(lay.partial2));
       else
-        launch_pcg_iter64(s, g, tm, vblocks, N, prob.eps_r, prob.semi, f64(lay.c), u8(lay.mask), f64(lay.invdiag),
-                          f64(lay.x), f64(lay.r), f64(lay.p), f64(lay.y), dctx, f64(lay.partial));
+        launch_pcg_iter64(s, g, tm, w, vblocks, N, it, prob.eps_r, prob.semi, f64(lay.c), u8(lay.mask),
+                          f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.p), f64(lay.y), dctx, f64(lay.partial),
+                          f64(lay.partial2));
     }
     QE_HIP(hipGetLastError());
     launched += nb;
@@ -497,7 +526,11 @@ qe_status qe_jv(const qe_problem* p, const qe_physics* ph, const double* phi, co
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, false, nullptr, nullptr));
-  launch_jv64(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, y, 1, nullptr, nullptr);
+  if (cx.jv_impl)
+    launch_jv_wave64(cx.s, cx.g, cx.wm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, y, 1, nullptr,
+                     nullptr);
+  else
+    launch_jv64(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, y, 1);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -515,8 +548,11 @@ qe_status qe_jv_f32(const qe_problem* p, const qe_physics* ph, const double* phi
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, true, nullptr, nullptr));
   launch_cast_d2f(cx.s, cx.vblocks, cx.E, p->eps_r, cx.f32(cx.lay.eps32));
-  launch_jv32(cx.s, cx.g, cx.tm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v, y, 1,
-              nullptr, nullptr);
+  if (cx.jv_impl)
+    launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v, y, 1,
+                     nullptr, nullptr);
+  else
+    launch_jv32(cx.s, cx.g, cx.tm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v, y, 1);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -537,20 +573,32 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, mixed, nullptr, nullptr));
+  // the CG operand: v with its Dirichlet entries zeroed, as CG keeps it
   if (mixed) {
     launch_cast_d2f(cx.s, cx.vblocks, cx.E, p->eps_r, cx.f32(cx.lay.eps32));
-    launch_cast_d2f(cx.s, cx.vblocks, cx.N, v, cx.f32(cx.lay.p32));
+    launch_masked_copy_d2f(cx.s, cx.vblocks, cx.N, cx.u8(cx.lay.mask), v, cx.f32(cx.lay.p32));
+  } else {
+    launch_masked_copy_d2d(cx.s, cx.vblocks, cx.N, cx.u8(cx.lay.mask), v, cx.f64(cx.lay.p));
   }
+  const PcgCtx* dctx = reinterpret_cast<const PcgCtx*>(cx.ws + cx.lay.ctx);  // zeroed: not done
   hipEvent_t e0, e1;
   QE_HIP(hipEventCreate(&e0));
   QE_HIP(hipEventCreate(&e1));
   auto once = [&]() {
-    if (mixed)
-      launch_jv32(cx.s, cx.g, cx.tm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask),
-                  cx.f32(cx.lay.p32), cx.f32(cx.lay.y32), 1, nullptr, nullptr);
-    else
-      launch_jv64(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, cx.f64(cx.lay.y), 1,
-                  nullptr, nullptr);
+    if (cx.jv_impl) {
+      if (mixed)
+        launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask),
+                         cx.f32(cx.lay.p32), cx.f32(cx.lay.y32), 1, dctx, cx.f64(cx.lay.partial));
+      else
+        launch_jv_wave64(cx.s, cx.g, cx.wm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask),
+                         cx.f64(cx.lay.p), cx.f64(cx.lay.y), 1, dctx, cx.f64(cx.lay.partial));
+    } else if (mixed) {
+      launch_jv_pcg32(cx.s, cx.g, cx.tm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask),
+                      cx.f32(cx.lay.p32), cx.f32(cx.lay.y32), dctx, cx.f64(cx.lay.partial));
+    } else {
+      launch_jv_pcg64(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), cx.f64(cx.lay.p),
+                      cx.f64(cx.lay.y), dctx, cx.f64(cx.lay.partial));
+    }
   };
   once();  // warm-up
   hipError_t e = hipEventRecord(e0, cx.s);

@@ -1,0 +1,300 @@
+// Wave-level element tiles shared by the single-instance kernels and the
+// batched persistent kernel.
+//
+// A wave owns an 8 x 8 column of elements -- lane (lx, ly) = element
+// (7 wx - 1 + lx, 7 wy - 1 + ly) -- and the 7 x 7 node columns that are the
+// (1,1) corner of its elements with lx, ly < 7.  It marches up node planes
+// k0 .. k0+kz-1, computing element layers k0-1 .. k0+kz-1.  The four
+// contributions an owned node receives from one element layer come from
+// lanes +0, +1, +8 and +9 (cross-lane shuffles); the one from the layer below
+// is carried in a register.  Every nodal sum is formed in a fixed order, and
+// every element is "owned" (written / counted) by exactly one wave: the one in
+// which it has lx, ly >= 1 and a layer >= k0.
+#pragma once
+
+#include "qe_device.h"
+
+namespace qe {
+
+template <typename T>
+__device__ __forceinline__ void load8(const T* __restrict__ p, T out[8]);
+
+template <>
+__device__ __forceinline__ void load8<double>(const double* __restrict__ p, double out[8]) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 v = q[i];
+    out[2 * i] = v.x;
+    out[2 * i + 1] = v.y;
+  }
+}
+
+template <>
+__device__ __forceinline__ void load8<float>(const float* __restrict__ p, float out[8]) {
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float4 v = q[i];
+    out[4 * i] = v.x;
+    out[4 * i + 1] = v.y;
+    out[4 * i + 2] = v.z;
+    out[4 * i + 3] = v.w;
+  }
+}
+
+__device__ __forceinline__ void store8(double* p, const double v[8]) {
+  double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
+}
+
+__device__ __forceinline__ void store8(float* p, const double v[8]) {
+  float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    q[i] = make_float4((float)v[4 * i], (float)v[4 * i + 1], (float)v[4 * i + 2], (float)v[4 * i + 3]);
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_down_t(T v, int d) {
+  return __shfl_down(v, d, 64);
+}
+
+// Sum of the four contributions of one element layer to this lane's owned node.
+template <typename T>
+__device__ __forceinline__ void gather_faces(const T out[8], T& bot, T& top) {
+  bot = out[3] + shfl_down_t(out[2], 1) + shfl_down_t(out[1], 8) + shfl_down_t(out[0], 9);
+  top = out[7] + shfl_down_t(out[6], 1) + shfl_down_t(out[5], 8) + shfl_down_t(out[4], 9);
+}
+
+// Geometry of one wave tile.
+struct WaveTile {
+  int lane, lx, ly, ex, ey, gi, gj, k0, Lbeg, Lend;
+  bool col_ok, own_el, node_ok;
+  long n00, ecol, elayer, sxy;
+  double hx, hy;
+
+  __device__ __forceinline__ WaveTile(const Geom& g, int wx, int wy, int wz, int kz, int lane_, bool active) {
+    lane = lane_;
+    lx = lane & 7;
+    ly = lane >> 3;
+    ex = 7 * wx - 1 + lx;
+    ey = 7 * wy - 1 + ly;
+    col_ok = active && ex >= 0 && ex < g.nx - 1 && ey >= 0 && ey < g.ny - 1;
+    own_el = col_ok && lx >= 1 && ly >= 1;
+    gi = 7 * wx + lx;
+    gj = 7 * wy + ly;
+    node_ok = active && lx < 7 && ly < 7 && gi < g.nx && gj < g.ny;
+    k0 = wz * kz;
+    Lbeg = k0 - 1;
+    Lend = min(k0 + kz - 1, g.nz - 1);
+    sxy = (long)g.nx * g.ny;
+    n00 = col_ok ? (long)ex + (long)g.nx * ey : 0;
+    elayer = (long)(g.nx - 1) * (g.ny - 1);
+    ecol = col_ok ? (long)ex + (long)(g.nx - 1) * ey : 0;
+    hx = hy = 1.0;
+    if (col_ok) {
+      hx = g.x[ex + 1] - g.x[ex];
+      hy = g.y[ey + 1] - g.y[ey];
+    }
+  }
+  __device__ __forceinline__ long node(const Geom& g, int L) const { return (long)gi + (long)g.nx * gj + sxy * L; }
+  // semiconductor flags of this column over the chunk, bit (L - Lbeg)
+  __device__ __forceinline__ unsigned int semi_bits(const Geom& g, const uint8_t* __restrict__ semi) const {
+    unsigned int b = 0;
+    if (col_ok)
+      for (int L = max(Lbeg, 0); L <= min(Lend, g.nz - 2); ++L)
+        if (semi[ecol + elayer * L]) b |= 1u << (L - Lbeg);
+    return b;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// J.v on one wave tile (see k_jv_wave).  v is read as 0 on Dirichlet nodes
+// (kPcg: v already vanishes there and Dirichlet rows are written as 0);
+// identity_rows: Dirichlet rows return v_i.  dot accumulates p^T J p over the
+// elements this wave owns (kPcg).
+template <typename T, bool kPcg>
+__device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const T* __restrict__ eps,
+                                        const uint8_t* __restrict__ semi, const T* __restrict__ cq,
+                                        const uint8_t* __restrict__ mask, const T* __restrict__ v,
+                                        T* __restrict__ y, int identity_rows, double& dot) {
+  const unsigned int sbits = w.semi_bits(g, semi);
+  auto face = [&](int P, T f[4]) {
+    const long b = w.n00 + w.sxy * P;
+    const long o[4] = {0, 1, g.nx, g.nx + 1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      T val = v[b + o[k]];
+      if (!kPcg && mask[b + o[k]]) val = T(0);
+      f[k] = val;
+    }
+  };
+  T fb[4], ft[4], fn[4];
+  T cc[8], cn[8], ee = T(0), en = T(0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) fb[k] = ft[k] = fn[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) cc[k] = cn[k] = T(0);
+  if (w.col_ok && w.Lbeg >= 0) face(w.Lbeg, fb);
+  if (w.col_ok && w.Lbeg + 1 <= g.nz - 1) face(w.Lbeg + 1, ft);
+  if (w.col_ok && w.Lbeg >= 0 && w.Lbeg <= g.nz - 2) {
+    const long el = w.ecol + w.elayer * w.Lbeg;
+    ee = eps[el];
+    if (sbits & 1u) load8(cq + 8 * el, cc);
+  }
+  T carry = T(0);
+  for (int L = w.Lbeg; L <= w.Lend; ++L) {
+    const bool layer_ok = (L >= 0 && L <= g.nz - 2);
+    const int L1 = L + 1;
+    // prefetch the next top face and the next layer's coefficients
+    if (w.col_ok && L1 <= w.Lend && L1 + 1 <= g.nz - 1) face(L1 + 1, fn);
+    if (w.col_ok && L1 <= w.Lend && L1 <= g.nz - 2) {
+      const long el = w.ecol + w.elayer * L1;
+      en = eps[el];
+      if ((sbits >> (L1 - w.Lbeg)) & 1u) load8(cq + 8 * el, cn);
+    }
+    T out[8];
+    if (w.col_ok && layer_ok) {
+      const double hz = g.z[L + 1] - g.z[L];
+      const T sx = ee * T(w.hy * hz / w.hx), sy = ee * T(w.hx * hz / w.hy), sz = ee * T(w.hx * w.hy / hz);
+      const T ve[8] = {fb[0], fb[1], fb[2], fb[3], ft[0], ft[1], ft[2], ft[3]};
+      jv_element(ve, sx, sy, sz, cc, ((sbits >> (L - w.Lbeg)) & 1u) != 0, out);
+      if (kPcg && w.own_el && L >= w.k0) {
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) d += (double)ve[k] * (double)out[k];
+        dot += d;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) out[k] = T(0);
+    }
+    T bot, top;
+    gather_faces(out, bot, top);
+    if (w.node_ok && L >= w.k0) {
+      const long n = w.node(g, L);
+      T val = carry + bot;
+      if (mask[n]) {
+        if (kPcg)
+          val = T(0);
+        else if (identity_rows)
+          val = v[n];
+      }
+      y[n] = val;
+    }
+    carry = top;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      fb[k] = ft[k];
+      ft[k] = fn[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cc[k] = cn[k];
+    ee = en;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual F(phi + lam delta), Jacobi diagonal and Gauss-point coefficients
+// c_q = KAPPA semi W n'(phi_q) on one wave tile.  F and the diagonal are
+// written on owned nodes (0 and 1 on Dirichlet rows); c_q by the owning wave.
+// norm2 accumulates F_i^2 over owned free nodes.
+template <typename TD>
+__device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, const Charge& ch,
+                                              const double* __restrict__ eps, const uint8_t* __restrict__ semi,
+                                              const double* __restrict__ netdop, const uint8_t* __restrict__ mask,
+                                              const double* __restrict__ phi, const TD* __restrict__ delta,
+                                              double lam, double* __restrict__ F, double* __restrict__ invdiag,
+                                              double* __restrict__ diag_out, double* __restrict__ cq,
+                                              float* __restrict__ cq32, float* __restrict__ invdiag32,
+                                              double& norm2) {
+  const unsigned int sbits = w.semi_bits(g, semi);
+  auto face = [&](int P, double f[4]) {
+    const long b = w.n00 + w.sxy * P;
+    const long o[4] = {0, 1, g.nx, g.nx + 1};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double val = phi[b + o[k]];
+      if (delta) val += lam * (double)delta[b + o[k]];
+      f[k] = val;
+    }
+  };
+  double fb[4], ft[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) fb[k] = ft[k] = 0.0;
+  if (w.col_ok && w.Lbeg >= 0) face(w.Lbeg, fb);
+  double carryF = 0.0, carryD = 0.0;
+  for (int L = w.Lbeg; L <= w.Lend; ++L) {
+    const bool layer_ok = (L >= 0 && L <= g.nz - 2);
+    if (w.col_ok && L + 1 <= g.nz - 1) face(L + 1, ft);
+    double outF[8], outD[8];
+    if (w.col_ok && layer_ok) {
+      const long el = w.ecol + w.elayer * L;
+      const double hz = g.z[L + 1] - g.z[L];
+      const double ee = eps[el];
+      const double sx = ee * (w.hy * hz / w.hx), sy = ee * (w.hx * hz / w.hy), sz = ee * (w.hx * w.hy / hz);
+      const double ve[8] = {fb[0], fb[1], fb[2], fb[3], ft[0], ft[1], ft[2], ft[3]};
+      double zero[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) zero[k] = 0.0;
+      jv_element(ve, sx, sy, sz, zero, false, outF);          // eps Khat phi
+      const double dg = (sx + sy + sz) * (1.0 / 9.0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) outD[k] = dg;
+      if ((sbits >> (L - w.Lbeg)) & 1u) {
+        const double kw = ch.kappa * w.hx * w.hy * hz * 0.125;
+        const double nd = netdop ? netdop[el] : 0.0;
+        double src[8], cc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) src[k] = ve[k];
+        gauss_interp(src);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          double n, dn;
+          electron_density(ch, src[q], n, dn);
+          src[q] = kw * (nd - n);
+          cc[q] = kw * dn;
+        }
+        if (w.own_el && L >= w.k0) {
+          store8(cq + 8 * el, cc);
+          if (cq32) store8(cq32 + 8 * el, cc);
+        }
+        gauss_interp(src);
+        gauss_sq_project(cc);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          outF[k] -= src[k];
+          outD[k] += cc[k];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) outF[k] = outD[k] = 0.0;
+    }
+    double bF, tF, bD, tD;
+    gather_faces(outF, bF, tF);
+    gather_faces(outD, bD, tD);
+    if (w.node_ok && L >= w.k0) {
+      const long n = w.node(g, L);
+      double f = carryF + bF, d = carryD + bD;
+      if (mask[n]) {
+        f = 0.0;
+        d = 1.0;
+      }
+      F[n] = f;
+      const double id = 1.0 / d;
+      invdiag[n] = id;
+      if (diag_out) diag_out[n] = d;
+      if (invdiag32) invdiag32[n] = (float)id;
+      norm2 += f * f;
+    }
+    carryF = tF;
+    carryD = tD;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fb[k] = ft[k];
+  }
+}
+
+}  // namespace qe
