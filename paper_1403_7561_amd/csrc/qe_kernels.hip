@@ -794,7 +794,9 @@ __global__ __launch_bounds__(kVecThreads) void k_axpy_phi(long N, double* __rest
 // loop ends with a grid-wide reduction: each block publishes a partial sum and
 // every block of the *next* kernel re-adds all partials in the same fixed
 // order, so all blocks agree on alpha / beta bit for bit.  Iteration k keeps
-// r^T z in ctx->rzs[k & 1]; the host passes k with every launch.
+// r^T z in ctx->rzs[k & 1]; the host passes the parity of k with every launch
+// (chunks of iterations have even length, so a captured chunk can be replayed),
+// and block 0 of the direction kernel counts the iterations.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, int stride, int off,
                                                double* sred) {
   double a = 0.0;
@@ -924,7 +926,7 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_dir(long N, int k, const T*
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctx->rzs[(k + 1) & 1] = RZ;
     ctx->rr = RR;
-    ctx->iters = k + 1;
+    ctx->iters += 1;
     ctx->beta = RZ / rzk;
     if (bad) {
       ctx->done = 1;
@@ -932,6 +934,9 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_dir(long N, int k, const T*
     } else if (conv) {
       ctx->done = 1;
       ctx->status = PCG_CONVERGED;
+    } else if (ctx->iters >= ctx->maxit) {
+      ctx->done = 1;
+      ctx->status = PCG_MAXIT;
     }
   }
   if (bad || conv) return;

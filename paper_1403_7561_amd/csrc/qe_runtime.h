@@ -33,6 +33,12 @@ struct Context {
   TileMap tm;
   WaveMap wm;
   int jv_impl = 1;
+  bool use_graphs = true;                   // replay captured CG chunks
+  hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+  ~Context() {
+    if (graph64) (void)hipGraphExecDestroy(graph64);
+    if (graph32) (void)hipGraphExecDestroy(graph32);
+  }
   long N = 0, E = 0;
   int vblocks = 0;
   Layout lay;

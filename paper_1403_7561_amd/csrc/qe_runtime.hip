@@ -240,6 +240,7 @@ qe_status Context::init(const qe_problem* p, void* ws_, size_t ws_bytes, void* s
   g.z = p->z;
   tm = make_tilemap(p->nx, p->ny, p->nz, kz);
   jv_impl = env_int("QE_JV_IMPL", 1);
+  use_graphs = env_int("QE_GRAPHS", 1) != 0;
   wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
   vblocks = vec_blocks(N);
   lay = make_layout(N, E, tm.nblocks, vblocks, p->n_dir);
@@ -328,27 +329,45 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
     launch_pcg_start64(s, vblocks, N, sign, b, u8(lay.mask), f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.p),
                        dctx, f64(lay.partial2), rtol, maxit);
   QE_HIP(hipGetLastError());
-  const int chunk = check_every > 0 ? check_every : 16;
+  int chunk = check_every > 0 ? check_every : 16;
+  chunk += chunk & 1;  // even: a replayed chunk starts on the same parity
+  auto enqueue_chunk = [&](hipStream_t st) {
+    for (int k = 0; k < chunk; ++k) {
+      const WaveMap* w = jv_impl ? &wm : nullptr;
+      if (mixed)
+        launch_pcg_iter32(st, g, tm, w, vblocks, N, k & 1, f32(lay.eps32), prob.semi, f32(lay.c32), u8(lay.mask),
+                          f32(lay.invdiag32), f32(lay.x32), f32(lay.r32), f32(lay.p32), f32(lay.y32), dctx,
+                          f64(lay.partial), f64(lay.partial2));
+      else
+        launch_pcg_iter64(st, g, tm, w, vblocks, N, k & 1, prob.eps_r, prob.semi, f64(lay.c), u8(lay.mask),
+                          f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.p), f64(lay.y), dctx, f64(lay.partial),
+                          f64(lay.partial2));
+    }
+  };
+  // one captured chunk per precision, replayed until CG stops
+  hipGraphExec_t& exec = mixed ? graph32 : graph64;
+  if (!exec && use_graphs && s) {
+    hipGraph_t gr = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      enqueue_chunk(s);
+      if (hipStreamEndCapture(s, &gr) == hipSuccess && gr) {
+        if (hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+        (void)hipGraphDestroy(gr);
+      }
+    }
+    (void)hipGetLastError();
+  }
   int launched = 0;
   for (;;) {
     QE_HIP(hipMemcpyAsync(&h, dctx, sizeof(PcgCtx), hipMemcpyDeviceToHost, s));
     QE_HIP(hipStreamSynchronize(s));
     if (h.done || launched >= maxit) break;
-    const int nb = std::min(chunk, maxit - launched);
-    for (int k = 0; k < nb; ++k) {
-      const int it = launched + k;
-      const WaveMap* w = jv_impl ? &wm : nullptr;
-      if (mixed)
-        launch_pcg_iter32(s, g, tm, w, vblocks, N, it, f32(lay.eps32), prob.semi, f32(lay.c32), u8(lay.mask),
-                          f32(lay.invdiag32), f32(lay.x32), f32(lay.r32), f32(lay.p32), f32(lay.y32), dctx,
-                          f64(lay.partial), f64(lay.partial2));
-      else
-        launch_pcg_iter64(s, g, tm, w, vblocks, N, it, prob.eps_r, prob.semi, f64(lay.c), u8(lay.mask),
-                          f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.p), f64(lay.y), dctx, f64(lay.partial),
-                          f64(lay.partial2));
-    }
+    if (exec)
+      QE_HIP(hipGraphLaunch(exec, s));
+    else
+      enqueue_chunk(s);
     QE_HIP(hipGetLastError());
-    launched += nb;
+    launched += chunk;
   }
   *pcg_status = h.done ? h.status : PCG_MAXIT;
   *iters = h.iters;
