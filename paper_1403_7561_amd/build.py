@@ -29,10 +29,12 @@ def hipcc():
     return exe
 
 
-def build(verbose=False):
+def build(verbose=False, out=None):
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-shared", "-o", tmp, *srcs, f"-I{os.path.join(ROOT, 'include')}"]
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    extra = os.environ.get("QE_EXTRA_FLAGS", "").split()
+    cmd = [hipcc(), *FLAGS, *extra, "-shared", "-o", tmp, *srcs, f"-I{os.path.join(ROOT, 'include')}"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -42,8 +44,8 @@ def build(verbose=False):
         raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
     if verbose and msgs:
         print("\n".join(msgs))
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -40,9 +40,9 @@ struct BatchInst {
   const int32_t* dir_id;
   const double* dir_val;
   double* phi;
-  double *F, *x, *r, *p, *y, *invdiag, *c;
+  double *F, *x, *r, *p, *y, *invdiag, *c, *eps_t;   // c, eps_t tile-major (tile_slot)
   uint8_t* mask;
-  long N;
+  long N, nslots;
   int gx, gy, gz, kz, ntiles;
 };
 
@@ -134,16 +134,16 @@ __device__ int b_pcg(const BatchInst& I, const double* b, double sign, double rt
     *st = PCG_NONFINITE;
     return 0;
   }
-  if (rr == 0.0) {
+  if (rz == 0.0) {
     *st = PCG_CONVERGED;
     return 0;
   }
-  const double tol2 = rtol * rtol * rr;
+  const double tol2 = rtol * rtol * rz;
   for (int it = 0; it < maxit; ++it) {
     double dot = 0.0;
     for (int t = threadIdx.x >> 6; t < I.ntiles; t += NT / 64) {
       const WaveTile w = tile_at(I, t);
-      jv_tile<double, true>(I.g, w, I.eps, I.semi, I.c, I.mask, I.p, I.y, 1, dot);
+      jv_tile<double, true>(I.g, w, I.eps_t, I.semi, I.c, nullptr, I.p, I.y, 1, dot);
     }
     const double pAp = bsum<NT>(dot, sred);
     if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -165,7 +165,7 @@ __device__ int b_pcg(const BatchInst& I, const double* b, double sign, double rt
       *st = PCG_NONFINITE;
       return it + 1;
     }
-    if (rrn <= tol2) {
+    if (rzn <= tol2) {
       *st = PCG_CONVERGED;
       return it + 1;
     }
@@ -186,11 +186,24 @@ __device__ void b_axpy_phi(const BatchInst& I, double lam) {
 
 template <int NT>
 __device__ void b_solve(const BatchParams& bp, const BatchInst& I, BatchOut& o, double* sred) {
-  // stage: Dirichlet mask, Dirichlet values, zeros elsewhere
+  // stage: Dirichlet mask, Dirichlet values, zeros elsewhere; tile-major eps
   for (long n = threadIdx.x; n < I.N; n += NT) {
     const int d = I.dir_id[n];
     I.mask[n] = d >= 0 ? 1 : 0;
     I.phi[n] = d >= 0 ? I.dir_val[d] : 0.0;
+  }
+  {
+    const int gx = (I.g.nx + 6) / 7, gy = (I.g.ny + 6) / 7;
+    for (long sl = threadIdx.x; sl < I.nslots; sl += NT) {
+      const int j = (int)(sl % 49);
+      const long blk = sl / 49;
+      const int tx = (int)(blk % gx), ty = (int)((blk / gx) % gy), L = (int)(blk / ((long)gx * gy));
+      const int ex = 7 * tx + j % 7, ey = 7 * ty + j / 7;
+      double e = 0.0;
+      if (ex < I.g.nx - 1 && ey < I.g.ny - 1)
+        e = I.eps[(long)ex + (long)(I.g.nx - 1) * ((long)ey + (long)(I.g.ny - 1) * L)];
+      I.eps_t[sl] = e;
+    }
   }
   __syncthreads();
   int status = QE_OK, newton = 0, kry = 0, halv = 0, nres = 0, pst = 0;
@@ -315,8 +328,8 @@ static size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 
 static size_t inst_bytes(const qe_problem& p) {
   const long N = (long)p.nx * p.ny * p.nz;
-  const long E = (long)(p.nx - 1) * (p.ny - 1) * (p.nz - 1);
-  return 6 * al256(N * 8) + al256(E * 64) + al256(N);
+  const long S = tile_slots(p.nx, p.ny, p.nz);
+  return 6 * al256(N * 8) + al256(S * 64) + al256(S * 8) + al256(N);
 }
 
 static size_t batch_bytes(int n, const qe_problem* probs) {
@@ -496,7 +509,7 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
     for (int i = 0; i < n_inst; ++i) {
       const qe_problem& p = probs[i];
       BatchInst& I = hinst[i];
-      const long N = (long)p.nx * p.ny * p.nz, E = (long)(p.nx - 1) * (p.ny - 1) * (p.nz - 1);
+      const long N = (long)p.nx * p.ny * p.nz, S = tile_slots(p.nx, p.ny, p.nz);
       I.g = Geom{p.nx, p.ny, p.nz, p.x, p.y, p.z};
       I.eps = p.eps_r;
       I.semi = p.semi;
@@ -516,7 +529,9 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
       I.p = reinterpret_cast<double*>(tk(N * 8));
       I.y = reinterpret_cast<double*>(tk(N * 8));
       I.invdiag = reinterpret_cast<double*>(tk(N * 8));
-      I.c = reinterpret_cast<double*>(tk(E * 64));
+      I.c = reinterpret_cast<double*>(tk(S * 64));
+      I.eps_t = reinterpret_cast<double*>(tk(S * 8));
+      I.nslots = S;
       I.mask = reinterpret_cast<uint8_t*>(tk(N));
       I.kz = cf.kz;
       I.gx = (p.nx + 6) / 7;

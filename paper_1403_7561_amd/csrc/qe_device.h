@@ -84,6 +84,19 @@ __device__ __forceinline__ int wave_of_block(int b, const WaveMap& wm) {
   return (xcd < rem) ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
 }
 
+// Tile-major order of the per-element work arrays (Gauss-point coefficients,
+// staged permittivity): element (ex, ey, L) of 7 x 7 tile (ex/7, ey/7) goes to
+// slot ((L gy + ty) gx + tx) 49 + (ex - 7 tx) + 7 (ey - 7 ty), gx = ceil(nx/7).
+// A wave then reads its 49 owned elements of a layer as one contiguous block.
+__host__ __device__ __forceinline__ long tile_slot(int ex, int ey, int L, int gx, int gy) {
+  const int tx = ex / 7, ty = ey / 7;
+  return ((long)L * gy + ty) * gx * 49L + (long)tx * 49 + (ex - 7 * tx) + 7 * (ey - 7 * ty);
+}
+
+__host__ __device__ __forceinline__ long tile_slots(int nx, int ny, int nz) {
+  return (long)((nx + 6) / 7) * ((ny + 6) / 7) * 49L * (nz - 1);
+}
+
 __device__ __forceinline__ int ci(int a, int b, int c) { return a + 2 * b + 4 * c; }
 
 // ---- 1D operators -------------------------------------------------------
@@ -204,25 +217,24 @@ __device__ __forceinline__ void haar3(T u[8]) {
 
 // out = (eps Khat + B3 diag(c) B3) v on one box element; sx = eps hy hz / hx,
 // sy = eps hx hz / hy, sz = eps hx hy / hz; c may be skipped (insulator).
-template <typename T>
-__device__ __forceinline__ void jv_element(const T v[8], T sx, T sy, T sz, const T c[8], bool have_c, T out[8]) {
+// With kDot, also returns v^T out, taken in the Haar basis before the last
+// transform (H3 is symmetric), so v need not stay live.
+template <typename T, bool kDot = false>
+__device__ __forceinline__ double jv_element(const T v[8], T sx, T sy, T sz, const T c[8], bool have_c, T out[8]) {
   // Khat diagonal in the Haar basis, times the 1/8 of the final inverse transform
   const T k2 = T(1.0 / 16.0), k6 = T(1.0 / 48.0), k18 = T(1.0 / 144.0);
-  T dk[8];
-  dk[0] = T(0);
-  dk[1] = sx * k2;
-  dk[2] = sy * k2;
-  dk[3] = (sx + sy) * k6;
-  dk[4] = sz * k2;
-  dk[5] = (sx + sz) * k6;
-  dk[6] = (sy + sz) * k6;
-  dk[7] = (sx + sy + sz) * k18;
   T vt[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) vt[k] = v[k];
   haar3(vt);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) out[k] = dk[k] * vt[k];
+  out[0] = T(0);
+  out[1] = (sx * k2) * vt[1];
+  out[2] = (sy * k2) * vt[2];
+  out[3] = ((sx + sy) * k6) * vt[3];
+  out[4] = (sz * k2) * vt[4];
+  out[5] = ((sx + sz) * k6) * vt[5];
+  out[6] = ((sy + sz) * k6) * vt[6];
+  out[7] = ((sx + sy + sz) * k18) * vt[7];
   if (have_c) {
     // D_B / 8 : (1/sqrt3)^(number of difference axes) / 8
     const T b0 = T(0.125), b1 = T(0.07216878364870322), b2 = T(0.041666666666666664),
@@ -238,7 +250,13 @@ __device__ __forceinline__ void jv_element(const T v[8], T sx, T sy, T sz, const
 #pragma unroll
     for (int k = 0; k < 8; ++k) out[k] += db[k] * q[k];
   }
+  double d = 0.0;
+  if (kDot) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) d += (double)vt[k] * (double)out[k];
+  }
   haar3(out);
+  return d;
 }
 
 // ---- charge statistics ----------------------------------------------------

@@ -28,15 +28,6 @@ struct PcgCtx {
   int iters, maxit, done, status;
 };
 
-void launch_residual(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const double* eps,
-                     const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
-                     const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
-                     double* diag_out, double* cq, float* cq32, float* invdiag32, double* partial,
-                     double* norm2);
-void launch_jv64(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
-                 const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows);
-void launch_jv32(hipStream_t s, const Geom& g, const TileMap& tm, const float* eps, const uint8_t* semi,
-                 const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows);
 void launch_adj_rhs(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const Box& box,
                     const uint8_t* semi, const double* phi, double* gvec, double* partial, unsigned int* counter,
                     double* Q);
@@ -56,13 +47,6 @@ void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, con
 void launch_cast_d2f(hipStream_t s, int nblocks, long n, const double* a, float* b);
 void launch_masked_copy_d2d(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, double* b);
 void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, float* b);
-// The J.v kernel exactly as CG launches it (p must vanish on Dirichlet nodes).
-void launch_jv_pcg64(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
-                     const double* cq, const uint8_t* mask, const double* p, double* y, const PcgCtx* ctx,
-                     double* part);
-void launch_jv_pcg32(hipStream_t s, const Geom& g, const TileMap& tm, const float* eps, const uint8_t* semi,
-                     const float* cq, const uint8_t* mask, const float* p, float* y, const PcgCtx* ctx,
-                     double* part);
 WaveMap make_wavemap(int nx, int ny, int nz, int kz);
 void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
                           const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
@@ -75,6 +59,9 @@ void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const dou
 void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const uint8_t* semi,
                       const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows,
                       const PcgCtx* ctx, double* part);
+// Tile-major permittivity copy for the wave-tiled J.v (see tile_slot).
+void launch_stage_eps64(hipStream_t s, int nblocks, const Geom& g, const double* eps, double* eps_t, long nslots);
+void launch_stage_eps32(hipStream_t s, int nblocks, const Geom& g, const double* eps, float* eps_t, long nslots);
 void launch_axpy_phi(hipStream_t s, int nblocks, long N, double* phi, const double* d64, const float* d32,
                      double lam);
 // CG start: x = 0, r = sign*b (free rows), p = D^-1 r, then the scalars.
@@ -84,14 +71,12 @@ void launch_pcg_start64(hipStream_t s, int vblocks, long N, double sign, const d
 void launch_pcg_start32(hipStream_t s, int vblocks, long N, double sign, const double* b, const uint8_t* mask,
                         const float* invdiag, float* x, float* r, float* p, PcgCtx* ctx, double* part2,
                         double rtol, int maxit);
-// CG iteration k: J.v, update, direction (three launches).
-void launch_pcg_iter64(hipStream_t s, const Geom& g, const TileMap& tm, const WaveMap* wm, int vblocks, long N, int k,
-                       const double* eps, const uint8_t* semi, const double* cq, const uint8_t* mask,
-                       const double* invdiag, double* x, double* r, double* p, double* y, PcgCtx* ctx,
-                       double* part_pap, double* part2);
-void launch_pcg_iter32(hipStream_t s, const Geom& g, const TileMap& tm, const WaveMap* wm, int vblocks, long N, int k,
-                       const float* eps, const uint8_t* semi, const float* cq, const uint8_t* mask,
-                       const float* invdiag, float* x, float* r, float* p, float* y, PcgCtx* ctx,
-                       double* part_pap, double* part2);
+// CG iteration (parity k): J.v, update, direction (three launches).
+void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int vblocks, long N, int k,
+                       const double* eps_t, const uint8_t* semi, const double* cq, const double* invdiag, double* x,
+                       double* r, double* p, double* y, PcgCtx* ctx, double* part_pap, double* part2);
+void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int vblocks, long N, int k,
+                       const float* eps_t, const uint8_t* semi, const float* cq, const float* invdiag, float* x,
+                       float* r, float* p, float* y, PcgCtx* ctx, double* part_pap, double* part2);
 
 }  // namespace qe

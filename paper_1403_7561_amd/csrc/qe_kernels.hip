@@ -29,19 +29,6 @@ __device__ __forceinline__ void stage_plane(T* dst, int P, int i0, int j0, const
   }
 }
 
-template <int NT, typename T, typename Load>
-__device__ __forceinline__ void stage_plane_n(T* dst, int P, int i0, int j0, const Geom& g, Load load) {
-  if (P < 0 || P >= g.nz) return;
-  for (int s = threadIdx.x; s < kNNL; s += NT) {
-    const int la = s % kNXL, lb = s / kNXL;
-    const int gi = i0 - 1 + la, gj = j0 - 1 + lb;
-    T val = T(0);
-    if (gi >= 0 && gi < g.nx && gj >= 0 && gj < g.ny)
-      val = load((long)gi + (long)g.nx * ((long)gj + (long)g.ny * P));
-    dst[s] = val;
-  }
-}
-
 template <typename T>
 __device__ __forceinline__ void corners(const T* p0, const T* p1, int ea, int eb, T ve[8]) {
   const int s = eb * kNXL + ea;
@@ -69,356 +56,6 @@ __device__ __forceinline__ long elem_index(const Geom& g, int ex, int ey, int ez
 }
 
 // ---------------------------------------------------------------------------
-// Residual F(phi + lam*delta), Jacobi diagonal and per-Gauss-point charge
-// linearisation c_q = KAPPA semi W n'(phi_q) (written once per element, by the
-// tile that owns it).  Also ||F_free||^2 (last block).
-template <typename TD>
-__global__ __launch_bounds__(kThreads) void k_residual(
-    Geom g, TileMap tm, Charge ch, const double* __restrict__ eps, const uint8_t* __restrict__ semi,
-    const double* __restrict__ netdop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
-    const TD* __restrict__ delta, double lam, double* __restrict__ F, double* __restrict__ invdiag,
-    double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
-    float* __restrict__ invdiag32, double* __restrict__ partial) {
-  __shared__ double sv[2][kNNL];
-  __shared__ double sF[8][kNEL];
-  __shared__ double sD[8][kNEL];
-  __shared__ double sred[kThreads / 64];
-  int tx, ty, tz;
-  tile_of_block(blockIdx.x, tm, tx, ty, tz);
-  const int i0 = tx * kTX, j0 = ty * kTY, k0 = tz * tm.kz;
-  const int t = threadIdx.x;
-  const int na = t % kTX, nb = t / kTX;
-  const int gi = i0 + na, gj = j0 + nb;
-  const bool node_ok = gi < g.nx && gj < g.ny;
-  auto ld = [&](long n) -> double {
-    double v = phi[n];
-    if (delta) v += lam * (double)delta[n];
-    return v;
-  };
-  double carryF = 0.0, carryD = 0.0, acc = 0.0;
-  const int Lend = min(k0 + tm.kz - 1, g.nz - 1);
-  stage_plane(sv[(k0 - 1) & 1], k0 - 1, i0, j0, g, ld);
-  for (int L = k0 - 1; L <= Lend; ++L) {
-    stage_plane(sv[(L + 1) & 1], L + 1, i0, j0, g, ld);
-    __syncthreads();
-    const bool layer_ok = (L >= 0 && L <= g.nz - 2);
-    if (layer_ok) {
-      const double hz = g.z[L + 1] - g.z[L];
-      for (int e = t; e < kNEL; e += kThreads) {
-        const int ea = e % kEX, eb = e / kEX;
-        const int ex = i0 - 1 + ea, ey = j0 - 1 + eb;
-        double outF[8], outD[8];
-        if (ex >= 0 && ex < g.nx - 1 && ey >= 0 && ey < g.ny - 1) {
-          const long el = elem_index(g, ex, ey, L);
-          const bool owned = (ea >= 1 && eb >= 1 && L >= k0);
-          const double hx = g.x[ex + 1] - g.x[ex], hy = g.y[ey + 1] - g.y[ey];
-          const double ee = eps[el];
-          const double sx = ee * hy * hz / hx, sy = ee * hx * hz / hy, sz = ee * hx * hy / hz;
-          double ve[8];
-          corners(sv[L & 1], sv[(L + 1) & 1], ea, eb, ve);
-          stiff_apply(ve, sx, sy, sz, outF);
-          const double dg = (sx + sy + sz) * (1.0 / 9.0);
-#pragma unroll
-          for (int k = 0; k < 8; ++k) outD[k] = dg;
-          if (semi[el]) {
-            const double kw = ch.kappa * hx * hy * hz * 0.125;
-            const double nd = netdop ? netdop[el] : 0.0;
-            double src[8], cc[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) src[k] = ve[k];
-            gauss_interp(src);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              double n, dn;
-              electron_density(ch, src[q], n, dn);
-              src[q] = kw * (nd - n);
-              cc[q] = kw * dn;
-            }
-            if (owned) {
-              store8(cq + 8 * el, cc);
-              if (cq32) store8(cq32 + 8 * el, cc);
-            }
-            gauss_interp(src);
-            gauss_sq_project(cc);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-              outF[k] -= src[k];
-              outD[k] += cc[k];
-            }
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < 8; ++k) outF[k] = outD[k] = 0.0;
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          sF[k][e] = outF[k];
-          sD[k][e] = outD[k];
-        }
-      }
-    }
-    __syncthreads();
-    if (node_ok) {
-      double bF = 0.0, tF = 0.0, bD = 0.0, tD = 0.0;
-      if (layer_ok) {
-        gather4(sF, na, nb, bF, tF);
-        gather4(sD, na, nb, bD, tD);
-      }
-      if (L >= k0) {
-        const long n = (long)gi + (long)g.nx * ((long)gj + (long)g.ny * L);
-        double f = carryF + bF, d = carryD + bD;
-        if (mask[n]) {
-          f = 0.0;
-          d = 1.0;
-        }
-        F[n] = f;
-        const double id = 1.0 / d;
-        invdiag[n] = id;
-        if (diag_out) diag_out[n] = d;
-        if (invdiag32) invdiag32[n] = (float)id;
-        acc += f * f;
-      }
-      carryF = tF;
-      carryD = tD;
-    }
-  }
-  const double s = block_sum(acc, sred);
-  if (t == 0) partial[blockIdx.x] = s;
-}
-
-// ---------------------------------------------------------------------------
-// y = J v (masked: v is read as 0 on Dirichlet nodes).  Dirichlet rows return
-// v_i when identity_rows is set; with kPcg the CG vectors vanish on Dirichlet
-// nodes, so those rows are written as 0 without reading v.
-//
-// One element per thread and one LDS-only barrier per element layer.  Loads
-// are issued in the order they are needed and never waited on early: at layer
-// L the block first fetches node plane L+2 (value and Dirichlet flag), then
-// the Gauss-point coefficients and permittivity of layer L+1, then computes
-// layer L from LDS and registers.  Three LDS plane buffers, two output
-// buffers; the loop is unrolled by two so the coefficient registers
-// ping-pong instead of being copied.  With kPcg the block also writes its
-// share of p^T J p, formed element by element (each element once, by the
-// tile that owns it).
-template <typename T>
-struct JvTile {
-  T sv[3][kNNL];           // node planes (Dirichlet entries zeroed)
-  uint8_t sm[3][kNNL];     // Dirichlet flags of those planes
-  T so[2][8][kNEL];        // per-element corner contributions
-  uint8_t ssemi[kMaxKz + 1][kNEL];
-  double sred[kJvThreads / 64];
-};
-
-template <typename T, bool kPcg>
-struct JvCtx {
-  const Geom& g;
-  const T* __restrict__ eps;
-  const T* __restrict__ cq;
-  const uint8_t* __restrict__ mask;
-  const T* __restrict__ v;
-  T* __restrict__ y;
-  JvTile<T>& sh;
-  int i0, j0, k0, Lbeg, Lend, t, ea, eb, na, nb, gi, gj;
-  long ecol, elayer;
-  bool col_ok, owned_col, node_ok;
-  double hx, hy;
-  int identity_rows;
-};
-
-__device__ __forceinline__ int plane_slot(int P) { return (P + 3) % 3; }
-
-template <typename T, bool kPcg>
-__device__ __forceinline__ void jv_layer(JvCtx<T, kPcg>& c, int L, T (&cc)[8], T& ee, bool& c_ok, T (&cn)[8],
-                                         T& en, bool& cn_ok, T& carry, double& dot) {
-  const Geom& g = c.g;
-  const int t = c.t;
-  const bool layer_ok = (L >= 0 && L <= g.nz - 2);
-  // 1. node plane L+2 (value and flag, independent loads)
-  const int L1 = L + 1, P2 = L + 2;
-  const bool stage2 = (L1 <= c.Lend && P2 <= g.nz - 1);
-  T st0 = T(0), st1 = T(0);
-  uint8_t m0 = 0, m1 = 0;
-  if (stage2) {
-    {
-      const int gi2 = c.i0 - 1 + t % kNXL, gj2 = c.j0 - 1 + t / kNXL;
-      if (gi2 >= 0 && gi2 < g.nx && gj2 >= 0 && gj2 < g.ny) {
-        const long n = (long)gi2 + (long)g.nx * ((long)gj2 + (long)g.ny * P2);
-        st0 = c.v[n];
-        m0 = c.mask[n];
-      }
-    }
-    const int s1 = t + kJvThreads;
-    if (s1 < kNNL) {
-      const int gi2 = c.i0 - 1 + s1 % kNXL, gj2 = c.j0 - 1 + s1 / kNXL;
-      if (gi2 >= 0 && gi2 < g.nx && gj2 >= 0 && gj2 < g.ny) {
-        const long n = (long)gi2 + (long)g.nx * ((long)gj2 + (long)g.ny * P2);
-        st1 = c.v[n];
-        m1 = c.mask[n];
-      }
-    }
-  }
-  // 2. coefficients of layer L+1
-  cn_ok = false;
-  en = T(0);
-  if (c.col_ok && L1 <= c.Lend && L1 <= g.nz - 2) {
-    const long el = c.ecol + c.elayer * L1;
-    en = c.eps[el];
-    if (c.sh.ssemi[L1 - c.Lbeg][t]) {
-      load8(c.cq + 8 * el, cn);
-      cn_ok = true;
-    }
-  }
-  // 3. layer L
-  if (t < kNEL) {
-    T out[8];
-    if (c.col_ok && layer_ok) {
-      const double hz = g.z[L + 1] - g.z[L];
-      const T sx = ee * T(c.hy * hz / c.hx), sy = ee * T(c.hx * hz / c.hy), sz = ee * T(c.hx * c.hy / hz);
-      T ve[8];
-      corners(c.sh.sv[plane_slot(L)], c.sh.sv[plane_slot(L + 1)], c.ea, c.eb, ve);
-      jv_element(ve, sx, sy, sz, cc, c_ok, out);
-      if (kPcg && c.owned_col && L >= c.k0) {
-        double d = 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) d += (double)ve[k] * (double)out[k];
-        dot += d;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) out[k] = T(0);
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) c.sh.so[L & 1][k][t] = out[k];
-  }
-  // 4. publish plane L+2
-  if (stage2) {
-    const int sl = plane_slot(P2);
-    c.sh.sv[sl][t] = m0 ? T(0) : st0;
-    c.sh.sm[sl][t] = m0;
-    if (t + kJvThreads < kNNL) {
-      c.sh.sv[sl][t + kJvThreads] = m1 ? T(0) : st1;
-      c.sh.sm[sl][t + kJvThreads] = m1;
-    }
-  }
-  lds_barrier();
-  // 5. nodes of plane L
-  if (c.node_ok) {
-    T bot = T(0), top = T(0);
-    if (layer_ok) gather4(c.sh.so[L & 1], c.na, c.nb, bot, top);
-    if (L >= c.k0) {
-      const long n = (long)c.gi + (long)g.nx * ((long)c.gj + (long)g.ny * L);
-      T val = carry + bot;
-      if (c.sh.sm[plane_slot(L)][(c.nb + 1) * kNXL + c.na + 1]) {
-        if (kPcg)
-          val = T(0);
-        else if (c.identity_rows)
-          val = c.v[n];
-      }
-      c.y[n] = val;
-    }
-    carry = top;
-  }
-}
-
-template <typename T, bool kPcg>
-__global__ __launch_bounds__(kJvThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_jv(
-    Geom g, TileMap tm, const T* __restrict__ eps, const uint8_t* __restrict__ semi,
-    const T* __restrict__ cq, const uint8_t* __restrict__ mask, const T* __restrict__ v,
-    T* __restrict__ y, int identity_rows, const PcgCtx* ctx, double* __restrict__ part) {
-  if (kPcg && ctx->done) return;
-  __shared__ JvTile<T> sh;
-  int tx, ty, tz;
-  tile_of_block(blockIdx.x, tm, tx, ty, tz);
-  const int t = threadIdx.x;
-  JvCtx<T, kPcg> c{g, eps, cq, mask, v, y, sh};
-  c.i0 = tx * kTX;
-  c.j0 = ty * kTY;
-  c.k0 = tz * tm.kz;
-  c.t = t;
-  c.Lbeg = c.k0 - 1;
-  c.Lend = min(c.k0 + tm.kz - 1, g.nz - 1);
-  c.ea = t % kEX;
-  c.eb = t / kEX;
-  const int ex = c.i0 - 1 + c.ea, ey = c.j0 - 1 + c.eb;
-  c.col_ok = t < kNEL && ex >= 0 && ex < g.nx - 1 && ey >= 0 && ey < g.ny - 1;
-  c.owned_col = c.col_ok && c.ea >= 1 && c.eb >= 1;
-  c.na = t % kTX;
-  c.nb = t / kTX;
-  c.gi = c.i0 + c.na;
-  c.gj = c.j0 + c.nb;
-  c.node_ok = t < kTX * kTY && c.gi < g.nx && c.gj < g.ny;
-  c.hx = c.hy = 1.0;
-  if (c.col_ok) {
-    c.hx = g.x[ex + 1] - g.x[ex];
-    c.hy = g.y[ey + 1] - g.y[ey];
-  }
-  c.ecol = c.col_ok ? (long)ex + (long)(g.nx - 1) * ey : 0;
-  c.elayer = (long)(g.nx - 1) * (g.ny - 1);
-  c.identity_rows = identity_rows;
-  const int nlay = c.Lend - c.Lbeg + 1;
-  // prologue: flags of the chunk, node planes Lbeg and Lbeg+1, layer Lbeg data
-  for (int s = t; s < nlay * kNEL; s += kJvThreads) {
-    const int li = s / kNEL, e = s % kNEL;
-    const int L = c.Lbeg + li;
-    const int xe = c.i0 - 1 + e % kEX, ye = c.j0 - 1 + e / kEX;
-    uint8_t f = 0;
-    if (L >= 0 && L <= g.nz - 2 && xe >= 0 && xe < g.nx - 1 && ye >= 0 && ye < g.ny - 1)
-      f = semi[elem_index(g, xe, ye, L)];
-    sh.ssemi[li][e] = f;
-  }
-  for (int P = c.Lbeg; P <= c.Lbeg + 1; ++P) {
-    if (P < 0 || P >= g.nz) continue;
-    const int sl = plane_slot(P);
-    for (int s = t; s < kNNL; s += kJvThreads) {
-      const int gi2 = c.i0 - 1 + s % kNXL, gj2 = c.j0 - 1 + s / kNXL;
-      T val = T(0);
-      uint8_t m = 0;
-      if (gi2 >= 0 && gi2 < g.nx && gj2 >= 0 && gj2 < g.ny) {
-        const long n = (long)gi2 + (long)g.nx * ((long)gj2 + (long)g.ny * P);
-        m = mask[n];
-        val = m ? T(0) : v[n];
-      }
-      sh.sv[sl][s] = val;
-      sh.sm[sl][s] = m;
-    }
-  }
-  T ca[8], cb[8], ea_ = T(0), eb_ = T(0);
-  bool oka = false, okb = false;
-  __syncthreads();
-  if (c.col_ok && c.Lbeg >= 0 && c.Lbeg <= g.nz - 2) {
-    const long el = c.ecol + c.elayer * c.Lbeg;
-    ea_ = eps[el];
-    if (sh.ssemi[0][t]) {
-      load8(cq + 8 * el, ca);
-      oka = true;
-    }
-  }
-  T carry = T(0);
-  double dot = 0.0;
-  int L = c.Lbeg;
-  if (sizeof(T) == 4) {
-    // ping-pong coefficient registers (fits the register budget in FP32)
-    for (; L + 1 <= c.Lend; L += 2) {
-      jv_layer(c, L, ca, ea_, oka, cb, eb_, okb, carry, dot);
-      jv_layer(c, L + 1, cb, eb_, okb, ca, ea_, oka, carry, dot);
-    }
-    if (L <= c.Lend) jv_layer(c, L, ca, ea_, oka, cb, eb_, okb, carry, dot);
-  } else {
-    for (; L <= c.Lend; ++L) {
-      jv_layer(c, L, ca, ea_, oka, cb, eb_, okb, carry, dot);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) ca[k] = cb[k];
-      ea_ = eb_;
-      oka = okb;
-    }
-  }
-  if (kPcg) {
-    const double s = block_sum(dot, sh.sred);
-    if (t == 0) part[blockIdx.x] = s;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Wave-tiled kernels: four independent waves per block, one wave tile each
 // (see qe_tiles.h).  No LDS and no block barrier in the sweep, so memory
 // latency is hidden by the other waves on the SIMD.
@@ -430,8 +67,11 @@ __device__ __forceinline__ void wave_coords(const WaveMap& wm, int& wx, int& wy,
   wz = w / (wm.gx * wm.gy);
 }
 
+#ifndef QE_JV_MIN_WAVES
+#define QE_JV_MIN_WAVES 4
+#endif
 template <typename T, bool kPcg>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_jv_wave(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_JV_MIN_WAVES, 8))) void k_jv_wave(
     Geom g, WaveMap wm, const T* __restrict__ eps, const uint8_t* __restrict__ semi,
     const T* __restrict__ cq, const uint8_t* __restrict__ mask, const T* __restrict__ v,
     T* __restrict__ y, int identity_rows, const PcgCtx* ctx, double* __restrict__ part) {
@@ -599,7 +239,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_grad(
           stiff_apply(le, ee * ux, ee * uy, ee * uz, out);
           if (semi[el]) {
             double c8[8];
-            load8(cq + 8 * el, c8);
+            load8(cq + 8 * tile_slot(ex, ey, L, (g.nx + 6) / 7, (g.ny + 6) / 7), c8);
             gauss_interp(le);
 #pragma unroll
             for (int q = 0; q < 8; ++q) le[q] *= c8[q];
@@ -781,6 +421,22 @@ __global__ __launch_bounds__(kVecThreads) void k_masked_copy(long n, const uint8
     b[i] = mask[i] ? TD(0) : (TD)a[i];
 }
 
+// Tile-major copy of the per-element permittivity (padding slots 0).
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_stage_eps(Geom g, const double* __restrict__ eps,
+                                                          T* __restrict__ eps_t, long nslots) {
+  const int gx = (g.nx + 6) / 7, gy = (g.ny + 6) / 7;
+  for (long sl = (long)blockIdx.x * blockDim.x + threadIdx.x; sl < nslots; sl += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(sl % 49);
+    const long blk = sl / 49;
+    const int tx = (int)(blk % gx), ty = (int)((blk / gx) % gy), L = (int)(blk / ((long)gx * gy));
+    const int ex = 7 * tx + j % 7, ey = 7 * ty + j / 7;
+    T v = T(0);
+    if (ex < g.nx - 1 && ey < g.ny - 1 && L < g.nz - 1) v = (T)eps[elem_index(g, ex, ey, L)];
+    eps_t[sl] = v;
+  }
+}
+
 // phi += lam * delta
 template <typename TD>
 __global__ __launch_bounds__(kVecThreads) void k_axpy_phi(long N, double* __restrict__ phi,
@@ -849,14 +505,14 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_init_fin(PcgCtx* ctx, const
     ctx->rzs[1] = 0.0;
     ctx->rr = RR;
     ctx->rr0 = RR;
-    ctx->tol2 = rtol * rtol * RR;
+    ctx->tol2 = rtol * rtol * RZ;
     ctx->iters = 0;
     ctx->maxit = maxit;
     ctx->alpha = ctx->beta = ctx->pAp = 0.0;
     if (!isfinite(RR) || !isfinite(RZ)) {
       ctx->done = 1;
       ctx->status = PCG_NONFINITE;
-    } else if (RR == 0.0) {
+    } else if (RZ == 0.0) {
       ctx->done = 1;
       ctx->status = PCG_CONVERGED;
     } else {
@@ -922,7 +578,7 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_dir(long N, int k, const T*
   const double RR = sum_partials(part2, n2, 2, 1, sred);
   const double rzk = ctx->rzs[k & 1];
   const bool bad = !isfinite(RR) || !isfinite(RZ);
-  const bool conv = !bad && RR <= ctx->tol2;
+  const bool conv = !bad && RZ <= ctx->tol2;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctx->rzs[(k + 1) & 1] = RZ;
     ctx->rr = RR;
@@ -957,32 +613,6 @@ __global__ __launch_bounds__(kVecThreads) void k_sum_partials(const double* __re
 // Launchers (host side, same translation unit so the templates instantiate).
 #define QE_LAUNCH(kernel, grid, block, stream, ...) \
   hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__)
-
-void launch_residual(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const double* eps,
-                     const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
-                     const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
-                     double* diag_out, double* cq, float* cq32, float* invdiag32, double* partial,
-                     double* norm2) {
-  if (delta32)
-    QE_LAUNCH(k_residual<float>, tm.nblocks, kThreads, s, g, tm, ch, eps, semi, netdop, mask, phi, delta32, lam, F,
-              invdiag, diag_out, cq, cq32, invdiag32, partial);
-  else
-    QE_LAUNCH(k_residual<double>, tm.nblocks, kThreads, s, g, tm, ch, eps, semi, netdop, mask, phi, delta64, lam, F,
-              invdiag, diag_out, cq, cq32, invdiag32, partial);
-  QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, tm.nblocks, norm2);
-}
-
-void launch_jv64(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
-                 const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows) {
-  QE_LAUNCH((k_jv<double, false>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, v, y, identity_rows,
-            (const PcgCtx*)nullptr, (double*)nullptr);
-}
-
-void launch_jv32(hipStream_t s, const Geom& g, const TileMap& tm, const float* eps, const uint8_t* semi,
-                 const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows) {
-  QE_LAUNCH((k_jv<float, false>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, v, y, identity_rows,
-            (const PcgCtx*)nullptr, (double*)nullptr);
-}
 
 void launch_adj_rhs(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const Box& box,
                     const uint8_t* semi, const double* phi, double* gvec, double* partial, unsigned int* counter,
@@ -1033,18 +663,6 @@ void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* m
   QE_LAUNCH((k_masked_copy<double, float>), nblocks, kVecThreads, s, n, mask, a, b);
 }
 
-void launch_jv_pcg64(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
-                     const double* cq, const uint8_t* mask, const double* p, double* y, const PcgCtx* ctx,
-                     double* part) {
-  QE_LAUNCH((k_jv<double, true>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, p, y, 1, ctx, part);
-}
-
-void launch_jv_pcg32(hipStream_t s, const Geom& g, const TileMap& tm, const float* eps, const uint8_t* semi,
-                     const float* cq, const uint8_t* mask, const float* p, float* y, const PcgCtx* ctx,
-                     double* part) {
-  QE_LAUNCH((k_jv<float, true>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, p, y, 1, ctx, part);
-}
-
 void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
                           const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
                           const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
@@ -1081,6 +699,14 @@ void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const flo
               part);
 }
 
+void launch_stage_eps64(hipStream_t s, int nblocks, const Geom& g, const double* eps, double* eps_t, long nslots) {
+  QE_LAUNCH(k_stage_eps<double>, nblocks, kVecThreads, s, g, eps, eps_t, nslots);
+}
+
+void launch_stage_eps32(hipStream_t s, int nblocks, const Geom& g, const double* eps, float* eps_t, long nslots) {
+  QE_LAUNCH(k_stage_eps<float>, nblocks, kVecThreads, s, g, eps, eps_t, nslots);
+}
+
 void launch_axpy_phi(hipStream_t s, int nblocks, long N, double* phi, const double* d64, const float* d32,
                      double lam) {
   if (d32)
@@ -1103,37 +729,23 @@ void launch_pcg_start32(hipStream_t s, int vblocks, long N, double sign, const d
   QE_LAUNCH(k_pcg_init_fin, 1, kVecThreads, s, ctx, part2, vblocks, rtol, maxit);
 }
 
-void launch_pcg_iter64(hipStream_t s, const Geom& g, const TileMap& tm, const WaveMap* wm, int vblocks, long N, int k,
-                       const double* eps, const uint8_t* semi, const double* cq, const uint8_t* mask,
-                       const double* invdiag, double* x, double* r, double* p, double* y, PcgCtx* ctx,
-                       double* part_pap, double* part2) {
-  int npap = tm.nblocks;
-  if (wm) {
-    QE_LAUNCH((k_jv_wave<double, true>), wm->nblocks, 256, s, g, *wm, eps, semi, cq, mask, p, y, 1, (const PcgCtx*)ctx,
-              part_pap);
-    npap = wm->nblocks;
-  } else {
-    QE_LAUNCH((k_jv<double, true>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, p, y, 1,
-              (const PcgCtx*)ctx, part_pap);
-  }
-  QE_LAUNCH(k_pcg_update<double>, vblocks, kVecThreads, s, N, k, x, r, p, y, invdiag, ctx, part_pap, npap, part2);
+void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int vblocks, long N, int k,
+                       const double* eps_t, const uint8_t* semi, const double* cq, const double* invdiag, double* x,
+                       double* r, double* p, double* y, PcgCtx* ctx, double* part_pap, double* part2) {
+  QE_LAUNCH((k_jv_wave<double, true>), wm.nblocks, 256, s, g, wm, eps_t, semi, cq, (const uint8_t*)nullptr, p, y, 1,
+            (const PcgCtx*)ctx, part_pap);
+  QE_LAUNCH(k_pcg_update<double>, vblocks, kVecThreads, s, N, k, x, r, p, y, invdiag, ctx, part_pap, wm.nblocks,
+            part2);
   QE_LAUNCH(k_pcg_dir<double>, vblocks, kVecThreads, s, N, k, r, invdiag, p, ctx, part2, vblocks);
 }
 
-void launch_pcg_iter32(hipStream_t s, const Geom& g, const TileMap& tm, const WaveMap* wm, int vblocks, long N, int k,
-                       const float* eps, const uint8_t* semi, const float* cq, const uint8_t* mask,
-                       const float* invdiag, float* x, float* r, float* p, float* y, PcgCtx* ctx,
-                       double* part_pap, double* part2) {
-  int npap = tm.nblocks;
-  if (wm) {
-    QE_LAUNCH((k_jv_wave<float, true>), wm->nblocks, 256, s, g, *wm, eps, semi, cq, mask, p, y, 1, (const PcgCtx*)ctx,
-              part_pap);
-    npap = wm->nblocks;
-  } else {
-    QE_LAUNCH((k_jv<float, true>), tm.nblocks, kJvThreads, s, g, tm, eps, semi, cq, mask, p, y, 1,
-              (const PcgCtx*)ctx, part_pap);
-  }
-  QE_LAUNCH(k_pcg_update<float>, vblocks, kVecThreads, s, N, k, x, r, p, y, invdiag, ctx, part_pap, npap, part2);
+void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int vblocks, long N, int k,
+                       const float* eps_t, const uint8_t* semi, const float* cq, const float* invdiag, float* x,
+                       float* r, float* p, float* y, PcgCtx* ctx, double* part_pap, double* part2) {
+  QE_LAUNCH((k_jv_wave<float, true>), wm.nblocks, 256, s, g, wm, eps_t, semi, cq, (const uint8_t*)nullptr, p, y, 1,
+            (const PcgCtx*)ctx, part_pap);
+  QE_LAUNCH(k_pcg_update<float>, vblocks, kVecThreads, s, N, k, x, r, p, y, invdiag, ctx, part_pap, wm.nblocks,
+            part2);
   QE_LAUNCH(k_pcg_dir<float>, vblocks, kVecThreads, s, N, k, r, invdiag, p, ctx, part2, vblocks);
 }
 

@@ -19,12 +19,12 @@ TileMap make_tilemap(int nx, int ny, int nz, int kz);
 // Byte offsets of the workspace carve-out.
 struct Layout {
   size_t F, x, r, p, y, invdiag, gvec, c, mask;
-  size_t x32, r32, p32, y32, invdiag32, c32, eps32;
+  size_t x32, r32, p32, y32, invdiag32, c32, eps32, eps_t;
   size_t partial, partial2, ctx, scal, counters, flags;
   long n_partial;
   size_t total;
 };
-Layout make_layout(long N, long E, int nblocks_tile, int vblocks, int n_dir);
+Layout make_layout(long N, long E, long nslots, int nblocks_tile, int vblocks, int n_dir);
 
 // One call's view of a problem, its workspace and its stream.
 struct Context {
@@ -32,14 +32,13 @@ struct Context {
   Geom g;
   TileMap tm;
   WaveMap wm;
-  int jv_impl = 1;
   bool use_graphs = true;                   // replay captured CG chunks
   hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
   ~Context() {
     if (graph64) (void)hipGraphExecDestroy(graph64);
     if (graph32) (void)hipGraphExecDestroy(graph32);
   }
-  long N = 0, E = 0;
+  long N = 0, E = 0, nslots = 0;
   int vblocks = 0;
   Layout lay;
   char* ws = nullptr;

@@ -120,8 +120,9 @@ WaveMap make_wavemap(int nx, int ny, int nz, int kz) {
   wm.gx = (nx + 6) / 7;
   wm.gy = (ny + 6) / 7;
   if (kz <= 0) {
-    kz = 16;
-    while (kz > 4 && (long)wm.gx * wm.gy * ((nz + kz - 1) / kz) < 4096) kz >>= 1;
+    // taller chunks recompute fewer halo layers; keep about four rounds of
+    // resident waves (256 CUs x 16) when the mesh allows it
+    kz = ((long)wm.gx * wm.gy * ((nz + 7) / 8) >= 16384) ? 8 : 4;
   }
   wm.kz = std::max(1, std::min(kz, 31));
   wm.gz = (nz + wm.kz - 1) / wm.kz;
@@ -138,7 +139,7 @@ static int env_int(const char* name, int dflt) {
 static const int kCountBlocks = 256;
 static const int kContactBlocks = 256;
 
-Layout make_layout(long N, long E, int nblocks_tile, int vblocks, int n_dir) {
+Layout make_layout(long N, long E, long nslots, int nblocks_tile, int vblocks, int n_dir) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -153,15 +154,16 @@ Layout make_layout(long N, long E, int nblocks_tile, int vblocks, int n_dir) {
   L.y = take(N * 8);
   L.invdiag = take(N * 8);
   L.gvec = take(N * 8);
-  L.c = take(E * 64);
+  L.c = take(nslots * 64);     // tile-major (tile_slot)
+  L.eps_t = take(nslots * 8);
   L.mask = take(N);
   L.x32 = take(N * 4);
   L.r32 = take(N * 4);
   L.p32 = take(N * 4);
   L.y32 = take(N * 4);
   L.invdiag32 = take(N * 4);
-  L.c32 = take(E * 32);
-  L.eps32 = take(E * 4);
+  L.c32 = take(nslots * 32);
+  L.eps32 = take(nslots * 4);
   long np = std::max<long>(nblocks_tile, 2L * vblocks);
   np = std::max<long>(np, (long)N / 64 + 64);   // wave-tiled J.v: one partial per block
   np = std::max<long>(np, (long)kCountBlocks * kMaxBoxes);
@@ -239,11 +241,11 @@ qe_status Context::init(const qe_problem* p, void* ws_, size_t ws_bytes, void* s
   g.y = p->y;
   g.z = p->z;
   tm = make_tilemap(p->nx, p->ny, p->nz, kz);
-  jv_impl = env_int("QE_JV_IMPL", 1);
   use_graphs = env_int("QE_GRAPHS", 1) != 0;
   wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
   vblocks = vec_blocks(N);
-  lay = make_layout(N, E, tm.nblocks, vblocks, p->n_dir);
+  nslots = tile_slots(p->nx, p->ny, p->nz);
+  lay = make_layout(N, E, nslots, tm.nblocks, vblocks, p->n_dir);
   if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (ws_bytes < lay.total)
@@ -293,20 +295,16 @@ qe_status Context::validate(const double* phi) {
 
 qe_status Context::stage(double* phi, int apply, int zero_free) {
   launch_stage(s, vblocks, N, prob.dir_id, prob.dir_val, u8(lay.mask), phi, apply, zero_free);
+  launch_stage_eps64(s, vblocks, g, prob.eps_r, f64(lay.eps_t), nslots);
   QE_HIP(hipGetLastError());
   return QE_OK;
 }
 
 qe_status Context::residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam,
                             bool mixed, double* diag_out, double* norm2_host) {
-  if (jv_impl)
-    launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
-                         f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
-                         mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial), f64(lay.scal));
-  else
-    launch_residual(s, g, tm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
-                    f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
-                    mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial), f64(lay.scal));
+  launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
+                       f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
+                       mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial), f64(lay.scal));
   QE_HIP(hipGetLastError());
   if (norm2_host) {
     QE_HIP(hipMemcpyAsync(mirror().scal, ws + lay.scal, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -333,15 +331,13 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
   chunk += chunk & 1;  // even: a replayed chunk starts on the same parity
   auto enqueue_chunk = [&](hipStream_t st) {
     for (int k = 0; k < chunk; ++k) {
-      const WaveMap* w = jv_impl ? &wm : nullptr;
       if (mixed)
-        launch_pcg_iter32(st, g, tm, w, vblocks, N, k & 1, f32(lay.eps32), prob.semi, f32(lay.c32), u8(lay.mask),
-                          f32(lay.invdiag32), f32(lay.x32), f32(lay.r32), f32(lay.p32), f32(lay.y32), dctx,
-                          f64(lay.partial), f64(lay.partial2));
-      else
-        launch_pcg_iter64(st, g, tm, w, vblocks, N, k & 1, prob.eps_r, prob.semi, f64(lay.c), u8(lay.mask),
-                          f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.p), f64(lay.y), dctx, f64(lay.partial),
+        launch_pcg_iter32(st, g, wm, vblocks, N, k & 1, f32(lay.eps32), prob.semi, f32(lay.c32), f32(lay.invdiag32),
+                          f32(lay.x32), f32(lay.r32), f32(lay.p32), f32(lay.y32), dctx, f64(lay.partial),
                           f64(lay.partial2));
+      else
+        launch_pcg_iter64(st, g, wm, vblocks, N, k & 1, f64(lay.eps_t), prob.semi, f64(lay.c), f64(lay.invdiag),
+                          f64(lay.x), f64(lay.r), f64(lay.p), f64(lay.y), dctx, f64(lay.partial), f64(lay.partial2));
     }
   };
   // one captured chunk per precision, replayed until CG stops
@@ -400,7 +396,7 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
   const long E = (long)(p->nx - 1) * (p->ny - 1) * (p->nz - 1);
   // the tile map with the smallest chunk height has the most blocks
   TileMap tm = make_tilemap(p->nx, p->ny, p->nz, 1);
-  return make_layout(N, E, tm.nblocks, vec_blocks(N), p->n_dir).total;
+  return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), tm.nblocks, vec_blocks(N), p->n_dir).total;
 }
 
 const char* qe_last_error(void) { return g_last_error.c_str(); }
@@ -431,7 +427,7 @@ qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* 
   if ((st = cx.validate(o->init_guess == 1 ? phi : nullptr)) != QE_OK) return finish(st, r, rep);
   if ((st = cx.stage(phi, 1, o->init_guess == 0 ? 1 : 0)) != QE_OK) return finish(st, r, rep);
   if (mixed) {
-    launch_cast_d2f(cx.s, cx.vblocks, cx.E, p->eps_r, cx.f32(cx.lay.eps32));
+    launch_stage_eps32(cx.s, cx.vblocks, cx.g, p->eps_r, cx.f32(cx.lay.eps32), cx.nslots);
     if (hipGetLastError() != hipSuccess) return finish(fail(QE_ERR_HIP, "cast launch failed"), r, rep);
   }
   const int check = o->check_every;
@@ -545,11 +541,8 @@ qe_status qe_jv(const qe_problem* p, const qe_physics* ph, const double* phi, co
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, false, nullptr, nullptr));
-  if (cx.jv_impl)
-    launch_jv_wave64(cx.s, cx.g, cx.wm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, y, 1, nullptr,
-                     nullptr);
-  else
-    launch_jv64(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, y, 1);
+  launch_jv_wave64(cx.s, cx.g, cx.wm, cx.f64(cx.lay.eps_t), p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, y, 1,
+                   nullptr, nullptr);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -566,12 +559,9 @@ qe_status qe_jv_f32(const qe_problem* p, const qe_physics* ph, const double* phi
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, true, nullptr, nullptr));
-  launch_cast_d2f(cx.s, cx.vblocks, cx.E, p->eps_r, cx.f32(cx.lay.eps32));
-  if (cx.jv_impl)
-    launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v, y, 1,
-                     nullptr, nullptr);
-  else
-    launch_jv32(cx.s, cx.g, cx.tm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v, y, 1);
+  launch_stage_eps32(cx.s, cx.vblocks, cx.g, p->eps_r, cx.f32(cx.lay.eps32), cx.nslots);
+  launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v, y, 1,
+                   nullptr, nullptr);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -594,7 +584,7 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, mixed, nullptr, nullptr));
   // the CG operand: v with its Dirichlet entries zeroed, as CG keeps it
   if (mixed) {
-    launch_cast_d2f(cx.s, cx.vblocks, cx.E, p->eps_r, cx.f32(cx.lay.eps32));
+    launch_stage_eps32(cx.s, cx.vblocks, cx.g, p->eps_r, cx.f32(cx.lay.eps32), cx.nslots);
     launch_masked_copy_d2f(cx.s, cx.vblocks, cx.N, cx.u8(cx.lay.mask), v, cx.f32(cx.lay.p32));
   } else {
     launch_masked_copy_d2d(cx.s, cx.vblocks, cx.N, cx.u8(cx.lay.mask), v, cx.f64(cx.lay.p));
@@ -604,20 +594,12 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
   QE_HIP(hipEventCreate(&e0));
   QE_HIP(hipEventCreate(&e1));
   auto once = [&]() {
-    if (cx.jv_impl) {
-      if (mixed)
-        launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask),
-                         cx.f32(cx.lay.p32), cx.f32(cx.lay.y32), 1, dctx, cx.f64(cx.lay.partial));
-      else
-        launch_jv_wave64(cx.s, cx.g, cx.wm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask),
-                         cx.f64(cx.lay.p), cx.f64(cx.lay.y), 1, dctx, cx.f64(cx.lay.partial));
-    } else if (mixed) {
-      launch_jv_pcg32(cx.s, cx.g, cx.tm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask),
-                      cx.f32(cx.lay.p32), cx.f32(cx.lay.y32), dctx, cx.f64(cx.lay.partial));
-    } else {
-      launch_jv_pcg64(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), cx.f64(cx.lay.p),
-                      cx.f64(cx.lay.y), dctx, cx.f64(cx.lay.partial));
-    }
+    if (mixed)
+      launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), nullptr,
+                       cx.f32(cx.lay.p32), cx.f32(cx.lay.y32), 1, dctx, cx.f64(cx.lay.partial));
+    else
+      launch_jv_wave64(cx.s, cx.g, cx.wm, cx.f64(cx.lay.eps_t), p->semi, cx.f64(cx.lay.c), nullptr, cx.f64(cx.lay.p),
+                       cx.f64(cx.lay.y), 1, dctx, cx.f64(cx.lay.partial));
   };
   once();  // warm-up
   hipError_t e = hipEventRecord(e0, cx.s);

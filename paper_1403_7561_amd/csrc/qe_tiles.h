@@ -73,6 +73,7 @@ struct WaveTile {
   int lane, lx, ly, ex, ey, gi, gj, k0, Lbeg, Lend;
   bool col_ok, own_el, node_ok;
   long n00, ecol, elayer, sxy;
+  long slot0, slot_layer;   // tile-major slot of this lane's element at layer 0, stride per layer
   double hx, hy;
 
   __device__ __forceinline__ WaveTile(const Geom& g, int wx, int wy, int wz, int kz, int lane_, bool active) {
@@ -93,12 +94,16 @@ struct WaveTile {
     n00 = col_ok ? (long)ex + (long)g.nx * ey : 0;
     elayer = (long)(g.nx - 1) * (g.ny - 1);
     ecol = col_ok ? (long)ex + (long)(g.nx - 1) * ey : 0;
+    const int tgx = (g.nx + 6) / 7, tgy = (g.ny + 6) / 7;
+    slot_layer = (long)tgx * tgy * 49;
+    slot0 = col_ok ? tile_slot(ex, ey, 0, tgx, tgy) : 0;
     hx = hy = 1.0;
     if (col_ok) {
       hx = g.x[ex + 1] - g.x[ex];
       hy = g.y[ey + 1] - g.y[ey];
     }
   }
+  __device__ __forceinline__ long slot(int L) const { return slot0 + slot_layer * L; }
   __device__ __forceinline__ long node(const Geom& g, int L) const { return (long)gi + (long)g.nx * gj + sxy * L; }
   // semiconductor flags of this column over the chunk, bit (L - Lbeg)
   __device__ __forceinline__ unsigned int semi_bits(const Geom& g, const uint8_t* __restrict__ semi) const {
@@ -111,12 +116,13 @@ struct WaveTile {
 };
 
 // ---------------------------------------------------------------------------
-// J.v on one wave tile (see k_jv_wave).  v is read as 0 on Dirichlet nodes
+// J.v on one wave tile (see k_jv_wave).  eps_t and cq are in tile-major order
+// (tile_slot).  v is read as 0 on Dirichlet nodes
 // (kPcg: v already vanishes there and Dirichlet rows are written as 0);
 // identity_rows: Dirichlet rows return v_i.  dot accumulates p^T J p over the
 // elements this wave owns (kPcg).
 template <typename T, bool kPcg>
-__device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const T* __restrict__ eps,
+__device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const T* __restrict__ eps_t,
                                         const uint8_t* __restrict__ semi, const T* __restrict__ cq,
                                         const uint8_t* __restrict__ mask, const T* __restrict__ v,
                                         T* __restrict__ y, int identity_rows, double& dot) {
@@ -131,8 +137,15 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
       f[k] = val;
     }
   };
+  // Everything a layer needs is loaded one layer ahead and consumed only in
+  // the next iteration, and no load is issued after those prefetches inside
+  // an iteration: a wait for any later load would drain them (loads retire
+  // in order).  In CG (kPcg) the Dirichlet flag is not read at all: p vanishes
+  // on Dirichlet nodes and D^-1 is 0 there, so whatever y holds on those rows
+  // never reaches z, p or x.
   T fb[4], ft[4], fn[4];
   T cc[8], cn[8], ee = T(0), en = T(0);
+  uint8_t mk = 0, mkn = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) fb[k] = ft[k] = fn[k] = T(0);
 #pragma unroll
@@ -140,33 +153,30 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
   if (w.col_ok && w.Lbeg >= 0) face(w.Lbeg, fb);
   if (w.col_ok && w.Lbeg + 1 <= g.nz - 1) face(w.Lbeg + 1, ft);
   if (w.col_ok && w.Lbeg >= 0 && w.Lbeg <= g.nz - 2) {
-    const long el = w.ecol + w.elayer * w.Lbeg;
-    ee = eps[el];
-    if (sbits & 1u) load8(cq + 8 * el, cc);
+    const long sl = w.slot(w.Lbeg);
+    ee = eps_t[sl];
+    if (sbits & 1u) load8(cq + 8 * sl, cc);
   }
+  if (!kPcg && w.node_ok && w.Lbeg >= 0) mk = mask[w.node(g, w.Lbeg)];
   T carry = T(0);
   for (int L = w.Lbeg; L <= w.Lend; ++L) {
     const bool layer_ok = (L >= 0 && L <= g.nz - 2);
     const int L1 = L + 1;
-    // prefetch the next top face and the next layer's coefficients
+    const double hz = layer_ok ? g.z[L + 1] - g.z[L] : 1.0;
+    // prefetch the next top face, the next layer's data and the next flag
     if (w.col_ok && L1 <= w.Lend && L1 + 1 <= g.nz - 1) face(L1 + 1, fn);
     if (w.col_ok && L1 <= w.Lend && L1 <= g.nz - 2) {
-      const long el = w.ecol + w.elayer * L1;
-      en = eps[el];
-      if ((sbits >> (L1 - w.Lbeg)) & 1u) load8(cq + 8 * el, cn);
+      const long sl = w.slot(L1);
+      en = eps_t[sl];
+      if ((sbits >> (L1 - w.Lbeg)) & 1u) load8(cq + 8 * sl, cn);
     }
+    if (!kPcg && w.node_ok && L1 <= w.Lend) mkn = mask[w.node(g, L1)];
     T out[8];
     if (w.col_ok && layer_ok) {
-      const double hz = g.z[L + 1] - g.z[L];
       const T sx = ee * T(w.hy * hz / w.hx), sy = ee * T(w.hx * hz / w.hy), sz = ee * T(w.hx * w.hy / hz);
       const T ve[8] = {fb[0], fb[1], fb[2], fb[3], ft[0], ft[1], ft[2], ft[3]};
-      jv_element(ve, sx, sy, sz, cc, ((sbits >> (L - w.Lbeg)) & 1u) != 0, out);
-      if (kPcg && w.own_el && L >= w.k0) {
-        double d = 0.0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) d += (double)ve[k] * (double)out[k];
-        dot += d;
-      }
+      const double d = jv_element<T, kPcg>(ve, sx, sy, sz, cc, ((sbits >> (L - w.Lbeg)) & 1u) != 0, out);
+      if (kPcg && w.own_el && L >= w.k0) dot += d;
     } else {
 #pragma unroll
       for (int k = 0; k < 8; ++k) out[k] = T(0);
@@ -176,12 +186,7 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
     if (w.node_ok && L >= w.k0) {
       const long n = w.node(g, L);
       T val = carry + bot;
-      if (mask[n]) {
-        if (kPcg)
-          val = T(0);
-        else if (identity_rows)
-          val = v[n];
-      }
+      if (!kPcg && mk && identity_rows) val = v[n];
       y[n] = val;
     }
     carry = top;
@@ -193,13 +198,15 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
 #pragma unroll
     for (int k = 0; k < 8; ++k) cc[k] = cn[k];
     ee = en;
+    mk = mkn;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Residual F(phi + lam delta), Jacobi diagonal and Gauss-point coefficients
 // c_q = KAPPA semi W n'(phi_q) on one wave tile.  F and the diagonal are
-// written on owned nodes (0 and 1 on Dirichlet rows); c_q by the owning wave.
+// written on owned nodes (0 and 1 on Dirichlet rows, where the stored inverse
+// diagonal is 0); c_q, in tile-major order, by the owning wave.
 // norm2 accumulates F_i^2 over owned free nodes.
 template <typename TD>
 __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, const Charge& ch,
@@ -258,8 +265,9 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
           cc[q] = kw * dn;
         }
         if (w.own_el && L >= w.k0) {
-          store8(cq + 8 * el, cc);
-          if (cq32) store8(cq32 + 8 * el, cc);
+          const long sl = w.slot(L);
+          store8(cq + 8 * sl, cc);
+          if (cq32) store8(cq32 + 8 * sl, cc);
         }
         gauss_interp(src);
         gauss_sq_project(cc);
@@ -279,12 +287,13 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
     if (w.node_ok && L >= w.k0) {
       const long n = w.node(g, L);
       double f = carryF + bF, d = carryD + bD;
-      if (mask[n]) {
+      const bool dir = mask[n] != 0;
+      if (dir) {
         f = 0.0;
         d = 1.0;
       }
       F[n] = f;
-      const double id = 1.0 / d;
+      const double id = dir ? 0.0 : 1.0 / d;  // 0 keeps CG vectors at 0 on Dirichlet rows
       invdiag[n] = id;
       if (diag_out) diag_out[n] = d;
       if (invdiag32) invdiag32[n] = (float)id;

@@ -15,7 +15,7 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqe.so")
+LIB_PATH = os.environ.get("QE_LIB_PATH") or os.path.join(HERE, "libqe.so")
 
 QE_OK = 0
 STATUS_NAMES = {
