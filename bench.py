@@ -17,15 +17,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1403_7561_amd/csrc/qe_device.h", "paper_1403_7561_amd/csrc/qe_tiles.h",
+                  "paper_1403_7561_amd/csrc/qe_kernels.hip"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "jv_wave_c2_hbm_traffic.md")
 METRIC = "GDOF/s of nonlinear-Poisson J·v; solves/s at ‖F‖<1e-8; adjoint/forward time"
 
 
-def jv_bytes(dev, elem_bytes, node_bytes, coef_bytes):
-    """Algorithmic bytes of one masked J.v launch: read v, mask; write y (per
-    node); read eps, semi (per element); read the 8 Gauss-point coefficients
-    of every semiconductor element."""
+def jv_bytes(dev, val_bytes):
+    """Algorithmic bytes of one CG J.v launch: read p and write y (per node),
+    read the permittivity and the semiconductor flag (per element) and the 8
+    Gauss-point coefficients of every semiconductor element."""
     n_semi = int(dev.semi.sum())
-    return dev.n_nodes * (2 * node_bytes + 1) + dev.n_elems * (elem_bytes + 1) + n_semi * 8 * coef_bytes
+    return dev.n_nodes * 2 * val_bytes + dev.n_elems * (val_bytes + 1) + n_semi * 8 * val_bytes
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per J.v launch from the committed counter summary, or None if
+    the kernel sources changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("source_hash:", "traffic_bytes_per_launch:")))
+    if fields.get("source_hash", "").strip() != kernel_source_hash():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(dev, gpu_newton, budget_s=25.0):
@@ -71,6 +96,8 @@ def main():
     ap.add_argument("--jv-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -116,8 +143,8 @@ def main():
     v = torch.randn(P.N, dtype=torch.float64, device="cuda")
     ms64 = qe.qe_time_jv(P, phi, v, "fp64", args.jv_reps, ws=ws)
     ms32 = qe.qe_time_jv(P, phi, v, "mixed", args.jv_reps, ws=ws)
-    b64 = jv_bytes(dev, 8, 8, 8)
-    b32 = jv_bytes(dev, 4, 4, 4)
+    b64 = jv_bytes(dev, 8)
+    b32 = jv_bytes(dev, 4)
     ach = b64 / (ms64 * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -142,9 +169,9 @@ def main():
         "jv_gdof_s": {"fp64": P.N / (ms64 * 1e-3) / 1e9, "fp32": P.N / (ms32 * 1e-3) / 1e9,
                       "ms_fp64": ms64, "ms_fp32": ms32},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_jv<double,false> (FP64 masked J.v)",
-                     "bytes_per_launch": b64},
+                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "k_jv_wave<double,true> (FP64 J.v of the CG loop)",
+                     "bytes_per_launch": b64, "ms_per_launch": ms64},
         "roofline_fp32": {"achieved": b32 / (ms32 * 1e-3) / 1e9, "bytes_per_launch": b32},
     }
     log("adjoint")
@@ -157,12 +184,56 @@ def main():
         ph4, _, rep4 = qe.qe_solve(P4, opts=opts, ws=ws4, want_density=False)
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        Q, dV, deps, _, arep = qe.qe_adjoint(P4, ph4, dev4.boxes["D1"], opts=opts, ws=ws4)
+        # differentiate the dot under the more positive plunger (the other is empty)
+        box_name = "D1" if dev4.dir_val[0] >= dev4.dir_val[1] else "D2"
+        Q, dV, deps, _, arep = qe.qe_adjoint(P4, ph4, dev4.boxes[box_name], opts=opts, ws=ws4)
         torch.cuda.synchronize()
         tc = time.perf_counter()
         out["adjoint"] = {"forward_ms": (tb - ta) * 1e3, "adjoint_ms": (tc - tb) * 1e3,
-                          "ratio": (tc - tb) / (tb - ta), "Q_D1": Q, "dQ_dV": [float(x) for x in dV],
-                          "adjoint_cg_iters": arep["krylov_iters"]}
+                          "ratio": (tc - tb) / (tb - ta), "box": box_name, "Q": Q,
+                          "dQ_dV": [float(x) for x in dV],
+                          "C_aF": [float(1.602176634e-19 * x * 1e18) for x in dV],
+                          "forward_cg_iters": rep4["krylov_iters"], "adjoint_cg_iters": arep["krylov_iters"]}
+    if not args.no_batch:
+        log("batched sweep (256 instances)")
+        spec = synth.config3_spec()
+        devs3 = [synth.config3_instance(k, spec) for k in range(len(spec[0]))]
+        P3 = [qe.Problem(d) for d in devs3]
+        cache = os.path.join("/tmp", "qe_batch_tune.txt")
+        qe.qe_solve_batch(P3, opts=opts, boxes=boxes, tune_cache=cache)      # tunes once, cached
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, cnt3, reps3 = qe.qe_solve_batch(P3, opts=opts, boxes=boxes, tune_cache=cache)
+        torch.cuda.synchronize()
+        tb3 = time.perf_counter() - t0
+        out["batch_c3"] = {"solves_per_s": len(P3) / tb3, "ms": tb3 * 1e3, "n_inst": len(P3),
+                           "dof_total": int(sum(p.N for p in P3)),
+                           "all_converged": all(r["status"] == 0 for r in reps3),
+                           "max_res_final": max(r["res_final"] for r in reps3),
+                           "dot_electrons_first": [float(x) for x in cnt3[0]]}
+        del P3, devs3
+    if not args.no_mixed:
+        log("mixed precision at 257x257x129")
+        dev5 = synth.config5()
+        P5 = qe.Problem(dev5)
+        ws5 = qe.workspace_for(P5, opts)
+        res = {}
+        for prec in ("fp64", "mixed"):
+            o5 = qe.qe_default_options(newton_atol=1e-8, precision=prec)
+            qe.qe_solve(P5, opts=o5, ws=ws5, want_density=False)            # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ph5, _, r5 = qe.qe_solve(P5, opts=o5, ws=ws5, want_density=False)
+            torch.cuda.synchronize()
+            res[prec] = (time.perf_counter() - t0, ph5.clone(), r5)
+        d = (res["mixed"][1] - res["fp64"][1]).abs().max().item() / res["fp64"][1].abs().max().item()
+        out["mixed_c5"] = {"fp64_s": res["fp64"][0], "mixed_s": res["mixed"][0],
+                           "speedup": res["fp64"][0] / res["mixed"][0],
+                           "max_rel_diff_phi": d,
+                           "fp64_cg_iters": res["fp64"][2]["krylov_iters"],
+                           "mixed_cg_iters": res["mixed"][2]["krylov_iters"],
+                           "res_final": [res["fp64"][2]["res_final"], res["mixed"][2]["res_final"]]}
+        del P5, ws5, res
     log("cpu baseline")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dev, reps[-1]["newton_iters"])
