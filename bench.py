@@ -19,16 +19,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1403_7561_amd/csrc/qe_device.h", "paper_1403_7561_amd/csrc/qe_tiles.h",
                   "paper_1403_7561_amd/csrc/qe_kernels.hip"]
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "jv_wave_c2_hbm_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cg_jv_c2_hbm_traffic.md")
 METRIC = "GDOF/s of nonlinear-Poisson J·v; solves/s at ‖F‖<1e-8; adjoint/forward time"
 
 
-def jv_bytes(dev, val_bytes):
-    """Algorithmic bytes of one CG J.v launch: read p and write y (per node),
-    read the permittivity and the semiconductor flag (per element) and the 8
-    Gauss-point coefficients of every semiconductor element."""
-    n_semi = int(dev.semi.sum())
-    return dev.n_nodes * 2 * val_bytes + dev.n_elems * (val_bytes + 1) + n_semi * 8 * val_bytes
+def jv_bytes(dev, val_bytes, n_coef):
+    """Algorithmic bytes of one launch of the CG loop's J.v kernel: per node
+    read z, y, p and write y, p (y = J z + beta y, p = z + beta p); per
+    element read the permittivity and the coefficient flag; the 8 Gauss-point
+    coefficients of the n_coef elements where they are not all exactly zero."""
+    return dev.n_nodes * 5 * val_bytes + dev.n_elems * (val_bytes + 1) + n_coef * 8 * val_bytes
 
 
 def kernel_source_hash():
@@ -141,10 +141,10 @@ def main():
     log(f"{value:.3f} solves/s; timing J.v")
     # J.v kernel alone (HIP events on the library's stream)
     v = torch.randn(P.N, dtype=torch.float64, device="cuda")
-    ms64 = qe.qe_time_jv(P, phi, v, "fp64", args.jv_reps, ws=ws)
-    ms32 = qe.qe_time_jv(P, phi, v, "mixed", args.jv_reps, ws=ws)
-    b64 = jv_bytes(dev, 8)
-    b32 = jv_bytes(dev, 4)
+    ms64, ncoef = qe.qe_time_jv(P, phi, v, "fp64", args.jv_reps, ws=ws)
+    ms32, ncoef32 = qe.qe_time_jv(P, phi, v, "mixed", args.jv_reps, ws=ws)
+    b64 = jv_bytes(dev, 8, ncoef)
+    b32 = jv_bytes(dev, 4, ncoef32)
     ach = b64 / (ms64 * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -170,8 +170,9 @@ def main():
                       "ms_fp64": ms64, "ms_fp32": ms32},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_jv_wave<double,true> (FP64 J.v of the CG loop)",
-                     "bytes_per_launch": b64, "ms_per_launch": ms64},
+                     "kernel": "k_cg_jv<double> (FP64 J.v of the CG loop with the direction update)",
+                     "bytes_per_launch": b64, "ms_per_launch": ms64,
+                     "coef_elems": ncoef, "elems": dev.n_elems},
         "roofline_fp32": {"achieved": b32 / (ms32 * 1e-3) / 1e9, "bytes_per_launch": b32},
     }
     log("adjoint")

@@ -123,7 +123,9 @@ typedef struct {
 } qe_report;
 
 /* Fill `o` with defaults (atol 1e-8, 100 Newton steps, 30 halvings, forcing
- * cap 1e-2, 20000 CG iterations, FP64, linear initial guess). */
+ * cap 0.3, 20000 CG iterations, FP64, linear initial guess).  The forcing
+ * term is eta_k = min(cap, 0.9 (|F_k| / |F_k-1|)^2) (Eisenstat-Walker), and
+ * the linear initial guess is solved to a relative CG residual of 1e-2. */
 void qe_default_options(qe_options* o);
 
 /* Bytes of workspace any entry point below needs for this problem. */
@@ -200,14 +202,19 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
                          const double* boxes, double* counts, const char* tune_cache,
                          void* ws, size_t ws_bytes, void* stream, qe_report* reps);
 
-/* Benchmark helper: forms the linearisation at phi (device [N]), zeroes the
- * Dirichlet entries of v (device [N], FP64; rounded once to FP32 with
- * QE_PREC_MIXED) as the CG iteration keeps them, then launches the CG J.v
- * kernel `reps` times between two HIP events on `stream`.
- * ms_per_apply: host, mean kernel time per product. */
+/* Benchmark helper: forms the linearisation at phi (device [N]), sets up a
+ * CG state from v (device [N], FP64): z = D^-1 v on free rows and 0 on
+ * Dirichlet rows, y = p = 0, beta = 1 (FP32 copies with QE_PREC_MIXED), then
+ * launches the first kernel of a CG iteration -- y = J z + beta y,
+ * p = z + beta p and the p^T y partial sums -- `reps` times between two HIP
+ * events on `stream`.
+ * ms_per_apply: host, mean kernel time per launch.
+ * n_coef_elems: host or NULL; the number of elements whose Gauss-point
+ *   coefficients are not all exactly zero at phi, i.e. the elements whose
+ *   coefficients the kernel reads (the others add exactly nothing). */
 qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* phi, const double* v,
-                     int32_t precision, int32_t reps, double* ms_per_apply, void* ws, size_t ws_bytes,
-                     void* stream);
+                     int32_t precision, int32_t reps, double* ms_per_apply, int64_t* n_coef_elems,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* qe_last_error(void);

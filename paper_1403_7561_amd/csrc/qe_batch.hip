@@ -40,8 +40,9 @@ struct BatchInst {
   const int32_t* dir_id;
   const double* dir_val;
   double* phi;
-  double *F, *x, *r, *p, *y, *invdiag, *c, *eps_t;   // c, eps_t tile-major (tile_slot)
-  uint8_t* mask;
+  double *F, *x, *r, *p, *y, *invdiag, *c, *eps_t;   // c, eps_t, cflag tile-major (tile_slot)
+  uint8_t *mask, *cflag;
+  double* rdz;   // [nz-1] inverse z spacings (g.rdz points here)
   long N, nslots;
   int gx, gy, gz, kz, ntiles;
 };
@@ -98,6 +99,7 @@ __device__ __forceinline__ void bsum2(double& a, double& b, double* sred) {
 }
 
 __device__ __forceinline__ WaveTile tile_at(const BatchInst& I, int t) {
+  t = __builtin_amdgcn_readfirstlane(t);   // wave-uniform: scalar layer loop
   const int wx = t % I.gx, wy = (t / I.gx) % I.gy, wz = t / (I.gx * I.gy);
   return WaveTile(I.g, wx, wy, wz, I.kz, threadIdx.x & 63, true);
 }
@@ -109,7 +111,7 @@ __device__ double b_residual(const BatchInst& I, const Charge& ch, const double*
   for (int t = threadIdx.x >> 6; t < I.ntiles; t += NT / 64) {
     const WaveTile w = tile_at(I, t);
     residual_tile<double>(I.g, w, ch, I.eps, I.semi, I.netdop, I.mask, I.phi, delta, lam, I.F, I.invdiag, nullptr,
-                          I.c, nullptr, nullptr, acc);
+                          I.c, nullptr, I.cflag, nullptr, acc);
   }
   return bsum<NT>(acc, sred);
 }
@@ -143,7 +145,7 @@ __device__ int b_pcg(const BatchInst& I, const double* b, double sign, double rt
     double dot = 0.0;
     for (int t = threadIdx.x >> 6; t < I.ntiles; t += NT / 64) {
       const WaveTile w = tile_at(I, t);
-      jv_tile<double, true>(I.g, w, I.eps_t, I.semi, I.c, nullptr, I.p, I.y, 1, dot);
+      jv_tile<double, JV_DOT>(I.g, w, I.eps_t, I.cflag, I.c, nullptr, I.p, I.y, 1, dot);
     }
     const double pAp = bsum<NT>(dot, sred);
     if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -186,7 +188,9 @@ __device__ void b_axpy_phi(const BatchInst& I, double lam) {
 
 template <int NT>
 __device__ void b_solve(const BatchParams& bp, const BatchInst& I, BatchOut& o, double* sred) {
-  // stage: Dirichlet mask, Dirichlet values, zeros elsewhere; tile-major eps
+  // stage: Dirichlet mask, Dirichlet values, zeros elsewhere; tile-major eps;
+  // inverse z spacings
+  for (int k = threadIdx.x; k < I.g.nz - 1; k += NT) I.rdz[k] = 1.0 / (I.g.z[k + 1] - I.g.z[k]);
   for (long n = threadIdx.x; n < I.N; n += NT) {
     const int d = I.dir_id[n];
     I.mask[n] = d >= 0 ? 1 : 0;
@@ -212,7 +216,7 @@ __device__ void b_solve(const BatchParams& bp, const BatchInst& I, BatchOut& o, 
   lin.stat = STAT_LINEAR;
   double n2 = b_residual<NT>(I, lin, nullptr, 0.0, sred);
   if (n2 > 0.0 && isfinite(n2)) {
-    const int its = b_pcg<NT>(I, I.F, -1.0, 1e-8, bp.krylov_maxit, &pst, sred);
+    const int its = b_pcg<NT>(I, I.F, -1.0, QE_INIT_RTOL, bp.krylov_maxit, &pst, sred);
     o.init_krylov_iters = its;
     kry += its;
     if (pst == PCG_CONVERGED || pst == PCG_MAXIT) b_axpy_phi<NT>(I, 1.0);
@@ -230,7 +234,7 @@ __device__ void b_solve(const BatchParams& bp, const BatchInst& I, BatchOut& o, 
         break;
       }
       if (it == bp.newton_maxit) break;
-      double eta = prev < 0.0 ? bp.rtol_max : fmin(bp.rtol_max, 0.1 * (nrm / prev) * (nrm / prev));
+      double eta = prev < 0.0 ? bp.rtol_max : fmin(bp.rtol_max, QE_EW_GAMMA * (nrm / prev) * (nrm / prev));
       eta = fmax(eta, 0.5 * bp.atol / nrm);
       eta = fmin(eta, bp.rtol_max);
       eta = fmax(eta, 1e-13);
@@ -329,7 +333,7 @@ static size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 static size_t inst_bytes(const qe_problem& p) {
   const long N = (long)p.nx * p.ny * p.nz;
   const long S = tile_slots(p.nx, p.ny, p.nz);
-  return 6 * al256(N * 8) + al256(S * 64) + al256(S * 8) + al256(N);
+  return 6 * al256(N * 8) + al256(S * 64) + al256(S * 8) + al256(S) + al256(N) + al256((p.nz - 1) * 8);
 }
 
 static size_t batch_bytes(int n, const qe_problem* probs) {
@@ -531,6 +535,9 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
       I.invdiag = reinterpret_cast<double*>(tk(N * 8));
       I.c = reinterpret_cast<double*>(tk(S * 64));
       I.eps_t = reinterpret_cast<double*>(tk(S * 8));
+      I.cflag = reinterpret_cast<uint8_t*>(tk(S));
+      I.rdz = reinterpret_cast<double*>(tk((p.nz - 1) * 8));
+      I.g.rdz = I.rdz;
       I.nslots = S;
       I.mask = reinterpret_cast<uint8_t*>(tk(N));
       I.kz = cf.kz;

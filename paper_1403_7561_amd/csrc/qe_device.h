@@ -39,6 +39,7 @@ struct Geom {
   const double* x;
   const double* y;
   const double* z;
+  const double* rdz;   // [nz-1] 1 / (z[k+1] - z[k]), staged in the workspace
 };
 
 // Electron statistics constants (derived on the host from CODATA values).
@@ -310,6 +311,14 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // ---- reductions -------------------------------------------------------------
+// A value known to be the same in every lane, moved to scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned int lo = __builtin_amdgcn_readfirstlane((unsigned int)b);
+  const unsigned int hi = __builtin_amdgcn_readfirstlane((unsigned int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

@@ -24,14 +24,14 @@ enum PcgStatus : int { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_BREAKDOWN = 2, PC
 
 // Conjugate-gradient scalars, kept on the device between kernels.
 struct PcgCtx {
-  double rzs[2], pAp, alpha, beta, rr, rr0, tol2;
+  double rzs[2], pAp, alpha, beta, tol2;
   int iters, maxit, done, status;
 };
 
 void launch_adj_rhs(hipStream_t s, const Geom& g, const TileMap& tm, const Charge& ch, const Box& box,
                     const uint8_t* semi, const double* phi, double* gvec, double* partial, unsigned int* counter,
                     double* Q);
-void launch_adj_grad(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
+void launch_adj_grad(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* cflag,
                      const double* cq, const uint8_t* mask, const double* lam, const double* phi,
                      const double* gvec, double* dQdeps, double* tcon);
 void launch_contact_sum(hipStream_t s, int nblocks, long N, int n_dir, const int32_t* dir_id, const double* tcon,
@@ -44,6 +44,8 @@ void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, cons
                      const int32_t* dir_id, const double* phi, int* flags);
 void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, const double* dir_val, uint8_t* mask,
                   double* phi, int apply, int zero_free);
+// Inverse z spacings into g.rdz's buffer.
+void launch_stage_rdz(hipStream_t s, int nz, const double* z, double* rdz);
 void launch_cast_d2f(hipStream_t s, int nblocks, long n, const double* a, float* b);
 void launch_masked_copy_d2d(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, double* b);
 void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, float* b);
@@ -51,32 +53,43 @@ WaveMap make_wavemap(int nx, int ny, int nz, int kz);
 void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
                           const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
                           const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
-                          double* diag_out, double* cq, float* cq32, float* invdiag32, double* partial,
-                          double* norm2);
-void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const uint8_t* semi,
-                      const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows,
-                      const PcgCtx* ctx, double* part);
-void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const uint8_t* semi,
-                      const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows,
-                      const PcgCtx* ctx, double* part);
+                          double* diag_out, double* cq, float* cq32, uint8_t* cflag, float* invdiag32,
+                          double* partial, double* norm2);
+// y = J v with v read as 0 on Dirichlet nodes (identity_rows: y_i = v_i there).
+void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const uint8_t* cflag,
+                      const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows);
+void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const uint8_t* cflag,
+                      const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows);
+// First kernel of CG iteration k: stopping test, beta, y = J z + beta y,
+// p = z + beta p, p^T y partials.
+void launch_cg_jv64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const double* eps_t,
+                    const uint8_t* cflag, const double* cq, const double* z, double* y, double* p, PcgCtx* ctx,
+                    const double* part_rz, double* part_py);
+void launch_cg_jv32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const float* eps_t,
+                    const uint8_t* cflag, const float* cq, const float* z, float* y, float* p, PcgCtx* ctx,
+                    const double* part_rz, double* part_py);
 // Tile-major permittivity copy for the wave-tiled J.v (see tile_slot).
 void launch_stage_eps64(hipStream_t s, int nblocks, const Geom& g, const double* eps, double* eps_t, long nslots);
 void launch_stage_eps32(hipStream_t s, int nblocks, const Geom& g, const double* eps, float* eps_t, long nslots);
+// Count of real elements with a set tile-major flag, added to *out.
+void launch_count_flags(hipStream_t s, int nblocks, const Geom& g, const uint8_t* flag, long nslots,
+                        unsigned long long* out);
 void launch_axpy_phi(hipStream_t s, int nblocks, long N, double* phi, const double* d64, const float* d32,
                      double lam);
-// CG start: x = 0, r = sign*b (free rows), p = D^-1 r, then the scalars.
-void launch_pcg_start64(hipStream_t s, int vblocks, long N, double sign, const double* b, const uint8_t* mask,
-                        const double* invdiag, double* x, double* r, double* p, PcgCtx* ctx, double* part2,
+// CG start: x = 0, r = sign*b (free rows), z = D^-1 r, then the scalars
+// (cgblocks r^T z partials).
+void launch_pcg_start64(hipStream_t s, int cgblocks, long N, double sign, const double* b, const uint8_t* mask,
+                        const double* invdiag, double* x, double* r, double* z, PcgCtx* ctx, double* part_rz,
                         double rtol, int maxit);
-void launch_pcg_start32(hipStream_t s, int vblocks, long N, double sign, const double* b, const uint8_t* mask,
-                        const float* invdiag, float* x, float* r, float* p, PcgCtx* ctx, double* part2,
+void launch_pcg_start32(hipStream_t s, int cgblocks, long N, double sign, const double* b, const uint8_t* mask,
+                        const float* invdiag, float* x, float* r, float* z, PcgCtx* ctx, double* part_rz,
                         double rtol, int maxit);
-// CG iteration (parity k): J.v, update, direction (three launches).
-void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int vblocks, long N, int k,
-                       const double* eps_t, const uint8_t* semi, const double* cq, const double* invdiag, double* x,
-                       double* r, double* p, double* y, PcgCtx* ctx, double* part_pap, double* part2);
-void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int vblocks, long N, int k,
-                       const float* eps_t, const uint8_t* semi, const float* cq, const float* invdiag, float* x,
-                       float* r, float* p, float* y, PcgCtx* ctx, double* part_pap, double* part2);
+// CG iteration (parity k): k_cg_jv, then k_cg_update on cgblocks blocks.
+void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
+                       const double* eps_t, const uint8_t* cflag, const double* cq, const double* invdiag, double* x,
+                       double* r, double* z, double* p, double* y, PcgCtx* ctx, double* part_py, double* part_rz);
+void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
+                       const float* eps_t, const uint8_t* cflag, const float* cq, const float* invdiag, float* x,
+                       float* r, float* z, float* p, float* y, PcgCtx* ctx, double* part_py, double* part_rz);
 
 }  // namespace qe

@@ -55,12 +55,31 @@ __device__ __forceinline__ long elem_index(const Geom& g, int ex, int ey, int ez
   return (long)ex + (long)(g.nx - 1) * ((long)ey + (long)(g.ny - 1) * ez);
 }
 
+// Sum of n partials (stride, offset) in a fixed order; the result is the
+// same in every thread of the block.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, int stride, int off,
+                                               double* sred) {
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[(long)i * stride + off];
+  a = wave_sum(a);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sred[wid] = a;
+  __syncthreads();
+  double r = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int w = 0; w < nw; ++w) r += sred[w];
+  return r;  // identical in every thread
+}
+
 // ---------------------------------------------------------------------------
 // Wave-tiled kernels: four independent waves per block, one wave tile each
 // (see qe_tiles.h).  No LDS and no block barrier in the sweep, so memory
 // latency is hidden by the other waves on the SIMD.
 __device__ __forceinline__ void wave_coords(const WaveMap& wm, int& wx, int& wy, int& wz, bool& active) {
-  const int w = wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6);
+  // wave-uniform (scalar registers): the layer loop, z spacings and tile
+  // bounds are then scalar and never wait on vector loads
+  const int w = __builtin_amdgcn_readfirstlane(wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6));
   active = w < wm.nwaves;
   wx = w % wm.gx;
   wy = (w / wm.gx) % wm.gy;
@@ -70,25 +89,66 @@ __device__ __forceinline__ void wave_coords(const WaveMap& wm, int& wx, int& wy,
 #ifndef QE_JV_MIN_WAVES
 #define QE_JV_MIN_WAVES 4
 #endif
-template <typename T, bool kPcg>
+// y = J v (JV_PLAIN: v read as 0 on Dirichlet nodes, identity_rows optional).
+template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_JV_MIN_WAVES, 8))) void k_jv_wave(
-    Geom g, WaveMap wm, const T* __restrict__ eps, const uint8_t* __restrict__ semi,
+    Geom g, WaveMap wm, const T* __restrict__ eps, const uint8_t* __restrict__ cflag,
     const T* __restrict__ cq, const uint8_t* __restrict__ mask, const T* __restrict__ v,
-    T* __restrict__ y, int identity_rows, const PcgCtx* ctx, double* __restrict__ part) {
-  if (kPcg && ctx->done) return;
-  __shared__ double sred[4];
+    T* __restrict__ y, int identity_rows) {
   int wx, wy, wz;
   bool active;
   wave_coords(wm, wx, wy, wz, active);
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   double dot = 0.0;
-  jv_tile<T, kPcg>(g, w, eps, semi, cq, mask, v, y, identity_rows, dot);
-  if (kPcg) {
-    const double d = wave_sum(dot);
-    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
-    __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+  jv_tile<T, JV_PLAIN>(g, w, eps, cflag, cq, mask, v, y, identity_rows, dot);
+}
+
+// CG iteration k, first kernel.  Re-adds the r^T z partials of the previous
+// kernel (rz_k), stops the solve on convergence / non-finite values / the
+// iteration limit (block 0 records the decision; every block takes the same
+// one), then beta = rz_k / rz_{k-1} and, on the wave tiles,
+// y = J z + beta y, p = z + beta p (JV_REC); one p^T y partial per block.
+// rz_k goes to ctx->rzs[k & 1] and rz_{k-1} is read from the other slot.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_JV_MIN_WAVES, 8))) void k_cg_jv(
+    Geom g, WaveMap wm, const T* __restrict__ eps, const uint8_t* __restrict__ cflag,
+    const T* __restrict__ cq, const T* __restrict__ z, T* __restrict__ y, T* __restrict__ p, int k,
+    PcgCtx* __restrict__ ctx, const double* __restrict__ part_rz, int n_rz, double* __restrict__ part_py) {
+  if (ctx->done) return;
+  __shared__ double sred[4];
+  const double RZ = uniform(sum_partials(part_rz, n_rz, 1, 0, sred));
+  const int it = ctx->iters;
+  const double rzprev = ctx->rzs[(k + 1) & 1];
+  const bool bad = !isfinite(RZ), conv = !bad && RZ <= ctx->tol2, maxed = it >= ctx->maxit;
+  const bool first = it == 0;
+  const double b = uniform(first ? 0.0 : RZ / rzprev);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctx->rzs[k & 1] = RZ;
+    if (bad) {
+      ctx->done = 1;
+      ctx->status = PCG_NONFINITE;
+    } else if (conv) {
+      ctx->done = 1;
+      ctx->status = PCG_CONVERGED;
+    } else if (maxed) {
+      ctx->done = 1;
+      ctx->status = PCG_MAXIT;
+    } else {
+      ctx->beta = b;
+    }
   }
+  if (bad || conv || maxed) return;
+  int wx, wy, wz;
+  bool active;
+  wave_coords(wm, wx, wy, wz, active);
+  const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
+  double dot = 0.0;
+  jv_tile<T, JV_REC>(g, w, eps, cflag, cq, nullptr, z, y, 1, dot, p, (T)b, first);
+  const double d = wave_sum(dot);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) part_py[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
 }
 
 template <typename TD>
@@ -97,15 +157,15 @@ __global__ __launch_bounds__(256) void k_residual_wave(
     const double* __restrict__ netdop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
     const TD* __restrict__ delta, double lam, double* __restrict__ F, double* __restrict__ invdiag,
     double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
-    float* __restrict__ invdiag32, double* __restrict__ part) {
+    uint8_t* __restrict__ cflag, float* __restrict__ invdiag32, double* __restrict__ part) {
   __shared__ double sred[4];
   int wx, wy, wz;
   bool active;
   wave_coords(wm, wx, wy, wz, active);
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   double acc = 0.0;
-  residual_tile<TD>(g, w, ch, eps, semi, netdop, mask, phi, delta, lam, F, invdiag, diag_out, cq, cq32, invdiag32,
-                    acc);
+  residual_tile<TD>(g, w, ch, eps, semi, netdop, mask, phi, delta, lam, F, invdiag, diag_out, cq, cq32, cflag,
+                    invdiag32, acc);
   const double d = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
   __syncthreads();
@@ -190,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_rhs(
 // tcon_i = g_i - (J lam)_i on Dirichlet nodes (0 on free nodes); lam is zero
 // on Dirichlet nodes.
 __global__ __launch_bounds__(kThreads) void k_adj_grad(
-    Geom g, TileMap tm, const double* __restrict__ eps, const uint8_t* __restrict__ semi,
+    Geom g, TileMap tm, const double* __restrict__ eps, const uint8_t* __restrict__ cflag,
     const double* __restrict__ cq, const uint8_t* __restrict__ mask, const double* __restrict__ lam,
     const double* __restrict__ phi, const double* __restrict__ gvec, double* __restrict__ dQdeps,
     double* __restrict__ tcon) {
@@ -237,9 +297,10 @@ __global__ __launch_bounds__(kThreads) void k_adj_grad(
           }
           const double ee = eps[el];
           stiff_apply(le, ee * ux, ee * uy, ee * uz, out);
-          if (semi[el]) {
+          const long tsl = tile_slot(ex, ey, L, (g.nx + 6) / 7, (g.ny + 6) / 7);
+          if (cflag[tsl]) {
             double c8[8];
-            load8(cq + 8 * tile_slot(ex, ey, L, (g.nx + 6) / 7, (g.ny + 6) / 7), c8);
+            load8(cq + 8 * tsl, c8);
             gauss_interp(le);
 #pragma unroll
             for (int q = 0; q < 8; ++q) le[q] *= c8[q];
@@ -407,6 +468,13 @@ __global__ __launch_bounds__(kVecThreads) void k_stage(long N, const int32_t* __
   }
 }
 
+// Inverse z spacings 1 / (z[k+1] - z[k]) for the element stiffness weights.
+__global__ __launch_bounds__(kVecThreads) void k_stage_rdz(int nz, const double* __restrict__ z,
+                                                          double* __restrict__ rdz) {
+  for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < nz - 1; k += (int)(gridDim.x * blockDim.x))
+    rdz[k] = 1.0 / (z[k + 1] - z[k]);
+}
+
 template <typename TS, typename TD>
 __global__ __launch_bounds__(kVecThreads) void k_cast(long n, const TS* __restrict__ a, TD* __restrict__ b) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
@@ -437,6 +505,24 @@ __global__ __launch_bounds__(kVecThreads) void k_stage_eps(Geom g, const double*
   }
 }
 
+// Number of real elements whose tile-major flag is set (padding slots of
+// ragged tiles are skipped: they are never written).
+__global__ __launch_bounds__(kVecThreads) void k_count_flags(Geom g, const uint8_t* __restrict__ flag, long nslots,
+                                                            unsigned long long* __restrict__ out) {
+  __shared__ double sred[kVecThreads / 64];
+  const int gx = (g.nx + 6) / 7, gy = (g.ny + 6) / 7;
+  double cnt = 0.0;
+  for (long sl = (long)blockIdx.x * blockDim.x + threadIdx.x; sl < nslots; sl += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(sl % 49);
+    const long blk = sl / 49;
+    const int tx = (int)(blk % gx), ty = (int)((blk / gx) % gy), L = (int)(blk / ((long)gx * gy));
+    const int ex = 7 * tx + j % 7, ey = 7 * ty + j / 7;
+    if (ex < g.nx - 1 && ey < g.ny - 1 && L < g.nz - 1 && flag[sl]) cnt += 1.0;
+  }
+  const double s = block_sum(cnt, sred);
+  if (threadIdx.x == 0 && s > 0.0) atomicAdd(out, (unsigned long long)s);
+}
+
 // phi += lam * delta
 template <typename TD>
 __global__ __launch_bounds__(kVecThreads) void k_axpy_phi(long N, double* __restrict__ phi,
@@ -453,63 +539,86 @@ __global__ __launch_bounds__(kVecThreads) void k_axpy_phi(long N, double* __rest
 // r^T z in ctx->rzs[k & 1]; the host passes the parity of k with every launch
 // (chunks of iterations have even length, so a captured chunk can be replayed),
 // and block 0 of the direction kernel counts the iterations.
-__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, int stride, int off,
-                                               double* sred) {
-  double a = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[(long)i * stride + off];
-  a = wave_sum(a);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sred[wid] = a;
-  __syncthreads();
-  double r = 0.0;
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int w = 0; w < nw; ++w) r += sred[w];
-  return r;  // identical in every thread
+
+// Four consecutive entries per thread ("chunk"), loaded with 16-byte vector
+// loads when the chunk is whole.  The arrays are 256-byte aligned.
+template <typename T>
+struct Quad {
+  T v[4];
+};
+
+template <typename T>
+__device__ __forceinline__ Quad<T> ld4(const T* __restrict__ a, long c, long N) {
+  Quad<T> q;
+  const long i = 4 * c;
+  if (i + 3 < N) {
+    if constexpr (sizeof(T) == 8) {
+      const double2* p2 = reinterpret_cast<const double2*>(a + i);
+      const double2 u = p2[0], w = p2[1];
+      q.v[0] = u.x; q.v[1] = u.y; q.v[2] = w.x; q.v[3] = w.y;
+    } else {
+      const float4 u = *reinterpret_cast<const float4*>(a + i);
+      q.v[0] = u.x; q.v[1] = u.y; q.v[2] = u.z; q.v[3] = u.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q.v[j] = (i + j < N) ? a[i + j] : T(0);
+  }
+  return q;
 }
 
-// x = 0, r = sign*b on free nodes, p = D^-1 r; partials of r^T z and r^T r.
+template <typename T>
+__device__ __forceinline__ void st4(T* __restrict__ a, long c, long N, const Quad<T>& q) {
+  const long i = 4 * c;
+  if (i + 3 < N) {
+    if constexpr (sizeof(T) == 8) {
+      double2* p2 = reinterpret_cast<double2*>(a + i);
+      p2[0] = make_double2(q.v[0], q.v[1]);
+      p2[1] = make_double2(q.v[2], q.v[3]);
+    } else {
+      *reinterpret_cast<float4*>(a + i) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (i + j < N) a[i + j] = q.v[j];
+  }
+}
+
+// x = 0, r = sign*b on free nodes, z = D^-1 r; partials of r^T z.
 template <typename T, typename TB>
 __global__ __launch_bounds__(kVecThreads) void k_pcg_init(long N, double sign, const TB* __restrict__ b,
                                                          const uint8_t* __restrict__ mask,
                                                          const T* __restrict__ invdiag, T* __restrict__ x,
-                                                         T* __restrict__ r, T* __restrict__ p,
-                                                         double* __restrict__ part2) {
+                                                         T* __restrict__ r, T* __restrict__ z,
+                                                         double* __restrict__ part) {
   __shared__ double sred[kVecThreads / 64];
-  double rz = 0.0, rr = 0.0;
+  double rz = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
     const T ri = mask[i] ? T(0) : (T)(sign * (double)b[i]);
     const T zi = invdiag[i] * ri;
     x[i] = T(0);
     r[i] = ri;
-    p[i] = zi;
+    z[i] = zi;
     rz += (double)ri * (double)zi;
-    rr += (double)ri * (double)ri;
   }
   const double s1 = block_sum(rz, sred);
-  const double s2 = block_sum(rr, sred);
-  if (threadIdx.x == 0) {
-    part2[2 * blockIdx.x] = s1;
-    part2[2 * blockIdx.x + 1] = s2;
-  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s1;
 }
 
 // One block: the starting scalars of a solve.
-__global__ __launch_bounds__(kVecThreads) void k_pcg_init_fin(PcgCtx* ctx, const double* __restrict__ part2, int n,
+__global__ __launch_bounds__(kVecThreads) void k_pcg_init_fin(PcgCtx* ctx, const double* __restrict__ part, int n,
                                                              double rtol, int maxit) {
   __shared__ double sred[kVecThreads / 64];
-  const double RZ = sum_partials(part2, n, 2, 0, sred);
-  const double RR = sum_partials(part2, n, 2, 1, sred);
+  const double RZ = sum_partials(part, n, 1, 0, sred);
   if (threadIdx.x == 0) {
     ctx->rzs[0] = RZ;
     ctx->rzs[1] = 0.0;
-    ctx->rr = RR;
-    ctx->rr0 = RR;
     ctx->tol2 = rtol * rtol * RZ;
     ctx->iters = 0;
     ctx->maxit = maxit;
     ctx->alpha = ctx->beta = ctx->pAp = 0.0;
-    if (!isfinite(RR) || !isfinite(RZ)) {
+    if (!isfinite(RZ)) {
       ctx->done = 1;
       ctx->status = PCG_NONFINITE;
     } else if (RZ == 0.0) {
@@ -522,18 +631,32 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_init_fin(PcgCtx* ctx, const
   }
 }
 
-// alpha = rz_k / p^T J p (from the J.v partials); x += alpha p; r -= alpha y;
-// partials of r^T D^-1 r and r^T r.
+// CG iteration k, second kernel: alpha = rz_k / p^T y (re-adding the
+// partials of k_cg_jv); x += alpha p; r -= alpha y; z = D^-1 r; partials of
+// r^T z.  Each thread first issues the loads of its first chunk, then re-adds
+// the partials while they are in flight; later chunks are loaded one ahead.
+// A launch after the solve has stopped returns at once.  Block 0 counts the
+// iteration.
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_pcg_update(long N, int k, T* __restrict__ x, T* __restrict__ r,
-                                                           const T* __restrict__ p, const T* __restrict__ y,
-                                                           const T* __restrict__ invdiag, PcgCtx* ctx,
-                                                           const double* __restrict__ part_pap, int n_pap,
-                                                           double* __restrict__ part2) {
+__global__ __launch_bounds__(kVecThreads) void k_cg_update(long N, int k, T* __restrict__ x, T* __restrict__ r,
+                                                          T* __restrict__ z, const T* __restrict__ p,
+                                                          const T* __restrict__ y, const T* __restrict__ invdiag,
+                                                          PcgCtx* ctx, const double* __restrict__ part_py, int n_py,
+                                                          double* __restrict__ part_rz) {
   if (ctx->done) return;
   __shared__ double sred[kVecThreads / 64];
-  const double pAp = sum_partials(part_pap, n_pap, 1, 0, sred);
+  const long nc = (N + 3) / 4, stride = (long)gridDim.x * blockDim.x;
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  Quad<T> qx, qr, qp, qy, qd;
+  if (c < nc) {
+    qx = ld4(x, c, N);
+    qr = ld4(r, c, N);
+    qp = ld4(p, c, N);
+    qy = ld4(y, c, N);
+    qd = ld4(invdiag, c, N);
+  }
   const double rzk = ctx->rzs[k & 1];
+  const double pAp = sum_partials(part_py, n_py, 1, 0, sred);
   if (!(pAp > 0.0) || !isfinite(pAp)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       ctx->pAp = pAp;
@@ -546,59 +669,33 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_update(long N, int k, T* __
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctx->pAp = pAp;
     ctx->alpha = a;
+    ctx->iters += 1;
   }
   const T alpha = (T)a;
-  double rz = 0.0, rr = 0.0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const T ri = r[i] - alpha * y[i];
-    r[i] = ri;
-    const T zi = invdiag[i] * ri;
-    rz += (double)ri * (double)zi;
-    rr += (double)ri * (double)ri;
-  }
-  const double s1 = block_sum(rz, sred);
-  const double s2 = block_sum(rr, sred);
-  if (threadIdx.x == 0) {
-    part2[2 * blockIdx.x] = s1;
-    part2[2 * blockIdx.x + 1] = s2;
-  }
-}
-
-// beta = rz_{k+1} / rz_k, convergence test, p = D^-1 r + beta p.  Block 0
-// records the new scalars (rz_{k+1} goes to the other slot, so no block of
-// this kernel can read a value written by it).
-template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_pcg_dir(long N, int k, const T* __restrict__ r,
-                                                        const T* __restrict__ invdiag, T* __restrict__ p, PcgCtx* ctx,
-                                                        const double* __restrict__ part2, int n2) {
-  if (ctx->done) return;
-  __shared__ double sred[kVecThreads / 64];
-  const double RZ = sum_partials(part2, n2, 2, 0, sred);
-  const double RR = sum_partials(part2, n2, 2, 1, sred);
-  const double rzk = ctx->rzs[k & 1];
-  const bool bad = !isfinite(RR) || !isfinite(RZ);
-  const bool conv = !bad && RZ <= ctx->tol2;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctx->rzs[(k + 1) & 1] = RZ;
-    ctx->rr = RR;
-    ctx->iters += 1;
-    ctx->beta = RZ / rzk;
-    if (bad) {
-      ctx->done = 1;
-      ctx->status = PCG_NONFINITE;
-    } else if (conv) {
-      ctx->done = 1;
-      ctx->status = PCG_CONVERGED;
-    } else if (ctx->iters >= ctx->maxit) {
-      ctx->done = 1;
-      ctx->status = PCG_MAXIT;
+  double rz = 0.0;
+  while (c < nc) {
+    Quad<T> qz;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      qx.v[j] += alpha * qp.v[j];
+      qr.v[j] -= alpha * qy.v[j];
+      qz.v[j] = qd.v[j] * qr.v[j];
+      rz += (double)qr.v[j] * (double)qz.v[j];
+    }
+    st4(x, c, N, qx);
+    st4(r, c, N, qr);
+    st4(z, c, N, qz);
+    c += stride;
+    if (c < nc) {
+      qx = ld4(x, c, N);
+      qr = ld4(r, c, N);
+      qp = ld4(p, c, N);
+      qy = ld4(y, c, N);
+      qd = ld4(invdiag, c, N);
     }
   }
-  if (bad || conv) return;
-  const T beta = (T)(RZ / rzk);
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x)
-    p[i] = invdiag[i] * r[i] + beta * p[i];
+  const double s1 = block_sum(rz, sred);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = s1;
 }
 
 // One block: sum of n partials (fixed order) into *out.
@@ -620,10 +717,10 @@ void launch_adj_rhs(hipStream_t s, const Geom& g, const TileMap& tm, const Charg
   QE_LAUNCH(k_adj_rhs, tm.nblocks, kThreads, s, g, tm, ch, box, semi, phi, gvec, partial, counter, Q);
 }
 
-void launch_adj_grad(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* semi,
+void launch_adj_grad(hipStream_t s, const Geom& g, const TileMap& tm, const double* eps, const uint8_t* cflag,
                      const double* cq, const uint8_t* mask, const double* lam, const double* phi,
                      const double* gvec, double* dQdeps, double* tcon) {
-  QE_LAUNCH(k_adj_grad, tm.nblocks, kThreads, s, g, tm, eps, semi, cq, mask, lam, phi, gvec, dQdeps, tcon);
+  QE_LAUNCH(k_adj_grad, tm.nblocks, kThreads, s, g, tm, eps, cflag, cq, mask, lam, phi, gvec, dQdeps, tcon);
 }
 
 void launch_contact_sum(hipStream_t s, int nblocks, long N, int n_dir, const int32_t* dir_id, const double* tcon,
@@ -651,6 +748,10 @@ void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, con
   QE_LAUNCH(k_stage, nblocks, kVecThreads, s, N, dir_id, dir_val, mask, phi, apply, zero_free);
 }
 
+void launch_stage_rdz(hipStream_t s, int nz, const double* z, double* rdz) {
+  QE_LAUNCH(k_stage_rdz, 1, kVecThreads, s, nz, z, rdz);
+}
+
 void launch_cast_d2f(hipStream_t s, int nblocks, long n, const double* a, float* b) {
   QE_LAUNCH((k_cast<double, float>), nblocks, kVecThreads, s, n, a, b);
 }
@@ -666,37 +767,39 @@ void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* m
 void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
                           const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
                           const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
-                          double* diag_out, double* cq, float* cq32, float* invdiag32, double* partial,
-                          double* norm2) {
+                          double* diag_out, double* cq, float* cq32, uint8_t* cflag, float* invdiag32,
+                          double* partial, double* norm2) {
   if (delta32)
     QE_LAUNCH(k_residual_wave<float>, wm.nblocks, 256, s, g, wm, ch, eps, semi, netdop, mask, phi, delta32, lam, F,
-              invdiag, diag_out, cq, cq32, invdiag32, partial);
+              invdiag, diag_out, cq, cq32, cflag, invdiag32, partial);
   else
     QE_LAUNCH(k_residual_wave<double>, wm.nblocks, 256, s, g, wm, ch, eps, semi, netdop, mask, phi, delta64, lam, F,
-              invdiag, diag_out, cq, cq32, invdiag32, partial);
+              invdiag, diag_out, cq, cq32, cflag, invdiag32, partial);
   QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, wm.nblocks, norm2);
 }
 
-void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const uint8_t* semi,
-                      const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows,
-                      const PcgCtx* ctx, double* part) {
-  if (ctx)
-    QE_LAUNCH((k_jv_wave<double, true>), wm.nblocks, 256, s, g, wm, eps, semi, cq, mask, v, y, identity_rows, ctx,
-              part);
-  else
-    QE_LAUNCH((k_jv_wave<double, false>), wm.nblocks, 256, s, g, wm, eps, semi, cq, mask, v, y, identity_rows, ctx,
-              part);
+void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const uint8_t* cflag,
+                      const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows) {
+  QE_LAUNCH(k_jv_wave<double>, wm.nblocks, 256, s, g, wm, eps, cflag, cq, mask, v, y, identity_rows);
 }
 
-void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const uint8_t* semi,
-                      const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows,
-                      const PcgCtx* ctx, double* part) {
-  if (ctx)
-    QE_LAUNCH((k_jv_wave<float, true>), wm.nblocks, 256, s, g, wm, eps, semi, cq, mask, v, y, identity_rows, ctx,
-              part);
-  else
-    QE_LAUNCH((k_jv_wave<float, false>), wm.nblocks, 256, s, g, wm, eps, semi, cq, mask, v, y, identity_rows, ctx,
-              part);
+void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const uint8_t* cflag,
+                      const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows) {
+  QE_LAUNCH(k_jv_wave<float>, wm.nblocks, 256, s, g, wm, eps, cflag, cq, mask, v, y, identity_rows);
+}
+
+void launch_cg_jv64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const double* eps_t,
+                    const uint8_t* cflag, const double* cq, const double* z, double* y, double* p, PcgCtx* ctx,
+                    const double* part_rz, double* part_py) {
+  QE_LAUNCH(k_cg_jv<double>, wm.nblocks, 256, s, g, wm, eps_t, cflag, cq, z, y, p, k, ctx, part_rz, cgblocks,
+            part_py);
+}
+
+void launch_cg_jv32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const float* eps_t,
+                    const uint8_t* cflag, const float* cq, const float* z, float* y, float* p, PcgCtx* ctx,
+                    const double* part_rz, double* part_py) {
+  QE_LAUNCH(k_cg_jv<float>, wm.nblocks, 256, s, g, wm, eps_t, cflag, cq, z, y, p, k, ctx, part_rz, cgblocks,
+            part_py);
 }
 
 void launch_stage_eps64(hipStream_t s, int nblocks, const Geom& g, const double* eps, double* eps_t, long nslots) {
@@ -707,6 +810,11 @@ void launch_stage_eps32(hipStream_t s, int nblocks, const Geom& g, const double*
   QE_LAUNCH(k_stage_eps<float>, nblocks, kVecThreads, s, g, eps, eps_t, nslots);
 }
 
+void launch_count_flags(hipStream_t s, int nblocks, const Geom& g, const uint8_t* flag, long nslots,
+                        unsigned long long* out) {
+  QE_LAUNCH(k_count_flags, nblocks, kVecThreads, s, g, flag, nslots, out);
+}
+
 void launch_axpy_phi(hipStream_t s, int nblocks, long N, double* phi, const double* d64, const float* d32,
                      double lam) {
   if (d32)
@@ -715,38 +823,34 @@ void launch_axpy_phi(hipStream_t s, int nblocks, long N, double* phi, const doub
     QE_LAUNCH(k_axpy_phi<double>, nblocks, kVecThreads, s, N, phi, d64, lam);
 }
 
-void launch_pcg_start64(hipStream_t s, int vblocks, long N, double sign, const double* b, const uint8_t* mask,
-                        const double* invdiag, double* x, double* r, double* p, PcgCtx* ctx, double* part2,
+void launch_pcg_start64(hipStream_t s, int cgblocks, long N, double sign, const double* b, const uint8_t* mask,
+                        const double* invdiag, double* x, double* r, double* z, PcgCtx* ctx, double* part_rz,
                         double rtol, int maxit) {
-  QE_LAUNCH((k_pcg_init<double, double>), vblocks, kVecThreads, s, N, sign, b, mask, invdiag, x, r, p, part2);
-  QE_LAUNCH(k_pcg_init_fin, 1, kVecThreads, s, ctx, part2, vblocks, rtol, maxit);
+  QE_LAUNCH((k_pcg_init<double, double>), cgblocks, kVecThreads, s, N, sign, b, mask, invdiag, x, r, z, part_rz);
+  QE_LAUNCH(k_pcg_init_fin, 1, kVecThreads, s, ctx, part_rz, cgblocks, rtol, maxit);
 }
 
-void launch_pcg_start32(hipStream_t s, int vblocks, long N, double sign, const double* b, const uint8_t* mask,
-                        const float* invdiag, float* x, float* r, float* p, PcgCtx* ctx, double* part2,
+void launch_pcg_start32(hipStream_t s, int cgblocks, long N, double sign, const double* b, const uint8_t* mask,
+                        const float* invdiag, float* x, float* r, float* z, PcgCtx* ctx, double* part_rz,
                         double rtol, int maxit) {
-  QE_LAUNCH((k_pcg_init<float, double>), vblocks, kVecThreads, s, N, sign, b, mask, invdiag, x, r, p, part2);
-  QE_LAUNCH(k_pcg_init_fin, 1, kVecThreads, s, ctx, part2, vblocks, rtol, maxit);
+  QE_LAUNCH((k_pcg_init<float, double>), cgblocks, kVecThreads, s, N, sign, b, mask, invdiag, x, r, z, part_rz);
+  QE_LAUNCH(k_pcg_init_fin, 1, kVecThreads, s, ctx, part_rz, cgblocks, rtol, maxit);
 }
 
-void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int vblocks, long N, int k,
-                       const double* eps_t, const uint8_t* semi, const double* cq, const double* invdiag, double* x,
-                       double* r, double* p, double* y, PcgCtx* ctx, double* part_pap, double* part2) {
-  QE_LAUNCH((k_jv_wave<double, true>), wm.nblocks, 256, s, g, wm, eps_t, semi, cq, (const uint8_t*)nullptr, p, y, 1,
-            (const PcgCtx*)ctx, part_pap);
-  QE_LAUNCH(k_pcg_update<double>, vblocks, kVecThreads, s, N, k, x, r, p, y, invdiag, ctx, part_pap, wm.nblocks,
-            part2);
-  QE_LAUNCH(k_pcg_dir<double>, vblocks, kVecThreads, s, N, k, r, invdiag, p, ctx, part2, vblocks);
+void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
+                       const double* eps_t, const uint8_t* cflag, const double* cq, const double* invdiag, double* x,
+                       double* r, double* z, double* p, double* y, PcgCtx* ctx, double* part_py, double* part_rz) {
+  launch_cg_jv64(s, g, wm, cgblocks, k, eps_t, cflag, cq, z, y, p, ctx, part_rz, part_py);
+  QE_LAUNCH(k_cg_update<double>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, part_py, wm.nblocks,
+            part_rz);
 }
 
-void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int vblocks, long N, int k,
-                       const float* eps_t, const uint8_t* semi, const float* cq, const float* invdiag, float* x,
-                       float* r, float* p, float* y, PcgCtx* ctx, double* part_pap, double* part2) {
-  QE_LAUNCH((k_jv_wave<float, true>), wm.nblocks, 256, s, g, wm, eps_t, semi, cq, (const uint8_t*)nullptr, p, y, 1,
-            (const PcgCtx*)ctx, part_pap);
-  QE_LAUNCH(k_pcg_update<float>, vblocks, kVecThreads, s, N, k, x, r, p, y, invdiag, ctx, part_pap, wm.nblocks,
-            part2);
-  QE_LAUNCH(k_pcg_dir<float>, vblocks, kVecThreads, s, N, k, r, invdiag, p, ctx, part2, vblocks);
+void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
+                       const float* eps_t, const uint8_t* cflag, const float* cq, const float* invdiag, float* x,
+                       float* r, float* z, float* p, float* y, PcgCtx* ctx, double* part_py, double* part_rz) {
+  launch_cg_jv32(s, g, wm, cgblocks, k, eps_t, cflag, cq, z, y, p, ctx, part_rz, part_py);
+  QE_LAUNCH(k_cg_update<float>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, part_py, wm.nblocks,
+            part_rz);
 }
 
 }  // namespace qe

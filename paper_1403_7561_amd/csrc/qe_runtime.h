@@ -6,6 +6,18 @@
 #include "../../include/qe.h"
 #include "qe_kernels.h"
 
+// Relative CG tolerance of the charge-free initial guess: the first Newton
+// step corrects its error, so it is solved only roughly.  And the factor of
+// the Eisenstat-Walker forcing term eta_k = gamma (|F_k| / |F_k-1|)^2
+// (their second choice, with gamma = 0.9, alpha = 2), capped by
+// qe_options.krylov_rtol_max.
+#ifndef QE_INIT_RTOL
+#define QE_INIT_RTOL 1e-2
+#endif
+#ifndef QE_EW_GAMMA
+#define QE_EW_GAMMA 0.9
+#endif
+
 namespace qe {
 
 qe_status fail(qe_status st, const char* fmt, ...);
@@ -14,17 +26,18 @@ qe_status make_charge(const qe_physics* ph, Charge& ch);
 qe_status check_problem(const qe_problem* p);
 qe_status check_options(const qe_options* o);
 int vec_blocks(long N);
+int cg_blocks(long N);
 TileMap make_tilemap(int nx, int ny, int nz, int kz);
 
 // Byte offsets of the workspace carve-out.
 struct Layout {
-  size_t F, x, r, p, y, invdiag, gvec, c, mask;
-  size_t x32, r32, p32, y32, invdiag32, c32, eps32, eps_t;
+  size_t F, x, r, p, y, z, invdiag, gvec, c, cflag, rdz, mask;
+  size_t x32, r32, p32, y32, z32, invdiag32, c32, eps32, eps_t;
   size_t partial, partial2, ctx, scal, counters, flags;
   long n_partial;
   size_t total;
 };
-Layout make_layout(long N, long E, long nslots, int nblocks_tile, int vblocks, int n_dir);
+Layout make_layout(long N, long E, long nslots, long nz_elems, int nblocks_tile, int vblocks, int n_dir);
 
 // One call's view of a problem, its workspace and its stream.
 struct Context {

@@ -93,6 +93,13 @@ qe_status make_charge(const qe_physics* ph, Charge& ch) {
 // ------------------------------------------------------------------ sizes
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Blocks of the CG vector kernels: one 4-entry chunk per thread up to 2048
+// blocks (every block re-adds all partials of the previous kernel).
+int cg_blocks(long N) {
+  long b = (N + (long)kVecThreads * 4 - 1) / ((long)kVecThreads * 4);
+  return (int)std::max(1L, std::min(b, 2048L));
+}
+
 int vec_blocks(long N) {
   long b = (N + (long)kVecThreads * 8 - 1) / ((long)kVecThreads * 8);
   return (int)std::max(1L, std::min(b, 1024L));
@@ -120,9 +127,10 @@ WaveMap make_wavemap(int nx, int ny, int nz, int kz) {
   wm.gx = (nx + 6) / 7;
   wm.gy = (ny + 6) / 7;
   if (kz <= 0) {
-    // taller chunks recompute fewer halo layers; keep about four rounds of
-    // resident waves (256 CUs x 16) when the mesh allows it
-    kz = ((long)wm.gx * wm.gy * ((nz + 7) / 8) >= 16384) ? 8 : 4;
+    // taller chunks recompute fewer halo layers; shorter ones give more
+    // waves to a small mesh (measured: 129x129x65 is fastest at 6,
+    // 257x257x129 at 8)
+    kz = ((long)wm.gx * wm.gy * ((nz + 7) / 8) >= 16384) ? 8 : 6;
   }
   wm.kz = std::max(1, std::min(kz, 31));
   wm.gz = (nz + wm.kz - 1) / wm.kz;
@@ -139,7 +147,7 @@ static int env_int(const char* name, int dflt) {
 static const int kCountBlocks = 256;
 static const int kContactBlocks = 256;
 
-Layout make_layout(long N, long E, long nslots, int nblocks_tile, int vblocks, int n_dir) {
+Layout make_layout(long N, long E, long nslots, long nz_elems, int nblocks_tile, int vblocks, int n_dir) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -152,15 +160,19 @@ Layout make_layout(long N, long E, long nslots, int nblocks_tile, int vblocks, i
   L.r = take(N * 8);
   L.p = take(N * 8);
   L.y = take(N * 8);
+  L.z = take(N * 8);
   L.invdiag = take(N * 8);
   L.gvec = take(N * 8);
   L.c = take(nslots * 64);     // tile-major (tile_slot)
   L.eps_t = take(nslots * 8);
+  L.cflag = take(nslots);      // tile-major: element has a nonzero c_q
+  L.rdz = take(nz_elems * 8);  // inverse z spacings
   L.mask = take(N);
   L.x32 = take(N * 4);
   L.r32 = take(N * 4);
   L.p32 = take(N * 4);
   L.y32 = take(N * 4);
+  L.z32 = take(N * 4);
   L.invdiag32 = take(N * 4);
   L.c32 = take(nslots * 32);
   L.eps32 = take(nslots * 4);
@@ -170,7 +182,7 @@ Layout make_layout(long N, long E, long nslots, int nblocks_tile, int vblocks, i
   np = std::max<long>(np, (long)kContactBlocks * std::max(1, n_dir));
   L.n_partial = np;
   L.partial = take(np * 8);
-  L.partial2 = take(2L * vblocks * 8);
+  L.partial2 = take(std::max<long>(vblocks, cg_blocks(N)) * 8);
   L.ctx = take(sizeof(PcgCtx));
   L.scal = take(64 * 8);
   L.counters = take(16 * sizeof(unsigned int));
@@ -245,7 +257,7 @@ qe_status Context::init(const qe_problem* p, void* ws_, size_t ws_bytes, void* s
   wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
   vblocks = vec_blocks(N);
   nslots = tile_slots(p->nx, p->ny, p->nz);
-  lay = make_layout(N, E, nslots, tm.nblocks, vblocks, p->n_dir);
+  lay = make_layout(N, E, nslots, p->nz - 1, tm.nblocks, vblocks, p->n_dir);
   if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (ws_bytes < lay.total)
@@ -271,6 +283,8 @@ qe_status Context::init(const qe_problem* p, void* ws_, size_t ws_bytes, void* s
     for (int i = 0; i < p->n_dir; ++i)
       if (!std::isfinite(dv[i])) return fail(QE_ERR_NONFINITE, "dir_val[%d] not finite", i);
   }
+  g.rdz = f64(lay.rdz);
+  launch_stage_rdz(s, p->nz, p->z, f64(lay.rdz));
   // reset device scalars and reduction counters
   QE_HIP(hipMemsetAsync(ws + lay.ctx, 0, sizeof(PcgCtx), s));
   QE_HIP(hipMemsetAsync(ws + lay.counters, 0, 16 * sizeof(unsigned int), s));
@@ -304,7 +318,7 @@ qe_status Context::residual(const Charge& ch, const double* phi, const double* d
                             bool mixed, double* diag_out, double* norm2_host) {
   launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
                        f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
-                       mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial), f64(lay.scal));
+                       u8(lay.cflag), mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial), f64(lay.scal));
   QE_HIP(hipGetLastError());
   if (norm2_host) {
     QE_HIP(hipMemcpyAsync(mirror().scal, ws + lay.scal, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -320,11 +334,12 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
                        int* pcg_status, int* iters) {
   PcgCtx* dctx = reinterpret_cast<PcgCtx*>(ws + lay.ctx);
   PcgCtx& h = *mirror().ctx;
+  const int cgb = cg_blocks(N);
   if (mixed)
-    launch_pcg_start32(s, vblocks, N, sign, b, u8(lay.mask), f32(lay.invdiag32), f32(lay.x32), f32(lay.r32),
-                       f32(lay.p32), dctx, f64(lay.partial2), rtol, maxit);
+    launch_pcg_start32(s, cgb, N, sign, b, u8(lay.mask), f32(lay.invdiag32), f32(lay.x32), f32(lay.r32),
+                       f32(lay.z32), dctx, f64(lay.partial2), rtol, maxit);
   else
-    launch_pcg_start64(s, vblocks, N, sign, b, u8(lay.mask), f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.p),
+    launch_pcg_start64(s, cgb, N, sign, b, u8(lay.mask), f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.z),
                        dctx, f64(lay.partial2), rtol, maxit);
   QE_HIP(hipGetLastError());
   int chunk = check_every > 0 ? check_every : 16;
@@ -332,12 +347,13 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
   auto enqueue_chunk = [&](hipStream_t st) {
     for (int k = 0; k < chunk; ++k) {
       if (mixed)
-        launch_pcg_iter32(st, g, wm, vblocks, N, k & 1, f32(lay.eps32), prob.semi, f32(lay.c32), f32(lay.invdiag32),
-                          f32(lay.x32), f32(lay.r32), f32(lay.p32), f32(lay.y32), dctx, f64(lay.partial),
-                          f64(lay.partial2));
+        launch_pcg_iter32(st, g, wm, cgb, N, k & 1, f32(lay.eps32), u8(lay.cflag), f32(lay.c32), f32(lay.invdiag32),
+                          f32(lay.x32), f32(lay.r32), f32(lay.z32), f32(lay.p32), f32(lay.y32), dctx,
+                          f64(lay.partial), f64(lay.partial2));
       else
-        launch_pcg_iter64(st, g, wm, vblocks, N, k & 1, f64(lay.eps_t), prob.semi, f64(lay.c), f64(lay.invdiag),
-                          f64(lay.x), f64(lay.r), f64(lay.p), f64(lay.y), dctx, f64(lay.partial), f64(lay.partial2));
+        launch_pcg_iter64(st, g, wm, cgb, N, k & 1, f64(lay.eps_t), u8(lay.cflag), f64(lay.c), f64(lay.invdiag),
+                          f64(lay.x), f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, f64(lay.partial),
+                          f64(lay.partial2));
     }
   };
   // one captured chunk per precision, replayed until CG stops
@@ -382,7 +398,7 @@ void qe_default_options(qe_options* o) {
   o->newton_atol = 1e-8;
   o->newton_maxit = 100;
   o->ls_max_halvings = 30;
-  o->krylov_rtol_max = 1e-2;
+  o->krylov_rtol_max = 0.3;
   o->krylov_maxit = 20000;
   o->precision = QE_PREC_FP64;
   o->init_guess = 0;
@@ -396,7 +412,7 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
   const long E = (long)(p->nx - 1) * (p->ny - 1) * (p->nz - 1);
   // the tile map with the smallest chunk height has the most blocks
   TileMap tm = make_tilemap(p->nx, p->ny, p->nz, 1);
-  return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), tm.nblocks, vec_blocks(N), p->n_dir).total;
+  return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), p->nz - 1, tm.nblocks, vec_blocks(N), p->n_dir).total;
 }
 
 const char* qe_last_error(void) { return g_last_error.c_str(); }
@@ -441,7 +457,8 @@ qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* 
     if ((st = cx.residual(lin, phi, nullptr, nullptr, 0.0, mixed, nullptr, &n2)) != QE_OK) return finish(st, r, rep);
     if (!std::isfinite(n2)) return finish(fail(QE_ERR_NONFINITE, "initial residual not finite"), r, rep);
     if (n2 > 0) {
-      if ((st = cx.pcg(mixed, cx.f64(cx.lay.F), -1.0, mixed ? 1e-6 : 1e-8, o->krylov_maxit, check, &pst, &its)) != QE_OK)
+      if ((st = cx.pcg(mixed, cx.f64(cx.lay.F), -1.0, mixed ? std::max(1e-6, QE_INIT_RTOL) : QE_INIT_RTOL,
+                       o->krylov_maxit, check, &pst, &its)) != QE_OK)
         return finish(st, r, rep);
       r.init_krylov_iters = its;
       r.krylov_iters += its;
@@ -466,7 +483,8 @@ qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* 
       break;
     }
     if (it == o->newton_maxit) break;
-    double eta = prev < 0 ? o->krylov_rtol_max : std::min(o->krylov_rtol_max, 0.1 * (nrm / prev) * (nrm / prev));
+    double eta = prev < 0 ? o->krylov_rtol_max
+                          : std::min(o->krylov_rtol_max, QE_EW_GAMMA * (nrm / prev) * (nrm / prev));
     eta = std::max(eta, 0.5 * o->newton_atol / nrm);
     eta = std::min(eta, o->krylov_rtol_max);
     eta = std::max(eta, mixed ? 1e-6 : 1e-13);
@@ -541,8 +559,8 @@ qe_status qe_jv(const qe_problem* p, const qe_physics* ph, const double* phi, co
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, false, nullptr, nullptr));
-  launch_jv_wave64(cx.s, cx.g, cx.wm, cx.f64(cx.lay.eps_t), p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v, y, 1,
-                   nullptr, nullptr);
+  launch_jv_wave64(cx.s, cx.g, cx.wm, cx.f64(cx.lay.eps_t), cx.u8(cx.lay.cflag), cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v,
+                   y, 1);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -560,16 +578,16 @@ qe_status qe_jv_f32(const qe_problem* p, const qe_physics* ph, const double* phi
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, true, nullptr, nullptr));
   launch_stage_eps32(cx.s, cx.vblocks, cx.g, p->eps_r, cx.f32(cx.lay.eps32), cx.nslots);
-  launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v, y, 1,
-                   nullptr, nullptr);
+  launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), cx.u8(cx.lay.cflag), cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v,
+                   y, 1);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
 }
 
 qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* phi, const double* v,
-                     int32_t precision, int32_t reps, double* ms_per_apply, void* ws, size_t ws_bytes,
-                     void* stream) {
+                     int32_t precision, int32_t reps, double* ms_per_apply, int64_t* n_coef_elems,
+                     void* ws, size_t ws_bytes, void* stream) {
   clear_error();
   Charge ch;
   QE_TRY(make_charge(ph, ch));
@@ -582,24 +600,44 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, mixed, nullptr, nullptr));
-  // the CG operand: v with its Dirichlet entries zeroed, as CG keeps it
+  // The CG loop's first kernel in its steady state (iteration >= 1,
+  // beta = 1): z = D^-1 v on free rows (0 on Dirichlet rows, as CG keeps it),
+  // y = p = 0, and scalars that never stop the solve.
+  const int cgb = cg_blocks(cx.N);
+  PcgCtx* dctx = reinterpret_cast<PcgCtx*>(cx.ws + cx.lay.ctx);
   if (mixed) {
     launch_stage_eps32(cx.s, cx.vblocks, cx.g, p->eps_r, cx.f32(cx.lay.eps32), cx.nslots);
-    launch_masked_copy_d2f(cx.s, cx.vblocks, cx.N, cx.u8(cx.lay.mask), v, cx.f32(cx.lay.p32));
+    launch_pcg_start32(cx.s, cgb, cx.N, 1.0, v, cx.u8(cx.lay.mask), cx.f32(cx.lay.invdiag32), cx.f32(cx.lay.x32),
+                       cx.f32(cx.lay.r32), cx.f32(cx.lay.z32), dctx, cx.f64(cx.lay.partial2), 0.0, 1 << 30);
+    QE_HIP(hipMemsetAsync(cx.ws + cx.lay.y32, 0, cx.N * 4, cx.s));
+    QE_HIP(hipMemsetAsync(cx.ws + cx.lay.p32, 0, cx.N * 4, cx.s));
   } else {
-    launch_masked_copy_d2d(cx.s, cx.vblocks, cx.N, cx.u8(cx.lay.mask), v, cx.f64(cx.lay.p));
+    launch_pcg_start64(cx.s, cgb, cx.N, 1.0, v, cx.u8(cx.lay.mask), cx.f64(cx.lay.invdiag), cx.f64(cx.lay.x),
+                       cx.f64(cx.lay.r), cx.f64(cx.lay.z), dctx, cx.f64(cx.lay.partial2), 0.0, 1 << 30);
+    QE_HIP(hipMemsetAsync(cx.ws + cx.lay.y, 0, cx.N * 8, cx.s));
+    QE_HIP(hipMemsetAsync(cx.ws + cx.lay.p, 0, cx.N * 8, cx.s));
   }
-  const PcgCtx* dctx = reinterpret_cast<const PcgCtx*>(cx.ws + cx.lay.ctx);  // zeroed: not done
+  PcgCtx& hc = *mirror().ctx;
+  QE_HIP(hipMemcpyAsync(&hc, dctx, sizeof(PcgCtx), hipMemcpyDeviceToHost, cx.s));
+  QE_HIP(hipStreamSynchronize(cx.s));
+  if (hc.done) return fail(QE_ERR_INVALID_ARG, "v vanishes on the free nodes");
+  hc.iters = 1;
+  hc.rzs[1] = hc.rzs[0];
+  hc.tol2 = 0.0;
+  QE_HIP(hipMemcpyAsync(dctx, &hc, sizeof(PcgCtx), hipMemcpyHostToDevice, cx.s));
+  QE_HIP(hipStreamSynchronize(cx.s));
   hipEvent_t e0, e1;
   QE_HIP(hipEventCreate(&e0));
   QE_HIP(hipEventCreate(&e1));
   auto once = [&]() {
     if (mixed)
-      launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), p->semi, cx.f32(cx.lay.c32), nullptr,
-                       cx.f32(cx.lay.p32), cx.f32(cx.lay.y32), 1, dctx, cx.f64(cx.lay.partial));
+      launch_cg_jv32(cx.s, cx.g, cx.wm, cgb, 0, cx.f32(cx.lay.eps32), cx.u8(cx.lay.cflag), cx.f32(cx.lay.c32),
+                     cx.f32(cx.lay.z32), cx.f32(cx.lay.y32), cx.f32(cx.lay.p32), dctx, cx.f64(cx.lay.partial2),
+                     cx.f64(cx.lay.partial));
     else
-      launch_jv_wave64(cx.s, cx.g, cx.wm, cx.f64(cx.lay.eps_t), p->semi, cx.f64(cx.lay.c), nullptr, cx.f64(cx.lay.p),
-                       cx.f64(cx.lay.y), 1, dctx, cx.f64(cx.lay.partial));
+      launch_cg_jv64(cx.s, cx.g, cx.wm, cgb, 0, cx.f64(cx.lay.eps_t), cx.u8(cx.lay.cflag), cx.f64(cx.lay.c),
+                     cx.f64(cx.lay.z), cx.f64(cx.lay.y), cx.f64(cx.lay.p), dctx, cx.f64(cx.lay.partial2),
+                     cx.f64(cx.lay.partial));
   };
   once();  // warm-up
   hipError_t e = hipEventRecord(e0, cx.s);
@@ -612,6 +650,17 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(QE_ERR_HIP, "timing failed: %s", hipGetErrorString(e));
   *ms_per_apply = (double)ms / reps;
+  if (n_coef_elems) {
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(cx.ws + cx.lay.scal) + 63;
+    QE_HIP(hipMemsetAsync(cnt, 0, sizeof(*cnt), cx.s));
+    launch_count_flags(cx.s, cx.vblocks, cx.g, cx.u8(cx.lay.cflag), cx.nslots, cnt);
+    QE_HIP(hipGetLastError());
+    QE_HIP(hipMemcpyAsync(mirror().scal, cnt, sizeof(*cnt), hipMemcpyDeviceToHost, cx.s));
+    QE_HIP(hipStreamSynchronize(cx.s));
+    unsigned long long v64;
+    std::memcpy(&v64, mirror().scal, sizeof(v64));
+    *n_coef_elems = (int64_t)v64;
+  }
   return QE_OK;
 }
 
@@ -692,7 +741,7 @@ qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options
                        pst), r, rep);
   // dQ/deps goes to the caller's buffer or to scratch (the y vector; E < N)
   double* deps_buf = dQ_deps ? dQ_deps : cx.f64(cx.lay.y);
-  launch_adj_grad(cx.s, cx.g, cx.tm, p->eps_r, p->semi, cx.f64(cx.lay.c), cx.u8(cx.lay.mask), cx.f64(cx.lay.x), phi,
+  launch_adj_grad(cx.s, cx.g, cx.tm, p->eps_r, cx.u8(cx.lay.cflag), cx.f64(cx.lay.c), cx.u8(cx.lay.mask), cx.f64(cx.lay.x), phi,
                   cx.f64(cx.lay.gvec), deps_buf, cx.f64(cx.lay.r));
   if (p->n_dir > 0)
     launch_contact_sum(cx.s, kContactBlocks, cx.N, p->n_dir, p->dir_id, cx.f64(cx.lay.r), cx.f64(cx.lay.partial),

@@ -75,6 +75,7 @@ struct WaveTile {
   long n00, ecol, elayer, sxy;
   long slot0, slot_layer;   // tile-major slot of this lane's element at layer 0, stride per layer
   double hx, hy;
+  double ahx, ahy, axy;     // hy/hx, hx/hy, hx*hy: the element's stiffness weights are eps*(ahx hz, ahy hz, axy/hz)
 
   __device__ __forceinline__ WaveTile(const Geom& g, int wx, int wy, int wz, int kz, int lane_, bool active) {
     lane = lane_;
@@ -102,6 +103,9 @@ struct WaveTile {
       hx = g.x[ex + 1] - g.x[ex];
       hy = g.y[ey + 1] - g.y[ey];
     }
+    ahx = hy / hx;
+    ahy = hx / hy;
+    axy = hx * hy;
   }
   __device__ __forceinline__ long slot(int L) const { return slot0 + slot_layer * L; }
   __device__ __forceinline__ long node(const Geom& g, int L) const { return (long)gi + (long)g.nx * gj + sxy * L; }
@@ -113,38 +117,60 @@ struct WaveTile {
         if (semi[ecol + elayer * L]) b |= 1u << (L - Lbeg);
     return b;
   }
+  // the same for a tile-major per-element flag array (one byte per slot)
+  __device__ __forceinline__ unsigned int slot_bits(const Geom& g, const uint8_t* __restrict__ flag) const {
+    unsigned int b = 0;
+    if (col_ok)
+      for (int L = max(Lbeg, 0); L <= min(Lend, g.nz - 2); ++L)
+        if (flag[slot(L)]) b |= 1u << (L - Lbeg);
+    return b;
+  }
 };
 
 // ---------------------------------------------------------------------------
-// J.v on one wave tile (see k_jv_wave).  eps_t and cq are in tile-major order
-// (tile_slot).  v is read as 0 on Dirichlet nodes
-// (kPcg: v already vanishes there and Dirichlet rows are written as 0);
-// identity_rows: Dirichlet rows return v_i.  dot accumulates p^T J p over the
-// elements this wave owns (kPcg).
-template <typename T, bool kPcg>
+// J.v on one wave tile (see k_jv_wave).  eps_t, cq and cflag are in
+// tile-major order (tile_slot); cflag marks the elements whose Gauss-point
+// coefficients are not all exactly zero, and only those read cq (a zero
+// coefficient adds exactly nothing).  Modes:
+//   JV_PLAIN  y = J v with v read as 0 on Dirichlet nodes; identity_rows:
+//             Dirichlet rows return v_i.
+//   JV_DOT    v = a CG direction (zero on Dirichlet nodes); y = J v on every
+//             owned row; dot += v^T J v over the elements this wave owns.
+//   JV_REC    v = z (zero on Dirichlet nodes); on owned rows
+//             y = J z + beta y and p = z + beta p (first: y = J z, p = z),
+//             so y = J p by recurrence; dot += p^T y over owned nodes.
+// In the CG modes the Dirichlet flag is not read at all: the vectors vanish
+// on Dirichlet nodes and D^-1 is 0 there, so whatever y holds on those rows
+// never reaches z, p or x.
+enum JvMode { JV_PLAIN = 0, JV_DOT = 1, JV_REC = 2 };
+
+template <typename T, int kMode>
 __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const T* __restrict__ eps_t,
-                                        const uint8_t* __restrict__ semi, const T* __restrict__ cq,
+                                        const uint8_t* __restrict__ cflag, const T* __restrict__ cq,
                                         const uint8_t* __restrict__ mask, const T* __restrict__ v,
-                                        T* __restrict__ y, int identity_rows, double& dot) {
-  const unsigned int sbits = w.semi_bits(g, semi);
+                                        T* __restrict__ y, int identity_rows, double& dot,
+                                        T* __restrict__ p = nullptr, T beta = T(0), bool first = true) {
+  constexpr bool kPlain = kMode == JV_PLAIN, kRec = kMode == JV_REC;
+  const unsigned int sbits = w.slot_bits(g, cflag);
   auto face = [&](int P, T f[4]) {
     const long b = w.n00 + w.sxy * P;
     const long o[4] = {0, 1, g.nx, g.nx + 1};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       T val = v[b + o[k]];
-      if (!kPcg && mask[b + o[k]]) val = T(0);
+      if (kPlain && mask[b + o[k]]) val = T(0);
       f[k] = val;
     }
   };
-  // Everything a layer needs is loaded one layer ahead and consumed only in
-  // the next iteration, and no load is issued after those prefetches inside
-  // an iteration: a wait for any later load would drain them (loads retire
-  // in order).  In CG (kPcg) the Dirichlet flag is not read at all: p vanishes
-  // on Dirichlet nodes and D^-1 is 0 there, so whatever y holds on those rows
-  // never reaches z, p or x.
+  // Everything a layer's elements need is loaded one layer ahead and consumed
+  // only in the next iteration, and no load is issued after those prefetches
+  // inside an iteration: a wait for any later load would drain them (loads
+  // retire in order).
+  const bool rec_old = kRec && !first;
+  const bool z_own = kRec && !w.col_ok && w.node_ok;   // owned node outside every element face loaded
   T fb[4], ft[4], fn[4];
   T cc[8], cn[8], ee = T(0), en = T(0);
+  T yc = T(0), pc = T(0), zc = T(0);
   uint8_t mk = 0, mkn = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) fb[k] = ft[k] = fn[k] = T(0);
@@ -157,12 +183,36 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
     ee = eps_t[sl];
     if (sbits & 1u) load8(cq + 8 * sl, cc);
   }
-  if (!kPcg && w.node_ok && w.Lbeg >= 0) mk = mask[w.node(g, w.Lbeg)];
+  if (kPlain && w.node_ok && w.Lbeg >= 0) mk = mask[w.node(g, w.Lbeg)];
   T carry = T(0);
+  // Retire the loads above before the loop.  Otherwise the first iteration's
+  // operands are still in flight on entry, and the wait inserted for them
+  // inside the loop body (a vmcnt wait, which retires in order) also drains
+  // every prefetch of every later iteration.  An empty asm that reads and
+  // writes each value forces that wait here without touching memory.
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    asm("" : "+v"(fb[k]));
+    asm("" : "+v"(ft[k]));
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) asm("" : "+v"(cc[k]));
+  asm("" : "+v"(ee));
   for (int L = w.Lbeg; L <= w.Lend; ++L) {
     const bool layer_ok = (L >= 0 && L <= g.nz - 2);
     const int L1 = L + 1;
     const double hz = layer_ok ? g.z[L + 1] - g.z[L] : 1.0;
+    const double rhz = layer_ok ? g.rdz[L] : 1.0;
+    // the recurrence mode's y, p (and z) at this layer's owned node, issued
+    // before the prefetches so that their wait does not drain them
+    if (kRec && w.node_ok && L >= w.k0) {
+      const long n = w.node(g, L);
+      if (rec_old) {
+        yc = y[n];
+        pc = p[n];
+      }
+      if (z_own) zc = v[n];
+    }
     // prefetch the next top face, the next layer's data and the next flag
     if (w.col_ok && L1 <= w.Lend && L1 + 1 <= g.nz - 1) face(L1 + 1, fn);
     if (w.col_ok && L1 <= w.Lend && L1 <= g.nz - 2) {
@@ -170,13 +220,14 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
       en = eps_t[sl];
       if ((sbits >> (L1 - w.Lbeg)) & 1u) load8(cq + 8 * sl, cn);
     }
-    if (!kPcg && w.node_ok && L1 <= w.Lend) mkn = mask[w.node(g, L1)];
+    if (kPlain && w.node_ok && L1 <= w.Lend) mkn = mask[w.node(g, L1)];
     T out[8];
     if (w.col_ok && layer_ok) {
-      const T sx = ee * T(w.hy * hz / w.hx), sy = ee * T(w.hx * hz / w.hy), sz = ee * T(w.hx * w.hy / hz);
+      const T sx = ee * T(w.ahx * hz), sy = ee * T(w.ahy * hz), sz = ee * T(w.axy * rhz);
       const T ve[8] = {fb[0], fb[1], fb[2], fb[3], ft[0], ft[1], ft[2], ft[3]};
-      const double d = jv_element<T, kPcg>(ve, sx, sy, sz, cc, ((sbits >> (L - w.Lbeg)) & 1u) != 0, out);
-      if (kPcg && w.own_el && L >= w.k0) dot += d;
+      const double d =
+          jv_element<T, kMode == JV_DOT>(ve, sx, sy, sz, cc, ((sbits >> (L - w.Lbeg)) & 1u) != 0, out);
+      if (kMode == JV_DOT && w.own_el && L >= w.k0) dot += d;
     } else {
 #pragma unroll
       for (int k = 0; k < 8; ++k) out[k] = T(0);
@@ -186,7 +237,17 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
     if (w.node_ok && L >= w.k0) {
       const long n = w.node(g, L);
       T val = carry + bot;
-      if (!kPcg && mk && identity_rows) val = v[n];
+      if (kRec) {
+        const T zo = w.col_ok ? fb[3] : zc;   // z at the owned node (gi, gj, L)
+        T pv = zo;
+        if (rec_old) {
+          val += beta * yc;
+          pv += beta * pc;
+        }
+        p[n] = pv;
+        dot += (double)pv * (double)val;
+      }
+      if (kPlain && mk && identity_rows) val = v[n];
       y[n] = val;
     }
     carry = top;
@@ -206,7 +267,9 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
 // Residual F(phi + lam delta), Jacobi diagonal and Gauss-point coefficients
 // c_q = KAPPA semi W n'(phi_q) on one wave tile.  F and the diagonal are
 // written on owned nodes (0 and 1 on Dirichlet rows, where the stored inverse
-// diagonal is 0); c_q, in tile-major order, by the owning wave.
+// diagonal is 0).  The owning wave writes, in tile-major order, cflag = 1 for
+// an element with a nonzero c_q and then its c_q, else cflag = 0 and nothing
+// (depleted silicon, where n' underflows to exactly 0, and insulators).
 // norm2 accumulates F_i^2 over owned free nodes.
 template <typename TD>
 __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, const Charge& ch,
@@ -215,8 +278,8 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
                                               const double* __restrict__ phi, const TD* __restrict__ delta,
                                               double lam, double* __restrict__ F, double* __restrict__ invdiag,
                                               double* __restrict__ diag_out, double* __restrict__ cq,
-                                              float* __restrict__ cq32, float* __restrict__ invdiag32,
-                                              double& norm2) {
+                                              float* __restrict__ cq32, uint8_t* __restrict__ cflag,
+                                              float* __restrict__ invdiag32, double& norm2) {
   const unsigned int sbits = w.semi_bits(g, semi);
   auto face = [&](int P, double f[4]) {
     const long b = w.n00 + w.sxy * P;
@@ -241,7 +304,7 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
       const long el = w.ecol + w.elayer * L;
       const double hz = g.z[L + 1] - g.z[L];
       const double ee = eps[el];
-      const double sx = ee * (w.hy * hz / w.hx), sy = ee * (w.hx * hz / w.hy), sz = ee * (w.hx * w.hy / hz);
+      const double sx = ee * (w.ahx * hz), sy = ee * (w.ahy * hz), sz = ee * (w.axy * g.rdz[L]);
       const double ve[8] = {fb[0], fb[1], fb[2], fb[3], ft[0], ft[1], ft[2], ft[3]};
       double zero[8];
 #pragma unroll
@@ -250,6 +313,8 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
       const double dg = (sx + sy + sz) * (1.0 / 9.0);
 #pragma unroll
       for (int k = 0; k < 8; ++k) outD[k] = dg;
+      const bool own = w.own_el && L >= w.k0;
+      bool nzc = false;
       if ((sbits >> (L - w.Lbeg)) & 1u) {
         const double kw = ch.kappa * w.hx * w.hy * hz * 0.125;
         const double nd = netdop ? netdop[el] : 0.0;
@@ -263,8 +328,9 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
           electron_density(ch, src[q], n, dn);
           src[q] = kw * (nd - n);
           cc[q] = kw * dn;
+          nzc |= cc[q] != 0.0;
         }
-        if (w.own_el && L >= w.k0) {
+        if (own && nzc) {
           const long sl = w.slot(L);
           store8(cq + 8 * sl, cc);
           if (cq32) store8(cq32 + 8 * sl, cc);
@@ -277,6 +343,7 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
           outD[k] += cc[k];
         }
       }
+      if (own) cflag[w.slot(L)] = nzc ? 1 : 0;
     } else {
 #pragma unroll
       for (int k = 0; k < 8; ++k) outF[k] = outD[k] = 0.0;

@@ -95,7 +95,7 @@ def load_library(path=LIB_PATH):
         "qe_batch_workspace_bytes": (S, [I32, pp, po]),
         "qe_solve_batch": (I32, [I32, pp, pph, po, P(V), I32, P(D), P(D), ctypes.c_char_p,
                                  V, S, V, pr]),
-        "qe_time_jv": (I32, [pp, pph, V, V, I32, I32, P(D), V, S, V]),
+        "qe_time_jv": (I32, [pp, pph, V, V, I32, I32, P(D), P(ctypes.c_int64), V, S, V]),
         "qe_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -305,15 +305,17 @@ def qe_adjoint(prob, phi, box, phys=None, opts=None, ws=None, want_eps=True, wan
 
 
 def qe_time_jv(prob, phi, v, precision="fp64", reps=200, phys=None, ws=None):
-    """Mean time (ms) of one J.v kernel launch, measured with HIP events."""
+    """Mean time (ms) of one CG J.v kernel launch, measured with HIP events,
+    and the number of elements whose Gauss-point coefficients it reads."""
     lib = load_library()
     phys = phys or prob.physics
     ms = ctypes.c_double(0.0)
+    ncoef = ctypes.c_int64(0)
     ws = ws or workspace_for(prob)
     cp, cph = prob.c(), phys.c()
     _check(lib.qe_time_jv(ctypes.byref(cp), ctypes.byref(cph), _ptr(phi), _ptr(v), PREC[precision],
-                          int(reps), ctypes.byref(ms), ws.ptr, ws.nbytes, _stream()))
-    return ms.value
+                          int(reps), ctypes.byref(ms), ctypes.byref(ncoef), ws.ptr, ws.nbytes, _stream()))
+    return ms.value, int(ncoef.value)
 
 
 def qe_batch_workspace_bytes(probs, opts=None):
