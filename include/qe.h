@@ -107,8 +107,8 @@ typedef struct {
   int32_t precision;             /* qe_precision */
   int32_t init_guess;            /* 0: linear (charge-free) Poisson solve;
                                     1: start from the phi passed in */
-  int32_t check_every;           /* CG iterations between host convergence checks
-                                    (0 = library default) */
+  int32_t check_every;           /* CG iterations the host keeps queued beyond
+                                    those known to have finished (0 = 4) */
 } qe_options;
 
 typedef struct {

@@ -42,6 +42,7 @@ struct BatchInst {
   double* phi;
   double *F, *x, *r, *p, *y, *invdiag, *c, *eps_t;   // c, eps_t, cflag tile-major (tile_slot)
   uint8_t *mask, *cflag;
+  unsigned int* cbits;   // [ntiles][64] per-lane coefficient flags over the chunk
   double* rdz;   // [nz-1] inverse z spacings (g.rdz points here)
   long N, nslots;
   int gx, gy, gz, kz, ntiles;
@@ -111,7 +112,7 @@ __device__ double b_residual(const BatchInst& I, const Charge& ch, const double*
   for (int t = threadIdx.x >> 6; t < I.ntiles; t += NT / 64) {
     const WaveTile w = tile_at(I, t);
     residual_tile<double>(I.g, w, ch, I.eps, I.semi, I.netdop, I.mask, I.phi, delta, lam, I.F, I.invdiag, nullptr,
-                          I.c, nullptr, I.cflag, nullptr, acc);
+                          I.c, nullptr, I.cflag, I.cbits + 64L * t + (threadIdx.x & 63), nullptr, acc);
   }
   return bsum<NT>(acc, sred);
 }
@@ -145,7 +146,8 @@ __device__ int b_pcg(const BatchInst& I, const double* b, double sign, double rt
     double dot = 0.0;
     for (int t = threadIdx.x >> 6; t < I.ntiles; t += NT / 64) {
       const WaveTile w = tile_at(I, t);
-      jv_tile<double, JV_DOT>(I.g, w, I.eps_t, I.cflag, I.c, nullptr, I.p, I.y, 1, dot);
+      jv_tile<double, JV_DOT>(I.g, w, I.eps_t, I.cbits[64L * t + (threadIdx.x & 63)], I.c, nullptr, I.p, I.y, 1,
+                              dot);
     }
     const double pAp = bsum<NT>(dot, sred);
     if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -330,10 +332,16 @@ struct BatchConfig {
 
 static size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 
+static const int kTuneKz[3] = {4, 8, 16};   // chunk heights the tuner tries
+static const int kMinKz = 4;
+
 static size_t inst_bytes(const qe_problem& p) {
   const long N = (long)p.nx * p.ny * p.nz;
   const long S = tile_slots(p.nx, p.ny, p.nz);
-  return 6 * al256(N * 8) + al256(S * 64) + al256(S * 8) + al256(S) + al256(N) + al256((p.nz - 1) * 8);
+  // per-lane coefficient words for the shortest chunk height the tuner uses
+  const long tiles = (long)((p.nx + 6) / 7) * ((p.ny + 6) / 7) * ((p.nz + kMinKz - 1) / kMinKz);
+  return 6 * al256(N * 8) + al256(S * 64) + al256(S * 8) + al256(S) + al256(N) + al256((p.nz - 1) * 8) +
+         al256(tiles * 64 * 4);
 }
 
 static size_t batch_bytes(int n, const qe_problem* probs) {
@@ -414,7 +422,8 @@ static bool read_cache(const char* path, const std::string& key, BatchConfig& cf
     std::istringstream is(line);
     std::string k;
     int t, kz;
-    if (is >> k >> t >> kz && k == key && (t == 256 || t == 512 || t == 1024) && kz >= 1 && kz <= 31) {
+    if (is >> k >> t >> kz && k == key && (t == 256 || t == 512 || t == 1024) &&
+        (kz == kTuneKz[0] || kz == kTuneKz[1] || kz == kTuneKz[2])) {
       cfg.threads = t;
       cfg.kz = kz;
       return true;
@@ -537,6 +546,8 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
       I.eps_t = reinterpret_cast<double*>(tk(S * 8));
       I.cflag = reinterpret_cast<uint8_t*>(tk(S));
       I.rdz = reinterpret_cast<double*>(tk((p.nz - 1) * 8));
+      I.cbits = reinterpret_cast<unsigned int*>(
+          tk((size_t)((p.nx + 6) / 7) * ((p.ny + 6) / 7) * ((p.nz + kMinKz - 1) / kMinKz) * 64 * 4));
       I.g.rdz = I.rdz;
       I.nslots = S;
       I.mask = reinterpret_cast<uint8_t*>(tk(N));
@@ -608,7 +619,7 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
     // autotune on the largest instances (the ones that bound the sweep)
     const int n_try = std::min(n_inst, std::max(1, cus / 8));
     const int cand_t[3] = {256, 512, 1024};
-    const int cand_kz[3] = {4, 8, 16};
+    const int* cand_kz = kTuneKz;
     double best = 1e300;
     BatchConfig bestc = cfg;
     for (int ti = 0; ti < 3 && result == QE_OK; ++ti)

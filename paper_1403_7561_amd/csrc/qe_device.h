@@ -319,6 +319,14 @@ __device__ __forceinline__ double uniform(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Lane `idx` (wave-uniform) of v, in scalar registers.
+__device__ __forceinline__ double lane_value(double v, int idx) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned int lo = __builtin_amdgcn_readlane((unsigned int)b, idx);
+  const unsigned int hi = __builtin_amdgcn_readlane((unsigned int)(b >> 32), idx);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

@@ -22,6 +22,13 @@ struct BoxSet {
 
 enum PcgStatus : int { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_BREAKDOWN = 2, PCG_MAXIT = 3, PCG_NONFINITE = 4 };
 
+// The stop of a CG solve, posted by the kernel that takes it into
+// host-coherent memory so the host learns it without copies, as one word:
+// ((iterations + 1) << 4) | (status << 1) | 1.
+struct CgProgress {
+  int word;
+};
+
 // Conjugate-gradient scalars, kept on the device between kernels.
 struct PcgCtx {
   double rzs[2], pAp, alpha, beta, tol2;
@@ -53,20 +60,20 @@ WaveMap make_wavemap(int nx, int ny, int nz, int kz);
 void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
                           const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
                           const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
-                          double* diag_out, double* cq, float* cq32, uint8_t* cflag, float* invdiag32,
-                          double* partial, double* norm2);
+                          double* diag_out, double* cq, float* cq32, uint8_t* cflag, unsigned int* cbits,
+                          float* invdiag32, double* partial, double* norm2);
 // y = J v with v read as 0 on Dirichlet nodes (identity_rows: y_i = v_i there).
-void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const uint8_t* cflag,
+void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const unsigned int* cbits,
                       const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows);
-void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const uint8_t* cflag,
+void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const unsigned int* cbits,
                       const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows);
 // First kernel of CG iteration k: stopping test, beta, y = J z + beta y,
 // p = z + beta p, p^T y partials.
 void launch_cg_jv64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const double* eps_t,
-                    const uint8_t* cflag, const double* cq, const double* z, double* y, double* p, PcgCtx* ctx,
+                    const unsigned int* cbits, const double* cq, const double* z, double* y, double* p, PcgCtx* ctx, CgProgress* prog,
                     const double* part_rz, double* part_py);
 void launch_cg_jv32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const float* eps_t,
-                    const uint8_t* cflag, const float* cq, const float* z, float* y, float* p, PcgCtx* ctx,
+                    const unsigned int* cbits, const float* cq, const float* z, float* y, float* p, PcgCtx* ctx, CgProgress* prog,
                     const double* part_rz, double* part_py);
 // Tile-major permittivity copy for the wave-tiled J.v (see tile_slot).
 void launch_stage_eps64(hipStream_t s, int nblocks, const Geom& g, const double* eps, double* eps_t, long nslots);
@@ -86,10 +93,10 @@ void launch_pcg_start32(hipStream_t s, int cgblocks, long N, double sign, const 
                         double rtol, int maxit);
 // CG iteration (parity k): k_cg_jv, then k_cg_update on cgblocks blocks.
 void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
-                       const double* eps_t, const uint8_t* cflag, const double* cq, const double* invdiag, double* x,
-                       double* r, double* z, double* p, double* y, PcgCtx* ctx, double* part_py, double* part_rz);
+                       const double* eps_t, const unsigned int* cbits, const double* cq, const double* invdiag, double* x,
+                       double* r, double* z, double* p, double* y, PcgCtx* ctx, CgProgress* prog, double* part_py, double* part_rz);
 void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
-                       const float* eps_t, const uint8_t* cflag, const float* cq, const float* invdiag, float* x,
-                       float* r, float* z, float* p, float* y, PcgCtx* ctx, double* part_py, double* part_rz);
+                       const float* eps_t, const unsigned int* cbits, const float* cq, const float* invdiag, float* x,
+                       float* r, float* z, float* p, float* y, PcgCtx* ctx, CgProgress* prog, double* part_py, double* part_rz);
 
 }  // namespace qe

@@ -59,8 +59,17 @@ __device__ __forceinline__ long elem_index(const Geom& g, int ex, int ey, int ez
 // same in every thread of the block.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, int stride, int off,
                                                double* sred) {
+  // eight loads in flight per thread before any is added (a load-add loop
+  // would wait for each in turn)
   double a = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[(long)i * stride + off];
+  const int bs = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * bs) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (i0 + j * bs < n) ? part[(long)(i0 + j * bs) * stride + off] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a += v[j];
+  }
   a = wave_sum(a);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -76,10 +85,11 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 // Wave-tiled kernels: four independent waves per block, one wave tile each
 // (see qe_tiles.h).  No LDS and no block barrier in the sweep, so memory
 // latency is hidden by the other waves on the SIMD.
-__device__ __forceinline__ void wave_coords(const WaveMap& wm, int& wx, int& wy, int& wz, bool& active) {
+__device__ __forceinline__ void wave_coords(const WaveMap& wm, int& wx, int& wy, int& wz, bool& active, int& wid) {
   // wave-uniform (scalar registers): the layer loop, z spacings and tile
   // bounds are then scalar and never wait on vector loads
   const int w = __builtin_amdgcn_readfirstlane(wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6));
+  wid = w;
   active = w < wm.nwaves;
   wx = w % wm.gx;
   wy = (w / wm.gx) % wm.gy;
@@ -92,58 +102,81 @@ __device__ __forceinline__ void wave_coords(const WaveMap& wm, int& wx, int& wy,
 // y = J v (JV_PLAIN: v read as 0 on Dirichlet nodes, identity_rows optional).
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_JV_MIN_WAVES, 8))) void k_jv_wave(
-    Geom g, WaveMap wm, const T* __restrict__ eps, const uint8_t* __restrict__ cflag,
+    Geom g, WaveMap wm, const T* __restrict__ eps, const unsigned int* __restrict__ cbits,
     const T* __restrict__ cq, const uint8_t* __restrict__ mask, const T* __restrict__ v,
     T* __restrict__ y, int identity_rows) {
-  int wx, wy, wz;
+  int wx, wy, wz, wid;
   bool active;
-  wave_coords(wm, wx, wy, wz, active);
+  wave_coords(wm, wx, wy, wz, active, wid);
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
+  const unsigned int cb = active ? cbits[64L * wid + (threadIdx.x & 63)] : 0u;
   double dot = 0.0;
-  jv_tile<T, JV_PLAIN>(g, w, eps, cflag, cq, mask, v, y, identity_rows, dot);
+  jv_tile<T, JV_PLAIN>(g, w, eps, cb, cq, mask, v, y, identity_rows, dot);
 }
 
-// CG iteration k, first kernel.  Re-adds the r^T z partials of the previous
-// kernel (rz_k), stops the solve on convergence / non-finite values / the
-// iteration limit (block 0 records the decision; every block takes the same
-// one), then beta = rz_k / rz_{k-1} and, on the wave tiles,
-// y = J z + beta y, p = z + beta p (JV_REC); one p^T y partial per block.
-// rz_k goes to ctx->rzs[k & 1] and rz_{k-1} is read from the other slot.
+// Posts a CG decision to host-coherent memory (one vector store, system scope).
+__device__ __forceinline__ void post_progress(CgProgress* prog, int iters, int done, int status) {
+  __hip_atomic_store(&prog->word, ((iters + 1) << 4) | (status << 1) | done, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// CG iteration k, first kernel.  Once each wave's first loads are in flight,
+// the block re-adds the r^T z partials of the previous kernel (rz_k) and
+// stops the solve on convergence / non-finite values / the iteration limit
+// (block 0 records the decision; every block takes the same one).  Then
+// beta = rz_k / rz_{k-1} and, on the wave tiles, y = J z + beta y,
+// p = z + beta p (JV_REC); one p^T y partial per block.  rz_k goes to
+// ctx->rzs[k & 1] and rz_{k-1} is read from the other slot.
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_JV_MIN_WAVES, 8))) void k_cg_jv(
-    Geom g, WaveMap wm, const T* __restrict__ eps, const uint8_t* __restrict__ cflag,
+    Geom g, WaveMap wm, const T* __restrict__ eps, const unsigned int* __restrict__ cbits,
     const T* __restrict__ cq, const T* __restrict__ z, T* __restrict__ y, T* __restrict__ p, int k,
-    PcgCtx* __restrict__ ctx, const double* __restrict__ part_rz, int n_rz, double* __restrict__ part_py) {
+    PcgCtx* __restrict__ ctx, CgProgress* __restrict__ prog, const double* __restrict__ part_rz, int n_rz,
+    double* __restrict__ part_py) {
   if (ctx->done) return;
   __shared__ double sred[4];
-  const double RZ = uniform(sum_partials(part_rz, n_rz, 1, 0, sred));
-  const int it = ctx->iters;
-  const double rzprev = ctx->rzs[(k + 1) & 1];
-  const bool bad = !isfinite(RZ), conv = !bad && RZ <= ctx->tol2, maxed = it >= ctx->maxit;
-  const bool first = it == 0;
-  const double b = uniform(first ? 0.0 : RZ / rzprev);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctx->rzs[k & 1] = RZ;
-    if (bad) {
-      ctx->done = 1;
-      ctx->status = PCG_NONFINITE;
-    } else if (conv) {
-      ctx->done = 1;
-      ctx->status = PCG_CONVERGED;
-    } else if (maxed) {
-      ctx->done = 1;
-      ctx->status = PCG_MAXIT;
-    } else {
-      ctx->beta = b;
-    }
-  }
-  if (bad || conv || maxed) return;
-  int wx, wy, wz;
+  int wx, wy, wz, wid;
   bool active;
-  wave_coords(wm, wx, wy, wz, active);
+  wave_coords(wm, wx, wy, wz, active, wid);
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
+  const unsigned int cb = active ? cbits[64L * wid + (threadIdx.x & 63)] : 0u;
+  int stop_status = PCG_RUNNING, stop_iters = 0;
+  double* const sp = sred;
+  // pointers captured by value keep their no-alias qualification, so the
+  // sweep's z-spacing loads stay scalar
+  auto decide = [=, &stop_status, &stop_iters]() -> JvGo<T> {
+    const double RZ = uniform(sum_partials(part_rz, n_rz, 1, 0, sp));
+    const int it = ctx->iters;
+    const double rzprev = ctx->rzs[(k + 1) & 1];
+    const bool bad = !isfinite(RZ), conv = !bad && RZ <= ctx->tol2, maxed = it >= ctx->maxit;
+    const bool first = it == 0;
+    const double b = uniform(first ? 0.0 : RZ / rzprev);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      ctx->rzs[k & 1] = RZ;
+      if (bad) {
+        ctx->done = 1;
+        ctx->status = PCG_NONFINITE;
+      } else if (conv) {
+        ctx->done = 1;
+        ctx->status = PCG_CONVERGED;
+      } else if (maxed) {
+        ctx->done = 1;
+        ctx->status = PCG_MAXIT;
+      } else {
+        ctx->beta = b;
+      }
+    }
+    stop_status = bad ? PCG_NONFINITE : conv ? PCG_CONVERGED : PCG_MAXIT;
+    stop_iters = it;
+    return {!(bad || conv || maxed), (T)b, first};
+  };
   double dot = 0.0;
-  jv_tile<T, JV_REC>(g, w, eps, cflag, cq, nullptr, z, y, 1, dot, p, (T)b, first);
+  if (!jv_tile<T, JV_REC>(g, w, eps, cb, cq, nullptr, z, y, 1, dot, p, decide)) {  // uniform
+    // posted after the sweep's code, so no store the sweep's loads must be
+    // ordered against precedes them
+    if (prog && blockIdx.x == 0 && threadIdx.x == 0) post_progress(prog, stop_iters, 1, stop_status);
+    return;
+  }
   const double d = wave_sum(dot);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
@@ -157,15 +190,16 @@ __global__ __launch_bounds__(256) void k_residual_wave(
     const double* __restrict__ netdop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
     const TD* __restrict__ delta, double lam, double* __restrict__ F, double* __restrict__ invdiag,
     double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
-    uint8_t* __restrict__ cflag, float* __restrict__ invdiag32, double* __restrict__ part) {
+    uint8_t* __restrict__ cflag, unsigned int* __restrict__ cbits, float* __restrict__ invdiag32,
+    double* __restrict__ part) {
   __shared__ double sred[4];
-  int wx, wy, wz;
+  int wx, wy, wz, wid;
   bool active;
-  wave_coords(wm, wx, wy, wz, active);
+  wave_coords(wm, wx, wy, wz, active, wid);
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   double acc = 0.0;
   residual_tile<TD>(g, w, ch, eps, semi, netdop, mask, phi, delta, lam, F, invdiag, diag_out, cq, cq32, cflag,
-                    invdiag32, acc);
+                    active ? cbits + 64L * wid + (threadIdx.x & 63) : nullptr, invdiag32, acc);
   const double d = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
   __syncthreads();
@@ -641,7 +675,8 @@ template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_cg_update(long N, int k, T* __restrict__ x, T* __restrict__ r,
                                                           T* __restrict__ z, const T* __restrict__ p,
                                                           const T* __restrict__ y, const T* __restrict__ invdiag,
-                                                          PcgCtx* ctx, const double* __restrict__ part_py, int n_py,
+                                                          PcgCtx* ctx, CgProgress* prog,
+                                                          const double* __restrict__ part_py, int n_py,
                                                           double* __restrict__ part_rz) {
   if (ctx->done) return;
   __shared__ double sred[kVecThreads / 64];
@@ -662,6 +697,7 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update(long N, int k, T* __r
       ctx->pAp = pAp;
       ctx->done = 1;
       ctx->status = PCG_BREAKDOWN;
+      if (prog) post_progress(prog, ctx->iters, 1, PCG_BREAKDOWN);
     }
     return;
   }
@@ -767,38 +803,38 @@ void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* m
 void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
                           const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
                           const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
-                          double* diag_out, double* cq, float* cq32, uint8_t* cflag, float* invdiag32,
-                          double* partial, double* norm2) {
+                          double* diag_out, double* cq, float* cq32, uint8_t* cflag, unsigned int* cbits,
+                          float* invdiag32, double* partial, double* norm2) {
   if (delta32)
     QE_LAUNCH(k_residual_wave<float>, wm.nblocks, 256, s, g, wm, ch, eps, semi, netdop, mask, phi, delta32, lam, F,
-              invdiag, diag_out, cq, cq32, cflag, invdiag32, partial);
+              invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
   else
     QE_LAUNCH(k_residual_wave<double>, wm.nblocks, 256, s, g, wm, ch, eps, semi, netdop, mask, phi, delta64, lam, F,
-              invdiag, diag_out, cq, cq32, cflag, invdiag32, partial);
+              invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
   QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, wm.nblocks, norm2);
 }
 
-void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const uint8_t* cflag,
+void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const unsigned int* cbits,
                       const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows) {
-  QE_LAUNCH(k_jv_wave<double>, wm.nblocks, 256, s, g, wm, eps, cflag, cq, mask, v, y, identity_rows);
+  QE_LAUNCH(k_jv_wave<double>, wm.nblocks, 256, s, g, wm, eps, cbits, cq, mask, v, y, identity_rows);
 }
 
-void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const uint8_t* cflag,
+void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const unsigned int* cbits,
                       const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows) {
-  QE_LAUNCH(k_jv_wave<float>, wm.nblocks, 256, s, g, wm, eps, cflag, cq, mask, v, y, identity_rows);
+  QE_LAUNCH(k_jv_wave<float>, wm.nblocks, 256, s, g, wm, eps, cbits, cq, mask, v, y, identity_rows);
 }
 
 void launch_cg_jv64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const double* eps_t,
-                    const uint8_t* cflag, const double* cq, const double* z, double* y, double* p, PcgCtx* ctx,
-                    const double* part_rz, double* part_py) {
-  QE_LAUNCH(k_cg_jv<double>, wm.nblocks, 256, s, g, wm, eps_t, cflag, cq, z, y, p, k, ctx, part_rz, cgblocks,
+                    const unsigned int* cbits, const double* cq, const double* z, double* y, double* p, PcgCtx* ctx,
+                    CgProgress* prog, const double* part_rz, double* part_py) {
+  QE_LAUNCH(k_cg_jv<double>, wm.nblocks, 256, s, g, wm, eps_t, cbits, cq, z, y, p, k, ctx, prog, part_rz, cgblocks,
             part_py);
 }
 
 void launch_cg_jv32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const float* eps_t,
-                    const uint8_t* cflag, const float* cq, const float* z, float* y, float* p, PcgCtx* ctx,
-                    const double* part_rz, double* part_py) {
-  QE_LAUNCH(k_cg_jv<float>, wm.nblocks, 256, s, g, wm, eps_t, cflag, cq, z, y, p, k, ctx, part_rz, cgblocks,
+                    const unsigned int* cbits, const float* cq, const float* z, float* y, float* p, PcgCtx* ctx,
+                    CgProgress* prog, const double* part_rz, double* part_py) {
+  QE_LAUNCH(k_cg_jv<float>, wm.nblocks, 256, s, g, wm, eps_t, cbits, cq, z, y, p, k, ctx, prog, part_rz, cgblocks,
             part_py);
 }
 
@@ -838,18 +874,20 @@ void launch_pcg_start32(hipStream_t s, int cgblocks, long N, double sign, const 
 }
 
 void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
-                       const double* eps_t, const uint8_t* cflag, const double* cq, const double* invdiag, double* x,
-                       double* r, double* z, double* p, double* y, PcgCtx* ctx, double* part_py, double* part_rz) {
-  launch_cg_jv64(s, g, wm, cgblocks, k, eps_t, cflag, cq, z, y, p, ctx, part_rz, part_py);
-  QE_LAUNCH(k_cg_update<double>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, part_py, wm.nblocks,
+                       const double* eps_t, const unsigned int* cbits, const double* cq, const double* invdiag, double* x,
+                       double* r, double* z, double* p, double* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
+                       double* part_rz) {
+  launch_cg_jv64(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, ctx, prog, part_rz, part_py);
+  QE_LAUNCH(k_cg_update<double>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, prog, part_py, wm.nblocks,
             part_rz);
 }
 
 void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
-                       const float* eps_t, const uint8_t* cflag, const float* cq, const float* invdiag, float* x,
-                       float* r, float* z, float* p, float* y, PcgCtx* ctx, double* part_py, double* part_rz) {
-  launch_cg_jv32(s, g, wm, cgblocks, k, eps_t, cflag, cq, z, y, p, ctx, part_rz, part_py);
-  QE_LAUNCH(k_cg_update<float>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, part_py, wm.nblocks,
+                       const float* eps_t, const unsigned int* cbits, const float* cq, const float* invdiag, float* x,
+                       float* r, float* z, float* p, float* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
+                       double* part_rz) {
+  launch_cg_jv32(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, ctx, prog, part_rz, part_py);
+  QE_LAUNCH(k_cg_update<float>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, prog, part_py, wm.nblocks,
             part_rz);
 }
 

@@ -31,13 +31,14 @@ TileMap make_tilemap(int nx, int ny, int nz, int kz);
 
 // Byte offsets of the workspace carve-out.
 struct Layout {
-  size_t F, x, r, p, y, z, invdiag, gvec, c, cflag, rdz, mask;
+  size_t F, x, r, p, y, z, invdiag, gvec, c, cflag, rdz, cbits, mask;
   size_t x32, r32, p32, y32, z32, invdiag32, c32, eps32, eps_t;
   size_t partial, partial2, ctx, scal, counters, flags;
   long n_partial;
   size_t total;
 };
-Layout make_layout(long N, long E, long nslots, long nz_elems, int nblocks_tile, int vblocks, int n_dir);
+Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int nblocks_tile, int vblocks,
+                   int n_dir);
 
 // One call's view of a problem, its workspace and its stream.
 struct Context {
@@ -45,11 +46,11 @@ struct Context {
   Geom g;
   TileMap tm;
   WaveMap wm;
-  bool use_graphs = true;                   // replay captured CG chunks
-  hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+  static constexpr int kEventRing = 8;
+  hipEvent_t events[kEventRing] = {};   // CG progress markers, created on first use
   ~Context() {
-    if (graph64) (void)hipGraphExecDestroy(graph64);
-    if (graph32) (void)hipGraphExecDestroy(graph32);
+    for (hipEvent_t e : events)
+      if (e) (void)hipEventDestroy(e);
   }
   long N = 0, E = 0, nslots = 0;
   int vblocks = 0;
@@ -60,6 +61,7 @@ struct Context {
   double* f64(size_t off) const { return reinterpret_cast<double*>(ws + off); }
   float* f32(size_t off) const { return reinterpret_cast<float*>(ws + off); }
   uint8_t* u8(size_t off) const { return reinterpret_cast<uint8_t*>(ws + off); }
+  unsigned int* u32(size_t off) const { return reinterpret_cast<unsigned int*>(ws + off); }
 
   qe_status init(const qe_problem* p, void* ws, size_t ws_bytes, void* stream, int kz = 0);
   qe_status validate(const double* phi);

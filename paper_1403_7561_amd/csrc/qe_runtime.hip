@@ -147,7 +147,8 @@ static int env_int(const char* name, int dflt) {
 static const int kCountBlocks = 256;
 static const int kContactBlocks = 256;
 
-Layout make_layout(long N, long E, long nslots, long nz_elems, int nblocks_tile, int vblocks, int n_dir) {
+Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int nblocks_tile, int vblocks,
+                   int n_dir) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -167,6 +168,7 @@ Layout make_layout(long N, long E, long nslots, long nz_elems, int nblocks_tile,
   L.eps_t = take(nslots * 8);
   L.cflag = take(nslots);      // tile-major: element has a nonzero c_q
   L.rdz = take(nz_elems * 8);  // inverse z spacings
+  L.cbits = take(nwaves * 64 * 4);  // per J.v lane: coefficient flags over its chunk
   L.mask = take(N);
   L.x32 = take(N * 4);
   L.r32 = take(N * 4);
@@ -222,15 +224,22 @@ struct HostMirror {
   PcgCtx* ctx = nullptr;
   double* scal = nullptr;
   int* flags = nullptr;
+  volatile CgProgress* prog = nullptr;   // host-coherent: written by the device while it runs
+  CgProgress* prog_dev = nullptr;        // the same memory as the device addresses it
   bool ok = false;
   HostMirror() {
     void* a = nullptr;
-    if (hipHostMalloc(&a, 4096, hipHostMallocDefault) == hipSuccess) {
-      ctx = reinterpret_cast<PcgCtx*>(a);
-      scal = reinterpret_cast<double*>(reinterpret_cast<char*>(a) + 1024);
-      flags = reinterpret_cast<int*>(reinterpret_cast<char*>(a) + 3072);
-      ok = true;
-    }
+    void* b = nullptr;
+    if (hipHostMalloc(&a, 4096, hipHostMallocDefault) != hipSuccess) return;
+    ctx = reinterpret_cast<PcgCtx*>(a);
+    scal = reinterpret_cast<double*>(reinterpret_cast<char*>(a) + 1024);
+    flags = reinterpret_cast<int*>(reinterpret_cast<char*>(a) + 3072);
+    if (hipHostMalloc(&b, 256, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) return;
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, b, 0) != hipSuccess) return;
+    prog = reinterpret_cast<volatile CgProgress*>(b);
+    prog_dev = reinterpret_cast<CgProgress*>(d);
+    ok = true;
   }
   // never freed: thread-exit destructors may run after the HIP runtime is gone
 };
@@ -253,11 +262,10 @@ qe_status Context::init(const qe_problem* p, void* ws_, size_t ws_bytes, void* s
   g.y = p->y;
   g.z = p->z;
   tm = make_tilemap(p->nx, p->ny, p->nz, kz);
-  use_graphs = env_int("QE_GRAPHS", 1) != 0;
   wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
   vblocks = vec_blocks(N);
   nslots = tile_slots(p->nx, p->ny, p->nz);
-  lay = make_layout(N, E, nslots, p->nz - 1, tm.nblocks, vblocks, p->n_dir);
+  lay = make_layout(N, E, nslots, p->nz - 1, wm.nwaves, tm.nblocks, vblocks, p->n_dir);
   if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (ws_bytes < lay.total)
@@ -318,7 +326,8 @@ qe_status Context::residual(const Charge& ch, const double* phi, const double* d
                             bool mixed, double* diag_out, double* norm2_host) {
   launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
                        f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
-                       u8(lay.cflag), mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial), f64(lay.scal));
+                       u8(lay.cflag), u32(lay.cbits), mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial),
+                       f64(lay.scal));
   QE_HIP(hipGetLastError());
   if (norm2_host) {
     QE_HIP(hipMemcpyAsync(mirror().scal, ws + lay.scal, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -333,7 +342,9 @@ qe_status Context::residual(const Charge& ch, const double* phi, const double* d
 qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, int maxit, int check_every,
                        int* pcg_status, int* iters) {
   PcgCtx* dctx = reinterpret_cast<PcgCtx*>(ws + lay.ctx);
-  PcgCtx& h = *mirror().ctx;
+  HostMirror& hm = mirror();
+  volatile CgProgress* hp = hm.prog;
+  hp->word = 0;  // the last decision of an earlier solve has been read: no write is pending
   const int cgb = cg_blocks(N);
   if (mixed)
     launch_pcg_start32(s, cgb, N, sign, b, u8(lay.mask), f32(lay.invdiag32), f32(lay.x32), f32(lay.r32),
@@ -342,48 +353,67 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
     launch_pcg_start64(s, cgb, N, sign, b, u8(lay.mask), f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.z),
                        dctx, f64(lay.partial2), rtol, maxit);
   QE_HIP(hipGetLastError());
-  int chunk = check_every > 0 ? check_every : 16;
-  chunk += chunk & 1;  // even: a replayed chunk starts on the same parity
-  auto enqueue_chunk = [&](hipStream_t st) {
-    for (int k = 0; k < chunk; ++k) {
-      if (mixed)
-        launch_pcg_iter32(st, g, wm, cgb, N, k & 1, f32(lay.eps32), u8(lay.cflag), f32(lay.c32), f32(lay.invdiag32),
-                          f32(lay.x32), f32(lay.r32), f32(lay.z32), f32(lay.p32), f32(lay.y32), dctx,
-                          f64(lay.partial), f64(lay.partial2));
-      else
-        launch_pcg_iter64(st, g, wm, cgb, N, k & 1, f64(lay.eps_t), u8(lay.cflag), f64(lay.c), f64(lay.invdiag),
-                          f64(lay.x), f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, f64(lay.partial),
-                          f64(lay.partial2));
-    }
+  auto queue_iter = [&](int k) {
+    if (mixed)
+      launch_pcg_iter32(s, g, wm, cgb, N, k & 1, f32(lay.eps32), u32(lay.cbits), f32(lay.c32), f32(lay.invdiag32),
+                        f32(lay.x32), f32(lay.r32), f32(lay.z32), f32(lay.p32), f32(lay.y32), dctx, hm.prog_dev,
+                        f64(lay.partial), f64(lay.partial2));
+    else
+      launch_pcg_iter64(s, g, wm, cgb, N, k & 1, f64(lay.eps_t), u32(lay.cbits), f64(lay.c), f64(lay.invdiag),
+                        f64(lay.x), f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, hm.prog_dev,
+                        f64(lay.partial), f64(lay.partial2));
   };
-  // one captured chunk per precision, replayed until CG stops
-  hipGraphExec_t& exec = mixed ? graph32 : graph64;
-  if (!exec && use_graphs && s) {
-    hipGraph_t gr = nullptr;
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-      enqueue_chunk(s);
-      if (hipStreamEndCapture(s, &gr) == hipSuccess && gr) {
-        if (hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
-        (void)hipGraphDestroy(gr);
+  // The host keeps `ahead` iterations queued beyond those it knows have
+  // finished (an event is recorded after every kEv-th iteration), so the
+  // device never waits for the host.  The first kernel posts to host-coherent
+  // memory only when it stops the solve (convergence, non-finite values, the
+  // iteration limit in iteration maxit; the second kernel on breakdown), once
+  // per solve; the queued iterations after that return at once.
+#ifndef QE_CG_EVENT_EVERY
+#define QE_CG_EVENT_EVERY 8
+#endif
+  constexpr int kEv = QE_CG_EVENT_EVERY, kRing = kEventRing;
+  hipEvent_t* ring = events;
+  for (int e = 0; e < kRing; ++e)
+    if (!ring[e]) QE_HIP(hipEventCreateWithFlags(&ring[e], hipEventDisableTiming));
+  const int ahead = std::min(std::max(check_every > 0 ? check_every : kEv + 4, kEv + 1), kEv * (kRing - 1));
+  int queued = 0, finished = 0, head = 0, tail = 0;  // events [head, tail) pending, in ring order
+  for (;;) {
+    while (queued <= maxit && queued < finished + ahead) {
+      queue_iter(queued++);
+      if (queued % kEv == 0 || queued > maxit) {
+        QE_HIP(hipEventRecord(ring[tail % kRing], s));
+        ++tail;
       }
     }
-    (void)hipGetLastError();
-  }
-  int launched = 0;
-  for (;;) {
+    QE_HIP(hipGetLastError());
+    const int wd = hp->word;
+    if (wd & 1) {
+      *pcg_status = (wd >> 1) & 7;
+      *iters = (wd >> 4) - 1;
+      return QE_OK;
+    }
+    if (head < tail) {
+      const hipError_t e = hipEventQuery(ring[head % kRing]);
+      if (e == hipSuccess) {
+        ++head;
+        finished = std::min(queued, head * kEv);
+      } else if (e != hipErrorNotReady) {
+        return fail(QE_ERR_HIP, "CG stream failed: %s", hipGetErrorString(e));
+      }
+      continue;
+    }
+    // everything queued has finished without a posted stop: read the
+    // scalars (a stop may also have been posted after the check above)
+    PcgCtx& h = *hm.ctx;
     QE_HIP(hipMemcpyAsync(&h, dctx, sizeof(PcgCtx), hipMemcpyDeviceToHost, s));
     QE_HIP(hipStreamSynchronize(s));
-    if (h.done || launched >= maxit) break;
-    if (exec)
-      QE_HIP(hipGraphLaunch(exec, s));
-    else
-      enqueue_chunk(s);
-    QE_HIP(hipGetLastError());
-    launched += chunk;
+    if (h.done || queued > maxit) {
+      *pcg_status = h.done ? h.status : PCG_MAXIT;
+      *iters = h.iters;
+      return QE_OK;
+    }
   }
-  *pcg_status = h.done ? h.status : PCG_MAXIT;
-  *iters = h.iters;
-  return QE_OK;
 }
 
 }  // namespace qe
@@ -412,7 +442,9 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
   const long E = (long)(p->nx - 1) * (p->ny - 1) * (p->nz - 1);
   // the tile map with the smallest chunk height has the most blocks
   TileMap tm = make_tilemap(p->nx, p->ny, p->nz, 1);
-  return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), p->nz - 1, tm.nblocks, vec_blocks(N), p->n_dir).total;
+  const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
+  return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), p->nz - 1, wm.nwaves, tm.nblocks, vec_blocks(N),
+                     p->n_dir).total;
 }
 
 const char* qe_last_error(void) { return g_last_error.c_str(); }
@@ -559,7 +591,7 @@ qe_status qe_jv(const qe_problem* p, const qe_physics* ph, const double* phi, co
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, false, nullptr, nullptr));
-  launch_jv_wave64(cx.s, cx.g, cx.wm, cx.f64(cx.lay.eps_t), cx.u8(cx.lay.cflag), cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v,
+  launch_jv_wave64(cx.s, cx.g, cx.wm, cx.f64(cx.lay.eps_t), cx.u32(cx.lay.cbits), cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v,
                    y, 1);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
@@ -578,7 +610,7 @@ qe_status qe_jv_f32(const qe_problem* p, const qe_physics* ph, const double* phi
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, true, nullptr, nullptr));
   launch_stage_eps32(cx.s, cx.vblocks, cx.g, p->eps_r, cx.f32(cx.lay.eps32), cx.nslots);
-  launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), cx.u8(cx.lay.cflag), cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v,
+  launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), cx.u32(cx.lay.cbits), cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v,
                    y, 1);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
@@ -631,13 +663,13 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
   QE_HIP(hipEventCreate(&e1));
   auto once = [&]() {
     if (mixed)
-      launch_cg_jv32(cx.s, cx.g, cx.wm, cgb, 0, cx.f32(cx.lay.eps32), cx.u8(cx.lay.cflag), cx.f32(cx.lay.c32),
-                     cx.f32(cx.lay.z32), cx.f32(cx.lay.y32), cx.f32(cx.lay.p32), dctx, cx.f64(cx.lay.partial2),
-                     cx.f64(cx.lay.partial));
+      launch_cg_jv32(cx.s, cx.g, cx.wm, cgb, 0, cx.f32(cx.lay.eps32), cx.u32(cx.lay.cbits), cx.f32(cx.lay.c32),
+                     cx.f32(cx.lay.z32), cx.f32(cx.lay.y32), cx.f32(cx.lay.p32), dctx, mirror().prog_dev,
+                     cx.f64(cx.lay.partial2), cx.f64(cx.lay.partial));
     else
-      launch_cg_jv64(cx.s, cx.g, cx.wm, cgb, 0, cx.f64(cx.lay.eps_t), cx.u8(cx.lay.cflag), cx.f64(cx.lay.c),
-                     cx.f64(cx.lay.z), cx.f64(cx.lay.y), cx.f64(cx.lay.p), dctx, cx.f64(cx.lay.partial2),
-                     cx.f64(cx.lay.partial));
+      launch_cg_jv64(cx.s, cx.g, cx.wm, cgb, 0, cx.f64(cx.lay.eps_t), cx.u32(cx.lay.cbits), cx.f64(cx.lay.c),
+                     cx.f64(cx.lay.z), cx.f64(cx.lay.y), cx.f64(cx.lay.p), dctx, mirror().prog_dev,
+                     cx.f64(cx.lay.partial2), cx.f64(cx.lay.partial));
   };
   once();  // warm-up
   hipError_t e = hipEventRecord(e0, cx.s);

@@ -74,8 +74,7 @@ struct WaveTile {
   bool col_ok, own_el, node_ok;
   long n00, ecol, elayer, sxy;
   long slot0, slot_layer;   // tile-major slot of this lane's element at layer 0, stride per layer
-  double hx, hy;
-  double ahx, ahy, axy;     // hy/hx, hx/hy, hx*hy: the element's stiffness weights are eps*(ahx hz, ahy hz, axy/hz)
+  double x0, x1, y0, y1;    // element corners: loaded here, first used once the sweep's first loads are issued
 
   __device__ __forceinline__ WaveTile(const Geom& g, int wx, int wy, int wz, int kz, int lane_, bool active) {
     lane = lane_;
@@ -98,31 +97,39 @@ struct WaveTile {
     const int tgx = (g.nx + 6) / 7, tgy = (g.ny + 6) / 7;
     slot_layer = (long)tgx * tgy * 49;
     slot0 = col_ok ? tile_slot(ex, ey, 0, tgx, tgy) : 0;
-    hx = hy = 1.0;
+    x0 = y0 = 0.0;
+    x1 = y1 = 1.0;
     if (col_ok) {
-      hx = g.x[ex + 1] - g.x[ex];
-      hy = g.y[ey + 1] - g.y[ey];
+      x0 = g.x[ex];
+      x1 = g.x[ex + 1];
+      y0 = g.y[ey];
+      y1 = g.y[ey + 1];
     }
+  }
+  // the element's stiffness weights are eps * (ahx hz, ahy hz, axy / hz)
+  __device__ __forceinline__ void weights(double& ahx, double& ahy, double& axy) const {
+    const double hx = x1 - x0, hy = y1 - y0;
     ahx = hy / hx;
     ahy = hx / hy;
     axy = hx * hy;
   }
   __device__ __forceinline__ long slot(int L) const { return slot0 + slot_layer * L; }
   __device__ __forceinline__ long node(const Geom& g, int L) const { return (long)gi + (long)g.nx * gj + sxy * L; }
-  // semiconductor flags of this column over the chunk, bit (L - Lbeg)
+  // semiconductor flags of this column over the chunk, bit (L - Lbeg); the
+  // byte loads are issued in groups of eight before any is waited for
   __device__ __forceinline__ unsigned int semi_bits(const Geom& g, const uint8_t* __restrict__ semi) const {
     unsigned int b = 0;
-    if (col_ok)
-      for (int L = max(Lbeg, 0); L <= min(Lend, g.nz - 2); ++L)
-        if (semi[ecol + elayer * L]) b |= 1u << (L - Lbeg);
-    return b;
-  }
-  // the same for a tile-major per-element flag array (one byte per slot)
-  __device__ __forceinline__ unsigned int slot_bits(const Geom& g, const uint8_t* __restrict__ flag) const {
-    unsigned int b = 0;
-    if (col_ok)
-      for (int L = max(Lbeg, 0); L <= min(Lend, g.nz - 2); ++L)
-        if (flag[slot(L)]) b |= 1u << (L - Lbeg);
+    if (col_ok) {
+      const int lo = max(Lbeg, 0), hi = min(Lend, g.nz - 2);
+      for (int L0 = lo; L0 <= hi; L0 += 8) {
+        uint8_t f[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) f[j] = (L0 + j <= hi) ? semi[ecol + elayer * (L0 + j)] : 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (f[j]) b |= 1u << (L0 + j - Lbeg);
+      }
+    }
     return b;
   }
 };
@@ -144,14 +151,32 @@ struct WaveTile {
 // never reaches z, p or x.
 enum JvMode { JV_PLAIN = 0, JV_DOT = 1, JV_REC = 2 };
 
-template <typename T, int kMode>
-__device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const T* __restrict__ eps_t,
-                                        const uint8_t* __restrict__ cflag, const T* __restrict__ cq,
+// What a CG-mode sweep learns once its first loads are in flight: whether to
+// go on (the solve has not stopped), and beta / first for JV_REC.
+template <typename T>
+struct JvGo {
+  bool go;
+  T beta;
+  bool first;
+};
+
+template <typename T>
+struct JvAlways {
+  __device__ __forceinline__ JvGo<T> operator()() const { return {true, T(0), true}; }
+};
+
+// cbits: this lane's coefficient flags over the chunk (bit L - Lbeg), as
+// written by residual_tile for the same wave tile.  pre() is called by every
+// wave once the first layer's loads are issued (it may synchronise the block).
+// Returns pre().go (false: nothing was stored).
+template <typename T, int kMode, typename Pre = JvAlways<T>>
+__device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const T* __restrict__ eps_t,
+                                        unsigned int cbits, const T* __restrict__ cq,
                                         const uint8_t* __restrict__ mask, const T* __restrict__ v,
                                         T* __restrict__ y, int identity_rows, double& dot,
-                                        T* __restrict__ p = nullptr, T beta = T(0), bool first = true) {
+                                        T* __restrict__ p = nullptr, Pre pre = Pre()) {
   constexpr bool kPlain = kMode == JV_PLAIN, kRec = kMode == JV_REC;
-  const unsigned int sbits = w.slot_bits(g, cflag);
+  const unsigned int sbits = cbits;
   auto face = [&](int P, T f[4]) {
     const long b = w.n00 + w.sxy * P;
     const long o[4] = {0, 1, g.nx, g.nx + 1};
@@ -166,7 +191,6 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
   // only in the next iteration, and no load is issued after those prefetches
   // inside an iteration: a wait for any later load would drain them (loads
   // retire in order).
-  const bool rec_old = kRec && !first;
   const bool z_own = kRec && !w.col_ok && w.node_ok;   // owned node outside every element face loaded
   T fb[4], ft[4], fn[4];
   T cc[8], cn[8], ee = T(0), en = T(0);
@@ -184,6 +208,24 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
     if (sbits & 1u) load8(cq + 8 * sl, cc);
   }
   if (kPlain && w.node_ok && w.Lbeg >= 0) mk = mask[w.node(g, w.Lbeg)];
+  // the chunk's z spacings: lane j holds layer Lbeg + j, read per layer with
+  // readlane (scalar, no memory access in the sweep)
+  double zlo = 0.0, zhi = 1.0, rdzl = 1.0;
+  {
+    const int L = w.Lbeg + w.lane;
+    if (L >= 0 && L <= min(w.Lend, g.nz - 2)) {
+      zlo = g.z[L];
+      zhi = g.z[L + 1];
+      rdzl = g.rdz[L];
+    }
+  }
+  const JvGo<T> go = pre();
+  if (!go.go) return false;
+  double ahx, ahy, axy;
+  w.weights(ahx, ahy, axy);
+  const double hzl = zhi - zlo;
+  const T beta = go.beta;
+  const bool rec_old = kRec && !go.first;
   T carry = T(0);
   // Retire the loads above before the loop.  Otherwise the first iteration's
   // operands are still in flight on entry, and the wait inserted for them
@@ -201,8 +243,8 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
   for (int L = w.Lbeg; L <= w.Lend; ++L) {
     const bool layer_ok = (L >= 0 && L <= g.nz - 2);
     const int L1 = L + 1;
-    const double hz = layer_ok ? g.z[L + 1] - g.z[L] : 1.0;
-    const double rhz = layer_ok ? g.rdz[L] : 1.0;
+    const double hz = lane_value(hzl, L - w.Lbeg);    // 1 outside [0, nz-2]
+    const double rhz = lane_value(rdzl, L - w.Lbeg);
     // the recurrence mode's y, p (and z) at this layer's owned node, issued
     // before the prefetches so that their wait does not drain them
     if (kRec && w.node_ok && L >= w.k0) {
@@ -223,7 +265,7 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
     if (kPlain && w.node_ok && L1 <= w.Lend) mkn = mask[w.node(g, L1)];
     T out[8];
     if (w.col_ok && layer_ok) {
-      const T sx = ee * T(w.ahx * hz), sy = ee * T(w.ahy * hz), sz = ee * T(w.axy * rhz);
+      const T sx = ee * T(ahx * hz), sy = ee * T(ahy * hz), sz = ee * T(axy * rhz);
       const T ve[8] = {fb[0], fb[1], fb[2], fb[3], ft[0], ft[1], ft[2], ft[3]};
       const double d =
           jv_element<T, kMode == JV_DOT>(ve, sx, sy, sz, cc, ((sbits >> (L - w.Lbeg)) & 1u) != 0, out);
@@ -261,6 +303,7 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
     ee = en;
     mk = mkn;
   }
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -279,8 +322,11 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
                                               double lam, double* __restrict__ F, double* __restrict__ invdiag,
                                               double* __restrict__ diag_out, double* __restrict__ cq,
                                               float* __restrict__ cq32, uint8_t* __restrict__ cflag,
-                                              float* __restrict__ invdiag32, double& norm2) {
+                                              unsigned int* __restrict__ cbits, float* __restrict__ invdiag32,
+                                              double& norm2) {
   const unsigned int sbits = w.semi_bits(g, semi);
+  double ahx, ahy, axy;
+  w.weights(ahx, ahy, axy);
   auto face = [&](int P, double f[4]) {
     const long b = w.n00 + w.sxy * P;
     const long o[4] = {0, 1, g.nx, g.nx + 1};
@@ -296,6 +342,7 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
   for (int k = 0; k < 4; ++k) fb[k] = ft[k] = 0.0;
   if (w.col_ok && w.Lbeg >= 0) face(w.Lbeg, fb);
   double carryF = 0.0, carryD = 0.0;
+  unsigned int cb = 0;
   for (int L = w.Lbeg; L <= w.Lend; ++L) {
     const bool layer_ok = (L >= 0 && L <= g.nz - 2);
     if (w.col_ok && L + 1 <= g.nz - 1) face(L + 1, ft);
@@ -304,7 +351,7 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
       const long el = w.ecol + w.elayer * L;
       const double hz = g.z[L + 1] - g.z[L];
       const double ee = eps[el];
-      const double sx = ee * (w.ahx * hz), sy = ee * (w.ahy * hz), sz = ee * (w.axy * g.rdz[L]);
+      const double sx = ee * (ahx * hz), sy = ee * (ahy * hz), sz = ee * (axy * g.rdz[L]);
       const double ve[8] = {fb[0], fb[1], fb[2], fb[3], ft[0], ft[1], ft[2], ft[3]};
       double zero[8];
 #pragma unroll
@@ -314,9 +361,9 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
 #pragma unroll
       for (int k = 0; k < 8; ++k) outD[k] = dg;
       const bool own = w.own_el && L >= w.k0;
-      bool nzc = false;
+      bool nzc = false;  // some c_q of this element is nonzero
       if ((sbits >> (L - w.Lbeg)) & 1u) {
-        const double kw = ch.kappa * w.hx * w.hy * hz * 0.125;
+        const double kw = ch.kappa * axy * hz * 0.125;
         const double nd = netdop ? netdop[el] : 0.0;
         double src[8], cc[8];
 #pragma unroll
@@ -344,6 +391,7 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
         }
       }
       if (own) cflag[w.slot(L)] = nzc ? 1 : 0;
+      if (nzc) cb |= 1u << (L - w.Lbeg);
     } else {
 #pragma unroll
       for (int k = 0; k < 8; ++k) outF[k] = outD[k] = 0.0;
@@ -371,6 +419,7 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
 #pragma unroll
     for (int k = 0; k < 4; ++k) fb[k] = ft[k];
   }
+  if (cbits) *cbits = cb;
 }
 
 }  // namespace qe
