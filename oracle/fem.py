@@ -104,6 +104,11 @@ class Problem:
         self.eps = np.asarray(dev.eps_r, dtype=np.float64)
         self.semi = np.asarray(dev.semi).astype(np.float64)
         self.netdop = np.asarray(dev.net_doping, dtype=np.float64)
+        # separate donor / acceptor densities (needed for incomplete ionization)
+        nd = getattr(dev, "donors", None)
+        na = getattr(dev, "acceptors", None)
+        self.nd = None if nd is None else np.asarray(nd, dtype=np.float64)
+        self.na = None if na is None else np.asarray(na, dtype=np.float64)
         self.dir_id = np.asarray(dev.dir_id, dtype=np.int64)
         self.dir_val = np.asarray(dev.dir_val, dtype=np.float64)
         if self.eps.shape != (m.E,) or self.semi.shape != (m.E,) or self.netdop.shape != (m.E,):
@@ -111,6 +116,8 @@ class Problem:
         if self.dir_id.shape != (m.N,):
             raise ValueError("dir_id must have one entry per node")
         self.stats = stats
+        if stats.ionization == "incomplete" and (self.nd is None or self.na is None):
+            raise ValueError("incomplete ionization needs donors and acceptors per element")
         self.dirichlet = self.dir_id >= 0
         self.free = ~self.dirichlet
         self.extra_load = extra_load
@@ -124,11 +131,15 @@ class Problem:
         return out
 
     def charge_load(self, phi, stats=None):
-        """b_i = KAPPA sum_e semi_e sum_q W_q (N_net - n(phi_q)) w_i(q)."""
+        """b_i = KAPPA sum_e semi_e sum_q W_q rho(phi_q) w_i(q) with the space
+        charge rho = p - n + N_D+ - N_A- (= N_net - n without holes and with
+        complete ionization)."""
         m = self.mesh
         st = self.stats if stats is None else stats
         phq = m.at_gauss(phi)
-        rho = self.netdop[:, None] - st.density(phq)
+        nd = None if self.nd is None else self.nd[:, None]
+        na = None if self.na is None else self.na[:, None]
+        rho = st.rho(phq, self.netdop[:, None], nd, na)
         qv = KAPPA * (self.semi * m.W)[:, None] * rho          # [E, q]
         b = m.scatter(qv @ INTERP)                               # project: sum_q qv_q w_a(q)
         if self.extra_load is not None:
@@ -146,9 +157,12 @@ class Problem:
         return F
 
     def coeff(self, phi):
-        """c_{e,q} = KAPPA semi_e W_q n'(phi_q): the linearised charge weights."""
+        """c_{e,q} = -KAPPA semi_e W_q rho'(phi_q) (= KAPPA semi_e W_q n'(phi_q)
+        for electrons alone): the linearised charge weights, >= 0."""
         m = self.mesh
-        return KAPPA * (self.semi * m.W)[:, None] * self.stats.ddensity(m.at_gauss(phi))
+        nd = None if self.nd is None else self.nd[:, None]
+        na = None if self.na is None else self.na[:, None]
+        return -KAPPA * (self.semi * m.W)[:, None] * self.stats.drho(m.at_gauss(phi), nd, na)
 
     def jacobian_full(self, phi):
         """dF/dphi on all nodes: eps K + sum_q c_q w(q) w(q)^T (N x N CSR)."""

@@ -103,7 +103,8 @@ def newton(prob, phi0=None, atol=1e-10, maxit=200, ls_max=30, method="auto",
 
 def make_problem(dev, extra_load=None):
     """Problem from a device description (see synth.devices.Device)."""
-    st = Statistics(dev.stat, dev.T_K, dev.m_eff, dev.Ec0_eV)
+    st = Statistics(dev.stat, dev.T_K, dev.m_eff, dev.Ec0_eV, holes=getattr(dev, "holes", False),
+                    ionization=getattr(dev, "ionization", "complete"))
     return Problem(dev, st, extra_load=extra_load)
 
 

@@ -5,6 +5,7 @@ contact voltages.  It holds none of the solver's arithmetic (no charge
 statistics, no discretisation, no physical constants).
 """
 from .devices import (  # noqa: F401
+    doped_block,
     Device,
     stack_z,
     make_stack_device,

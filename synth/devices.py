@@ -46,11 +46,16 @@ class Device:
     dir_id: np.ndarray         # [N] int32
     dir_val: np.ndarray        # [G] float64, V
     contacts: list = field(default_factory=list)
-    stat: str = "fd"           # "linear" | "tf" | "fd"
+    stat: str = "fd"           # "linear" | "tf" | "fd" | "mb"
     T_K: float = 4.0
     m_eff: float = 1.08
     Ec0_eV: float = 0.56
     boxes: dict = field(default_factory=dict)
+    # the full space charge of Eq. Poisson: holes and dopant ionization
+    holes: bool = False
+    ionization: str = "complete"   # "complete" | "incomplete"
+    donors: np.ndarray = None      # [E] float64, nm^-3 (incomplete ionization)
+    acceptors: np.ndarray = None   # [E] float64, nm^-3
 
     @property
     def nx(self):
@@ -264,3 +269,33 @@ def config5(nx=257, ny=257, nz=129):
     return make_stack_device("c5", _uniform_xy(nx), _uniform_xy(ny), stack_z(nz - 1),
                              gates, volts, stat="fd", T_K=4.0, interface=interface,
                              boxes={"D1": DOT_BOX_D1, "D2": DOT_BOX_D2})
+
+
+def doped_block(name, nx, ny, nz, size_nm, donors_fn, acceptors_fn, contacts, stat="mb", T_K=300.0,
+                holes=True, ionization="complete"):
+    """A silicon block with position-dependent doping and Ohmic contacts.
+
+    size_nm: (Lx, Ly, Lz); donors_fn / acceptors_fn: callables of the element
+    centroid (x, y, z) returning nm^-3; contacts: list of (name, face) with
+    face one of "bottom", "top" -- every node of that face gets the contact's
+    Dirichlet value, which the caller fills into ``dir_val`` (zeros here)."""
+    Lx, Ly, Lz = size_nm
+    x = np.linspace(0.0, Lx, nx)
+    y = np.linspace(0.0, Ly, ny)
+    z = np.linspace(0.0, Lz, nz)
+    xc = 0.5 * (x[1:] + x[:-1])
+    yc = 0.5 * (y[1:] + y[:-1])
+    zc = 0.5 * (z[1:] + z[:-1])
+    ZC, YC, XC = np.meshgrid(zc, yc, xc, indexing="ij")
+    nd = np.asarray(donors_fn(XC, YC, ZC), dtype=np.float64).ravel() * np.ones(XC.size)
+    na = np.asarray(acceptors_fn(XC, YC, ZC), dtype=np.float64).ravel() * np.ones(XC.size)
+    E = XC.size
+    dir_id = np.full(nx * ny * nz, -1, dtype=np.int32)
+    names = []
+    for c, (cname, face) in enumerate(contacts):
+        k = 0 if face == "bottom" else nz - 1
+        dir_id[k * nx * ny:(k + 1) * nx * ny] = c
+        names.append(cname)
+    return Device(name=name, x=x, y=y, z=z, eps_r=np.full(E, EPS_SI), semi=np.ones(E, dtype=np.uint8),
+                  net_doping=nd - na, dir_id=dir_id, dir_val=np.zeros(len(contacts)), contacts=names,
+                  stat=stat, T_K=T_K, holes=holes, ionization=ionization, donors=nd, acceptors=na)
