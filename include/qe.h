@@ -4,15 +4,19 @@
  * The library solves the discrete Galerkin form (Eq. PoissonWeakForm, Sec.
  * II.A) of
  *
- *     -div(eps_r grad phi) = KAPPA * (N_D - N_A - n(phi)),   KAPPA = q/eps0
+ *     -div(eps_r grad phi) = KAPPA * (p - n + N_D+ - N_A-),   KAPPA = q/eps0
  *
- * on a rectilinear Q1 hexahedral mesh of a Si/SiO2 gate stack.  Electrons
- * follow Thomas-Fermi (T = 0) or Fermi-Dirac statistics with the Bednarczyk
- * F_1/2 form (Eqs. FDstatistics, EffectiveDOS, FDIntApprox, with exp(x) below
- * x = -50); holes are absent and dopants fully ionised.  Gate electrodes and
- * the substrate contact are Dirichlet nodes (Eq. ContOnIns with a mid-gap
- * work function, so a gate node carries its applied voltage); every other
- * outer face is the default zero-flux Neumann boundary (Sec. II.A.5).
+ * (Eq. Poisson) on a rectilinear Q1 hexahedral mesh of a Si/SiO2 gate stack.
+ * Carriers follow Thomas-Fermi (T = 0), Maxwell-Boltzmann (Eq. MBstatistics)
+ * or Fermi-Dirac statistics with the Bednarczyk F_1/2 form (Eqs.
+ * FDstatistics, EffectiveDOS, FDIntApprox, with exp(x) below x = -50).  By
+ * default holes are absent and dopants fully ionised (p = 0, N_D+ - N_A- =
+ * net_doping); qe_physics switches on holes and incomplete ionization
+ * (Eqs. Ionization, FinalIonization).  Gate electrodes and contacts are
+ * Dirichlet nodes (Eq. ContOnIns with a mid-gap work function, so a gate node
+ * carries its applied voltage; Ohmic contacts take qe_ohmic_potential);
+ * every other outer face is the default zero-flux Neumann boundary (Sec.
+ * II.A.5).
  * Newton's method with the exact Jacobian (Sec. II.A.4, II.C) is globalised
  * by backtracking; the linear systems are solved by Jacobi-preconditioned
  * conjugate gradients, all on the GPU.
@@ -22,7 +26,9 @@
  *
  * Layout: node (i, j, k) is i + nx*(j + ny*k) (x fastest); element (i, j, k),
  * whose lowest corner is node (i, j, k), is i + (nx-1)*(j + (ny-1)*k).
- * E_F = 0 (grounded substrate, Sec. II.A.2), and E_F - E_C = phi - Ec0.
+ * E_F = 0 (grounded substrate, Sec. II.A.2), E_F - E_C = phi - Ec0 and, with
+ * holes, E_V - E_F = Ec0 - Eg - phi (Eq. EcEv_phi with the constant offset
+ * folded into Ec0).
  *
  * Conventions shared by every entry point:
  *  - Every array pointer in qe_problem and every "device" argument is DEVICE
@@ -66,8 +72,14 @@ typedef enum {
 typedef enum {
   QE_STAT_LINEAR = 0,            /* no mobile charge (doping only) */
   QE_STAT_TF = 1,                /* Thomas-Fermi: n = C_TF max(0, phi-Ec0)^(3/2) */
-  QE_STAT_FD12 = 2               /* n = N_C F_1/2((phi-Ec0)/kT), Eq. FDIntApprox */
+  QE_STAT_FD12 = 2,              /* n = N_C F_1/2((phi-Ec0)/kT), Eq. FDIntApprox */
+  QE_STAT_MB = 3                 /* n = N_C exp((phi-Ec0)/kT), Eq. MBstatistics */
 } qe_statistics;
+
+typedef enum {
+  QE_ION_COMPLETE = 0,           /* N_D+ - N_A- = net_doping */
+  QE_ION_INCOMPLETE = 1          /* Eq. FinalIonization from donors / acceptors */
+} qe_ionization;
 
 typedef enum {
   QE_PREC_FP64 = 0,              /* everything in FP64 */
@@ -84,18 +96,32 @@ typedef struct {
   const double* eps_r;           /* [E] relative permittivity, finite, > 0 */
   const uint8_t* semi;           /* [E] 1 = semiconductor (carries electrons and
                                     doping), 0 = insulator */
-  const double* net_doping;      /* [E] N_D - N_A in nm^-3; NULL means 0 */
+  const double* net_doping;      /* [E] N_D - N_A in nm^-3 (complete ionization);
+                                    NULL means donors - acceptors when those are
+                                    given, else 0 */
   const int32_t* dir_id;         /* [N] -1 = free node, else index < n_dir */
   const double* dir_val;         /* [n_dir] Dirichlet potential in V */
   int32_t n_dir;                 /* >= 0; a problem with no Dirichlet node needs
                                     n'(phi) > 0 somewhere to be solvable */
+  const double* donors;          /* [E] N_D in nm^-3, finite, >= 0, or NULL; required
+                                    with QE_ION_INCOMPLETE */
+  const double* acceptors;       /* [E] N_A in nm^-3, likewise; NULL exactly when
+                                    donors is NULL */
 } qe_problem;
 
 typedef struct {
-  int32_t stat;                  /* qe_statistics */
-  double T_K;                    /* > 0 for QE_STAT_FD12, ignored otherwise */
-  double m_eff;                  /* DOS effective mass / m0 (Eq. EffectiveMass), > 0 */
+  int32_t stat;                  /* qe_statistics (electrons and holes) */
+  double T_K;                    /* > 0 for QE_STAT_FD12 / QE_STAT_MB and for
+                                    incomplete ionization, ignored otherwise */
+  double m_eff;                  /* conduction DOS mass / m0 (Eq. EffectiveMass), > 0 */
   double Ec0_eV;                 /* E_C - E_F at phi = 0 */
+  int32_t holes;                 /* 1: p(phi) from the same statistics (Eq. Poisson) */
+  double m_h;                    /* valence DOS mass / m0 (Eq. EffectiveMass), > 0 with holes */
+  double Eg_eV;                  /* band gap, E_V = E_C - Eg (Eq. EcEv_phi), >= 0 */
+  int32_t ionization;            /* qe_ionization; incomplete needs T > 0 and
+                                    QE_STAT_FD12 or QE_STAT_MB */
+  double Ed_eV, Ea_eV;           /* donor / acceptor ionization energies (Sec. II.A.3) */
+  double gD, gA;                 /* ground-state degeneracy factors, > 0 (2 and 4 for Si) */
 } qe_physics;
 
 typedef struct {
@@ -108,7 +134,8 @@ typedef struct {
   int32_t init_guess;            /* 0: linear (charge-free) Poisson solve;
                                     1: start from the phi passed in */
   int32_t check_every;           /* CG iterations the host keeps queued beyond
-                                    those known to have finished (0 = 4) */
+                                    those known to have finished (0 = 12;
+                                    clamped to [9, 56]) */
 } qe_options;
 
 typedef struct {
@@ -215,6 +242,23 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
 qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* phi, const double* v,
                      int32_t precision, int32_t reps, double* ms_per_apply, int64_t* n_coef_elems,
                      void* ws, size_t ws_bytes, void* stream);
+
+/* Dirichlet value of an Ohmic contact on semiconductor (Sec. II.A.5, second
+ * case): thermal equilibrium and charge neutrality of the majority carriers
+ * at the contact, in this library's convention (E_F = 0, E_C = Ec0 - phi).
+ * n-type when N_D >= N_A, else p-type (densities in nm^-3, host scalars).
+ *  - complete ionization, QE_STAT_MB: Eq. PotBC4MBCompIon with the net
+ *    doping |N_D - N_A| as the majority density;
+ *  - complete ionization, QE_STAT_FD12: Eq. PotBC4FDCompIon with eta from the
+ *    Nilsson inverse (Eq. FDintInverse), likewise;
+ *  - incomplete ionization (MB or FD, as the paper does for FD): Eqs.
+ *    Yval4MBIncompIon and PotBC4MBIncompIon with the majority dopant alone,
+ *    ln y from Eq. ApproxLogTerms once exp(E_d/kT) terms exceed 1e300; the
+ *    p-type form carries +E_a, which the definitions of y_p and E_a give.
+ * V_a: applied voltage (V), added as printed.  phi: host, out.
+ * Errors: QE_ERR_INVALID_ARG for TF or linear statistics, T <= 0, a zero or
+ * negative majority density, or NULL pointers. */
+qe_status qe_ohmic_potential(const qe_physics* ph, double N_D, double N_A, double V_a, double* phi);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* qe_last_error(void);

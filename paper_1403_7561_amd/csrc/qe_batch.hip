@@ -36,7 +36,7 @@ struct BatchInst {
   Geom g;
   const double* eps;
   const uint8_t* semi;
-  const double* netdop;
+  Doping dop;
   const int32_t* dir_id;
   const double* dir_val;
   double* phi;
@@ -111,7 +111,7 @@ __device__ double b_residual(const BatchInst& I, const Charge& ch, const double*
   double acc = 0.0;
   for (int t = threadIdx.x >> 6; t < I.ntiles; t += NT / 64) {
     const WaveTile w = tile_at(I, t);
-    residual_tile<double>(I.g, w, ch, I.eps, I.semi, I.netdop, I.mask, I.phi, delta, lam, I.F, I.invdiag, nullptr,
+    residual_tile<double>(I.g, w, ch, I.eps, I.semi, I.dop, I.mask, I.phi, delta, lam, I.F, I.invdiag, nullptr,
                           I.c, nullptr, I.cflag, I.cbits + 64L * t + (threadIdx.x & 63), nullptr, acc);
   }
   return bsum<NT>(acc, sred);
@@ -214,8 +214,7 @@ __device__ void b_solve(const BatchParams& bp, const BatchInst& I, BatchOut& o, 
   __syncthreads();
   int status = QE_OK, newton = 0, kry = 0, halv = 0, nres = 0, pst = 0;
   // charge-free linear initial guess
-  Charge lin = bp.ch;
-  lin.stat = STAT_LINEAR;
+  const Charge lin = linear_charge(bp.ch);
   double n2 = b_residual<NT>(I, lin, nullptr, 0.0, sred);
   if (n2 > 0.0 && isfinite(n2)) {
     const int its = b_pcg<NT>(I, I.F, -1.0, QE_INIT_RTOL, bp.krylov_maxit, &pst, sred);
@@ -476,6 +475,8 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
   for (int i = 0; i < n_inst; ++i) {
     if ((st = check_problem(&probs[i])) != QE_OK) return fail(st, "instance %d: %s", i, qe_last_error());
     if (!phi[i]) return fail(QE_ERR_INVALID_ARG, "phi[%d] is NULL", i);
+    if (ch.incomplete && !probs[i].donors)
+      return fail(QE_ERR_INVALID_ARG, "instance %d: incomplete ionization needs donors and acceptors", i);
   }
   const size_t need = batch_bytes(n_inst, probs);
   if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
@@ -526,7 +527,7 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
       I.g = Geom{p.nx, p.ny, p.nz, p.x, p.y, p.z};
       I.eps = p.eps_r;
       I.semi = p.semi;
-      I.netdop = p.net_doping;
+      I.dop = Doping{p.net_doping, p.donors, p.acceptors};
       I.dir_id = p.dir_id;
       I.dir_val = p.dir_val;
       I.phi = phi[i];
@@ -565,14 +566,15 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
     for (int i = 0; i < n_inst; ++i) {
       const qe_problem& p = probs[i];
       const long N = (long)p.nx * p.ny * p.nz, E = (long)(p.nx - 1) * (p.ny - 1) * (p.nz - 1);
-      launch_validate(s, vec_blocks(N), N, E, p.n_dir, p.eps_r, p.net_doping, p.dir_id, nullptr, dflags);
+      launch_validate(s, vec_blocks(N), N, E, p.n_dir, p.eps_r, Doping{p.net_doping, p.donors, p.acceptors},
+                      p.dir_id, nullptr, dflags);
     }
     int f = 0;
     if (hipMemcpyAsync(&f, dflags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return fail(QE_ERR_HIP, "validation failed to run");
     if (f & 1) return fail(QE_ERR_INVALID_ARG, "eps_r must be finite and > 0");
-    if (f & 2) return fail(QE_ERR_NONFINITE, "net_doping not finite");
+    if (f & 2) return fail(QE_ERR_NONFINITE, "net_doping not finite or donors / acceptors not finite and >= 0");
     if (f & 4) return fail(QE_ERR_INVALID_ARG, "dir_id outside [-1, n_dir)");
   }
   // largest instances first

@@ -31,7 +31,7 @@ constexpr int kVecThreads = 256;
 constexpr double kG1 = 0.78867513459481288225;   // (1 + 1/sqrt(3)) / 2
 constexpr double kG0 = 0.21132486540518711775;   // (1 - 1/sqrt(3)) / 2
 
-enum Stat : int { STAT_LINEAR = 0, STAT_TF = 1, STAT_FD = 2 };
+enum Stat : int { STAT_LINEAR = 0, STAT_TF = 1, STAT_FD = 2, STAT_MB = 3 };
 
 // Mesh geometry (device pointers to the caller's coordinate arrays).
 struct Geom {
@@ -50,7 +50,25 @@ struct Charge {
   double Nc;       // nm^-3
   double Ctf;      // nm^-3 eV^-3/2
   double kappa;    // q/eps0 in V nm
+  // the rest of the space charge of Eq. Poisson
+  int holes;       // p(phi) with E_V - E_F = Ec0 - Eg - phi
+  int incomplete;  // Eq. FinalIonization from per-element N_D, N_A
+  double Nv;       // valence effective DOS, nm^-3
+  double Ctf_h;    // valence Thomas-Fermi prefactor
+  double Eg;       // eV
+  double ed_kT, ea_kT;   // E_d / kT, E_a / kT
+  double ln_gD, ln_gA;   // ln of the degeneracy factors
 };
+
+// Charge of the linear initial-guess problem: no mobile charge, dopants fully
+// ionised (N_D - N_A from the species when no net doping is given).
+__host__ __device__ inline Charge linear_charge(const Charge& ch) {
+  Charge lin = ch;
+  lin.stat = STAT_LINEAR;
+  lin.holes = 0;
+  lin.incomplete = 0;
+  return lin;
+}
 
 // Tile decomposition of the node grid: gx*gy tiles of kTX x kTY node columns,
 // gz chunks of kz node planes.
@@ -260,22 +278,32 @@ __device__ __forceinline__ double jv_element(const T v[8], T sx, T sy, T sz, con
   return d;
 }
 
+// Per-element doping: the net N_D - N_A (complete ionization; NULL = 0, or
+// donors - acceptors when only those are given) or the two species.
+struct Doping {
+  const double* net;
+  const double* donors;
+  const double* acceptors;
+};
+
 // ---- charge statistics ----------------------------------------------------
-// n(phi) and dn/dphi.  Fermi-Dirac uses Bednarczyk's F_1/2 with its exact
-// derivative, and exp(eta) below eta = -50; Thomas-Fermi is its T -> 0 limit.
-__device__ __forceinline__ void electron_density(const Charge& ch, double phi, double& n, double& dn) {
-  const double u = phi - ch.Ec0;
+// Density of one band, N F(u/kT), and its derivative in u, where u is
+// E_F minus the band edge (V): Fermi-Dirac uses Bednarczyk's F_1/2 with its
+// exact derivative and exp(eta) below eta = -50; Boltzmann is exp; Thomas-
+// Fermi is the T -> 0 limit with prefactor C.
+__device__ __forceinline__ void band_density(const Charge& ch, double u, double N, double C, double& f,
+                                             double& df) {
   if (ch.stat == STAT_TF) {
     const double up = fmax(u, 0.0);
     const double s = sqrt(up);
-    n = ch.Ctf * up * s;
-    dn = 1.5 * ch.Ctf * s;
-  } else if (ch.stat == STAT_FD) {
+    f = C * up * s;
+    df = 1.5 * C * s;
+  } else if (ch.stat == STAT_FD || ch.stat == STAT_MB) {
     const double eta = u * ch.inv_kT;
-    if (eta < -50.0) {
+    if (ch.stat == STAT_MB || eta < -50.0) {
       const double e = exp(eta);
-      n = ch.Nc * e;
-      dn = ch.Nc * e * ch.inv_kT;
+      f = N * e;
+      df = N * e * ch.inv_kT;
     } else {
       const double a = 1.3293403881791355;          // 3 sqrt(pi) / 4
       const double xp1 = eta + 1.0;
@@ -287,12 +315,55 @@ __device__ __forceinline__ void electron_density(const Charge& ch, double phi, d
       const double vp = exp(-0.375 * log(v));          // v^(-3/8)
       const double F = 1.0 / (em + a * vp);
       const double Fp = (em + 0.375 * a * (vp / v) * dv) * F * F;
-      n = ch.Nc * F;
-      dn = ch.Nc * Fp * ch.inv_kT;
+      f = N * F;
+      df = N * Fp * ch.inv_kT;
     }
   } else {
-    n = 0.0;
-    dn = 0.0;
+    f = 0.0;
+    df = 0.0;
+  }
+}
+
+// n(phi) and dn/dphi (E_F - E_C = phi - Ec0).
+__device__ __forceinline__ void electron_density(const Charge& ch, double phi, double& n, double& dn) {
+  band_density(ch, phi - ch.Ec0, ch.Nc, ch.Ctf, n, dn);
+}
+
+// 1 / (1 + exp(A)) and its derivative in A, without overflow.
+__device__ __forceinline__ void fermi_factor(double A, double& f, double& df) {
+  if (A > 0.0) {
+    const double e = exp(-A);
+    f = e / (1.0 + e);
+  } else {
+    f = 1.0 / (1.0 + exp(A));
+  }
+  df = -f * (1.0 - f);
+}
+
+// Space charge rho = p - n + N_D+ - N_A- (nm^-3) and drho/dphi at one point:
+// net = N_D - N_A with complete ionization; nd, na per element otherwise.
+__device__ __forceinline__ void space_charge(const Charge& ch, double phi, double net, double nd, double na,
+                                             double& rho, double& drho) {
+  double n, dn;
+  electron_density(ch, phi, n, dn);
+  rho = -n;
+  drho = -dn;
+  if (ch.holes) {
+    double p, dp;
+    band_density(ch, ch.Ec0 - ch.Eg - phi, ch.Nv, ch.Ctf_h, p, dp);  // u = E_V - E_F
+    rho += p;
+    drho -= dp;
+  }
+  if (ch.incomplete) {
+    // N_D+ = N_D / (1 + g_D exp((E_F - E_D)/kT)), E_F - E_D = phi - Ec0 + E_d
+    double fd, dfd, fa, dfa;
+    fermi_factor((phi - ch.Ec0) * ch.inv_kT + ch.ed_kT + ch.ln_gD, fd, dfd);
+    // N_A- = N_A / (1 + g_A exp((E_A - E_F)/kT)), E_A - E_F = Ec0 - Eg - phi + E_a
+    fermi_factor((ch.Ec0 - ch.Eg - phi) * ch.inv_kT + ch.ea_kT + ch.ln_gA, fa, dfa);
+    rho += nd * fd - na * fa;
+    drho += (nd * dfd + na * dfa) * ch.inv_kT;
+  } else {
+    rho += net;
   }
 }
 

@@ -47,7 +47,7 @@ void launch_count(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, c
                   const uint8_t* semi, const double* phi, double* partial, unsigned int* counter, double* out);
 void launch_density(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, const uint8_t* semi,
                     const double* phi, double* nout);
-void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const double* netdop,
+void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const Doping& dop,
                      const int32_t* dir_id, const double* phi, int* flags);
 void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, const double* dir_val, uint8_t* mask,
                   double* phi, int apply, int zero_free);
@@ -58,7 +58,7 @@ void launch_masked_copy_d2d(hipStream_t s, int nblocks, long n, const uint8_t* m
 void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, float* b);
 WaveMap make_wavemap(int nx, int ny, int nz, int kz);
 void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
-                          const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
+                          const uint8_t* semi, const Doping& dop, const uint8_t* mask, const double* phi,
                           const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
                           double* diag_out, double* cq, float* cq32, uint8_t* cflag, unsigned int* cbits,
                           float* invdiag32, double* partial, double* norm2);

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_JV_MIN_W
 template <typename TD>
 __global__ __launch_bounds__(256) void k_residual_wave(
     Geom g, WaveMap wm, Charge ch, const double* __restrict__ eps, const uint8_t* __restrict__ semi,
-    const double* __restrict__ netdop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
+    const Doping dop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
     const TD* __restrict__ delta, double lam, double* __restrict__ F, double* __restrict__ invdiag,
     double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
     uint8_t* __restrict__ cflag, unsigned int* __restrict__ cbits, float* __restrict__ invdiag32,
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_residual_wave(
   wave_coords(wm, wx, wy, wz, active, wid);
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   double acc = 0.0;
-  residual_tile<TD>(g, w, ch, eps, semi, netdop, mask, phi, delta, lam, F, invdiag, diag_out, cq, cq32, cflag,
+  residual_tile<TD>(g, w, ch, eps, semi, dop, mask, phi, delta, lam, F, invdiag, diag_out, cq, cq32, cflag,
                     active ? cbits + 64L * wid + (threadIdx.x & 63) : nullptr, invdiag32, acc);
   const double d = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
@@ -466,16 +466,18 @@ __global__ __launch_bounds__(kVecThreads) void k_density(Geom g, Charge ch, cons
 
 // ---------------------------------------------------------------------------
 // Input validation.  Sets bits of *flags: 1 eps not finite/positive,
-// 2 net doping not finite, 4 dir_id out of range, 8 phi not finite.
+// 2 net doping not finite or a dopant density not finite and >= 0,
+// 4 dir_id out of range, 8 phi not finite.
 __global__ __launch_bounds__(kVecThreads) void k_validate(long N, long E, int n_dir, const double* __restrict__ eps,
-                                                         const double* __restrict__ netdop,
-                                                         const int32_t* __restrict__ dir_id,
+                                                         const Doping dop, const int32_t* __restrict__ dir_id,
                                                          const double* __restrict__ phi, int* flags) {
   int f = 0;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (long)gridDim.x * blockDim.x) {
     const double v = eps[e];
     if (!(v > 0.0) || !isfinite(v)) f |= 1;
-    if (netdop && !isfinite(netdop[e])) f |= 2;
+    if (dop.net && !isfinite(dop.net[e])) f |= 2;
+    if (dop.donors && !(dop.donors[e] >= 0.0 && isfinite(dop.donors[e]))) f |= 2;
+    if (dop.acceptors && !(dop.acceptors[e] >= 0.0 && isfinite(dop.acceptors[e]))) f |= 2;
   }
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
     const int d = dir_id[n];
@@ -774,9 +776,9 @@ void launch_density(hipStream_t s, int nblocks, const Geom& g, const Charge& ch,
   QE_LAUNCH(k_density, nblocks, kVecThreads, s, g, ch, semi, phi, nout);
 }
 
-void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const double* netdop,
+void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const Doping& dop,
                      const int32_t* dir_id, const double* phi, int* flags) {
-  QE_LAUNCH(k_validate, nblocks, kVecThreads, s, N, E, n_dir, eps, netdop, dir_id, phi, flags);
+  QE_LAUNCH(k_validate, nblocks, kVecThreads, s, N, E, n_dir, eps, dop, dir_id, phi, flags);
 }
 
 void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, const double* dir_val, uint8_t* mask,
@@ -801,15 +803,15 @@ void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* m
 }
 
 void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
-                          const uint8_t* semi, const double* netdop, const uint8_t* mask, const double* phi,
+                          const uint8_t* semi, const Doping& dop, const uint8_t* mask, const double* phi,
                           const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
                           double* diag_out, double* cq, float* cq32, uint8_t* cflag, unsigned int* cbits,
                           float* invdiag32, double* partial, double* norm2) {
   if (delta32)
-    QE_LAUNCH(k_residual_wave<float>, wm.nblocks, 256, s, g, wm, ch, eps, semi, netdop, mask, phi, delta32, lam, F,
+    QE_LAUNCH(k_residual_wave<float>, wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam, F,
               invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
   else
-    QE_LAUNCH(k_residual_wave<double>, wm.nblocks, 256, s, g, wm, ch, eps, semi, netdop, mask, phi, delta64, lam, F,
+    QE_LAUNCH(k_residual_wave<double>, wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam, F,
               invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
   QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, wm.nblocks, norm2);
 }

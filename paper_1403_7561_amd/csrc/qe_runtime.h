@@ -63,7 +63,8 @@ struct Context {
   uint8_t* u8(size_t off) const { return reinterpret_cast<uint8_t*>(ws + off); }
   unsigned int* u32(size_t off) const { return reinterpret_cast<unsigned int*>(ws + off); }
 
-  qe_status init(const qe_problem* p, void* ws, size_t ws_bytes, void* stream, int kz = 0);
+  qe_status init(const qe_problem* p, const Charge& ch, void* ws, size_t ws_bytes, void* stream, int kz = 0);
+  Doping doping() const;
   qe_status validate(const double* phi);
   qe_status stage(double* phi, int apply, int zero_free);
   qe_status residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam, bool mixed,

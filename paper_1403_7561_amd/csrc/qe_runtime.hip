@@ -55,37 +55,74 @@ void clear_error() { g_last_error.clear(); }
 static const double kQ = 1.602176634e-19, kEps0 = 8.8541878128e-12, kHbar = 1.054571817e-34,
                     kM0 = 9.1093837015e-31, kKB = 1.380649e-23, kPi = 3.14159265358979323846;
 
+// Effective density of states (Eq. EffectiveDOS) in nm^-3 and the T = 0
+// density prefactor C (n = C u^(3/2), u in eV) from integrating the 3D
+// density of states up to E_F.
+static double effective_dos(double m_eff, double T_K) {
+  const double m = m_eff * kM0, kT_J = kKB * T_K;
+  return 2.0 * std::pow(m * kT_J / (2.0 * kPi * kHbar * kHbar), 1.5) * 1e-27;
+}
+
+static double tf_prefactor(double m_eff) {
+  const double m = m_eff * kM0;
+  return std::pow(2.0 * m * kQ, 1.5) / (3.0 * kPi * kPi * kHbar * kHbar * kHbar) * 1e-27;
+}
+
+static bool positive(double v) { return v > 0.0 && std::isfinite(v); }
+
 qe_status make_charge(const qe_physics* ph, Charge& ch) {
   if (!ph) return fail(QE_ERR_INVALID_ARG, "physics is NULL");
   std::memset(&ch, 0, sizeof(ch));
   ch.kappa = kQ / kEps0 * 1e9;  // V nm: Poisson divided by eps0, nm units
   ch.Ec0 = ph->Ec0_eV;
   if (!std::isfinite(ph->Ec0_eV)) return fail(QE_ERR_INVALID_ARG, "Ec0_eV not finite");
+  if (ph->holes != 0 && ph->holes != 1) return fail(QE_ERR_INVALID_ARG, "holes must be 0 or 1");
+  if (ph->ionization != QE_ION_COMPLETE && ph->ionization != QE_ION_INCOMPLETE)
+    return fail(QE_ERR_INVALID_ARG, "unknown ionization %d", ph->ionization);
+  const bool holes = ph->holes == 1 && ph->stat != QE_STAT_LINEAR;
+  const bool incomplete = ph->ionization == QE_ION_INCOMPLETE;
+  if (holes && !positive(ph->m_h)) return fail(QE_ERR_INVALID_ARG, "m_h must be > 0 with holes");
+  if ((holes || incomplete) && !(ph->Eg_eV >= 0.0 && std::isfinite(ph->Eg_eV)))
+    return fail(QE_ERR_INVALID_ARG, "Eg_eV must be finite and >= 0");
   switch (ph->stat) {
     case QE_STAT_LINEAR:
       ch.stat = STAT_LINEAR;
       break;
-    case QE_STAT_TF: {
-      if (!(ph->m_eff > 0) || !std::isfinite(ph->m_eff)) return fail(QE_ERR_INVALID_ARG, "m_eff must be > 0");
+    case QE_STAT_TF:
+      if (!positive(ph->m_eff)) return fail(QE_ERR_INVALID_ARG, "m_eff must be > 0");
       ch.stat = STAT_TF;
-      // T = 0 limit of the 3D density of states integral: n = (2 m* E)^(3/2) / (3 pi^2 hbar^3)
-      const double m = ph->m_eff * kM0;
-      ch.Ctf = std::pow(2.0 * m * kQ, 1.5) / (3.0 * kPi * kPi * kHbar * kHbar * kHbar) * 1e-27;
+      ch.Ctf = tf_prefactor(ph->m_eff);
+      if (holes) ch.Ctf_h = tf_prefactor(ph->m_h);
       break;
-    }
-    case QE_STAT_FD12: {
-      if (!(ph->m_eff > 0) || !std::isfinite(ph->m_eff)) return fail(QE_ERR_INVALID_ARG, "m_eff must be > 0");
-      if (!(ph->T_K > 0) || !std::isfinite(ph->T_K))
-        return fail(QE_ERR_INVALID_ARG, "Fermi-Dirac statistics need T_K > 0");
-      ch.stat = STAT_FD;
-      const double m = ph->m_eff * kM0;
-      const double kT_J = kKB * ph->T_K;
-      ch.inv_kT = kQ / kT_J;  // 1/eV
-      ch.Nc = 2.0 * std::pow(m * kT_J / (2.0 * kPi * kHbar * kHbar), 1.5) * 1e-27;
+    case QE_STAT_FD12:
+    case QE_STAT_MB:
+      if (!positive(ph->m_eff)) return fail(QE_ERR_INVALID_ARG, "m_eff must be > 0");
+      if (!positive(ph->T_K))
+        return fail(QE_ERR_INVALID_ARG, "Fermi-Dirac and Boltzmann statistics need T_K > 0");
+      ch.stat = ph->stat == QE_STAT_MB ? STAT_MB : STAT_FD;
+      ch.inv_kT = kQ / (kKB * ph->T_K);  // 1/eV
+      ch.Nc = effective_dos(ph->m_eff, ph->T_K);
+      if (holes) ch.Nv = effective_dos(ph->m_h, ph->T_K);
       break;
-    }
     default:
       return fail(QE_ERR_INVALID_ARG, "unknown statistics %d", ph->stat);
+  }
+  if (holes) {
+    ch.holes = 1;
+    ch.Eg = ph->Eg_eV;
+  }
+  if (incomplete) {
+    if (ch.stat != STAT_FD && ch.stat != STAT_MB)
+      return fail(QE_ERR_INVALID_ARG, "incomplete ionization needs Fermi-Dirac or Boltzmann statistics");
+    if (!std::isfinite(ph->Ed_eV) || !std::isfinite(ph->Ea_eV))
+      return fail(QE_ERR_INVALID_ARG, "Ed_eV and Ea_eV must be finite");
+    if (!positive(ph->gD) || !positive(ph->gA)) return fail(QE_ERR_INVALID_ARG, "gD and gA must be > 0");
+    ch.incomplete = 1;
+    ch.Eg = ph->Eg_eV;
+    ch.ed_kT = ph->Ed_eV * ch.inv_kT;
+    ch.ea_kT = ph->Ea_eV * ch.inv_kT;
+    ch.ln_gD = std::log(ph->gD);
+    ch.ln_gA = std::log(ph->gA);
   }
   return QE_OK;
 }
@@ -203,6 +240,8 @@ qe_status check_problem(const qe_problem* p) {
     return fail(QE_ERR_INVALID_ARG, "NULL array in problem");
   if (p->n_dir < 0) return fail(QE_ERR_INVALID_ARG, "n_dir < 0");
   if (p->n_dir > 0 && !p->dir_val) return fail(QE_ERR_INVALID_ARG, "dir_val is NULL");
+  if ((p->donors == nullptr) != (p->acceptors == nullptr))
+    return fail(QE_ERR_INVALID_ARG, "donors and acceptors must be given together");
   return QE_OK;
 }
 
@@ -249,8 +288,10 @@ HostMirror& mirror() {
   return m;
 }
 
-qe_status Context::init(const qe_problem* p, void* ws_, size_t ws_bytes, void* stream_, int kz) {
+qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t ws_bytes, void* stream_, int kz) {
   QE_TRY(check_problem(p));
+  if (ch.incomplete && !p->donors)
+    return fail(QE_ERR_INVALID_ARG, "incomplete ionization needs donors and acceptors");
   prob = *p;
   s = (hipStream_t)stream_;
   N = (long)p->nx * p->ny * p->nz;
@@ -300,16 +341,21 @@ qe_status Context::init(const qe_problem* p, void* ws_, size_t ws_bytes, void* s
   return QE_OK;
 }
 
-// Device-side checks of eps_r, net doping, dir_id and (optionally) phi.
+// Doping arrays of the problem (the species only when both are given).
+Doping Context::doping() const {
+  return Doping{prob.net_doping, prob.donors, prob.acceptors};
+}
+
+// Device-side checks of eps_r, doping, dir_id and (optionally) phi.
 qe_status Context::validate(const double* phi) {
   int* dflags = reinterpret_cast<int*>(ws + lay.flags);
-  launch_validate(s, vblocks, N, E, prob.n_dir, prob.eps_r, prob.net_doping, prob.dir_id, phi, dflags);
+  launch_validate(s, vblocks, N, E, prob.n_dir, prob.eps_r, doping(), prob.dir_id, phi, dflags);
   QE_HIP(hipGetLastError());
   QE_HIP(hipMemcpyAsync(mirror().flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
   QE_HIP(hipStreamSynchronize(s));
   const int f = *mirror().flags;
   if (f & 1) return fail(QE_ERR_INVALID_ARG, "eps_r must be finite and > 0");
-  if (f & 2) return fail(QE_ERR_NONFINITE, "net_doping not finite");
+  if (f & 2) return fail(QE_ERR_NONFINITE, "net_doping not finite or donors / acceptors not finite and >= 0");
   if (f & 4) return fail(QE_ERR_INVALID_ARG, "dir_id outside [-1, n_dir)");
   if (f & 8) return fail(QE_ERR_NONFINITE, "phi not finite");
   return QE_OK;
@@ -324,7 +370,7 @@ qe_status Context::stage(double* phi, int apply, int zero_free) {
 
 qe_status Context::residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam,
                             bool mixed, double* diag_out, double* norm2_host) {
-  launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, prob.net_doping, u8(lay.mask), phi, d64, d32, lam,
+  launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, doping(), u8(lay.mask), phi, d64, d32, lam,
                        f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
                        u8(lay.cflag), u32(lay.cbits), mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial),
                        f64(lay.scal));
@@ -421,6 +467,32 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
 using namespace qe;
 
 // ====================================================================== C ABI
+// ------------------------------------------------------------------ contacts
+// eta with F_1/2(eta) ~= u: the Nilsson inverse of Eq. FDintInverse (the
+// first term tends to -1/2 at u = 1).
+static double nilsson_eta(double u) {
+  const double nu = std::cbrt(std::pow(0.75 * std::sqrt(kPi) * u, 2.0));
+  const double lead = std::fabs(u - 1.0) < 1e-8 ? -0.5 : std::log(u) / (1.0 - u * u);
+  const double t = 0.24 + 1.08 * nu;
+  return lead + nu / (1.0 + 1.0 / (t * t));
+}
+
+// ln y of the neutral contact with incomplete ionization (Eqs. Yval4MBIncompIon
+// and ApproxLogTerms): y = e^((E_F - E_D)/kT) solves g y^2 + y = K with
+// K = (N / N_band) e^(E_level/kT) (the paper's factors 8 and 16 are 4g for
+// g_D = 2 and g_A = 4).  The root is taken in the rationalised form
+// 2K / (1 + sqrt(1 + 4gK)); once 4gK passes 1e300 only the leading term
+// ln y = (ln(K/g))/2 is kept.
+static double incomplete_ln_y(double N, double Nband, double level_kT, double g) {
+  const double lnK = std::log(N / Nband) + level_kT;
+  const double ln4gK = std::log(4.0 * g) + lnK;
+  if (ln4gK < std::log(1e300)) {
+    const double K = std::exp(lnK);
+    return std::log(2.0 * K / (1.0 + std::sqrt(1.0 + 4.0 * g * K)));
+  }
+  return 0.5 * (lnK - std::log(g));
+}
+
 extern "C" {
 
 void qe_default_options(qe_options* o) {
@@ -470,7 +542,7 @@ qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* 
   if ((st = make_charge(ph, ch)) != QE_OK) return finish(st, r, rep);
   if (!phi) return finish(fail(QE_ERR_INVALID_ARG, "phi is NULL"), r, rep);
   Context cx;
-  if ((st = cx.init(p, ws, ws_bytes, stream)) != QE_OK) return finish(st, r, rep);
+  if ((st = cx.init(p, ch, ws, ws_bytes, stream)) != QE_OK) return finish(st, r, rep);
   const bool mixed = o->precision == QE_PREC_MIXED;
   if ((st = cx.validate(o->init_guess == 1 ? phi : nullptr)) != QE_OK) return finish(st, r, rep);
   if ((st = cx.stage(phi, 1, o->init_guess == 0 ? 1 : 0)) != QE_OK) return finish(st, r, rep);
@@ -483,8 +555,7 @@ qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* 
   if (o->init_guess == 0) {
     // charge-free linear Poisson with the doping kept: one Newton step from
     // phi = (Dirichlet values, 0) on the linear problem
-    lin = ch;
-    lin.stat = STAT_LINEAR;
+    lin = linear_charge(ch);
     double n2;
     if ((st = cx.residual(lin, phi, nullptr, nullptr, 0.0, mixed, nullptr, &n2)) != QE_OK) return finish(st, r, rep);
     if (!std::isfinite(n2)) return finish(fail(QE_ERR_NONFINITE, "initial residual not finite"), r, rep);
@@ -569,7 +640,7 @@ qe_status qe_residual(const qe_problem* p, const qe_physics* ph, const double* p
   QE_TRY(make_charge(ph, ch));
   if (!phi || !F) return fail(QE_ERR_INVALID_ARG, "phi/F is NULL");
   Context cx;
-  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.init(p, ch, ws, ws_bytes, stream));
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   double n2;
@@ -587,7 +658,7 @@ qe_status qe_jv(const qe_problem* p, const qe_physics* ph, const double* phi, co
   QE_TRY(make_charge(ph, ch));
   if (!phi || !v || !y) return fail(QE_ERR_INVALID_ARG, "phi/v/y is NULL");
   Context cx;
-  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.init(p, ch, ws, ws_bytes, stream));
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, false, nullptr, nullptr));
@@ -605,7 +676,7 @@ qe_status qe_jv_f32(const qe_problem* p, const qe_physics* ph, const double* phi
   QE_TRY(make_charge(ph, ch));
   if (!phi || !v || !y) return fail(QE_ERR_INVALID_ARG, "phi/v/y is NULL");
   Context cx;
-  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.init(p, ch, ws, ws_bytes, stream));
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, true, nullptr, nullptr));
@@ -628,7 +699,7 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
   if (precision != QE_PREC_FP64 && precision != QE_PREC_MIXED) return fail(QE_ERR_INVALID_ARG, "bad precision");
   const bool mixed = precision == QE_PREC_MIXED;
   Context cx;
-  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.init(p, ch, ws, ws_bytes, stream));
   QE_TRY(cx.validate(phi));
   QE_TRY(cx.stage(nullptr, 0, 0));
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, mixed, nullptr, nullptr));
@@ -712,7 +783,7 @@ qe_status qe_count_electrons(const qe_problem* p, const qe_physics* ph, const do
     bs.b[r] = Box{b[0], b[1], b[2], b[3], b[4], b[5]};
   }
   Context cx;
-  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.init(p, ch, ws, ws_bytes, stream));
   QE_TRY(cx.validate(phi));
   launch_count(cx.s, kCountBlocks, cx.g, ch, bs, p->semi, phi, cx.f64(cx.lay.partial),
                reinterpret_cast<unsigned int*>(cx.ws + cx.lay.counters) + 1, cx.f64(cx.lay.scal));
@@ -730,7 +801,7 @@ qe_status qe_density(const qe_problem* p, const qe_physics* ph, const double* ph
   QE_TRY(make_charge(ph, ch));
   if (!phi || !n) return fail(QE_ERR_INVALID_ARG, "phi/n is NULL");
   Context cx;
-  QE_TRY(cx.init(p, ws, ws_bytes, stream));
+  QE_TRY(cx.init(p, ch, ws, ws_bytes, stream));
   QE_TRY(cx.validate(phi));
   launch_density(cx.s, cx.vblocks, cx.g, ch, p->semi, phi, n);
   QE_HIP(hipGetLastError());
@@ -753,7 +824,7 @@ qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options
   for (int k = 0; k < 6; ++k)
     if (std::isnan(box[k])) return finish(fail(QE_ERR_INVALID_ARG, "box has NaN"), r, rep);
   Context cx;
-  if ((st = cx.init(p, ws, ws_bytes, stream)) != QE_OK) return finish(st, r, rep);
+  if ((st = cx.init(p, ch, ws, ws_bytes, stream)) != QE_OK) return finish(st, r, rep);
   if ((st = cx.validate(phi)) != QE_OK) return finish(st, r, rep);
   if (p->n_dir > 56) return finish(fail(QE_ERR_INVALID_ARG, "the adjoint supports at most 56 contacts"), r, rep);
   if ((st = cx.stage(nullptr, 0, 0)) != QE_OK) return finish(st, r, rep);
@@ -789,6 +860,46 @@ qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options
   for (int c = 0; c < nd; ++c) dQ_ddir[c] = mirror().scal[8 + c];
   st = (pst == PCG_MAXIT) ? fail(QE_ERR_KRYLOV_MAXIT, "adjoint CG hit krylov_maxit (%d)", its) : QE_OK;
   return finish(st, r, rep);
+}
+
+qe_status qe_ohmic_potential(const qe_physics* ph, double N_D, double N_A, double V_a, double* phi) {
+  clear_error();
+  if (!ph || !phi) return fail(QE_ERR_INVALID_ARG, "NULL argument");
+  if (ph->stat != QE_STAT_MB && ph->stat != QE_STAT_FD12)
+    return fail(QE_ERR_INVALID_ARG, "Ohmic contacts need Boltzmann or Fermi-Dirac statistics");
+  if (!positive(ph->T_K)) return fail(QE_ERR_INVALID_ARG, "T_K must be > 0");
+  if (!(N_D >= 0.0 && std::isfinite(N_D)) || !(N_A >= 0.0 && std::isfinite(N_A)))
+    return fail(QE_ERR_INVALID_ARG, "N_D and N_A must be finite and >= 0");
+  if (!std::isfinite(V_a) || !std::isfinite(ph->Ec0_eV)) return fail(QE_ERR_INVALID_ARG, "V_a and Ec0_eV must be finite");
+  const bool ntype = N_D >= N_A;
+  const double m = ntype ? ph->m_eff : ph->m_h;
+  if (!positive(m)) return fail(QE_ERR_INVALID_ARG, ntype ? "m_eff must be > 0" : "m_h must be > 0");
+  if (!ntype && !(ph->Eg_eV >= 0.0 && std::isfinite(ph->Eg_eV)))
+    return fail(QE_ERR_INVALID_ARG, "Eg_eV must be finite and >= 0");
+  const double kT = kKB * ph->T_K / kQ;  // eV
+  const double Nband = effective_dos(m, ph->T_K);
+  const double Ev0 = ph->Ec0_eV - ph->Eg_eV;   // E_V - E_F at phi = 0
+  double v;
+  if (ph->ionization == QE_ION_COMPLETE) {
+    // majority carriers balance the net doping: n = N_D - N_A or p = N_A - N_D
+    const double net = std::fabs(N_D - N_A);
+    if (!(net > 0.0)) return fail(QE_ERR_INVALID_ARG, "net doping at the contact is zero");
+    const double eta = ph->stat == QE_STAT_MB ? std::log(net / Nband) : nilsson_eta(net / Nband);
+    v = ntype ? ph->Ec0_eV + kT * eta : Ev0 - kT * eta;   // Eqs. PotBC4MBCompIon, PotBC4FDCompIon
+  } else if (ph->ionization == QE_ION_INCOMPLETE) {
+    const double N = ntype ? N_D : N_A;
+    const double E = ntype ? ph->Ed_eV : ph->Ea_eV, g = ntype ? ph->gD : ph->gA;
+    if (!(N > 0.0)) return fail(QE_ERR_INVALID_ARG, "majority dopant density at the contact is zero");
+    if (!std::isfinite(E) || !positive(g)) return fail(QE_ERR_INVALID_ARG, "bad ionization energy or degeneracy");
+    const double ln_y = incomplete_ln_y(N, Nband, E / kT, g);
+    // E_F - E_D = kT ln y_n with E_D = E_C - E_d; E_A - E_F = kT ln y_p with
+    // E_A = E_V + E_a (Eq. PotBC4MBIncompIon)
+    v = ntype ? ph->Ec0_eV - E + kT * ln_y : Ev0 + E - kT * ln_y;
+  } else {
+    return fail(QE_ERR_INVALID_ARG, "unknown ionization %d", ph->ionization);
+  }
+  *phi = v + V_a;
+  return QE_OK;
 }
 
 }  // extern "C"

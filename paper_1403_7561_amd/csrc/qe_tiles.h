@@ -308,7 +308,8 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
 
 // ---------------------------------------------------------------------------
 // Residual F(phi + lam delta), Jacobi diagonal and Gauss-point coefficients
-// c_q = KAPPA semi W n'(phi_q) on one wave tile.  F and the diagonal are
+// c_q = -KAPPA semi W rho'(phi_q) (= KAPPA semi W n'(phi_q) with electrons
+// alone) on one wave tile.  F and the diagonal are
 // written on owned nodes (0 and 1 on Dirichlet rows, where the stored inverse
 // diagonal is 0).  The owning wave writes, in tile-major order, cflag = 1 for
 // an element with a nonzero c_q and then its c_q, else cflag = 0 and nothing
@@ -317,7 +318,7 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
 template <typename TD>
 __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, const Charge& ch,
                                               const double* __restrict__ eps, const uint8_t* __restrict__ semi,
-                                              const double* __restrict__ netdop, const uint8_t* __restrict__ mask,
+                                              const Doping dop, const uint8_t* __restrict__ mask,
                                               const double* __restrict__ phi, const TD* __restrict__ delta,
                                               double lam, double* __restrict__ F, double* __restrict__ invdiag,
                                               double* __restrict__ diag_out, double* __restrict__ cq,
@@ -364,17 +365,25 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
       bool nzc = false;  // some c_q of this element is nonzero
       if ((sbits >> (L - w.Lbeg)) & 1u) {
         const double kw = ch.kappa * axy * hz * 0.125;
-        const double nd = netdop ? netdop[el] : 0.0;
+        double net = 0.0, ndo = 0.0, nac = 0.0;
+        if (ch.incomplete) {
+          ndo = dop.donors[el];
+          nac = dop.acceptors[el];
+        } else if (dop.net) {
+          net = dop.net[el];
+        } else if (dop.donors) {
+          net = dop.donors[el] - dop.acceptors[el];
+        }
         double src[8], cc[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) src[k] = ve[k];
         gauss_interp(src);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          double n, dn;
-          electron_density(ch, src[q], n, dn);
-          src[q] = kw * (nd - n);
-          cc[q] = kw * dn;
+          double rho, drho;
+          space_charge(ch, src[q], net, ndo, nac, rho, drho);
+          src[q] = kw * rho;
+          cc[q] = -kw * drho;
           nzc |= cc[q] != 0.0;
         }
         if (own && nzc) {

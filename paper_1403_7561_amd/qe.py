@@ -22,14 +22,22 @@ STATUS_NAMES = {
     0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "WORKSPACE", -4: "NOT_CONVERGED",
     -5: "LINESEARCH", -6: "KRYLOV_BREAKDOWN", -7: "NONFINITE", -8: "KRYLOV_MAXIT",
 }
-STAT = {"linear": 0, "tf": 1, "fd": 2}
+STAT = {"linear": 0, "tf": 1, "fd": 2, "mb": 3}
+IONIZATION = {"complete": 0, "incomplete": 1}
 PREC = {"fp64": 0, "mixed": 1}
 
 EXPORTED = [
     "qe_default_options", "qe_workspace_bytes", "qe_solve", "qe_residual", "qe_jv",
     "qe_jv_f32", "qe_count_electrons", "qe_density", "qe_adjoint",
-    "qe_batch_workspace_bytes", "qe_solve_batch", "qe_time_jv", "qe_last_error",
+    "qe_batch_workspace_bytes", "qe_solve_batch", "qe_time_jv", "qe_ohmic_potential",
+    "qe_last_error",
 ]
+
+# Silicon parameters of Sec. II.A.3: band gap, phosphorus / boron ionization
+# energies, ground-state degeneracies, and the valence DOS mass from the heavy
+# and light holes (Eq. EffectiveMass: m_h^(3/2) = m_hh^(3/2) + m_lh^(3/2)).
+SI_EG_EV, SI_ED_EV, SI_EA_EV, SI_GD, SI_GA = 1.12, 0.046, 0.044, 2.0, 4.0
+SI_M_H = (0.49 ** 1.5 + 0.16 ** 1.5) ** (2.0 / 3.0)
 
 
 class QeError(RuntimeError):
@@ -44,12 +52,16 @@ class CProblem(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("eps_r", ctypes.c_void_p), ("semi", ctypes.c_void_p),
                 ("net_doping", ctypes.c_void_p), ("dir_id", ctypes.c_void_p),
-                ("dir_val", ctypes.c_void_p), ("n_dir", ctypes.c_int32)]
+                ("dir_val", ctypes.c_void_p), ("n_dir", ctypes.c_int32),
+                ("donors", ctypes.c_void_p), ("acceptors", ctypes.c_void_p)]
 
 
 class CPhysics(ctypes.Structure):
     _fields_ = [("stat", ctypes.c_int32), ("T_K", ctypes.c_double),
-                ("m_eff", ctypes.c_double), ("Ec0_eV", ctypes.c_double)]
+                ("m_eff", ctypes.c_double), ("Ec0_eV", ctypes.c_double),
+                ("holes", ctypes.c_int32), ("m_h", ctypes.c_double), ("Eg_eV", ctypes.c_double),
+                ("ionization", ctypes.c_int32), ("Ed_eV", ctypes.c_double), ("Ea_eV", ctypes.c_double),
+                ("gD", ctypes.c_double), ("gA", ctypes.c_double)]
 
 
 class COptions(ctypes.Structure):
@@ -96,6 +108,7 @@ def load_library(path=LIB_PATH):
         "qe_solve_batch": (I32, [I32, pp, pph, po, P(V), I32, P(D), P(D), ctypes.c_char_p,
                                  V, S, V, pr]),
         "qe_time_jv": (I32, [pp, pph, V, V, I32, I32, P(D), P(ctypes.c_int64), V, S, V]),
+        "qe_ohmic_potential": (I32, [pph, D, D, D, P(D)]),
         "qe_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -136,13 +149,25 @@ class Physics:
     T_K: float = 4.0
     m_eff: float = 1.08
     Ec0_eV: float = 0.56
+    holes: bool = False
+    m_h: float = SI_M_H
+    Eg_eV: float = SI_EG_EV
+    ionization: str = "complete"
+    Ed_eV: float = SI_ED_EV
+    Ea_eV: float = SI_EA_EV
+    gD: float = SI_GD
+    gA: float = SI_GA
 
     def c(self):
-        return CPhysics(STAT[self.stat], float(self.T_K), float(self.m_eff), float(self.Ec0_eV))
+        return CPhysics(STAT[self.stat], float(self.T_K), float(self.m_eff), float(self.Ec0_eV),
+                        int(bool(self.holes)), float(self.m_h), float(self.Eg_eV),
+                        IONIZATION[self.ionization], float(self.Ed_eV), float(self.Ea_eV),
+                        float(self.gD), float(self.gA))
 
     @classmethod
     def of(cls, dev):
-        return cls(dev.stat, dev.T_K, dev.m_eff, dev.Ec0_eV)
+        return cls(dev.stat, dev.T_K, dev.m_eff, dev.Ec0_eV, holes=bool(getattr(dev, "holes", False)),
+                   ionization=getattr(dev, "ionization", "complete"))
 
 
 def qe_default_options(**over):
@@ -173,14 +198,20 @@ class Problem:
         dv = np.ascontiguousarray(dev.dir_val, dtype=np.float64)
         self.dir_val = torch.as_tensor(dv if dv.size else np.zeros(1), **f64)
         self.n_dir = int(dv.size)
+        nd, na = getattr(dev, "donors", None), getattr(dev, "acceptors", None)
+        self.donors = None if nd is None else torch.as_tensor(np.ascontiguousarray(nd, dtype=np.float64), **f64)
+        self.acceptors = None if na is None else torch.as_tensor(np.ascontiguousarray(na, dtype=np.float64), **f64)
         self.physics = Physics.of(dev) if hasattr(dev, "stat") else Physics()
         self.device = device
 
     def c(self):
         return CProblem(self.nx, self.ny, self.nz, self.x.data_ptr(), self.y.data_ptr(),
                         self.z.data_ptr(), self.eps_r.data_ptr(), self.semi.data_ptr(),
-                        self.net_doping.data_ptr(), self.dir_id.data_ptr(),
-                        self.dir_val.data_ptr(), self.n_dir)
+                        self.net_doping.data_ptr() if self.net_doping is not None else None,
+                        self.dir_id.data_ptr(),
+                        self.dir_val.data_ptr(), self.n_dir,
+                        self.donors.data_ptr() if self.donors is not None else None,
+                        self.acceptors.data_ptr() if self.acceptors is not None else None)
 
 
 class Workspace:
@@ -352,3 +383,12 @@ def qe_solve_batch(probs, phys=None, opts=None, phis=None, boxes=(), tune_cache=
     if check:
         _check(st, rlist)
     return phis, counts[:, : b.shape[0]], rlist
+
+
+def qe_ohmic_potential(phys, N_D, N_A, V_a=0.0):
+    """Dirichlet potential (V) of an Ohmic contact with donor / acceptor
+    densities N_D, N_A (nm^-3) at applied voltage V_a (host computation)."""
+    out = ctypes.c_double()
+    _check(load_library().qe_ohmic_potential(ctypes.byref(phys.c()), float(N_D), float(N_A), float(V_a),
+                                              ctypes.byref(out)))
+    return out.value

@@ -6,6 +6,7 @@ statistics, no discretisation, no physical constants).
 """
 from .devices import (  # noqa: F401
     doped_block,
+    with_species,
     Device,
     stack_z,
     make_stack_device,

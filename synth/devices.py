@@ -299,3 +299,17 @@ def doped_block(name, nx, ny, nz, size_nm, donors_fn, acceptors_fn, contacts, st
     return Device(name=name, x=x, y=y, z=z, eps_r=np.full(E, EPS_SI), semi=np.ones(E, dtype=np.uint8),
                   net_doping=nd - na, dir_id=dir_id, dir_val=np.zeros(len(contacts)), contacts=names,
                   stat=stat, T_K=T_K, holes=holes, ionization=ionization, donors=nd, acceptors=na)
+
+
+def with_species(dev, donors_si=0.0, acceptors_si=NA_BULK_NM3, holes=True, ionization="incomplete"):
+    """A copy of a gate-stack device with the full space charge switched on:
+    holes, the chosen ionization model, and per-element donor / acceptor
+    densities (nm^-3) in the silicon (zero in the oxide); net_doping becomes
+    donors - acceptors.  Contact values are left as they are: the caller sets
+    the Ohmic potential of the substrate contact."""
+    from dataclasses import replace
+    semi = np.asarray(dev.semi).astype(bool)
+    nd = np.where(semi, donors_si, 0.0).astype(np.float64)
+    na = np.where(semi, acceptors_si, 0.0).astype(np.float64)
+    return replace(dev, holes=holes, ionization=ionization, donors=nd, acceptors=na,
+                   net_doping=nd - na, dir_val=np.array(dev.dir_val, dtype=np.float64, copy=True))

@@ -26,7 +26,10 @@ def sub_device(dev, i, j, k):
     sub = synth.Device(name="sub", x=dev.x[i0:i1 + 1], y=dev.y[j0:j1 + 1], z=dev.z[k0:k1 + 1],
                        eps_r=dev.eps_r[el], semi=dev.semi[el], net_doping=dev.net_doping[el],
                        dir_id=np.full(snx * sny * snz, -1, np.int32), dir_val=np.zeros(0),
-                       stat=dev.stat, T_K=dev.T_K, m_eff=dev.m_eff, Ec0_eV=dev.Ec0_eV)
+                       stat=dev.stat, T_K=dev.T_K, m_eff=dev.m_eff, Ec0_eV=dev.Ec0_eV,
+                       holes=dev.holes, ionization=dev.ionization,
+                       donors=None if dev.donors is None else dev.donors[el],
+                       acceptors=None if dev.acceptors is None else dev.acceptors[el])
     kk, jj, ii = np.meshgrid(np.arange(k0, k1 + 1), np.arange(j0, j1 + 1), np.arange(i0, i1 + 1),
                              indexing="ij")
     glob = (ii + dev.nx * (jj + dev.ny * kk)).ravel()
@@ -67,4 +70,15 @@ def ragged_device(stat="fd", T=4.0, volts=(1.5, 1.4, 0.5, 0.7, 0.3)):
     """A double-dot stack whose node counts leave ragged tiles in x, y and z."""
     dev = synth.double_dot_device("ragged", 37, 29, 19, np.asarray(volts, float),
                                   stat=stat, T_K=T)
+    return dev
+
+
+def full_charge_device(ionization="incomplete", volts=(2.1, 2.0, 1.1, 1.3, 0.9), stat="fd", T=4.0):
+    """The ragged double-dot stack with the full space charge: holes, a
+    1e15 cm^-3 boron substrate with the given ionization model, and the
+    bottom contact at the oracle's Ohmic potential of that substrate."""
+    from oracle import physics as ph
+    dev = synth.with_species(ragged_device(stat=stat, T=T, volts=volts), ionization=ionization)
+    st = ph.Statistics(stat, T, dev.m_eff, dev.Ec0_eV, holes=True, ionization=ionization)
+    dev.dir_val[dev.contacts.index("bottom")] = ph.ohmic_potential(st, 0.0, synth.devices.NA_BULK_NM3)
     return dev

@@ -142,3 +142,63 @@ def test_count_and_adjoint_argument_checks():
                         boxes.ctypes.data_as(P), None, out.ctypes.data_as(P), None, None,
                         ctypes.c_void_p(256), 1 << 40, None, None)
     assert st == -1 and "FP64" in qe.qe_last_error()
+
+
+def full_physics(**kw):
+    f = dict(stat="fd", T_K=4.0, holes=True, ionization="incomplete")
+    f.update(kw)
+    return qe.Physics(**f).c()
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(holes=2), "holes must be 0 or 1"),
+    (dict(ionization=5), "unknown ionization"),
+    (dict(m_h=0.0), "m_h"),
+    (dict(Eg_eV=-0.1), "Eg_eV"),
+    (dict(Ed_eV=float("nan")), "Ed_eV"),
+    (dict(gA=0.0), "gD and gA"),
+    (dict(stat=1, T_K=0.0), "incomplete ionization needs"),
+    (dict(stat=3, T_K=0.0), "T_K > 0"),
+])
+def test_invalid_full_charge_physics_rejected(over, needle):
+    lib = qe.load_library()
+    p = fake_problem()
+    p.donors = p.acceptors = 16
+    o = qe.qe_default_options()
+    ph = full_physics()
+    for k, v in over.items():
+        setattr(ph, k, v)
+    st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                      None, ctypes.c_void_p(256), 1 << 40, None, None)
+    assert st == -1 and needle in qe.qe_last_error()
+
+
+def test_dopant_species_arguments_checked_before_device_work():
+    lib = qe.load_library()
+    o = qe.qe_default_options()
+    ph = full_physics()
+    p = fake_problem()
+    p.donors = 16                       # acceptors missing
+    st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                      None, ctypes.c_void_p(256), 1 << 40, None, None)
+    assert st == -1 and "together" in qe.qe_last_error()
+    p = fake_problem()                  # neither: fine for complete ionization, not for incomplete
+    st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                      None, ctypes.c_void_p(256), 1 << 40, None, None)
+    assert st == -1 and "needs donors and acceptors" in qe.qe_last_error()
+
+
+def test_ohmic_potential_argument_checks():
+    lib = qe.load_library()
+    out = ctypes.c_double()
+    for ph, nd, na, needle in [
+        (qe.Physics(stat="tf", T_K=0.0).c(), 1e-3, 0.0, "Boltzmann or Fermi-Dirac"),
+        (qe.Physics(stat="mb", T_K=0.0).c(), 1e-3, 0.0, "T_K"),
+        (qe.Physics(stat="mb", T_K=300.0).c(), -1e-3, 0.0, "N_D and N_A"),
+        (qe.Physics(stat="mb", T_K=300.0).c(), 1e-3, 1e-3, "net doping"),
+        (qe.Physics(stat="mb", T_K=300.0, ionization="incomplete").c(), 0.0, 0.0, "majority dopant"),
+        (qe.Physics(stat="fd", T_K=300.0, m_h=0.0).c(), 0.0, 1e-3, "m_h"),
+    ]:
+        st = lib.qe_ohmic_potential(ctypes.byref(ph), nd, na, 0.0, ctypes.byref(out))
+        assert st == -1 and needle in qe.qe_last_error(), (needle, qe.qe_last_error())
+    assert lib.qe_ohmic_potential(None, 1e-3, 0.0, 0.0, ctypes.byref(out)) == -1
