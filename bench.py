@@ -84,6 +84,35 @@ def cpu_baseline(dev, gpu_newton, budget_s=25.0):
                       f"{gpu_newton} Newton steps = {est:.1f} s (scipy CSR/CG, single-threaded)"}
 
 
+def full_charge_run(synth, qe, torch, dev, opts, ws, boxes, jv_reps):
+    """The same stack with the full space charge: holes, a 1e15 cm^-3 boron
+    substrate with incomplete ionization, the bottom contact at the library's
+    Ohmic potential of that substrate.  One warm-up and two timed solves,
+    then the CG loop's J.v kernel at the solution."""
+    fdev = synth.with_species(dev, ionization="incomplete")
+    phys = qe.Physics(stat=fdev.stat, T_K=fdev.T_K, m_eff=fdev.m_eff, Ec0_eV=fdev.Ec0_eV, holes=True,
+                      ionization="incomplete")
+    vb = qe.qe_ohmic_potential(phys, 0.0, float(fdev.acceptors.max()))
+    fdev.dir_val[fdev.contacts.index("bottom")] = vb
+    P = qe.Problem(fdev)
+    qe.qe_solve(P, opts=opts, ws=ws, want_density=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        ph, _, rep = qe.qe_solve(P, opts=opts, ws=ws, want_density=True)
+        c = qe.qe_count_electrons(P, ph, boxes, ws=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 2
+    v = torch.randn(P.N, dtype=torch.float64, device="cuda")
+    ms64, ncoef = qe.qe_time_jv(P, ph, v, "fp64", jv_reps, ws=ws)
+    b64 = jv_bytes(fdev, 8, ncoef)
+    ach = b64 / (ms64 * 1e-3) / 1e9
+    return {"solves_per_s": 1.0 / dt, "ms": dt * 1e3, "ohmic_bottom_V": vb,
+            "newton_iters": rep["newton_iters"], "krylov_iters": rep["krylov_iters"],
+            "res_final": rep["res_final"], "dot_electrons": [float(x) for x in c],
+            "jv": {"ms": ms64, "coef_elems": ncoef, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -98,6 +127,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-full-charge", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -235,6 +265,9 @@ def main():
                            "mixed_cg_iters": res["mixed"][2]["krylov_iters"],
                            "res_final": [res["fp64"][2]["res_final"], res["mixed"][2]["res_final"]]}
         del P5, ws5, res
+    if not args.no_full_charge:
+        log("full space charge on the same stack")
+        out["full_charge_c2"] = full_charge_run(synth, qe, torch, dev, opts, ws, boxes, args.jv_reps)
     log("cpu baseline")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dev, reps[-1]["newton_iters"])

@@ -160,3 +160,34 @@ def test_uniform_block_at_ohmic_potential_is_flat():
         P = qe.Problem(dev)
         phi, _, rep = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-12))
         assert np.abs(phi.cpu().numpy() - vb).max() < 1e-10, (ion, rep)
+
+
+def test_full_size_stack_with_full_charge_sampled():
+    """The 129 x 129 x 65 stack with holes, incomplete ionization of the boron
+    substrate and the bottom contact at the library's Ohmic potential: the
+    converged GPU potential leaves an oracle residual at the FP64 floor on
+    sampled nodes, and sampled residual and J.v values at a perturbed
+    potential match the oracle."""
+    dev = synth.with_species(synth.config2(), ionization="incomplete")
+    P = qe.Problem(dev)
+    vb = qe.qe_ohmic_potential(P.physics, 0.0, float(dev.acceptors.max()))
+    st = ph.Statistics("fd", 4.0, dev.m_eff, dev.Ec0_eV, holes=True, ionization="incomplete")
+    assert vb == pytest.approx(ph.ohmic_potential(st, 0.0, float(dev.acceptors.max())), abs=1e-12)
+    dev.dir_val[dev.contacts.index("bottom")] = vb
+    P = qe.Problem(dev)
+    phi, n, rep = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-8))
+    print(rep)
+    assert rep["status"] == 0 and rep["res_final"] <= 1e-8
+    phn = phi.cpu().numpy()
+    rng = np.random.default_rng(12)
+    nodes = rng.choice(dev.n_nodes, 300, replace=False)
+    assert np.abs(gs.sampled_residual(dev, phn, nodes)).max() < 1e-8
+    pert = phn + 0.01 * rng.standard_normal(phn.size)
+    pert[dev.dir_id >= 0] = dev.dir_val[dev.dir_id[dev.dir_id >= 0]]
+    F, _, _ = qe.qe_residual(P, dev_tensor(pert))
+    Fo = gs.sampled_residual(dev, pert, nodes)
+    assert np.abs(F.cpu().numpy()[nodes] - Fo).max() <= 1e-12 * np.abs(Fo).max()
+    v = rng.standard_normal(phn.size)
+    y = qe.qe_jv(P, dev_tensor(pert), dev_tensor(v)).cpu().numpy()[nodes]
+    yo = gs.sampled_jv(dev, pert, v, nodes)
+    assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
