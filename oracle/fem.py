@@ -7,7 +7,9 @@ basis function w_i of a free node,
                        - KAPPA semi_e sum_q W_q (N_net,e - n(phi_q)) w_i(q) ] = 0
 
 with the boundary integral dropped on every non-Dirichlet face (the default
-flux-conserving Neumann condition, Sec. II.A.5).  Khat_e is the unit-
+flux-conserving Neumann condition, Sec. II.A.5) except on the faces of the
+device's sheets, which carry a surface charge and / or a Robin condition
+(``sheet_terms``).  Khat_e is the unit-
 permittivity trilinear stiffness of a box element, exact under 2x2x2 Gauss
 quadrature; phi_q is the trilinear interpolant at the Gauss points and
 W_q = hx*hy*hz/8.  Everything is assembled into scipy.sparse matrices.
@@ -90,6 +92,75 @@ class Mesh:
         return nodal[self.conn] @ INTERP.T
 
 
+def sheet_nodes(mesh, sh):
+    """Global node indices [nb+1, na+1] of a sheet's face range (a fastest)."""
+    a = np.arange(sh.a0, sh.a1 + 1)
+    b = np.arange(sh.b0, sh.b1 + 1)
+    B, A = np.meshgrid(b, a, indexing="ij")
+    nx, ny = mesh.nx, mesh.ny
+    if sh.axis == 2:
+        i, j, k = A, B, np.full_like(A, sh.plane)
+    elif sh.axis == 1:
+        i, j, k = A, np.full_like(A, sh.plane), B
+    elif sh.axis == 0:
+        i, j, k = np.full_like(A, sh.plane), A, B
+    else:
+        raise ValueError("sheet axis must be 0, 1 or 2")
+    return i + nx * (j + ny * k)
+
+
+def sheet_coords(mesh, sh):
+    """Coordinates along the sheet's first and second in-plane axes."""
+    xs = {0: (mesh.y, mesh.z), 1: (mesh.x, mesh.z), 2: (mesh.x, mesh.y)}[sh.axis]
+    return xs
+
+
+def sheet_terms(mesh, sheets):
+    """Face integrals of the interface and Robin conditions (Sec. II.A.5).
+
+    For every face f of a sheet (a rectangle of the plane x_axis = const):
+
+    * surface charge (Eq. NeuBC4fc): the flux jump across the face equals
+      q sigma_f, so the weak form gains the load KAPPA sigma_f int_f w_i, the
+      same sign as a volume charge;
+    * Robin (a pinned plane at potential phi0 a distance d beyond the face,
+      with the layer's permittivity eps): the outward flux is
+      eps (phi0 - phi)/d, so the weak form gains (eps/d) int_f (phi - phi0) w_i.
+
+    Returns the face-mass matrix R (N x N CSR, (eps/d) int_f w_i w_j) and the
+    constant load s (KAPPA sigma int_f w_i + (eps/d) phi0 int_f w_i); the
+    residual is then K phi + R phi - s - b(phi)."""
+    N = mesh.N
+    rows, cols, vals = [], [], []
+    load = np.zeros(N)
+    for sh in sheets:
+        ca, cb = sheet_coords(mesh, sh)
+        if not (0 <= sh.a0 < sh.a1 <= ca.size - 1 and 0 <= sh.b0 < sh.b1 <= cb.size - 1):
+            raise ValueError("sheet face range outside the mesh")
+        nodes = sheet_nodes(mesh, sh)                 # [nb+1, na+1]
+        ha = np.diff(ca)[sh.a0:sh.a1]
+        hb = np.diff(cb)[sh.b0:sh.b1]
+        na, nb = sh.a1 - sh.a0, sh.b1 - sh.b0
+        sigma = np.zeros((nb, na)) if sh.sigma is None else np.asarray(sh.sigma, float).reshape(nb, na)
+        alpha = sh.robin_eps / sh.robin_d if sh.robin_d > 0 else 0.0
+        for jb in range(nb):
+            for ia in range(na):
+                corners = [nodes[jb, ia], nodes[jb, ia + 1], nodes[jb + 1, ia], nodes[jb + 1, ia + 1]]
+                area = ha[ia] * hb[jb]
+                # int_f w_i w_j = (int X_i X_j da)(int Y_i Y_j db), 1D linear mass [[2,1],[1,2]]/6
+                Mf = np.kron(_M1 * hb[jb], _M1 * ha[ia])
+                if alpha > 0:
+                    for r in range(4):
+                        for c in range(4):
+                            rows.append(corners[r])
+                            cols.append(corners[c])
+                            vals.append(alpha * Mf[r, c])
+                for r in range(4):
+                    load[corners[r]] += (KAPPA * sigma[jb, ia] + alpha * sh.phi0) * area / 4.0
+    R = sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
+    return R, load
+
+
 class Problem:
     """One device: mesh, materials, Dirichlet data, statistics.
 
@@ -123,6 +194,10 @@ class Problem:
         self.extra_load = extra_load
         self.Khat = m.unit_stiffness()
         self.K = m.assemble(self.eps[:, None, None] * self.Khat)
+        # interface charge and Robin faces (Sec. II.A.5)
+        self.sheets = list(getattr(dev, "sheets", None) or [])
+        self.R, self.sheet_load = sheet_terms(m, self.sheets)
+        self.K_lin = self.K + self.R      # the phi-linear part of F
 
     # --- nodal vectors -------------------------------------------------
     def with_dirichlet(self, phi):
@@ -148,7 +223,7 @@ class Problem:
 
     def residual_full(self, phi, stats=None):
         """K phi - b(phi) on every node (Dirichlet rows included)."""
-        return self.K @ phi - self.charge_load(phi, stats)
+        return self.K_lin @ phi - self.sheet_load - self.charge_load(phi, stats)
 
     def residual(self, phi, stats=None):
         """Eq. PoissonWeakForm residual on free nodes, zero on Dirichlet rows."""
@@ -168,7 +243,7 @@ class Problem:
         """dF/dphi on all nodes: eps K + sum_q c_q w(q) w(q)^T (N x N CSR)."""
         c = self.coeff(phi)
         Me = np.einsum("eq,qa,qb->eab", c, INTERP, INTERP)
-        return self.K + self.mesh.assemble(Me)
+        return self.K_lin + self.mesh.assemble(Me)
 
     def jacobian_free(self, phi):
         J = self.jacobian_full(phi)

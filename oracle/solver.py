@@ -51,7 +51,7 @@ def initial_guess(prob, method="auto"):
     lin = Statistics("linear")
     F = prob.residual(phi, stats=lin)
     f = prob.free
-    K_ff = prob.K[np.nonzero(f)[0]][:, np.nonzero(f)[0]]
+    K_ff = prob.K_lin[np.nonzero(f)[0]][:, np.nonzero(f)[0]]
     phi[f] -= linear_solve(K_ff, F[f], rtol=1e-13, method=method)
     return phi
 

@@ -7,6 +7,9 @@ statistics, no discretisation, no physical constants).
 from .devices import (  # noqa: F401
     doped_block,
     with_species,
+    with_interface_charge,
+    with_charged_gates,
+    Sheet,
     Device,
     stack_z,
     make_stack_device,

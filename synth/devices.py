@@ -35,6 +35,27 @@ DOT_BOX_D2 = (140.0, 200.0, 70.0, 130.0, 70.0, 90.0)
 
 
 @dataclass
+class Sheet:
+    """A rectangle of mesh faces in the plane x_axis = coordinate[plane]
+    (axis 0: x, 1: y, 2: z) covering faces a0..a1-1 along its first in-plane
+    axis and b0..b1-1 along its second (axis 2: x then y; axis 1: x then z;
+    axis 0: y then z).  sigma: per-face surface charge density in nm^-2
+    (a fastest) or None; a Robin condition pins the potential phi0 (V) on a
+    plane robin_d nm beyond the faces through a layer of relative permittivity
+    robin_eps (robin_d = 0: no Robin term)."""
+    axis: int
+    plane: int
+    a0: int
+    a1: int
+    b0: int
+    b1: int
+    sigma: np.ndarray = None
+    robin_d: float = 0.0
+    robin_eps: float = 0.0
+    phi0: float = 0.0
+
+
+@dataclass
 class Device:
     name: str
     x: np.ndarray
@@ -56,6 +77,8 @@ class Device:
     ionization: str = "complete"   # "complete" | "incomplete"
     donors: np.ndarray = None      # [E] float64, nm^-3 (incomplete ionization)
     acceptors: np.ndarray = None   # [E] float64, nm^-3
+    # interface-charge and Robin faces (list of Sheet)
+    sheets: list = field(default_factory=list)
 
     @property
     def nx(self):
@@ -313,3 +336,42 @@ def with_species(dev, donors_si=0.0, acceptors_si=NA_BULK_NM3, holes=True, ioniz
     na = np.where(semi, acceptors_si, 0.0).astype(np.float64)
     return replace(dev, holes=holes, ionization=ionization, donors=nd, acceptors=na,
                    net_doping=nd - na, dir_val=np.array(dev.dir_val, dtype=np.float64, copy=True))
+
+
+def with_interface_charge(dev, sigma_nm2, z_nm=SI_NM, seed=None, spread=0.0):
+    """A copy of a flat-interface stack with a surface charge on the Si/SiO2
+    interface plane z = z_nm: sigma_nm2 per face, optionally varied by a
+    seeded factor U[1 - spread, 1 + spread] per face."""
+    from dataclasses import replace
+    k = int(np.argmin(np.abs(dev.z - z_nm)))
+    if abs(dev.z[k] - z_nm) > 1e-9:
+        raise ValueError("the interface is not a mesh plane")
+    na, nb = dev.nx - 1, dev.ny - 1
+    sig = np.full(na * nb, float(sigma_nm2))
+    if spread:
+        sig *= np.random.default_rng(seed).uniform(1.0 - spread, 1.0 + spread, sig.size)
+    sh = Sheet(axis=2, plane=k, a0=0, a1=na, b0=0, b1=nb, sigma=sig)
+    return replace(dev, sheets=list(dev.sheets) + [sh])
+
+
+def with_charged_gates(dev, gates, sigma_nm2=0.0, d_nm=10.0, eps_r=EPS_OX, gate_tol=1e-9):
+    """A copy of a stack whose top gates are Robin faces instead of Dirichlet
+    nodes: each gate rectangle becomes a sheet on the top plane with its
+    voltage as phi0, a charge sigma_nm2 per face and the pinned plane d_nm
+    away through a layer of relative permittivity eps_r; its nodes become
+    free.  gates: the (name, (x0, x1, y0, y1)) list the device was built with."""
+    from dataclasses import replace
+    dir_id = dev.dir_id.copy()
+    sheets = list(dev.sheets)
+    top = dev.nz - 1
+    for gname, (x0, x1, y0, y1) in gates:
+        ii = np.nonzero((dev.x >= x0 - gate_tol) & (dev.x <= x1 + gate_tol))[0]
+        jj = np.nonzero((dev.y >= y0 - gate_tol) & (dev.y <= y1 + gate_tol))[0]
+        c = dev.contacts.index(gname)
+        J, I = np.meshgrid(jj, ii, indexing="ij")
+        dir_id[(I + dev.nx * (J + dev.ny * top)).ravel()] = -1
+        na, nb = ii[-1] - ii[0], jj[-1] - jj[0]
+        sheets.append(Sheet(axis=2, plane=top, a0=int(ii[0]), a1=int(ii[-1]), b0=int(jj[0]), b1=int(jj[-1]),
+                            sigma=np.full(na * nb, float(sigma_nm2)), robin_d=d_nm, robin_eps=eps_r,
+                            phi0=float(dev.dir_val[c])))
+    return replace(dev, dir_id=dir_id, sheets=sheets)
