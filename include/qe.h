@@ -87,7 +87,36 @@ typedef enum {
                                     Newton update in FP64 */
 } qe_precision;
 
-/* One device.  All pointers are DEVICE memory, read only. */
+/* A rectangle of mesh faces carrying a surface charge and / or a Robin
+ * condition (Sec. II.A.5).  The sheet lies in the node plane
+ * x_axis = coordinate[plane] (axis 0: x, 1: y, 2: z) and covers faces a0..a1-1
+ * along its first in-plane axis and b0..b1-1 along its second (axis 2: x then
+ * y; axis 1: x then z; axis 0: y then z); a face is the rectangle between
+ * nodes a..a+1 and b..b+1 of that plane.  It may lie inside the mesh (an
+ * interface) or on its outer boundary.  On every face f the weak form gains
+ *  - the surface-charge load KAPPA sigma_f int_f w_i (Eq. NeuBC4fc: the flux
+ *    jump across the face is q sigma_f; positive sigma = positive charge);
+ *  - with robin_d > 0, the Robin term alpha int_f (phi - phi0) w_i with
+ *    alpha = robin_eps / robin_d: the potential is pinned to phi0 on a plane
+ *    robin_d beyond the face, through a layer of relative permittivity
+ *    robin_eps (the charged-gate construction of Sec. II.A.5, d = 10 nm there).
+ * Both integrals are exact (bilinear traces on rectangles).  Rows of
+ * Dirichlet nodes are unaffected.  Sheets may share nodes and planes. */
+typedef struct {
+  int32_t axis;                  /* 0, 1 or 2 */
+  int32_t plane;                 /* node index along `axis`, in [0, n_axis) */
+  int32_t a0, a1;                /* 0 <= a0 < a1 <= n_a - 1 */
+  int32_t b0, b1;                /* 0 <= b0 < b1 <= n_b - 1 */
+  const double* sigma;           /* DEVICE [(a1-a0)*(b1-b0)], a fastest, nm^-2,
+                                    finite; NULL = no surface charge */
+  double robin_d;                /* nm, finite, >= 0; 0 = no Robin term */
+  double robin_eps;              /* > 0 when robin_d > 0 */
+  double phi0;                   /* V, finite */
+} qe_sheet;
+
+#define QE_MAX_SHEETS 16
+
+/* One device.  All pointers are DEVICE memory, read only, except `sheets`. */
 typedef struct {
   int32_t nx, ny, nz;            /* nodes per axis, each >= 2 */
   const double* x;               /* [nx] nm, strictly increasing */
@@ -107,6 +136,10 @@ typedef struct {
                                     with QE_ION_INCOMPLETE */
   const double* acceptors;       /* [E] N_A in nm^-3, likewise; NULL exactly when
                                     donors is NULL */
+  int32_t n_sheets;              /* 0 .. QE_MAX_SHEETS; not supported by
+                                    qe_solve_batch */
+  const qe_sheet* sheets;        /* HOST array [n_sheets] (its sigma arrays are
+                                    device memory); NULL when n_sheets = 0 */
 } qe_problem;
 
 typedef struct {

@@ -111,7 +111,7 @@ __device__ double b_residual(const BatchInst& I, const Charge& ch, const double*
   double acc = 0.0;
   for (int t = threadIdx.x >> 6; t < I.ntiles; t += NT / 64) {
     const WaveTile w = tile_at(I, t);
-    residual_tile<double>(I.g, w, ch, I.eps, I.semi, I.dop, I.mask, I.phi, delta, lam, I.F, I.invdiag, nullptr,
+    residual_tile<double>(I.g, w, ch, I.eps, I.semi, I.dop, I.mask, I.phi, delta, lam, nullptr, nullptr, I.F, I.invdiag, nullptr,
                           I.c, nullptr, I.cflag, I.cbits + 64L * t + (threadIdx.x & 63), nullptr, acc);
   }
   return bsum<NT>(acc, sred);
@@ -475,6 +475,8 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
   for (int i = 0; i < n_inst; ++i) {
     if ((st = check_problem(&probs[i])) != QE_OK) return fail(st, "instance %d: %s", i, qe_last_error());
     if (!phi[i]) return fail(QE_ERR_INVALID_ARG, "phi[%d] is NULL", i);
+    if (probs[i].n_sheets > 0)
+      return fail(QE_ERR_INVALID_ARG, "instance %d: interface / Robin sheets are not supported by the batch", i);
     if (ch.incomplete && !probs[i].donors)
       return fail(QE_ERR_INVALID_ARG, "instance %d: incomplete ionization needs donors and acceptors", i);
   }

@@ -278,6 +278,28 @@ __device__ __forceinline__ double jv_element(const T v[8], T sx, T sy, T sz, con
   return d;
 }
 
+// Interface-charge / Robin sheets as the kernels see them.  Node (a, b) of
+// sheet s (a in [a0, a1], b in [b0, b1]) is base + a*sa + b*sb; ca / cb are
+// the coordinates along the two in-plane axes.
+constexpr int kMaxSheets = 16;
+struct SheetDev {
+  int axis, plane;
+  int a0, a1, b0, b1;
+  long base, sa, sb;
+  const double* ca;
+  const double* cb;
+  const double* sigma;   // [(a1-a0)*(b1-b0)] or NULL
+  double alpha;          // robin_eps / robin_d, 0 = no Robin term
+  double phi0;
+};
+struct SheetSet {
+  int n;
+  int any_robin;
+  int nx, ny;
+  long start[kMaxSheets + 1];   // prefix sums of the sheets' node counts
+  SheetDev s[kMaxSheets];
+};
+
 // Per-element doping: the net N_D - N_A (complete ionization; NULL = 0, or
 // donors - acceptors when only those are given) or the two species.
 struct Doping {

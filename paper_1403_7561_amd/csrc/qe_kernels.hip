@@ -188,7 +188,8 @@ template <typename TD>
 __global__ __launch_bounds__(256) void k_residual_wave(
     Geom g, WaveMap wm, Charge ch, const double* __restrict__ eps, const uint8_t* __restrict__ semi,
     const Doping dop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
-    const TD* __restrict__ delta, double lam, double* __restrict__ F, double* __restrict__ invdiag,
+    const TD* __restrict__ delta, double lam, const double* __restrict__ fsheet,
+    const double* __restrict__ fdiag, double* __restrict__ F, double* __restrict__ invdiag,
     double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
     uint8_t* __restrict__ cflag, unsigned int* __restrict__ cbits, float* __restrict__ invdiag32,
     double* __restrict__ part) {
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(256) void k_residual_wave(
   wave_coords(wm, wx, wy, wz, active, wid);
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   double acc = 0.0;
-  residual_tile<TD>(g, w, ch, eps, semi, dop, mask, phi, delta, lam, F, invdiag, diag_out, cq, cq32, cflag,
+  residual_tile<TD>(g, w, ch, eps, semi, dop, mask, phi, delta, lam, fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag,
                     active ? cbits + 64L * wid + (threadIdx.x & 63) : nullptr, invdiag32, acc);
   const double d = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
@@ -804,15 +805,15 @@ void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* m
 
 void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
                           const uint8_t* semi, const Doping& dop, const uint8_t* mask, const double* phi,
-                          const double* delta64, const float* delta32, double lam, double* F, double* invdiag,
-                          double* diag_out, double* cq, float* cq32, uint8_t* cflag, unsigned int* cbits,
-                          float* invdiag32, double* partial, double* norm2) {
+                          const double* delta64, const float* delta32, double lam, const double* fsheet,
+                          const double* fdiag, double* F, double* invdiag, double* diag_out, double* cq, float* cq32,
+                          uint8_t* cflag, unsigned int* cbits, float* invdiag32, double* partial, double* norm2) {
   if (delta32)
-    QE_LAUNCH(k_residual_wave<float>, wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam, F,
-              invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
+    QE_LAUNCH(k_residual_wave<float>, wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam, fsheet,
+              fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
   else
-    QE_LAUNCH(k_residual_wave<double>, wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam, F,
-              invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
+    QE_LAUNCH(k_residual_wave<double>, wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam, fsheet,
+              fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
   QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, wm.nblocks, norm2);
 }
 
@@ -878,18 +879,28 @@ void launch_pcg_start32(hipStream_t s, int cgblocks, long N, double sign, const 
 void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
                        const double* eps_t, const unsigned int* cbits, const double* cq, const double* invdiag, double* x,
                        double* r, double* z, double* p, double* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
-                       double* part_rz) {
+                       double* part_rz, const SheetSet* S, const uint8_t* mask) {
   launch_cg_jv64(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, ctx, prog, part_rz, part_py);
-  QE_LAUNCH(k_cg_update<double>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, prog, part_py, wm.nblocks,
+  int n_py = wm.nblocks;
+  if (S && S->any_robin) {
+    launch_sheet_jv64(s, *S, mask, z, y, p, ctx, part_py + wm.nblocks);
+    n_py += sheet_blocks(*S);
+  }
+  QE_LAUNCH(k_cg_update<double>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, prog, part_py, n_py,
             part_rz);
 }
 
 void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
                        const float* eps_t, const unsigned int* cbits, const float* cq, const float* invdiag, float* x,
                        float* r, float* z, float* p, float* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
-                       double* part_rz) {
+                       double* part_rz, const SheetSet* S, const uint8_t* mask) {
   launch_cg_jv32(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, ctx, prog, part_rz, part_py);
-  QE_LAUNCH(k_cg_update<float>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, prog, part_py, wm.nblocks,
+  int n_py = wm.nblocks;
+  if (S && S->any_robin) {
+    launch_sheet_jv32(s, *S, mask, z, y, p, ctx, part_py + wm.nblocks);
+    n_py += sheet_blocks(*S);
+  }
+  QE_LAUNCH(k_cg_update<float>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, prog, part_py, n_py,
             part_rz);
 }
 

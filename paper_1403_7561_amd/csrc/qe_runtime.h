@@ -31,14 +31,15 @@ TileMap make_tilemap(int nx, int ny, int nz, int kz);
 
 // Byte offsets of the workspace carve-out.
 struct Layout {
-  size_t F, x, r, p, y, z, invdiag, gvec, c, cflag, rdz, cbits, mask;
+  size_t F, x, r, p, y, z, invdiag, gvec, c, cflag, rdz, cbits, mask, fsheet, fdiag;
   size_t x32, r32, p32, y32, z32, invdiag32, c32, eps32, eps_t;
   size_t partial, partial2, ctx, scal, counters, flags;
   long n_partial;
   size_t total;
 };
 Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int nblocks_tile, int vblocks,
-                   int n_dir);
+                   int n_dir, bool sheets);
+SheetSet make_sheets(const qe_problem* p);
 
 // One call's view of a problem, its workspace and its stream.
 struct Context {
@@ -46,6 +47,7 @@ struct Context {
   Geom g;
   TileMap tm;
   WaveMap wm;
+  SheetSet sheets{};
   static constexpr int kEventRing = 8;
   hipEvent_t events[kEventRing] = {};   // CG progress markers, created on first use
   ~Context() {

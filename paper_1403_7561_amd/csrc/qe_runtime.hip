@@ -185,7 +185,7 @@ static const int kCountBlocks = 256;
 static const int kContactBlocks = 256;
 
 Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int nblocks_tile, int vblocks,
-                   int n_dir) {
+                   int n_dir, bool sheets) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -207,6 +207,8 @@ Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int 
   L.rdz = take(nz_elems * 8);  // inverse z spacings
   L.cbits = take(nwaves * 64 * 4);  // per J.v lane: coefficient flags over its chunk
   L.mask = take(N);
+  L.fsheet = sheets ? take(N * 8) : 0;   // face terms of F at sheet nodes, 0 elsewhere
+  L.fdiag = sheets ? take(N * 8) : 0;
   L.x32 = take(N * 4);
   L.r32 = take(N * 4);
   L.p32 = take(N * 4);
@@ -217,6 +219,7 @@ Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int 
   L.eps32 = take(nslots * 4);
   long np = std::max<long>(nblocks_tile, 2L * vblocks);
   np = std::max<long>(np, (long)N / 64 + 64);   // wave-tiled J.v: one partial per block
+  np = std::max<long>(np, (nwaves + 3) / 4 + kSheetBlocks);   // ... then the Robin faces' partials
   np = std::max<long>(np, (long)kCountBlocks * kMaxBoxes);
   np = std::max<long>(np, (long)kContactBlocks * std::max(1, n_dir));
   L.n_partial = np;
@@ -242,7 +245,57 @@ qe_status check_problem(const qe_problem* p) {
   if (p->n_dir > 0 && !p->dir_val) return fail(QE_ERR_INVALID_ARG, "dir_val is NULL");
   if ((p->donors == nullptr) != (p->acceptors == nullptr))
     return fail(QE_ERR_INVALID_ARG, "donors and acceptors must be given together");
+  if (p->n_sheets < 0 || p->n_sheets > QE_MAX_SHEETS)
+    return fail(QE_ERR_INVALID_ARG, "n_sheets outside [0, %d]", QE_MAX_SHEETS);
+  if (p->n_sheets > 0 && !p->sheets) return fail(QE_ERR_INVALID_ARG, "sheets is NULL");
+  for (int i = 0; i < p->n_sheets; ++i) {
+    const qe_sheet& h = p->sheets[i];
+    const int n[3] = {p->nx, p->ny, p->nz};
+    if (h.axis < 0 || h.axis > 2) return fail(QE_ERR_INVALID_ARG, "sheet %d: axis must be 0, 1 or 2", i);
+    const int na = n[h.axis == 0 ? 1 : 0], nb = n[h.axis == 2 ? 1 : 2];
+    if (h.plane < 0 || h.plane >= n[h.axis]) return fail(QE_ERR_INVALID_ARG, "sheet %d: plane out of range", i);
+    if (!(0 <= h.a0 && h.a0 < h.a1 && h.a1 <= na - 1 && 0 <= h.b0 && h.b0 < h.b1 && h.b1 <= nb - 1))
+      return fail(QE_ERR_INVALID_ARG, "sheet %d: face range out of range", i);
+    if (!(h.robin_d >= 0.0 && std::isfinite(h.robin_d)) || !std::isfinite(h.phi0))
+      return fail(QE_ERR_INVALID_ARG, "sheet %d: robin_d must be finite and >= 0, phi0 finite", i);
+    if (h.robin_d > 0.0 && !(h.robin_eps > 0.0 && std::isfinite(h.robin_eps)))
+      return fail(QE_ERR_INVALID_ARG, "sheet %d: robin_eps must be > 0", i);
+  }
   return QE_OK;
+}
+
+// Kernel view of a problem's sheets (checked by check_problem).
+SheetSet make_sheets(const qe_problem* p) {
+  SheetSet S;
+  std::memset(&S, 0, sizeof(S));
+  S.n = p->n_sheets;
+  S.nx = p->nx;
+  S.ny = p->ny;
+  const long nxy = (long)p->nx * p->ny;
+  const double* c[3] = {p->x, p->y, p->z};
+  const long stride[3] = {1, p->nx, nxy};
+  for (int i = 0; i < S.n; ++i) {
+    const qe_sheet& h = p->sheets[i];
+    SheetDev& d = S.s[i];
+    const int ia = h.axis == 0 ? 1 : 0, ib = h.axis == 2 ? 1 : 2;   // in-plane axes
+    d.axis = h.axis;
+    d.plane = h.plane;
+    d.a0 = h.a0;
+    d.a1 = h.a1;
+    d.b0 = h.b0;
+    d.b1 = h.b1;
+    d.base = h.plane * stride[h.axis];
+    d.sa = stride[ia];
+    d.sb = stride[ib];
+    d.ca = c[ia];
+    d.cb = c[ib];
+    d.sigma = h.sigma;
+    d.alpha = h.robin_d > 0.0 ? h.robin_eps / h.robin_d : 0.0;
+    d.phi0 = h.phi0;
+    S.any_robin |= d.alpha != 0.0;
+    S.start[i + 1] = S.start[i] + (long)(h.a1 - h.a0 + 1) * (h.b1 - h.b0 + 1);
+  }
+  return S;
 }
 
 qe_status check_options(const qe_options* o) {
@@ -306,7 +359,7 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
   vblocks = vec_blocks(N);
   nslots = tile_slots(p->nx, p->ny, p->nz);
-  lay = make_layout(N, E, nslots, p->nz - 1, wm.nwaves, tm.nblocks, vblocks, p->n_dir);
+  lay = make_layout(N, E, nslots, p->nz - 1, wm.nwaves, tm.nblocks, vblocks, p->n_dir, p->n_sheets > 0);
   if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (ws_bytes < lay.total)
@@ -334,6 +387,11 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   }
   g.rdz = f64(lay.rdz);
   launch_stage_rdz(s, p->nz, p->z, f64(lay.rdz));
+  sheets = make_sheets(p);
+  if (sheets.n > 0) {
+    QE_HIP(hipMemsetAsync(ws + lay.fsheet, 0, N * sizeof(double), s));
+    QE_HIP(hipMemsetAsync(ws + lay.fdiag, 0, N * sizeof(double), s));
+  }
   // reset device scalars and reduction counters
   QE_HIP(hipMemsetAsync(ws + lay.ctx, 0, sizeof(PcgCtx), s));
   QE_HIP(hipMemsetAsync(ws + lay.counters, 0, 16 * sizeof(unsigned int), s));
@@ -350,6 +408,7 @@ Doping Context::doping() const {
 qe_status Context::validate(const double* phi) {
   int* dflags = reinterpret_cast<int*>(ws + lay.flags);
   launch_validate(s, vblocks, N, E, prob.n_dir, prob.eps_r, doping(), prob.dir_id, phi, dflags);
+  if (sheets.n > 0) launch_validate_sheets(s, sheets, dflags);
   QE_HIP(hipGetLastError());
   QE_HIP(hipMemcpyAsync(mirror().flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
   QE_HIP(hipStreamSynchronize(s));
@@ -358,6 +417,7 @@ qe_status Context::validate(const double* phi) {
   if (f & 2) return fail(QE_ERR_NONFINITE, "net_doping not finite or donors / acceptors not finite and >= 0");
   if (f & 4) return fail(QE_ERR_INVALID_ARG, "dir_id outside [-1, n_dir)");
   if (f & 8) return fail(QE_ERR_NONFINITE, "phi not finite");
+  if (f & 16) return fail(QE_ERR_NONFINITE, "sheet sigma not finite");
   return QE_OK;
 }
 
@@ -370,8 +430,10 @@ qe_status Context::stage(double* phi, int apply, int zero_free) {
 
 qe_status Context::residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam,
                             bool mixed, double* diag_out, double* norm2_host) {
+  const bool sh = sheets.n > 0;
+  if (sh) launch_sheet_residual(s, sheets, ch.kappa, u8(lay.mask), phi, d64, d32, lam, f64(lay.fsheet), f64(lay.fdiag));
   launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, doping(), u8(lay.mask), phi, d64, d32, lam,
-                       f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
+                       sh ? f64(lay.fsheet) : nullptr, sh ? f64(lay.fdiag) : nullptr, f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
                        u8(lay.cflag), u32(lay.cbits), mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial),
                        f64(lay.scal));
   QE_HIP(hipGetLastError());
@@ -403,11 +465,11 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
     if (mixed)
       launch_pcg_iter32(s, g, wm, cgb, N, k & 1, f32(lay.eps32), u32(lay.cbits), f32(lay.c32), f32(lay.invdiag32),
                         f32(lay.x32), f32(lay.r32), f32(lay.z32), f32(lay.p32), f32(lay.y32), dctx, hm.prog_dev,
-                        f64(lay.partial), f64(lay.partial2));
+                        f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, u8(lay.mask));
     else
       launch_pcg_iter64(s, g, wm, cgb, N, k & 1, f64(lay.eps_t), u32(lay.cbits), f64(lay.c), f64(lay.invdiag),
                         f64(lay.x), f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, hm.prog_dev,
-                        f64(lay.partial), f64(lay.partial2));
+                        f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, u8(lay.mask));
   };
   // The host keeps `ahead` iterations queued beyond those it knows have
   // finished (an event is recorded after every kEv-th iteration), so the
@@ -516,7 +578,7 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
   TileMap tm = make_tilemap(p->nx, p->ny, p->nz, 1);
   const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
   return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), p->nz - 1, wm.nwaves, tm.nblocks, vec_blocks(N),
-                     p->n_dir).total;
+                     p->n_dir, p->n_sheets > 0).total;
 }
 
 const char* qe_last_error(void) { return g_last_error.c_str(); }
@@ -664,6 +726,7 @@ qe_status qe_jv(const qe_problem* p, const qe_physics* ph, const double* phi, co
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, false, nullptr, nullptr));
   launch_jv_wave64(cx.s, cx.g, cx.wm, cx.f64(cx.lay.eps_t), cx.u32(cx.lay.cbits), cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v,
                    y, 1);
+  if (cx.sheets.any_robin) launch_sheet_jv64(cx.s, cx.sheets, cx.u8(cx.lay.mask), v, y, nullptr, nullptr, nullptr);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -683,6 +746,7 @@ qe_status qe_jv_f32(const qe_problem* p, const qe_physics* ph, const double* phi
   launch_stage_eps32(cx.s, cx.vblocks, cx.g, p->eps_r, cx.f32(cx.lay.eps32), cx.nslots);
   launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), cx.u32(cx.lay.cbits), cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v,
                    y, 1);
+  if (cx.sheets.any_robin) launch_sheet_jv32(cx.s, cx.sheets, cx.u8(cx.lay.mask), v, y, nullptr, nullptr, nullptr);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -846,6 +910,7 @@ qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options
   double* deps_buf = dQ_deps ? dQ_deps : cx.f64(cx.lay.y);
   launch_adj_grad(cx.s, cx.g, cx.tm, p->eps_r, cx.u8(cx.lay.cflag), cx.f64(cx.lay.c), cx.u8(cx.lay.mask), cx.f64(cx.lay.x), phi,
                   cx.f64(cx.lay.gvec), deps_buf, cx.f64(cx.lay.r));
+  if (cx.sheets.any_robin) launch_sheet_contact(cx.s, cx.sheets, cx.u8(cx.lay.mask), cx.f64(cx.lay.x), cx.f64(cx.lay.r));
   if (p->n_dir > 0)
     launch_contact_sum(cx.s, kContactBlocks, cx.N, p->n_dir, p->dir_id, cx.f64(cx.lay.r), cx.f64(cx.lay.partial),
                        counters + 3, cx.f64(cx.lay.scal) + 8);

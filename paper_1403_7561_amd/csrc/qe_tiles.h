@@ -320,7 +320,9 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
                                               const double* __restrict__ eps, const uint8_t* __restrict__ semi,
                                               const Doping dop, const uint8_t* __restrict__ mask,
                                               const double* __restrict__ phi, const TD* __restrict__ delta,
-                                              double lam, double* __restrict__ F, double* __restrict__ invdiag,
+                                              double lam, const double* __restrict__ fsheet,
+                                              const double* __restrict__ fdiag, double* __restrict__ F,
+                                              double* __restrict__ invdiag,
                                               double* __restrict__ diag_out, double* __restrict__ cq,
                                               float* __restrict__ cq32, uint8_t* __restrict__ cflag,
                                               unsigned int* __restrict__ cbits, float* __restrict__ invdiag32,
@@ -415,6 +417,9 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
       if (dir) {
         f = 0.0;
         d = 1.0;
+      } else if (fsheet) {
+        f += fsheet[n];   // interface-charge / Robin face terms
+        d += fdiag[n];
       }
       F[n] = f;
       const double id = dir ? 0.0 : 1.0 / d;  // 0 keeps CG vectors at 0 on Dirichlet rows

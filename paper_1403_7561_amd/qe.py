@@ -47,13 +47,21 @@ class QeError(RuntimeError):
         self.report = report
 
 
+class CSheet(ctypes.Structure):
+    _fields_ = [("axis", ctypes.c_int32), ("plane", ctypes.c_int32), ("a0", ctypes.c_int32),
+                ("a1", ctypes.c_int32), ("b0", ctypes.c_int32), ("b1", ctypes.c_int32),
+                ("sigma", ctypes.c_void_p), ("robin_d", ctypes.c_double), ("robin_eps", ctypes.c_double),
+                ("phi0", ctypes.c_double)]
+
+
 class CProblem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("eps_r", ctypes.c_void_p), ("semi", ctypes.c_void_p),
                 ("net_doping", ctypes.c_void_p), ("dir_id", ctypes.c_void_p),
                 ("dir_val", ctypes.c_void_p), ("n_dir", ctypes.c_int32),
-                ("donors", ctypes.c_void_p), ("acceptors", ctypes.c_void_p)]
+                ("donors", ctypes.c_void_p), ("acceptors", ctypes.c_void_p),
+                ("n_sheets", ctypes.c_int32), ("sheets", ctypes.POINTER(CSheet))]
 
 
 class CPhysics(ctypes.Structure):
@@ -202,6 +210,18 @@ class Problem:
         self.donors = None if nd is None else torch.as_tensor(np.ascontiguousarray(nd, dtype=np.float64), **f64)
         self.acceptors = None if na is None else torch.as_tensor(np.ascontiguousarray(na, dtype=np.float64), **f64)
         self.physics = Physics.of(dev) if hasattr(dev, "stat") else Physics()
+        # interface-charge / Robin sheets: host descriptors, sigma on the device
+        sheets = list(getattr(dev, "sheets", None) or [])
+        self.sheet_sigma = [None if sh.sigma is None else
+                            torch.as_tensor(np.ascontiguousarray(sh.sigma, dtype=np.float64), **f64)
+                            for sh in sheets]
+        self.c_sheets = (CSheet * max(len(sheets), 1))()
+        for i, sh in enumerate(sheets):
+            sg = self.sheet_sigma[i]
+            self.c_sheets[i] = CSheet(int(sh.axis), int(sh.plane), int(sh.a0), int(sh.a1), int(sh.b0), int(sh.b1),
+                                      sg.data_ptr() if sg is not None else None, float(sh.robin_d),
+                                      float(sh.robin_eps), float(sh.phi0))
+        self.n_sheets = len(sheets)
         self.device = device
 
     def c(self):
@@ -211,7 +231,8 @@ class Problem:
                         self.dir_id.data_ptr(),
                         self.dir_val.data_ptr(), self.n_dir,
                         self.donors.data_ptr() if self.donors is not None else None,
-                        self.acceptors.data_ptr() if self.acceptors is not None else None)
+                        self.acceptors.data_ptr() if self.acceptors is not None else None,
+                        self.n_sheets, self.c_sheets if self.n_sheets else None)
 
 
 class Workspace:

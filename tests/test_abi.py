@@ -202,3 +202,40 @@ def test_ohmic_potential_argument_checks():
         st = lib.qe_ohmic_potential(ctypes.byref(ph), nd, na, 0.0, ctypes.byref(out))
         assert st == -1 and needle in qe.qe_last_error(), (needle, qe.qe_last_error())
     assert lib.qe_ohmic_potential(None, 1e-3, 0.0, 0.0, ctypes.byref(out)) == -1
+
+
+@pytest.mark.parametrize("sheet,needle", [
+    (dict(axis=3), "axis"),
+    (dict(plane=2), "plane out of range"),          # nz = 2 for axis 2
+    (dict(a0=1, a1=1), "face range"),
+    (dict(a1=4), "face range"),                      # nx - 1 = 3 faces
+    (dict(b1=3), "face range"),                      # ny - 1 = 2 faces
+    (dict(robin_d=-1.0), "robin_d"),
+    (dict(robin_d=10.0, robin_eps=0.0), "robin_eps"),
+    (dict(phi0=float("nan")), "phi0"),
+])
+def test_invalid_sheet_rejected(sheet, needle):
+    lib = qe.load_library()
+    p = fake_problem()
+    f = dict(axis=2, plane=1, a0=0, a1=3, b0=0, b1=2, sigma=None, robin_d=0.0, robin_eps=0.0, phi0=0.0)
+    f.update(sheet)
+    arr = (qe.CSheet * 1)(qe.CSheet(**f))
+    p.n_sheets = 1
+    p.sheets = arr
+    o = qe.qe_default_options()
+    ph = qe.CPhysics(2, 4.0, 1.08, 0.56)
+    st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                      None, ctypes.c_void_p(256), 1 << 40, None, None)
+    assert st == -1 and needle in qe.qe_last_error(), qe.qe_last_error()
+
+
+def test_sheet_count_checks():
+    lib = qe.load_library()
+    o = qe.qe_default_options()
+    ph = qe.CPhysics(2, 4.0, 1.08, 0.56)
+    for n, needle in ((17, "n_sheets"), (-1, "n_sheets"), (1, "sheets is NULL")):
+        p = fake_problem()
+        p.n_sheets = n
+        st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                          None, ctypes.c_void_p(256), 1 << 40, None, None)
+        assert st == -1 and needle in qe.qe_last_error()
