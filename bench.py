@@ -113,6 +113,28 @@ def full_charge_run(synth, qe, torch, dev, opts, ws, boxes, jv_reps):
             "jv": {"ms": ms64, "coef_elems": ncoef, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}}
 
 
+def sheets_run(synth, qe, torch, dev, opts, ws, boxes):
+    """The same stack with a fixed charge of 1e11 cm^-2 (+-50 %, seeded) on the
+    Si/SiO2 interface and the two plungers as charged gates (Robin faces,
+    d = 10 nm through oxide, -2e11 cm^-2 trapped charge).  One warm-up and two
+    timed solves."""
+    sdev = synth.with_interface_charge(dev, 1e-3, seed=7563, spread=0.5)
+    sdev = synth.with_charged_gates(sdev, synth.double_dot_gates()[:2], sigma_nm2=-2e-3)
+    P = qe.Problem(sdev)
+    wsz = qe.workspace_for(P, opts)
+    qe.qe_solve(P, opts=opts, ws=wsz, want_density=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        ph, _, rep = qe.qe_solve(P, opts=opts, ws=wsz, want_density=True)
+        c = qe.qe_count_electrons(P, ph, boxes, ws=wsz)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 2
+    return {"solves_per_s": 1.0 / dt, "ms": dt * 1e3, "newton_iters": rep["newton_iters"],
+            "krylov_iters": rep["krylov_iters"], "res_final": rep["res_final"],
+            "dot_electrons": [float(x) for x in c], "n_sheets": len(sdev.sheets)}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -128,6 +150,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-full-charge", action="store_true")
+    ap.add_argument("--no-sheets", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -268,6 +291,9 @@ def main():
     if not args.no_full_charge:
         log("full space charge on the same stack")
         out["full_charge_c2"] = full_charge_run(synth, qe, torch, dev, opts, ws, boxes, args.jv_reps)
+    if not args.no_sheets:
+        log("interface charge and charged plunger gates on the same stack")
+        out["sheets_c2"] = sheets_run(synth, qe, torch, dev, opts, ws, boxes)
     log("cpu baseline")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dev, reps[-1]["newton_iters"])

@@ -280,7 +280,10 @@ __device__ __forceinline__ double jv_element(const T v[8], T sx, T sy, T sz, con
 
 // Interface-charge / Robin sheets as the kernels see them.  Node (a, b) of
 // sheet s (a in [a0, a1], b in [b0, b1]) is base + a*sa + b*sb; ca / cb are
-// the coordinates along the two in-plane axes.
+// the coordinates along the two in-plane axes.  The kernels work on a list of
+// the distinct sheet nodes (int4: node, sheet | shared << 8, a, b), where
+// `sheet` is the first sheet containing the node and `shared` says that a
+// later one does too.
 constexpr int kMaxSheets = 16;
 struct SheetDev {
   int axis, plane;
@@ -295,8 +298,7 @@ struct SheetDev {
 struct SheetSet {
   int n;
   int any_robin;
-  int nx, ny;
-  long start[kMaxSheets + 1];   // prefix sums of the sheets' node counts
+  int n_items;   // distinct sheet nodes (work items)
   SheetDev s[kMaxSheets];
 };
 

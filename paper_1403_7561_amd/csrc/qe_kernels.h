@@ -96,27 +96,29 @@ void launch_pcg_start32(hipStream_t s, int cgblocks, long N, double sign, const 
 void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
                        const double* eps_t, const unsigned int* cbits, const double* cq, const double* invdiag, double* x,
                        double* r, double* z, double* p, double* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
-                       double* part_rz, const SheetSet* S, const uint8_t* mask);
+                       double* part_rz, const SheetSet* S, const int4* items, const uint8_t* mask);
 void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
                        const float* eps_t, const unsigned int* cbits, const float* cq, const float* invdiag, float* x,
                        float* r, float* z, float* p, float* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
-                       double* part_rz, const SheetSet* S, const uint8_t* mask);
+                       double* part_rz, const SheetSet* S, const int4* items, const uint8_t* mask);
 
 // ---- interface-charge / Robin sheets (qe_sheets.hip)
 constexpr int kSheetBlocks = 256;
 int sheet_blocks(const SheetSet& S);
 // fsheet[n] = face terms of F(phi + lam delta) at free sheet nodes, fdiag[n]
 // their Jacobian diagonal (other entries untouched).
-void launch_sheet_residual(hipStream_t s, const SheetSet& S, double kappa, const uint8_t* mask, const double* phi,
-                           const double* delta64, const float* delta32, double lam, double* fsheet, double* fdiag);
+void launch_sheet_residual(hipStream_t s, const SheetSet& S, const int4* items, double kappa, const uint8_t* mask,
+                           const double* phi, const double* delta64, const float* delta32, double lam, double* fsheet,
+                           double* fdiag);
 // y += R v on free sheet nodes (v masked); with ctx, skipped once the CG has
 // stopped and one p^T R v partial per block into part.
-void launch_sheet_jv64(hipStream_t s, const SheetSet& S, const uint8_t* mask, const double* v, double* y,
-                       const double* p, const PcgCtx* ctx, double* part);
-void launch_sheet_jv32(hipStream_t s, const SheetSet& S, const uint8_t* mask, const float* v, float* y,
-                       const float* p, const PcgCtx* ctx, double* part);
+void launch_sheet_jv64(hipStream_t s, const SheetSet& S, const int4* items, const uint8_t* mask, const double* v,
+                       double* y, const double* p, const PcgCtx* ctx, double* part);
+void launch_sheet_jv32(hipStream_t s, const SheetSet& S, const int4* items, const uint8_t* mask, const float* v,
+                       float* y, const float* p, const PcgCtx* ctx, double* part);
 // tcon -= R lam on Dirichlet sheet nodes (the adjoint's contact terms).
-void launch_sheet_contact(hipStream_t s, const SheetSet& S, const uint8_t* mask, const double* lam, double* tcon);
+void launch_sheet_contact(hipStream_t s, const SheetSet& S, const int4* items, const uint8_t* mask, const double* lam,
+                          double* tcon);
 void launch_validate_sheets(hipStream_t s, const SheetSet& S, int* flags);
 
 }  // namespace qe

@@ -879,11 +879,11 @@ void launch_pcg_start32(hipStream_t s, int cgblocks, long N, double sign, const 
 void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
                        const double* eps_t, const unsigned int* cbits, const double* cq, const double* invdiag, double* x,
                        double* r, double* z, double* p, double* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
-                       double* part_rz, const SheetSet* S, const uint8_t* mask) {
+                       double* part_rz, const SheetSet* S, const int4* items, const uint8_t* mask) {
   launch_cg_jv64(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, ctx, prog, part_rz, part_py);
   int n_py = wm.nblocks;
   if (S && S->any_robin) {
-    launch_sheet_jv64(s, *S, mask, z, y, p, ctx, part_py + wm.nblocks);
+    launch_sheet_jv64(s, *S, items, mask, z, y, p, ctx, part_py + wm.nblocks);
     n_py += sheet_blocks(*S);
   }
   QE_LAUNCH(k_cg_update<double>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, prog, part_py, n_py,
@@ -893,11 +893,11 @@ void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgbl
 void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, long N, int k,
                        const float* eps_t, const unsigned int* cbits, const float* cq, const float* invdiag, float* x,
                        float* r, float* z, float* p, float* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
-                       double* part_rz, const SheetSet* S, const uint8_t* mask) {
+                       double* part_rz, const SheetSet* S, const int4* items, const uint8_t* mask) {
   launch_cg_jv32(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, ctx, prog, part_rz, part_py);
   int n_py = wm.nblocks;
   if (S && S->any_robin) {
-    launch_sheet_jv32(s, *S, mask, z, y, p, ctx, part_py + wm.nblocks);
+    launch_sheet_jv32(s, *S, items, mask, z, y, p, ctx, part_py + wm.nblocks);
     n_py += sheet_blocks(*S);
   }
   QE_LAUNCH(k_cg_update<float>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, prog, part_py, n_py,

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "../../include/qe.h"
 #include "qe_kernels.h"
 
@@ -31,15 +33,16 @@ TileMap make_tilemap(int nx, int ny, int nz, int kz);
 
 // Byte offsets of the workspace carve-out.
 struct Layout {
-  size_t F, x, r, p, y, z, invdiag, gvec, c, cflag, rdz, cbits, mask, fsheet, fdiag;
+  size_t F, x, r, p, y, z, invdiag, gvec, c, cflag, rdz, cbits, mask, fsheet, fdiag, sheet_items;
   size_t x32, r32, p32, y32, z32, invdiag32, c32, eps32, eps_t;
   size_t partial, partial2, ctx, scal, counters, flags;
   long n_partial;
   size_t total;
 };
 Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int nblocks_tile, int vblocks,
-                   int n_dir, bool sheets);
-SheetSet make_sheets(const qe_problem* p);
+                   int n_dir, long sheet_slots);
+long sheet_slots(const qe_problem* p);
+SheetSet make_sheets(const qe_problem* p, std::vector<int4>& items);
 
 // One call's view of a problem, its workspace and its stream.
 struct Context {
@@ -64,6 +67,7 @@ struct Context {
   float* f32(size_t off) const { return reinterpret_cast<float*>(ws + off); }
   uint8_t* u8(size_t off) const { return reinterpret_cast<uint8_t*>(ws + off); }
   unsigned int* u32(size_t off) const { return reinterpret_cast<unsigned int*>(ws + off); }
+  const int4* sheet_items() const { return reinterpret_cast<const int4*>(ws + lay.sheet_items); }
 
   qe_status init(const qe_problem* p, const Charge& ch, void* ws, size_t ws_bytes, void* stream, int kz = 0);
   Doping doping() const;

@@ -185,7 +185,7 @@ static const int kCountBlocks = 256;
 static const int kContactBlocks = 256;
 
 Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int nblocks_tile, int vblocks,
-                   int n_dir, bool sheets) {
+                   int n_dir, long sheet_slots) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -207,8 +207,9 @@ Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int 
   L.rdz = take(nz_elems * 8);  // inverse z spacings
   L.cbits = take(nwaves * 64 * 4);  // per J.v lane: coefficient flags over its chunk
   L.mask = take(N);
-  L.fsheet = sheets ? take(N * 8) : 0;   // face terms of F at sheet nodes, 0 elsewhere
-  L.fdiag = sheets ? take(N * 8) : 0;
+  L.fsheet = sheet_slots ? take(N * 8) : 0;   // face terms of F at sheet nodes, 0 elsewhere
+  L.fdiag = sheet_slots ? take(N * 8) : 0;
+  L.sheet_items = sheet_slots ? take(sheet_slots * 16) : 0;   // int4 per distinct sheet node
   L.x32 = take(N * 4);
   L.r32 = take(N * 4);
   L.p32 = take(N * 4);
@@ -264,13 +265,21 @@ qe_status check_problem(const qe_problem* p) {
   return QE_OK;
 }
 
-// Kernel view of a problem's sheets (checked by check_problem).
-SheetSet make_sheets(const qe_problem* p) {
+// Nodes of all sheets counted with multiplicity (an upper bound of the
+// distinct ones).
+long sheet_slots(const qe_problem* p) {
+  long n = 0;
+  for (int i = 0; i < p->n_sheets; ++i)
+    n += (long)(p->sheets[i].a1 - p->sheets[i].a0 + 1) * (p->sheets[i].b1 - p->sheets[i].b0 + 1);
+  return n;
+}
+
+// Kernel view of a problem's sheets (checked by check_problem) and the list
+// of their distinct nodes: index bookkeeping only, from the sheets' ranges.
+SheetSet make_sheets(const qe_problem* p, std::vector<int4>& items) {
   SheetSet S;
   std::memset(&S, 0, sizeof(S));
   S.n = p->n_sheets;
-  S.nx = p->nx;
-  S.ny = p->ny;
   const long nxy = (long)p->nx * p->ny;
   const double* c[3] = {p->x, p->y, p->z};
   const long stride[3] = {1, p->nx, nxy};
@@ -293,8 +302,35 @@ SheetSet make_sheets(const qe_problem* p) {
     d.alpha = h.robin_d > 0.0 ? h.robin_eps / h.robin_d : 0.0;
     d.phi0 = h.phi0;
     S.any_robin |= d.alpha != 0.0;
-    S.start[i + 1] = S.start[i] + (long)(h.a1 - h.a0 + 1) * (h.b1 - h.b0 + 1);
   }
+  // a node belongs to sheet t when it lies in t's plane inside t's node range
+  auto contains = [&](int t, int ijk[3]) {
+    const qe_sheet& h = p->sheets[t];
+    const int ia = h.axis == 0 ? 1 : 0, ib = h.axis == 2 ? 1 : 2;
+    return ijk[h.axis] == h.plane && ijk[ia] >= h.a0 && ijk[ia] <= h.a1 && ijk[ib] >= h.b0 && ijk[ib] <= h.b1;
+  };
+  items.clear();
+  for (int i = 0; i < S.n; ++i) {
+    const qe_sheet& h = p->sheets[i];
+    const int ia = h.axis == 0 ? 1 : 0, ib = h.axis == 2 ? 1 : 2;
+    for (int b = h.b0; b <= h.b1; ++b)
+      for (int a = h.a0; a <= h.a1; ++a) {
+        int ijk[3];
+        ijk[h.axis] = h.plane;
+        ijk[ia] = a;
+        ijk[ib] = b;
+        bool first = true, shared = false;
+        for (int t = 0; t < S.n && first; ++t)
+          if (t != i && contains(t, ijk)) {
+            if (t < i) first = false;
+            else shared = true;
+          }
+        if (!first) continue;
+        const long n = ijk[0] + p->nx * ((long)ijk[1] + (long)p->ny * ijk[2]);
+        items.push_back(make_int4((int)n, i | (shared ? 256 : 0), a, b));
+      }
+  }
+  S.n_items = (int)items.size();
   return S;
 }
 
@@ -359,7 +395,7 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
   vblocks = vec_blocks(N);
   nslots = tile_slots(p->nx, p->ny, p->nz);
-  lay = make_layout(N, E, nslots, p->nz - 1, wm.nwaves, tm.nblocks, vblocks, p->n_dir, p->n_sheets > 0);
+  lay = make_layout(N, E, nslots, p->nz - 1, wm.nwaves, tm.nblocks, vblocks, p->n_dir, sheet_slots(p));
   if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (ws_bytes < lay.total)
@@ -387,10 +423,13 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   }
   g.rdz = f64(lay.rdz);
   launch_stage_rdz(s, p->nz, p->z, f64(lay.rdz));
-  sheets = make_sheets(p);
+  std::vector<int4> items;
+  sheets = make_sheets(p, items);
   if (sheets.n > 0) {
     QE_HIP(hipMemsetAsync(ws + lay.fsheet, 0, N * sizeof(double), s));
     QE_HIP(hipMemsetAsync(ws + lay.fdiag, 0, N * sizeof(double), s));
+    QE_HIP(hipMemcpyAsync(ws + lay.sheet_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    QE_HIP(hipStreamSynchronize(s));   // `items` is a host temporary
   }
   // reset device scalars and reduction counters
   QE_HIP(hipMemsetAsync(ws + lay.ctx, 0, sizeof(PcgCtx), s));
@@ -431,7 +470,7 @@ qe_status Context::stage(double* phi, int apply, int zero_free) {
 qe_status Context::residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam,
                             bool mixed, double* diag_out, double* norm2_host) {
   const bool sh = sheets.n > 0;
-  if (sh) launch_sheet_residual(s, sheets, ch.kappa, u8(lay.mask), phi, d64, d32, lam, f64(lay.fsheet), f64(lay.fdiag));
+  if (sh) launch_sheet_residual(s, sheets, sheet_items(), ch.kappa, u8(lay.mask), phi, d64, d32, lam, f64(lay.fsheet), f64(lay.fdiag));
   launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, doping(), u8(lay.mask), phi, d64, d32, lam,
                        sh ? f64(lay.fsheet) : nullptr, sh ? f64(lay.fdiag) : nullptr, f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
                        u8(lay.cflag), u32(lay.cbits), mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial),
@@ -465,11 +504,11 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
     if (mixed)
       launch_pcg_iter32(s, g, wm, cgb, N, k & 1, f32(lay.eps32), u32(lay.cbits), f32(lay.c32), f32(lay.invdiag32),
                         f32(lay.x32), f32(lay.r32), f32(lay.z32), f32(lay.p32), f32(lay.y32), dctx, hm.prog_dev,
-                        f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, u8(lay.mask));
+                        f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
     else
       launch_pcg_iter64(s, g, wm, cgb, N, k & 1, f64(lay.eps_t), u32(lay.cbits), f64(lay.c), f64(lay.invdiag),
                         f64(lay.x), f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, hm.prog_dev,
-                        f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, u8(lay.mask));
+                        f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
   };
   // The host keeps `ahead` iterations queued beyond those it knows have
   // finished (an event is recorded after every kEv-th iteration), so the
@@ -578,7 +617,7 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
   TileMap tm = make_tilemap(p->nx, p->ny, p->nz, 1);
   const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
   return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), p->nz - 1, wm.nwaves, tm.nblocks, vec_blocks(N),
-                     p->n_dir, p->n_sheets > 0).total;
+                     p->n_dir, sheet_slots(p)).total;
 }
 
 const char* qe_last_error(void) { return g_last_error.c_str(); }
@@ -726,7 +765,7 @@ qe_status qe_jv(const qe_problem* p, const qe_physics* ph, const double* phi, co
   QE_TRY(cx.residual(ch, phi, nullptr, nullptr, 0.0, false, nullptr, nullptr));
   launch_jv_wave64(cx.s, cx.g, cx.wm, cx.f64(cx.lay.eps_t), cx.u32(cx.lay.cbits), cx.f64(cx.lay.c), cx.u8(cx.lay.mask), v,
                    y, 1);
-  if (cx.sheets.any_robin) launch_sheet_jv64(cx.s, cx.sheets, cx.u8(cx.lay.mask), v, y, nullptr, nullptr, nullptr);
+  if (cx.sheets.any_robin) launch_sheet_jv64(cx.s, cx.sheets, cx.sheet_items(), cx.u8(cx.lay.mask), v, y, nullptr, nullptr, nullptr);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -746,7 +785,7 @@ qe_status qe_jv_f32(const qe_problem* p, const qe_physics* ph, const double* phi
   launch_stage_eps32(cx.s, cx.vblocks, cx.g, p->eps_r, cx.f32(cx.lay.eps32), cx.nslots);
   launch_jv_wave32(cx.s, cx.g, cx.wm, cx.f32(cx.lay.eps32), cx.u32(cx.lay.cbits), cx.f32(cx.lay.c32), cx.u8(cx.lay.mask), v,
                    y, 1);
-  if (cx.sheets.any_robin) launch_sheet_jv32(cx.s, cx.sheets, cx.u8(cx.lay.mask), v, y, nullptr, nullptr, nullptr);
+  if (cx.sheets.any_robin) launch_sheet_jv32(cx.s, cx.sheets, cx.sheet_items(), cx.u8(cx.lay.mask), v, y, nullptr, nullptr, nullptr);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -910,7 +949,7 @@ qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options
   double* deps_buf = dQ_deps ? dQ_deps : cx.f64(cx.lay.y);
   launch_adj_grad(cx.s, cx.g, cx.tm, p->eps_r, cx.u8(cx.lay.cflag), cx.f64(cx.lay.c), cx.u8(cx.lay.mask), cx.f64(cx.lay.x), phi,
                   cx.f64(cx.lay.gvec), deps_buf, cx.f64(cx.lay.r));
-  if (cx.sheets.any_robin) launch_sheet_contact(cx.s, cx.sheets, cx.u8(cx.lay.mask), cx.f64(cx.lay.x), cx.f64(cx.lay.r));
+  if (cx.sheets.any_robin) launch_sheet_contact(cx.s, cx.sheets, cx.sheet_items(), cx.u8(cx.lay.mask), cx.f64(cx.lay.x), cx.f64(cx.lay.r));
   if (p->n_dir > 0)
     launch_contact_sum(cx.s, kContactBlocks, cx.N, p->n_dir, p->dir_id, cx.f64(cx.lay.r), cx.f64(cx.lay.partial),
                        counters + 3, cx.f64(cx.lay.scal) + 8);
