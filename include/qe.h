@@ -116,7 +116,32 @@ typedef struct {
 
 #define QE_MAX_SHEETS 16
 
-/* One device.  All pointers are DEVICE memory, read only, except `sheets`. */
+/* Eigenstates of an earlier outer Schrodinger-Poisson iteration k, for the
+ * predictor step of the predictor-corrector method (Eq. pcPoisson): the
+ * electron density becomes
+ *   n~(phi) = sum_i P |psi_i|^2 G((E_F - E_i + (phi - phi^(k))) / kT)
+ * with 3D confinement (Eq. ApproxEDens3DConfined) P = 4, G(x) = 1/(1 + e^-x)
+ * -- the printed minus sign in front of q(phi - phi^(k)) in its exponent --
+ * and with 1D confinement (Eq. ApproxEDens1DConfined)
+ * P = 2 m_t kT / (pi hbar^2), G(x) = ln(1 + e^x).  |psi_i|^2 and phi^(k) are
+ * nodal fields interpolated to the Gauss points like phi.  n~ replaces the
+ * electron statistics everywhere (holes and dopants stay as qe_physics says);
+ * T_K > 0 is needed.  Supported by qe_solve, qe_residual, qe_jv, qe_jv_f32,
+ * qe_density and qe_count_electrons (which then report n~); qe_adjoint and
+ * qe_solve_batch reject it. */
+#define QE_MAX_STATES 32
+typedef struct {
+  int32_t n_states;              /* 1 .. QE_MAX_STATES */
+  int32_t confinement;           /* 3 or 1 */
+  const double* psi2;            /* DEVICE [n_states][N] nodal |psi_i^(k)|^2, finite,
+                                    >= 0 (nm^-3 for 3D, nm^-1 for 1D) */
+  const double* phi_k;           /* DEVICE [N] the potential phi^(k), V */
+  const double* E_i;             /* HOST [n_states] levels E_i^(k) - E_F, eV, finite */
+  double m_t;                    /* transverse mass / m0, > 0 (1D form) */
+} qe_quantum;
+
+/* One device.  All pointers are DEVICE memory, read only, except `sheets`
+ * and `quantum`. */
 typedef struct {
   int32_t nx, ny, nz;            /* nodes per axis, each >= 2 */
   const double* x;               /* [nx] nm, strictly increasing */
@@ -140,6 +165,7 @@ typedef struct {
                                     qe_solve_batch */
   const qe_sheet* sheets;        /* HOST array [n_sheets] (its sigma arrays are
                                     device memory); NULL when n_sheets = 0 */
+  const qe_quantum* quantum;     /* HOST, or NULL: electrons from the statistics */
 } qe_problem;
 
 typedef struct {

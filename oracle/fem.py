@@ -20,6 +20,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .physics import KAPPA
+from .quantum import QuantumDensity
 
 # 1D linear-element pieces on a unit interval: stiffness and mass.
 _A1 = np.array([[1.0, -1.0], [-1.0, 1.0]])
@@ -198,6 +199,10 @@ class Problem:
         self.sheets = list(getattr(dev, "sheets", None) or [])
         self.R, self.sheet_load = sheet_terms(m, self.sheets)
         self.K_lin = self.K + self.R      # the phi-linear part of F
+        # predictor-corrector electrons from given eigenstates (replace n(phi))
+        q = getattr(dev, "quantum", None)
+        self.quantum = None if q is None else QuantumDensity(q.psi2, q.phi_k, q.E_i, stats.T_K, q.confinement,
+                                                             q.m_t)
 
     # --- nodal vectors -------------------------------------------------
     def with_dirichlet(self, phi):
@@ -214,7 +219,10 @@ class Problem:
         phq = m.at_gauss(phi)
         nd = None if self.nd is None else self.nd[:, None]
         na = None if self.na is None else self.na[:, None]
-        rho = st.rho(phq, self.netdop[:, None], nd, na)
+        nq = None
+        if self.quantum is not None and stats is None:
+            nq, _ = self.quantum.at_gauss(m, phi)
+        rho = st.rho(phq, self.netdop[:, None], nd, na, electrons=nq)
         qv = KAPPA * (self.semi * m.W)[:, None] * rho          # [E, q]
         b = m.scatter(qv @ INTERP)                               # project: sum_q qv_q w_a(q)
         if self.extra_load is not None:
@@ -237,7 +245,8 @@ class Problem:
         m = self.mesh
         nd = None if self.nd is None else self.nd[:, None]
         na = None if self.na is None else self.na[:, None]
-        return -KAPPA * (self.semi * m.W)[:, None] * self.stats.drho(m.at_gauss(phi), nd, na)
+        dnq = None if self.quantum is None else self.quantum.at_gauss(m, phi)[1]
+        return -KAPPA * (self.semi * m.W)[:, None] * self.stats.drho(m.at_gauss(phi), nd, na, delectrons=dnq)
 
     def jacobian_full(self, phi):
         """dF/dphi on all nodes: eps K + sum_q c_q w(q) w(q)^T (N x N CSR)."""
@@ -266,7 +275,8 @@ class Problem:
         """n(phi_i) at nodes that touch a semiconductor element, else 0."""
         touch = np.zeros(self.mesh.N, dtype=bool)
         touch[self.mesh.conn[self.semi > 0].ravel()] = True
-        return np.where(touch, self.stats.density(phi), 0.0)
+        n = self.stats.density(phi) if self.quantum is None else self.quantum.at_nodes(phi)[0]
+        return np.where(touch, n, 0.0)
 
     def box_elements(self, box):
         """Semiconductor elements whose centroid lies in the closed box
@@ -282,5 +292,8 @@ class Problem:
         (the integral of n that enters C = q dN/dV in Sec. III)."""
         sel = self.box_elements(box)
         m = self.mesh
-        nq = self.stats.density(m.at_gauss(phi))
+        if self.quantum is None:
+            nq = self.stats.density(m.at_gauss(phi))
+        else:
+            nq = self.quantum.at_gauss(m, phi)[0]
         return float(np.sum(m.W[sel][:, None] * nq[sel]))

@@ -235,19 +235,22 @@ class Statistics:
         sb = special.expit(b)
         return -nd * sa * (1.0 - sa) / self.kT, na * sb * (1.0 - sb) / self.kT
 
-    def rho(self, phi, netdop, nd=None, na=None):
+    def rho(self, phi, netdop, nd=None, na=None, electrons=None):
         """Space charge p - n + N_D+ - N_A- in nm^-3 (Eq. Poisson).  With
-        complete ionization the dopants enter through netdop = N_D - N_A."""
+        complete ionization the dopants enter through netdop = N_D - N_A.
+        ``electrons`` replaces n(phi) (the predictor-corrector density)."""
         phi = np.asarray(phi, dtype=np.float64)
-        r = self.hole_density(phi) - self.density(phi)
+        n = self.density(phi) if electrons is None else electrons
+        r = self.hole_density(phi) - n
         if self.ionization == "complete":
             return r + np.asarray(netdop, dtype=np.float64)
         dp, am = self.ionized(phi, nd, na)
         return r + dp - am
 
-    def drho(self, phi, nd=None, na=None):
+    def drho(self, phi, nd=None, na=None, delectrons=None):
         phi = np.asarray(phi, dtype=np.float64)
-        r = self.dhole_density(phi) - self.ddensity(phi)
+        dn = self.ddensity(phi) if delectrons is None else delectrons
+        r = self.dhole_density(phi) - dn
         if self.ionization == "complete":
             return r
         ddp, dam = self.dionized(phi, nd, na)

@@ -475,6 +475,8 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
   for (int i = 0; i < n_inst; ++i) {
     if ((st = check_problem(&probs[i])) != QE_OK) return fail(st, "instance %d: %s", i, qe_last_error());
     if (!phi[i]) return fail(QE_ERR_INVALID_ARG, "phi[%d] is NULL", i);
+    if (probs[i].quantum)
+      return fail(QE_ERR_INVALID_ARG, "instance %d: predictor-corrector states are not supported by the batch", i);
     if (probs[i].n_sheets > 0)
       return fail(QE_ERR_INVALID_ARG, "instance %d: interface / Robin sheets are not supported by the batch", i);
     if (ch.incomplete && !probs[i].donors)

@@ -58,6 +58,7 @@ struct Charge {
   double Eg;       // eV
   double ed_kT, ea_kT;   // E_d / kT, E_a / kT
   double ln_gD, ln_gA;   // ln of the degeneracy factors
+  double T_K;
 };
 
 // Charge of the linear initial-guess problem: no mobile charge, dopants fully
@@ -364,12 +365,11 @@ __device__ __forceinline__ void fermi_factor(double A, double& f, double& df) {
   df = -f * (1.0 - f);
 }
 
-// Space charge rho = p - n + N_D+ - N_A- (nm^-3) and drho/dphi at one point:
-// net = N_D - N_A with complete ionization; nd, na per element otherwise.
-__device__ __forceinline__ void space_charge(const Charge& ch, double phi, double net, double nd, double na,
-                                             double& rho, double& drho) {
-  double n, dn;
-  electron_density(ch, phi, n, dn);
+// Space charge rho = p - n + N_D+ - N_A- (nm^-3) and drho/dphi at one point
+// for a given electron density n and dn/dphi: net = N_D - N_A with complete
+// ionization; nd, na per element otherwise.
+__device__ __forceinline__ void space_charge_n(const Charge& ch, double phi, double n, double dn, double net,
+                                               double nd, double na, double& rho, double& drho) {
   rho = -n;
   drho = -dn;
   if (ch.holes) {
@@ -391,6 +391,43 @@ __device__ __forceinline__ void space_charge(const Charge& ch, double phi, doubl
   }
 }
 
+// The same with the electrons of the charge statistics.
+__device__ __forceinline__ void space_charge(const Charge& ch, double phi, double net, double nd, double na,
+                                             double& rho, double& drho) {
+  double n, dn;
+  electron_density(ch, phi, n, dn);
+  space_charge_n(ch, phi, n, dn, net, nd, na, rho, drho);
+}
+
+// Predictor-corrector electrons from the eigenstates of an earlier outer
+// iteration (Eq. pcPoisson): n~ = sum_i P |psi_i|^2 G(x_i) with
+// x_i = (E_F - E_i + (phi - phi^(k)))/kT, E_F = 0.  3D confinement (Eq.
+// ApproxEDens3DConfined): P = 4, G = 1/(1 + e^-x); 1D confinement (Eq.
+// ApproxEDens1DConfined): P = 2 m_t kT/(pi hbar^2), G = ln(1 + e^x).
+constexpr int kMaxStates = 32;
+struct Quantum {
+  int n;                 // states; 0 = electrons from the statistics
+  int conf;              // 3 or 1
+  long N;                // stride of psi2 between states
+  const double* psi2;    // [n][N] nodal |psi_i|^2
+  const double* phik;    // [N] phi^(k)
+  double pref;           // P
+  double inv_kT;         // 1/eV
+  double E[kMaxStates];  // E_i - E_F, eV
+};
+
+// G(x) and G'(x) of the confinement's occupation.
+__device__ __forceinline__ void pc_occupation(int conf, double x, double& G, double& dG) {
+  const double e = exp(-fabs(x));
+  const double s = x >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);   // 1/(1 + e^-x)
+  if (conf == 3) {
+    G = s;
+    dG = s * (1.0 - s);
+  } else {
+    G = fmax(x, 0.0) + log1p(e);   // ln(1 + e^x)
+    dG = s;
+  }
+}
 __device__ __forceinline__ double electron_density_only(const Charge& ch, double phi) {
   double n, dn;
   electron_density(ch, phi, n, dn);

@@ -43,10 +43,15 @@ void launch_adj_grad(hipStream_t s, const Geom& g, const TileMap& tm, const doub
                      const double* gvec, double* dQdeps, double* tcon);
 void launch_contact_sum(hipStream_t s, int nblocks, long N, int n_dir, const int32_t* dir_id, const double* tcon,
                         double* partial, unsigned int* counter, double* out);
+// Electrons per box / at the nodes: from the statistics, or from the
+// predictor-corrector states when qm.n > 0.
 void launch_count(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, const BoxSet& boxes,
-                  const uint8_t* semi, const double* phi, double* partial, unsigned int* counter, double* out);
+                  const uint8_t* semi, const double* phi, double* partial, unsigned int* counter, double* out,
+                  const Quantum& qm);
 void launch_density(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, const uint8_t* semi,
-                    const double* phi, double* nout);
+                    const double* phi, double* nout, const Quantum& qm);
+// Bits 32 (|psi|^2 not finite or negative) and 64 (phi^(k) not finite) of *flags.
+void launch_validate_quantum(hipStream_t s, int nblocks, const Quantum& qm, int* flags);
 void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const Doping& dop,
                      const int32_t* dir_id, const double* phi, int* flags);
 void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, const double* dir_val, uint8_t* mask,
@@ -61,7 +66,8 @@ void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const
                           const uint8_t* semi, const Doping& dop, const uint8_t* mask, const double* phi,
                           const double* delta64, const float* delta32, double lam, const double* fsheet,
                           const double* fdiag, double* F, double* invdiag, double* diag_out, double* cq, float* cq32,
-                          uint8_t* cflag, unsigned int* cbits, float* invdiag32, double* partial, double* norm2);
+                          uint8_t* cflag, unsigned int* cbits, float* invdiag32, double* partial, double* norm2,
+                          const Quantum& qm);
 // y = J v with v read as 0 on Dirichlet nodes (identity_rows: y_i = v_i there).
 void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const unsigned int* cbits,
                       const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows);

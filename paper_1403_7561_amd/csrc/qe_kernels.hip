@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_JV_MIN_W
   if (threadIdx.x == 0) part_py[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
 }
 
-template <typename TD>
+template <typename TD, bool kQ>
 __global__ __launch_bounds__(256) void k_residual_wave(
     Geom g, WaveMap wm, Charge ch, const double* __restrict__ eps, const uint8_t* __restrict__ semi,
     const Doping dop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
@@ -192,15 +192,15 @@ __global__ __launch_bounds__(256) void k_residual_wave(
     const double* __restrict__ fdiag, double* __restrict__ F, double* __restrict__ invdiag,
     double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
     uint8_t* __restrict__ cflag, unsigned int* __restrict__ cbits, float* __restrict__ invdiag32,
-    double* __restrict__ part) {
+    double* __restrict__ part, Quantum qm) {
   __shared__ double sred[4];
   int wx, wy, wz, wid;
   bool active;
   wave_coords(wm, wx, wy, wz, active, wid);
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   double acc = 0.0;
-  residual_tile<TD>(g, w, ch, eps, semi, dop, mask, phi, delta, lam, fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag,
-                    active ? cbits + 64L * wid + (threadIdx.x & 63) : nullptr, invdiag32, acc);
+  residual_tile<TD, kQ>(g, w, ch, eps, semi, dop, mask, phi, delta, lam, fsheet, fdiag, F, invdiag, diag_out, cq, cq32,
+                        cflag, active ? cbits + 64L * wid + (threadIdx.x & 63) : nullptr, invdiag32, acc, &qm);
   const double d = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
   __syncthreads();
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(kVecThreads) void k_contact_sum(
 // Electron counts in up to kMaxBoxes boxes; one grid-stride pass over elements.
 __global__ __launch_bounds__(kVecThreads) void k_count(
     Geom g, Charge ch, BoxSet boxes, const uint8_t* __restrict__ semi, const double* __restrict__ phi,
-    double* __restrict__ partial, unsigned int* counter, double* __restrict__ out) {
+    double* __restrict__ partial, unsigned int* counter, double* __restrict__ out, Quantum qm) {
   __shared__ double sred[kVecThreads / 64];
   double acc[kMaxBoxes];
 #pragma unroll
@@ -423,8 +423,36 @@ __global__ __launch_bounds__(kVecThreads) void k_count(
     ve[7] = phi[n0 + sz + sy + 1];
     gauss_interp(ve);
     double s = 0.0;
+    if (qm.n > 0) {
+      const long o[8] = {0, 1, sy, sy + 1, sz, sz + 1, sz + sy, sz + sy + 1};
+      double dph[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s += electron_density_only(ch, ve[q]);
+      for (int k = 0; k < 8; ++k) dph[k] = qm.phik[n0 + o[k]];
+      gauss_interp(dph);
+      double nq[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        dph[q] = ve[q] - dph[q];
+        nq[q] = 0.0;
+      }
+      for (int st = 0; st < qm.n; ++st) {
+        double s2[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s2[k] = qm.psi2[qm.N * st + n0 + o[k]];
+        gauss_interp(s2);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          double G, dG;
+          pc_occupation(qm.conf, (dph[q] - qm.E[st]) * qm.inv_kT, G, dG);
+          nq[q] += qm.pref * s2[q] * G;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += nq[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += electron_density_only(ch, ve[q]);
+    }
     s *= (g.x[i + 1] - g.x[i]) * (g.y[j + 1] - g.y[j]) * (g.z[k + 1] - g.z[k]) * 0.125;
     for (int r = 0; r < boxes.n; ++r)
       if (boxes.b[r].contains(xc, yc, zc)) acc[r] += s;
@@ -447,7 +475,8 @@ __global__ __launch_bounds__(kVecThreads) void k_count(
 
 // Nodal density: n(phi_i) if node i touches a semiconductor element, else 0.
 __global__ __launch_bounds__(kVecThreads) void k_density(Geom g, Charge ch, const uint8_t* __restrict__ semi,
-                                                        const double* __restrict__ phi, double* __restrict__ nout) {
+                                                        const double* __restrict__ phi, double* __restrict__ nout,
+                                                        Quantum qm) {
   const long N = (long)g.nx * g.ny * g.nz;
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
     const int i = (int)(n % g.nx);
@@ -461,7 +490,18 @@ __global__ __launch_bounds__(kVecThreads) void k_density(Geom g, Charge ch, cons
           if (ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1 && ek >= 0 && ek < g.nz - 1)
             touch |= semi[elem_index(g, ei, ej, ek)] != 0;
         }
-    nout[n] = touch ? electron_density_only(ch, phi[n]) : 0.0;
+    double nn = 0.0;
+    if (touch && qm.n > 0) {
+      const double dph = phi[n] - qm.phik[n];
+      for (int st = 0; st < qm.n; ++st) {
+        double G, dG;
+        pc_occupation(qm.conf, (dph - qm.E[st]) * qm.inv_kT, G, dG);
+        nn += qm.pref * qm.psi2[qm.N * st + n] * G;
+      }
+    } else if (touch) {
+      nn = electron_density_only(ch, phi[n]);
+    }
+    nout[n] = nn;
   }
 }
 
@@ -768,13 +808,30 @@ void launch_contact_sum(hipStream_t s, int nblocks, long N, int n_dir, const int
 }
 
 void launch_count(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, const BoxSet& boxes,
-                  const uint8_t* semi, const double* phi, double* partial, unsigned int* counter, double* out) {
-  QE_LAUNCH(k_count, nblocks, kVecThreads, s, g, ch, boxes, semi, phi, partial, counter, out);
+                  const uint8_t* semi, const double* phi, double* partial, unsigned int* counter, double* out,
+                  const Quantum& qm) {
+  QE_LAUNCH(k_count, nblocks, kVecThreads, s, g, ch, boxes, semi, phi, partial, counter, out, qm);
 }
 
 void launch_density(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, const uint8_t* semi,
-                    const double* phi, double* nout) {
-  QE_LAUNCH(k_density, nblocks, kVecThreads, s, g, ch, semi, phi, nout);
+                    const double* phi, double* nout, const Quantum& qm) {
+  QE_LAUNCH(k_density, nblocks, kVecThreads, s, g, ch, semi, phi, nout, qm);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_validate_quantum(Quantum qm, int* flags) {
+  int f = 0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < qm.N; i += (long)gridDim.x * blockDim.x) {
+    if (!isfinite(qm.phik[i])) f |= 64;
+    for (int st = 0; st < qm.n; ++st) {
+      const double v = qm.psi2[qm.N * st + i];
+      if (!(v >= 0.0 && isfinite(v))) f |= 32;
+    }
+  }
+  if (f) atomicOr(flags, f);
+}
+
+void launch_validate_quantum(hipStream_t s, int nblocks, const Quantum& qm, int* flags) {
+  QE_LAUNCH(k_validate_quantum, nblocks, kVecThreads, s, qm, flags);
 }
 
 void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const Doping& dop,
@@ -807,13 +864,21 @@ void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const
                           const uint8_t* semi, const Doping& dop, const uint8_t* mask, const double* phi,
                           const double* delta64, const float* delta32, double lam, const double* fsheet,
                           const double* fdiag, double* F, double* invdiag, double* diag_out, double* cq, float* cq32,
-                          uint8_t* cflag, unsigned int* cbits, float* invdiag32, double* partial, double* norm2) {
-  if (delta32)
-    QE_LAUNCH(k_residual_wave<float>, wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam, fsheet,
-              fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
+                          uint8_t* cflag, unsigned int* cbits, float* invdiag32, double* partial, double* norm2,
+                          const Quantum& qm) {
+  const bool q = qm.n > 0;
+  if (delta32 && q)
+    QE_LAUNCH((k_residual_wave<float, true>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam,
+              fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
+  else if (delta32)
+    QE_LAUNCH((k_residual_wave<float, false>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam,
+              fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
+  else if (q)
+    QE_LAUNCH((k_residual_wave<double, true>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam,
+              fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
   else
-    QE_LAUNCH(k_residual_wave<double>, wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam, fsheet,
-              fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial);
+    QE_LAUNCH((k_residual_wave<double, false>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam,
+              fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
   QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, wm.nblocks, norm2);
 }
 

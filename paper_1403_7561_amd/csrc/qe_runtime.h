@@ -42,6 +42,7 @@ struct Layout {
 Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int nblocks_tile, int vblocks,
                    int n_dir, long sheet_slots);
 long sheet_slots(const qe_problem* p);
+qe_status make_quantum(const qe_problem* p, const Charge& ch, Quantum& Q);
 SheetSet make_sheets(const qe_problem* p, std::vector<int4>& items);
 
 // One call's view of a problem, its workspace and its stream.
@@ -51,6 +52,7 @@ struct Context {
   TileMap tm;
   WaveMap wm;
   SheetSet sheets{};
+  Quantum quantum{};
   static constexpr int kEventRing = 8;
   hipEvent_t events[kEventRing] = {};   // CG progress markers, created on first use
   ~Context() {

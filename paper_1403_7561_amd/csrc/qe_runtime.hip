@@ -75,6 +75,7 @@ qe_status make_charge(const qe_physics* ph, Charge& ch) {
   std::memset(&ch, 0, sizeof(ch));
   ch.kappa = kQ / kEps0 * 1e9;  // V nm: Poisson divided by eps0, nm units
   ch.Ec0 = ph->Ec0_eV;
+  ch.T_K = ph->T_K;
   if (!std::isfinite(ph->Ec0_eV)) return fail(QE_ERR_INVALID_ARG, "Ec0_eV not finite");
   if (ph->holes != 0 && ph->holes != 1) return fail(QE_ERR_INVALID_ARG, "holes must be 0 or 1");
   if (ph->ionization != QE_ION_COMPLETE && ph->ionization != QE_ION_INCOMPLETE)
@@ -265,6 +266,32 @@ qe_status check_problem(const qe_problem* p) {
   return QE_OK;
 }
 
+// Kernel view of the predictor-corrector states, checked on the host.
+qe_status make_quantum(const qe_problem* p, const Charge& ch, Quantum& Q) {
+  std::memset(&Q, 0, sizeof(Q));
+  const qe_quantum* q = p->quantum;
+  if (!q) return QE_OK;
+  if (q->n_states < 1 || q->n_states > QE_MAX_STATES)
+    return fail(QE_ERR_INVALID_ARG, "quantum: n_states outside [1, %d]", QE_MAX_STATES);
+  if (q->confinement != 3 && q->confinement != 1) return fail(QE_ERR_INVALID_ARG, "quantum: confinement must be 3 or 1");
+  if (!q->psi2 || !q->phi_k || !q->E_i) return fail(QE_ERR_INVALID_ARG, "quantum: NULL array");
+  if (!positive(ch.T_K)) return fail(QE_ERR_INVALID_ARG, "quantum: the predictor-corrector density needs T_K > 0");
+  if (q->confinement == 1 && !positive(q->m_t)) return fail(QE_ERR_INVALID_ARG, "quantum: m_t must be > 0");
+  for (int i = 0; i < q->n_states; ++i)
+    if (!std::isfinite(q->E_i[i])) return fail(QE_ERR_INVALID_ARG, "quantum: E_i[%d] not finite", i);
+  Q.n = q->n_states;
+  Q.conf = q->confinement;
+  Q.N = (long)p->nx * p->ny * p->nz;
+  Q.psi2 = q->psi2;
+  Q.phik = q->phi_k;
+  const double kT_J = kKB * ch.T_K;
+  Q.inv_kT = kQ / kT_J;
+  // 3D: two spins x two valleys; 1D: 2 m_t kT / (pi hbar^2) in nm^-2
+  Q.pref = q->confinement == 3 ? 4.0 : 2.0 * q->m_t * kM0 * kT_J / (kPi * kHbar * kHbar) * 1e-18;
+  for (int i = 0; i < q->n_states; ++i) Q.E[i] = q->E_i[i];
+  return QE_OK;
+}
+
 // Nodes of all sheets counted with multiplicity (an upper bound of the
 // distinct ones).
 long sheet_slots(const qe_problem* p) {
@@ -381,6 +408,7 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   QE_TRY(check_problem(p));
   if (ch.incomplete && !p->donors)
     return fail(QE_ERR_INVALID_ARG, "incomplete ionization needs donors and acceptors");
+  QE_TRY(make_quantum(p, ch, quantum));
   prob = *p;
   s = (hipStream_t)stream_;
   N = (long)p->nx * p->ny * p->nz;
@@ -448,6 +476,7 @@ qe_status Context::validate(const double* phi) {
   int* dflags = reinterpret_cast<int*>(ws + lay.flags);
   launch_validate(s, vblocks, N, E, prob.n_dir, prob.eps_r, doping(), prob.dir_id, phi, dflags);
   if (sheets.n > 0) launch_validate_sheets(s, sheets, dflags);
+  if (quantum.n > 0) launch_validate_quantum(s, vblocks, quantum, dflags);
   QE_HIP(hipGetLastError());
   QE_HIP(hipMemcpyAsync(mirror().flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
   QE_HIP(hipStreamSynchronize(s));
@@ -457,6 +486,8 @@ qe_status Context::validate(const double* phi) {
   if (f & 4) return fail(QE_ERR_INVALID_ARG, "dir_id outside [-1, n_dir)");
   if (f & 8) return fail(QE_ERR_NONFINITE, "phi not finite");
   if (f & 16) return fail(QE_ERR_NONFINITE, "sheet sigma not finite");
+  if (f & 32) return fail(QE_ERR_NONFINITE, "quantum psi2 not finite and >= 0");
+  if (f & 64) return fail(QE_ERR_NONFINITE, "quantum phi_k not finite");
   return QE_OK;
 }
 
@@ -474,7 +505,7 @@ qe_status Context::residual(const Charge& ch, const double* phi, const double* d
   launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, doping(), u8(lay.mask), phi, d64, d32, lam,
                        sh ? f64(lay.fsheet) : nullptr, sh ? f64(lay.fdiag) : nullptr, f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
                        u8(lay.cflag), u32(lay.cbits), mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial),
-                       f64(lay.scal));
+                       f64(lay.scal), quantum);
   QE_HIP(hipGetLastError());
   if (norm2_host) {
     QE_HIP(hipMemcpyAsync(mirror().scal, ws + lay.scal, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -728,7 +759,7 @@ qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* 
   }
   if (st == QE_ERR_NOT_CONVERGED)
     fail(st, "Newton did not reach atol %.3e in %d steps (||F|| = %.3e)", o->newton_atol, o->newton_maxit, nrm);
-  if (n_nodal) launch_density(cx.s, cx.vblocks, cx.g, ch, p->semi, phi, n_nodal);
+  if (n_nodal) launch_density(cx.s, cx.vblocks, cx.g, ch, p->semi, phi, n_nodal, cx.quantum);
   if (hipStreamSynchronize(cx.s) != hipSuccess || hipGetLastError() != hipSuccess)
     return finish(fail(QE_ERR_HIP, "stream error at the end of the solve"), r, rep);
   return finish(st, r, rep);
@@ -889,7 +920,7 @@ qe_status qe_count_electrons(const qe_problem* p, const qe_physics* ph, const do
   QE_TRY(cx.init(p, ch, ws, ws_bytes, stream));
   QE_TRY(cx.validate(phi));
   launch_count(cx.s, kCountBlocks, cx.g, ch, bs, p->semi, phi, cx.f64(cx.lay.partial),
-               reinterpret_cast<unsigned int*>(cx.ws + cx.lay.counters) + 1, cx.f64(cx.lay.scal));
+               reinterpret_cast<unsigned int*>(cx.ws + cx.lay.counters) + 1, cx.f64(cx.lay.scal), cx.quantum);
   QE_HIP(hipGetLastError());
   QE_HIP(hipMemcpyAsync(mirror().scal, cx.ws + cx.lay.scal, n_boxes * sizeof(double), hipMemcpyDeviceToHost, cx.s));
   QE_HIP(hipStreamSynchronize(cx.s));
@@ -906,7 +937,7 @@ qe_status qe_density(const qe_problem* p, const qe_physics* ph, const double* ph
   Context cx;
   QE_TRY(cx.init(p, ch, ws, ws_bytes, stream));
   QE_TRY(cx.validate(phi));
-  launch_density(cx.s, cx.vblocks, cx.g, ch, p->semi, phi, n);
+  launch_density(cx.s, cx.vblocks, cx.g, ch, p->semi, phi, n, cx.quantum);
   QE_HIP(hipGetLastError());
   QE_HIP(hipStreamSynchronize(cx.s));
   return QE_OK;
@@ -924,6 +955,8 @@ qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options
   if (o->precision != QE_PREC_FP64) return finish(fail(QE_ERR_INVALID_ARG, "the adjoint runs in FP64"), r, rep);
   if ((st = make_charge(ph, ch)) != QE_OK) return finish(st, r, rep);
   if (!phi || !box || !dQ_ddir) return finish(fail(QE_ERR_INVALID_ARG, "phi/box/dQ_ddir is NULL"), r, rep);
+  if (p && p->quantum)
+    return finish(fail(QE_ERR_INVALID_ARG, "the adjoint does not support predictor-corrector states"), r, rep);
   for (int k = 0; k < 6; ++k)
     if (std::isnan(box[k])) return finish(fail(QE_ERR_INVALID_ARG, "box has NaN"), r, rep);
   Context cx;

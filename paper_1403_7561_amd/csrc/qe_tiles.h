@@ -315,7 +315,7 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
 // an element with a nonzero c_q and then its c_q, else cflag = 0 and nothing
 // (depleted silicon, where n' underflows to exactly 0, and insulators).
 // norm2 accumulates F_i^2 over owned free nodes.
-template <typename TD>
+template <typename TD, bool kQ = false>
 __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, const Charge& ch,
                                               const double* __restrict__ eps, const uint8_t* __restrict__ semi,
                                               const Doping dop, const uint8_t* __restrict__ mask,
@@ -326,7 +326,7 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
                                               double* __restrict__ diag_out, double* __restrict__ cq,
                                               float* __restrict__ cq32, uint8_t* __restrict__ cflag,
                                               unsigned int* __restrict__ cbits, float* __restrict__ invdiag32,
-                                              double& norm2) {
+                                              double& norm2, const Quantum* qm = nullptr) {
   const unsigned int sbits = w.semi_bits(g, semi);
   double ahx, ahy, axy;
   w.weights(ahx, ahy, axy);
@@ -380,10 +380,44 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
 #pragma unroll
         for (int k = 0; k < 8; ++k) src[k] = ve[k];
         gauss_interp(src);
+        double nq[8], dnq[8];
+        if constexpr (kQ) {
+          // predictor-corrector electrons: |psi_i|^2 and phi^(k) interpolated
+          // to the Gauss points like phi
+          const long b0 = w.n00 + w.sxy * L;
+          const long o[8] = {0, 1, g.nx, g.nx + 1, w.sxy, w.sxy + 1, w.sxy + g.nx, w.sxy + g.nx + 1};
+          double dph[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) dph[k] = qm->phik[b0 + o[k]];
+          gauss_interp(dph);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            dph[q] = src[q] - dph[q];
+            nq[q] = dnq[q] = 0.0;
+          }
+          for (int i = 0; i < qm->n; ++i) {
+            double s2[8];
+            const double* ps = qm->psi2 + qm->N * i + b0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s2[k] = ps[o[k]];
+            gauss_interp(s2);
+            const double Ei = qm->E[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              double G, dG;
+              pc_occupation(qm->conf, (dph[q] - Ei) * qm->inv_kT, G, dG);
+              nq[q] += qm->pref * s2[q] * G;
+              dnq[q] += qm->pref * s2[q] * dG * qm->inv_kT;
+            }
+          }
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           double rho, drho;
-          space_charge(ch, src[q], net, ndo, nac, rho, drho);
+          if constexpr (kQ)
+            space_charge_n(ch, src[q], nq[q], dnq[q], net, ndo, nac, rho, drho);
+          else
+            space_charge(ch, src[q], net, ndo, nac, rho, drho);
           src[q] = kw * rho;
           cc[q] = -kw * drho;
           nzc |= cc[q] != 0.0;

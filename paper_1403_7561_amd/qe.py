@@ -54,6 +54,11 @@ class CSheet(ctypes.Structure):
                 ("phi0", ctypes.c_double)]
 
 
+class CQuantum(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int32), ("confinement", ctypes.c_int32), ("psi2", ctypes.c_void_p),
+                ("phi_k", ctypes.c_void_p), ("E_i", ctypes.POINTER(ctypes.c_double)), ("m_t", ctypes.c_double)]
+
+
 class CProblem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
@@ -61,7 +66,8 @@ class CProblem(ctypes.Structure):
                 ("net_doping", ctypes.c_void_p), ("dir_id", ctypes.c_void_p),
                 ("dir_val", ctypes.c_void_p), ("n_dir", ctypes.c_int32),
                 ("donors", ctypes.c_void_p), ("acceptors", ctypes.c_void_p),
-                ("n_sheets", ctypes.c_int32), ("sheets", ctypes.POINTER(CSheet))]
+                ("n_sheets", ctypes.c_int32), ("sheets", ctypes.POINTER(CSheet)),
+                ("quantum", ctypes.POINTER(CQuantum))]
 
 
 class CPhysics(ctypes.Structure):
@@ -222,6 +228,16 @@ class Problem:
                                       sg.data_ptr() if sg is not None else None, float(sh.robin_d),
                                       float(sh.robin_eps), float(sh.phi0))
         self.n_sheets = len(sheets)
+        # predictor-corrector states: |psi|^2 and phi^(k) on the device, levels on the host
+        q = getattr(dev, "quantum", None)
+        self.c_quantum = None
+        if q is not None:
+            self.q_psi2 = torch.as_tensor(np.ascontiguousarray(q.psi2, dtype=np.float64), **f64)
+            self.q_phik = torch.as_tensor(np.ascontiguousarray(q.phi_k, dtype=np.float64), **f64)
+            E = np.ascontiguousarray(q.E_i, dtype=np.float64)
+            self.q_E = (ctypes.c_double * E.size)(*E.tolist())
+            self.c_quantum = CQuantum(int(E.size), int(q.confinement), self.q_psi2.data_ptr(),
+                                      self.q_phik.data_ptr(), self.q_E, float(q.m_t))
         self.device = device
 
     def c(self):
@@ -232,7 +248,8 @@ class Problem:
                         self.dir_val.data_ptr(), self.n_dir,
                         self.donors.data_ptr() if self.donors is not None else None,
                         self.acceptors.data_ptr() if self.acceptors is not None else None,
-                        self.n_sheets, self.c_sheets if self.n_sheets else None)
+                        self.n_sheets, self.c_sheets if self.n_sheets else None,
+                        ctypes.pointer(self.c_quantum) if self.c_quantum is not None else None)
 
 
 class Workspace:

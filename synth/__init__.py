@@ -10,6 +10,9 @@ from .devices import (  # noqa: F401
     with_interface_charge,
     with_charged_gates,
     Sheet,
+    QuantumStates,
+    box_states,
+    with_quantum,
     Device,
     stack_z,
     make_stack_device,

@@ -56,6 +56,20 @@ class Sheet:
 
 
 @dataclass
+class QuantumStates:
+    """Eigenstates of an earlier outer iteration for the predictor-corrector
+    density: psi2 [n_states, N] nodal |psi_i|^2 (nm^-3 for 3D confinement,
+    nm^-1 for 1D), phi_k [N] the potential they were computed in (V), E_i
+    [n_states] levels relative to E_F (eV), confinement 3 or 1, m_t the
+    transverse mass (1D form)."""
+    psi2: np.ndarray
+    phi_k: np.ndarray
+    E_i: np.ndarray
+    confinement: int = 3
+    m_t: float = 0.19
+
+
+@dataclass
 class Device:
     name: str
     x: np.ndarray
@@ -79,6 +93,8 @@ class Device:
     acceptors: np.ndarray = None   # [E] float64, nm^-3
     # interface-charge and Robin faces (list of Sheet)
     sheets: list = field(default_factory=list)
+    # predictor-corrector electrons (QuantumStates) instead of n(phi)
+    quantum: object = None
 
     @property
     def nx(self):
@@ -375,3 +391,32 @@ def with_charged_gates(dev, gates, sigma_nm2=0.0, d_nm=10.0, eps_r=EPS_OX, gate_
                             sigma=np.full(na * nb, float(sigma_nm2)), robin_d=d_nm, robin_eps=eps_r,
                             phi0=float(dev.dir_val[c])))
     return replace(dev, dir_id=dir_id, sheets=sheets)
+
+
+def box_states(dev, box, n_states, phi_k, seed=None, e0=-0.004, spacing=0.002):
+    """Synthetic 3D-confined states in a box (x0, x1, y0, y1, z0, z1) nm: the
+    standing waves of a hard-walled box, |psi|^2 = (8/V) prod sin^2(pi m (s -
+    s0)/L) (normalised in the continuum), zero outside; modes taken in order
+    of m_x^2/Lx^2 + m_y^2/Ly^2 + m_z^2/Lz^2.  Levels: e0, then seeded steps
+    of spacing * U[0.5, 1.5] (eV relative to E_F)."""
+    x0, x1, y0, y1, z0, z1 = box
+    L = np.array([x1 - x0, y1 - y0, z1 - z0])
+    modes = sorted(((mx, my, mz) for mx in range(1, 6) for my in range(1, 6) for mz in range(1, 4)),
+                   key=lambda m: (m[0] / L[0]) ** 2 + (m[1] / L[1]) ** 2 + (m[2] / L[2]) ** 2)[:n_states]
+    Z, Y, X = np.meshgrid(dev.z, dev.y, dev.x, indexing="ij")
+    X, Y, Z = X.ravel(), Y.ravel(), Z.ravel()
+    inside = (X >= x0) & (X <= x1) & (Y >= y0) & (Y <= y1) & (Z >= z0) & (Z <= z1)
+    psi2 = np.zeros((n_states, X.size))
+    for i, (mx, my, mz) in enumerate(modes):
+        f = (np.sin(np.pi * mx * (X - x0) / L[0]) * np.sin(np.pi * my * (Y - y0) / L[1])
+             * np.sin(np.pi * mz * (Z - z0) / L[2])) ** 2 * 8.0 / np.prod(L)
+        psi2[i] = np.where(inside, f, 0.0)
+    rng = np.random.default_rng(seed)
+    E = e0 + np.concatenate([[0.0], np.cumsum(spacing * rng.uniform(0.5, 1.5, n_states - 1))])
+    return QuantumStates(psi2=psi2, phi_k=np.asarray(phi_k, dtype=np.float64).copy(), E_i=E)
+
+
+def with_quantum(dev, states):
+    """A copy of a device whose electrons come from the given states."""
+    from dataclasses import replace
+    return replace(dev, quantum=states)

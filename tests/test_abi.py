@@ -239,3 +239,28 @@ def test_sheet_count_checks():
         st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
                           None, ctypes.c_void_p(256), 1 << 40, None, None)
         assert st == -1 and needle in qe.qe_last_error()
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(n_states=0), "n_states"),
+    (dict(n_states=33), "n_states"),
+    (dict(confinement=2), "confinement"),
+    (dict(psi2=None), "NULL array"),
+    (dict(confinement=1, m_t=0.0), "m_t"),
+    (dict(E_nan=True), "E_i[1]"),
+    (dict(T=0.0), "T_K > 0"),
+])
+def test_invalid_quantum_rejected(over, needle):
+    lib = qe.load_library()
+    p = fake_problem()
+    E = (ctypes.c_double * 2)(-0.01, float("nan") if over.pop("E_nan", False) else 0.01)
+    T = over.pop("T", 4.0)
+    f = dict(n_states=2, confinement=3, psi2=16, phi_k=16, E_i=E, m_t=0.19)
+    f.update(over)
+    q = qe.CQuantum(**f)
+    p.quantum = ctypes.pointer(q)
+    o = qe.qe_default_options()
+    ph = qe.Physics(stat="tf", T_K=T).c()
+    st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
+                      None, ctypes.c_void_p(256), 1 << 40, None, None)
+    assert st in (-1, -3) and needle in qe.qe_last_error(), qe.qe_last_error()

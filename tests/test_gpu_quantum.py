@@ -1,0 +1,126 @@
+"""GPU parity of the predictor step of the predictor-corrector method
+(Eq. pcPoisson with Eqs. ApproxEDens3DConfined and ApproxEDens1DConfined):
+synthetic eigenstates as inputs, residual, diagonal, J.v, solves, nodal
+density and counts through the C ABI against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import solver
+from paper_1403_7561_amd import qe
+from tests import gpu_support as gs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DOT = (10.0, 60.0, 80.0, 120.0, 75.0, 90.0)
+
+
+def dev_tensor(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def pc_device(n_states=12, conf=3, full=False):
+    """The ragged stack with states in the D1 dot computed (synthetically) in
+    the semiclassical solution phi^(k); levels around E_F so that some are
+    partly occupied."""
+    base = gs.full_charge_device("incomplete", volts=(2.2, 2.0, 1.0, 1.3, 0.9)) if full else \
+        gs.ragged_device(volts=(2.0, 1.8, 0.9, 1.1, 0.7))
+    _, res = solver.solve(base, atol=1e-10)
+    st = synth.box_states(base, DOT, n_states, res.phi, seed=3, e0=-0.003, spacing=0.0006)
+    if conf == 1:
+        # a 1D-confined form: |psi|^2 per nm (the z profile), levels further
+        # from E_F (a 2D gas)
+        st.psi2 = st.psi2 * 100.0
+        st.confinement = 1
+        st.E_i = st.E_i * 5.0
+    return synth.with_quantum(base, st)
+
+
+CASES = {
+    "3d": lambda: pc_device(),
+    "3d_full_charge": lambda: pc_device(6, full=True),
+    "1d": lambda: pc_device(4, conf=1),
+}
+
+
+@pytest.fixture(scope="module")
+def solved():
+    cache = {}
+
+    def get(case):
+        if case not in cache:
+            dev = CASES[case]()
+            po, res = solver.solve(dev, atol=1e-10)
+            assert res.status == "ok"
+            cache[case] = (dev, po, res)
+        return cache[case]
+    return get
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_residual_diag_and_jv(case, solved):
+    dev, po, res = solved(case)
+    rng = np.random.default_rng(8)
+    phi = po.with_dirichlet(res.phi + 0.003 * rng.standard_normal(po.mesh.N))
+    P = qe.Problem(dev)
+    F, d, n2 = qe.qe_residual(P, dev_tensor(phi))
+    Fo, do = po.residual(phi), po.jacobi_diag(phi)
+    print(case, "F", rel_max(F.cpu().numpy(), Fo), "diag", rel_max(d.cpu().numpy(), do))
+    assert rel_max(F.cpu().numpy(), Fo) < 1e-12
+    assert rel_max(d.cpu().numpy(), do) < 1e-12
+    assert n2 == pytest.approx(float(Fo @ Fo), rel=1e-11)
+    v = rng.standard_normal(po.mesh.N)
+    y = qe.qe_jv(P, dev_tensor(phi), dev_tensor(v)).cpu().numpy()
+    yo = po.jv(phi, v)
+    assert rel_max(y, yo) < 1e-12
+    y32 = qe.qe_jv(P, dev_tensor(phi), dev_tensor(v, torch.float32)).cpu().numpy()
+    assert rel_max(y32, yo) < 2e-5
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_solve_density_and_counts(case, solved):
+    dev, po, res = solved(case)
+    P = qe.Problem(dev)
+    phi, n, rep = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-10))
+    print(case, rep)
+    err = rel_max(phi.cpu().numpy(), res.phi)
+    print(case, "phi rel err", err)
+    assert rep["res_final"] <= 1e-10 and err < 1e-9
+    n_o = po.nodal_density(res.phi)
+    assert np.abs(n.cpu().numpy() - n_o).max() <= 1e-8 * n_o.max()
+    boxes = [DOT, dev.boxes["D2"], (0, 200, 0, 200, 0, 100)]
+    c = qe.qe_count_electrons(P, dev_tensor(res.phi), boxes)
+    co = np.array([po.count(res.phi, b) for b in boxes])
+    print(case, "counts", c, co)
+    assert np.allclose(c, co, rtol=1e-12, atol=1e-300) and co[0] > 0.5 and co[1] == 0.0
+    nd = qe.qe_density(P, dev_tensor(res.phi)).cpu().numpy()
+    assert np.abs(nd - n_o).max() <= 1e-13 * n_o.max()
+
+
+def test_mixed_precision_predictor(solved):
+    dev, po, res = solved("3d")
+    P = qe.Problem(dev)
+    phi64, _, r64 = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-9))
+    phi32, _, r32 = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-9, precision=1))
+    assert r32["res_final"] <= 1e-9
+    assert rel_max(phi32.cpu().numpy(), phi64.cpu().numpy()) < 1e-6
+
+
+def test_states_validated_and_unsupported_paths_rejected():
+    dev = pc_device(2)
+    dev.quantum.psi2 = dev.quantum.psi2.copy()
+    dev.quantum.psi2[1, 5] = -1.0
+    with pytest.raises(qe.QeError, match="psi2"):
+        qe.qe_solve(qe.Problem(dev))
+    dev = pc_device(2)
+    P = qe.Problem(dev)
+    with pytest.raises(qe.QeError, match="predictor-corrector"):
+        qe.qe_adjoint(P, dev_tensor(dev.quantum.phi_k), DOT)
+    with pytest.raises(qe.QeError, match="predictor-corrector"):
+        qe.qe_solve_batch([P], opts=qe.qe_default_options())
