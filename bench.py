@@ -135,6 +135,29 @@ def sheets_run(synth, qe, torch, dev, opts, ws, boxes):
             "dot_electrons": [float(x) for x in c], "n_sheets": len(sdev.sheets)}
 
 
+def predictor_run(synth, qe, torch, dev, P, opts, ws, boxes, phi_sc):
+    """The predictor step of the predictor-corrector loop on the same stack:
+    16 synthetic 3D-confined states in the D1 dot (hard-wall box modes,
+    seeded levels from -3 meV around E_F) computed in the semiclassical
+    solution phi_sc, which is also phi^(k).  One warm-up and two timed
+    solves from the default guess."""
+    st = synth.box_states(dev, (10.0, 60.0, 80.0, 120.0, 75.0, 90.0), 16, phi_sc.cpu().numpy(), seed=7564,
+                          e0=-0.003, spacing=0.0006)
+    Pq = qe.Problem(synth.with_quantum(dev, st))
+    qe.qe_solve(Pq, opts=opts, ws=ws, want_density=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        ph, _, rep = qe.qe_solve(Pq, opts=opts, ws=ws, want_density=True)
+        c = qe.qe_count_electrons(Pq, ph, boxes, ws=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 2
+    return {"solves_per_s": 1.0 / dt, "ms": dt * 1e3, "n_states": 16, "newton_iters": rep["newton_iters"],
+            "krylov_iters": rep["krylov_iters"], "res_final": rep["res_final"],
+            "dot_electrons": [float(x) for x in c],
+            "max_dphi_vs_phi_k": float((ph - phi_sc).abs().max())}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -151,6 +174,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-full-charge", action="store_true")
     ap.add_argument("--no-sheets", action="store_true")
+    ap.add_argument("--no-predictor", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -294,6 +318,9 @@ def main():
     if not args.no_sheets:
         log("interface charge and charged plunger gates on the same stack")
         out["sheets_c2"] = sheets_run(synth, qe, torch, dev, opts, ws, boxes)
+    if not args.no_predictor:
+        log("predictor step with 16 synthetic dot states")
+        out["predictor_c2"] = predictor_run(synth, qe, torch, dev, P, opts, ws, boxes, phi)
     log("cpu baseline")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dev, reps[-1]["newton_iters"])
