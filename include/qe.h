@@ -125,7 +125,8 @@ typedef struct {
  * and with 1D confinement (Eq. ApproxEDens1DConfined)
  * P = 2 m_t kT / (pi hbar^2), G(x) = ln(1 + e^x).  |psi_i|^2 and phi^(k) are
  * nodal fields interpolated to the Gauss points like phi.  n~ replaces the
- * electron statistics everywhere (holes and dopants stay as qe_physics says);
+ * electron statistics in the quantum region (holes and dopants stay as
+ * qe_physics says; nodal densities take n~ at nodes touching the region);
  * T_K > 0 is needed.  Supported by qe_solve, qe_residual, qe_jv, qe_jv_f32,
  * qe_density and qe_count_electrons (which then report n~); qe_adjoint and
  * qe_solve_batch reject it. */
@@ -138,6 +139,9 @@ typedef struct {
   const double* phi_k;           /* DEVICE [N] the potential phi^(k), V */
   const double* E_i;             /* HOST [n_states] levels E_i^(k) - E_F, eV, finite */
   double m_t;                    /* transverse mass / m0, > 0 (1D form) */
+  const uint8_t* region;         /* DEVICE [E] nonzero: the element's electrons are n~
+                                    (the quantum region); elsewhere the statistics;
+                                    NULL = every element */
 } qe_quantum;
 
 /* One device.  All pointers are DEVICE memory, read only, except `sheets`
@@ -318,6 +322,43 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
  * Errors: QE_ERR_INVALID_ARG for TF or linear statistics, T <= 0, a zero or
  * negative majority density, or NULL pointers. */
 qe_status qe_ohmic_potential(const qe_physics* ph, double N_D, double N_A, double V_a, double* phi);
+
+/* Effective-mass Schrodinger eigenproblem on the same Q1 mesh (Sec. II.B,
+ * Eqs. SchrodEqn, SchrodEqnWeakForm): H psi = E M psi with
+ *   H_ij = sum_e (hbar^2/2m0)(m0/m*_e) int_e grad w_i . grad w_j + int V w_i w_j,
+ *   M_ij = int w_i w_j,  V = v0_e - phi (eV; phi interpolated to the Gauss
+ * points), psi = 0 on the `fixed` nodes and natural (Neumann) conditions on
+ * every other boundary.  Only nx, ny, nz, x, y, z of the qe_problem are read. */
+typedef struct {
+  const double* inv_mass;        /* DEVICE [E] m0 / m*_e, finite, > 0 */
+  const double* v0;              /* DEVICE [E] conduction-band edge at phi = 0 relative
+                                    to E_F, eV, finite (Ec0 in Si, plus the band
+                                    offset in an insulator) */
+  const uint8_t* fixed;          /* DEVICE [N] nonzero: psi = 0 there; or NULL */
+} qe_schrodinger;
+
+#define QE_MAX_EIG 16
+
+/* Device scratch of qe_schrodinger_solve for n_states states (0 if invalid). */
+size_t qe_schrodinger_workspace_bytes(const qe_problem* p, int32_t n_states);
+
+/* Lowest n_states (1 .. QE_MAX_EIG) eigenpairs by block LOBPCG (Knyazev's
+ * locally optimal block preconditioned CG) on H - sigma M with sigma below
+ * every V (so the operator is SPD), two guard vectors, the Jacobi
+ * preconditioner, soft locking of converged vectors, and Rayleigh-Ritz on
+ * the block [X, W, P] (Gram matrices by rocBLAS; the small dense generalized
+ * eigenproblem on the host).  Operators use the wave-tiled J.v.
+ * phi: device [N].  Stops when every wanted pair has
+ * ||H x - E M x||_2 <= tol (||H x||_2 + |E| ||M x||_2) or after maxit
+ * iterations (QE_ERR_NOT_CONVERGED, results still written).
+ * E: host [n_states] ascending, eV.  psi: device [n_states][N], M-orthonormal,
+ * 0 on fixed nodes (sign arbitrary).  psi2: device [n_states][N] or NULL,
+ * receives psi^2 (the input of qe_quantum).  iters: host or NULL.
+ * seed: the starting block's counter-based random numbers (SplitMix64). */
+qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* s, const double* phi,
+                               int32_t n_states, double tol, int32_t maxit, uint64_t seed,
+                               double* E, double* psi, double* psi2, int32_t* iters,
+                               void* ws, size_t ws_bytes, void* stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* qe_last_error(void);

@@ -203,6 +203,23 @@ class Problem:
         q = getattr(dev, "quantum", None)
         self.quantum = None if q is None else QuantumDensity(q.psi2, q.phi_k, q.E_i, stats.T_K, q.confinement,
                                                              q.m_t)
+        # elements whose electrons come from the states (all when no region is given)
+        reg = None if q is None else getattr(q, "region", None)
+        self.qregion = None if reg is None else np.asarray(reg).astype(bool)
+
+    def electrons_at_gauss(self, phi):
+        """(n, dn/dphi) at the Gauss points, [E, 8]: the statistics, or the
+        predictor-corrector density inside the quantum region."""
+        m = self.mesh
+        phq = m.at_gauss(phi)
+        n, dn = self.stats.density(phq), self.stats.ddensity(phq)
+        if self.quantum is None:
+            return n, dn
+        nq, dnq = self.quantum.at_gauss(m, phi)
+        if self.qregion is None:
+            return nq, dnq
+        r = self.qregion[:, None]
+        return np.where(r, nq, n), np.where(r, dnq, dn)
 
     # --- nodal vectors -------------------------------------------------
     def with_dirichlet(self, phi):
@@ -221,7 +238,7 @@ class Problem:
         na = None if self.na is None else self.na[:, None]
         nq = None
         if self.quantum is not None and stats is None:
-            nq, _ = self.quantum.at_gauss(m, phi)
+            nq, _ = self.electrons_at_gauss(phi)
         rho = st.rho(phq, self.netdop[:, None], nd, na, electrons=nq)
         qv = KAPPA * (self.semi * m.W)[:, None] * rho          # [E, q]
         b = m.scatter(qv @ INTERP)                               # project: sum_q qv_q w_a(q)
@@ -245,7 +262,7 @@ class Problem:
         m = self.mesh
         nd = None if self.nd is None else self.nd[:, None]
         na = None if self.na is None else self.na[:, None]
-        dnq = None if self.quantum is None else self.quantum.at_gauss(m, phi)[1]
+        dnq = None if self.quantum is None else self.electrons_at_gauss(phi)[1]
         return -KAPPA * (self.semi * m.W)[:, None] * self.stats.drho(m.at_gauss(phi), nd, na, delectrons=dnq)
 
     def jacobian_full(self, phi):
@@ -275,7 +292,14 @@ class Problem:
         """n(phi_i) at nodes that touch a semiconductor element, else 0."""
         touch = np.zeros(self.mesh.N, dtype=bool)
         touch[self.mesh.conn[self.semi > 0].ravel()] = True
-        n = self.stats.density(phi) if self.quantum is None else self.quantum.at_nodes(phi)[0]
+        n = self.stats.density(phi)
+        if self.quantum is not None:
+            # nodes touching a quantum-region element take the states' density
+            qn = np.ones(self.mesh.N, dtype=bool)
+            if self.qregion is not None:
+                qn[:] = False
+                qn[self.mesh.conn[self.qregion].ravel()] = True
+            n = np.where(qn, self.quantum.at_nodes(phi)[0], n)
         return np.where(touch, n, 0.0)
 
     def box_elements(self, box):
@@ -292,8 +316,5 @@ class Problem:
         (the integral of n that enters C = q dN/dV in Sec. III)."""
         sel = self.box_elements(box)
         m = self.mesh
-        if self.quantum is None:
-            nq = self.stats.density(m.at_gauss(phi))
-        else:
-            nq = self.quantum.at_gauss(m, phi)[0]
+        nq = self.electrons_at_gauss(phi)[0]
         return float(np.sum(m.W[sel][:, None] * nq[sel]))

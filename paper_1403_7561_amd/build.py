@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqe.so")
-SOURCES = ["qe_kernels.hip", "qe_sheets.hip", "qe_runtime.hip", "qe_batch.hip"]
+SOURCES = ["qe_kernels.hip", "qe_sheets.hip", "qe_runtime.hip", "qe_batch.hip", "qe_schrod.hip"]
 ARCH = os.environ.get("QE_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -20,6 +20,10 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
+
+
+# rocBLAS: the Gram matrices and block updates of the eigensolver (dgemm)
+LIBS = ["-lrocblas"]
 
 
 def hipcc():
@@ -34,7 +38,7 @@ def build(verbose=False, out=None):
     lib = out or LIB
     tmp = lib + ".tmp"
     extra = os.environ.get("QE_EXTRA_FLAGS", "").split()
-    cmd = [hipcc(), *FLAGS, *extra, "-shared", "-o", tmp, *srcs, f"-I{os.path.join(ROOT, 'include')}"]
+    cmd = [hipcc(), *FLAGS, *extra, "-shared", "-o", tmp, *srcs, f"-I{os.path.join(ROOT, 'include')}", *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

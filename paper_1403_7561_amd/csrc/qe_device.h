@@ -411,6 +411,7 @@ struct Quantum {
   long N;                // stride of psi2 between states
   const double* psi2;    // [n][N] nodal |psi_i|^2
   const double* phik;    // [N] phi^(k)
+  const uint8_t* region; // [E] quantum-region elements, NULL = all
   double pref;           // P
   double inv_kT;         // 1/eV
   double E[kMaxStates];  // E_i - E_F, eV

@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kVecThreads) void k_count(
     ve[7] = phi[n0 + sz + sy + 1];
     gauss_interp(ve);
     double s = 0.0;
-    if (qm.n > 0) {
+    if (qm.n > 0 && (!qm.region || qm.region[el])) {
       const long o[8] = {0, 1, sy, sy + 1, sz, sz + 1, sz + sy, sz + sy + 1};
       double dph[8];
 #pragma unroll
@@ -491,7 +491,16 @@ __global__ __launch_bounds__(kVecThreads) void k_density(Geom g, Charge ch, cons
             touch |= semi[elem_index(g, ei, ej, ek)] != 0;
         }
     double nn = 0.0;
-    if (touch && qm.n > 0) {
+    bool qnode = qm.n > 0 && !qm.region;   // touches a quantum-region element
+    if (qm.n > 0 && qm.region)
+      for (int dk = -1; dk <= 0; ++dk)
+        for (int dj = -1; dj <= 0; ++dj)
+          for (int di = -1; di <= 0; ++di) {
+            const int ei = i + di, ej = j + dj, ek = k + dk;
+            if (ei >= 0 && ei < g.nx - 1 && ej >= 0 && ej < g.ny - 1 && ek >= 0 && ek < g.nz - 1)
+              qnode |= qm.region[elem_index(g, ei, ej, ek)] != 0;
+          }
+    if (touch && qnode) {
       const double dph = phi[n] - qm.phik[n];
       for (int st = 0; st < qm.n; ++st) {
         double G, dG;

@@ -20,6 +20,13 @@
 #define QE_EW_GAMMA 0.9
 #endif
 
+// Returns the status of `expr` from the enclosing function unless it is QE_OK.
+#define QE_TRY(expr)              \
+  do {                            \
+    qe_status s_ = (expr);        \
+    if (s_ != QE_OK) return s_;   \
+  } while (0)
+
 namespace qe {
 
 qe_status fail(qe_status st, const char* fmt, ...);

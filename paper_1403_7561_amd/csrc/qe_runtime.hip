@@ -44,11 +44,6 @@ void clear_error() { g_last_error.clear(); }
                   __FILE__, __LINE__);                                                \
   } while (0)
 
-#define QE_TRY(expr)              \
-  do {                            \
-    qe_status s_ = (expr);        \
-    if (s_ != QE_OK) return s_;   \
-  } while (0)
 
 // ------------------------------------------------------------------ physics
 // CODATA 2018 values (q, hbar, kB exact).
@@ -284,6 +279,7 @@ qe_status make_quantum(const qe_problem* p, const Charge& ch, Quantum& Q) {
   Q.N = (long)p->nx * p->ny * p->nz;
   Q.psi2 = q->psi2;
   Q.phik = q->phi_k;
+  Q.region = q->region;
   const double kT_J = kKB * ch.T_K;
   Q.inv_kT = kQ / kT_J;
   // 3D: two spins x two valleys; 1D: 2 m_t kT / (pi hbar^2) in nm^-2

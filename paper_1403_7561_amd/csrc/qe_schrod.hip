@@ -1,0 +1,601 @@
+// Effective-mass Schrodinger eigenpairs on the Q1 mesh (Sec. II.B, Eqs.
+// SchrodEqn, SchrodEqnWeakForm) by block LOBPCG.
+//
+// Both operators of H psi = E M psi go through the wave-tiled J.v kernel:
+// H' = H - sigma M is "stiffness weighted by (hbar^2/2m0)(m0/m*) plus Gauss-
+// point coefficients W (V_q - sigma)", M is "zero stiffness plus
+// coefficients W" -- the same element operator as the Poisson Jacobian.
+// sigma lies below every V, so H' is SPD and the Jacobi preconditioner is
+// positive.  Fixed nodes (psi = 0) are masked: every block vector is zero
+// there and the J.v writes zero rows.
+//
+// One LOBPCG iteration: residuals R = H'X - M X diag(lambda) and their norms
+// (device), soft locking of converged columns (host decision), W = D^-1 R
+// for the active ones and its H', M products, the Gram matrices of
+// [X, W, P] under H' and M (rocBLAS dgemm; FP64 matrix cores), the small
+// generalized eigenproblem on the host (column scaling, Cholesky, cyclic
+// Jacobi), and the new X, P (with their products) as dgemm combinations.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/qe.h"
+#include "qe_kernels.h"
+#include "qe_runtime.h"
+#include "qe_tiles.h"
+
+namespace qe {
+
+// hbar^2 / (2 m0) in eV nm^2 (CODATA 2018)
+static const double kHB2M = 1.054571817e-34 * 1.054571817e-34 / (2.0 * 9.1093837015e-31) / 1.602176634e-19 * 1e18;
+constexpr int kSchBlocks = 256;
+constexpr int kMaxCols = QE_MAX_EIG + 2;
+
+// Input checks: bit 1 inv_mass not finite / positive, 2 v0 not finite, 4 phi not finite.
+__global__ __launch_bounds__(kVecThreads) void k_sch_validate(long E, long N, const double* __restrict__ inv_mass,
+                                                             const double* __restrict__ v0,
+                                                             const double* __restrict__ phi, int* flags) {
+  int f = 0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (long)gridDim.x * blockDim.x) {
+    if (!(inv_mass[e] > 0.0) || !isfinite(inv_mass[e])) f |= 1;
+    if (!isfinite(v0[e])) f |= 2;
+  }
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x)
+    if (!isfinite(phi[n])) f |= 4;
+  if (f) atomicOr(flags, f);
+}
+
+__device__ __forceinline__ void elem_ijk(const Geom& g, long e, int& i, int& j, int& k) {
+  const long ex = g.nx - 1, ey = g.ny - 1;
+  i = (int)(e % ex);
+  j = (int)((e / ex) % ey);
+  k = (int)(e / (ex * ey));
+}
+
+// Per block: min over elements of v0_e - phi at the element's corners (a
+// lower bound of V at every Gauss point, which interpolates phi).
+__global__ __launch_bounds__(kVecThreads) void k_sch_vmin(Geom g, const double* __restrict__ v0,
+                                                         const double* __restrict__ phi, double* __restrict__ part) {
+  __shared__ double sred[kVecThreads / 64];
+  const long E = (long)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+  double m = INFINITY;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    elem_ijk(g, e, i, j, k);
+    const long n0 = (long)i + (long)g.nx * ((long)j + (long)g.ny * k);
+    const long sy = g.nx, sz = (long)g.nx * g.ny;
+    double pm = phi[n0];
+    pm = fmax(pm, phi[n0 + 1]);
+    pm = fmax(pm, phi[n0 + sy]);
+    pm = fmax(pm, phi[n0 + sy + 1]);
+    pm = fmax(pm, phi[n0 + sz]);
+    pm = fmax(pm, phi[n0 + sz + 1]);
+    pm = fmax(pm, phi[n0 + sz + sy]);
+    pm = fmax(pm, phi[n0 + sz + sy + 1]);
+    m = fmin(m, v0[e] - pm);
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_down(m, o, 64));
+  if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = sred[0];
+    for (int w = 1; w < kVecThreads / 64; ++w) r = fmin(r, sred[w]);
+    part[blockIdx.x] = r;
+  }
+}
+
+// Tile-major operator data: kinetic weight (hbar^2/2m0)(m0/m*) and the
+// Gauss-point coefficients W (V_q - sigma) of H', W of M.
+__global__ __launch_bounds__(kVecThreads) void k_sch_coef(Geom g, const double* __restrict__ inv_mass,
+                                                         const double* __restrict__ v0,
+                                                         const double* __restrict__ phi, double sigma, double hb2m,
+                                                         double* __restrict__ eH, double* __restrict__ cH,
+                                                         double* __restrict__ cM) {
+  const long E = (long)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+  const int tgx = (g.nx + 6) / 7, tgy = (g.ny + 6) / 7;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    elem_ijk(g, e, i, j, k);
+    const long n0 = (long)i + (long)g.nx * ((long)j + (long)g.ny * k);
+    const long sy = g.nx, sz = (long)g.nx * g.ny;
+    double q[8] = {phi[n0], phi[n0 + 1], phi[n0 + sy], phi[n0 + sy + 1],
+                   phi[n0 + sz], phi[n0 + sz + 1], phi[n0 + sz + sy], phi[n0 + sz + sy + 1]};
+    gauss_interp(q);
+    const double W = (g.x[i + 1] - g.x[i]) * (g.y[j + 1] - g.y[j]) * (g.z[k + 1] - g.z[k]) * 0.125;
+    const double ve = v0[e];
+    double ch[8], cm[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      ch[t] = W * (ve - q[t] - sigma);
+      cm[t] = W;
+    }
+    const long sl = tile_slot(i, j, k, tgx, tgy);
+    eH[sl] = hb2m * inv_mass[e];
+    store8(cH + 8 * sl, ch);
+    store8(cM + 8 * sl, cm);
+  }
+}
+
+// Coefficient flags of every J.v lane: all element layers of its column.
+__global__ __launch_bounds__(256) void k_sch_bits(Geom g, WaveMap wm, unsigned int* __restrict__ cbits) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= wm.nwaves) return;
+  const int wx = w % wm.gx, wy = (w / wm.gx) % wm.gy, wz = w / (wm.gx * wm.gy);
+  const WaveTile t(g, wx, wy, wz, wm.kz, threadIdx.x & 63, true);
+  unsigned int b = 0;
+  if (t.col_ok)
+    for (int L = max(t.Lbeg, 0); L <= min(t.Lend, g.nz - 2); ++L) b |= 1u << (L - t.Lbeg);
+  cbits[64L * w + (threadIdx.x & 63)] = b;
+}
+
+// Jacobi preconditioner: 1 / (kinetic diagonal + consistent-mass diagonal
+// times (v0_e - phi_n - sigma)) on free nodes, 0 on fixed ones.
+__global__ __launch_bounds__(kVecThreads) void k_sch_diag(Geom g, const double* __restrict__ inv_mass,
+                                                         const double* __restrict__ v0,
+                                                         const double* __restrict__ phi,
+                                                         const uint8_t* __restrict__ mask, double sigma,
+                                                         double hb2m, double* __restrict__ dinv) {
+  const long N = (long)g.nx * g.ny * g.nz;
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
+    if (mask[n]) {
+      dinv[n] = 0.0;
+      continue;
+    }
+    const int i = (int)(n % g.nx), j = (int)((n / g.nx) % g.ny), k = (int)(n / ((long)g.nx * g.ny));
+    double d = 0.0;
+    for (int dk = -1; dk <= 0; ++dk)
+      for (int dj = -1; dj <= 0; ++dj)
+        for (int di = -1; di <= 0; ++di) {
+          const int ei = i + di, ej = j + dj, ek = k + dk;
+          if (ei < 0 || ei >= g.nx - 1 || ej < 0 || ej >= g.ny - 1 || ek < 0 || ek >= g.nz - 1) continue;
+          const long e = (long)ei + (long)(g.nx - 1) * ((long)ej + (long)(g.ny - 1) * ek);
+          const double hx = g.x[ei + 1] - g.x[ei], hy = g.y[ej + 1] - g.y[ej], hz = g.z[ek + 1] - g.z[ek];
+          d += hb2m * inv_mass[e] * (hy * hz / hx + hx * hz / hy + hx * hy / hz) * (1.0 / 9.0);
+          d += hx * hy * hz * (1.0 / 27.0) * fmax(v0[e] - phi[n] - sigma, 0.0);
+        }
+    dinv[n] = d > 0.0 ? 1.0 / d : 0.0;
+  }
+}
+
+// Starting block: SplitMix64 (Steele, Lea, Flood 2014) of (seed, column,
+// node) mapped to [-1, 1), zero on fixed nodes.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_sch_rand(long N, int ncol, uint64_t seed,
+                                                         const uint8_t* __restrict__ mask, double* __restrict__ X) {
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x)
+    for (int c = 0; c < ncol; ++c) {
+      const uint64_t r = splitmix64(seed ^ splitmix64((uint64_t)c * 0x100000001B3ull + (uint64_t)n));
+      const double u = (double)(r >> 11) * (1.0 / 9007199254740992.0);   // [0, 1)
+      X[(long)c * N + n] = mask[n] ? 0.0 : 2.0 * u - 1.0;
+    }
+}
+
+struct ColMap {
+  int n;
+  int src[kMaxCols];
+  int dst[kMaxCols];
+  double lam[kMaxCols];
+};
+
+// Per block and column c of the map: partial sums of |r|^2, |H'x|^2, |Mx|^2
+// with r = H'x - lam M x (blockIdx.y = column).
+__global__ __launch_bounds__(kVecThreads) void k_sch_norms(long N, ColMap cm, const double* __restrict__ HX,
+                                                          const double* __restrict__ MX, double* __restrict__ part) {
+  __shared__ double sred[kVecThreads / 64];
+  const int c = blockIdx.y;
+  const long o = (long)cm.src[c] * N;
+  const double lam = cm.lam[c];
+  double r2 = 0.0, h2 = 0.0, m2 = 0.0;
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
+    const double h = HX[o + n], m = MX[o + n];
+    const double r = h - lam * m;
+    r2 += r * r;
+    h2 += h * h;
+    m2 += m * m;
+  }
+  const double a = block_sum(r2, sred), b = block_sum(h2, sred), d = block_sum(m2, sred);
+  if (threadIdx.x == 0) {
+    double* p = part + ((long)c * 3) * gridDim.x + blockIdx.x;
+    p[0] = a;
+    p[gridDim.x] = b;
+    p[2 * gridDim.x] = d;
+  }
+}
+
+// out[c] = sum of the gridDim-wide partial rows (fixed order), one block per row.
+__global__ __launch_bounds__(kVecThreads) void k_sch_rowsum(const double* __restrict__ part, int nper,
+                                                           double* __restrict__ out) {
+  __shared__ double sred[kVecThreads / 64];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nper; i += blockDim.x) a += part[(long)blockIdx.x * nper + i];
+  const double s = block_sum(a, sred);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// W[dst] = D^-1 (H'x - lam M x) for the mapped columns.
+__global__ __launch_bounds__(kVecThreads) void k_sch_precond(long N, ColMap cm, const double* __restrict__ HX,
+                                                            const double* __restrict__ MX,
+                                                            const double* __restrict__ dinv, double* __restrict__ Z) {
+  const int c = blockIdx.y;
+  const long o = (long)cm.src[c] * N, d = (long)cm.dst[c] * N;
+  const double lam = cm.lam[c];
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x)
+    Z[d + n] = dinv[n] * (HX[o + n] - lam * MX[o + n]);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_sch_square(long n, const double* __restrict__ a,
+                                                           double* __restrict__ b) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    b[i] = a[i] * a[i];
+}
+
+// ---------------------------------------------------------------- host side
+// Cyclic Jacobi eigenvalues of the symmetric k x k matrix A (row-major, in
+// place); V receives the eigenvectors as columns, w the eigenvalues.
+static void jacobi_eig(int k, std::vector<double>& A, std::vector<double>& V, std::vector<double>& w) {
+  V.assign((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
+  double norm = 0.0;
+  for (double a : A) norm += a * a;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) off += 2.0 * A[(size_t)p * k + q] * A[(size_t)p * k + q];
+    if (off <= 1e-30 * norm) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = A[(size_t)p * k + q];
+        if (apq == 0.0) continue;
+        const double app = A[(size_t)p * k + p], aqq = A[(size_t)q * k + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < k; ++r) {   // A <- A J (columns p, q)
+          const double arp = A[(size_t)r * k + p], arq = A[(size_t)r * k + q];
+          A[(size_t)r * k + p] = c * arp - s * arq;
+          A[(size_t)r * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {   // A <- J^T A (rows p, q)
+          const double apr = A[(size_t)p * k + r], aqr = A[(size_t)q * k + r];
+          A[(size_t)p * k + r] = c * apr - s * aqr;
+          A[(size_t)q * k + r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = V[(size_t)r * k + p], vrq = V[(size_t)r * k + q];
+          V[(size_t)r * k + p] = c * vrp - s * vrq;
+          V[(size_t)r * k + q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  w.resize(k);
+  for (int i = 0; i < k; ++i) w[i] = A[(size_t)i * k + i];
+}
+
+// Rayleigh-Ritz on the k x k pencil (GA, GB) (column-major, symmetric):
+// the nb lowest eigenvalues into lam and the coefficient matrix C (k x nb,
+// column-major) with C^T GB C = I.  False if GB is not numerically SPD.
+static bool rayleigh_ritz(int k, int nb, const double* GA, const double* GB, std::vector<double>& lam,
+                          std::vector<double>& C) {
+  std::vector<double> d(k), B((size_t)k * k), A((size_t)k * k), L((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    const double b = GB[(size_t)i * k + i];
+    if (!(b > 0.0) || !std::isfinite(b)) return false;
+    d[i] = 1.0 / std::sqrt(b);
+  }
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      // symmetrised and scaled to a unit diagonal of B
+      B[(size_t)i * k + j] = 0.5 * (GB[(size_t)j * k + i] + GB[(size_t)i * k + j]) * d[i] * d[j];
+      A[(size_t)i * k + j] = 0.5 * (GA[(size_t)j * k + i] + GA[(size_t)i * k + j]) * d[i] * d[j];
+    }
+  for (int j = 0; j < k; ++j) {   // B = L L^T
+    double s = B[(size_t)j * k + j];
+    for (int t = 0; t < j; ++t) s -= L[(size_t)j * k + t] * L[(size_t)j * k + t];
+    if (!(s > 1e-13)) return false;
+    L[(size_t)j * k + j] = std::sqrt(s);
+    for (int i = j + 1; i < k; ++i) {
+      double r = B[(size_t)i * k + j];
+      for (int t = 0; t < j; ++t) r -= L[(size_t)i * k + t] * L[(size_t)j * k + t];
+      L[(size_t)i * k + j] = r / L[(size_t)j * k + j];
+    }
+  }
+  // A' = L^-1 A L^-T: solve L Y = A, then L A'^T = Y^T
+  std::vector<double> Y((size_t)k * k);
+  for (int c = 0; c < k; ++c)
+    for (int i = 0; i < k; ++i) {
+      double r = A[(size_t)i * k + c];
+      for (int t = 0; t < i; ++t) r -= L[(size_t)i * k + t] * Y[(size_t)t * k + c];
+      Y[(size_t)i * k + c] = r / L[(size_t)i * k + i];
+    }
+  std::vector<double> Ap((size_t)k * k);
+  for (int c = 0; c < k; ++c)
+    for (int i = 0; i < k; ++i) {
+      double r = Y[(size_t)c * k + i];
+      for (int t = 0; t < i; ++t) r -= L[(size_t)i * k + t] * Ap[(size_t)c * k + t];
+      Ap[(size_t)c * k + i] = r / L[(size_t)i * k + i];
+    }
+  for (int i = 0; i < k; ++i)
+    for (int j = i + 1; j < k; ++j) {
+      const double m = 0.5 * (Ap[(size_t)i * k + j] + Ap[(size_t)j * k + i]);
+      Ap[(size_t)i * k + j] = Ap[(size_t)j * k + i] = m;
+    }
+  std::vector<double> V, w;
+  jacobi_eig(k, Ap, V, w);
+  std::vector<int> ord(k);
+  for (int i = 0; i < k; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a] < w[b]; });
+  lam.resize(nb);
+  C.assign((size_t)k * nb, 0.0);
+  for (int c = 0; c < nb; ++c) {
+    lam[c] = w[ord[c]];
+    // C = D L^-T v: back substitution with L^T
+    for (int i = k - 1; i >= 0; --i) {
+      double r = V[(size_t)i * k + ord[c]];
+      for (int t = i + 1; t < k; ++t) r -= L[(size_t)t * k + i] * C[(size_t)c * k + t];
+      C[(size_t)c * k + i] = r / L[(size_t)i * k + i];
+    }
+    for (int i = 0; i < k; ++i) C[(size_t)c * k + i] *= d[i];
+  }
+  return true;
+}
+
+struct SchLayout {
+  size_t eH, eM, cH, cM, rdz, cbits, mask, dinv, Z, HZ, MZ, P, HP, MP, Xn, HXn, MXn, G, C, part, sums, flags;
+  size_t total;
+};
+
+static SchLayout sch_layout(long N, long nslots, int nz, long nwaves, int nb) {
+  SchLayout L;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off = (off + b + 255) & ~size_t(255);
+    return o;
+  };
+  const int K = 3 * nb;
+  L.eH = take(nslots * 8);
+  L.eM = take(nslots * 8);
+  L.cH = take(nslots * 64);
+  L.cM = take(nslots * 64);
+  L.rdz = take((size_t)(nz - 1) * 8);
+  L.cbits = take(nwaves * 64 * 4);
+  L.mask = take(N);
+  L.dinv = take(N * 8);
+  L.Z = take((size_t)K * N * 8);
+  L.HZ = take((size_t)K * N * 8);
+  L.MZ = take((size_t)K * N * 8);
+  L.P = take((size_t)nb * N * 8);
+  L.HP = take((size_t)nb * N * 8);
+  L.MP = take((size_t)nb * N * 8);
+  L.Xn = take((size_t)nb * N * 8);
+  L.HXn = take((size_t)nb * N * 8);
+  L.MXn = take((size_t)nb * N * 8);
+  L.G = take((size_t)2 * K * K * 8);
+  L.C = take((size_t)K * nb * 8);
+  L.part = take((size_t)kSchBlocks * 3 * kMaxCols * 8);
+  L.sums = take((size_t)3 * kMaxCols * 8);
+  L.flags = take(64);
+  L.total = off;
+  return L;
+}
+
+static bool mesh_ok(const qe_problem* p) {
+  return p && p->nx >= 2 && p->ny >= 2 && p->nz >= 2 && p->x && p->y && p->z &&
+         (long)p->nx * p->ny * p->nz <= (1L << 31) - 1;
+}
+
+static rocblas_handle blas_handle() {
+  static thread_local rocblas_handle h = nullptr;
+  if (!h && rocblas_create_handle(&h) != rocblas_status_success) h = nullptr;
+  return h;
+}
+
+}  // namespace qe
+
+using namespace qe;
+
+extern "C" {
+
+size_t qe_schrodinger_workspace_bytes(const qe_problem* p, int32_t n_states) {
+  if (!mesh_ok(p) || n_states < 1 || n_states > QE_MAX_EIG) return 0;
+  const long N = (long)p->nx * p->ny * p->nz;
+  const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, 0);
+  return sch_layout(N, tile_slots(p->nx, p->ny, p->nz), p->nz, wm.nwaves, n_states + 2).total;
+}
+
+qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, const double* phi, int32_t n_states,
+                               double tol, int32_t maxit, uint64_t seed, double* E, double* psi, double* psi2,
+                               int32_t* iters, void* ws_, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!mesh_ok(p)) return fail(QE_ERR_INVALID_ARG, "bad mesh (nx, ny, nz >= 2 and x, y, z needed)");
+  if (!sp || !sp->inv_mass || !sp->v0) return fail(QE_ERR_INVALID_ARG, "inv_mass / v0 is NULL");
+  if (!phi || !E || !psi) return fail(QE_ERR_INVALID_ARG, "phi / E / psi is NULL");
+  if (n_states < 1 || n_states > QE_MAX_EIG) return fail(QE_ERR_INVALID_ARG, "n_states outside [1, %d]", QE_MAX_EIG);
+  if (!(tol > 0.0 && tol < 1.0)) return fail(QE_ERR_INVALID_ARG, "tol must be in (0, 1)");
+  if (maxit < 1) return fail(QE_ERR_INVALID_ARG, "maxit < 1");
+  const long N = (long)p->nx * p->ny * p->nz, Ecount = (long)(p->nx - 1) * (p->ny - 1) * (p->nz - 1);
+  const int nb = n_states + 2, K = 3 * nb;
+  if (N < 4L * nb) return fail(QE_ERR_INVALID_ARG, "mesh too small for %d states", n_states);
+  Geom g{p->nx, p->ny, p->nz, p->x, p->y, p->z, nullptr};
+  const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, 0);
+  const long nslots = tile_slots(p->nx, p->ny, p->nz);
+  const SchLayout L = sch_layout(N, nslots, p->nz, wm.nwaves, nb);
+  if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total) return fail(QE_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  char* ws = reinterpret_cast<char*>(ws_);
+  hipStream_t s = (hipStream_t)stream;
+  rocblas_handle bh = blas_handle();
+  if (!bh) return fail(QE_ERR_HIP, "rocBLAS handle creation failed");
+  if (rocblas_set_stream(bh, s) != rocblas_status_success) return fail(QE_ERR_HIP, "rocblas_set_stream failed");
+  auto f64 = [&](size_t o) { return reinterpret_cast<double*>(ws + o); };
+  auto ck = [&](hipError_t e, const char* what) -> qe_status {
+    return e == hipSuccess ? QE_OK : fail(QE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  };
+  const int vb = vec_blocks(N);
+  // ---- checks and the shift sigma below every V
+  int* dflags = reinterpret_cast<int*>(ws + L.flags);
+  QE_TRY(ck(hipMemsetAsync(dflags, 0, sizeof(int), s), "memset"));
+  hipLaunchKernelGGL(k_sch_validate, dim3(vb), dim3(kVecThreads), 0, s, Ecount, N, sp->inv_mass, sp->v0, phi, dflags);
+  hipLaunchKernelGGL(k_sch_vmin, dim3(kSchBlocks), dim3(kVecThreads), 0, s, g, sp->v0, phi, f64(L.part));
+  std::vector<double> hp(kSchBlocks);
+  int hf = 0;
+  QE_TRY(ck(hipMemcpyAsync(&hf, dflags, sizeof(int), hipMemcpyDeviceToHost, s), "copy"));
+  QE_TRY(ck(hipMemcpyAsync(hp.data(), f64(L.part), kSchBlocks * 8, hipMemcpyDeviceToHost, s), "copy"));
+  QE_TRY(ck(hipStreamSynchronize(s), "sync"));
+  if (hf & 1) return fail(QE_ERR_INVALID_ARG, "inv_mass must be finite and > 0");
+  if (hf & 2) return fail(QE_ERR_NONFINITE, "v0 not finite");
+  if (hf & 4) return fail(QE_ERR_NONFINITE, "phi not finite");
+  double vmin = INFINITY;
+  for (double v : hp) vmin = std::min(vmin, v);
+  const double sigma = vmin - 0.1;   // eV below every V: H - sigma M is SPD
+  // ---- operators
+  g.rdz = f64(L.rdz);
+  launch_stage_rdz(s, p->nz, p->z, f64(L.rdz));
+  QE_TRY(ck(hipMemsetAsync(ws + L.eM, 0, nslots * 8, s), "memset"));
+  hipLaunchKernelGGL(k_sch_coef, dim3(vb), dim3(kVecThreads), 0, s, g, sp->inv_mass, sp->v0, phi, sigma, kHB2M,
+                     f64(L.eH), f64(L.cH), f64(L.cM));
+  hipLaunchKernelGGL(k_sch_bits, dim3(wm.nblocks), dim3(256), 0, s, g, wm, reinterpret_cast<unsigned int*>(ws + L.cbits));
+  uint8_t* mask = reinterpret_cast<uint8_t*>(ws + L.mask);
+  if (sp->fixed)
+    QE_TRY(ck(hipMemcpyAsync(mask, sp->fixed, N, hipMemcpyDeviceToDevice, s), "copy"));
+  else
+    QE_TRY(ck(hipMemsetAsync(mask, 0, N, s), "memset"));
+  hipLaunchKernelGGL(k_sch_diag, dim3(vb), dim3(kVecThreads), 0, s, g, sp->inv_mass, sp->v0, phi, mask, sigma, kHB2M,
+                     f64(L.dinv));
+  const unsigned int* cbits = reinterpret_cast<const unsigned int*>(ws + L.cbits);
+  auto applyH = [&](const double* v, double* y) {
+    launch_jv_wave64(s, g, wm, f64(L.eH), cbits, f64(L.cH), mask, v, y, 2);
+  };
+  auto applyM = [&](const double* v, double* y) {
+    launch_jv_wave64(s, g, wm, f64(L.eM), cbits, f64(L.cM), mask, v, y, 2);
+  };
+  double *Z = f64(L.Z), *HZ = f64(L.HZ), *MZ = f64(L.MZ);
+  auto col = [&](double* base, int c) { return base + (long)c * N; };
+  const double one = 1.0, zero = 0.0;
+  std::vector<double> hG(2 * (size_t)K * K), lam, Cm;
+  // Gram matrices of the first k columns, Rayleigh-Ritz, and the new X (and
+  // P from columns nb.. when with_p).
+  auto rr_update = [&](int k, bool with_p) -> qe_status {
+    double* G = f64(L.G);
+    if (rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, k, k, (int)N, &one, Z, (int)N, HZ,
+                      (int)N, &zero, G, k) != rocblas_status_success ||
+        rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, k, k, (int)N, &one, Z, (int)N, MZ,
+                      (int)N, &zero, G + (size_t)k * k, k) != rocblas_status_success)
+      return fail(QE_ERR_HIP, "rocblas_dgemm (Gram) failed");
+    QE_TRY(ck(hipMemcpyAsync(hG.data(), G, 2 * (size_t)k * k * 8, hipMemcpyDeviceToHost, s), "copy"));
+    QE_TRY(ck(hipStreamSynchronize(s), "sync"));
+    if (!rayleigh_ritz(k, nb, hG.data(), hG.data() + (size_t)k * k, lam, Cm)) return QE_ERR_KRYLOV_BREAKDOWN;
+    QE_TRY(ck(hipMemcpyAsync(f64(L.C), Cm.data(), Cm.size() * 8, hipMemcpyHostToDevice, s), "copy"));
+    const double* C = f64(L.C);
+    double* outs[3] = {f64(L.Xn), f64(L.HXn), f64(L.MXn)};
+    double* srcs[3] = {Z, HZ, MZ};
+    double* pout[3] = {f64(L.P), f64(L.HP), f64(L.MP)};
+    for (int t = 0; t < 3; ++t) {
+      if (rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)N, nb, k, &one, srcs[t], (int)N, C, k,
+                        &zero, outs[t], (int)N) != rocblas_status_success)
+        return fail(QE_ERR_HIP, "rocblas_dgemm (update) failed");
+      if (with_p && rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)N, nb, k - nb, &one,
+                                  srcs[t] + (long)nb * N, (int)N, C + nb, k, &zero, pout[t],
+                                  (int)N) != rocblas_status_success)
+        return fail(QE_ERR_HIP, "rocblas_dgemm (update) failed");
+    }
+    for (int t = 0; t < 3; ++t)
+      QE_TRY(ck(hipMemcpyAsync(srcs[t], outs[t], (size_t)nb * N * 8, hipMemcpyDeviceToDevice, s), "copy"));
+    return QE_OK;
+  };
+  // ---- starting block
+  hipLaunchKernelGGL(k_sch_rand, dim3(vb), dim3(kVecThreads), 0, s, N, nb, seed, mask, Z);
+  for (int c = 0; c < nb; ++c) {
+    applyH(col(Z, c), col(HZ, c));
+    applyM(col(Z, c), col(MZ, c));
+  }
+  qe_status st = rr_update(nb, false);
+  if (st != QE_OK) return st == QE_ERR_KRYLOV_BREAKDOWN ? fail(st, "starting block is rank deficient") : st;
+  bool have_p = false;
+  int it = 0;
+  std::vector<double> sums(3 * kMaxCols);
+  std::vector<int> active;
+  bool converged = false;
+  for (it = 1; it <= maxit; ++it) {
+    // residual norms of every column
+    ColMap cm;
+    std::memset(&cm, 0, sizeof(cm));
+    cm.n = nb;
+    for (int c = 0; c < nb; ++c) {
+      cm.src[c] = c;
+      cm.lam[c] = lam[c];
+    }
+    hipLaunchKernelGGL(k_sch_norms, dim3(kSchBlocks, nb), dim3(kVecThreads), 0, s, N, cm, HZ, MZ, f64(L.part));
+    hipLaunchKernelGGL(k_sch_rowsum, dim3(3 * nb), dim3(kVecThreads), 0, s, f64(L.part), kSchBlocks, f64(L.sums));
+    QE_TRY(ck(hipMemcpyAsync(sums.data(), f64(L.sums), 3 * nb * 8, hipMemcpyDeviceToHost, s), "copy"));
+    QE_TRY(ck(hipStreamSynchronize(s), "sync"));
+    active.clear();
+    bool done = true;
+    for (int c = 0; c < nb; ++c) {
+      const double r = std::sqrt(sums[3 * c]), h = std::sqrt(sums[3 * c + 1]), m = std::sqrt(sums[3 * c + 2]);
+      const double rel = r / std::max(h + std::fabs(lam[c]) * m, 1e-300);
+      if (!std::isfinite(rel)) return fail(QE_ERR_NONFINITE, "non-finite residual in the eigensolver");
+      if (rel > tol) {
+        active.push_back(c);
+        if (c < n_states) done = false;
+      }
+    }
+    if (done) {
+      converged = true;
+      break;
+    }
+    if (it == maxit) break;
+    // W = D^-1 R for the active columns, after X in Z; P's active columns after W
+    const int na = (int)active.size();
+    ColMap wmap;
+    std::memset(&wmap, 0, sizeof(wmap));
+    wmap.n = na;
+    for (int a = 0; a < na; ++a) {
+      wmap.src[a] = active[a];
+      wmap.dst[a] = nb + a;
+      wmap.lam[a] = lam[active[a]];
+    }
+    hipLaunchKernelGGL(k_sch_precond, dim3(kSchBlocks, na), dim3(kVecThreads), 0, s, N, wmap, HZ, MZ, f64(L.dinv), Z);
+    for (int a = 0; a < na; ++a) {
+      applyH(col(Z, nb + a), col(HZ, nb + a));
+      applyM(col(Z, nb + a), col(MZ, nb + a));
+    }
+    int k = nb + na;
+    if (have_p) {
+      for (int a = 0; a < na; ++a) {
+        const size_t bytes = (size_t)N * 8;
+        QE_TRY(ck(hipMemcpyAsync(col(Z, k + a), col(f64(L.P), active[a]), bytes, hipMemcpyDeviceToDevice, s), "copy"));
+        QE_TRY(ck(hipMemcpyAsync(col(HZ, k + a), col(f64(L.HP), active[a]), bytes, hipMemcpyDeviceToDevice, s), "copy"));
+        QE_TRY(ck(hipMemcpyAsync(col(MZ, k + a), col(f64(L.MP), active[a]), bytes, hipMemcpyDeviceToDevice, s), "copy"));
+      }
+      st = rr_update(k + na, true);
+      if (st == QE_ERR_KRYLOV_BREAKDOWN) st = rr_update(k, true);   // drop P when [X W P] lost rank
+    } else {
+      st = rr_update(k, true);
+    }
+    if (st == QE_ERR_KRYLOV_BREAKDOWN) return fail(st, "the LOBPCG basis lost rank at iteration %d", it);
+    if (st != QE_OK) return st;
+    have_p = true;
+  }
+  // ---- results: X's first n_states columns
+  for (int c = 0; c < n_states; ++c) E[c] = lam[c] + sigma;
+  QE_TRY(ck(hipMemcpyAsync(psi, Z, (size_t)n_states * N * 8, hipMemcpyDeviceToDevice, s), "copy"));
+  if (psi2) hipLaunchKernelGGL(k_sch_square, dim3(vb), dim3(kVecThreads), 0, s, (long)n_states * N, Z, psi2);
+  QE_TRY(ck(hipGetLastError(), "launch"));
+  QE_TRY(ck(hipStreamSynchronize(s), "sync"));
+  if (iters) *iters = it;
+  return converged ? QE_OK : fail(QE_ERR_NOT_CONVERGED, "eigensolver hit maxit (%d)", maxit);
+}
+
+}  // extern "C"

@@ -139,7 +139,8 @@ struct WaveTile {
 // tile-major order (tile_slot); cflag marks the elements whose Gauss-point
 // coefficients are not all exactly zero, and only those read cq (a zero
 // coefficient adds exactly nothing).  Modes:
-//   JV_PLAIN  y = J v with v read as 0 on Dirichlet nodes; identity_rows:
+//   JV_PLAIN  y = J v with v read as 0 on Dirichlet nodes; identity_rows
+//             (1: y = v on Dirichlet rows, 2: y = 0 there):
 //             Dirichlet rows return v_i.
 //   JV_DOT    v = a CG direction (zero on Dirichlet nodes); y = J v on every
 //             owned row; dot += v^T J v over the elements this wave owns.
@@ -289,7 +290,7 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
         p[n] = pv;
         dot += (double)pv * (double)val;
       }
-      if (kPlain && mk && identity_rows) val = v[n];
+      if (kPlain && mk && identity_rows) val = identity_rows == 1 ? v[n] : T(0);
       y[n] = val;
     }
     carry = top;
@@ -381,7 +382,8 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
         for (int k = 0; k < 8; ++k) src[k] = ve[k];
         gauss_interp(src);
         double nq[8], dnq[8];
-        if constexpr (kQ) {
+        const bool qel = kQ && (!qm->region || qm->region[el]);   // electrons from the states
+        if (qel) {
           // predictor-corrector electrons: |psi_i|^2 and phi^(k) interpolated
           // to the Gauss points like phi
           const long b0 = w.n00 + w.sxy * L;
@@ -414,7 +416,7 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           double rho, drho;
-          if constexpr (kQ)
+          if (qel)
             space_charge_n(ch, src[q], nq[q], dnq[q], net, ndo, nac, rho, drho);
           else
             space_charge(ch, src[q], net, ndo, nac, rho, drho);

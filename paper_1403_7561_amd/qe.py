@@ -30,7 +30,7 @@ EXPORTED = [
     "qe_default_options", "qe_workspace_bytes", "qe_solve", "qe_residual", "qe_jv",
     "qe_jv_f32", "qe_count_electrons", "qe_density", "qe_adjoint",
     "qe_batch_workspace_bytes", "qe_solve_batch", "qe_time_jv", "qe_ohmic_potential",
-    "qe_last_error",
+    "qe_schrodinger_workspace_bytes", "qe_schrodinger_solve", "qe_last_error",
 ]
 
 # Silicon parameters of Sec. II.A.3: band gap, phosphorus / boron ionization
@@ -56,7 +56,12 @@ class CSheet(ctypes.Structure):
 
 class CQuantum(ctypes.Structure):
     _fields_ = [("n_states", ctypes.c_int32), ("confinement", ctypes.c_int32), ("psi2", ctypes.c_void_p),
-                ("phi_k", ctypes.c_void_p), ("E_i", ctypes.POINTER(ctypes.c_double)), ("m_t", ctypes.c_double)]
+                ("phi_k", ctypes.c_void_p), ("E_i", ctypes.POINTER(ctypes.c_double)), ("m_t", ctypes.c_double),
+                ("region", ctypes.c_void_p)]
+
+
+class CSchrodinger(ctypes.Structure):
+    _fields_ = [("inv_mass", ctypes.c_void_p), ("v0", ctypes.c_void_p), ("fixed", ctypes.c_void_p)]
 
 
 class CProblem(ctypes.Structure):
@@ -123,6 +128,9 @@ def load_library(path=LIB_PATH):
                                  V, S, V, pr]),
         "qe_time_jv": (I32, [pp, pph, V, V, I32, I32, P(D), P(ctypes.c_int64), V, S, V]),
         "qe_ohmic_potential": (I32, [pph, D, D, D, P(D)]),
+        "qe_schrodinger_workspace_bytes": (S, [pp, I32]),
+        "qe_schrodinger_solve": (I32, [pp, P(CSchrodinger), V, I32, D, I32, ctypes.c_uint64, P(D), V, V,
+                                       P(I32), V, S, V]),
         "qe_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -236,8 +244,12 @@ class Problem:
             self.q_phik = torch.as_tensor(np.ascontiguousarray(q.phi_k, dtype=np.float64), **f64)
             E = np.ascontiguousarray(q.E_i, dtype=np.float64)
             self.q_E = (ctypes.c_double * E.size)(*E.tolist())
+            reg = getattr(q, "region", None)
+            self.q_region = None if reg is None else torch.as_tensor(
+                np.ascontiguousarray(reg, dtype=np.uint8), device=device)
             self.c_quantum = CQuantum(int(E.size), int(q.confinement), self.q_psi2.data_ptr(),
-                                      self.q_phik.data_ptr(), self.q_E, float(q.m_t))
+                                      self.q_phik.data_ptr(), self.q_E, float(q.m_t),
+                                      self.q_region.data_ptr() if self.q_region is not None else None)
         self.device = device
 
     def c(self):
@@ -430,3 +442,33 @@ def qe_ohmic_potential(phys, N_D, N_A, V_a=0.0):
     _check(load_library().qe_ohmic_potential(ctypes.byref(phys.c()), float(N_D), float(N_A), float(V_a),
                                               ctypes.byref(out)))
     return out.value
+
+
+def qe_schrodinger_solve(prob, inv_mass, v0, phi, n_states, fixed=None, tol=1e-8, maxit=500, seed=1,
+                         want_psi2=True, ws=None, check=True):
+    """Lowest eigenpairs of the effective-mass Schrodinger problem on the
+    problem's mesh: V = v0_e - phi.  inv_mass, v0: per element (m0/m*, eV);
+    fixed: per node booleans (psi = 0) or None.  Returns (E [n] eV, psi
+    [n, N], psi2 [n, N] or None, iterations)."""
+    torch = _torch()
+    lib = load_library()
+    f64 = dict(dtype=torch.float64, device=prob.device)
+    im = torch.as_tensor(np.ascontiguousarray(inv_mass, dtype=np.float64), **f64)
+    vv = torch.as_tensor(np.ascontiguousarray(v0, dtype=np.float64), **f64)
+    fx = None if fixed is None else torch.as_tensor(np.ascontiguousarray(fixed, dtype=np.uint8), device=prob.device)
+    ph = phi if hasattr(phi, "data_ptr") else torch.as_tensor(np.ascontiguousarray(phi, dtype=np.float64), **f64)
+    cp = prob.c()
+    cs = CSchrodinger(im.data_ptr(), vv.data_ptr(), fx.data_ptr() if fx is not None else None)
+    if ws is None:
+        ws = Workspace(lib.qe_schrodinger_workspace_bytes(ctypes.byref(cp), int(n_states)), prob.device)
+    E = np.zeros(int(n_states))
+    psi = torch.empty((int(n_states), prob.N), **f64)
+    psi2 = torch.empty((int(n_states), prob.N), **f64) if want_psi2 else None
+    it = ctypes.c_int32(0)
+    st = lib.qe_schrodinger_solve(ctypes.byref(cp), ctypes.byref(cs), _ptr(ph), int(n_states), float(tol),
+                                  int(maxit), ctypes.c_uint64(int(seed)),
+                                  E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(psi), _ptr(psi2),
+                                  ctypes.byref(it), ws.ptr, ws.nbytes, _stream())
+    if check:
+        _check(st)
+    return E, psi, psi2, it.value

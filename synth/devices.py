@@ -61,12 +61,14 @@ class QuantumStates:
     density: psi2 [n_states, N] nodal |psi_i|^2 (nm^-3 for 3D confinement,
     nm^-1 for 1D), phi_k [N] the potential they were computed in (V), E_i
     [n_states] levels relative to E_F (eV), confinement 3 or 1, m_t the
-    transverse mass (1D form)."""
+    transverse mass (1D form), region the elements whose electrons come from
+    the states (the semiclassical statistics elsewhere; None: everywhere)."""
     psi2: np.ndarray
     phi_k: np.ndarray
     E_i: np.ndarray
     confinement: int = 3
     m_t: float = 0.19
+    region: np.ndarray = None      # [E] quantum-region elements (None: all)
 
 
 @dataclass

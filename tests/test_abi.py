@@ -264,3 +264,23 @@ def test_invalid_quantum_rejected(over, needle):
     st = lib.qe_solve(ctypes.byref(p), ctypes.byref(ph), ctypes.byref(o), ctypes.c_void_p(16),
                       None, ctypes.c_void_p(256), 1 << 40, None, None)
     assert st in (-1, -3) and needle in qe.qe_last_error(), qe.qe_last_error()
+
+
+def test_schrodinger_argument_checks():
+    lib = qe.load_library()
+    p = fake_problem(6, 5, 4)
+    P = ctypes.POINTER(ctypes.c_double)
+    E = np.zeros(20)
+    assert lib.qe_schrodinger_workspace_bytes(ctypes.byref(p), 17) == 0
+    assert lib.qe_schrodinger_workspace_bytes(ctypes.byref(p), 3) > 0
+    s = qe.CSchrodinger(16, 16, None)
+    cases = [(dict(n=0), "n_states"), (dict(n=17), "n_states"), (dict(tol=0.0), "tol"), (dict(tol=1.5), "tol"),
+             (dict(maxit=0), "maxit"), (dict(inv=None), "inv_mass"), (dict(ws=None), "workspace is NULL")]
+    for over, needle in cases:
+        a = dict(n=3, tol=1e-8, maxit=10, inv=16, ws=256)
+        a.update(over)
+        s.inv_mass = a["inv"]
+        st = lib.qe_schrodinger_solve(ctypes.byref(p), ctypes.byref(s), ctypes.c_void_p(16), a["n"], a["tol"],
+                                      a["maxit"], ctypes.c_uint64(1), E.ctypes.data_as(P), ctypes.c_void_p(16),
+                                      None, None, ctypes.c_void_p(a["ws"]) if a["ws"] else None, 1 << 40, None)
+        assert st in (-1, -3) and needle in qe.qe_last_error(), (needle, qe.qe_last_error())

@@ -1,0 +1,156 @@
+"""GPU parity of the effective-mass Schrodinger eigensolver (Sec. II.B, Eqs.
+SchrodEqn, SchrodEqnWeakForm) through the C ABI against the oracle's dense /
+shift-invert generalized eigenproblem on the same mesh and inputs: the 1D
+infinite well (exact discrete levels), an anisotropic 3D box, the finite
+well with unequal masses, and the gate-stack dot in the semiclassical
+potential; eigenvalues to 1e-9 relative, eigenvectors (up to sign) to 1e-5.
+Then one closed predictor-corrector loop."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import schrodinger as sch
+from oracle import solver
+from paper_1403_7561_amd import qe
+from tests import gpu_support as gs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def mesh_problem(x, y, z):
+    nx, ny, nz = len(x), len(y), len(z)
+    E = (nx - 1) * (ny - 1) * (nz - 1)
+    dev = synth.Device(name="mesh", x=np.asarray(x, float), y=np.asarray(y, float), z=np.asarray(z, float),
+                       eps_r=np.ones(E), semi=np.ones(E, np.uint8), net_doping=np.zeros(E),
+                       dir_id=np.full(nx * ny * nz, -1, np.int32), dir_val=np.zeros(0), stat="linear", T_K=0.0)
+    return qe.Problem(dev)
+
+
+def compare(P, inv_mass, v0, phi, fixed, n, tol=1e-10):
+    Eo, psio, (H, M) = sch.solve(P.x.cpu().numpy(), P.y.cpu().numpy(), P.z.cpu().numpy(), inv_mass, v0, phi, fixed, n)
+    E, psi, psi2, it = qe.qe_schrodinger_solve(P, inv_mass, v0, phi, n, fixed=fixed, tol=tol, maxit=2000)
+    print("E gpu", E, "\nE ora", Eo, "iters", it)
+    assert np.allclose(E, Eo, rtol=1e-9, atol=1e-12)
+    ps = psi.cpu().numpy()
+    for i in range(n):
+        d = min(np.abs(ps[i] - psio[i]).max(), np.abs(ps[i] + psio[i]).max()) / np.abs(psio[i]).max()
+        assert d < 1e-5, (i, d)
+    G = ps @ (M @ ps.T)
+    assert np.allclose(G, np.eye(n), atol=1e-10)
+    assert np.array_equal(psi2.cpu().numpy(), ps * ps)
+    assert np.all(ps[:, np.asarray(fixed, bool)] == 0.0)
+    return E, ps, it
+
+
+def test_infinite_well_column():
+    n = 40
+    z = np.linspace(0.0, 20.0, n + 1)
+    P = mesh_problem([0.0, 0.5], [0.0, 0.5], z)
+    fixed = np.zeros(P.N, bool)
+    fixed[:4] = fixed[-4:] = True
+    compare(P, np.full(n, 1 / 0.19), np.zeros(n), np.zeros(P.N), fixed, 4)
+
+
+def test_three_dimensional_box():
+    x, y, z = np.linspace(0, 12, 13), np.linspace(0, 8, 10), np.linspace(0, 6, 8)
+    P = mesh_problem(x, y, z)
+    Z, Y, X = np.meshgrid(np.arange(8), np.arange(10), np.arange(13), indexing="ij")
+    fixed = ((X == 0) | (X == 12) | (Y == 0) | (Y == 9) | (Z == 0) | (Z == 7)).ravel()
+    E_ = 12 * 9 * 7
+    compare(P, np.full(E_, 1.0), np.zeros(E_), np.zeros(P.N), fixed, 5)
+
+
+def test_finite_well_unequal_masses():
+    n = 400
+    z = np.linspace(-40.0, 40.0, n + 1)
+    P = mesh_problem([0.0, 0.5], [0.0, 0.5], z)
+    zc = 0.5 * (z[1:] + z[:-1])
+    well = np.abs(zc) < 10.0
+    fixed = np.zeros(P.N, bool)
+    fixed[:4] = fixed[-4:] = True
+    compare(P, np.where(well, 1 / 0.067, 1.0), np.where(well, 0.0, 0.1), np.zeros(P.N), fixed, 3)
+
+
+def stack_dot(volts=(2.0, 1.8, 0.9, 1.1, 0.7)):
+    dev = gs.ragged_device(volts=volts)
+    _, res = solver.solve(dev, atol=1e-10)
+    ox = dev.semi == 0
+    v0 = np.where(ox, dev.Ec0_eV + 3.1, dev.Ec0_eV)          # SiO2 conduction-band offset 3.1 eV
+    inv_mass = np.where(ox, 1 / 0.5, 1 / 0.19)
+    # psi = 0 on the outer faces of the quantum region: the nodes outside the
+    # box around the plunger P1 (x 0..70, y 60..140, z 40..100 nm)
+    Z, Y, X = np.meshgrid(dev.z, dev.y, dev.x, indexing="ij")
+    inside = (X > 0) & (X < 70) & (Y > 60) & (Y < 140) & (Z > 40) & (Z < 100)
+    return dev, res.phi, inv_mass, v0, ~inside.ravel()
+
+
+def dot_region(dev):
+    """Elements of the quantum region (centroid inside the box of stack_dot)."""
+    xc, yc, zc = [0.5 * (c[1:] + c[:-1]) for c in (dev.x, dev.y, dev.z)]
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    return ((X > 0) & (X < 70) & (Y > 60) & (Y < 140) & (Z > 40) & (Z < 100)).ravel()
+
+
+def test_gate_stack_dot_states():
+    dev, phi, inv_mass, v0, fixed = stack_dot()
+    P = qe.Problem(dev)
+    E, ps, it = compare(P, inv_mass, v0, phi, fixed, 6)
+    assert np.all(np.diff(E) >= 0)
+
+
+def test_predictor_corrector_loop_closes():
+    """The S-P loop of the predictor-corrector method (the four steps listed
+    in Sec. II.C) on the GPU: semiclassical start, then alternately the
+    lowest states in V = E_C(phi^(k)) inside a quantum region around the
+    plunger P1 (psi = 0 on its boundary, the semiclassical electrons outside
+    it) and the predictor Poisson step with their density, until
+    max |phi^(k) - phi^(k-1)| < 1e-5 V.  The same loop run with the oracle's
+    eigenproblem and Newton solve reaches the same fixed point."""
+    volts = (1.5, 1.2, 0.6, 0.7, 0.5)           # a few electrons in the dot
+    dev, phi0, inv_mass, v0, fixed = stack_dot(volts)
+    reg = dot_region(dev)
+    box = (0, 70, 60, 140, 40, 100)
+
+    def loop(eig, poisson, phi):
+        hist = []
+        for _ in range(40):
+            E, psi2 = eig(phi)
+            qdev = synth.with_quantum(dev, synth.QuantumStates(psi2=psi2, phi_k=phi.copy(), E_i=E, region=reg))
+            new, count = poisson(qdev)
+            hist.append(float(np.abs(new - phi).max()))
+            phi = new
+            if hist[-1] < 1e-5:
+                break
+        return phi, E, count, hist
+
+    base = qe.Problem(dev)
+    opts = qe.qe_default_options(newton_atol=1e-10)
+
+    def eig_gpu(phi):
+        E, _, psi2, _ = qe.qe_schrodinger_solve(base, inv_mass, v0, phi, 8, fixed=fixed, tol=1e-10)
+        return E, psi2.cpu().numpy()
+
+    def poisson_gpu(qdev):
+        P = qe.Problem(qdev)
+        phi, _, _ = qe.qe_solve(P, opts=opts)
+        return phi.cpu().numpy(), qe.qe_count_electrons(P, phi, [box])[0]
+
+    def eig_oracle(phi):
+        E, psi, _ = sch.solve(dev.x, dev.y, dev.z, inv_mass, v0, phi, fixed, 8)
+        return E, psi ** 2
+
+    def poisson_oracle(qdev):
+        po, res = solver.solve(qdev, atol=1e-10)
+        return res.phi, po.count(res.phi, box)
+
+    phi_g, E_g, n_g, hist = loop(eig_gpu, poisson_gpu, phi0)
+    print("GPU loop: max |dphi| per outer iteration", hist, "levels", E_g, "electrons", n_g)
+    assert hist[-1] < 1e-5 and len(hist) < 40
+    assert 1.0 < n_g < 16.0
+    phi_o, E_o, n_o, hist_o = loop(eig_oracle, poisson_oracle, phi0)
+    print("oracle loop", hist_o, E_o, n_o)
+    assert np.abs(phi_g - phi_o).max() < 2e-4
+    assert np.allclose(E_g, E_o, atol=2e-4)
+    assert n_g == pytest.approx(n_o, rel=1e-3)

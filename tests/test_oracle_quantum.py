@@ -106,3 +106,19 @@ def test_pc_solution_unique_and_counts_states():
     n = po.count(a.phi, (0, 200, 0, 200, 0, 100))
     assert 0.5 < n < 16.0
     assert po.count(a.phi, (100, 200, 0, 200, 0, 100)) == 0.0
+
+
+def test_quantum_region_selects_the_electron_model():
+    # outside the region the statistics hold: an empty region reproduces the
+    # semiclassical residual, a full one the states-only residual
+    dev, phi0 = pc_stack()
+    E = dev.n_elems
+    rng = np.random.default_rng(9)
+    phi = phi0 + 0.01 * rng.standard_normal(dev.n_nodes)
+    semi = solver.make_problem(synth.Device(**{**dev.__dict__, "quantum": None}))
+    q_all = solver.make_problem(dev)
+    st = dev.quantum
+    none_reg = synth.QuantumStates(st.psi2, st.phi_k, st.E_i, region=np.zeros(E, bool))
+    full_reg = synth.QuantumStates(st.psi2, st.phi_k, st.E_i, region=np.ones(E, bool))
+    assert np.array_equal(solver.make_problem(synth.with_quantum(dev, none_reg)).residual(phi), semi.residual(phi))
+    assert np.array_equal(solver.make_problem(synth.with_quantum(dev, full_reg)).residual(phi), q_all.residual(phi))
