@@ -158,6 +158,44 @@ def predictor_run(synth, qe, torch, dev, P, opts, ws, boxes, phi_sc):
             "max_dphi_vs_phi_k": float((ph - phi_sc).abs().max())}
 
 
+def schrodinger_run(synth, qe, torch, dev, P, opts, phi_sc):
+    """The Schrodinger step on the same stack: the 8 lowest states of a
+    quantum region around the plunger P1 (x 0..70, y 60..140, z 40..100 nm)
+    in V = E_C(phi_sc), from a random start to a relative residual of 1e-8;
+    then the predictor-corrector loop with 16 states (warm starts) until
+    max |phi^(k) - phi^(k-1)| < 1e-5 V or 60 outer iterations."""
+    inv_mass, v0, fixed, region = synth.quantum_region(dev, (0.0, 70.0, 60.0, 140.0, 40.0, 100.0))
+    ws = qe.Workspace(qe.load_library().qe_schrodinger_workspace_bytes(qe.ctypes.byref(P.c()), 16), P.device)
+    qe.qe_schrodinger_solve(P, inv_mass, v0, phi_sc, 8, fixed=fixed, tol=1e-8, maxit=3000, ws=ws)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, psi, _, it = qe.qe_schrodinger_solve(P, inv_mass, v0, phi_sc, 8, fixed=fixed, tol=1e-8, maxit=3000, ws=ws)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    box = (0.0, 70.0, 60.0, 140.0, 40.0, 100.0)
+    t0 = time.perf_counter()
+    phi_k, guess, hist, lob = phi_sc.clone(), None, [], []
+    for _ in range(60):
+        E16, psi16, psi2, it16 = qe.qe_schrodinger_solve(P, inv_mass, v0, phi_k, 16, fixed=fixed, tol=1e-8,
+                                                         maxit=3000, ws=ws, guess=guess)
+        guess = psi16
+        lob.append(it16)
+        st = synth.QuantumStates(psi2=psi2.cpu().numpy(), phi_k=phi_k.cpu().numpy(), E_i=E16, region=region)
+        Pq = qe.Problem(synth.with_quantum(dev, st))
+        new, _, rep = qe.qe_solve(Pq, opts=opts, want_density=False)
+        hist.append(float((new - phi_k).abs().max()))
+        phi_k = new
+        if hist[-1] < 1e-5:
+            break
+    n_dot = qe.qe_count_electrons(Pq, phi_k, [box])[0]
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    return {"eig8_ms": t_eig * 1e3, "eig8_lobpcg_iters": it, "E8_meV": [float(e * 1e3) for e in E],
+            "sp_loop_s": t_loop, "sp_outer_iters": len(hist), "sp_final_dphi_V": hist[-1],
+            "sp_lobpcg_iters": lob, "sp_dot_electrons": float(n_dot),
+            "sp_levels_meV": [float(e * 1e3) for e in E16[:4]]}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -175,6 +213,7 @@ def main():
     ap.add_argument("--no-full-charge", action="store_true")
     ap.add_argument("--no-sheets", action="store_true")
     ap.add_argument("--no-predictor", action="store_true")
+    ap.add_argument("--no-schrodinger", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -321,6 +360,9 @@ def main():
     if not args.no_predictor:
         log("predictor step with 16 synthetic dot states")
         out["predictor_c2"] = predictor_run(synth, qe, torch, dev, P, opts, ws, boxes, phi)
+    if not args.no_schrodinger:
+        log("Schrodinger states and the predictor-corrector loop")
+        out["schrodinger_c2"] = schrodinger_run(synth, qe, torch, dev, P, opts, phi)
     log("cpu baseline")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dev, reps[-1]["newton_iters"])

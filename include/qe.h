@@ -354,9 +354,11 @@ size_t qe_schrodinger_workspace_bytes(const qe_problem* p, int32_t n_states);
  * E: host [n_states] ascending, eV.  psi: device [n_states][N], M-orthonormal,
  * 0 on fixed nodes (sign arbitrary).  psi2: device [n_states][N] or NULL,
  * receives psi^2 (the input of qe_quantum).  iters: host or NULL.
- * seed: the starting block's counter-based random numbers (SplitMix64). */
+ * seed: the starting block's counter-based random numbers (SplitMix64).
+ * guess: nonzero = psi holds starting vectors on entry (e.g. the previous
+ * outer iteration's states; the two guard vectors stay random). */
 qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* s, const double* phi,
-                               int32_t n_states, double tol, int32_t maxit, uint64_t seed,
+                               int32_t n_states, double tol, int32_t maxit, uint64_t seed, int32_t guess,
                                double* E, double* psi, double* psi2, int32_t* iters,
                                void* ws, size_t ws_bytes, void* stream);
 

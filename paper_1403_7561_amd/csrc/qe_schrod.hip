@@ -180,6 +180,13 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_rand(long N, int ncol, uint
     }
 }
 
+__global__ __launch_bounds__(kVecThreads) void k_sch_mask(long N, int ncol, const uint8_t* __restrict__ mask,
+                                                         double* __restrict__ X) {
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x)
+    if (mask[n])
+      for (int c = 0; c < ncol; ++c) X[(long)c * N + n] = 0.0;
+}
+
 struct ColMap {
   int n;
   int src[kMaxCols];
@@ -414,8 +421,8 @@ size_t qe_schrodinger_workspace_bytes(const qe_problem* p, int32_t n_states) {
 }
 
 qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, const double* phi, int32_t n_states,
-                               double tol, int32_t maxit, uint64_t seed, double* E, double* psi, double* psi2,
-                               int32_t* iters, void* ws_, size_t ws_bytes, void* stream) {
+                               double tol, int32_t maxit, uint64_t seed, int32_t guess, double* E, double* psi,
+                               double* psi2, int32_t* iters, void* ws_, size_t ws_bytes, void* stream) {
   clear_error();
   if (!mesh_ok(p)) return fail(QE_ERR_INVALID_ARG, "bad mesh (nx, ny, nz >= 2 and x, y, z needed)");
   if (!sp || !sp->inv_mass || !sp->v0) return fail(QE_ERR_INVALID_ARG, "inv_mass / v0 is NULL");
@@ -516,6 +523,10 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
   };
   // ---- starting block
   hipLaunchKernelGGL(k_sch_rand, dim3(vb), dim3(kVecThreads), 0, s, N, nb, seed, mask, Z);
+  if (guess) {   // the caller's vectors start the first n_states columns (guards stay random)
+    QE_TRY(ck(hipMemcpyAsync(Z, psi, (size_t)n_states * N * 8, hipMemcpyDeviceToDevice, s), "copy"));
+    hipLaunchKernelGGL(k_sch_mask, dim3(vb), dim3(kVecThreads), 0, s, N, n_states, mask, Z);
+  }
   for (int c = 0; c < nb; ++c) {
     applyH(col(Z, c), col(HZ, c));
     applyM(col(Z, c), col(MZ, c));

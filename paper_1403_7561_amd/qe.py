@@ -129,7 +129,7 @@ def load_library(path=LIB_PATH):
         "qe_time_jv": (I32, [pp, pph, V, V, I32, I32, P(D), P(ctypes.c_int64), V, S, V]),
         "qe_ohmic_potential": (I32, [pph, D, D, D, P(D)]),
         "qe_schrodinger_workspace_bytes": (S, [pp, I32]),
-        "qe_schrodinger_solve": (I32, [pp, P(CSchrodinger), V, I32, D, I32, ctypes.c_uint64, P(D), V, V,
+        "qe_schrodinger_solve": (I32, [pp, P(CSchrodinger), V, I32, D, I32, ctypes.c_uint64, I32, P(D), V, V,
                                        P(I32), V, S, V]),
         "qe_last_error": (ctypes.c_char_p, []),
     }
@@ -445,11 +445,12 @@ def qe_ohmic_potential(phys, N_D, N_A, V_a=0.0):
 
 
 def qe_schrodinger_solve(prob, inv_mass, v0, phi, n_states, fixed=None, tol=1e-8, maxit=500, seed=1,
-                         want_psi2=True, ws=None, check=True):
+                         want_psi2=True, ws=None, check=True, guess=None):
     """Lowest eigenpairs of the effective-mass Schrodinger problem on the
     problem's mesh: V = v0_e - phi.  inv_mass, v0: per element (m0/m*, eV);
-    fixed: per node booleans (psi = 0) or None.  Returns (E [n] eV, psi
-    [n, N], psi2 [n, N] or None, iterations)."""
+    fixed: per node booleans (psi = 0) or None; guess: device [n, N] starting
+    vectors or None.  Returns (E [n] eV, psi [n, N], psi2 [n, N] or None,
+    iterations)."""
     torch = _torch()
     lib = load_library()
     f64 = dict(dtype=torch.float64, device=prob.device)
@@ -462,11 +463,11 @@ def qe_schrodinger_solve(prob, inv_mass, v0, phi, n_states, fixed=None, tol=1e-8
     if ws is None:
         ws = Workspace(lib.qe_schrodinger_workspace_bytes(ctypes.byref(cp), int(n_states)), prob.device)
     E = np.zeros(int(n_states))
-    psi = torch.empty((int(n_states), prob.N), **f64)
+    psi = torch.empty((int(n_states), prob.N), **f64) if guess is None else guess.clone()
     psi2 = torch.empty((int(n_states), prob.N), **f64) if want_psi2 else None
     it = ctypes.c_int32(0)
     st = lib.qe_schrodinger_solve(ctypes.byref(cp), ctypes.byref(cs), _ptr(ph), int(n_states), float(tol),
-                                  int(maxit), ctypes.c_uint64(int(seed)),
+                                  int(maxit), ctypes.c_uint64(int(seed)), int(guess is not None),
                                   E.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(psi), _ptr(psi2),
                                   ctypes.byref(it), ws.ptr, ws.nbytes, _stream())
     if check:

@@ -13,6 +13,7 @@ from .devices import (  # noqa: F401
     QuantumStates,
     box_states,
     with_quantum,
+    quantum_region,
     Device,
     stack_z,
     make_stack_device,

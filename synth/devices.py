@@ -422,3 +422,25 @@ def with_quantum(dev, states):
     """A copy of a device whose electrons come from the given states."""
     from dataclasses import replace
     return replace(dev, quantum=states)
+
+
+SIO2_CB_OFFSET_EV = 3.1          # Si/SiO2 conduction-band offset
+M_SI_T, M_OX = 0.19, 0.5         # effective masses (m0): Si transverse, SiO2
+
+
+def quantum_region(dev, box):
+    """Inputs of the Schrodinger step for a quantum region `box` (x0, x1, y0,
+    y1, z0, z1) nm of a gate stack: per-element m0/m* and conduction-band
+    edge at phi = 0 (Ec0 in Si, Ec0 + the band offset in the oxide), the
+    fixed nodes (psi = 0: every node not strictly inside the box) and the
+    region's elements (centroid strictly inside)."""
+    x0, x1, y0, y1, z0, z1 = box
+    ox = np.asarray(dev.semi) == 0
+    v0 = np.where(ox, dev.Ec0_eV + SIO2_CB_OFFSET_EV, dev.Ec0_eV).astype(np.float64)
+    inv_mass = np.where(ox, 1.0 / M_OX, 1.0 / M_SI_T).astype(np.float64)
+    Z, Y, X = np.meshgrid(dev.z, dev.y, dev.x, indexing="ij")
+    inside = (X > x0) & (X < x1) & (Y > y0) & (Y < y1) & (Z > z0) & (Z < z1)
+    xc, yc, zc = [0.5 * (c[1:] + c[:-1]) for c in (dev.x, dev.y, dev.z)]
+    Zc, Yc, Xc = np.meshgrid(zc, yc, xc, indexing="ij")
+    region = (Xc > x0) & (Xc < x1) & (Yc > y0) & (Yc < y1) & (Zc > z0) & (Zc < z1)
+    return inv_mass, v0, ~inside.ravel(), region.ravel()

@@ -281,6 +281,6 @@ def test_schrodinger_argument_checks():
         a.update(over)
         s.inv_mass = a["inv"]
         st = lib.qe_schrodinger_solve(ctypes.byref(p), ctypes.byref(s), ctypes.c_void_p(16), a["n"], a["tol"],
-                                      a["maxit"], ctypes.c_uint64(1), E.ctypes.data_as(P), ctypes.c_void_p(16),
+                                      a["maxit"], ctypes.c_uint64(1), 0, E.ctypes.data_as(P), ctypes.c_void_p(16),
                                       None, None, ctypes.c_void_p(a["ws"]) if a["ws"] else None, 1 << 40, None)
         assert st in (-1, -3) and needle in qe.qe_last_error(), (needle, qe.qe_last_error())

@@ -73,24 +73,18 @@ def test_finite_well_unequal_masses():
     compare(P, np.where(well, 1 / 0.067, 1.0), np.where(well, 0.0, 0.1), np.zeros(P.N), fixed, 3)
 
 
+QBOX = (0.0, 70.0, 60.0, 140.0, 40.0, 100.0)   # quantum region around the plunger P1
+
+
 def stack_dot(volts=(2.0, 1.8, 0.9, 1.1, 0.7)):
     dev = gs.ragged_device(volts=volts)
     _, res = solver.solve(dev, atol=1e-10)
-    ox = dev.semi == 0
-    v0 = np.where(ox, dev.Ec0_eV + 3.1, dev.Ec0_eV)          # SiO2 conduction-band offset 3.1 eV
-    inv_mass = np.where(ox, 1 / 0.5, 1 / 0.19)
-    # psi = 0 on the outer faces of the quantum region: the nodes outside the
-    # box around the plunger P1 (x 0..70, y 60..140, z 40..100 nm)
-    Z, Y, X = np.meshgrid(dev.z, dev.y, dev.x, indexing="ij")
-    inside = (X > 0) & (X < 70) & (Y > 60) & (Y < 140) & (Z > 40) & (Z < 100)
-    return dev, res.phi, inv_mass, v0, ~inside.ravel()
+    inv_mass, v0, fixed, _ = synth.quantum_region(dev, QBOX)
+    return dev, res.phi, inv_mass, v0, fixed
 
 
 def dot_region(dev):
-    """Elements of the quantum region (centroid inside the box of stack_dot)."""
-    xc, yc, zc = [0.5 * (c[1:] + c[:-1]) for c in (dev.x, dev.y, dev.z)]
-    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
-    return ((X > 0) & (X < 70) & (Y > 60) & (Y < 140) & (Z > 40) & (Z < 100)).ravel()
+    return synth.quantum_region(dev, QBOX)[3]
 
 
 def test_gate_stack_dot_states():
@@ -128,8 +122,14 @@ def test_predictor_corrector_loop_closes():
     base = qe.Problem(dev)
     opts = qe.qe_default_options(newton_atol=1e-10)
 
+    prev = {}
+
     def eig_gpu(phi):
-        E, _, psi2, _ = qe.qe_schrodinger_solve(base, inv_mass, v0, phi, 8, fixed=fixed, tol=1e-10)
+        # warm start from the previous outer iteration's states
+        E, psi, psi2, it = qe.qe_schrodinger_solve(base, inv_mass, v0, phi, 8, fixed=fixed, tol=1e-10,
+                                                   guess=prev.get("psi"))
+        prev["psi"] = psi
+        prev.setdefault("iters", []).append(it)
         return E, psi2.cpu().numpy()
 
     def poisson_gpu(qdev):
@@ -146,7 +146,9 @@ def test_predictor_corrector_loop_closes():
         return res.phi, po.count(res.phi, box)
 
     phi_g, E_g, n_g, hist = loop(eig_gpu, poisson_gpu, phi0)
-    print("GPU loop: max |dphi| per outer iteration", hist, "levels", E_g, "electrons", n_g)
+    print("GPU loop: max |dphi| per outer iteration", hist, "levels", E_g, "electrons", n_g,
+          "LOBPCG iterations", prev["iters"])
+    assert max(prev["iters"][3:]) < prev["iters"][0]      # warm starts converge faster
     assert hist[-1] < 1e-5 and len(hist) < 40
     assert 1.0 < n_g < 16.0
     phi_o, E_o, n_o, hist_o = loop(eig_oracle, poisson_oracle, phi0)
