@@ -14,7 +14,8 @@
 // for the active ones and its H', M products, the Gram matrices of
 // [X, W, P] under H' and M (rocBLAS dgemm; FP64 matrix cores), the small
 // generalized eigenproblem on the host (column scaling, Cholesky, cyclic
-// Jacobi), and the new X, P (with their products) as dgemm combinations.
+// Jacobi), and the new X, P (with their products) in one streaming pass
+// (the update is memory bound: k reads and 2 nb writes per row).
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -240,6 +241,66 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_precond(long N, ColMap cm, 
     Z[d + n] = dinv[n] * (HX[o + n] - lam * MX[o + n]);
 }
 
+// The Rayleigh-Ritz update of one operator's block (blockIdx.y: the block
+// vectors Z, H'Z, MZ): X <- Z[:, :k] C, in place in Z's first nb columns, and
+// (with_p) P <- Z[:, nb:k] C[nb:k, :].  C (k x nb, column-major) is staged in
+// LDS; each thread owns whole rows, so reading a row before writing it back
+// is safe.  A streaming pass: k reads and 2 nb writes per row.
+__global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int nb, int with_p,
+                                                           const double* __restrict__ C, double* Z, double* HZ,
+                                                           double* MZ, double* P, double* HP, double* MP) {
+  __shared__ double sc[3 * kMaxCols * kMaxCols];
+  for (int i = threadIdx.x; i < k * nb; i += blockDim.x) sc[i] = C[i];
+  __syncthreads();
+  double* const Zs[3] = {Z, HZ, MZ};
+  double* const Ps[3] = {P, HP, MP};
+  double* const B = Zs[blockIdx.y];
+  double* const Pb = Ps[blockIdx.y];
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
+    double ax[kMaxCols], ap[kMaxCols];
+#pragma unroll
+    for (int c = 0; c < kMaxCols; ++c) ax[c] = ap[c] = 0.0;
+    for (int j0 = 0; j0 < k; j0 += 6) {
+      double z[6];   // six loads in flight before any is used
+#pragma unroll
+      for (int u = 0; u < 6; ++u) z[u] = j0 + u < k ? B[(long)(j0 + u) * N + n] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        const int j = j0 + u;
+        if (j >= k) break;
+        const bool pj = with_p && j >= nb;
+#pragma unroll
+        for (int c = 0; c < kMaxCols; ++c) {
+          if (c < nb) {
+            const double t = z[u] * sc[c * k + j];
+            ax[c] += t;
+            if (pj) ap[c] += t;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxCols; ++c) {
+      if (c < nb) {
+        B[(long)c * N + n] = ax[c];
+        if (with_p) Pb[(long)c * N + n] = ap[c];
+      }
+    }
+  }
+}
+
+// Z[:, dst] <- P[:, src] for the mapped columns, for the three block vectors
+// (blockIdx.y = 3 column + operator).
+__global__ __launch_bounds__(kVecThreads) void k_sch_gather(long N, ColMap cm, const double* __restrict__ P,
+                                                           const double* __restrict__ HP,
+                                                           const double* __restrict__ MP, double* Z, double* HZ,
+                                                           double* MZ) {
+  const int c = blockIdx.y / 3, t = blockIdx.y % 3;
+  const double* src = (t == 0 ? P : t == 1 ? HP : MP) + (long)cm.src[c] * N;
+  double* dst = (t == 0 ? Z : t == 1 ? HZ : MZ) + (long)cm.dst[c] * N;
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) dst[n] = src[n];
+}
+
 __global__ __launch_bounds__(kVecThreads) void k_sch_square(long n, const double* __restrict__ a,
                                                            double* __restrict__ b) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
@@ -357,7 +418,7 @@ static bool rayleigh_ritz(int k, int nb, const double* GA, const double* GB, std
 }
 
 struct SchLayout {
-  size_t eH, eM, cH, cM, rdz, cbits, mask, dinv, Z, HZ, MZ, P, HP, MP, Xn, HXn, MXn, G, C, part, sums, flags;
+  size_t eH, eM, cH, cM, rdz, cbits, mask, dinv, Z, HZ, MZ, P, HP, MP, G, C, part, sums, flags;
   size_t total;
 };
 
@@ -384,9 +445,6 @@ static SchLayout sch_layout(long N, long nslots, int nz, long nwaves, int nb) {
   L.P = take((size_t)nb * N * 8);
   L.HP = take((size_t)nb * N * 8);
   L.MP = take((size_t)nb * N * 8);
-  L.Xn = take((size_t)nb * N * 8);
-  L.HXn = take((size_t)nb * N * 8);
-  L.MXn = take((size_t)nb * N * 8);
   L.G = take((size_t)2 * K * K * 8);
   L.C = take((size_t)K * nb * 8);
   L.part = take((size_t)kSchBlocks * 3 * kMaxCols * 8);
@@ -504,22 +562,10 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
     QE_TRY(ck(hipStreamSynchronize(s), "sync"));
     if (!rayleigh_ritz(k, nb, hG.data(), hG.data() + (size_t)k * k, lam, Cm)) return QE_ERR_KRYLOV_BREAKDOWN;
     QE_TRY(ck(hipMemcpyAsync(f64(L.C), Cm.data(), Cm.size() * 8, hipMemcpyHostToDevice, s), "copy"));
-    const double* C = f64(L.C);
-    double* outs[3] = {f64(L.Xn), f64(L.HXn), f64(L.MXn)};
-    double* srcs[3] = {Z, HZ, MZ};
-    double* pout[3] = {f64(L.P), f64(L.HP), f64(L.MP)};
-    for (int t = 0; t < 3; ++t) {
-      if (rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)N, nb, k, &one, srcs[t], (int)N, C, k,
-                        &zero, outs[t], (int)N) != rocblas_status_success)
-        return fail(QE_ERR_HIP, "rocblas_dgemm (update) failed");
-      if (with_p && rocblas_dgemm(bh, rocblas_operation_none, rocblas_operation_none, (int)N, nb, k - nb, &one,
-                                  srcs[t] + (long)nb * N, (int)N, C + nb, k, &zero, pout[t],
-                                  (int)N) != rocblas_status_success)
-        return fail(QE_ERR_HIP, "rocblas_dgemm (update) failed");
-    }
-    for (int t = 0; t < 3; ++t)
-      QE_TRY(ck(hipMemcpyAsync(srcs[t], outs[t], (size_t)nb * N * 8, hipMemcpyDeviceToDevice, s), "copy"));
-    return QE_OK;
+    const int ub = (int)std::max(1L, std::min((N + kVecThreads - 1) / kVecThreads, 1024L));
+    hipLaunchKernelGGL(k_sch_update, dim3(ub, 3), dim3(kVecThreads), 0, s, N, k, nb, with_p ? 1 : 0,
+                       f64(L.C), Z, HZ, MZ, f64(L.P), f64(L.HP), f64(L.MP));
+    return ck(hipGetLastError(), "update launch");
   };
   // ---- starting block
   hipLaunchKernelGGL(k_sch_rand, dim3(vb), dim3(kVecThreads), 0, s, N, nb, seed, mask, Z);
@@ -584,12 +630,15 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
     }
     int k = nb + na;
     if (have_p) {
+      ColMap pmap;
+      std::memset(&pmap, 0, sizeof(pmap));
+      pmap.n = na;
       for (int a = 0; a < na; ++a) {
-        const size_t bytes = (size_t)N * 8;
-        QE_TRY(ck(hipMemcpyAsync(col(Z, k + a), col(f64(L.P), active[a]), bytes, hipMemcpyDeviceToDevice, s), "copy"));
-        QE_TRY(ck(hipMemcpyAsync(col(HZ, k + a), col(f64(L.HP), active[a]), bytes, hipMemcpyDeviceToDevice, s), "copy"));
-        QE_TRY(ck(hipMemcpyAsync(col(MZ, k + a), col(f64(L.MP), active[a]), bytes, hipMemcpyDeviceToDevice, s), "copy"));
+        pmap.src[a] = active[a];
+        pmap.dst[a] = k + a;
       }
+      hipLaunchKernelGGL(k_sch_gather, dim3(kSchBlocks, 3 * na), dim3(kVecThreads), 0, s, N, pmap, f64(L.P),
+                         f64(L.HP), f64(L.MP), Z, HZ, MZ);
       st = rr_update(k + na, true);
       if (st == QE_ERR_KRYLOV_BREAKDOWN) st = rr_update(k, true);   // drop P when [X W P] lost rank
     } else {

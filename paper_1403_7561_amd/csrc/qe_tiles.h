@@ -247,7 +247,9 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
     const double hz = lane_value(hzl, L - w.Lbeg);    // 1 outside [0, nz-2]
     const double rhz = lane_value(rdzl, L - w.Lbeg);
     // the recurrence mode's y, p (and z) at this layer's owned node, issued
-    // before the prefetches so that their wait does not drain them
+    // before the prefetches so that their wait does not drain them (loading
+    // them a layer ahead too costs registers: spills at 4 waves per SIMD,
+    // measured slower, as is 3 waves per SIMD)
     if (kRec && w.node_ok && L >= w.k0) {
       const long n = w.node(g, L);
       if (rec_old) {
