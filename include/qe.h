@@ -346,7 +346,7 @@ size_t qe_schrodinger_workspace_bytes(const qe_problem* p, int32_t n_states);
  * locally optimal block preconditioned CG) on H - sigma M with sigma below
  * every V (so the operator is SPD), two guard vectors, the Jacobi
  * preconditioner, soft locking of converged vectors, and Rayleigh-Ritz on
- * the block [X, W, P] (Gram matrices by rocBLAS; the small dense generalized
+ * the block [X, W, P] (Gram matrices on the GPU; the small dense generalized
  * eigenproblem on the host).  Operators use the wave-tiled J.v.
  * phi: device [N].  Stops when every wanted pair has
  * ||H x - E M x||_2 <= tol (||H x||_2 + |E| ||M x||_2) or after maxit

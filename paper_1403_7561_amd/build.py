@@ -22,8 +22,7 @@ FLAGS = [
 ]
 
 
-# rocBLAS: the Gram matrices and block updates of the eigensolver (dgemm)
-LIBS = ["-lrocblas"]
+LIBS = []
 
 
 def hipcc():

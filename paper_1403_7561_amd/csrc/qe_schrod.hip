@@ -12,12 +12,12 @@
 // One LOBPCG iteration: residuals R = H'X - M X diag(lambda) and their norms
 // (device), soft locking of converged columns (host decision), W = D^-1 R
 // for the active ones and its H', M products, the Gram matrices of
-// [X, W, P] under H' and M (rocBLAS dgemm; FP64 matrix cores), the small
+// [X, W, P] under H' and M (one pass over the three blocks, LDS-staged
+// register tiles), the small
 // generalized eigenproblem on the host (column scaling, Cholesky, cyclic
 // Jacobi), and the new X, P (with their products) in one streaming pass
 // (the update is memory bound: k reads and 2 nb writes per row).
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -35,6 +35,7 @@ namespace qe {
 static const double kHB2M = 1.054571817e-34 * 1.054571817e-34 / (2.0 * 9.1093837015e-31) / 1.602176634e-19 * 1e18;
 constexpr int kSchBlocks = 256;
 constexpr int kMaxCols = QE_MAX_EIG + 2;
+constexpr int kGramBlocks = 512;   // row ranges of the Gram matrices
 
 // Input checks: bit 1 inv_mass not finite / positive, 2 v0 not finite, 4 phi not finite.
 __global__ __launch_bounds__(kVecThreads) void k_sch_validate(long E, long N, const double* __restrict__ inv_mass,
@@ -289,6 +290,77 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int n
   }
 }
 
+// Both Gram matrices of the block, Z^T H'Z and Z^T MZ (k x k each), per
+// block over its rows: slabs of kGramRows rows of Z, H'Z, MZ are staged in
+// LDS, and each thread accumulates a 4 x 6 register tile of one Gram matrix
+// (consecutive threads share the 4 rows of Z, whose LDS reads broadcast).
+// One partial per block and entry, summed in a fixed order afterwards.
+constexpr int kGramRows = 32, kGramTI = 4, kGramTJ = 6;
+__global__ __launch_bounds__(256) void k_sch_gram(long N, int k, const double* __restrict__ Z,
+                                                  const double* __restrict__ HZ, const double* __restrict__ MZ,
+                                                  double* __restrict__ part) {
+  __shared__ double sz[kGramRows * 3 * kMaxCols], sh[kGramRows * 3 * kMaxCols], sm[kGramRows * 3 * kMaxCols];
+  const int KI = (k + kGramTI - 1) / kGramTI, KJ = (k + kGramTJ - 1) / kGramTJ;
+  const int t = threadIdx.x;
+  const bool worker = t < 2 * KI * KJ;
+  const int g = worker ? t / (KI * KJ) : 0, rest = worker ? t % (KI * KJ) : 0;
+  const int i0 = (rest / KJ) * kGramTI, j0 = (rest % KJ) * kGramTJ;
+  const double* sb = g == 0 ? sh : sm;
+  double acc[kGramTI][kGramTJ];
+#pragma unroll
+  for (int a = 0; a < kGramTI; ++a)
+#pragma unroll
+    for (int b = 0; b < kGramTJ; ++b) acc[a][b] = 0.0;
+  const long per = (N + gridDim.x - 1) / gridDim.x;
+  const long r0 = (long)blockIdx.x * per, r1 = min(N, r0 + per);
+  for (long base = r0; base < r1; base += kGramRows) {
+    const int rows = (int)min((long)kGramRows, r1 - base);
+    __syncthreads();
+    for (int e = t; e < kGramRows * k; e += blockDim.x) {   // e = c * kGramRows + r: coalesced along rows
+      const int c = e / kGramRows, r = e % kGramRows;
+      const bool in = r < rows;
+      const long o = (long)c * N + base + r;
+      sz[r * k + c] = in ? Z[o] : 0.0;
+      sh[r * k + c] = in ? HZ[o] : 0.0;
+      sm[r * k + c] = in ? MZ[o] : 0.0;
+    }
+    __syncthreads();
+    if (worker) {
+      for (int r = 0; r < rows; ++r) {
+        double a[kGramTI], b[kGramTJ];
+#pragma unroll
+        for (int u = 0; u < kGramTI; ++u) a[u] = i0 + u < k ? sz[r * k + i0 + u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kGramTJ; ++u) b[u] = j0 + u < k ? sb[r * k + j0 + u] : 0.0;
+#pragma unroll
+        for (int x = 0; x < kGramTI; ++x)
+#pragma unroll
+          for (int y = 0; y < kGramTJ; ++y) acc[x][y] += a[x] * b[y];
+      }
+    }
+  }
+  if (worker) {
+    double* out = part + ((long)blockIdx.x * 2 + g) * k * k;
+#pragma unroll
+    for (int x = 0; x < kGramTI; ++x)
+#pragma unroll
+      for (int y = 0; y < kGramTJ; ++y)
+        if (i0 + x < k && j0 + y < k) out[(long)(j0 + y) * k + i0 + x] = acc[x][y];   // column-major
+  }
+}
+
+// G[m * len + i] = sum over the n blocks of part[(b * 2 + m) * len + i], for
+// the two matrices m.
+__global__ __launch_bounds__(kVecThreads) void k_sch_sum_parts2(const double* __restrict__ part, int n, int len,
+                                                               double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * len) return;
+  const int m = i / len, e = i % len;
+  double a = 0.0;
+  for (int b = 0; b < n; ++b) a += part[((long)b * 2 + m) * len + e];
+  out[i] = a;
+}
+
 // Z[:, dst] <- P[:, src] for the mapped columns, for the three block vectors
 // (blockIdx.y = 3 column + operator).
 __global__ __launch_bounds__(kVecThreads) void k_sch_gather(long N, ColMap cm, const double* __restrict__ P,
@@ -418,7 +490,7 @@ static bool rayleigh_ritz(int k, int nb, const double* GA, const double* GB, std
 }
 
 struct SchLayout {
-  size_t eH, eM, cH, cM, rdz, cbits, mask, dinv, Z, HZ, MZ, P, HP, MP, G, C, part, sums, flags;
+  size_t eH, eM, cH, cM, rdz, cbits, mask, dinv, Z, HZ, MZ, P, HP, MP, G, gpart, C, part, sums, flags;
   size_t total;
 };
 
@@ -446,6 +518,7 @@ static SchLayout sch_layout(long N, long nslots, int nz, long nwaves, int nb) {
   L.HP = take((size_t)nb * N * 8);
   L.MP = take((size_t)nb * N * 8);
   L.G = take((size_t)2 * K * K * 8);
+  L.gpart = take((size_t)kGramBlocks * 2 * K * K * 8);
   L.C = take((size_t)K * nb * 8);
   L.part = take((size_t)kSchBlocks * 3 * kMaxCols * 8);
   L.sums = take((size_t)3 * kMaxCols * 8);
@@ -459,11 +532,6 @@ static bool mesh_ok(const qe_problem* p) {
          (long)p->nx * p->ny * p->nz <= (1L << 31) - 1;
 }
 
-static rocblas_handle blas_handle() {
-  static thread_local rocblas_handle h = nullptr;
-  if (!h && rocblas_create_handle(&h) != rocblas_status_success) h = nullptr;
-  return h;
-}
 
 }  // namespace qe
 
@@ -500,9 +568,6 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
   if (ws_bytes < L.total) return fail(QE_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
   char* ws = reinterpret_cast<char*>(ws_);
   hipStream_t s = (hipStream_t)stream;
-  rocblas_handle bh = blas_handle();
-  if (!bh) return fail(QE_ERR_HIP, "rocBLAS handle creation failed");
-  if (rocblas_set_stream(bh, s) != rocblas_status_success) return fail(QE_ERR_HIP, "rocblas_set_stream failed");
   auto f64 = [&](size_t o) { return reinterpret_cast<double*>(ws + o); };
   auto ck = [&](hipError_t e, const char* what) -> qe_status {
     return e == hipSuccess ? QE_OK : fail(QE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
@@ -547,17 +612,16 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
   };
   double *Z = f64(L.Z), *HZ = f64(L.HZ), *MZ = f64(L.MZ);
   auto col = [&](double* base, int c) { return base + (long)c * N; };
-  const double one = 1.0, zero = 0.0;
   std::vector<double> hG(2 * (size_t)K * K), lam, Cm;
   // Gram matrices of the first k columns, Rayleigh-Ritz, and the new X (and
   // P from columns nb.. when with_p).
   auto rr_update = [&](int k, bool with_p) -> qe_status {
     double* G = f64(L.G);
-    if (rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, k, k, (int)N, &one, Z, (int)N, HZ,
-                      (int)N, &zero, G, k) != rocblas_status_success ||
-        rocblas_dgemm(bh, rocblas_operation_transpose, rocblas_operation_none, k, k, (int)N, &one, Z, (int)N, MZ,
-                      (int)N, &zero, G + (size_t)k * k, k) != rocblas_status_success)
-      return fail(QE_ERR_HIP, "rocblas_dgemm (Gram) failed");
+    hipLaunchKernelGGL(k_sch_gram, dim3(kGramBlocks), dim3(256), 0, s, N, k, Z, HZ, MZ, f64(L.gpart));
+    // G (both matrices, column-major, one after the other) = fixed-order sum of the block partials
+    hipLaunchKernelGGL(k_sch_sum_parts2, dim3((2 * k * k + kVecThreads - 1) / kVecThreads), dim3(kVecThreads), 0, s,
+                       f64(L.gpart), kGramBlocks, k * k, G);
+    QE_TRY(ck(hipGetLastError(), "Gram launch"));
     QE_TRY(ck(hipMemcpyAsync(hG.data(), G, 2 * (size_t)k * k * 8, hipMemcpyDeviceToHost, s), "copy"));
     QE_TRY(ck(hipStreamSynchronize(s), "sync"));
     if (!rayleigh_ritz(k, nb, hG.data(), hG.data() + (size_t)k * k, lam, Cm)) return QE_ERR_KRYLOV_BREAKDOWN;
