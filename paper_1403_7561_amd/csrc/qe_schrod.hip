@@ -12,8 +12,8 @@
 // One LOBPCG iteration: residuals R = H'X - M X diag(lambda) and their norms
 // (device), soft locking of converged columns (host decision), W = D^-1 R
 // for the active ones and its H', M products, the Gram matrices of
-// [X, W, P] under H' and M (one pass over the three blocks, LDS-staged
-// register tiles), the small
+// [X, W, P] under H' and M (one pass over the three blocks on the FP64
+// matrix cores), the small
 // generalized eigenproblem on the host (column scaling, Cholesky, cyclic
 // Jacobi), and the new X, P (with their products) in one streaming pass
 // (the update is memory bound: k reads and 2 nb writes per row).
@@ -290,29 +290,36 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int n
   }
 }
 
-// Both Gram matrices of the block, Z^T H'Z and Z^T MZ (k x k each), per
-// block over its rows: slabs of kGramRows rows of Z, H'Z, MZ are staged in
-// LDS, and each thread accumulates a 4 x 6 register tile of one Gram matrix
-// (consecutive threads share the 4 rows of Z, whose LDS reads broadcast).
+// Both Gram matrices of the block, Z^T H'Z and Z^T MZ (k x k each, k <= 54),
+// on the FP64 matrix cores: per block over its rows, slabs of kGramRows rows
+// of Z, H'Z and MZ are staged in LDS (columns padded to 64 with zeros), and
+// each wave accumulates 16 x 16 output tiles with v_mfma_f64_16x16x4f64,
+// four rows per instruction.  Operand layout of that instruction (checked on
+// the device): lane l supplies A[l % 16][l / 16] of the 16 x 4 left operand
+// and B[l / 16][l % 16] of the 4 x 16 right one, and holds
+// D[l / 16 + 4 r][l % 16] in accumulator element r.  Waves 0, 1 compute
+// Z^T H'Z, waves 2, 3 Z^T MZ, each two tile rows by up to four tile columns.
 // One partial per block and entry, summed in a fixed order afterwards.
-constexpr int kGramRows = 32, kGramTI = 4, kGramTJ = 6;
+constexpr int kGramRows = 32, kGramLd = 64;
+typedef double qe_v4d __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_sch_gram(long N, int k, const double* __restrict__ Z,
                                                   const double* __restrict__ HZ, const double* __restrict__ MZ,
                                                   double* __restrict__ part) {
-  __shared__ double sz[kGramRows * 3 * kMaxCols], sh[kGramRows * 3 * kMaxCols], sm[kGramRows * 3 * kMaxCols];
-  const int KI = (k + kGramTI - 1) / kGramTI, KJ = (k + kGramTJ - 1) / kGramTJ;
-  const int t = threadIdx.x;
-  const bool worker = t < 2 * KI * KJ;
-  const int g = worker ? t / (KI * KJ) : 0, rest = worker ? t % (KI * KJ) : 0;
-  const int i0 = (rest / KJ) * kGramTI, j0 = (rest % KJ) * kGramTJ;
+  __shared__ double sz[kGramRows * kGramLd], sh[kGramRows * kGramLd], sm[kGramRows * kGramLd];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int e = t; e < kGramRows * kGramLd; e += blockDim.x) sz[e] = sh[e] = sm[e] = 0.0;
+  const int KT = (k + 15) / 16;
+  const int g = wave >> 1;                 // 0: Z^T H'Z, 1: Z^T MZ
+  const int I0 = 2 * (wave & 1);           // this wave's tile rows I0, I0 + 1
   const double* sb = g == 0 ? sh : sm;
-  double acc[kGramTI][kGramTJ];
+  qe_v4d acc[2][4];
 #pragma unroll
-  for (int a = 0; a < kGramTI; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < kGramTJ; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < 4; ++b) acc[a][b] = qe_v4d{0.0, 0.0, 0.0, 0.0};
   const long per = (N + gridDim.x - 1) / gridDim.x;
   const long r0 = (long)blockIdx.x * per, r1 = min(N, r0 + per);
+  const int li = lane & 15, lk = lane >> 4;
   for (long base = r0; base < r1; base += kGramRows) {
     const int rows = (int)min((long)kGramRows, r1 - base);
     __syncthreads();
@@ -320,32 +327,39 @@ __global__ __launch_bounds__(256) void k_sch_gram(long N, int k, const double* _
       const int c = e / kGramRows, r = e % kGramRows;
       const bool in = r < rows;
       const long o = (long)c * N + base + r;
-      sz[r * k + c] = in ? Z[o] : 0.0;
-      sh[r * k + c] = in ? HZ[o] : 0.0;
-      sm[r * k + c] = in ? MZ[o] : 0.0;
+      sz[r * kGramLd + c] = in ? Z[o] : 0.0;
+      sh[r * kGramLd + c] = in ? HZ[o] : 0.0;
+      sm[r * kGramLd + c] = in ? MZ[o] : 0.0;
     }
     __syncthreads();
-    if (worker) {
-      for (int r = 0; r < rows; ++r) {
-        double a[kGramTI], b[kGramTJ];
+    if (I0 < KT) {
+#pragma unroll 2
+      for (int r4 = 0; r4 < kGramRows; r4 += 4) {
+        const int row = r4 + lk;
+        const double a0 = sz[row * kGramLd + I0 * 16 + li];
+        const double a1 = I0 + 1 < KT ? sz[row * kGramLd + (I0 + 1) * 16 + li] : 0.0;
 #pragma unroll
-        for (int u = 0; u < kGramTI; ++u) a[u] = i0 + u < k ? sz[r * k + i0 + u] : 0.0;
-#pragma unroll
-        for (int u = 0; u < kGramTJ; ++u) b[u] = j0 + u < k ? sb[r * k + j0 + u] : 0.0;
-#pragma unroll
-        for (int x = 0; x < kGramTI; ++x)
-#pragma unroll
-          for (int y = 0; y < kGramTJ; ++y) acc[x][y] += a[x] * b[y];
+        for (int J = 0; J < 4; ++J) {
+          if (J < KT) {
+            const double b = sb[row * kGramLd + J * 16 + li];
+            acc[0][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][J], 0, 0, 0);
+            if (I0 + 1 < KT) acc[1][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][J], 0, 0, 0);
+          }
+        }
       }
     }
   }
-  if (worker) {
+  if (I0 < KT) {
     double* out = part + ((long)blockIdx.x * 2 + g) * k * k;
 #pragma unroll
-    for (int x = 0; x < kGramTI; ++x)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int y = 0; y < kGramTJ; ++y)
-        if (i0 + x < k && j0 + y < k) out[(long)(j0 + y) * k + i0 + x] = acc[x][y];   // column-major
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = (I0 + a) * 16 + lk + 4 * r, j = J * 16 + li;
+          if (I0 + a < KT && J < KT && i < k && j < k) out[(long)j * k + i] = acc[a][J][r];   // column-major
+        }
   }
 }
 
@@ -357,7 +371,15 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_sum_parts2(const double* __
   if (i >= 2 * len) return;
   const int m = i / len, e = i % len;
   double a = 0.0;
-  for (int b = 0; b < n; ++b) a += part[((long)b * 2 + m) * len + e];
+  int b = 0;
+  for (; b + 8 <= n; b += 8) {   // eight loads in flight, added in block order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[((long)(b + u) * 2 + m) * len + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a += v[u];
+  }
+  for (; b < n; ++b) a += part[((long)b * 2 + m) * len + e];
   out[i] = a;
 }
 
