@@ -528,7 +528,7 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
       const qe_problem& p = probs[i];
       BatchInst& I = hinst[i];
       const long N = (long)p.nx * p.ny * p.nz, S = tile_slots(p.nx, p.ny, p.nz);
-      I.g = Geom{p.nx, p.ny, p.nz, p.x, p.y, p.z};
+      I.g = Geom{p.nx, p.ny, p.nz, p.x, p.y, p.z, nullptr, nullptr};
       I.eps = p.eps_r;
       I.semi = p.semi;
       I.dop = Doping{p.net_doping, p.donors, p.acceptors};

@@ -40,6 +40,7 @@ struct Geom {
   const double* y;
   const double* z;
   const double* rdz;   // [nz-1] 1 / (z[k+1] - z[k]), staged in the workspace
+  const double* hz;    // [nz-1] z[k+1] - z[k], staged after rdz (NULL where unused)
 };
 
 // Electron statistics constants (derived on the host from CODATA values).

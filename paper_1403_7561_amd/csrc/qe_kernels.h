@@ -56,7 +56,7 @@ void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, cons
                      const int32_t* dir_id, const double* phi, int* flags);
 void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, const double* dir_val, uint8_t* mask,
                   double* phi, int apply, int zero_free);
-// Inverse z spacings into g.rdz's buffer.
+// Inverse z spacings, then the spacings, into g.rdz's buffer (2 (nz - 1) values).
 void launch_stage_rdz(hipStream_t s, int nz, const double* z, double* rdz);
 void launch_cast_d2f(hipStream_t s, int nblocks, long n, const double* a, float* b);
 void launch_masked_copy_d2d(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, double* b);

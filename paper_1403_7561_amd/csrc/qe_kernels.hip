@@ -55,6 +55,21 @@ __device__ __forceinline__ long elem_index(const Geom& g, int ex, int ey, int ez
   return (long)ex + (long)(g.nx - 1) * ((long)ey + (long)(g.ny - 1) * ez);
 }
 
+// Sum over the block of one value per thread, the same in every thread
+// (NT = 0: blockDim.x threads, read from the dispatch packet).
+template <int NT = 0>
+__device__ __forceinline__ double block_sum_all(double a, double* sred) {
+  a = wave_sum(a);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sred[wid] = a;
+  __syncthreads();
+  double r = 0.0;
+  const int nw = ((NT ? NT : (int)blockDim.x) + 63) >> 6;
+  for (int w = 0; w < nw; ++w) r += sred[w];
+  return r;
+}
+
 // Sum of n partials (stride, offset) in a fixed order; the result is the
 // same in every thread of the block.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, int stride, int off,
@@ -70,15 +85,7 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 #pragma unroll
     for (int j = 0; j < 8; ++j) a += v[j];
   }
-  a = wave_sum(a);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sred[wid] = a;
-  __syncthreads();
-  double r = 0.0;
-  const int nw = (blockDim.x + 63) >> 6;
-  for (int w = 0; w < nw; ++w) r += sred[w];
-  return r;  // identical in every thread
+  return block_sum_all(a, sred);
 }
 
 // ---------------------------------------------------------------------------
@@ -127,25 +134,47 @@ __device__ __forceinline__ void post_progress(CgProgress* prog, int iters, int d
 // beta = rz_k / rz_{k-1} and, on the wave tiles, y = J z + beta y,
 // p = z + beta p (JV_REC); one p^T y partial per block.  rz_k goes to
 // ctx->rzs[k & 1] and rz_{k-1} is read from the other slot.
+#ifndef QE_CG_MIN_WAVES
+#define QE_CG_MIN_WAVES 3
+#endif
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_JV_MIN_WAVES, 8))) void k_cg_jv(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_CG_MIN_WAVES, 8))) void k_cg_jv(
     Geom g, WaveMap wm, const T* __restrict__ eps, const unsigned int* __restrict__ cbits,
     const T* __restrict__ cq, const T* __restrict__ z, T* __restrict__ y, T* __restrict__ p, int k,
     PcgCtx* __restrict__ ctx, CgProgress* __restrict__ prog, const double* __restrict__ part_rz, int n_rz,
     double* __restrict__ part_py) {
   if (ctx->done) return;
   __shared__ double sred[4];
+  // the previous kernel's r^T z partials, loaded before anything else so
+  // that waiting for them never waits for the sweep's first loads (the
+  // block size is the constant 256: reading blockDim.x is a load too)
+  constexpr int NT = 256;
+  double rz_part[8];
+  const bool rz_one = n_rz <= 8 * NT;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) rz_part[j] = part_rz[min((int)threadIdx.x + j * NT, n_rz - 1)];
   int wx, wy, wz, wid;
   bool active;
   wave_coords(wm, wx, wy, wz, active, wid);
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
-  const unsigned int cb = active ? cbits[64L * wid + (threadIdx.x & 63)] : 0u;
+  // loaded unconditionally: an idle wave reads the last wave's word, which is
+  // harmless (its lanes own nothing, read zeros and store nothing)
+  const unsigned int cb = cbits[64L * min(wid, wm.nwaves - 1) + (threadIdx.x & 63)];
   int stop_status = PCG_RUNNING, stop_iters = 0;
   double* const sp = sred;
   // pointers captured by value keep their no-alias qualification, so the
   // sweep's z-spacing loads stay scalar
   auto decide = [=, &stop_status, &stop_iters]() -> JvGo<T> {
-    const double RZ = uniform(sum_partials(part_rz, n_rz, 1, 0, sp));
+    double RZ;
+    if (rz_one) {
+      // the same fixed-order sum as sum_partials
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a += ((int)threadIdx.x + j * NT < n_rz) ? rz_part[j] : 0.0;
+      RZ = uniform(block_sum_all<NT>(a, sp));
+    } else {
+      RZ = uniform(sum_partials(part_rz, n_rz, 1, 0, sp));
+    }
     const int it = ctx->iters;
     const double rzprev = ctx->rzs[(k + 1) & 1];
     const bool bad = !isfinite(RZ), conv = !bad && RZ <= ctx->tol2, maxed = it >= ctx->maxit;
@@ -171,7 +200,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_JV_MIN_W
     return {!(bad || conv || maxed), (T)b, first};
   };
   double dot = 0.0;
-  if (!jv_tile<T, JV_REC>(g, w, eps, cb, cq, nullptr, z, y, 1, dot, p, decide)) {  // uniform
+  if (!jv_tile_cg<T>(g, w, wm.kz, eps, cb, cq, z, y, p, dot, decide)) {  // uniform
     // posted after the sweep's code, so no store the sweep's loads must be
     // ordered against precedes them
     if (prog && blockIdx.x == 0 && threadIdx.x == 0) post_progress(prog, stop_iters, 1, stop_status);
@@ -554,11 +583,15 @@ __global__ __launch_bounds__(kVecThreads) void k_stage(long N, const int32_t* __
   }
 }
 
-// Inverse z spacings 1 / (z[k+1] - z[k]) for the element stiffness weights.
+// Inverse z spacings 1 / (z[k+1] - z[k]) for the element stiffness weights,
+// then the spacings themselves (rdz holds 2 (nz - 1) values).
 __global__ __launch_bounds__(kVecThreads) void k_stage_rdz(int nz, const double* __restrict__ z,
                                                           double* __restrict__ rdz) {
-  for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < nz - 1; k += (int)(gridDim.x * blockDim.x))
-    rdz[k] = 1.0 / (z[k + 1] - z[k]);
+  for (int k = (int)(blockIdx.x * blockDim.x + threadIdx.x); k < nz - 1; k += (int)(gridDim.x * blockDim.x)) {
+    const double h = z[k + 1] - z[k];
+    rdz[k] = 1.0 / h;
+    rdz[nz - 1 + k] = h;
+  }
 }
 
 template <typename TS, typename TD>

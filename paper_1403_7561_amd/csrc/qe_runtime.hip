@@ -160,10 +160,12 @@ WaveMap make_wavemap(int nx, int ny, int nz, int kz) {
   wm.gx = (nx + 6) / 7;
   wm.gy = (ny + 6) / 7;
   if (kz <= 0) {
-    // taller chunks recompute fewer halo layers; shorter ones give more
-    // waves to a small mesh (measured: 129x129x65 is fastest at 6,
-    // 257x257x129 at 8)
-    kz = ((long)wm.gx * wm.gy * ((nz + 7) / 8) >= 16384) ? 8 : 6;
+    // taller chunks recompute fewer halo layers and, at 9, put a
+    // 129x129x65 mesh's CG sweep in one round of 3 waves per SIMD
+    // (measured fastest there and at 257x257x129); a small mesh gets
+    // shorter chunks, hence more waves
+    kz = 9;
+    while (kz > 4 && (long)wm.gx * wm.gy * ((nz + kz - 1) / kz) < 2048) --kz;
   }
   wm.kz = std::max(1, std::min(kz, 31));
   wm.gz = (nz + wm.kz - 1) / wm.kz;
@@ -200,7 +202,7 @@ Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int 
   L.c = take(nslots * 64);     // tile-major (tile_slot)
   L.eps_t = take(nslots * 8);
   L.cflag = take(nslots);      // tile-major: element has a nonzero c_q
-  L.rdz = take(nz_elems * 8);  // inverse z spacings
+  L.rdz = take(2 * nz_elems * 8);  // inverse z spacings, then the spacings
   L.cbits = take(nwaves * 64 * 4);  // per J.v lane: coefficient flags over its chunk
   L.mask = take(N);
   L.fsheet = sheet_slots ? take(N * 8) : 0;   // face terms of F at sheet nodes, 0 elsewhere
@@ -446,6 +448,7 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
       if (!std::isfinite(dv[i])) return fail(QE_ERR_NONFINITE, "dir_val[%d] not finite", i);
   }
   g.rdz = f64(lay.rdz);
+  g.hz = g.rdz + (p->nz - 1);
   launch_stage_rdz(s, p->nz, p->z, f64(lay.rdz));
   std::vector<int4> items;
   sheets = make_sheets(p, items);

@@ -529,7 +529,7 @@ static SchLayout sch_layout(long N, long nslots, int nz, long nwaves, int nb) {
   L.eM = take(nslots * 8);
   L.cH = take(nslots * 64);
   L.cM = take(nslots * 64);
-  L.rdz = take((size_t)(nz - 1) * 8);
+  L.rdz = take((size_t)(nz - 1) * 16);
   L.cbits = take(nwaves * 64 * 4);
   L.mask = take(N);
   L.dinv = take(N * 8);
@@ -613,6 +613,7 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
   const double sigma = vmin - 0.1;   // eV below every V: H - sigma M is SPD
   // ---- operators
   g.rdz = f64(L.rdz);
+  g.hz = g.rdz + (p->nz - 1);
   launch_stage_rdz(s, p->nz, p->z, f64(L.rdz));
   QE_TRY(ck(hipMemsetAsync(ws + L.eM, 0, nslots * 8, s), "memset"));
   hipLaunchKernelGGL(k_sch_coef, dim3(vb), dim3(kVecThreads), 0, s, g, sp->inv_mass, sp->v0, phi, sigma, kHB2M,

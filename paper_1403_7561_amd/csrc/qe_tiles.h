@@ -71,22 +71,23 @@ __device__ __forceinline__ void gather_faces(const T out[8], T& bot, T& top) {
 // Geometry of one wave tile.
 struct WaveTile {
   int lane, lx, ly, ex, ey, gi, gj, k0, Lbeg, Lend;
-  bool col_ok, own_el, node_ok;
+  bool active, col_ok, own_el, node_ok;
   long n00, ecol, elayer, sxy;
   long slot0, slot_layer;   // tile-major slot of this lane's element at layer 0, stride per layer
   double x0, x1, y0, y1;    // element corners: loaded here, first used once the sweep's first loads are issued
 
-  __device__ __forceinline__ WaveTile(const Geom& g, int wx, int wy, int wz, int kz, int lane_, bool active) {
+  __device__ __forceinline__ WaveTile(const Geom& g, int wx, int wy, int wz, int kz, int lane_, bool active_) {
     lane = lane_;
+    active = active_;
     lx = lane & 7;
     ly = lane >> 3;
     ex = 7 * wx - 1 + lx;
     ey = 7 * wy - 1 + ly;
-    col_ok = active && ex >= 0 && ex < g.nx - 1 && ey >= 0 && ey < g.ny - 1;
+    col_ok = active_ && ex >= 0 && ex < g.nx - 1 && ey >= 0 && ey < g.ny - 1;
     own_el = col_ok && lx >= 1 && ly >= 1;
     gi = 7 * wx + lx;
     gj = 7 * wy + ly;
-    node_ok = active && lx < 7 && ly < 7 && gi < g.nx && gj < g.ny;
+    node_ok = active_ && lx < 7 && ly < 7 && gi < g.nx && gj < g.ny;
     k0 = wz * kz;
     Lbeg = k0 - 1;
     Lend = min(k0 + kz - 1, g.nz - 1);
@@ -97,14 +98,13 @@ struct WaveTile {
     const int tgx = (g.nx + 6) / 7, tgy = (g.ny + 6) / 7;
     slot_layer = (long)tgx * tgy * 49;
     slot0 = col_ok ? tile_slot(ex, ey, 0, tgx, tgy) : 0;
-    x0 = y0 = 0.0;
-    x1 = y1 = 1.0;
-    if (col_ok) {
-      x0 = g.x[ex];
-      x1 = g.x[ex + 1];
-      y0 = g.y[ey];
-      y1 = g.y[ey + 1];
-    }
+    // loaded in every lane (outside the mesh: the nearest element's, never
+    // used), so that no branch leaves the count of loads in flight unknown
+    const int cx = min(max(ex, 0), g.nx - 2), cy = min(max(ey, 0), g.ny - 2);
+    x0 = g.x[cx];
+    x1 = g.x[cx + 1];
+    y0 = g.y[cy];
+    y1 = g.y[cy + 1];
   }
   // the element's stiffness weights are eps * (ahx hz, ahy hz, axy / hz)
   __device__ __forceinline__ void weights(double& ahx, double& ahy, double& axy) const {
@@ -306,6 +306,275 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
     ee = en;
     mk = mkn;
   }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// The CG sweep (JV_REC) on raw buffer resources.
+//
+// Every load and store of this sweep is a raw buffer access.  A lane whose
+// access is not wanted passes an offset beyond the resource's range; the
+// hardware then returns zeros (load) or drops the write (store) without
+// touching memory.  So the sweep issues the same memory instructions in every
+// layer step and in every lane, with no branch around any of them, and the
+// compiler's wait counts stay exact: the wait for one layer's operands never
+// drains the loads already issued for the next layer (vector memory counts
+// retire in order, and a load under a branch leaves the count after the join
+// unknown, which forces a full drain).
+//
+// Each wave's resources start at its lowest layer, and per-layer steps are
+// scalar offsets, so per-lane offsets are 32-bit and fixed over the sweep.
+typedef unsigned int qe_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int qe_u32x4 __attribute__((ext_vector_type(4)));
+constexpr unsigned int kBufOob = 0x80000000u;     // offset past every range below
+constexpr long kBufRangeMax = 0x7fffffffL;
+constexpr unsigned int kBufConfig = 0x00020000u;  // raw 32-bit dword data format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_res(const void* base, long bytes) {
+  const long n = bytes <= 0 ? 0 : (bytes < kBufRangeMax ? bytes : kBufRangeMax);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, (int)kBufConfig);
+}
+
+template <typename T>
+struct BufIO;
+
+template <>
+struct BufIO<double> {
+  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned int v, unsigned int s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, double x, unsigned int v, unsigned int s) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qe_u32x2, x), r, v, s, 0);
+  }
+  // eight consecutive values (one element's Gauss-point coefficients)
+  static __device__ __forceinline__ void ld8(__amdgpu_buffer_rsrc_t r, unsigned int v, unsigned int s, double o[8]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const qe_u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, v + 16 * i, s, 0);
+      o[2 * i] = __builtin_bit_cast(double, (qe_u32x2){q.x, q.y});
+      o[2 * i + 1] = __builtin_bit_cast(double, (qe_u32x2){q.z, q.w});
+    }
+  }
+};
+
+template <>
+struct BufIO<float> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned int v, unsigned int s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, float x, unsigned int v, unsigned int s) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, x), r, v, s, 0);
+  }
+  static __device__ __forceinline__ void ld8(__amdgpu_buffer_rsrc_t r, unsigned int v, unsigned int s, float o[8]) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const qe_u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, v + 16 * i, s, 0);
+      // by value: a bit cast of a vector element reads element 0
+      o[4 * i] = __uint_as_float(q.x);
+      o[4 * i + 1] = __uint_as_float(q.y);
+      o[4 * i + 2] = __uint_as_float(q.z);
+      o[4 * i + 3] = __uint_as_float(q.w);
+    }
+  }
+};
+
+// 2D Haar butterflies of one face (index bit 0 = x, bit 1 = y); the same
+// transform inverts itself up to a factor 4.
+template <typename T>
+__device__ __forceinline__ void haar2(const T f[4], T u[4]) {
+  const T a0 = f[0] + f[1], a1 = f[0] - f[1], a2 = f[2] + f[3], a3 = f[2] - f[3];
+  u[0] = a0 + a2;
+  u[1] = a1 + a3;
+  u[2] = a0 - a2;
+  u[3] = a1 - a3;
+}
+
+// What one layer step needs from memory, loaded one step ahead: the top face
+// of the element layer (raw z values at its corners), the element's
+// permittivity and Gauss-point coefficients and, at the lane's owned node of
+// that layer, y and p.
+template <typename T>
+struct CgStage {
+  T f[4];
+  T e;
+  T yv, pv;
+  T c[8];
+};
+
+// CG sweep on one wave tile, numerically the JV_REC mode of jv_tile (the
+// arithmetic is the same Haar-diagonal element operator; partial sums are
+// grouped differently).  The bottom face of each element layer is kept in
+// the 2D Haar basis from the step before, and the top-face output of one
+// element layer is added to the bottom-face output of the next in that basis,
+// so each face is transformed, inverse-transformed and gathered across lanes
+// once.  Layer steps run in pairs over kz + 1 layers rounded up to even (the
+// last step loads nothing ahead); a step beyond the chunk or the mesh loads
+// in-range data it does not use (its z spacing is 0, its coefficient flag is
+// clear) and stores nothing.
+template <typename T, typename Pre>
+__device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int kz, const T* __restrict__ eps_t,
+                                           unsigned int cbits, const T* __restrict__ cq, const T* __restrict__ z,
+                                           T* __restrict__ y, T* __restrict__ p, double& dot, Pre pre) {
+  using IO = BufIO<T>;
+  constexpr unsigned int B = sizeof(T);
+  const long sxy = w.sxy, sl = w.slot_layer;
+  // lowest node (and element) layer the sweep reads; an idle wave (past the
+  // last tile, its chunk above the mesh) gets the top element layer, so that
+  // every range below is positive and it reads only zeros
+  const int Pb = min(max(w.Lbeg, 0), g.nz - 2);
+  const __amdgpu_buffer_rsrc_t rz = buf_res(z + sxy * Pb, (long)(g.nz - Pb) * sxy * B);
+  const __amdgpu_buffer_rsrc_t ry = buf_res(y + sxy * Pb, (long)(g.nz - Pb) * sxy * B);
+  const __amdgpu_buffer_rsrc_t rp = buf_res(p + sxy * Pb, (long)(g.nz - Pb) * sxy * B);
+  const __amdgpu_buffer_rsrc_t re = buf_res(eps_t + sl * Pb, (long)(g.nz - 1 - Pb) * sl * B);
+  const __amdgpu_buffer_rsrc_t rc = buf_res(cq + 8 * sl * Pb, (long)(g.nz - 1 - Pb) * sl * 8 * B);
+  // per-lane byte offsets within a layer; corner 3 of the face is the owned
+  // node, also read by lanes that own a node but no element (mesh edge x = 0
+  // or y = 0), whose element terms are zero (their permittivity reads 0)
+  const long nxy = (long)w.gi + (long)g.nx * w.gj;
+  const unsigned int o_f[4] = {w.col_ok ? (unsigned int)(w.n00 * B) : kBufOob,
+                               w.col_ok ? (unsigned int)((w.n00 + 1) * B) : kBufOob,
+                               w.col_ok ? (unsigned int)((w.n00 + g.nx) * B) : kBufOob,
+                               (w.col_ok || w.node_ok) ? (unsigned int)(nxy * B) : kBufOob};
+  const unsigned int o_n = w.node_ok ? (unsigned int)(nxy * B) : kBufOob;
+  const unsigned int o_e = w.col_ok ? (unsigned int)(w.slot0 * B) : kBufOob;
+  const unsigned int o_c = (unsigned int)(w.slot0 * 8 * B);
+  // scalar offset of node layer P / element layer L (clamped into the mesh)
+  auto s_node = [&](int P) -> unsigned int { return (unsigned int)((min(max(P, 0), g.nz - 1) - Pb) * sxy * B); };
+  auto s_elem = [&](int L) -> unsigned int { return (unsigned int)((min(max(L, 0), g.nz - 2) - Pb) * sl * B); };
+
+  // The prologue's loads are all unconditional, so that pre() can wait for
+  // loads its caller issued before them without waiting for them.  First the
+  // chunk's z spacings: lane j holds layer Lbeg + j (clamped into the mesh),
+  // read per step with readlane.
+  double hzl, rdzl;
+  {
+    const int L = min(max(w.Lbeg + w.lane, 0), g.nz - 2);
+    hzl = g.hz[L];
+    rdzl = g.rdz[L];
+  }
+  CgStage<T> A, Bs;
+  T fb[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) fb[k] = IO::ld(rz, o_f[k], s_node(w.Lbeg));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) A.f[k] = IO::ld(rz, o_f[k], s_node(w.Lbeg + 1));
+  A.e = IO::ld(re, o_e, s_elem(w.Lbeg));
+  A.yv = A.pv = T(0);   // node layer Lbeg is never owned
+  // the flag word is first used here, after the loads above are issued (an
+  // idle wave's word is not its own: cleared)
+  __builtin_amdgcn_sched_barrier(0);
+  if (!w.active) cbits = 0u;
+  IO::ld8(rc, (cbits & 1u) ? o_c : kBufOob, 8 * s_elem(w.Lbeg), A.c);
+  const JvGo<T> go = pre();
+  if (!go.go) return false;
+  double ahx, ahy, axy;
+  w.weights(ahx, ahy, axy);
+  const T beta = go.beta;
+  const bool rec_old = !go.first;
+  // retire the prologue's loads before the loop (see jv_tile)
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    asm("" : "+v"(fb[k]));
+    asm("" : "+v"(A.f[k]));
+  }
+  asm("" : "+v"(A.e));
+  T Tb[4], carry[4] = {T(0), T(0), T(0), T(0)};
+  haar2(fb, Tb);
+  T zb = fb[3];
+  const bool own_lane = w.node_ok;
+
+  // kNext: load the next step's operands (the chunk's last step has none)
+  auto step = [&](int L, CgStage<T>& cur, CgStage<T>& nxt, auto next_tag) {
+    constexpr bool kNext = decltype(next_tag)::value;
+    const int j = L - w.Lbeg;
+    const bool flag = (cbits >> j) & 1u;
+    // The next step's operands.  Its Gauss-point coefficients are loaded by
+    // the flagged lanes only (the one conditional access of the step) and
+    // issued first: a wait that the compiler sizes for the path without them
+    // then waits at most for them early, never for the loads issued after
+    // them (scheduling barriers keep this order).
+    if constexpr (kNext) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) nxt.c[k] = T(0);
+      if ((cbits >> (j + 1)) & 1u) IO::ld8(rc, o_c, 8 * s_elem(L + 1), nxt.c);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) nxt.f[k] = IO::ld(rz, o_f[k], s_node(L + 2));
+      nxt.e = IO::ld(re, o_e, s_elem(L + 1));
+      nxt.yv = IO::ld(ry, o_n, s_node(L + 1));
+      nxt.pv = IO::ld(rp, o_n, s_node(L + 1));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // element layer L: Haar coefficients, diagonal stiffness, mass term
+    // 0 off the mesh (a scalar select)
+    const bool lay_ok = L >= 0 && L <= g.nz - 2;
+    const double hz = lay_ok ? lane_value(hzl, j) : 0.0, rhz = lay_ok ? lane_value(rdzl, j) : 0.0;
+    const T sx = cur.e * T(ahx * hz), sy = cur.e * T(ahy * hz), sz = cur.e * T(axy * rhz);
+    T Tt[4];
+    haar2(cur.f, Tt);
+    T vt[8], out[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      vt[k] = Tb[k] + Tt[k];
+      vt[k + 4] = Tb[k] - Tt[k];
+    }
+    const T k2 = T(1.0 / 16.0), k6 = T(1.0 / 48.0), k18 = T(1.0 / 144.0);
+    out[0] = T(0);
+    out[1] = (sx * k2) * vt[1];
+    out[2] = (sy * k2) * vt[2];
+    out[3] = ((sx + sy) * k6) * vt[3];
+    out[4] = (sz * k2) * vt[4];
+    out[5] = ((sx + sz) * k6) * vt[5];
+    out[6] = ((sy + sz) * k6) * vt[6];
+    out[7] = ((sx + sy + sz) * k18) * vt[7];
+    if (flag) {
+      const T b0 = T(0.125), b1 = T(0.07216878364870322), b2 = T(0.041666666666666664),
+              b3 = T(0.024056261216234407);
+      const T db[8] = {b0, b1, b1, b2, b1, b2, b2, b3};
+      T q[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) q[k] = db[k] * vt[k];
+      haar3(q);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) q[k] *= cur.c[k];
+      haar3(q);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) out[k] += db[k] * q[k];
+    }
+    // bottom-face output joins the top-face output of the layer below, then
+    // one inverse face transform and one gather give node layer L
+    T on[4], corner[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      on[k] = carry[k] + (out[k] + out[k + 4]);
+      carry[k] = out[k] - out[k + 4];
+    }
+    haar2(on, corner);
+    const T u = corner[3] + shfl_down_t(corner[2], 1);
+    const T v2 = corner[1] + shfl_down_t(corner[0], 1);
+    T val = u + shfl_down_t(v2, 8);
+    T pv = zb;
+    if (rec_old) {
+      val += beta * cur.yv;
+      pv += beta * cur.pv;
+    }
+    const bool st = L >= w.k0 && L <= w.Lend;
+    IO::st(ry, val, st ? o_n : kBufOob, s_node(L));
+    IO::st(rp, pv, st ? o_n : kBufOob, s_node(L));
+    if (st && own_lane) dot += (double)pv * (double)val;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Tb[k] = Tt[k];
+    zb = cur.f[3];
+  };
+  using Next = std::integral_constant<bool, true>;
+  using Last = std::integral_constant<bool, false>;
+  const int nsteps = (kz + 2) & ~1;
+  for (int s = 0; s < nsteps - 2; s += 2) {
+    step(w.Lbeg + s, A, Bs, Next());
+    step(w.Lbeg + s + 1, Bs, A, Next());
+  }
+  step(w.Lbeg + nsteps - 2, A, Bs, Next());
+  step(w.Lbeg + nsteps - 1, Bs, A, Last());
   return true;
 }
 
