@@ -98,9 +98,7 @@ __device__ __forceinline__ void wave_coords(const WaveMap& wm, int& wx, int& wy,
   const int w = __builtin_amdgcn_readfirstlane(wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6));
   wid = w;
   active = w < wm.nwaves;
-  wx = w % wm.gx;
-  wy = (w / wm.gx) % wm.gy;
-  wz = w / (wm.gx * wm.gy);
+  wave_tile_of(w, wm, wx, wy, wz);
 }
 
 #ifndef QE_JV_MIN_WAVES

@@ -126,7 +126,8 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_coef(Geom g, const double* 
 __global__ __launch_bounds__(256) void k_sch_bits(Geom g, WaveMap wm, unsigned int* __restrict__ cbits) {
   const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= wm.nwaves) return;
-  const int wx = w % wm.gx, wy = (w / wm.gx) % wm.gy, wz = w / (wm.gx * wm.gy);
+  int wx, wy, wz;
+  wave_tile_of(w, wm, wx, wy, wz);
   const WaveTile t(g, wx, wy, wz, wm.kz, threadIdx.x & 63, true);
   unsigned int b = 0;
   if (t.col_ok)

@@ -378,6 +378,19 @@ struct BufIO<float> {
   }
 };
 
+// The value of lane + 1 (DPP row shift: lanes 15, 31, 47, 63 read 0).  In a
+// wave tile the lanes with lx = 7, the only ones whose lane + 1 is in another
+// row of 8, own no node.
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x101, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x101, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x101, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // 2D Haar butterflies of one face (index bit 0 = x, bit 1 = y); the same
 // transform inverts itself up to a factor 4.
 template <typename T>
@@ -550,8 +563,8 @@ __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int
       carry[k] = out[k] - out[k + 4];
     }
     haar2(on, corner);
-    const T u = corner[3] + shfl_down_t(corner[2], 1);
-    const T v2 = corner[1] + shfl_down_t(corner[0], 1);
+    const T u = corner[3] + lane_next(corner[2]);
+    const T v2 = corner[1] + lane_next(corner[0]);
     T val = u + shfl_down_t(v2, 8);
     T pv = zb;
     if (rec_old) {
