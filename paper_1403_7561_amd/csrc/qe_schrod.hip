@@ -95,8 +95,7 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_vmin(Geom g, const double* 
 __global__ __launch_bounds__(kVecThreads) void k_sch_coef(Geom g, const double* __restrict__ inv_mass,
                                                          const double* __restrict__ v0,
                                                          const double* __restrict__ phi, double sigma, double hb2m,
-                                                         double* __restrict__ eH, double* __restrict__ cH,
-                                                         double* __restrict__ cM) {
+                                                         double* __restrict__ eH, double* __restrict__ cH) {
   const long E = (long)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
   const int tgx = (g.nx + 6) / 7, tgy = (g.ny + 6) / 7;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (long)gridDim.x * blockDim.x) {
@@ -109,30 +108,50 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_coef(Geom g, const double* 
     gauss_interp(q);
     const double W = (g.x[i + 1] - g.x[i]) * (g.y[j + 1] - g.y[j]) * (g.z[k + 1] - g.z[k]) * 0.125;
     const double ve = v0[e];
-    double ch[8], cm[8];
+    double ch[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      ch[t] = W * (ve - q[t] - sigma);
-      cm[t] = W;
-    }
+    for (int t = 0; t < 8; ++t) ch[t] = W * (ve - q[t] - sigma);
     const long sl = tile_slot(i, j, k, tgx, tgy);
     eH[sl] = hb2m * inv_mass[e];
     store8(cH + 8 * sl, ch);
-    store8(cM + 8 * sl, cm);
   }
 }
 
-// Coefficient flags of every J.v lane: all element layers of its column.
-__global__ __launch_bounds__(256) void k_sch_bits(Geom g, WaveMap wm, unsigned int* __restrict__ cbits) {
+// Fixed-node flags of every lane of the operator sweep: bit L - Lbeg is set
+// when the lane's owned node of layer L is fixed.
+__global__ __launch_bounds__(256) void k_sch_mbits(Geom g, WaveMap wm, const uint8_t* __restrict__ mask,
+                                                   unsigned int* __restrict__ mbits) {
   const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= wm.nwaves) return;
   int wx, wy, wz;
   wave_tile_of(w, wm, wx, wy, wz);
   const WaveTile t(g, wx, wy, wz, wm.kz, threadIdx.x & 63, true);
   unsigned int b = 0;
-  if (t.col_ok)
-    for (int L = max(t.Lbeg, 0); L <= min(t.Lend, g.nz - 2); ++L) b |= 1u << (L - t.Lbeg);
-  cbits[64L * w + (threadIdx.x & 63)] = b;
+  if (t.node_ok)
+    for (int L = t.k0; L <= t.Lend; ++L)
+      if (mask[t.node(g, L)]) b |= 1u << (L - t.Lbeg);
+  mbits[64L * w + (threadIdx.x & 63)] = b;
+}
+
+// H and M applied to columns c0 .. c0 + ncols - 1 of Z (column stride N):
+// block (bx, by) sweeps four wave tiles for columns c0 + 2 by and the next.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_sch_apply(
+    Geom g, WaveMap wm, const double* __restrict__ eH, const double* __restrict__ cH,
+    const unsigned int* __restrict__ mbits, long N, int c0, int ncols, const double* __restrict__ Z,
+    double* __restrict__ HZ, double* __restrict__ MZ) {
+  const int w = __builtin_amdgcn_readfirstlane(wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6));
+  const bool active = w < wm.nwaves;
+  int wx, wy, wz;
+  wave_tile_of(w, wm, wx, wy, wz);
+  const WaveTile t(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
+  const unsigned int mb = mbits[64L * min(w, wm.nwaves - 1) + (threadIdx.x & 63)];
+  const int ca = c0 + 2 * (int)blockIdx.y;
+  const bool ok[2] = {true, ca + 1 < c0 + ncols};
+  const int cb = ok[1] ? ca + 1 : ca;
+  const double* const zc[2] = {Z + (long)ca * N, Z + (long)cb * N};
+  double* const yh[2] = {HZ + (long)ca * N, HZ + (long)cb * N};
+  double* const ym[2] = {MZ + (long)ca * N, MZ + (long)cb * N};
+  jv_tile_hm(g, t, wm.kz, eH, cH, mb, zc, yh, ym, ok);
 }
 
 // Jacobi preconditioner: 1 / (kinetic diagonal + consistent-mass diagonal
@@ -513,7 +532,7 @@ static bool rayleigh_ritz(int k, int nb, const double* GA, const double* GB, std
 }
 
 struct SchLayout {
-  size_t eH, eM, cH, cM, rdz, cbits, mask, dinv, Z, HZ, MZ, P, HP, MP, G, gpart, C, part, sums, flags;
+  size_t eH, cH, rdz, mbits, mask, dinv, Z, HZ, MZ, P, HP, MP, G, gpart, C, part, sums, flags;
   size_t total;
 };
 
@@ -527,11 +546,9 @@ static SchLayout sch_layout(long N, long nslots, int nz, long nwaves, int nb) {
   };
   const int K = 3 * nb;
   L.eH = take(nslots * 8);
-  L.eM = take(nslots * 8);
   L.cH = take(nslots * 64);
-  L.cM = take(nslots * 64);
   L.rdz = take((size_t)(nz - 1) * 16);
-  L.cbits = take(nwaves * 64 * 4);
+  L.mbits = take(nwaves * 64 * 4);
   L.mask = take(N);
   L.dinv = take(N * 8);
   L.Z = take((size_t)K * N * 8);
@@ -616,26 +633,24 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
   g.rdz = f64(L.rdz);
   g.hz = g.rdz + (p->nz - 1);
   launch_stage_rdz(s, p->nz, p->z, f64(L.rdz));
-  QE_TRY(ck(hipMemsetAsync(ws + L.eM, 0, nslots * 8, s), "memset"));
   hipLaunchKernelGGL(k_sch_coef, dim3(vb), dim3(kVecThreads), 0, s, g, sp->inv_mass, sp->v0, phi, sigma, kHB2M,
-                     f64(L.eH), f64(L.cH), f64(L.cM));
-  hipLaunchKernelGGL(k_sch_bits, dim3(wm.nblocks), dim3(256), 0, s, g, wm, reinterpret_cast<unsigned int*>(ws + L.cbits));
+                     f64(L.eH), f64(L.cH));
   uint8_t* mask = reinterpret_cast<uint8_t*>(ws + L.mask);
   if (sp->fixed)
     QE_TRY(ck(hipMemcpyAsync(mask, sp->fixed, N, hipMemcpyDeviceToDevice, s), "copy"));
   else
     QE_TRY(ck(hipMemsetAsync(mask, 0, N, s), "memset"));
+  unsigned int* mbits = reinterpret_cast<unsigned int*>(ws + L.mbits);
+  hipLaunchKernelGGL(k_sch_mbits, dim3(wm.nblocks), dim3(256), 0, s, g, wm, mask, mbits);
   hipLaunchKernelGGL(k_sch_diag, dim3(vb), dim3(kVecThreads), 0, s, g, sp->inv_mass, sp->v0, phi, mask, sigma, kHB2M,
                      f64(L.dinv));
-  const unsigned int* cbits = reinterpret_cast<const unsigned int*>(ws + L.cbits);
-  auto applyH = [&](const double* v, double* y) {
-    launch_jv_wave64(s, g, wm, f64(L.eH), cbits, f64(L.cH), mask, v, y, 2);
-  };
-  auto applyM = [&](const double* v, double* y) {
-    launch_jv_wave64(s, g, wm, f64(L.eM), cbits, f64(L.cM), mask, v, y, 2);
-  };
   double *Z = f64(L.Z), *HZ = f64(L.HZ), *MZ = f64(L.MZ);
-  auto col = [&](double* base, int c) { return base + (long)c * N; };
+  // H and M of columns c0 .. c0 + n - 1 of Z into HZ, MZ (one launch; the
+  // columns vanish on the fixed nodes, and so do their images)
+  auto apply = [&](int c0, int n) {
+    hipLaunchKernelGGL(k_sch_apply, dim3(wm.nblocks, (n + 1) / 2), dim3(256), 0, s, g, wm, f64(L.eH), f64(L.cH),
+                       mbits, N, c0, n, Z, HZ, MZ);
+  };
   std::vector<double> hG(2 * (size_t)K * K), lam, Cm;
   // Gram matrices of the first k columns, Rayleigh-Ritz, and the new X (and
   // P from columns nb.. when with_p).
@@ -661,10 +676,7 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
     QE_TRY(ck(hipMemcpyAsync(Z, psi, (size_t)n_states * N * 8, hipMemcpyDeviceToDevice, s), "copy"));
     hipLaunchKernelGGL(k_sch_mask, dim3(vb), dim3(kVecThreads), 0, s, N, n_states, mask, Z);
   }
-  for (int c = 0; c < nb; ++c) {
-    applyH(col(Z, c), col(HZ, c));
-    applyM(col(Z, c), col(MZ, c));
-  }
+  apply(0, nb);
   qe_status st = rr_update(nb, false);
   if (st != QE_OK) return st == QE_ERR_KRYLOV_BREAKDOWN ? fail(st, "starting block is rank deficient") : st;
   bool have_p = false;
@@ -712,10 +724,7 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
       wmap.lam[a] = lam[active[a]];
     }
     hipLaunchKernelGGL(k_sch_precond, dim3(kSchBlocks, na), dim3(kVecThreads), 0, s, N, wmap, HZ, MZ, f64(L.dinv), Z);
-    for (int a = 0; a < na; ++a) {
-      applyH(col(Z, nb + a), col(HZ, nb + a));
-      applyM(col(Z, nb + a), col(MZ, nb + a));
-    }
+    apply(nb, na);
     int k = nb + na;
     if (have_p) {
       ColMap pmap;

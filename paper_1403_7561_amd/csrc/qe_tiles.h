@@ -592,6 +592,184 @@ __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int
 }
 
 // ---------------------------------------------------------------------------
+// H v and M v of the generalized Schrodinger eigenproblem for two columns at
+// once, on raw buffer resources like jv_tile_cg.  H's element operator is the
+// stiffness with per-element weight eH plus the Gauss-point coefficients cH
+// (eight per element); M's is the consistent mass matrix, which in the Haar
+// basis is diagonal, (V / 64) (1/3)^(number of difference axes) for an
+// element of volume V, so it costs eight products and no memory.  Both share
+// the face loads, the forward transforms and the first Gauss-point transform;
+// the element data (eH, cH) are loaded once for both columns.
+//
+// The input columns must vanish on the fixed nodes (the eigensolver keeps its
+// basis in that subspace); outputs are 0 on owned nodes whose bit in mbits
+// (bit L - Lbeg: the node of layer L is fixed) is set.  col_ok[1] = false:
+// the second column is absent (its resources are empty: zeros in, no stores).
+struct HmStage {
+  double f[2][4];
+  double e;
+  double c[8];
+};
+
+__device__ __forceinline__ void jv_tile_hm(const Geom& g, const WaveTile& w, int kz, const double* __restrict__ eH,
+                                           const double* __restrict__ cH, unsigned int mbits,
+                                           const double* const zc[2], double* const yh[2], double* const ym[2],
+                                           const bool col_ok[2]) {
+  using IO = BufIO<double>;
+  constexpr unsigned int B = 8;
+  const long sxy = w.sxy, sl = w.slot_layer;
+  const int Pb = min(max(w.Lbeg, 0), g.nz - 2);
+  const long vbytes = (long)(g.nz - Pb) * sxy * B;
+  __amdgpu_buffer_rsrc_t rz[2], rh[2], rm[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    rz[c] = buf_res(zc[c] + sxy * Pb, col_ok[c] ? vbytes : 0);
+    rh[c] = buf_res(yh[c] + sxy * Pb, col_ok[c] ? vbytes : 0);
+    rm[c] = buf_res(ym[c] + sxy * Pb, col_ok[c] ? vbytes : 0);
+  }
+  const __amdgpu_buffer_rsrc_t re = buf_res(eH + sl * Pb, (long)(g.nz - 1 - Pb) * sl * B);
+  const __amdgpu_buffer_rsrc_t rc = buf_res(cH + 8 * sl * Pb, (long)(g.nz - 1 - Pb) * sl * 8 * B);
+  const long nxy = (long)w.gi + (long)g.nx * w.gj;
+  const unsigned int o_f[4] = {w.col_ok ? (unsigned int)(w.n00 * B) : kBufOob,
+                               w.col_ok ? (unsigned int)((w.n00 + 1) * B) : kBufOob,
+                               w.col_ok ? (unsigned int)((w.n00 + g.nx) * B) : kBufOob,
+                               w.col_ok ? (unsigned int)((w.n00 + g.nx + 1) * B) : kBufOob};
+  const unsigned int o_n = w.node_ok ? (unsigned int)(nxy * B) : kBufOob;
+  const unsigned int o_e = w.col_ok ? (unsigned int)(w.slot0 * B) : kBufOob;
+  const unsigned int o_c = w.col_ok ? (unsigned int)(w.slot0 * 8 * B) : kBufOob;
+  auto s_node = [&](int P) -> unsigned int { return (unsigned int)((min(max(P, 0), g.nz - 1) - Pb) * sxy * B); };
+  auto s_elem = [&](int L) -> unsigned int { return (unsigned int)((min(max(L, 0), g.nz - 2) - Pb) * sl * B); };
+  // element data of layer L: zeros off the mesh (the coefficients are not
+  // scaled by the layer's z spacing, so they need their own guard)
+  auto o_cl = [&](int L) -> unsigned int { return (L >= 0 && L <= g.nz - 2) ? o_c : kBufOob; };
+  if (!w.active) mbits = 0u;
+
+  double hzl, rdzl;
+  {
+    const int L = min(max(w.Lbeg + w.lane, 0), g.nz - 2);
+    hzl = g.hz[L];
+    rdzl = g.rdz[L];
+  }
+  HmStage A, Bs;
+  double fb[2][4];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      fb[c][k] = IO::ld(rz[c], o_f[k], s_node(w.Lbeg));
+      A.f[c][k] = IO::ld(rz[c], o_f[k], s_node(w.Lbeg + 1));
+    }
+  A.e = IO::ld(re, o_e, s_elem(w.Lbeg));
+  IO::ld8(rc, o_cl(w.Lbeg), 8 * s_elem(w.Lbeg), A.c);
+  double ahx, ahy, axy;
+  w.weights(ahx, ahy, axy);
+  // retire the prologue's loads before the loop (see jv_tile)
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      asm("" : "+v"(fb[c][k]));
+      asm("" : "+v"(A.f[c][k]));
+    }
+  asm("" : "+v"(A.e));
+#pragma unroll
+  for (int k = 0; k < 8; ++k) asm("" : "+v"(A.c[k]));
+  double Tb[2][4], carH[2][4], carM[2][4];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    haar2(fb[c], Tb[c]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) carH[c][k] = carM[c][k] = 0.0;
+  }
+
+  auto step = [&](int L, HmStage& cur, HmStage& nxt, auto next_tag) {
+    constexpr bool kNext = decltype(next_tag)::value;
+    const int j = L - w.Lbeg;
+    if constexpr (kNext) {
+      IO::ld8(rc, o_cl(L + 1), 8 * s_elem(L + 1), nxt.c);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nxt.f[c][k] = IO::ld(rz[c], o_f[k], s_node(L + 2));
+      nxt.e = IO::ld(re, o_e, s_elem(L + 1));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const bool lay_ok = L >= 0 && L <= g.nz - 2;
+    const double hz = lay_ok ? lane_value(hzl, j) : 0.0, rhz = lay_ok ? lane_value(rdzl, j) : 0.0;
+    const double sx = cur.e * (ahx * hz), sy = cur.e * (ahy * hz), sz = cur.e * (axy * rhz);
+    const double k2 = 1.0 / 16.0, k6 = 1.0 / 48.0, k18 = 1.0 / 144.0;
+    const double d1 = sx * k2, d2 = sy * k2, d3 = (sx + sy) * k6, d4 = sz * k2, d5 = (sx + sz) * k6,
+                 d6 = (sy + sz) * k6, d7 = (sx + sy + sz) * k18;
+    // M in the Haar basis (volume axy hz), with the final transform's 1/8
+    const double V = axy * hz;
+    const double m0 = V * (1.0 / 64.0), m1 = V * (1.0 / 192.0), m2 = V * (1.0 / 576.0), m3 = V * (1.0 / 1728.0);
+    const double db[8] = {0.125, 0.07216878364870322, 0.07216878364870322, 0.041666666666666664,
+                          0.07216878364870322, 0.041666666666666664, 0.041666666666666664, 0.024056261216234407};
+    const bool st = L >= w.k0 && L <= w.Lend;
+    const bool fixed = (mbits >> j) & 1u;
+    const unsigned int os = st ? o_n : kBufOob;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double Tt[4], vt[8], oh[8], om[8], q[8];
+      haar2(cur.f[c], Tt);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        vt[k] = Tb[c][k] + Tt[k];
+        vt[k + 4] = Tb[c][k] - Tt[k];
+      }
+      om[0] = m0 * vt[0];
+      om[1] = m1 * vt[1];
+      om[2] = m1 * vt[2];
+      om[3] = m2 * vt[3];
+      om[4] = m1 * vt[4];
+      om[5] = m2 * vt[5];
+      om[6] = m2 * vt[6];
+      om[7] = m3 * vt[7];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) q[k] = db[k] * vt[k];
+      haar3(q);   // Gauss-point values
+#pragma unroll
+      for (int k = 0; k < 8; ++k) q[k] *= cur.c[k];
+      haar3(q);
+      oh[0] = db[0] * q[0];
+      oh[1] = d1 * vt[1] + db[1] * q[1];
+      oh[2] = d2 * vt[2] + db[2] * q[2];
+      oh[3] = d3 * vt[3] + db[3] * q[3];
+      oh[4] = d4 * vt[4] + db[4] * q[4];
+      oh[5] = d5 * vt[5] + db[5] * q[5];
+      oh[6] = d6 * vt[6] + db[6] * q[6];
+      oh[7] = d7 * vt[7] + db[7] * q[7];
+      double onH[4], onM[4], crH[4], crM[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        onH[k] = carH[c][k] + (oh[k] + oh[k + 4]);
+        carH[c][k] = oh[k] - oh[k + 4];
+        onM[k] = carM[c][k] + (om[k] + om[k + 4]);
+        carM[c][k] = om[k] - om[k + 4];
+      }
+      haar2(onH, crH);
+      haar2(onM, crM);
+      double vh = (crH[3] + lane_next(crH[2])) + shfl_down_t(crH[1] + lane_next(crH[0]), 8);
+      double vm = (crM[3] + lane_next(crM[2])) + shfl_down_t(crM[1] + lane_next(crM[0]), 8);
+      if (fixed) vh = vm = 0.0;
+      IO::st(rh[c], vh, os, s_node(L));
+      IO::st(rm[c], vm, os, s_node(L));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Tb[c][k] = Tt[k];
+    }
+  };
+  using Next = std::integral_constant<bool, true>;
+  using Last = std::integral_constant<bool, false>;
+  const int nsteps = (kz + 2) & ~1;
+  for (int s = 0; s < nsteps - 2; s += 2) {
+    step(w.Lbeg + s, A, Bs, Next());
+    step(w.Lbeg + s + 1, Bs, A, Next());
+  }
+  step(w.Lbeg + nsteps - 2, A, Bs, Next());
+  step(w.Lbeg + nsteps - 1, Bs, A, Last());
+}
+
+// ---------------------------------------------------------------------------
 // Residual F(phi + lam delta), Jacobi diagonal and Gauss-point coefficients
 // c_q = -KAPPA semi W rho'(phi_q) (= KAPPA semi W n'(phi_q) with electrons
 // alone) on one wave tile.  F and the diagonal are
