@@ -763,8 +763,16 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update(long N, int k, T* __r
                                                           double* __restrict__ part_rz) {
   if (ctx->done) return;
   __shared__ double sred[kVecThreads / 64];
-  const long nc = (N + 3) / 4, stride = (long)gridDim.x * blockDim.x;
-  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  // the J.v kernel's p^T y partials first, so that waiting for them does not
+  // wait for the vector loads below (the block size is the constant
+  // kVecThreads: reading blockDim.x is a load too)
+  constexpr int NT = kVecThreads;
+  double py_part[8];
+  const bool py_one = n_py <= 8 * NT;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) py_part[j] = part_py[min((int)threadIdx.x + j * NT, n_py - 1)];
+  const long nc = (N + 3) / 4, stride = (long)gridDim.x * NT;
+  long c = (long)blockIdx.x * NT + threadIdx.x;
   Quad<T> qx, qr, qp, qy, qd;
   if (c < nc) {
     qx = ld4(x, c, N);
@@ -774,7 +782,16 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update(long N, int k, T* __r
     qd = ld4(invdiag, c, N);
   }
   const double rzk = ctx->rzs[k & 1];
-  const double pAp = sum_partials(part_py, n_py, 1, 0, sred);
+  double pAp;
+  if (py_one) {
+    // the same fixed-order sum as sum_partials
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a += ((int)threadIdx.x + j * NT < n_py) ? py_part[j] : 0.0;
+    pAp = block_sum_all<NT>(a, sred);
+  } else {
+    pAp = sum_partials(part_py, n_py, 1, 0, sred);
+  }
   if (!(pAp > 0.0) || !isfinite(pAp)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       ctx->pAp = pAp;
