@@ -264,9 +264,11 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_precond(long N, ColMap cm, 
 
 // The Rayleigh-Ritz update of one operator's block (blockIdx.y: the block
 // vectors Z, H'Z, MZ): X <- Z[:, :k] C, in place in Z's first nb columns, and
-// (with_p) P <- Z[:, nb:k] C[nb:k, :].  C (k x nb, column-major) is staged in
-// LDS; each thread owns whole rows, so reading a row before writing it back
-// is safe.  A streaming pass: k reads and 2 nb writes per row.
+// (with_p) P <- Z[:, nb:k] C[nb:k, :], formed first so that X = P +
+// Z[:, :nb] C[:nb, :] takes k nb products per row, not (2k - nb) nb.  C (k x
+// nb, column-major) is staged in LDS; each thread owns whole rows, so reading
+// a row before writing it back is safe.  A streaming pass: k reads and 2 nb
+// writes per row.
 __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int nb, int with_p,
                                                            const double* __restrict__ C, double* Z, double* HZ,
                                                            double* MZ, double* P, double* HP, double* MP) {
@@ -278,28 +280,30 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int n
   double* const B = Zs[blockIdx.y];
   double* const Pb = Ps[blockIdx.y];
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
-    double ax[kMaxCols], ap[kMaxCols];
+    double ax[kMaxCols];
 #pragma unroll
-    for (int c = 0; c < kMaxCols; ++c) ax[c] = ap[c] = 0.0;
-    for (int j0 = 0; j0 < k; j0 += 6) {
-      double z[6];   // six loads in flight before any is used
+    for (int c = 0; c < kMaxCols; ++c) ax[c] = 0.0;
+    // columns nb .. k-1 (P's part), then 0 .. nb-1 on top of it
+    auto accumulate = [&](int jb, int je) {
+      for (int j0 = jb; j0 < je; j0 += 6) {
+        double z[6];   // six loads in flight before any is used
 #pragma unroll
-      for (int u = 0; u < 6; ++u) z[u] = j0 + u < k ? B[(long)(j0 + u) * N + n] : 0.0;
+        for (int u = 0; u < 6; ++u) z[u] = j0 + u < je ? B[(long)(j0 + u) * N + n] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 6; ++u) {
-        const int j = j0 + u;
-        if (j >= k) break;
-        const bool pj = with_p && j >= nb;
+        for (int u = 0; u < 6; ++u) {
+          const int j = j0 + u;
+          if (j >= je) break;
 #pragma unroll
-        for (int c = 0; c < kMaxCols; ++c) {
-          if (c < nb) {
-            const double t = z[u] * sc[c * k + j];
-            ax[c] += t;
-            if (pj) ap[c] += t;
-          }
+          for (int c = 0; c < kMaxCols; ++c)
+            if (c < nb) ax[c] += z[u] * sc[c * k + j];
         }
       }
-    }
+    };
+    accumulate(nb, k);
+    double ap[kMaxCols];
+#pragma unroll
+    for (int c = 0; c < kMaxCols; ++c) ap[c] = ax[c];
+    accumulate(0, nb);
 #pragma unroll
     for (int c = 0; c < kMaxCols; ++c) {
       if (c < nb) {
