@@ -321,69 +321,89 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int n
 // four rows per instruction.  Operand layout of that instruction (checked on
 // the device): lane l supplies A[l % 16][l / 16] of the 16 x 4 left operand
 // and B[l / 16][l % 16] of the 4 x 16 right one, and holds
-// D[l / 16 + 4 r][l % 16] in accumulator element r.  Waves 0, 1 compute
-// Z^T H'Z, waves 2, 3 Z^T MZ, each two tile rows by up to four tile columns.
-// One partial per block and entry, summed in a fixed order afterwards.
+// D[l / 16 + 4 r][l % 16] in accumulator element r.  Both matrices are
+// symmetric, so only the tiles on and above the diagonal are formed (10 of
+// 16) and mirrored on output: waves 0, 1 take Z^T H'Z, waves 2, 3 Z^T MZ,
+// five tiles each.  The next slab's loads are in flight (in registers) while
+// the current one is multiplied.  One partial per block and entry, summed in
+// a fixed order afterwards.
 constexpr int kGramRows = 32, kGramLd = 64;
+constexpr int kGramPer = (kGramRows * kGramLd + 255) / 256;   // staged values per thread and array
 typedef double qe_v4d __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_sch_gram(long N, int k, const double* __restrict__ Z,
                                                   const double* __restrict__ HZ, const double* __restrict__ MZ,
                                                   double* __restrict__ part) {
   __shared__ double sz[kGramRows * kGramLd], sh[kGramRows * kGramLd], sm[kGramRows * kGramLd];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int e = t; e < kGramRows * kGramLd; e += blockDim.x) sz[e] = sh[e] = sm[e] = 0.0;
+  for (int e = t; e < kGramRows * kGramLd; e += 256) sz[e] = sh[e] = sm[e] = 0.0;
   const int KT = (k + 15) / 16;
   const int g = wave >> 1;                 // 0: Z^T H'Z, 1: Z^T MZ
-  const int I0 = 2 * (wave & 1);           // this wave's tile rows I0, I0 + 1
   const double* sb = g == 0 ? sh : sm;
-  qe_v4d acc[2][4];
+  // this wave's tiles (I, J), J >= I: (0,0..3), (3,3) or (1,1..3), (2,2..3)
+  const int sub = wave & 1;
+  const int TI[5] = {sub, sub, sub, sub == 0 ? 0 : 2, sub == 0 ? 3 : 2};
+  const int TJ[5] = {sub == 0 ? 0 : 1, sub == 0 ? 1 : 2, sub == 0 ? 2 : 3, sub == 0 ? 3 : 2, 3};
+  qe_v4d acc[5];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = qe_v4d{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < 5; ++q) acc[q] = qe_v4d{0.0, 0.0, 0.0, 0.0};
   const long per = (N + gridDim.x - 1) / gridDim.x;
   const long r0 = (long)blockIdx.x * per, r1 = min(N, r0 + per);
   const int li = lane & 15, lk = lane >> 4;
-  for (long base = r0; base < r1; base += kGramRows) {
+  const int ne = kGramRows * k;             // staged values per array
+  double nz[kGramPer], nh[kGramPer], nm[kGramPer];
+  auto load_slab = [&](long base) {
     const int rows = (int)min((long)kGramRows, r1 - base);
-    __syncthreads();
-    for (int e = t; e < kGramRows * k; e += blockDim.x) {   // e = c * kGramRows + r: coalesced along rows
+#pragma unroll
+    for (int i = 0; i < kGramPer; ++i) {
+      const int e = t + 256 * i;           // e = c * kGramRows + r: coalesced along rows
       const int c = e / kGramRows, r = e % kGramRows;
-      const bool in = r < rows;
-      const long o = (long)c * N + base + r;
-      sz[r * kGramLd + c] = in ? Z[o] : 0.0;
-      sh[r * kGramLd + c] = in ? HZ[o] : 0.0;
-      sm[r * kGramLd + c] = in ? MZ[o] : 0.0;
+      const bool in = e < ne && r < rows;
+      const long o = in ? (long)c * N + base + r : 0;
+      nz[i] = in ? Z[o] : 0.0;
+      nh[i] = in ? HZ[o] : 0.0;
+      nm[i] = in ? MZ[o] : 0.0;
+    }
+  };
+  if (r0 < r1) load_slab(r0);
+  for (long base = r0; base < r1; base += kGramRows) {
+    __syncthreads();   // the previous slab's products have read the LDS
+#pragma unroll
+    for (int i = 0; i < kGramPer; ++i) {
+      const int e = t + 256 * i;
+      if (e < ne) {
+        const int c = e / kGramRows, r = e % kGramRows;
+        sz[r * kGramLd + c] = nz[i];
+        sh[r * kGramLd + c] = nh[i];
+        sm[r * kGramLd + c] = nm[i];
+      }
     }
     __syncthreads();
-    if (I0 < KT) {
+    if (base + kGramRows < r1) load_slab(base + kGramRows);
 #pragma unroll 2
-      for (int r4 = 0; r4 < kGramRows; r4 += 4) {
-        const int row = r4 + lk;
-        const double a0 = sz[row * kGramLd + I0 * 16 + li];
-        const double a1 = I0 + 1 < KT ? sz[row * kGramLd + (I0 + 1) * 16 + li] : 0.0;
+    for (int r4 = 0; r4 < kGramRows; r4 += 4) {
+      const int row = r4 + lk;
 #pragma unroll
-        for (int J = 0; J < 4; ++J) {
-          if (J < KT) {
-            const double b = sb[row * kGramLd + J * 16 + li];
-            acc[0][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][J], 0, 0, 0);
-            if (I0 + 1 < KT) acc[1][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][J], 0, 0, 0);
-          }
+      for (int q = 0; q < 5; ++q) {
+        if (TJ[q] < KT) {   // uniform (J >= I, so I < KT too)
+          const double a = sz[row * kGramLd + TI[q] * 16 + li];
+          const double b = sb[row * kGramLd + TJ[q] * 16 + li];
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
         }
       }
     }
   }
-  if (I0 < KT) {
-    double* out = part + ((long)blockIdx.x * 2 + g) * k * k;
+  double* out = part + ((long)blockIdx.x * 2 + g) * k * k;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+  for (int q = 0; q < 5; ++q) {
+    if (TJ[q] >= KT) continue;
 #pragma unroll
-      for (int J = 0; J < 4; ++J)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = (I0 + a) * 16 + lk + 4 * r, j = J * 16 + li;
-          if (I0 + a < KT && J < KT && i < k && j < k) out[(long)j * k + i] = acc[a][J][r];   // column-major
-        }
+    for (int r = 0; r < 4; ++r) {
+      const int i = TI[q] * 16 + lk + 4 * r, j = TJ[q] * 16 + li;
+      if (i < k && j < k) {
+        out[(long)j * k + i] = acc[q][r];   // column-major
+        if (TI[q] != TJ[q]) out[(long)i * k + j] = acc[q][r];
+      }
+    }
   }
 }
 
