@@ -864,6 +864,12 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
             const double* ps = qm->psi2 + qm->N * i + b0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) s2[k] = ps[o[k]];
+            // a state that vanishes on the element adds exactly nothing (its
+            // occupations are finite): skip them (whole waves outside the
+            // states' support skip the transcendentals)
+            if (s2[0] == 0.0 && s2[1] == 0.0 && s2[2] == 0.0 && s2[3] == 0.0 && s2[4] == 0.0 && s2[5] == 0.0 &&
+                s2[6] == 0.0 && s2[7] == 0.0)
+              continue;
             gauss_interp(s2);
             const double Ei = qm->E[i];
 #pragma unroll
