@@ -130,7 +130,7 @@ __device__ __forceinline__ void post_progress(CgProgress* prog, int iters, int d
 // stops the solve on convergence / non-finite values / the iteration limit
 // (block 0 records the decision; every block takes the same one).  Then
 // beta = rz_k / rz_{k-1} and, on the wave tiles, y = J z + beta y,
-// p = z + beta p (JV_REC); one p^T y partial per block.  rz_k goes to
+// p = z + beta p (jv_tile_cg); one p^T y partial per block.  rz_k goes to
 // ctx->rzs[k & 1] and rz_{k-1} is read from the other slot.
 #ifndef QE_CG_MIN_WAVES
 #define QE_CG_MIN_WAVES 3

@@ -266,14 +266,19 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_precond(long N, ColMap cm, 
 // vectors Z, H'Z, MZ): X <- Z[:, :k] C, in place in Z's first nb columns, and
 // (with_p) P <- Z[:, nb:k] C[nb:k, :], formed first so that X = P +
 // Z[:, :nb] C[:nb, :] takes k nb products per row, not (2k - nb) nb.  C (k x
-// nb, column-major) is staged in LDS; each thread owns whole rows, so reading
-// a row before writing it back is safe.  A streaming pass: k reads and 2 nb
-// writes per row.
+// nb, column-major) is staged in LDS transposed (row j's nb coefficients
+// adjacent, rows padded to even), so one 16-byte LDS read serves two
+// products; each thread owns whole rows, so reading a row before writing it
+// back is safe.  A streaming pass: k reads and 2 nb writes per row.
 __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int nb, int with_p,
                                                            const double* __restrict__ C, double* Z, double* HZ,
                                                            double* MZ, double* P, double* HP, double* MP) {
-  __shared__ double sc[3 * kMaxCols * kMaxCols];
-  for (int i = threadIdx.x; i < k * nb; i += blockDim.x) sc[i] = C[i];
+  constexpr int kLd = (kMaxCols + 1) & ~1;
+  __shared__ __attribute__((aligned(16))) double sc[3 * kMaxCols * kLd];
+  for (int i = threadIdx.x; i < 3 * kMaxCols * kLd; i += blockDim.x) {
+    const int j = i / kLd, c = i % kLd;
+    sc[i] = (j < k && c < nb) ? C[c * k + j] : 0.0;
+  }
   __syncthreads();
   double* const Zs[3] = {Z, HZ, MZ};
   double* const Ps[3] = {P, HP, MP};
@@ -293,9 +298,14 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int n
         for (int u = 0; u < 6; ++u) {
           const int j = j0 + u;
           if (j >= je) break;
+          const double2* row = reinterpret_cast<const double2*>(sc + j * kLd);
 #pragma unroll
-          for (int c = 0; c < kMaxCols; ++c)
-            if (c < nb) ax[c] += z[u] * sc[c * k + j];
+          for (int c = 0; c < kMaxCols; c += 2)
+            if (c < nb) {
+              const double2 cc = row[c / 2];
+              ax[c] += z[u] * cc.x;
+              if (c + 1 < kMaxCols) ax[c + 1] += z[u] * cc.y;
+            }
         }
       }
     };

@@ -140,43 +140,22 @@ struct WaveTile {
 // coefficients are not all exactly zero, and only those read cq (a zero
 // coefficient adds exactly nothing).  Modes:
 //   JV_PLAIN  y = J v with v read as 0 on Dirichlet nodes; identity_rows
-//             (1: y = v on Dirichlet rows, 2: y = 0 there):
-//             Dirichlet rows return v_i.
+//             (1: y = v on Dirichlet rows, 2: y = 0 there).
 //   JV_DOT    v = a CG direction (zero on Dirichlet nodes); y = J v on every
 //             owned row; dot += v^T J v over the elements this wave owns.
-//   JV_REC    v = z (zero on Dirichlet nodes); on owned rows
-//             y = J z + beta y and p = z + beta p (first: y = J z, p = z),
-//             so y = J p by recurrence; dot += p^T y over owned nodes.
-// In the CG modes the Dirichlet flag is not read at all: the vectors vanish
+// In the CG mode the Dirichlet flag is not read at all: the vectors vanish
 // on Dirichlet nodes and D^-1 is 0 there, so whatever y holds on those rows
-// never reaches z, p or x.
-enum JvMode { JV_PLAIN = 0, JV_DOT = 1, JV_REC = 2 };
-
-// What a CG-mode sweep learns once its first loads are in flight: whether to
-// go on (the solve has not stopped), and beta / first for JV_REC.
-template <typename T>
-struct JvGo {
-  bool go;
-  T beta;
-  bool first;
-};
-
-template <typename T>
-struct JvAlways {
-  __device__ __forceinline__ JvGo<T> operator()() const { return {true, T(0), true}; }
-};
+// never reaches z, p or x.  (The single-instance CG uses jv_tile_cg below.)
+enum JvMode { JV_PLAIN = 0, JV_DOT = 1 };
 
 // cbits: this lane's coefficient flags over the chunk (bit L - Lbeg), as
-// written by residual_tile for the same wave tile.  pre() is called by every
-// wave once the first layer's loads are issued (it may synchronise the block).
-// Returns pre().go (false: nothing was stored).
-template <typename T, int kMode, typename Pre = JvAlways<T>>
-__device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const T* __restrict__ eps_t,
+// written by residual_tile for the same wave tile.
+template <typename T, int kMode>
+__device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const T* __restrict__ eps_t,
                                         unsigned int cbits, const T* __restrict__ cq,
                                         const uint8_t* __restrict__ mask, const T* __restrict__ v,
-                                        T* __restrict__ y, int identity_rows, double& dot,
-                                        T* __restrict__ p = nullptr, Pre pre = Pre()) {
-  constexpr bool kPlain = kMode == JV_PLAIN, kRec = kMode == JV_REC;
+                                        T* __restrict__ y, int identity_rows, double& dot) {
+  constexpr bool kPlain = kMode == JV_PLAIN;
   const unsigned int sbits = cbits;
   auto face = [&](int P, T f[4]) {
     const long b = w.n00 + w.sxy * P;
@@ -192,10 +171,8 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
   // only in the next iteration, and no load is issued after those prefetches
   // inside an iteration: a wait for any later load would drain them (loads
   // retire in order).
-  const bool z_own = kRec && !w.col_ok && w.node_ok;   // owned node outside every element face loaded
   T fb[4], ft[4], fn[4];
   T cc[8], cn[8], ee = T(0), en = T(0);
-  T yc = T(0), pc = T(0), zc = T(0);
   uint8_t mk = 0, mkn = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) fb[k] = ft[k] = fn[k] = T(0);
@@ -220,13 +197,9 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
       rdzl = g.rdz[L];
     }
   }
-  const JvGo<T> go = pre();
-  if (!go.go) return false;
   double ahx, ahy, axy;
   w.weights(ahx, ahy, axy);
   const double hzl = zhi - zlo;
-  const T beta = go.beta;
-  const bool rec_old = kRec && !go.first;
   T carry = T(0);
   // Retire the loads above before the loop.  Otherwise the first iteration's
   // operands are still in flight on entry, and the wait inserted for them
@@ -246,18 +219,6 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
     const int L1 = L + 1;
     const double hz = lane_value(hzl, L - w.Lbeg);    // 1 outside [0, nz-2]
     const double rhz = lane_value(rdzl, L - w.Lbeg);
-    // the recurrence mode's y, p (and z) at this layer's owned node, issued
-    // before the prefetches so that their wait does not drain them (loading
-    // them a layer ahead too costs registers: spills at 4 waves per SIMD,
-    // measured slower, as is 3 waves per SIMD)
-    if (kRec && w.node_ok && L >= w.k0) {
-      const long n = w.node(g, L);
-      if (rec_old) {
-        yc = y[n];
-        pc = p[n];
-      }
-      if (z_own) zc = v[n];
-    }
     // prefetch the next top face, the next layer's data and the next flag
     if (w.col_ok && L1 <= w.Lend && L1 + 1 <= g.nz - 1) face(L1 + 1, fn);
     if (w.col_ok && L1 <= w.Lend && L1 <= g.nz - 2) {
@@ -282,16 +243,6 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
     if (w.node_ok && L >= w.k0) {
       const long n = w.node(g, L);
       T val = carry + bot;
-      if (kRec) {
-        const T zo = w.col_ok ? fb[3] : zc;   // z at the owned node (gi, gj, L)
-        T pv = zo;
-        if (rec_old) {
-          val += beta * yc;
-          pv += beta * pc;
-        }
-        p[n] = pv;
-        dot += (double)pv * (double)val;
-      }
       if (kPlain && mk && identity_rows) val = identity_rows == 1 ? v[n] : T(0);
       y[n] = val;
     }
@@ -306,11 +257,20 @@ __device__ __forceinline__ bool jv_tile(const Geom& g, const WaveTile& w, const 
     ee = en;
     mk = mkn;
   }
-  return true;
 }
 
+// What the CG sweep learns once its first loads are in flight: whether to go
+// on (the solve has not stopped), beta, and whether this is the first
+// iteration (p = z, y = J z).
+template <typename T>
+struct JvGo {
+  bool go;
+  T beta;
+  bool first;
+};
+
 // ---------------------------------------------------------------------------
-// The CG sweep (JV_REC) on raw buffer resources.
+// The CG sweep on raw buffer resources.
 //
 // Every load and store of this sweep is a raw buffer access.  A lane whose
 // access is not wanted passes an offset beyond the resource's range; the
@@ -414,9 +374,12 @@ struct CgStage {
   T c[8];
 };
 
-// CG sweep on one wave tile, numerically the JV_REC mode of jv_tile (the
-// arithmetic is the same Haar-diagonal element operator; partial sums are
-// grouped differently).  The bottom face of each element layer is kept in
+// CG sweep on one wave tile: v = z (zero on Dirichlet nodes); on owned rows
+// y = J z + beta y and p = z + beta p (first: y = J z, p = z), so y = J p by
+// recurrence; dot += p^T y over owned nodes.  pre() is called by every wave
+// once the first loads are issued (it may synchronise the block); false: the
+// solve has stopped and nothing was stored.  The element operator is
+// jv_element's, with the partial sums grouped per face.  The bottom face of each element layer is kept in
 // the 2D Haar basis from the step before, and the top-face output of one
 // element layer is added to the bottom-face output of the next in that basis,
 // so each face is transformed, inverse-transformed and gathered across lanes
