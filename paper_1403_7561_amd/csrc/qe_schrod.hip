@@ -456,45 +456,117 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_square(long n, const double
 }
 
 // ---------------------------------------------------------------- host side
-// Cyclic Jacobi eigenvalues of the symmetric k x k matrix A (row-major, in
-// place); V receives the eigenvectors as columns, w the eigenvalues.
-static void jacobi_eig(int k, std::vector<double>& A, std::vector<double>& V, std::vector<double>& w) {
-  V.assign((size_t)k * k, 0.0);
-  for (int i = 0; i < k; ++i) V[(size_t)i * k + i] = 1.0;
-  double norm = 0.0;
-  for (double a : A) norm += a * a;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0;
-    for (int p = 0; p < k; ++p)
-      for (int q = p + 1; q < k; ++q) off += 2.0 * A[(size_t)p * k + q] * A[(size_t)p * k + q];
-    if (off <= 1e-30 * norm) break;
-    for (int p = 0; p < k; ++p)
-      for (int q = p + 1; q < k; ++q) {
-        const double apq = A[(size_t)p * k + q];
-        if (apq == 0.0) continue;
-        const double app = A[(size_t)p * k + p], aqq = A[(size_t)q * k + q];
-        const double theta = (aqq - app) / (2.0 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-        for (int r = 0; r < k; ++r) {   // A <- A J (columns p, q)
-          const double arp = A[(size_t)r * k + p], arq = A[(size_t)r * k + q];
-          A[(size_t)r * k + p] = c * arp - s * arq;
-          A[(size_t)r * k + q] = s * arp + c * arq;
+// Eigen-decomposition of the symmetric k x k matrix A (row-major, destroyed):
+// Householder reduction to tridiagonal form with the transformations
+// accumulated, then the implicit QL iteration with Wilkinson-type shifts on
+// the tridiagonal matrix, each plane rotation also applied to the
+// accumulated basis (Golub and Van Loan, Matrix Computations, Secs. 8.3.1
+// and 8.3.5; Bowdler, Martin, Reinsch and Wilkinson, Numer. Math. 11, 1968).
+// V receives the eigenvectors as columns (row-major), w the eigenvalues.
+static void sym_eig(int k, std::vector<double>& A, std::vector<double>& V, std::vector<double>& w) {
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * k + j]; };
+  // the basis is accumulated transposed (row i = column i of V), so that
+  // each transformation updates contiguous rows
+  std::vector<double> Qt((size_t)k * k, 0.0);
+  auto q = [&](int i, int j) -> double& { return Qt[(size_t)j * k + i]; };
+  for (int i = 0; i < k; ++i) q(i, i) = 1.0;
+  std::vector<double> v(k), p(k), d(k), e(k, 0.0);
+  // reduction: column j's part below the subdiagonal is annihilated by
+  // H = I - 2 v v^T / (v^T v) acting on rows / columns j+1 .. k-1
+  for (int j = 0; j + 2 < k; ++j) {
+    double nx = 0.0;
+    for (int i = j + 1; i < k; ++i) nx += a(i, j) * a(i, j);
+    nx = std::sqrt(nx);
+    if (nx == 0.0) continue;
+    const double x0 = a(j + 1, j);
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    double vv = 0.0;
+    for (int i = j + 1; i < k; ++i) {
+      v[i] = a(i, j);
+      if (i == j + 1) v[i] -= alpha;
+      vv += v[i] * v[i];
+    }
+    if (vv == 0.0) continue;
+    const double tau = 2.0 / vv;
+    // H A H = A - v w^T - w v^T with p = tau A v, w = p - (tau/2)(v^T p) v
+    double vp = 0.0;
+    for (int i = j + 1; i < k; ++i) {
+      double s = 0.0;
+      for (int t = j + 1; t < k; ++t) s += a(i, t) * v[t];
+      p[i] = tau * s;
+      vp += v[i] * p[i];
+    }
+    const double h = 0.5 * tau * vp;
+    for (int i = j + 1; i < k; ++i) p[i] -= h * v[i];
+    for (int i = j + 1; i < k; ++i)
+      for (int t = j + 1; t < k; ++t) a(i, t) -= v[i] * p[t] + p[i] * v[t];
+    a(j + 1, j) = a(j, j + 1) = alpha;
+    for (int i = j + 2; i < k; ++i) a(i, j) = a(j, i) = 0.0;
+    // V <- V H, i.e. rows j+1 .. k-1 of Qt <- H (those rows)
+    for (int r = 0; r < k; ++r) p[r] = 0.0;
+    for (int t = j + 1; t < k; ++t) {
+      const double* qt = &Qt[(size_t)t * k];
+      for (int r = 0; r < k; ++r) p[r] += v[t] * qt[r];
+    }
+    for (int t = j + 1; t < k; ++t) {
+      double* qt = &Qt[(size_t)t * k];
+      const double f = tau * v[t];
+      for (int r = 0; r < k; ++r) qt[r] -= f * p[r];
+    }
+  }
+  for (int i = 0; i < k; ++i) d[i] = a(i, i);
+  for (int i = 0; i + 1 < k; ++i) e[i] = a(i + 1, i);   // e[i] couples i and i+1
+  // implicit QL on (d, e)
+  for (int l = 0; l < k; ++l) {
+    for (int iter = 0; iter < 60; ++iter) {
+      int m = l;
+      for (; m + 1 < k; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= 1e-16 * dd) break;
+      }
+      if (m == l) break;
+      // shift from the leading 2 x 2 block, the eigenvalue closer to d[l]
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      double s = 1.0, c = 1.0, pp = 0.0;
+      int i = m - 1;
+      bool deflated = false;
+      for (; i >= l; --i) {
+        const double f = s * e[i], b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {   // underflow: the chain splits here
+          d[i + 1] -= pp;
+          e[m] = 0.0;
+          deflated = true;
+          break;
         }
-        for (int r = 0; r < k; ++r) {   // A <- J^T A (rows p, q)
-          const double apr = A[(size_t)p * k + r], aqr = A[(size_t)q * k + r];
-          A[(size_t)p * k + r] = c * apr - s * aqr;
-          A[(size_t)q * k + r] = s * apr + c * aqr;
-        }
-        for (int r = 0; r < k; ++r) {
-          const double vrp = V[(size_t)r * k + p], vrq = V[(size_t)r * k + q];
-          V[(size_t)r * k + p] = c * vrp - s * vrq;
-          V[(size_t)r * k + q] = s * vrp + c * vrq;
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - pp;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        pp = s * r;
+        d[i + 1] = g + pp;
+        g = c * r - b;
+        double* qi = &Qt[(size_t)i * k];   // the same rotation on columns i, i+1 of V
+        double* qi1 = &Qt[(size_t)(i + 1) * k];
+        for (int t = 0; t < k; ++t) {
+          const double vi = qi[t], vi1 = qi1[t];
+          qi1[t] = s * vi + c * vi1;
+          qi[t] = c * vi - s * vi1;
         }
       }
+      if (deflated) continue;
+      d[l] -= pp;
+      e[l] = g;
+      e[m] = 0.0;
+    }
   }
-  w.resize(k);
-  for (int i = 0; i < k; ++i) w[i] = A[(size_t)i * k + i];
+  w = d;
+  V.resize((size_t)k * k);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) V[(size_t)i * k + j] = Qt[(size_t)j * k + i];
 }
 
 // Rayleigh-Ritz on the k x k pencil (GA, GB) (column-major, symmetric):
@@ -546,7 +618,7 @@ static bool rayleigh_ritz(int k, int nb, const double* GA, const double* GB, std
       Ap[(size_t)i * k + j] = Ap[(size_t)j * k + i] = m;
     }
   std::vector<double> V, w;
-  jacobi_eig(k, Ap, V, w);
+  sym_eig(k, Ap, V, w);
   std::vector<int> ord(k);
   for (int i = 0; i < k; ++i) ord[i] = i;
   std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a] < w[b]; });
