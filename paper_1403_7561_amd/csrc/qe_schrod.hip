@@ -216,6 +216,18 @@ struct ColMap {
   double lam[kMaxCols];
 };
 
+// Columns of the Rayleigh-Ritz basis: 0 .. k0-1 are those of Z (and H'Z, MZ);
+// k0 + i is column src[i] of P (and HP, MP), read in place.  P is stored
+// right after its block's K columns, so basis column c is column
+// basis_col(c) of the block.
+struct PCols {
+  int k0, K;
+  int src[kMaxCols];
+};
+__device__ __forceinline__ long basis_col(const PCols& pc, int c) {
+  return c < pc.k0 ? c : pc.K + pc.src[c - pc.k0];
+}
+
 // Per block and column c of the map: partial sums of |r|^2, |H'x|^2, |Mx|^2
 // with r = H'x - lam M x (blockIdx.y = column).
 __global__ __launch_bounds__(kVecThreads) void k_sch_norms(long N, ColMap cm, const double* __restrict__ HX,
@@ -263,14 +275,15 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_precond(long N, ColMap cm, 
 }
 
 // The Rayleigh-Ritz update of one operator's block (blockIdx.y: the block
-// vectors Z, H'Z, MZ): X <- Z[:, :k] C, in place in Z's first nb columns, and
-// (with_p) P <- Z[:, nb:k] C[nb:k, :], formed first so that X = P +
+// vectors Z, H'Z, MZ): X <- S C, in place in Z's first nb columns, and
+// (with_p) P <- S[:, nb:k] C[nb:k, :], where S is the basis [X W P] (pc:
+// P's columns read in place, before this thread overwrites its rows of P), formed first so that X = P +
 // Z[:, :nb] C[:nb, :] takes k nb products per row, not (2k - nb) nb.  C (k x
 // nb, column-major) is staged in LDS transposed (row j's nb coefficients
 // adjacent, rows padded to even), so one 16-byte LDS read serves two
 // products; each thread owns whole rows, so reading a row before writing it
 // back is safe.  A streaming pass: k reads and 2 nb writes per row.
-__global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int nb, int with_p,
+__global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int nb, int with_p, PCols pc,
                                                            const double* __restrict__ C, double* Z, double* HZ,
                                                            double* MZ, double* P, double* HP, double* MP) {
   constexpr int kLd = (kMaxCols + 1) & ~1;
@@ -293,7 +306,7 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int n
       for (int j0 = jb; j0 < je; j0 += 6) {
         double z[6];   // six loads in flight before any is used
 #pragma unroll
-        for (int u = 0; u < 6; ++u) z[u] = j0 + u < je ? B[(long)(j0 + u) * N + n] : 0.0;
+        for (int u = 0; u < 6; ++u) z[u] = j0 + u < je ? B[basis_col(pc, j0 + u) * N + n] : 0.0;
 #pragma unroll
         for (int u = 0; u < 6; ++u) {
           const int j = j0 + u;
@@ -324,7 +337,8 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int n
   }
 }
 
-// Both Gram matrices of the block, Z^T H'Z and Z^T MZ (k x k each, k <= 54),
+// Both Gram matrices of the basis S = [X W P], S^T H'S and S^T MS (k x k each,
+// k <= 54; pc: P's columns read in place),
 // on the FP64 matrix cores: per block over its rows, slabs of kGramRows rows
 // of Z, H'Z and MZ are staged in LDS (columns padded to 64 with zeros), and
 // each wave accumulates 16 x 16 output tiles with v_mfma_f64_16x16x4f64,
@@ -340,7 +354,7 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_update(long N, int k, int n
 constexpr int kGramRows = 32, kGramLd = 64;
 constexpr int kGramPer = (kGramRows * kGramLd + 255) / 256;   // staged values per thread and array
 typedef double qe_v4d __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(256) void k_sch_gram(long N, int k, const double* __restrict__ Z,
+__global__ __launch_bounds__(256) void k_sch_gram(long N, int k, PCols pc, const double* __restrict__ Z,
                                                   const double* __restrict__ HZ, const double* __restrict__ MZ,
                                                   double* __restrict__ part) {
   __shared__ double sz[kGramRows * kGramLd], sh[kGramRows * kGramLd], sm[kGramRows * kGramLd];
@@ -368,7 +382,7 @@ __global__ __launch_bounds__(256) void k_sch_gram(long N, int k, const double* _
       const int e = t + 256 * i;           // e = c * kGramRows + r: coalesced along rows
       const int c = e / kGramRows, r = e % kGramRows;
       const bool in = e < ne && r < rows;
-      const long o = in ? (long)c * N + base + r : 0;
+      const long o = in ? basis_col(pc, c) * N + base + r : 0;
       nz[i] = in ? Z[o] : 0.0;
       nh[i] = in ? HZ[o] : 0.0;
       nm[i] = in ? MZ[o] : 0.0;
@@ -435,18 +449,6 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_sum_parts2(const double* __
   }
   for (; b < n; ++b) a += part[((long)b * 2 + m) * len + e];
   out[i] = a;
-}
-
-// Z[:, dst] <- P[:, src] for the mapped columns, for the three block vectors
-// (blockIdx.y = 3 column + operator).
-__global__ __launch_bounds__(kVecThreads) void k_sch_gather(long N, ColMap cm, const double* __restrict__ P,
-                                                           const double* __restrict__ HP,
-                                                           const double* __restrict__ MP, double* Z, double* HZ,
-                                                           double* MZ) {
-  const int c = blockIdx.y / 3, t = blockIdx.y % 3;
-  const double* src = (t == 0 ? P : t == 1 ? HP : MP) + (long)cm.src[c] * N;
-  double* dst = (t == 0 ? Z : t == 1 ? HZ : MZ) + (long)cm.dst[c] * N;
-  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) dst[n] = src[n];
 }
 
 __global__ __launch_bounds__(kVecThreads) void k_sch_square(long n, const double* __restrict__ a,
@@ -657,12 +659,13 @@ static SchLayout sch_layout(long N, long nslots, int nz, long nwaves, int nb) {
   L.mbits = take(nwaves * 64 * 4);
   L.mask = take(N);
   L.dinv = take(N * 8);
-  L.Z = take((size_t)K * N * 8);
-  L.HZ = take((size_t)K * N * 8);
-  L.MZ = take((size_t)K * N * 8);
-  L.P = take((size_t)nb * N * 8);
-  L.HP = take((size_t)nb * N * 8);
-  L.MP = take((size_t)nb * N * 8);
+  // each block's P follows it: P's column i is the block's column K + i
+  L.Z = take((size_t)(K + nb) * N * 8);
+  L.P = L.Z + (size_t)K * N * 8;
+  L.HZ = take((size_t)(K + nb) * N * 8);
+  L.HP = L.HZ + (size_t)K * N * 8;
+  L.MZ = take((size_t)(K + nb) * N * 8);
+  L.MP = L.MZ + (size_t)K * N * 8;
   L.G = take((size_t)2 * K * K * 8);
   L.gpart = take((size_t)kGramBlocks * 2 * K * K * 8);
   L.C = take((size_t)K * nb * 8);
@@ -760,9 +763,10 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
   std::vector<double> hG(2 * (size_t)K * K), lam, Cm;
   // Gram matrices of the first k columns, Rayleigh-Ritz, and the new X (and
   // P from columns nb.. when with_p).
-  auto rr_update = [&](int k, bool with_p) -> qe_status {
+  // pc: the basis' P columns (none: pc.k0 = k)
+  auto rr_update = [&](int k, bool with_p, const PCols& pc) -> qe_status {
     double* G = f64(L.G);
-    hipLaunchKernelGGL(k_sch_gram, dim3(kGramBlocks), dim3(256), 0, s, N, k, Z, HZ, MZ, f64(L.gpart));
+    hipLaunchKernelGGL(k_sch_gram, dim3(kGramBlocks), dim3(256), 0, s, N, k, pc, Z, HZ, MZ, f64(L.gpart));
     // G (both matrices, column-major, one after the other) = fixed-order sum of the block partials
     hipLaunchKernelGGL(k_sch_sum_parts2, dim3((2 * k * k + kVecThreads - 1) / kVecThreads), dim3(kVecThreads), 0, s,
                        f64(L.gpart), kGramBlocks, k * k, G);
@@ -772,7 +776,7 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
     if (!rayleigh_ritz(k, nb, hG.data(), hG.data() + (size_t)k * k, lam, Cm)) return QE_ERR_KRYLOV_BREAKDOWN;
     QE_TRY(ck(hipMemcpyAsync(f64(L.C), Cm.data(), Cm.size() * 8, hipMemcpyHostToDevice, s), "copy"));
     const int ub = (int)std::max(1L, std::min((N + kVecThreads - 1) / kVecThreads, 1024L));
-    hipLaunchKernelGGL(k_sch_update, dim3(ub, 3), dim3(kVecThreads), 0, s, N, k, nb, with_p ? 1 : 0,
+    hipLaunchKernelGGL(k_sch_update, dim3(ub, 3), dim3(kVecThreads), 0, s, N, k, nb, with_p ? 1 : 0, pc,
                        f64(L.C), Z, HZ, MZ, f64(L.P), f64(L.HP), f64(L.MP));
     return ck(hipGetLastError(), "update launch");
   };
@@ -783,7 +787,11 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
     hipLaunchKernelGGL(k_sch_mask, dim3(vb), dim3(kVecThreads), 0, s, N, n_states, mask, Z);
   }
   apply(0, nb);
-  qe_status st = rr_update(nb, false);
+  PCols nopc;
+  std::memset(&nopc, 0, sizeof(nopc));
+  nopc.k0 = nb;
+  nopc.K = K;
+  qe_status st = rr_update(nb, false, nopc);
   if (st != QE_OK) return st == QE_ERR_KRYLOV_BREAKDOWN ? fail(st, "starting block is rank deficient") : st;
   bool have_p = false;
   int it = 0;
@@ -831,21 +839,18 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
     }
     hipLaunchKernelGGL(k_sch_precond, dim3(kSchBlocks, na), dim3(kVecThreads), 0, s, N, wmap, HZ, MZ, f64(L.dinv), Z);
     apply(nb, na);
-    int k = nb + na;
+    const int k = nb + na;
+    PCols pc;
+    std::memset(&pc, 0, sizeof(pc));
+    pc.k0 = k;
+    pc.K = K;
     if (have_p) {
-      ColMap pmap;
-      std::memset(&pmap, 0, sizeof(pmap));
-      pmap.n = na;
-      for (int a = 0; a < na; ++a) {
-        pmap.src[a] = active[a];
-        pmap.dst[a] = k + a;
-      }
-      hipLaunchKernelGGL(k_sch_gather, dim3(kSchBlocks, 3 * na), dim3(kVecThreads), 0, s, N, pmap, f64(L.P),
-                         f64(L.HP), f64(L.MP), Z, HZ, MZ);
-      st = rr_update(k + na, true);
-      if (st == QE_ERR_KRYLOV_BREAKDOWN) st = rr_update(k, true);   // drop P when [X W P] lost rank
+      // P's active columns join the basis where they are (no copy)
+      for (int a = 0; a < na; ++a) pc.src[a] = active[a];
+      st = rr_update(k + na, true, pc);
+      if (st == QE_ERR_KRYLOV_BREAKDOWN) st = rr_update(k, true, pc);   // drop P when [X W P] lost rank
     } else {
-      st = rr_update(k, true);
+      st = rr_update(k, true, pc);
     }
     if (st == QE_ERR_KRYLOV_BREAKDOWN) return fail(st, "the LOBPCG basis lost rank at iteration %d", it);
     if (st != QE_OK) return st;
