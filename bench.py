@@ -280,6 +280,7 @@ def main():
                    "global_batch": 1, "parallelism": "single GPU"},
         "newton_iters": reps[-1]["newton_iters"],
         "krylov_iters": reps[-1]["krylov_iters"],
+        "init_krylov_iters": reps[-1]["init_krylov_iters"],
         "res_final": reps[-1]["res_final"],
         "dot_electrons": [float(c) for c in counts],
         "jv_gdof_s": {"fp64": P.N / (ms64 * 1e-3) / 1e9, "fp32": P.N / (ms32 * 1e-3) / 1e9,
