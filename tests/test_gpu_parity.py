@@ -274,3 +274,31 @@ def test_full_size_double_dot_sampled():
     y = qe.qe_jv(P, dev_tensor(pert), dev_tensor(v)).cpu().numpy()[nodes]
     yo = gs.sampled_jv(dev, pert, v, nodes)
     assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+@pytest.mark.parametrize("stat,delta,ratio", [("linear", 1e-6, 1e-6), ("fd", 1e-8, 1e-3)])
+def test_cg_product_is_the_exact_jacobian(stat, delta, ratio):
+    """The CG's own J.v (the loop's sweep, not the qe_jv product) must be the
+    exact Jacobian of the residual.  From a start delta off the solution one
+    Newton step with a CG solved to 1e-10 multiplies ||F|| by about the
+    relative error of the Jacobian used, plus, for Fermi-Dirac electrons,
+    the quadratic term (delta / kT ~ 3e-5 here), so ||F_1|| / ||F_0|| <
+    ratio bounds that error.  The linear statistics make the residual affine
+    in phi (stiffness only); the FD case has Gauss-point coefficients on the
+    inversion layers, so it covers the sweep's coefficient path too."""
+    dev = gs.ragged_device(stat=stat)
+    po, res = solver.solve(dev, atol=1e-11)
+    P = qe.Problem(dev)
+    rng = np.random.default_rng(5)
+    free = dev.dir_id < 0
+    phi0 = res.phi.copy()
+    phi0[free] += delta * rng.standard_normal(int(free.sum()))
+    f0 = float(np.linalg.norm(po.residual(phi0)))
+    # one Newton step, an atol it cannot reach (so the CG tolerance is 1e-10)
+    opts = qe.qe_default_options(newton_atol=1e-30, newton_maxit=1, krylov_rtol_max=1e-10, init_guess=1)
+    phi, _, rep = qe.qe_solve(P, opts=opts, phi=dev_tensor(phi0), check=False)
+    print(stat, "||F0||", f0, rep)
+    assert rep["newton_iters"] == 1 and rep["ls_halvings"] == 0
+    assert rep["res0"] == pytest.approx(f0, rel=1e-6)
+    assert rep["res_final"] < ratio * rep["res0"]
+    assert rel_max(phi.cpu().numpy(), res.phi) < delta
