@@ -348,6 +348,10 @@ size_t qe_schrodinger_workspace_bytes(const qe_problem* p, int32_t n_states);
  * preconditioner, soft locking of converged vectors, and Rayleigh-Ritz on
  * the block [X, W, P] (Gram matrices on the GPU; the small dense generalized
  * eigenproblem on the host).  Operators use the wave-tiled J.v.
+ * The iteration runs on the bounding box of the free nodes grown by one
+ * node whenever that box is smaller than the mesh and the workspace holds
+ * it next to the box's copies of the inputs (the eigenpairs are the same:
+ * psi vanishes outside it); psi and psi2 are written on the whole mesh.
  * phi: device [N].  Stops when every wanted pair has
  * ||H x - E M x||_2 <= tol (||H x||_2 + |E| ||M x||_2) or after maxit
  * iterations (QE_ERR_NOT_CONVERGED, results still written).

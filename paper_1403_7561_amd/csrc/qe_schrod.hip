@@ -192,11 +192,23 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_sch_rand(long N, int ncol, uint64_t seed,
+// A box of nodes [i0, i0 + bx) x [j0, j0 + by) x [k0, k0 + bz) of a gx x gy x gz
+// mesh, x fastest in both numberings.
+struct BoxMap {
+  int bx, by, bz, i0, j0, k0, gx, gy;
+};
+__device__ __forceinline__ long box_to_mesh(const BoxMap& b, long n) {
+  const int i = (int)(n % b.bx), j = (int)((n / b.bx) % b.by), k = (int)(n / ((long)b.bx * b.by));
+  return (long)(i + b.i0) + (long)b.gx * ((long)(j + b.j0) + (long)b.gy * (k + b.k0));
+}
+
+// The random numbers are drawn by mesh node index, so a box's block equals
+// the mesh's block restricted to it.
+__global__ __launch_bounds__(kVecThreads) void k_sch_rand(long N, int ncol, uint64_t seed, BoxMap bm,
                                                          const uint8_t* __restrict__ mask, double* __restrict__ X) {
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x)
     for (int c = 0; c < ncol; ++c) {
-      const uint64_t r = splitmix64(seed ^ splitmix64((uint64_t)c * 0x100000001B3ull + (uint64_t)n));
+      const uint64_t r = splitmix64(seed ^ splitmix64((uint64_t)c * 0x100000001B3ull + (uint64_t)box_to_mesh(bm, n)));
       const double u = (double)(r >> 11) * (1.0 / 9007199254740992.0);   // [0, 1)
       X[(long)c * N + n] = mask[n] ? 0.0 : 2.0 * u - 1.0;
     }
@@ -207,6 +219,59 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_mask(long N, int ncol, cons
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x)
     if (mask[n])
       for (int c = 0; c < ncol; ++c) X[(long)c * N + n] = 0.0;
+}
+
+// Bounding box of the nodes that are not fixed, as maxima that start at 0:
+// b[d] = max (n_d - 1 - i_d) and b[3 + d] = max (i_d + 1) over those nodes.
+__global__ __launch_bounds__(kVecThreads) void k_sch_box(int nx, int ny, long N, const uint8_t* __restrict__ fixed,
+                                                        int* __restrict__ b) {
+  const int nz = (int)(N / ((long)nx * ny));
+  int m[6] = {0, 0, 0, 0, 0, 0};
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
+    if (fixed[n]) continue;
+    const int i = (int)(n % nx), j = (int)((n / nx) % ny), k = (int)(n / ((long)nx * ny));
+    m[0] = max(m[0], nx - 1 - i);
+    m[1] = max(m[1], ny - 1 - j);
+    m[2] = max(m[2], nz - 1 - k);
+    m[3] = max(m[3], i + 1);
+    m[4] = max(m[4], j + 1);
+    m[5] = max(m[5], k + 1);
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    for (int o = 32; o > 0; o >>= 1) m[d] = max(m[d], __shfl_xor(m[d], o, 64));
+    if ((threadIdx.x & 63) == 0 && m[d] > 0) atomicMax(b + d, m[d]);
+  }
+}
+
+// dst[c][n] = src[c][mesh index of box node n] for the ncol columns.
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_sch_box_gather(BoxMap bm, int ncol, long sstride,
+                                                               const T* __restrict__ src, T* __restrict__ dst) {
+  const long nb = (long)bm.bx * bm.by * bm.bz;
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < nb; n += (long)gridDim.x * blockDim.x) {
+    const long m = box_to_mesh(bm, n);
+    for (int c = 0; c < ncol; ++c) dst[c * nb + n] = src[c * sstride + m];
+  }
+}
+
+// The box's columns back on the whole mesh, 0 outside the box; psi2 (if
+// not NULL) receives their squares.
+__global__ __launch_bounds__(kVecThreads) void k_sch_box_scatter(BoxMap bm, long N, int ncol,
+                                                                const double* __restrict__ src,
+                                                                double* __restrict__ psi, double* __restrict__ psi2) {
+  const long nb = (long)bm.bx * bm.by * bm.bz;
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(n % bm.gx) - bm.i0, j = (int)((n / bm.gx) % bm.gy) - bm.j0,
+              k = (int)(n / ((long)bm.gx * bm.gy)) - bm.k0;
+    const bool in = i >= 0 && i < bm.bx && j >= 0 && j < bm.by && k >= 0 && k < bm.bz;
+    const long l = in ? (long)i + (long)bm.bx * ((long)j + (long)bm.by * k) : 0;
+    for (int c = 0; c < ncol; ++c) {
+      const double v = in ? src[c * nb + l] : 0.0;
+      psi[c * N + n] = v;
+      if (psi2) psi2[c * N + n] = v * v;
+    }
+  }
 }
 
 struct ColMap {
@@ -682,76 +747,39 @@ static bool mesh_ok(const qe_problem* p) {
 }
 
 
-}  // namespace qe
-
-using namespace qe;
-
-extern "C" {
-
-size_t qe_schrodinger_workspace_bytes(const qe_problem* p, int32_t n_states) {
-  if (!mesh_ok(p) || n_states < 1 || n_states > QE_MAX_EIG) return 0;
+// LOBPCG on the mesh of p, which is the caller's mesh or a box of it: the
+// operators, the iteration and the results (psi, psi2: column stride p's
+// node count).  bm places p's nodes in the caller's mesh for the random
+// starting block.
+static qe_status sch_core(const qe_problem* p, const double* inv_mass, const double* v0, const uint8_t* fixed,
+                          const double* phi, double sigma, const BoxMap& bm, int32_t n_states, double tol,
+                          int32_t maxit, uint64_t seed, int32_t guess, double* E, double* psi, double* psi2,
+                          int32_t* iters, char* ws, size_t ws_bytes, hipStream_t s) {
   const long N = (long)p->nx * p->ny * p->nz;
-  const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, 0);
-  return sch_layout(N, tile_slots(p->nx, p->ny, p->nz), p->nz, wm.nwaves, n_states + 2).total;
-}
-
-qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, const double* phi, int32_t n_states,
-                               double tol, int32_t maxit, uint64_t seed, int32_t guess, double* E, double* psi,
-                               double* psi2, int32_t* iters, void* ws_, size_t ws_bytes, void* stream) {
-  clear_error();
-  if (!mesh_ok(p)) return fail(QE_ERR_INVALID_ARG, "bad mesh (nx, ny, nz >= 2 and x, y, z needed)");
-  if (!sp || !sp->inv_mass || !sp->v0) return fail(QE_ERR_INVALID_ARG, "inv_mass / v0 is NULL");
-  if (!phi || !E || !psi) return fail(QE_ERR_INVALID_ARG, "phi / E / psi is NULL");
-  if (n_states < 1 || n_states > QE_MAX_EIG) return fail(QE_ERR_INVALID_ARG, "n_states outside [1, %d]", QE_MAX_EIG);
-  if (!(tol > 0.0 && tol < 1.0)) return fail(QE_ERR_INVALID_ARG, "tol must be in (0, 1)");
-  if (maxit < 1) return fail(QE_ERR_INVALID_ARG, "maxit < 1");
-  const long N = (long)p->nx * p->ny * p->nz, Ecount = (long)(p->nx - 1) * (p->ny - 1) * (p->nz - 1);
   const int nb = n_states + 2, K = 3 * nb;
-  if (N < 4L * nb) return fail(QE_ERR_INVALID_ARG, "mesh too small for %d states", n_states);
   Geom g{p->nx, p->ny, p->nz, p->x, p->y, p->z, nullptr};
   const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, 0);
-  const long nslots = tile_slots(p->nx, p->ny, p->nz);
-  const SchLayout L = sch_layout(N, nslots, p->nz, wm.nwaves, nb);
-  if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  const SchLayout L = sch_layout(N, tile_slots(p->nx, p->ny, p->nz), p->nz, wm.nwaves, nb);
   if (ws_bytes < L.total) return fail(QE_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
-  char* ws = reinterpret_cast<char*>(ws_);
-  hipStream_t s = (hipStream_t)stream;
   auto f64 = [&](size_t o) { return reinterpret_cast<double*>(ws + o); };
   auto ck = [&](hipError_t e, const char* what) -> qe_status {
     return e == hipSuccess ? QE_OK : fail(QE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
   };
   const int vb = vec_blocks(N);
-  // ---- checks and the shift sigma below every V
-  int* dflags = reinterpret_cast<int*>(ws + L.flags);
-  QE_TRY(ck(hipMemsetAsync(dflags, 0, sizeof(int), s), "memset"));
-  hipLaunchKernelGGL(k_sch_validate, dim3(vb), dim3(kVecThreads), 0, s, Ecount, N, sp->inv_mass, sp->v0, phi, dflags);
-  hipLaunchKernelGGL(k_sch_vmin, dim3(kSchBlocks), dim3(kVecThreads), 0, s, g, sp->v0, phi, f64(L.part));
-  std::vector<double> hp(kSchBlocks);
-  int hf = 0;
-  QE_TRY(ck(hipMemcpyAsync(&hf, dflags, sizeof(int), hipMemcpyDeviceToHost, s), "copy"));
-  QE_TRY(ck(hipMemcpyAsync(hp.data(), f64(L.part), kSchBlocks * 8, hipMemcpyDeviceToHost, s), "copy"));
-  QE_TRY(ck(hipStreamSynchronize(s), "sync"));
-  if (hf & 1) return fail(QE_ERR_INVALID_ARG, "inv_mass must be finite and > 0");
-  if (hf & 2) return fail(QE_ERR_NONFINITE, "v0 not finite");
-  if (hf & 4) return fail(QE_ERR_NONFINITE, "phi not finite");
-  double vmin = INFINITY;
-  for (double v : hp) vmin = std::min(vmin, v);
-  const double sigma = vmin - 0.1;   // eV below every V: H - sigma M is SPD
   // ---- operators
   g.rdz = f64(L.rdz);
   g.hz = g.rdz + (p->nz - 1);
   launch_stage_rdz(s, p->nz, p->z, f64(L.rdz));
-  hipLaunchKernelGGL(k_sch_coef, dim3(vb), dim3(kVecThreads), 0, s, g, sp->inv_mass, sp->v0, phi, sigma, kHB2M,
+  hipLaunchKernelGGL(k_sch_coef, dim3(vb), dim3(kVecThreads), 0, s, g, inv_mass, v0, phi, sigma, kHB2M,
                      f64(L.eH), f64(L.cH));
   uint8_t* mask = reinterpret_cast<uint8_t*>(ws + L.mask);
-  if (sp->fixed)
-    QE_TRY(ck(hipMemcpyAsync(mask, sp->fixed, N, hipMemcpyDeviceToDevice, s), "copy"));
+  if (fixed)
+    QE_TRY(ck(hipMemcpyAsync(mask, fixed, N, hipMemcpyDeviceToDevice, s), "copy"));
   else
     QE_TRY(ck(hipMemsetAsync(mask, 0, N, s), "memset"));
   unsigned int* mbits = reinterpret_cast<unsigned int*>(ws + L.mbits);
   hipLaunchKernelGGL(k_sch_mbits, dim3(wm.nblocks), dim3(256), 0, s, g, wm, mask, mbits);
-  hipLaunchKernelGGL(k_sch_diag, dim3(vb), dim3(kVecThreads), 0, s, g, sp->inv_mass, sp->v0, phi, mask, sigma, kHB2M,
+  hipLaunchKernelGGL(k_sch_diag, dim3(vb), dim3(kVecThreads), 0, s, g, inv_mass, v0, phi, mask, sigma, kHB2M,
                      f64(L.dinv));
   double *Z = f64(L.Z), *HZ = f64(L.HZ), *MZ = f64(L.MZ);
   // H and M of columns c0 .. c0 + n - 1 of Z into HZ, MZ (one launch; the
@@ -781,7 +809,7 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
     return ck(hipGetLastError(), "update launch");
   };
   // ---- starting block
-  hipLaunchKernelGGL(k_sch_rand, dim3(vb), dim3(kVecThreads), 0, s, N, nb, seed, mask, Z);
+  hipLaunchKernelGGL(k_sch_rand, dim3(vb), dim3(kVecThreads), 0, s, N, nb, seed, bm, mask, Z);
   if (guess) {   // the caller's vectors start the first n_states columns (guards stay random)
     QE_TRY(ck(hipMemcpyAsync(Z, psi, (size_t)n_states * N * 8, hipMemcpyDeviceToDevice, s), "copy"));
     hipLaunchKernelGGL(k_sch_mask, dim3(vb), dim3(kVecThreads), 0, s, N, n_states, mask, Z);
@@ -864,6 +892,121 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
   QE_TRY(ck(hipStreamSynchronize(s), "sync"));
   if (iters) *iters = it;
   return converged ? QE_OK : fail(QE_ERR_NOT_CONVERGED, "eigensolver hit maxit (%d)", maxit);
+}
+
+
+}  // namespace qe
+
+using namespace qe;
+
+extern "C" {
+
+size_t qe_schrodinger_workspace_bytes(const qe_problem* p, int32_t n_states) {
+  if (!mesh_ok(p) || n_states < 1 || n_states > QE_MAX_EIG) return 0;
+  const long N = (long)p->nx * p->ny * p->nz;
+  const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, 0);
+  return sch_layout(N, tile_slots(p->nx, p->ny, p->nz), p->nz, wm.nwaves, n_states + 2).total;
+}
+
+qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, const double* phi, int32_t n_states,
+                               double tol, int32_t maxit, uint64_t seed, int32_t guess, double* E, double* psi,
+                               double* psi2, int32_t* iters, void* ws_, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!mesh_ok(p)) return fail(QE_ERR_INVALID_ARG, "bad mesh (nx, ny, nz >= 2 and x, y, z needed)");
+  if (!sp || !sp->inv_mass || !sp->v0) return fail(QE_ERR_INVALID_ARG, "inv_mass / v0 is NULL");
+  if (!phi || !E || !psi) return fail(QE_ERR_INVALID_ARG, "phi / E / psi is NULL");
+  if (n_states < 1 || n_states > QE_MAX_EIG) return fail(QE_ERR_INVALID_ARG, "n_states outside [1, %d]", QE_MAX_EIG);
+  if (!(tol > 0.0 && tol < 1.0)) return fail(QE_ERR_INVALID_ARG, "tol must be in (0, 1)");
+  if (maxit < 1) return fail(QE_ERR_INVALID_ARG, "maxit < 1");
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const long N = (long)nx * ny * nz, Ecount = (long)(nx - 1) * (ny - 1) * (nz - 1);
+  const int nb = n_states + 2;
+  if (N < 4L * nb) return fail(QE_ERR_INVALID_ARG, "mesh too small for %d states", n_states);
+  const Geom g{nx, ny, nz, p->x, p->y, p->z, nullptr};
+  const WaveMap wm = make_wavemap(nx, ny, nz, 0);
+  const SchLayout L = sch_layout(N, tile_slots(nx, ny, nz), nz, wm.nwaves, nb);
+  if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total) return fail(QE_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  char* ws = reinterpret_cast<char*>(ws_);
+  hipStream_t s = (hipStream_t)stream;
+  auto ck = [&](hipError_t e, const char* what) -> qe_status {
+    return e == hipSuccess ? QE_OK : fail(QE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  };
+  const int vb = vec_blocks(N);
+  // ---- checks, the shift sigma below every V, and the box of the free nodes
+  int* dflags = reinterpret_cast<int*>(ws + L.flags);
+  QE_TRY(ck(hipMemsetAsync(dflags, 0, 7 * sizeof(int), s), "memset"));
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  hipLaunchKernelGGL(k_sch_validate, dim3(vb), dim3(kVecThreads), 0, s, Ecount, N, sp->inv_mass, sp->v0, phi, dflags);
+  hipLaunchKernelGGL(k_sch_vmin, dim3(kSchBlocks), dim3(kVecThreads), 0, s, g, sp->v0, phi, part);
+  if (sp->fixed) hipLaunchKernelGGL(k_sch_box, dim3(vb), dim3(kVecThreads), 0, s, nx, ny, N, sp->fixed, dflags + 1);
+  std::vector<double> hp(kSchBlocks);
+  int hf[7] = {0, 0, 0, 0, 0, 0, 0};
+  QE_TRY(ck(hipMemcpyAsync(hf, dflags, sizeof(hf), hipMemcpyDeviceToHost, s), "copy"));
+  QE_TRY(ck(hipMemcpyAsync(hp.data(), part, kSchBlocks * 8, hipMemcpyDeviceToHost, s), "copy"));
+  QE_TRY(ck(hipStreamSynchronize(s), "sync"));
+  if (hf[0] & 1) return fail(QE_ERR_INVALID_ARG, "inv_mass must be finite and > 0");
+  if (hf[0] & 2) return fail(QE_ERR_NONFINITE, "v0 not finite");
+  if (hf[0] & 4) return fail(QE_ERR_NONFINITE, "phi not finite");
+  double vmin = INFINITY;
+  for (double v : hp) vmin = std::min(vmin, v);
+  const double sigma = vmin - 0.1;   // eV below every V: H - sigma M is SPD
+  const BoxMap whole{nx, ny, nz, 0, 0, 0, nx, ny};
+  // Every node outside the free nodes' bounding box grown by one node is
+  // fixed and touches only elements whose nodes are all fixed, so psi is 0
+  // there and the box (with its own fixed nodes, and the natural condition
+  // wherever it meets the mesh boundary) has the same eigenpairs.
+  if (sp->fixed && hf[4] > 0) {
+    const int n[3] = {nx, ny, nz};
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::max(n[d] - 1 - hf[1 + d] - 1, 0);
+      hi[d] = std::min(hf[4 + d] - 1 + 1, n[d] - 1);
+    }
+    const BoxMap bm{hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1, lo[0], lo[1], lo[2], nx, ny};
+    const long Nb = (long)bm.bx * bm.by * bm.bz, Eb = (long)(bm.bx - 1) * (bm.by - 1) * (bm.bz - 1);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+      const size_t o = off;
+      off = (off + b + 255) & ~size_t(255);
+      return o;
+    };
+    const size_t o_psi = take((size_t)n_states * Nb * 8), o_im = take(Eb * 8), o_v0 = take(Eb * 8),
+                 o_phi = take(Nb * 8), o_fx = take(Nb);
+    const WaveMap wmb = make_wavemap(bm.bx, bm.by, bm.bz, 0);
+    const size_t need = off + sch_layout(Nb, tile_slots(bm.bx, bm.by, bm.bz), bm.bz, wmb.nwaves, nb).total;
+    if (Nb < N && Nb >= 4L * nb && need <= ws_bytes) {
+      qe_problem pb = *p;
+      pb.nx = bm.bx;
+      pb.ny = bm.by;
+      pb.nz = bm.bz;
+      pb.x = p->x + bm.i0;
+      pb.y = p->y + bm.j0;
+      pb.z = p->z + bm.k0;
+      const BoxMap em{bm.bx - 1, bm.by - 1, bm.bz - 1, bm.i0, bm.j0, bm.k0, nx - 1, ny - 1};
+      double *psib = reinterpret_cast<double*>(ws + o_psi), *imb = reinterpret_cast<double*>(ws + o_im),
+             *v0b = reinterpret_cast<double*>(ws + o_v0), *phib = reinterpret_cast<double*>(ws + o_phi);
+      uint8_t* fxb = reinterpret_cast<uint8_t*>(ws + o_fx);
+      const int gb = vec_blocks(Nb);
+      hipLaunchKernelGGL(k_sch_box_gather<double>, dim3(gb), dim3(kVecThreads), 0, s, em, 1, Ecount, sp->inv_mass, imb);
+      hipLaunchKernelGGL(k_sch_box_gather<double>, dim3(gb), dim3(kVecThreads), 0, s, em, 1, Ecount, sp->v0, v0b);
+      hipLaunchKernelGGL(k_sch_box_gather<double>, dim3(gb), dim3(kVecThreads), 0, s, bm, 1, N, phi, phib);
+      hipLaunchKernelGGL(k_sch_box_gather<uint8_t>, dim3(gb), dim3(kVecThreads), 0, s, bm, 1, N, sp->fixed, fxb);
+      if (guess)
+        hipLaunchKernelGGL(k_sch_box_gather<double>, dim3(gb), dim3(kVecThreads), 0, s, bm, n_states, N, psi, psib);
+      QE_TRY(ck(hipGetLastError(), "box launch"));
+      const qe_status st = sch_core(&pb, imb, v0b, fxb, phib, sigma, bm, n_states, tol, maxit, seed, guess, E, psib,
+                                    nullptr, iters, ws + off, ws_bytes - off, s);
+      if (st != QE_OK && st != QE_ERR_NOT_CONVERGED) return st;
+      hipLaunchKernelGGL(k_sch_box_scatter, dim3(vb), dim3(kVecThreads), 0, s, bm, N, n_states, psib, psi, psi2);
+      QE_TRY(ck(hipGetLastError(), "launch"));
+      QE_TRY(ck(hipStreamSynchronize(s), "sync"));
+      return st;
+    }
+  }
+  return sch_core(p, sp->inv_mass, sp->v0, sp->fixed, phi, sigma, whole, n_states, tol, maxit, seed, guess, E, psi,
+                  psi2, iters, ws, ws_bytes, s);
 }
 
 }  // extern "C"

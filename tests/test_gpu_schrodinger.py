@@ -73,6 +73,21 @@ def test_finite_well_unequal_masses():
     compare(P, np.where(well, 1 / 0.067, 1.0), np.where(well, 0.0, 0.1), np.zeros(P.N), fixed, 3)
 
 
+def test_free_nodes_in_a_corner():
+    """Free nodes in one corner, including nodes on two faces of the mesh
+    (the natural condition holds there), with per-element masses and band
+    edges and a nodal potential drawn at random: the solve runs on the free
+    nodes' bounding box grown by one node, and its eigenpairs, scattered back
+    with zeros outside, must be the whole-mesh eigenpairs of the oracle."""
+    x, y, z = np.linspace(0, 12, 13), np.linspace(0, 8, 10) ** 1.2, np.linspace(0, 6, 8)
+    P = mesh_problem(x, y, z)
+    Z, Y, X = np.meshgrid(np.arange(8), np.arange(10), np.arange(13), indexing="ij")
+    fixed = ~((X <= 6) & (Y >= 3) & (Z >= 1) & (Z <= 5)).ravel()
+    E_ = 12 * 9 * 7
+    rng = np.random.default_rng(3)
+    compare(P, 1.0 + rng.random(E_), 0.2 * rng.random(E_), 0.05 * rng.standard_normal(P.N), fixed, 4)
+
+
 QBOX = (0.0, 70.0, 60.0, 140.0, 40.0, 100.0)   # quantum region around the plunger P1
 
 
