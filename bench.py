@@ -173,6 +173,7 @@ def schrodinger_run(synth, qe, torch, dev, P, opts, phi_sc):
     torch.cuda.synchronize()
     t_eig = time.perf_counter() - t0
     box = (0.0, 70.0, 60.0, 140.0, 40.0, 100.0)
+    region_t = torch.as_tensor(region.astype("uint8"), device=P.device)
     t0 = time.perf_counter()
     phi_k, guess, hist, lob = phi_sc.clone(), None, [], []
     for _ in range(60):
@@ -180,8 +181,8 @@ def schrodinger_run(synth, qe, torch, dev, P, opts, phi_sc):
                                                          maxit=3000, ws=ws, guess=guess)
         guess = psi16
         lob.append(it16)
-        st = synth.QuantumStates(psi2=psi2.cpu().numpy(), phi_k=phi_k.cpu().numpy(), E_i=E16, region=region)
-        Pq = qe.Problem(synth.with_quantum(dev, st))
+        # the states stay on the device; the problem's other arrays are shared
+        Pq = P.with_quantum(synth.QuantumStates(psi2=psi2, phi_k=phi_k, E_i=E16, region=region_t))
         new, _, rep = qe.qe_solve(Pq, opts=opts, want_density=False)
         hist.append(float((new - phi_k).abs().max()))
         phi_k = new

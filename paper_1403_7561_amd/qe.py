@@ -236,21 +236,46 @@ class Problem:
                                       sg.data_ptr() if sg is not None else None, float(sh.robin_d),
                                       float(sh.robin_eps), float(sh.phi0))
         self.n_sheets = len(sheets)
-        # predictor-corrector states: |psi|^2 and phi^(k) on the device, levels on the host
-        q = getattr(dev, "quantum", None)
-        self.c_quantum = None
-        if q is not None:
-            self.q_psi2 = torch.as_tensor(np.ascontiguousarray(q.psi2, dtype=np.float64), **f64)
-            self.q_phik = torch.as_tensor(np.ascontiguousarray(q.phi_k, dtype=np.float64), **f64)
-            E = np.ascontiguousarray(q.E_i, dtype=np.float64)
-            self.q_E = (ctypes.c_double * E.size)(*E.tolist())
-            reg = getattr(q, "region", None)
-            self.q_region = None if reg is None else torch.as_tensor(
-                np.ascontiguousarray(reg, dtype=np.uint8), device=device)
-            self.c_quantum = CQuantum(int(E.size), int(q.confinement), self.q_psi2.data_ptr(),
-                                      self.q_phik.data_ptr(), self.q_E, float(q.m_t),
-                                      self.q_region.data_ptr() if self.q_region is not None else None)
         self.device = device
+        self._set_quantum(getattr(dev, "quantum", None))
+
+    def _set_quantum(self, q):
+        """Predictor-corrector states: |psi|^2 and phi^(k) on the device (a
+        float64 device tensor is used as it is, arrays are copied), levels on
+        the host."""
+        torch = _torch()
+        f64 = dict(dtype=torch.float64, device=self.device)
+
+        def dev64(a):
+            if hasattr(a, "data_ptr"):
+                return a.to(**f64).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), **f64)
+
+        self.c_quantum = None
+        if q is None:
+            return
+        self.q_psi2 = dev64(q.psi2)
+        self.q_phik = dev64(q.phi_k)
+        E = np.ascontiguousarray(q.E_i, dtype=np.float64)
+        self.q_E = (ctypes.c_double * E.size)(*E.tolist())
+        reg = getattr(q, "region", None)
+        if reg is None:
+            self.q_region = None
+        elif hasattr(reg, "data_ptr"):
+            self.q_region = reg.to(dtype=torch.uint8, device=self.device).contiguous()
+        else:
+            self.q_region = torch.as_tensor(np.ascontiguousarray(reg, dtype=np.uint8), device=self.device)
+        self.c_quantum = CQuantum(int(E.size), int(q.confinement), self.q_psi2.data_ptr(),
+                                  self.q_phik.data_ptr(), self.q_E, float(q.m_t),
+                                  self.q_region.data_ptr() if self.q_region is not None else None)
+
+    def with_quantum(self, q):
+        """The same problem (its device arrays shared, not copied) with the
+        electrons of the quantum region taken from the states q."""
+        import copy
+        o = copy.copy(self)
+        o._set_quantum(q)
+        return o
 
     def c(self):
         return CProblem(self.nx, self.ny, self.nz, self.x.data_ptr(), self.y.data_ptr(),

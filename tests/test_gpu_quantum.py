@@ -124,6 +124,25 @@ def test_mixed_precision_predictor(solved):
     assert rel_max(phi32.cpu().numpy(), phi64.cpu().numpy()) < 1e-6
 
 
+def test_states_from_device_tensors(solved):
+    """Problem.with_quantum on a problem without states, given the states as
+    device tensors (as a predictor-corrector loop holds them), solves
+    exactly as a problem staged from host arrays."""
+    dev, po, res = solved("3d_region")
+    q = dev.quantum
+    base = qe.Problem(synth.with_quantum(dev, None))
+    qt = synth.QuantumStates(psi2=dev_tensor(q.psi2), phi_k=dev_tensor(q.phi_k), E_i=q.E_i,
+                             confinement=q.confinement, m_t=q.m_t,
+                             region=dev_tensor(np.asarray(q.region, np.uint8)))
+    Pt = base.with_quantum(qt)
+    assert base.c_quantum is None and Pt.eps_r is base.eps_r
+    opts = qe.qe_default_options(newton_atol=1e-10)
+    phi_t, _, _ = qe.qe_solve(Pt, opts=opts)
+    phi_h, _, _ = qe.qe_solve(qe.Problem(dev), opts=opts)
+    assert torch.equal(phi_t, phi_h)
+    assert rel_max(phi_t.cpu().numpy(), res.phi) < 1e-9
+
+
 def test_states_validated_and_unsupported_paths_rejected():
     dev = pc_device(2)
     dev.quantum.psi2 = dev.quantum.psi2.copy()
