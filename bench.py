@@ -25,10 +25,12 @@ METRIC = "GDOF/s of nonlinear-Poisson J·v; solves/s at ‖F‖<1e-8; adjoint/fo
 
 def jv_bytes(dev, val_bytes, n_coef):
     """Algorithmic bytes of one launch of the CG loop's J.v kernel: per node
-    read z, y, p and write y, p (y = J z + beta y, p = z + beta p); per
+    read z, y, p and write y, p (y = J z + beta y, p = z + beta p) and, in
+    FP64, read and write x (the previous iteration's x += alpha p); per
     element read the permittivity and the coefficient flag; the 8 Gauss-point
     coefficients of the n_coef elements where they are not all exactly zero."""
-    return dev.n_nodes * 5 * val_bytes + dev.n_elems * (val_bytes + 1) + n_coef * 8 * val_bytes
+    per_node = 7 if val_bytes == 8 else 5
+    return dev.n_nodes * per_node * val_bytes + dev.n_elems * (val_bytes + 1) + n_coef * 8 * val_bytes
 
 
 def kernel_source_hash():

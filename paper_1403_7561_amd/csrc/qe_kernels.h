@@ -74,13 +74,17 @@ void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const dou
 void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const float* eps, const unsigned int* cbits,
                       const float* cq, const uint8_t* mask, const float* v, float* y, int identity_rows);
 // First kernel of CG iteration k: stopping test, beta, y = J z + beta y,
-// p = z + beta p, p^T y partials.
+// p = z + beta p, in FP64 the previous iteration's x += alpha p (x is not
+// touched in FP32), p^T y partials.
 void launch_cg_jv64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const double* eps_t,
-                    const unsigned int* cbits, const double* cq, const double* z, double* y, double* p, PcgCtx* ctx, CgProgress* prog,
-                    const double* part_rz, double* part_py);
+                    const unsigned int* cbits, const double* cq, const double* z, double* y, double* p, double* x,
+                    PcgCtx* ctx, CgProgress* prog, const double* part_rz, double* part_py);
 void launch_cg_jv32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const float* eps_t,
-                    const unsigned int* cbits, const float* cq, const float* z, float* y, float* p, PcgCtx* ctx, CgProgress* prog,
-                    const double* part_rz, double* part_py);
+                    const unsigned int* cbits, const float* cq, const float* z, float* y, float* p, float* x,
+                    PcgCtx* ctx, CgProgress* prog, const double* part_rz, double* part_py);
+// After an FP64 CG loop: the last iteration's x += alpha p (none after a
+// breakdown).
+void launch_cg_finish_x64(hipStream_t s, int nblocks, long N, const PcgCtx* ctx, const double* p, double* x);
 // Tile-major permittivity copy for the wave-tiled J.v (see tile_slot).
 void launch_stage_eps64(hipStream_t s, int nblocks, const Geom& g, const double* eps, double* eps_t, long nslots);
 void launch_stage_eps32(hipStream_t s, int nblocks, const Geom& g, const double* eps, float* eps_t, long nslots);

@@ -130,16 +130,18 @@ __device__ __forceinline__ void post_progress(CgProgress* prog, int iters, int d
 // stops the solve on convergence / non-finite values / the iteration limit
 // (block 0 records the decision; every block takes the same one).  Then
 // beta = rz_k / rz_{k-1} and, on the wave tiles, y = J z + beta y,
-// p = z + beta p (jv_tile_cg); one p^T y partial per block.  rz_k goes to
-// ctx->rzs[k & 1] and rz_{k-1} is read from the other slot.
+// p = z + beta p and, in FP64, the previous iteration's x += alpha p
+// (jv_tile_cg); one p^T y partial per block.  rz_k goes to ctx->rzs[k & 1]
+// and rz_{k-1} is read from the other slot.  A stopping kernel stores
+// nothing, so the last step x += alpha p is left to k_cg_finish_x.
 #ifndef QE_CG_MIN_WAVES
 #define QE_CG_MIN_WAVES 3
 #endif
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_CG_MIN_WAVES, 8))) void k_cg_jv(
     Geom g, WaveMap wm, const T* __restrict__ eps, const unsigned int* __restrict__ cbits,
-    const T* __restrict__ cq, const T* __restrict__ z, T* __restrict__ y, T* __restrict__ p, int k,
-    PcgCtx* __restrict__ ctx, CgProgress* __restrict__ prog, const double* __restrict__ part_rz, int n_rz,
+    const T* __restrict__ cq, const T* __restrict__ z, T* __restrict__ y, T* __restrict__ p, T* __restrict__ x,
+    int k, PcgCtx* __restrict__ ctx, CgProgress* __restrict__ prog, const double* __restrict__ part_rz, int n_rz,
     double* __restrict__ part_py) {
   if (ctx->done) return;
   __shared__ double sred[4];
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_CG_MIN_W
     const double rzprev = ctx->rzs[(k + 1) & 1];
     const bool bad = !isfinite(RZ), conv = !bad && RZ <= ctx->tol2, maxed = it >= ctx->maxit;
     const bool first = it == 0;
-    const double b = uniform(first ? 0.0 : RZ / rzprev);
+    const double b = uniform(first ? 0.0 : RZ / rzprev), al = first ? 0.0 : ctx->alpha;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       ctx->rzs[k & 1] = RZ;
       if (bad) {
@@ -195,10 +197,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_CG_MIN_W
     }
     stop_status = bad ? PCG_NONFINITE : conv ? PCG_CONVERGED : PCG_MAXIT;
     stop_iters = it;
-    return {!(bad || conv || maxed), (T)b, first};
+    return {!(bad || conv || maxed), (T)b, first, (T)al};
   };
   double dot = 0.0;
-  if (!jv_tile_cg<T>(g, w, wm.kz, eps, cb, cq, z, y, p, dot, decide)) {  // uniform
+  if (!jv_tile_cg<T>(g, w, wm.kz, eps, cb, cq, z, y, p, x, dot, decide)) {  // uniform
     // posted after the sweep's code, so no store the sweep's loads must be
     // ordered against precedes them
     if (prog && blockIdx.x == 0 && threadIdx.x == 0) post_progress(prog, stop_iters, 1, stop_status);
@@ -749,8 +751,8 @@ __global__ __launch_bounds__(kVecThreads) void k_pcg_init_fin(PcgCtx* ctx, const
 }
 
 // CG iteration k, second kernel: alpha = rz_k / p^T y (re-adding the
-// partials of k_cg_jv); x += alpha p; r -= alpha y; z = D^-1 r; partials of
-// r^T z.  Each thread first issues the loads of its first chunk, then re-adds
+// partials of k_cg_jv); r -= alpha y; z = D^-1 r; partials of r^T z; in FP32
+// also x += alpha p (in FP64 the next k_cg_jv takes that step).  Each thread first issues the loads of its first chunk, then re-adds
 // the partials while they are in flight; later chunks are loaded one ahead.
 // A launch after the solve has stopped returns at once.  Block 0 counts the
 // iteration.
@@ -773,11 +775,12 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update(long N, int k, T* __r
   for (int j = 0; j < 8; ++j) py_part[j] = part_py[min((int)threadIdx.x + j * NT, n_py - 1)];
   const long nc = (N + 3) / 4, stride = (long)gridDim.x * NT;
   long c = (long)blockIdx.x * NT + threadIdx.x;
+  constexpr bool kX = !cg_jv_steps_x<T>();
   Quad<T> qx, qr, qp, qy, qd;
   if (c < nc) {
-    qx = ld4(x, c, N);
+    if constexpr (kX) qx = ld4(x, c, N);
     qr = ld4(r, c, N);
-    qp = ld4(p, c, N);
+    if constexpr (kX) qp = ld4(p, c, N);
     qy = ld4(y, c, N);
     qd = ld4(invdiag, c, N);
   }
@@ -813,25 +816,38 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update(long N, int k, T* __r
     Quad<T> qz;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      qx.v[j] += alpha * qp.v[j];
+      if constexpr (kX) qx.v[j] += alpha * qp.v[j];
       qr.v[j] -= alpha * qy.v[j];
       qz.v[j] = qd.v[j] * qr.v[j];
       rz += (double)qr.v[j] * (double)qz.v[j];
     }
-    st4(x, c, N, qx);
+    if constexpr (kX) st4(x, c, N, qx);
     st4(r, c, N, qr);
     st4(z, c, N, qz);
     c += stride;
     if (c < nc) {
-      qx = ld4(x, c, N);
+      if constexpr (kX) qx = ld4(x, c, N);
       qr = ld4(r, c, N);
-      qp = ld4(p, c, N);
+      if constexpr (kX) qp = ld4(p, c, N);
       qy = ld4(y, c, N);
       qd = ld4(invdiag, c, N);
     }
   }
   const double s1 = block_sum(rz, sred);
   if (threadIdx.x == 0) part_rz[blockIdx.x] = s1;
+}
+
+// After an FP64 CG loop: the step x += alpha p of the last iteration whose
+// alpha was formed, which no k_cg_jv took (the one after it stopped the
+// solve, or none ran).  A breakdown forms no alpha: its step was taken.
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_cg_finish_x(long N, const PcgCtx* __restrict__ ctx,
+                                                            const T* __restrict__ p, T* __restrict__ x) {
+  static_assert(cg_jv_steps_x<T>(), "only the sweep that takes the step leaves one to finish");
+  if (ctx->status == PCG_BREAKDOWN || ctx->iters < 1) return;
+  const T alpha = (T)ctx->alpha;
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x)
+    x[n] += alpha * p[n];
 }
 
 // One block: sum of n partials (fixed order) into *out.
@@ -950,16 +966,16 @@ void launch_jv_wave32(hipStream_t s, const Geom& g, const WaveMap& wm, const flo
 }
 
 void launch_cg_jv64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const double* eps_t,
-                    const unsigned int* cbits, const double* cq, const double* z, double* y, double* p, PcgCtx* ctx,
-                    CgProgress* prog, const double* part_rz, double* part_py) {
-  QE_LAUNCH(k_cg_jv<double>, wm.nblocks, 256, s, g, wm, eps_t, cbits, cq, z, y, p, k, ctx, prog, part_rz, cgblocks,
+                    const unsigned int* cbits, const double* cq, const double* z, double* y, double* p, double* x,
+                    PcgCtx* ctx, CgProgress* prog, const double* part_rz, double* part_py) {
+  QE_LAUNCH(k_cg_jv<double>, wm.nblocks, 256, s, g, wm, eps_t, cbits, cq, z, y, p, x, k, ctx, prog, part_rz, cgblocks,
             part_py);
 }
 
 void launch_cg_jv32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgblocks, int k, const float* eps_t,
-                    const unsigned int* cbits, const float* cq, const float* z, float* y, float* p, PcgCtx* ctx,
-                    CgProgress* prog, const double* part_rz, double* part_py) {
-  QE_LAUNCH(k_cg_jv<float>, wm.nblocks, 256, s, g, wm, eps_t, cbits, cq, z, y, p, k, ctx, prog, part_rz, cgblocks,
+                    const unsigned int* cbits, const float* cq, const float* z, float* y, float* p, float* x,
+                    PcgCtx* ctx, CgProgress* prog, const double* part_rz, double* part_py) {
+  QE_LAUNCH(k_cg_jv<float>, wm.nblocks, 256, s, g, wm, eps_t, cbits, cq, z, y, p, x, k, ctx, prog, part_rz, cgblocks,
             part_py);
 }
 
@@ -1002,7 +1018,7 @@ void launch_pcg_iter64(hipStream_t s, const Geom& g, const WaveMap& wm, int cgbl
                        const double* eps_t, const unsigned int* cbits, const double* cq, const double* invdiag, double* x,
                        double* r, double* z, double* p, double* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
                        double* part_rz, const SheetSet* S, const int4* items, const uint8_t* mask) {
-  launch_cg_jv64(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, ctx, prog, part_rz, part_py);
+  launch_cg_jv64(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, x, ctx, prog, part_rz, part_py);
   int n_py = wm.nblocks;
   if (S && S->any_robin) {
     launch_sheet_jv64(s, *S, items, mask, z, y, p, ctx, part_py + wm.nblocks);
@@ -1016,7 +1032,7 @@ void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgbl
                        const float* eps_t, const unsigned int* cbits, const float* cq, const float* invdiag, float* x,
                        float* r, float* z, float* p, float* y, PcgCtx* ctx, CgProgress* prog, double* part_py,
                        double* part_rz, const SheetSet* S, const int4* items, const uint8_t* mask) {
-  launch_cg_jv32(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, ctx, prog, part_rz, part_py);
+  launch_cg_jv32(s, g, wm, cgblocks, k, eps_t, cbits, cq, z, y, p, x, ctx, prog, part_rz, part_py);
   int n_py = wm.nblocks;
   if (S && S->any_robin) {
     launch_sheet_jv32(s, *S, items, mask, z, y, p, ctx, part_py + wm.nblocks);
@@ -1024,6 +1040,10 @@ void launch_pcg_iter32(hipStream_t s, const Geom& g, const WaveMap& wm, int cgbl
   }
   QE_LAUNCH(k_cg_update<float>, cgblocks, kVecThreads, s, N, k, x, r, z, p, y, invdiag, ctx, prog, part_py, n_py,
             part_rz);
+}
+
+void launch_cg_finish_x64(hipStream_t s, int nblocks, long N, const PcgCtx* ctx, const double* p, double* x) {
+  QE_LAUNCH(k_cg_finish_x<double>, nblocks, kVecThreads, s, N, ctx, p, x);
 }
 
 }  // namespace qe

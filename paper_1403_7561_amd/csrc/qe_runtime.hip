@@ -555,6 +555,14 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
     if (!ring[e]) QE_HIP(hipEventCreateWithFlags(&ring[e], hipEventDisableTiming));
   const int ahead = std::min(std::max(check_every > 0 ? check_every : kEv + 4, kEv + 1), kEv * (kRing - 1));
   int queued = 0, finished = 0, head = 0, tail = 0;  // events [head, tail) pending, in ring order
+  // FP64: the last x += alpha p, queued after every launch of the loop
+  auto finish = [&]() -> qe_status {
+    if (!mixed) {
+      launch_cg_finish_x64(s, vblocks, N, dctx, f64(lay.p), f64(lay.x));
+      QE_HIP(hipGetLastError());
+    }
+    return QE_OK;
+  };
   for (;;) {
     while (queued <= maxit && queued < finished + ahead) {
       queue_iter(queued++);
@@ -568,7 +576,7 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
     if (wd & 1) {
       *pcg_status = (wd >> 1) & 7;
       *iters = (wd >> 4) - 1;
-      return QE_OK;
+      return finish();
     }
     if (head < tail) {
       const hipError_t e = hipEventQuery(ring[head % kRing]);
@@ -588,7 +596,7 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
     if (h.done || queued > maxit) {
       *pcg_status = h.done ? h.status : PCG_MAXIT;
       *iters = h.iters;
-      return QE_OK;
+      return finish();
     }
   }
 }
@@ -860,6 +868,7 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
   hc.iters = 1;
   hc.rzs[1] = hc.rzs[0];
   hc.tol2 = 0.0;
+  hc.alpha = 0.0;   // the fused solution step leaves x = 0
   QE_HIP(hipMemcpyAsync(dctx, &hc, sizeof(PcgCtx), hipMemcpyHostToDevice, cx.s));
   QE_HIP(hipStreamSynchronize(cx.s));
   hipEvent_t e0, e1;
@@ -868,11 +877,13 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
   auto once = [&]() {
     if (mixed)
       launch_cg_jv32(cx.s, cx.g, cx.wm, cgb, 0, cx.f32(cx.lay.eps32), cx.u32(cx.lay.cbits), cx.f32(cx.lay.c32),
-                     cx.f32(cx.lay.z32), cx.f32(cx.lay.y32), cx.f32(cx.lay.p32), dctx, mirror().prog_dev,
+                     cx.f32(cx.lay.z32), cx.f32(cx.lay.y32), cx.f32(cx.lay.p32), cx.f32(cx.lay.x32), dctx,
+                     mirror().prog_dev,
                      cx.f64(cx.lay.partial2), cx.f64(cx.lay.partial));
     else
       launch_cg_jv64(cx.s, cx.g, cx.wm, cgb, 0, cx.f64(cx.lay.eps_t), cx.u32(cx.lay.cbits), cx.f64(cx.lay.c),
-                     cx.f64(cx.lay.z), cx.f64(cx.lay.y), cx.f64(cx.lay.p), dctx, mirror().prog_dev,
+                     cx.f64(cx.lay.z), cx.f64(cx.lay.y), cx.f64(cx.lay.p), cx.f64(cx.lay.x), dctx,
+                     mirror().prog_dev,
                      cx.f64(cx.lay.partial2), cx.f64(cx.lay.partial));
   };
   once();  // warm-up

@@ -262,11 +262,21 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
 // What the CG sweep learns once its first loads are in flight: whether to go
 // on (the solve has not stopped), beta, and whether this is the first
 // iteration (p = z, y = J z).
+// Whether the CG loop's first kernel also takes the previous iteration's
+// solution step x += alpha p (it reads p anyway): in FP64 this saves the
+// second kernel a read of p and a read and write of x; the FP32 sweep
+// measured slower with it, so there the second kernel keeps the step.
+template <typename T>
+constexpr bool cg_jv_steps_x() {
+  return sizeof(T) == 8;
+}
+
 template <typename T>
 struct JvGo {
   bool go;
   T beta;
   bool first;
+  T alpha;   // the previous iteration's step length (not read on the first)
 };
 
 // ---------------------------------------------------------------------------
@@ -365,18 +375,20 @@ __device__ __forceinline__ void haar2(const T f[4], T u[4]) {
 // What one layer step needs from memory, loaded one step ahead: the top face
 // of the element layer (raw z values at its corners), the element's
 // permittivity and Gauss-point coefficients and, at the lane's owned node of
-// that layer, y and p.
+// that layer, y, p and x.
 template <typename T>
 struct CgStage {
   T f[4];
   T e;
-  T yv, pv;
+  T yv, pv, xv;
   T c[8];
 };
 
 // CG sweep on one wave tile: v = z (zero on Dirichlet nodes); on owned rows
 // y = J z + beta y and p = z + beta p (first: y = J z, p = z), so y = J p by
-// recurrence; dot += p^T y over owned nodes.  pre() is called by every wave
+// recurrence, and (when cg_jv_steps_x<T>()) the previous iteration's
+// solution step x += alpha p with the p read before its update (not on the
+// first); dot += p^T y over owned nodes.  pre() is called by every wave
 // once the first loads are issued (it may synchronise the block); false: the
 // solve has stopped and nothing was stored.  The element operator is
 // jv_element's, with the partial sums grouped per face.  The bottom face of each element layer is kept in
@@ -390,7 +402,8 @@ struct CgStage {
 template <typename T, typename Pre>
 __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int kz, const T* __restrict__ eps_t,
                                            unsigned int cbits, const T* __restrict__ cq, const T* __restrict__ z,
-                                           T* __restrict__ y, T* __restrict__ p, double& dot, Pre pre) {
+                                           T* __restrict__ y, T* __restrict__ p, T* __restrict__ x, double& dot,
+                                           Pre pre) {
   using IO = BufIO<T>;
   constexpr unsigned int B = sizeof(T);
   const long sxy = w.sxy, sl = w.slot_layer;
@@ -401,6 +414,7 @@ __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int
   const __amdgpu_buffer_rsrc_t rz = buf_res(z + sxy * Pb, (long)(g.nz - Pb) * sxy * B);
   const __amdgpu_buffer_rsrc_t ry = buf_res(y + sxy * Pb, (long)(g.nz - Pb) * sxy * B);
   const __amdgpu_buffer_rsrc_t rp = buf_res(p + sxy * Pb, (long)(g.nz - Pb) * sxy * B);
+  const __amdgpu_buffer_rsrc_t rx = buf_res(x + sxy * Pb, (long)(g.nz - Pb) * sxy * B);
   const __amdgpu_buffer_rsrc_t re = buf_res(eps_t + sl * Pb, (long)(g.nz - 1 - Pb) * sl * B);
   const __amdgpu_buffer_rsrc_t rc = buf_res(cq + 8 * sl * Pb, (long)(g.nz - 1 - Pb) * sl * 8 * B);
   // per-lane byte offsets within a layer; corner 3 of the face is the owned
@@ -435,7 +449,7 @@ __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int
 #pragma unroll
   for (int k = 0; k < 4; ++k) A.f[k] = IO::ld(rz, o_f[k], s_node(w.Lbeg + 1));
   A.e = IO::ld(re, o_e, s_elem(w.Lbeg));
-  A.yv = A.pv = T(0);   // node layer Lbeg is never owned
+  A.yv = A.pv = A.xv = T(0);   // node layer Lbeg is never owned
   // the flag word is first used here, after the loads above are issued (an
   // idle wave's word is not its own: cleared)
   __builtin_amdgcn_sched_barrier(0);
@@ -445,7 +459,7 @@ __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int
   if (!go.go) return false;
   double ahx, ahy, axy;
   w.weights(ahx, ahy, axy);
-  const T beta = go.beta;
+  const T beta = go.beta, alpha = go.alpha;
   const bool rec_old = !go.first;
   // retire the prologue's loads before the loop (see jv_tile)
 #pragma unroll
@@ -479,6 +493,7 @@ __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int
       nxt.e = IO::ld(re, o_e, s_elem(L + 1));
       nxt.yv = IO::ld(ry, o_n, s_node(L + 1));
       nxt.pv = IO::ld(rp, o_n, s_node(L + 1));
+      if constexpr (cg_jv_steps_x<T>()) nxt.xv = IO::ld(rx, o_n, s_node(L + 1));
       __builtin_amdgcn_sched_barrier(0);
     }
     // element layer L: Haar coefficients, diagonal stiffness, mass term
@@ -537,6 +552,7 @@ __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int
     const bool st = L >= w.k0 && L <= w.Lend;
     IO::st(ry, val, st ? o_n : kBufOob, s_node(L));
     IO::st(rp, pv, st ? o_n : kBufOob, s_node(L));
+    if constexpr (cg_jv_steps_x<T>()) IO::st(rx, cur.xv + alpha * cur.pv, (st && rec_old) ? o_n : kBufOob, s_node(L));
     if (st && own_lane) dot += (double)pv * (double)val;
 #pragma unroll
     for (int k = 0; k < 4; ++k) Tb[k] = Tt[k];
