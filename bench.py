@@ -290,7 +290,7 @@ def main():
                       "ms_fp64": ms64, "ms_fp32": ms32},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "k_cg_jv<double> (FP64 J.v of the CG loop with the direction update)",
+                     "kernel": "k_cg_jv<double> (FP64 J.v of the CG loop with the direction update and the solution step)",
                      "bytes_per_launch": b64, "ms_per_launch": ms64,
                      "coef_elems": ncoef, "elems": dev.n_elems},
         "roofline_fp32": {"achieved": b32 / (ms32 * 1e-3) / 1e9, "bytes_per_launch": b32},
