@@ -302,3 +302,32 @@ def test_cg_product_is_the_exact_jacobian(stat, delta, ratio):
     assert rep["res0"] == pytest.approx(f0, rel=1e-6)
     assert rep["res_final"] < ratio * rep["res0"]
     assert rel_max(phi.cpu().numpy(), res.phi) < delta
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 25])
+def test_cg_iterate_at_the_iteration_limit(k):
+    """A Newton step whose CG stops at its iteration limit k takes the k-th
+    Jacobi-PCG iterate from x = 0, the last update included (the FP64 loop
+    leaves that update to a kernel queued after it): the oracle's Jacobian
+    and a library CG run for exactly k iterations give the same vector."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    dev = gs.ragged_device(stat="fd")
+    po, res = solver.solve(dev, atol=1e-11)
+    rng = np.random.default_rng(11)
+    free = po.free
+    phi0 = res.phi.copy()
+    phi0[free] += 1e-3 * rng.standard_normal(int(free.sum()))
+    J = po.jacobian_free(phi0)
+    b = -po.residual(phi0)[free]
+    xo, info = spla.cg(J, b, rtol=0.0, atol=0.0, maxiter=k, M=sp.diags(1.0 / J.diagonal()))
+    assert info == k
+    P = qe.Problem(dev)
+    opts = qe.qe_default_options(newton_atol=1e-30, newton_maxit=1, krylov_rtol_max=1e-12, krylov_maxit=k,
+                                 init_guess=1)
+    phi, _, rep = qe.qe_solve(P, opts=opts, phi=dev_tensor(phi0), check=False)
+    print(k, rep)
+    assert rep["newton_iters"] == 1 and rep["krylov_iters"] == k
+    x = (phi.cpu().numpy() - phi0)[free] / 0.5 ** rep["ls_halvings"]
+    print(k, "rel diff", rel_max(x, xo))
+    assert rel_max(x, xo) < 1e-10
