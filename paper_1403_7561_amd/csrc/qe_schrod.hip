@@ -497,23 +497,35 @@ __global__ __launch_bounds__(256) void k_sch_gram(long N, int k, PCols pc, const
 }
 
 // G[m * len + i] = sum over the n blocks of part[(b * 2 + m) * len + i], for
-// the two matrices m.
-__global__ __launch_bounds__(kVecThreads) void k_sch_sum_parts2(const double* __restrict__ part, int n, int len,
-                                                               double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 2 * len) return;
-  const int m = i / len, e = i % len;
+// the two matrices m.  A block takes 64 consecutive entries of the two
+// matrices; its wave w adds the partials of blocks w, w + 16, ... in order and
+// the 16 wave sums are added in wave order: a fixed order, with 16 times the
+// loads in flight of one thread per entry.
+constexpr int kSumWaves = 16;
+__global__ __launch_bounds__(64 * kSumWaves) void k_sch_sum_parts2(const double* __restrict__ part, int n, int len,
+                                                                  double* __restrict__ out) {
+  __shared__ double acc[kSumWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const bool ok = i < 2 * len;
+  const int m = ok ? i / len : 0, e = ok ? i % len : 0;
   double a = 0.0;
-  int b = 0;
-  for (; b + 8 <= n; b += 8) {   // eight loads in flight, added in block order
+  int b = w;
+  for (; b + 7 * kSumWaves < n; b += 8 * kSumWaves) {   // eight loads in flight
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = part[((long)(b + u) * 2 + m) * len + e];
+    for (int u = 0; u < 8; ++u) v[u] = part[((long)(b + u * kSumWaves) * 2 + m) * len + e];
 #pragma unroll
     for (int u = 0; u < 8; ++u) a += v[u];
   }
-  for (; b < n; ++b) a += part[((long)b * 2 + m) * len + e];
-  out[i] = a;
+  for (; b < n; b += kSumWaves) a += part[((long)b * 2 + m) * len + e];
+  acc[w][lane] = a;
+  __syncthreads();
+  if (w == 0 && ok) {
+    double t = acc[0][lane];
+    for (int j = 1; j < kSumWaves; ++j) t += acc[j][lane];
+    out[i] = t;
+  }
 }
 
 __global__ __launch_bounds__(kVecThreads) void k_sch_square(long n, const double* __restrict__ a,
@@ -796,8 +808,8 @@ static qe_status sch_core(const qe_problem* p, const double* inv_mass, const dou
     double* G = f64(L.G);
     hipLaunchKernelGGL(k_sch_gram, dim3(kGramBlocks), dim3(256), 0, s, N, k, pc, Z, HZ, MZ, f64(L.gpart));
     // G (both matrices, column-major, one after the other) = fixed-order sum of the block partials
-    hipLaunchKernelGGL(k_sch_sum_parts2, dim3((2 * k * k + kVecThreads - 1) / kVecThreads), dim3(kVecThreads), 0, s,
-                       f64(L.gpart), kGramBlocks, k * k, G);
+    hipLaunchKernelGGL(k_sch_sum_parts2, dim3((2 * k * k + 63) / 64), dim3(64 * kSumWaves), 0, s, f64(L.gpart),
+                       kGramBlocks, k * k, G);
     QE_TRY(ck(hipGetLastError(), "Gram launch"));
     QE_TRY(ck(hipMemcpyAsync(hG.data(), G, 2 * (size_t)k * k * 8, hipMemcpyDeviceToHost, s), "copy"));
     QE_TRY(ck(hipStreamSynchronize(s), "sync"));
