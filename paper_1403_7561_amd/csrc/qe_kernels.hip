@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QE_CG_MIN_W
 }
 
 template <typename TD, bool kQ>
-__global__ __launch_bounds__(256) void k_residual_wave(
+__device__ __forceinline__ void residual_wave(
     Geom g, WaveMap wm, Charge ch, const double* __restrict__ eps, const uint8_t* __restrict__ semi,
     const Doping dop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
     const TD* __restrict__ delta, double lam, const double* __restrict__ fsheet,
@@ -234,6 +234,35 @@ __global__ __launch_bounds__(256) void k_residual_wave(
   if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = sred[0] + sred[1] + sred[2] + sred[3];
+}
+
+// The statistics residual runs at most 168 VGPRs (3 waves per SIMD) and the
+// residual with eigenstates at most 256 (2 waves): the fastest caps measured
+// at 129x129x65 (without one they take 190 and 257, 2 and 1 waves).
+template <typename TD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_residual_wave(
+    Geom g, WaveMap wm, Charge ch, const double* __restrict__ eps, const uint8_t* __restrict__ semi,
+    const Doping dop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
+    const TD* __restrict__ delta, double lam, const double* __restrict__ fsheet,
+    const double* __restrict__ fdiag, double* __restrict__ F, double* __restrict__ invdiag,
+    double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
+    uint8_t* __restrict__ cflag, unsigned int* __restrict__ cbits, float* __restrict__ invdiag32,
+    double* __restrict__ part, Quantum qm) {
+  residual_wave<TD, false>(g, wm, ch, eps, semi, dop, mask, phi, delta, lam, fsheet, fdiag, F, invdiag, diag_out, cq,
+                          cq32, cflag, cbits, invdiag32, part, qm);
+}
+
+template <typename TD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_residual_wave_q(
+    Geom g, WaveMap wm, Charge ch, const double* __restrict__ eps, const uint8_t* __restrict__ semi,
+    const Doping dop, const uint8_t* __restrict__ mask, const double* __restrict__ phi,
+    const TD* __restrict__ delta, double lam, const double* __restrict__ fsheet,
+    const double* __restrict__ fdiag, double* __restrict__ F, double* __restrict__ invdiag,
+    double* __restrict__ diag_out, double* __restrict__ cq, float* __restrict__ cq32,
+    uint8_t* __restrict__ cflag, unsigned int* __restrict__ cbits, float* __restrict__ invdiag32,
+    double* __restrict__ part, Quantum qm) {
+  residual_wave<TD, true>(g, wm, ch, eps, semi, dop, mask, phi, delta, lam, fsheet, fdiag, F, invdiag, diag_out, cq,
+                          cq32, cflag, cbits, invdiag32, part, qm);
 }
 
 // ---------------------------------------------------------------------------
@@ -941,16 +970,16 @@ void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const
                           const Quantum& qm) {
   const bool q = qm.n > 0;
   if (delta32 && q)
-    QE_LAUNCH((k_residual_wave<float, true>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam,
+    QE_LAUNCH((k_residual_wave_q<float>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam,
               fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
   else if (delta32)
-    QE_LAUNCH((k_residual_wave<float, false>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam,
+    QE_LAUNCH((k_residual_wave<float>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam,
               fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
   else if (q)
-    QE_LAUNCH((k_residual_wave<double, true>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam,
+    QE_LAUNCH((k_residual_wave_q<double>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam,
               fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
   else
-    QE_LAUNCH((k_residual_wave<double, false>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam,
+    QE_LAUNCH((k_residual_wave<double>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam,
               fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
   QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, wm.nblocks, norm2);
 }
