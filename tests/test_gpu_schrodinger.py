@@ -109,6 +109,22 @@ def test_gate_stack_dot_states():
     assert np.all(np.diff(E) >= 0)
 
 
+def test_unconverged_solve_still_writes_the_states():
+    """Stopped by maxit on the quantum region's box, the solve reports it and
+    still returns its current block on the whole mesh: zeros on every fixed
+    node (those outside the box included), psi2 = psi^2, maxit iterations."""
+    dev, phi, inv_mass, v0, fixed = stack_dot()
+    P = qe.Problem(dev)
+    with pytest.raises(qe.QeError) as ei:
+        qe.qe_schrodinger_solve(P, inv_mass, v0, phi, 4, fixed=fixed, tol=1e-12, maxit=3)
+    assert qe.STATUS_NAMES[ei.value.status] == "NOT_CONVERGED"
+    E, psi, psi2, it = qe.qe_schrodinger_solve(P, inv_mass, v0, phi, 4, fixed=fixed, tol=1e-12, maxit=3, check=False)
+    ps = psi.cpu().numpy()
+    assert it == 3 and np.all(np.isfinite(E)) and np.all(np.isfinite(ps))
+    assert np.all(ps[:, np.asarray(fixed, bool)] == 0.0) and np.abs(ps).max() > 0.0
+    assert np.array_equal(psi2.cpu().numpy(), ps * ps)
+
+
 def test_predictor_corrector_loop_closes():
     """The S-P loop of the predictor-corrector method (the four steps listed
     in Sec. II.C) on the GPU: semiclassical start, then alternately the
