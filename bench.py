@@ -347,6 +347,20 @@ def main():
             ph5, _, r5 = qe.qe_solve(P5, opts=o5, ws=ws5, want_density=False)
             torch.cuda.synchronize()
             res[prec] = (time.perf_counter() - t0, ph5.clone(), r5)
+        # the CG loop's kernel at the FP64 solution: vectors and coefficients
+        # exceed the 256 MB Infinity Cache here, so this rate is HBM-bound
+        v5 = torch.randn(P5.N, dtype=torch.float64, device="cuda")
+        ms5_64, nc5_64 = qe.qe_time_jv(P5, res["fp64"][1], v5, "fp64", args.jv_reps, ws=ws5)
+        ms5_32, nc5_32 = qe.qe_time_jv(P5, res["fp64"][1], v5, "mixed", args.jv_reps, ws=ws5)
+        b5_64, b5_32 = jv_bytes(dev5, 8, nc5_64), jv_bytes(dev5, 4, nc5_32)
+        out["roofline_c5"] = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "achieved": b5_64 / (ms5_64 * 1e-3) / 1e9,
+                              "frac": b5_64 / (ms5_64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "bytes_per_launch": b5_64, "ms_per_launch": ms5_64, "coef_elems": nc5_64,
+                              "fp32": {"achieved": b5_32 / (ms5_32 * 1e-3) / 1e9,
+                                       "frac": b5_32 / (ms5_32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                       "bytes_per_launch": b5_32, "ms_per_launch": ms5_32},
+                              "gdof_s": {"fp64": P5.N / (ms5_64 * 1e-3) / 1e9, "fp32": P5.N / (ms5_32 * 1e-3) / 1e9}}
         d = (res["mixed"][1] - res["fp64"][1]).abs().max().item() / res["fp64"][1].abs().max().item()
         out["mixed_c5"] = {"fp64_s": res["fp64"][0], "mixed_s": res["mixed"][0],
                            "speedup": res["fp64"][0] / res["mixed"][0],
