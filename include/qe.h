@@ -16,8 +16,8 @@
  * Dirichlet nodes (Eq. ContOnIns with a mid-gap work function, so a gate node
  * carries its applied voltage; Ohmic contacts take qe_ohmic_potential);
  * every other outer face is the default zero-flux Neumann boundary (Sec.
- * II.A.5).
- * Newton's method with the exact Jacobian (Sec. II.A.4, II.C) is globalised
+ * II.A.4).
+ * Newton's method with the exact Jacobian (Sec. II.A.3, II.C) is globalised
  * by backtracking; the linear systems are solved by Jacobi-preconditioned
  * conjugate gradients, all on the GPU.
  *
@@ -88,7 +88,7 @@ typedef enum {
 } qe_precision;
 
 /* A rectangle of mesh faces carrying a surface charge and / or a Robin
- * condition (Sec. II.A.5).  The sheet lies in the node plane
+ * condition (Sec. II.A.4).  The sheet lies in the node plane
  * x_axis = coordinate[plane] (axis 0: x, 1: y, 2: z) and covers faces a0..a1-1
  * along its first in-plane axis and b0..b1-1 along its second (axis 2: x then
  * y; axis 1: x then z; axis 0: y then z); a face is the rectangle between
@@ -99,7 +99,7 @@ typedef enum {
  *  - with robin_d > 0, the Robin term alpha int_f (phi - phi0) w_i with
  *    alpha = robin_eps / robin_d: the potential is pinned to phi0 on a plane
  *    robin_d beyond the face, through a layer of relative permittivity
- *    robin_eps (the charged-gate construction of Sec. II.A.5, d = 10 nm there).
+ *    robin_eps (the charged-gate construction of Sec. II.A.4, d = 10 nm there).
  * Both integrals are exact (bilinear traces on rectangles).  Rows of
  * Dirichlet nodes are unaffected.  Sheets may share nodes and planes. */
 typedef struct {
@@ -270,15 +270,20 @@ qe_status qe_density(const qe_problem* p, const qe_physics* ph, const double* ph
  * Q: host scalar or NULL.  dQ_ddir: host [n_dir] (per Dirichlet value).
  * dQ_deps: device [E] or NULL.  lam: device [N] or NULL (adjoint state).
  * opts: krylov_maxit and precision (must be FP64) are used; the adjoint CG
- * runs to a relative residual of 1e-12.  rep: host or NULL. */
+ * stops when the preconditioned residual norm (r^T D^-1 r)^(1/2) falls to
+ * 1e-12 of its initial value.  rep: host or NULL. */
 qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options* o,
                      const double* phi, const double* box, double* Q, double* dQ_ddir,
                      double* dQ_deps, double* lam, void* ws, size_t ws_bytes,
                      void* stream, qe_report* rep);
 
-/* Batched solve of many independent devices (a gate-voltage sweep over
- * uneven meshes) in one persistent launch: Newton, line search and CG run
- * on the device for every instance.
+/* Batched solve of many independent devices in one persistent launch: the
+ * design searches of Sec. IV run many device simulations at once (gate
+ * voltages varied as parameters, many layouts side by side, each device the
+ * nonlinear Poisson problem of Sec. II.A), which here becomes a gate-voltage
+ * sweep over uneven meshes on one GPU.  Newton, line search and CG run on
+ * the device for every instance, with the same algorithm and stopping rules
+ * as qe_solve.
  *   probs: host [n_inst] of qe_problem (device arrays inside);
  *   phi: host [n_inst] of device pointers, each [N_k]; out: solutions;
  *   boxes: host [n_boxes][6]; counts: host [n_inst][n_boxes] (may be NULL
@@ -306,7 +311,7 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
                      int32_t precision, int32_t reps, double* ms_per_apply, int64_t* n_coef_elems,
                      void* ws, size_t ws_bytes, void* stream);
 
-/* Dirichlet value of an Ohmic contact on semiconductor (Sec. II.A.5, second
+/* Dirichlet value of an Ohmic contact on semiconductor (Sec. II.A.4, second
  * case): thermal equilibrium and charge neutrality of the majority carriers
  * at the contact, in this library's convention (E_F = 0, E_C = Ec0 - phi).
  * n-type when N_D >= N_A, else p-type (densities in nm^-3, host scalars).

@@ -7,7 +7,7 @@ basis function w_i of a free node,
                        - KAPPA semi_e sum_q W_q (N_net,e - n(phi_q)) w_i(q) ] = 0
 
 with the boundary integral dropped on every non-Dirichlet face (the default
-flux-conserving Neumann condition, Sec. II.A.5) except on the faces of the
+flux-conserving Neumann condition, Sec. II.A.4) except on the faces of the
 device's sheets, which carry a surface charge and / or a Robin condition
 (``sheet_terms``).  Khat_e is the unit-
 permittivity trilinear stiffness of a box element, exact under 2x2x2 Gauss
@@ -117,7 +117,7 @@ def sheet_coords(mesh, sh):
 
 
 def sheet_terms(mesh, sheets):
-    """Face integrals of the interface and Robin conditions (Sec. II.A.5).
+    """Face integrals of the interface and Robin conditions (Sec. II.A.4).
 
     For every face f of a sheet (a rectangle of the plane x_axis = const):
 
@@ -195,7 +195,7 @@ class Problem:
         self.extra_load = extra_load
         self.Khat = m.unit_stiffness()
         self.K = m.assemble(self.eps[:, None, None] * self.Khat)
-        # interface charge and Robin faces (Sec. II.A.5)
+        # interface charge and Robin faces (Sec. II.A.4)
         self.sheets = list(getattr(dev, "sheets", None) or [])
         self.R, self.sheet_load = sheet_terms(m, self.sheets)
         self.K_lin = self.K + self.R      # the phi-linear part of F

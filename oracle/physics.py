@@ -268,7 +268,7 @@ class Statistics:
 
 
 def ohmic_potential(st, nd, na, Va=0.0, low_T_log_min=None):
-    """Dirichlet value of an Ohmic contact (Sec. II.A.5, second case):
+    """Dirichlet value of an Ohmic contact (Sec. II.A.4, second case):
     thermal equilibrium and charge neutrality at the contact, majority
     carriers only.  n-type when nd >= na, else p-type; with complete
     ionization the net doping |nd - na| sets the majority density, with
@@ -318,6 +318,10 @@ def ohmic_potential(st, nd, na, Va=0.0, low_T_log_min=None):
 
 def neutral_root(st, netdop, nd=None, na=None, lo=-3.0, hi=3.0):
     """phi with rho(phi) = 0 for a uniform material, by a bracketed root of
-    the coded space charge (a check for the closed forms above)."""
-    f = lambda p: float(st.rho(np.array([p]), netdop, nd, na)[0])
+    the coded space charge (a check for the closed forms above).  At low
+    temperature a Boltzmann density at the bracket ends exceeds the double
+    range; +inf or -inf there still gives the sign the bracket needs."""
+    def f(p):
+        with np.errstate(over="ignore"):
+            return float(st.rho(np.array([p]), netdop, nd, na)[0])
     return optimize.brentq(f, lo, hi, xtol=1e-15, rtol=4 * np.finfo(float).eps, maxiter=1000)

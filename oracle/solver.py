@@ -1,7 +1,7 @@
 """Newton solve, outputs and adjoint of the discrete nonlinear Poisson system.
 
 The paper solves the discretised weak form with Trilinos' Newton method and
-an exact (automatically differentiated) Jacobian (Sec. II.A.4 and II.C); it
+an exact (automatically differentiated) Jacobian (Sec. II.A.3 and II.C); it
 does not state the initial guess or the globalisation.  This reference uses:
 
 * initial guess: the charge-free linear problem (n = 0, doping kept) with the
@@ -9,7 +9,7 @@ does not state the initial guess or the globalisation.  This reference uses:
 * Newton steps J_ff delta = -F_f with the exact Jacobian of the coded
   residual, solved directly (SuperLU) or by Jacobi-preconditioned CG;
 * backtracking on ||F||_2: lambda = 1, halved until
-  ||F(phi + lambda delta)|| <= (1 - 1e-4 lambda) ||F(phi)||;
+  ||F(phi + lambda delta)|| is finite and <= (1 - 1e-4 lambda) ||F(phi)||;
 * stop when ||F_free||_2 <= atol.
 
 The discrete solution is unique (F is the gradient of a strictly convex
@@ -87,9 +87,13 @@ def newton(prob, phi0=None, atol=1e-10, maxit=200, ls_max=30, method="auto",
         lam = 1.0
         for h in range(ls_max + 1):
             trial = phi + lam * delta
-            Ft = prob.residual(trial)
-            nt = float(np.linalg.norm(Ft[f]))
-            if nt <= (1.0 - sufficient * lam) * nrm:
+            # a full step can put a Boltzmann exponent beyond the double range
+            # (the density is then +inf and the residual not finite): such a
+            # trial is rejected like any other that does not decrease ||F||
+            with np.errstate(over="ignore", invalid="ignore"):
+                Ft = prob.residual(trial)
+                nt = float(np.linalg.norm(Ft[f]))
+            if np.isfinite(nt) and nt <= (1.0 - sufficient * lam) * nrm:
                 break
             lam *= 0.5
             halv += 1

@@ -379,6 +379,9 @@ static qe_status launch_batch(const BatchParams& bp, const BatchConfig& cfg, int
   if (e != hipSuccess) return fail(QE_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+  // the executable graph is released only after the launch has finished
+  const hipError_t es = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = es;
   if (exec) (void)hipGraphExecDestroy(exec);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) return fail(QE_ERR_HIP, "graph launch failed: %s", hipGetErrorString(e));

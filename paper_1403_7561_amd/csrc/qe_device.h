@@ -15,6 +15,7 @@
 
 namespace qe {
 
+// Block tiles of the adjoint sweeps (k_adj_rhs, k_adj_grad).
 constexpr int kTX = 16;               // owned node columns per tile in x
 constexpr int kTY = 16;               // ... in y
 constexpr int kEX = kTX + 1;          // element columns per tile (one halo column)

@@ -1,14 +1,16 @@
 // HIP kernels (gfx950) of the Q1 nonlinear-Poisson Newton-Krylov path.
 //
-// Element sweeps (residual, J.v, adjoint) share one tiling.  A block of 256
-// threads owns a 16 x 16 column of nodes over kz node planes.  It marches up
-// the planes; at each element layer it stages the next node plane of the
-// input field in LDS (with a one-node halo), computes the (16+1) x (16+1)
-// elements that touch its nodes (the halo column is recomputed by the
-// neighbouring tile), writes each element's 8 corner contributions to LDS and
-// lets every owned node gather its 4 + 4 contributions from the elements
-// below and above it.  There are no atomics: every nodal sum is formed in a
-// fixed order, so results are bitwise reproducible.
+// The residual, J.v and CG sweeps run on wave tiles (qe_tiles.h): a wave owns
+// a 7 x 7 column of nodes, computes the 8 x 8 elements that touch them while
+// it marches up a chunk of node planes, and gathers each owned node's sums
+// across lanes, with no LDS and no block barrier.  The adjoint's two
+// element sweeps (k_adj_rhs, k_adj_grad) use block tiles instead: 256
+// threads own a 16 x 16 column of nodes, stage each node plane of the input
+// field in LDS with a one-node halo, compute the 17 x 17 elements around
+// their nodes (the halo column is recomputed by the neighbouring tile) and
+// gather the 4 + 4 corner contributions of every owned node from LDS.
+// There are no atomics in any sweep: every nodal sum is formed in a fixed
+// order, so results are bitwise reproducible.
 #include "qe_kernels.h"
 #include "qe_tiles.h"
 

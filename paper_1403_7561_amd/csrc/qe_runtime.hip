@@ -982,7 +982,7 @@ qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options
   launch_adj_rhs(cx.s, cx.g, cx.tm, ch, bx, p->semi, phi, cx.f64(cx.lay.gvec), cx.f64(cx.lay.partial), counters + 2,
                  cx.f64(cx.lay.scal) + 1);
   int pst = 0, its = 0;
-  if ((st = cx.pcg(false, cx.f64(cx.lay.gvec), 1.0, 1e-11, o->krylov_maxit, o->check_every, &pst, &its)) != QE_OK)
+  if ((st = cx.pcg(false, cx.f64(cx.lay.gvec), 1.0, 1e-12, o->krylov_maxit, o->check_every, &pst, &its)) != QE_OK)
     return finish(st, r, rep);
   r.krylov_iters = its;
   if (pst == PCG_BREAKDOWN || pst == PCG_NONFINITE)

@@ -1,4 +1,4 @@
-// Interface-charge and Robin face terms (Sec. II.A.5) on mesh-plane sheets.
+// Interface-charge and Robin face terms (Sec. II.A.4) on mesh-plane sheets.
 //
 // On a face f (a rectangle of a node plane, sides ha x hb) the weak form
 // gains alpha int_f (phi - phi0) w_i - KAPPA sigma_f int_f w_i.  With bilinear

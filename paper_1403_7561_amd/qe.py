@@ -165,6 +165,34 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _device(device):
+    """torch.device with the index resolved (a bare "cuda" is the current one)."""
+    import torch
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
+def _dev(t, dtype, n, device, name):
+    """t itself if it is a contiguous tensor of exactly ``dtype`` with ``n``
+    entries on ``device``; anything else raises ValueError before the library
+    is called (the kernels trust every pointer and length they are given)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    d = _device(device)
+    if t.device.type != d.type or (d.index is not None and t.device.index != d.index):
+        raise ValueError(f"{name}: tensor on {t.device}, the problem is on {d}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if t.numel() != n:
+        raise ValueError(f"{name}: {t.numel()} entries, expected {n}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    return t
+
+
 @dataclass
 class Physics:
     stat: str = "fd"
@@ -236,7 +264,7 @@ class Problem:
                                       sg.data_ptr() if sg is not None else None, float(sh.robin_d),
                                       float(sh.robin_eps), float(sh.phi0))
         self.n_sheets = len(sheets)
-        self.device = device
+        self.device = _device(device)
         self._set_quantum(getattr(dev, "quantum", None))
 
     def _set_quantum(self, q):
@@ -257,6 +285,8 @@ class Problem:
         self.q_psi2 = dev64(q.psi2)
         self.q_phik = dev64(q.phi_k)
         E = np.ascontiguousarray(q.E_i, dtype=np.float64)
+        _dev(self.q_psi2, torch.float64, E.size * self.N, self.device, "quantum psi2 [n_states, N]")
+        _dev(self.q_phik, torch.float64, self.N, self.device, "quantum phi_k")
         self.q_E = (ctypes.c_double * E.size)(*E.tolist())
         reg = getattr(q, "region", None)
         if reg is None:
@@ -265,6 +295,8 @@ class Problem:
             self.q_region = reg.to(dtype=torch.uint8, device=self.device).contiguous()
         else:
             self.q_region = torch.as_tensor(np.ascontiguousarray(reg, dtype=np.uint8), device=self.device)
+        if self.q_region is not None:
+            _dev(self.q_region, torch.uint8, self.E, self.device, "quantum region")
         self.c_quantum = CQuantum(int(E.size), int(q.confinement), self.q_psi2.data_ptr(),
                                   self.q_phik.data_ptr(), self.q_E, float(q.m_t),
                                   self.q_region.data_ptr() if self.q_region is not None else None)
@@ -319,6 +351,7 @@ def qe_solve(prob, phys=None, opts=None, phi=None, want_density=True, ws=None, c
     o = opts if opts is not None else qe_default_options()
     if phi is None:
         phi = torch.zeros(prob.N, dtype=torch.float64, device=prob.device)
+    _dev(phi, torch.float64, prob.N, prob.device, "phi")
     n = torch.empty(prob.N, dtype=torch.float64, device=prob.device) if want_density else None
     ws = ws or workspace_for(prob, o)
     cp, cph, rep = prob.c(), phys.c(), CReport()
@@ -333,6 +366,7 @@ def qe_residual(prob, phi, phys=None, ws=None, want_diag=True):
     torch = _torch()
     lib = load_library()
     phys = phys or prob.physics
+    _dev(phi, torch.float64, prob.N, prob.device, "phi")
     F = torch.empty(prob.N, dtype=torch.float64, device=prob.device)
     d = torch.empty_like(F) if want_diag else None
     n2 = ctypes.c_double(0.0)
@@ -347,6 +381,11 @@ def qe_jv(prob, phi, v, phys=None, ws=None):
     torch = _torch()
     lib = load_library()
     phys = phys or prob.physics
+    _dev(phi, torch.float64, prob.N, prob.device, "phi")
+    if getattr(v, "dtype", None) not in (torch.float64, torch.float32):
+        raise ValueError(f"v: dtype {getattr(v, 'dtype', type(v).__name__)}, expected torch.float64 (qe_jv) "
+                         "or torch.float32 (qe_jv_f32)")
+    _dev(v, v.dtype, prob.N, prob.device, "v")
     y = torch.empty_like(v)
     ws = ws or workspace_for(prob)
     cp, cph = prob.c(), phys.c()
@@ -361,8 +400,10 @@ def qe_jv_f32(prob, phi, v32, phys=None, ws=None):
 
 
 def qe_count_electrons(prob, phi, boxes, phys=None, ws=None):
+    torch = _torch()
     lib = load_library()
     phys = phys or prob.physics
+    _dev(phi, torch.float64, prob.N, prob.device, "phi")
     b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 6))
     out = np.zeros(b.shape[0])
     ws = ws or workspace_for(prob)
@@ -378,6 +419,7 @@ def qe_density(prob, phi, phys=None, ws=None):
     torch = _torch()
     lib = load_library()
     phys = phys or prob.physics
+    _dev(phi, torch.float64, prob.N, prob.device, "phi")
     n = torch.empty(prob.N, dtype=torch.float64, device=prob.device)
     ws = ws or workspace_for(prob)
     cp, cph = prob.c(), phys.c()
@@ -394,6 +436,7 @@ def qe_adjoint(prob, phi, box, phys=None, opts=None, ws=None, want_eps=True, wan
     lib = load_library()
     phys = phys or prob.physics
     o = opts if opts is not None else qe_default_options()
+    _dev(phi, torch.float64, prob.N, prob.device, "phi")
     b = np.ascontiguousarray(np.asarray(box, dtype=np.float64).reshape(6))
     dV = np.zeros(max(prob.n_dir, 1))
     Q = ctypes.c_double(0.0)
@@ -413,8 +456,11 @@ def qe_adjoint(prob, phi, box, phys=None, opts=None, ws=None, want_eps=True, wan
 def qe_time_jv(prob, phi, v, precision="fp64", reps=200, phys=None, ws=None):
     """Mean time (ms) of one CG J.v kernel launch, measured with HIP events,
     and the number of elements whose Gauss-point coefficients it reads."""
+    torch = _torch()
     lib = load_library()
     phys = phys or prob.physics
+    _dev(phi, torch.float64, prob.N, prob.device, "phi")
+    _dev(v, torch.float64, prob.N, prob.device, "v")
     ms = ctypes.c_double(0.0)
     ncoef = ctypes.c_int64(0)
     ws = ws or workspace_for(prob)
@@ -441,6 +487,10 @@ def qe_solve_batch(probs, phys=None, opts=None, phis=None, boxes=(), tune_cache=
     n = len(probs)
     if phis is None:
         phis = [torch.zeros(p.N, dtype=torch.float64, device=p.device) for p in probs]
+    if len(phis) != n:
+        raise ValueError(f"phis: {len(phis)} tensors for {n} problems")
+    for k, (p, ph) in enumerate(zip(probs, phis)):
+        _dev(ph, torch.float64, p.N, p.device, f"phis[{k}]")
     arr = (CProblem * n)(*[p.c() for p in probs])
     ptrs = (ctypes.c_void_p * n)(*[ph.data_ptr() for ph in phis])
     b = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 6))
@@ -483,6 +533,13 @@ def qe_schrodinger_solve(prob, inv_mass, v0, phi, n_states, fixed=None, tol=1e-8
     vv = torch.as_tensor(np.ascontiguousarray(v0, dtype=np.float64), **f64)
     fx = None if fixed is None else torch.as_tensor(np.ascontiguousarray(fixed, dtype=np.uint8), device=prob.device)
     ph = phi if hasattr(phi, "data_ptr") else torch.as_tensor(np.ascontiguousarray(phi, dtype=np.float64), **f64)
+    _dev(ph, torch.float64, prob.N, prob.device, "phi")
+    _dev(im, torch.float64, prob.E, prob.device, "inv_mass")
+    _dev(vv, torch.float64, prob.E, prob.device, "v0")
+    if fx is not None:
+        _dev(fx, torch.uint8, prob.N, prob.device, "fixed")
+    if guess is not None:
+        _dev(guess, torch.float64, int(n_states) * prob.N, prob.device, "guess [n_states, N]")
     cp = prob.c()
     cs = CSchrodinger(im.data_ptr(), vv.data_ptr(), fx.data_ptr() if fx is not None else None)
     if ws is None:

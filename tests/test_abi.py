@@ -14,7 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "qe.h")).read()
+    with open(os.path.join(ROOT, "include", "qe.h")) as fh:
+        src = fh.read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(qe_[a-z0-9_]+)\s*\(", src)))
 
@@ -284,3 +285,26 @@ def test_schrodinger_argument_checks():
                                       a["maxit"], ctypes.c_uint64(1), 0, E.ctypes.data_as(P), ctypes.c_void_p(16),
                                       None, None, ctypes.c_void_p(a["ws"]) if a["ws"] else None, 1 << 40, None)
         assert st in (-1, -3) and needle in qe.qe_last_error(), (needle, qe.qe_last_error())
+
+
+def test_tensor_arguments_checked_before_the_library():
+    """The binding rejects a tensor on the wrong device, of the wrong dtype or
+    length, or not contiguous, before any pointer reaches the library."""
+    import numpy as np
+    import torch
+    from paper_1403_7561_amd.qe import _dev
+    cpu = torch.device("cpu")
+    t = torch.zeros(10, dtype=torch.float64)
+    assert _dev(t, torch.float64, 10, cpu, "phi") is t
+    with pytest.raises(ValueError, match="tensor on cpu"):
+        _dev(t, torch.float64, 10, torch.device("cuda", 0), "phi")
+    with pytest.raises(ValueError, match="dtype"):
+        _dev(t.to(torch.float32), torch.float64, 10, cpu, "phi")
+    with pytest.raises(ValueError, match="dtype"):
+        _dev(t.to(torch.int16), torch.float64, 10, cpu, "phi")
+    with pytest.raises(ValueError, match="11"):
+        _dev(t, torch.float64, 11, cpu, "phi")
+    with pytest.raises(ValueError, match="contiguous"):
+        _dev(torch.zeros(20, dtype=torch.float64)[::2], torch.float64, 10, cpu, "phi")
+    with pytest.raises(ValueError, match="torch tensor"):
+        _dev(np.zeros(10), torch.float64, 10, cpu, "phi")

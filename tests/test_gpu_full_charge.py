@@ -1,6 +1,6 @@
 """GPU parity of the full space charge of Eq. Poisson (holes, Boltzmann and
 Fermi-Dirac statistics, incomplete dopant ionization, Sec. II.A.1-3) with
-Ohmic contacts (Sec. II.A.5), through the C ABI, against the FP64 oracle on
+Ohmic contacts (Sec. II.A.4), through the C ABI, against the FP64 oracle on
 the same seeded inputs.  Tolerances as in the other parity tests: kernel
 outputs to 1e-12 of their scale, converged potentials to 1e-9 relative."""
 import numpy as np

@@ -152,6 +152,9 @@ def test_mixed_precision_matches_fp64():
 
 
 def test_adjoint_matches_oracle_and_differences():
+    """dQ/dV, dQ/deps and lam against the oracle's adjoint to 1e-10 (both at
+    the oracle's converged potential), and central differences of the GPU
+    solve on two gates."""
     volts = np.array([1.6, 1.5, 0.5, 0.8, 0.4])
     dev = synth.double_dot_device("adj", 17, 17, 11, volts)
     box = dev.boxes["D1"]
@@ -160,11 +163,13 @@ def test_adjoint_matches_oracle_and_differences():
     P = qe.Problem(dev)
     Q, dV, deps, lam, rep = qe.qe_adjoint(P, dev_tensor(res.phi), box, want_lam=True)
     print("Q", Q, adj_o.Q, "dV", dV, adj_o.dQ_ddir, rep)
-    assert Q == pytest.approx(adj_o.Q, rel=1e-12)
-    assert np.allclose(dV, adj_o.dQ_ddir, rtol=1e-8, atol=1e-10 * np.abs(adj_o.dQ_ddir).max())
     de = deps.cpu().numpy()
-    assert rel_max(de, adj_o.dQ_deps) < 1e-8
-    assert rel_max(lam.cpu().numpy(), adj_o.lam) < 1e-8
+    print("rel dV", rel_max(dV, adj_o.dQ_ddir), "deps", rel_max(de, adj_o.dQ_deps), "lam",
+          rel_max(lam.cpu().numpy(), adj_o.lam))
+    assert Q == pytest.approx(adj_o.Q, rel=1e-12)
+    assert rel_max(dV, adj_o.dQ_ddir) < 1e-10
+    assert rel_max(de, adj_o.dQ_deps) < 1e-10
+    assert rel_max(lam.cpu().numpy(), adj_o.lam) < 1e-10
     # central differences of the GPU solve (h = 1e-4 V) on two gates
     opts = qe.qe_default_options(newton_atol=1e-11)
     for g in (0, 3):

@@ -3,8 +3,10 @@ SchrodEqn, SchrodEqnWeakForm) through the C ABI against the oracle's dense /
 shift-invert generalized eigenproblem on the same mesh and inputs: the 1D
 infinite well (exact discrete levels), an anisotropic 3D box, the finite
 well with unequal masses, and the gate-stack dot in the semiclassical
-potential; eigenvalues to 1e-9 relative, eigenvectors (up to sign) to 1e-5.
-Then one closed predictor-corrector loop."""
+potential; eigenvalues to 1e-9 relative, eigenvectors (up to sign, or their
+projector within a cluster of equal levels) to 1e-8.  Then one closed
+predictor-corrector loop, run with the GPU solvers and with the oracle's,
+which must agree to 1e-9 relative in phi, the levels and the electrons.""" 
 import numpy as np
 import pytest
 
@@ -28,15 +30,33 @@ def mesh_problem(x, y, z):
     return qe.Problem(dev)
 
 
-def compare(P, inv_mass, v0, phi, fixed, n, tol=1e-10):
-    Eo, psio, (H, M) = sch.solve(P.x.cpu().numpy(), P.y.cpu().numpy(), P.z.cpu().numpy(), inv_mass, v0, phi, fixed, n)
-    E, psi, psi2, it = qe.qe_schrodinger_solve(P, inv_mass, v0, phi, n, fixed=fixed, tol=tol, maxit=2000)
-    print("E gpu", E, "\nE ora", Eo, "iters", it)
-    assert np.allclose(E, Eo, rtol=1e-9, atol=1e-12)
+def compare(P, inv_mass, v0, phi, fixed, n, tol=1e-12):
+    """Levels to 1e-9 relative; a state whose level is separated from every
+    other by at least 1e-6 of the spectrum's scale (the next level included)
+    to 1e-8 (up to sign); the states of a closer cluster through their
+    M-orthogonal projector, to 1e-8."""
+    Eo, psio, (H, M) = sch.solve(P.x.cpu().numpy(), P.y.cpu().numpy(), P.z.cpu().numpy(), inv_mass, v0, phi, fixed,
+                                 n + 1)
+    E, psi, psi2, it = qe.qe_schrodinger_solve(P, inv_mass, v0, phi, n, fixed=fixed, tol=tol, maxit=3000)
+    print("E gpu", E, "\nE ora", Eo[:n], "iters", it)
+    assert np.allclose(E, Eo[:n], rtol=1e-9, atol=1e-12)
     ps = psi.cpu().numpy()
+    scale = max(np.abs(Eo).max(), 1e-30)
+    gaps = np.abs(Eo[:n, None] - Eo[None, :])
+    np.fill_diagonal(gaps[:, :n], np.inf)
+    isolated = gaps.min(axis=1) >= 1e-6 * scale
+    worst = 0.0
     for i in range(n):
-        d = min(np.abs(ps[i] - psio[i]).max(), np.abs(ps[i] + psio[i]).max()) / np.abs(psio[i]).max()
-        assert d < 1e-5, (i, d)
+        if isolated[i]:
+            d = min(np.abs(ps[i] - psio[i]).max(), np.abs(ps[i] + psio[i]).max()) / np.abs(psio[i]).max()
+        else:
+            c = [j for j in range(n) if gaps[i, j] < 1e-6 * scale] + [i]
+            Pg = ps[c].T @ (ps[c] @ M)
+            Po = psio[c].T @ (psio[c] @ M)
+            d = np.abs(Pg - Po).max() / np.abs(Po).max()
+        worst = max(worst, d)
+        assert d < 1e-8, (i, d)
+    print("eigenvector difference (max)", worst, "isolated", isolated)
     G = ps @ (M @ ps.T)
     assert np.allclose(G, np.eye(n), atol=1e-10)
     assert np.array_equal(psi2.cpu().numpy(), ps * ps)
@@ -70,7 +90,9 @@ def test_finite_well_unequal_masses():
     well = np.abs(zc) < 10.0
     fixed = np.zeros(P.N, bool)
     fixed[:4] = fixed[-4:] = True
-    compare(P, np.where(well, 1 / 0.067, 1.0), np.where(well, 0.0, 0.1), np.zeros(P.N), fixed, 3)
+    # a 400-element column converges slowly under the Jacobi preconditioner:
+    # a residual of 1e-10 already puts the vectors within 1e-8 (gaps ~ E / 3)
+    compare(P, np.where(well, 1 / 0.067, 1.0), np.where(well, 0.0, 0.1), np.zeros(P.N), fixed, 3, tol=1e-10)
 
 
 def test_free_nodes_in_a_corner():
@@ -157,7 +179,7 @@ def test_predictor_corrector_loop_closes():
 
     def eig_gpu(phi):
         # warm start from the previous outer iteration's states
-        E, psi, psi2, it = qe.qe_schrodinger_solve(base, inv_mass, v0, phi, 8, fixed=fixed, tol=1e-10,
+        E, psi, psi2, it = qe.qe_schrodinger_solve(base, inv_mass, v0, phi, 8, fixed=fixed, tol=1e-12,
                                                    guess=prev.get("psi"))
         prev["psi"] = psi
         prev.setdefault("iters", []).append(it)
@@ -184,6 +206,10 @@ def test_predictor_corrector_loop_closes():
     assert 1.0 < n_g < 16.0
     phi_o, E_o, n_o, hist_o = loop(eig_oracle, poisson_oracle, phi0)
     print("oracle loop", hist_o, E_o, n_o)
-    assert np.abs(phi_g - phi_o).max() < 2e-4
-    assert np.allclose(E_g, E_o, atol=2e-4)
-    assert n_g == pytest.approx(n_o, rel=1e-3)
+    dphi = np.abs(phi_g - phi_o).max() / np.abs(phi_o).max()
+    print("loop parity: phi", dphi, "levels", np.abs(E_g - E_o).max() / np.abs(E_o).max(),
+          "electrons", abs(n_g - n_o) / n_o, "histories", np.abs(np.array(hist) - np.array(hist_o)).max())
+    assert len(hist) == len(hist_o)
+    assert dphi <= 1e-9
+    assert np.abs(E_g - E_o).max() <= 1e-9 * np.abs(E_o).max()
+    assert n_g == pytest.approx(n_o, rel=1e-9)

@@ -1,5 +1,5 @@
 """GPU parity of the interface-charge (Eq. NeuBC4fc) and Robin (charged gate)
-face terms of Sec. II.A.5 through the C ABI, against the FP64 oracle on the
+face terms of Sec. II.A.4 through the C ABI, against the FP64 oracle on the
 same seeded inputs: residual, diagonal and J.v at a perturbed potential,
 solves, the adjoint's contact terms, mixed precision.  Sheets in all three
 plane orientations, partial face ranges, sheets sharing nodes, and Robin

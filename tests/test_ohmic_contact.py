@@ -1,4 +1,4 @@
-"""The library's Ohmic-contact potential (a host computation, Sec. II.A.5)
+"""The library's Ohmic-contact potential (a host computation, Sec. II.A.4)
 against the oracle's, and against the neutrality it is defined by, over
 statistics, ionization models, dopant densities, temperatures and the
 low-temperature form of the logarithm."""

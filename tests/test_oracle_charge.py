@@ -1,6 +1,6 @@
 """Pins of the oracle's full space charge (Eq. Poisson with holes and dopant
 ionization, Sec. II.A.1 and II.A.3) and of the Ohmic-contact potentials
-(Sec. II.A.5), against textbook identities that the formulas must obey rather
+(Sec. II.A.4), against textbook identities that the formulas must obey rather
 than against the formulas themselves."""
 import numpy as np
 import pytest

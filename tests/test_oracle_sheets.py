@@ -1,5 +1,5 @@
 """Pins of the oracle's interface-charge (Eq. NeuBC4fc) and Robin face terms
-(Sec. II.A.5) against closed forms: Q1 elements reproduce piecewise-linear
+(Sec. II.A.4) against closed forms: Q1 elements reproduce piecewise-linear
 potentials exactly at the nodes, so charge-free slabs with a sheet charge or
 a Robin condition must match the 1D electrostatics to rounding."""
 import numpy as np
