@@ -230,6 +230,22 @@ qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* 
                    double* phi, double* n_nodal, void* ws, size_t ws_bytes,
                    void* stream, qe_report* rep);
 
+/* qe_solve for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation).  The same
+ * problem, options, results and errors as qe_solve, without a caller
+ * workspace: the library uses a static device array of QE_STATIC_WS_BYTES
+ * bytes (256 MiB, enough for 129 x 129 x 65 nodes) that it holds on each GPU
+ * it runs on until the process ends.  The call allocates no device or
+ * pinned host memory and creates no HIP event (its CG loop is polled by
+ * stream synchronisations instead of events and a posted host word).
+ * QE_ERR_WORKSPACE, before any device work, when qe_workspace_bytes(p, o)
+ * exceeds QE_STATIC_WS_BYTES.  Every call on one GPU uses that GPU's array,
+ * which keeps the last call's contents (a solve writes every part it reads
+ * first), so calls that overlap on one GPU race. */
+#define QE_STATIC_WS_BYTES (256u << 20)
+qe_status qe_solve_static(const qe_problem* p, const qe_physics* ph, const qe_options* o, double* phi,
+                          double* n_nodal, void* stream, qe_report* rep);
+
 /* Residual of Eq. PoissonWeakForm at phi (device [N], used as given, Dirichlet
  * entries included): F device [N] (free rows; 0 on Dirichlet rows).
  * diag: device [N] or NULL, the Jacobian diagonal (1 on Dirichlet rows).

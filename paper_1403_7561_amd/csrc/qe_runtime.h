@@ -29,6 +29,7 @@
 
 namespace qe {
 
+struct HostMirror;
 qe_status fail(qe_status st, const char* fmt, ...);
 void clear_error();
 qe_status make_charge(const qe_physics* ph, Charge& ch);
@@ -78,7 +79,10 @@ struct Context {
   unsigned int* u32(size_t off) const { return reinterpret_cast<unsigned int*>(ws + off); }
   const int4* sheet_items() const { return reinterpret_cast<const int4*>(ws + lay.sheet_items); }
 
-  qe_status init(const qe_problem* p, const Charge& ch, void* ws, size_t ws_bytes, void* stream, int kz = 0);
+  bool no_alloc = false;                // host read-backs in static storage, no events
+  HostMirror* hm = nullptr;
+  qe_status init(const qe_problem* p, const Charge& ch, void* ws, size_t ws_bytes, void* stream, int kz = 0,
+                 bool no_alloc = false);
   Doping doping() const;
   qe_status validate(const double* phi);
   qe_status stage(double* phi, int apply, int zero_free);
@@ -86,6 +90,8 @@ struct Context {
                      double* diag_out, double* norm2_host);
   qe_status pcg(bool mixed, const double* b, double sign, double rtol, int maxit, int check_every, int* pcg_status,
                 int* iters);
+  qe_status pcg_polled(bool mixed, const double* b, double sign, double rtol, int maxit, int* pcg_status,
+                       int* iters);
 };
 
 }  // namespace qe

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -372,7 +373,10 @@ qe_status check_options(const qe_options* o) {
   return QE_OK;
 }
 
-// Pinned host mirror for scalar read-backs (one per thread).
+// Host memory for scalar read-backs (one per thread): pinned, with a
+// host-coherent word the CG's stopping kernel posts to; or, for the entry
+// point that allocates nothing, the thread's own static storage (no posted
+// word: that CG loop is polled by stream synchronisations).
 struct HostMirror {
   PcgCtx* ctx = nullptr;
   double* scal = nullptr;
@@ -380,29 +384,45 @@ struct HostMirror {
   volatile CgProgress* prog = nullptr;   // host-coherent: written by the device while it runs
   CgProgress* prog_dev = nullptr;        // the same memory as the device addresses it
   bool ok = false;
-  HostMirror() {
-    void* a = nullptr;
-    void* b = nullptr;
-    if (hipHostMalloc(&a, 4096, hipHostMallocDefault) != hipSuccess) return;
-    ctx = reinterpret_cast<PcgCtx*>(a);
-    scal = reinterpret_cast<double*>(reinterpret_cast<char*>(a) + 1024);
-    flags = reinterpret_cast<int*>(reinterpret_cast<char*>(a) + 3072);
-    if (hipHostMalloc(&b, 256, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) return;
-    void* d = nullptr;
-    if (hipHostGetDevicePointer(&d, b, 0) != hipSuccess) return;
-    prog = reinterpret_cast<volatile CgProgress*>(b);
-    prog_dev = reinterpret_cast<CgProgress*>(d);
-    ok = true;
-  }
-  // never freed: thread-exit destructors may run after the HIP runtime is gone
 };
 
+static HostMirror make_pinned_mirror() {
+  HostMirror m;
+  void* a = nullptr;
+  void* b = nullptr;
+  if (hipHostMalloc(&a, 4096, hipHostMallocDefault) != hipSuccess) return m;
+  m.ctx = reinterpret_cast<PcgCtx*>(a);
+  m.scal = reinterpret_cast<double*>(reinterpret_cast<char*>(a) + 1024);
+  m.flags = reinterpret_cast<int*>(reinterpret_cast<char*>(a) + 3072);
+  if (hipHostMalloc(&b, 256, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) return m;
+  void* d = nullptr;
+  if (hipHostGetDevicePointer(&d, b, 0) != hipSuccess) return m;
+  m.prog = reinterpret_cast<volatile CgProgress*>(b);
+  m.prog_dev = reinterpret_cast<CgProgress*>(d);
+  m.ok = true;
+  return m;
+  // never freed: thread-exit destructors may run after the HIP runtime is gone
+}
+
 HostMirror& mirror() {
-  static thread_local HostMirror m;
+  static thread_local HostMirror m = make_pinned_mirror();
   return m;
 }
 
-qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t ws_bytes, void* stream_, int kz) {
+static HostMirror& plain_mirror() {
+  struct Store {
+    PcgCtx ctx;
+    double scal[64];
+    int flags[4];
+  };
+  static thread_local Store st;
+  static thread_local HostMirror m{&st.ctx, st.scal, st.flags, nullptr, nullptr, true};
+  return m;
+}
+
+qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t ws_bytes, void* stream_, int kz,
+                        bool no_alloc_) {
+  no_alloc = no_alloc_;
   QE_TRY(check_problem(p));
   if (ch.incomplete && !p->donors)
     return fail(QE_ERR_INVALID_ARG, "incomplete ionization needs donors and acceptors");
@@ -427,7 +447,8 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   if (ws_bytes < lay.total)
     return fail(QE_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, lay.total);
   ws = reinterpret_cast<char*>(ws_);
-  if (!mirror().ok) return fail(QE_ERR_HIP, "pinned host buffer allocation failed");
+  hm = no_alloc ? &plain_mirror() : &mirror();
+  if (!hm->ok) return fail(QE_ERR_HIP, "pinned host buffer allocation failed");
   // coordinates: strictly increasing (host copy; a few KB)
   std::vector<double> c(std::max({p->nx, p->ny, p->nz}));
   const double* arrs[3] = {p->x, p->y, p->z};
@@ -477,9 +498,9 @@ qe_status Context::validate(const double* phi) {
   if (sheets.n > 0) launch_validate_sheets(s, sheets, dflags);
   if (quantum.n > 0) launch_validate_quantum(s, vblocks, quantum, dflags);
   QE_HIP(hipGetLastError());
-  QE_HIP(hipMemcpyAsync(mirror().flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
+  QE_HIP(hipMemcpyAsync(hm->flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
   QE_HIP(hipStreamSynchronize(s));
-  const int f = *mirror().flags;
+  const int f = *hm->flags;
   if (f & 1) return fail(QE_ERR_INVALID_ARG, "eps_r must be finite and > 0");
   if (f & 2) return fail(QE_ERR_NONFINITE, "net_doping not finite or donors / acceptors not finite and >= 0");
   if (f & 4) return fail(QE_ERR_INVALID_ARG, "dir_id outside [-1, n_dir)");
@@ -507,9 +528,9 @@ qe_status Context::residual(const Charge& ch, const double* phi, const double* d
                        f64(lay.scal), quantum);
   QE_HIP(hipGetLastError());
   if (norm2_host) {
-    QE_HIP(hipMemcpyAsync(mirror().scal, ws + lay.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    QE_HIP(hipMemcpyAsync(hm->scal, ws + lay.scal, sizeof(double), hipMemcpyDeviceToHost, s));
     QE_HIP(hipStreamSynchronize(s));
-    *norm2_host = mirror().scal[0];
+    *norm2_host = hm->scal[0];
   }
   return QE_OK;
 }
@@ -519,7 +540,8 @@ qe_status Context::residual(const Charge& ch, const double* phi, const double* d
 qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, int maxit, int check_every,
                        int* pcg_status, int* iters) {
   PcgCtx* dctx = reinterpret_cast<PcgCtx*>(ws + lay.ctx);
-  HostMirror& hm = mirror();
+  if (no_alloc) return pcg_polled(mixed, b, sign, rtol, maxit, pcg_status, iters);
+  HostMirror& hm = *this->hm;
   volatile CgProgress* hp = hm.prog;
   hp->word = 0;  // the last decision of an earlier solve has been read: no write is pending
   const int cgb = cg_blocks(N);
@@ -601,6 +623,51 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
   }
 }
 
+// The same CG loop without events or a posted stop: chunks of iterations are
+// queued, the stream synchronised and the scalars read back after each.  For
+// the entry point that allocates nothing (a queued launch after the stop
+// returns at once, as in pcg).
+qe_status Context::pcg_polled(bool mixed, const double* b, double sign, double rtol, int maxit, int* pcg_status,
+                              int* iters) {
+  PcgCtx* dctx = reinterpret_cast<PcgCtx*>(ws + lay.ctx);
+  const int cgb = cg_blocks(N);
+  if (mixed)
+    launch_pcg_start32(s, cgb, N, sign, b, u8(lay.mask), f32(lay.invdiag32), f32(lay.x32), f32(lay.r32),
+                       f32(lay.z32), dctx, f64(lay.partial2), rtol, maxit);
+  else
+    launch_pcg_start64(s, cgb, N, sign, b, u8(lay.mask), f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.z),
+                       dctx, f64(lay.partial2), rtol, maxit);
+  QE_HIP(hipGetLastError());
+  constexpr int kChunk = 16;
+  int queued = 0;
+  for (;;) {
+    for (int c = 0; c < kChunk && queued <= maxit; ++c, ++queued) {
+      if (mixed)
+        launch_pcg_iter32(s, g, wm, cgb, N, queued & 1, f32(lay.eps32), u32(lay.cbits), f32(lay.c32),
+                          f32(lay.invdiag32), f32(lay.x32), f32(lay.r32), f32(lay.z32), f32(lay.p32), f32(lay.y32),
+                          dctx, nullptr, f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr,
+                          sheet_items(), u8(lay.mask));
+      else
+        launch_pcg_iter64(s, g, wm, cgb, N, queued & 1, f64(lay.eps_t), u32(lay.cbits), f64(lay.c), f64(lay.invdiag),
+                          f64(lay.x), f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, nullptr, f64(lay.partial),
+                          f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
+    }
+    QE_HIP(hipGetLastError());
+    PcgCtx& h = *hm->ctx;
+    QE_HIP(hipMemcpyAsync(&h, dctx, sizeof(PcgCtx), hipMemcpyDeviceToHost, s));
+    QE_HIP(hipStreamSynchronize(s));
+    if (h.done || queued > maxit) {
+      *pcg_status = h.done ? h.status : PCG_MAXIT;
+      *iters = h.iters;
+      if (!mixed) {   // the last x += alpha p, as in pcg (none after a breakdown)
+        launch_cg_finish_x64(s, vblocks, N, dctx, f64(lay.p), f64(lay.x));
+        QE_HIP(hipGetLastError());
+      }
+      return QE_OK;
+    }
+  }
+}
+
 }  // namespace qe
 
 using namespace qe;
@@ -670,8 +737,12 @@ static qe_status finish(qe_status st, qe_report& r, qe_report* rep) {
   return st;
 }
 
-qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* o, double* phi, double* n_nodal,
-                   void* ws, size_t ws_bytes, void* stream, qe_report* rep) {
+}  // extern "C"
+
+// qe_solve's body; no_alloc: host read-backs in static storage and the CG
+// polled without events (qe_solve_static).
+static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_options* o, double* phi,
+                            double* n_nodal, void* ws, size_t ws_bytes, void* stream, qe_report* rep, bool no_alloc) {
   clear_error();
   qe_report r;
   std::memset(&r, 0, sizeof(r));
@@ -681,7 +752,7 @@ qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* 
   if ((st = make_charge(ph, ch)) != QE_OK) return finish(st, r, rep);
   if (!phi) return finish(fail(QE_ERR_INVALID_ARG, "phi is NULL"), r, rep);
   Context cx;
-  if ((st = cx.init(p, ch, ws, ws_bytes, stream)) != QE_OK) return finish(st, r, rep);
+  if ((st = cx.init(p, ch, ws, ws_bytes, stream, 0, no_alloc)) != QE_OK) return finish(st, r, rep);
   const bool mixed = o->precision == QE_PREC_MIXED;
   if ((st = cx.validate(o->init_guess == 1 ? phi : nullptr)) != QE_OK) return finish(st, r, rep);
   if ((st = cx.stage(phi, 1, o->init_guess == 0 ? 1 : 0)) != QE_OK) return finish(st, r, rep);
@@ -770,6 +841,53 @@ qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* 
   if (hipStreamSynchronize(cx.s) != hipSuccess || hipGetLastError() != hipSuccess)
     return finish(fail(QE_ERR_HIP, "stream error at the end of the solve"), r, rep);
   return finish(st, r, rep);
+}
+
+// The workspace of qe_solve_static on each GPU: a file-scope device array
+// (QE_STATIC_WS_BYTES), whose address is taken once per device with that
+// device current; host code passes that address, never the array's name.
+static __device__ __align__(256) char scratch[QE_STATIC_WS_BYTES];
+static void* g_scratch_ptr[64] = {};
+static std::mutex g_scratch_mutex;
+
+static qe_status scratch_ptr(void** out) {
+  int dev = -1;
+  QE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(QE_ERR_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    QE_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(QE_ERR_HIP, "hipGetSymbolAddress returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return QE_OK;
+}
+
+extern "C" {
+
+qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* o, double* phi, double* n_nodal,
+                   void* ws, size_t ws_bytes, void* stream, qe_report* rep) {
+  return solve_impl(p, ph, o, phi, n_nodal, ws, ws_bytes, stream, rep, false);
+}
+
+qe_status qe_solve_static(const qe_problem* p, const qe_physics* ph, const qe_options* o, double* phi,
+                          double* n_nodal, void* stream, qe_report* rep) {
+  clear_error();
+  qe_report r;
+  std::memset(&r, 0, sizeof(r));
+  qe_status st;
+  if ((st = check_problem(p)) != QE_OK) return finish(st, r, rep);
+  const size_t need = qe_workspace_bytes(p, o);
+  if (need > (size_t)QE_STATIC_WS_BYTES)
+    return finish(fail(QE_ERR_WORKSPACE, "the problem needs %zu bytes of workspace, more than the %zu of the static "
+                                         "workspace (use qe_solve with a caller workspace)",
+                       need, (size_t)QE_STATIC_WS_BYTES),
+                  r, rep);
+  void* ws = nullptr;
+  if ((st = scratch_ptr(&ws)) != QE_OK) return finish(st, r, rep);
+  return solve_impl(p, ph, o, phi, n_nodal, ws, QE_STATIC_WS_BYTES, stream, rep, true);
 }
 
 qe_status qe_residual(const qe_problem* p, const qe_physics* ph, const double* phi, double* F, double* diag,

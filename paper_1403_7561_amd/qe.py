@@ -27,7 +27,7 @@ IONIZATION = {"complete": 0, "incomplete": 1}
 PREC = {"fp64": 0, "mixed": 1}
 
 EXPORTED = [
-    "qe_default_options", "qe_workspace_bytes", "qe_solve", "qe_residual", "qe_jv",
+    "qe_default_options", "qe_workspace_bytes", "qe_solve", "qe_solve_static", "qe_residual", "qe_jv",
     "qe_jv_f32", "qe_count_electrons", "qe_density", "qe_adjoint",
     "qe_batch_workspace_bytes", "qe_solve_batch", "qe_time_jv", "qe_ohmic_potential",
     "qe_schrodinger_workspace_bytes", "qe_schrodinger_solve", "qe_last_error",
@@ -117,6 +117,7 @@ def load_library(path=LIB_PATH):
         "qe_default_options": (None, [po]),
         "qe_workspace_bytes": (S, [pp, po]),
         "qe_solve": (I32, [pp, pph, po, V, V, V, S, V, pr]),
+        "qe_solve_static": (I32, [pp, pph, po, V, V, V, pr]),
         "qe_residual": (I32, [pp, pph, V, V, V, P(D), V, S, V]),
         "qe_jv": (I32, [pp, pph, V, V, V, V, S, V]),
         "qe_jv_f32": (I32, [pp, pph, V, V, V, V, S, V]),
@@ -360,6 +361,26 @@ def qe_solve(prob, phys=None, opts=None, phi=None, want_density=True, ws=None, c
     if check:
         _check(st, rep.as_dict())
     return phi, n, rep.as_dict()
+
+
+def qe_solve_static(prob, phi, n=None, phys=None, opts=None, check=True):
+    """qe_solve on the library's static workspace, for callers that cannot
+    allocate: phi (device, float64 [N]) holds the guess when opts.init_guess
+    = 1 and receives the solution; n (device [N] or None) the nodal density.
+    The call itself allocates nothing; returns the report dict."""
+    torch = _torch()
+    lib = load_library()
+    phys = phys or prob.physics
+    o = opts if opts is not None else qe_default_options()
+    _dev(phi, torch.float64, prob.N, prob.device, "phi")
+    if n is not None:
+        _dev(n, torch.float64, prob.N, prob.device, "n")
+    cp, cph, rep = prob.c(), phys.c(), CReport()
+    st = lib.qe_solve_static(ctypes.byref(cp), ctypes.byref(cph), ctypes.byref(o), _ptr(phi), _ptr(n), _stream(),
+                             ctypes.byref(rep))
+    if check:
+        _check(st, rep.as_dict())
+    return rep.as_dict()
 
 
 def qe_residual(prob, phi, phys=None, ws=None, want_diag=True):

@@ -308,3 +308,16 @@ def test_tensor_arguments_checked_before_the_library():
         _dev(torch.zeros(20, dtype=torch.float64)[::2], torch.float64, 10, cpu, "phi")
     with pytest.raises(ValueError, match="torch tensor"):
         _dev(np.zeros(10), torch.float64, 10, cpu, "phi")
+
+
+def test_static_solve_rejects_a_problem_too_large_before_device_work():
+    """qe_solve_static checks the workspace a problem needs against its static
+    array before any device work (so this runs without a GPU)."""
+    lib = qe.load_library()
+    p = fake_problem(400, 400, 200)
+    o = qe.qe_default_options()
+    assert lib.qe_workspace_bytes(ctypes.byref(p), ctypes.byref(o)) > (256 << 20)
+    rep = qe.CReport()
+    st = lib.qe_solve_static(ctypes.byref(p), ctypes.byref(qe.Physics().c()), ctypes.byref(o),
+                             ctypes.c_void_p(8), None, None, ctypes.byref(rep))
+    assert st == -3 and rep.status == -3 and "static workspace" in qe.qe_last_error()
