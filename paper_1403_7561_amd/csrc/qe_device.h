@@ -430,10 +430,19 @@ struct Quantum {
   const double* psi2;    // [n][N] nodal |psi_i|^2
   const double* phik;    // [N] phi^(k)
   const uint8_t* region; // [E] quantum-region elements, NULL = all
+  // [n][6] node-index box (i0, i1, j0, j1, k0, k1, inclusive) holding every
+  // node where |psi_i|^2 is not zero (empty when i0 > i1); an element outside
+  // it gets exactly nothing from state i
+  const int* sbox;
   double pref;           // P
   double inv_kT;         // 1/eV
   double E[kMaxStates];  // E_i - E_F, eV
+  // 3D confinement with every |E_i/kT| <= kPcExpMax: e^(E_i/kT), so that
+  // e^-x_i = e^-y e^(E_i/kT) with one exponential per Gauss point
+  int fast;
+  double B[kMaxStates];
 };
+constexpr double kPcExpMax = 300.0;
 
 // G(x) and G'(x) of the confinement's occupation.
 __device__ __forceinline__ void pc_occupation(int conf, double x, double& G, double& dG) {

@@ -50,6 +50,8 @@ void launch_count(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, c
                   const Quantum& qm);
 void launch_density(hipStream_t s, int nblocks, const Geom& g, const Charge& ch, const uint8_t* semi,
                     const double* phi, double* nout, const Quantum& qm);
+// Quantum.sbox: per state, the node-index box of its nonzero |psi|^2 (box: [n][6]).
+void launch_state_boxes(hipStream_t s, int nblocks, const Geom& g, const Quantum& qm, int* box);
 // Bits 32 (|psi|^2 not finite or negative) and 64 (phi^(k) not finite) of *flags.
 void launch_validate_quantum(hipStream_t s, int nblocks, const Quantum& qm, int* flags);
 void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const Doping& dop,

@@ -934,6 +934,53 @@ __global__ __launch_bounds__(kVecThreads) void k_validate_quantum(Quantum qm, in
   if (f) atomicOr(flags, f);
 }
 
+// Node-index bounding box of the nonzero |psi_i|^2 of every state (Quantum.sbox):
+// an empty box per state, then per-wave minima / maxima merged by atomics
+// (min / max are order independent).
+__global__ __launch_bounds__(64) void k_state_boxes_init(int n, int* __restrict__ box) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    int* b = box + 6 * t;
+    b[0] = b[2] = b[4] = 0x7fffffff;
+    b[1] = b[3] = b[5] = -1;
+  }
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_state_boxes(Geom g, Quantum qm, int* __restrict__ box) {
+  const long N = (long)g.nx * g.ny * g.nz;
+  for (int st = 0; st < qm.n; ++st) {
+    int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
+    for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
+      if (qm.psi2[qm.N * st + n] != 0.0) {
+        const int c[3] = {(int)(n % g.nx), (int)((n / g.nx) % g.ny), (int)(n / ((long)g.nx * g.ny))};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = min(lo[a], c[a]);
+          hi[a] = max(hi[a], c[a]);
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      for (int off = 32; off > 0; off >>= 1) {
+        lo[a] = min(lo[a], __shfl_down(lo[a], off, 64));
+        hi[a] = max(hi[a], __shfl_down(hi[a], off, 64));
+      }
+    }
+    if ((threadIdx.x & 63) == 0 && hi[0] >= 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        atomicMin(box + 6 * st + 2 * a, lo[a]);
+        atomicMax(box + 6 * st + 2 * a + 1, hi[a]);
+      }
+    }
+  }
+}
+
+void launch_state_boxes(hipStream_t s, int nblocks, const Geom& g, const Quantum& qm, int* box) {
+  QE_LAUNCH(k_state_boxes_init, 1, 64, s, qm.n, box);
+  QE_LAUNCH(k_state_boxes, nblocks, kVecThreads, s, g, qm, box);
+}
+
 void launch_validate_quantum(hipStream_t s, int nblocks, const Quantum& qm, int* flags) {
   QE_LAUNCH(k_validate_quantum, nblocks, kVecThreads, s, qm, flags);
 }

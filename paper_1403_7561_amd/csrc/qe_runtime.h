@@ -43,7 +43,7 @@ TileMap make_tilemap(int nx, int ny, int nz, int kz);
 struct Layout {
   size_t F, x, r, p, y, z, invdiag, gvec, c, cflag, rdz, cbits, mask, fsheet, fdiag, sheet_items;
   size_t x32, r32, p32, y32, z32, invdiag32, c32, eps32, eps_t;
-  size_t partial, partial2, ctx, scal, counters, flags;
+  size_t partial, partial2, ctx, scal, counters, flags, sbox;
   long n_partial;
   size_t total;
 };

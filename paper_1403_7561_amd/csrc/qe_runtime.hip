@@ -229,6 +229,7 @@ Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int 
   L.scal = take(64 * 8);
   L.counters = take(16 * sizeof(unsigned int));
   L.flags = take(16);
+  L.sbox = take(kMaxStates * 6 * sizeof(int));   // support boxes of the predictor's states
   L.total = off;
   return L;
 }
@@ -280,6 +281,8 @@ qe_status make_quantum(const qe_problem* p, const Charge& ch, Quantum& Q) {
   Q.n = q->n_states;
   Q.conf = q->confinement;
   Q.N = (long)p->nx * p->ny * p->nz;
+  // the kernels address one state's |psi|^2 with 32-bit byte offsets
+  if (Q.N * 8 > 0x7fffffffL) return fail(QE_ERR_INVALID_ARG, "quantum: more than 2^28 - 1 nodes");
   Q.psi2 = q->psi2;
   Q.phik = q->phi_k;
   Q.region = q->region;
@@ -288,6 +291,13 @@ qe_status make_quantum(const qe_problem* p, const Charge& ch, Quantum& Q) {
   // 3D: two spins x two valleys; 1D: 2 m_t kT / (pi hbar^2) in nm^-2
   Q.pref = q->confinement == 3 ? 4.0 : 2.0 * q->m_t * kM0 * kT_J / (kPi * kHbar * kHbar) * 1e-18;
   for (int i = 0; i < q->n_states; ++i) Q.E[i] = q->E_i[i];
+  // e^(E_i/kT) for the one-exponential form of the 3D occupation
+  Q.fast = q->confinement == 3;
+  for (int i = 0; i < q->n_states; ++i) {
+    const double e = q->E_i[i] * Q.inv_kT;
+    if (!(std::fabs(e) <= kPcExpMax)) Q.fast = 0;
+    Q.B[i] = Q.fast ? std::exp(e) : 0.0;
+  }
   return QE_OK;
 }
 
@@ -478,6 +488,10 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
     QE_HIP(hipMemsetAsync(ws + lay.fdiag, 0, N * sizeof(double), s));
     QE_HIP(hipMemcpyAsync(ws + lay.sheet_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, s));
     QE_HIP(hipStreamSynchronize(s));   // `items` is a host temporary
+  }
+  if (quantum.n > 0) {
+    quantum.sbox = reinterpret_cast<const int*>(ws + lay.sbox);
+    launch_state_boxes(s, vblocks, g, quantum, reinterpret_cast<int*>(ws + lay.sbox));
   }
   // reset device scalars and reduction counters
   QE_HIP(hipMemsetAsync(ws + lay.ctx, 0, sizeof(PcgCtx), s));

@@ -749,6 +749,136 @@ __device__ __forceinline__ void jv_tile_hm(const Geom& g, const WaveTile& w, int
 }
 
 // ---------------------------------------------------------------------------
+// Predictor-corrector electrons of one element at its Gauss points (Sec.
+// II.B.2): nq_q = P sum_i |psi_i|^2_q G(x_iq) and dnq_q = P/kT sum_i
+// |psi_i|^2_q G'(x_iq), x_iq = (phi_q - phi^(k)_q - E_i)/kT, over the states
+// in act (wave-uniform); |psi_i|^2 and phi^(k) are interpolated from the
+// nodes like phi, and src holds phi at the Gauss points.
+//
+// 3D confinement (G = 1/(1 + e^-x)): e^-x_iq = e^-y_q e^(E_i/kT) with y_q =
+// (phi_q - phi^(k)_q)/kT, so one exponential per Gauss point serves every
+// state.  An element with some |y_q| > kPcExpMax (and 1D confinement) takes
+// the per-state form, so that no product leaves the double range.  The form
+// is chosen per element, never per wave: the owner of an element and the
+// waves that see it as a halo get the same coefficients, zeros included (the
+// J.v of a wave reads the owner's coefficients where its own are nonzero).
+//
+// The |psi_i|^2 loads are buffer loads with one per-lane offset (the
+// element's first node; 8 N < 2^31 bytes, checked on the host) and scalar
+// layer, corner and state steps; the next state's eight loads are issued
+// before the current state is used, into the other of two register sets.
+__device__ __forceinline__ void pc_electrons(const Geom& g, const WaveTile& w, int L, const Quantum& qm,
+                                             unsigned int act, const double src[8], double nq[8],
+                                             double dnq[8]) {
+  const long b0 = w.n00 + w.sxy * L;
+  double u[8];
+  {
+    const long o[8] = {0, 1, g.nx, g.nx + 1, w.sxy, w.sxy + 1, w.sxy + g.nx, w.sxy + g.nx + 1};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) u[k] = qm.phik[b0 + o[k]];
+  }
+  gauss_interp(u);
+  bool fast = qm.fast != 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    u[q] = (src[q] - u[q]) * qm.inv_kT;   // y_q
+    fast = fast && fabs(u[q]) <= kPcExpMax;
+  }
+  if (fast) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u[q] = exp(-u[q]);   // e^-y_q
+  }
+  const bool all_fast = __builtin_amdgcn_ballot_w64(!fast) == 0;
+  const unsigned int vo = (unsigned int)(w.n00 * 8);
+  const unsigned int s0 = (unsigned int)(w.sxy * L * 8), sy = (unsigned int)(g.nx * 8),
+                     sz = (unsigned int)(w.sxy * 8);
+  const long nbytes = qm.N * 8;
+  auto load = [&](int i, double s2[8]) {
+    const __amdgpu_buffer_rsrc_t r = buf_res(qm.psi2 + qm.N * i, nbytes);
+    s2[0] = BufIO<double>::ld(r, vo, s0);
+    s2[1] = BufIO<double>::ld(r, vo + 8, s0);
+    s2[2] = BufIO<double>::ld(r, vo, s0 + sy);
+    s2[3] = BufIO<double>::ld(r, vo + 8, s0 + sy);
+    s2[4] = BufIO<double>::ld(r, vo, s0 + sz);
+    s2[5] = BufIO<double>::ld(r, vo + 8, s0 + sz);
+    s2[6] = BufIO<double>::ld(r, vo, s0 + sz + sy);
+    s2[7] = BufIO<double>::ld(r, vo + 8, s0 + sz + sy);
+  };
+  // G = 1/(1 + t), t = e^-x in [e^-600, e^600]: a reciprocal refined twice
+  // by Newton's iteration; dG/dx = t G^2 = G (t G), in that order so that it
+  // does not underflow; P and 1/kT are applied after the sum.  Written with
+  // explicit fma so that every copy rounds alike.
+  auto fast_terms = [&](int i, const double s2[8]) {
+    const double Bi = qm.B[i];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double t = u[q] * Bi;
+      const double d = fma(u[q], Bi, 1.0);
+      double G = __builtin_amdgcn_rcp(d);
+      G = fma(G, fma(-d, G, 1.0), G);
+      G = fma(G, fma(-d, G, 1.0), G);
+      nq[q] = fma(s2[q], G, nq[q]);
+      dnq[q] = fma(s2[q], G * (t * G), dnq[q]);
+    }
+  };
+  auto slow_terms = [&](int i, const double s2[8]) {
+    const double ei = qm.E[i] * qm.inv_kT;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double G, dG;
+      pc_occupation(qm.conf, u[q] - ei, G, dG);
+      nq[q] = fma(s2[q], G, nq[q]);
+      dnq[q] = fma(s2[q], dG, dnq[q]);
+    }
+  };
+  // one state's terms; the loop over states has one copy for waves whose
+  // elements all take the one-exponential form and one that chooses per lane
+  auto add = [&](auto kAllFast, int i, double s2[8]) {
+    gauss_interp(s2);
+    if constexpr (decltype(kAllFast)::value) {
+      fast_terms(i, s2);
+    } else {
+      if (fast)
+        fast_terms(i, s2);
+      else
+        slow_terms(i, s2);
+    }
+  };
+  // states in increasing order; the pass for the last state reloads it into
+  // the idle set (not used), so that every pass issues its loads unconditionally
+  auto states = [&](auto kAllFast) {
+    unsigned int m = act;
+    int i = __builtin_ctz(m);
+    m &= m - 1;
+    double sa[8], sb[8];
+    load(i, sa);
+    for (;;) {
+      int j = m ? __builtin_ctz(m) : i;
+      load(j, sb);
+      add(kAllFast, i, sa);
+      if (!m) break;
+      m &= m - 1;
+      i = j;
+      j = m ? __builtin_ctz(m) : i;
+      load(j, sa);
+      add(kAllFast, i, sb);
+      if (!m) break;
+      m &= m - 1;
+      i = j;
+    }
+  };
+  if (all_fast)
+    states(std::integral_constant<bool, true>());
+  else
+    states(std::integral_constant<bool, false>());
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    nq[q] *= qm.pref;
+    dnq[q] *= qm.pref * qm.inv_kT;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Residual F(phi + lam delta), Jacobi diagonal and Gauss-point coefficients
 // c_q = -KAPPA semi W rho'(phi_q) (= KAPPA semi W n'(phi_q) with electrons
 // alone) on one wave tile.  F and the diagonal are
@@ -772,6 +902,15 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
   const unsigned int sbits = w.semi_bits(g, semi);
   double ahx, ahy, axy;
   w.weights(ahx, ahy, axy);
+  // eigenstates whose support box meets a column of this wave (wave-uniform)
+  unsigned int qcols = 0;
+  if (kQ && qm->n > 0) {
+    for (int i = 0; i < qm->n; ++i) {
+      const int* bx = qm->sbox + 6 * i;
+      const bool in = w.col_ok && w.ex + 1 >= bx[0] && w.ex <= bx[1] && w.ey + 1 >= bx[2] && w.ey <= bx[3];
+      if (__builtin_amdgcn_ballot_w64(in)) qcols |= 1u << i;
+    }
+  }
   auto face = [&](int P, double f[4]) {
     const long b = w.n00 + w.sxy * P;
     const long o[4] = {0, 1, g.nx, g.nx + 1};
@@ -798,11 +937,15 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
       const double ee = eps[el];
       const double sx = ee * (ahx * hz), sy = ee * (ahy * hz), sz = ee * (axy * g.rdz[L]);
       const double ve[8] = {fb[0], fb[1], fb[2], fb[3], ft[0], ft[1], ft[2], ft[3]};
-      double zero[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) zero[k] = 0.0;
-      jv_element(ve, sx, sy, sz, zero, false, outF);          // eps Khat phi
       const double dg = (sx + sy + sz) * (1.0 / 9.0);
+      // eps Khat phi: with eigenstates it is formed after the charge, so that
+      // it is not live across the states' loop
+      if (kQ) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) outF[k] = 0.0;
+      } else {
+        jv_element(ve, sx, sy, sz, outF, false, outF);
+      }
 #pragma unroll
       for (int k = 0; k < 8; ++k) outD[k] = dg;
       const bool own = w.own_el && L >= w.k0;
@@ -825,40 +968,17 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
         double nq[8], dnq[8];
         const bool qel = kQ && (!qm->region || qm->region[el]);   // electrons from the states
         if (qel) {
-          // predictor-corrector electrons: |psi_i|^2 and phi^(k) interpolated
-          // to the Gauss points like phi
-          const long b0 = w.n00 + w.sxy * L;
-          const long o[8] = {0, 1, g.nx, g.nx + 1, w.sxy, w.sxy + 1, w.sxy + g.nx, w.sxy + g.nx + 1};
-          double dph[8];
 #pragma unroll
-          for (int k = 0; k < 8; ++k) dph[k] = qm->phik[b0 + o[k]];
-          gauss_interp(dph);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            dph[q] = src[q] - dph[q];
-            nq[q] = dnq[q] = 0.0;
+          for (int q = 0; q < 8; ++q) nq[q] = dnq[q] = 0.0;
+          // states whose support box meets this layer of the wave's columns
+          // (wave-uniform); in a lane outside a state's box all eight |psi_i|^2
+          // read are exactly 0, and so is what the state adds there
+          unsigned int act = 0;
+          for (unsigned int m = qcols; m; m &= m - 1) {
+            const int i = __builtin_ctz(m);
+            if (L + 1 >= qm->sbox[6 * i + 4] && L <= qm->sbox[6 * i + 5]) act |= 1u << i;
           }
-          for (int i = 0; i < qm->n; ++i) {
-            double s2[8];
-            const double* ps = qm->psi2 + qm->N * i + b0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) s2[k] = ps[o[k]];
-            // a state that vanishes on the element adds exactly nothing (its
-            // occupations are finite): skip them (whole waves outside the
-            // states' support skip the transcendentals)
-            if (s2[0] == 0.0 && s2[1] == 0.0 && s2[2] == 0.0 && s2[3] == 0.0 && s2[4] == 0.0 && s2[5] == 0.0 &&
-                s2[6] == 0.0 && s2[7] == 0.0)
-              continue;
-            gauss_interp(s2);
-            const double Ei = qm->E[i];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              double G, dG;
-              pc_occupation(qm->conf, (dph[q] - Ei) * qm->inv_kT, G, dG);
-              nq[q] += qm->pref * s2[q] * G;
-              dnq[q] += qm->pref * s2[q] * dG * qm->inv_kT;
-            }
-          }
+          if (act) pc_electrons(g, w, L, *qm, act, src, nq, dnq);
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -883,6 +1003,12 @@ __device__ __forceinline__ void residual_tile(const Geom& g, const WaveTile& w, 
           outF[k] -= src[k];
           outD[k] += cc[k];
         }
+      }
+      if (kQ) {
+        double kf[8];
+        jv_element(ve, sx, sy, sz, kf, false, kf);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) outF[k] += kf[k];
       }
       if (own) cflag[w.slot(L)] = nzc ? 1 : 0;
       if (nzc) cb |= 1u << (L - w.Lbeg);

@@ -143,6 +143,28 @@ def test_states_from_device_tensors(solved):
     assert rel_max(phi_t.cpu().numpy(), res.phi) < 1e-9
 
 
+@pytest.mark.parametrize("case", ["3d_region", "3d", "statistics"])
+def test_solve_independent_of_workspace_contents(case, solved):
+    """The solve reads no workspace it has not written: a workspace filled
+    with zero bytes, with NaN bytes or with huge values gives the same
+    potential bit for bit.  (A wave reads an element's Gauss-point
+    coefficients written by the element's owner wherever its own are
+    nonzero, so owner and halo waves must agree on which are zero.)"""
+    dev, po, res = solved("3d" if case == "statistics" else case)
+    if case == "statistics":
+        dev = synth.with_quantum(dev, None)
+    P = qe.Problem(dev)
+    opts = qe.qe_default_options(newton_atol=1e-10)
+    ws = qe.workspace_for(P)
+    out = []
+    for fill in (0x00, 0xFF, 0x7F):
+        ws.t.fill_(fill)
+        phi, _, rep = qe.qe_solve(P, opts=opts, ws=ws)
+        assert rep["status"] == 0
+        out.append(phi.clone())
+    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+
+
 def test_states_validated_and_unsupported_paths_rejected():
     dev = pc_device(2)
     dev.quantum.psi2 = dev.quantum.psi2.copy()
