@@ -78,6 +78,13 @@ class Mesh:
                 + (self.hx * self.hz / self.hy)[:, None, None] * KHAT_Y
                 + (self.hx * self.hy / self.hz)[:, None, None] * KHAT_Z)
 
+    def axis_stiffness(self):
+        """The three parts of Khat_e, int_e d_a w_i d_a w_j for a = x, y, z,
+        each [E, 8, 8] (their sum is unit_stiffness())."""
+        return ((self.hy * self.hz / self.hx)[:, None, None] * KHAT_X,
+                (self.hx * self.hz / self.hy)[:, None, None] * KHAT_Y,
+                (self.hx * self.hy / self.hz)[:, None, None] * KHAT_Z)
+
     def assemble(self, elem_mats):
         """Sum element matrices [E, 8, 8] into an N x N CSR matrix."""
         rows = np.broadcast_to(self.conn[:, :, None], elem_mats.shape).ravel()

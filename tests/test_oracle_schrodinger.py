@@ -1,7 +1,8 @@
-"""Pins of the oracle's Schrodinger eigenproblem (Eqs. SchrodEqn and
-SchrodEqnWeakForm): exact discrete eigenvalues of linear elements for the
-infinite well and the 3D box (tensor products of the closed-form 1D
-generalized eigenvalues), the harmonic oscillator, and the finite well with
+"""Pins of the oracle's Schrodinger eigenproblem (Eqs. SchrodEqn,
+SchrodEqnWeakForm and Schrodinger3D): exact discrete eigenvalues of linear
+elements for the infinite well and the 3D box, isotropic and with a
+diagonal mass tensor (tensor products of the closed-form 1D generalized
+eigenvalues, scaled per axis), the harmonic oscillator, and the finite well with
 equal and unequal masses against the BenDaniel-Duke transcendental
 equations (the paper's 20 nm, 100 meV example)."""
 import numpy as np
@@ -64,6 +65,55 @@ def test_three_dimensional_box_levels_are_sums():
     levels = sorted(HB2M * (lam1d(a, nx, Lx / nx) + lam1d(b, ny, Ly / ny) + lam1d(c, nz, Lz / nz))
                     for a in range(1, nx) for b in range(1, ny) for c in range(1, nz))
     assert np.allclose(E, levels[:6], rtol=1e-12)
+
+
+@pytest.mark.parametrize("masses", [(0.19, 0.19, 0.98), (0.3, 0.5, 0.9)])
+def test_anisotropic_box_levels_are_scaled_sums(masses):
+    # a diagonal mass tensor (Eq. Schrodinger3D: m_t, m_t, m_l for the Si
+    # Delta_2 valleys) separates too: every level is a sum of 1D discrete
+    # levels, each scaled by its own axis's 1/m.  Unequal box lengths and
+    # masses make any exchange of axes change the levels.
+    nx, ny, nz = 6, 5, 4
+    Lx, Ly, Lz = 12.0, 8.0, 6.0
+    x, y, z = np.linspace(0, Lx, nx + 1), np.linspace(0, Ly, ny + 1), np.linspace(0, Lz, nz + 1)
+    Z, Y, X = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    fixed = ((X == 0) | (X == nx) | (Y == 0) | (Y == ny) | (Z == 0) | (Z == nz)).ravel()
+    E_ = nx * ny * nz
+    mx, my, mz = masses
+    im = np.stack([np.full(E_, 1.0 / mx), np.full(E_, 1.0 / my), np.full(E_, 1.0 / mz)])
+    E, psi, _ = sch.solve(x, y, z, im, np.zeros(E_), np.zeros(fixed.size), fixed, 8)
+    levels = sorted(HB2M * (lam1d(a, nx, Lx / nx) / mx + lam1d(b, ny, Ly / ny) / my + lam1d(c, nz, Lz / nz) / mz)
+                    for a in range(1, nx) for b in range(1, ny) for c in range(1, nz))
+    assert np.allclose(E, levels[:8], rtol=1e-12)
+
+
+def test_anisotropic_column_levels_follow_the_axis_mass():
+    # a column confined along z only sees m_l (the Sec. II.C 1D-confined
+    # case): the z-well levels scale with 1/m_z and not with 1/m_x or 1/m_y
+    n, L = 40, 20.0
+    x, y, z = column(np.linspace(0.0, L, n + 1))
+    N = 4 * (n + 1)
+    fixed = np.zeros(N, bool)
+    fixed[:4] = fixed[-4:] = True
+    im = np.stack([np.full(n, 1.0 / 0.19), np.full(n, 1.0 / 0.19), np.full(n, 1.0 / 0.98)])
+    E, _, _ = sch.solve(x, y, z, im, np.zeros(n), np.zeros(N), fixed, 4)
+    assert np.allclose(E, HB2M / 0.98 * lam1d(np.arange(1, 5), n, L / n), rtol=1e-12)
+
+
+def test_isotropic_masses_given_per_axis_or_once():
+    nx, ny, nz = 5, 4, 3
+    x, y, z = np.linspace(0, 5, nx + 1), np.linspace(0, 4, ny + 1), np.linspace(0, 3, nz + 1)
+    Z, Y, X = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    fixed = ((X == 0) | (X == nx) | (Z == nz)).ravel()
+    E_ = nx * ny * nz
+    rng = np.random.default_rng(4)
+    m = rng.uniform(1.0, 5.0, E_)
+    v0 = rng.uniform(0.0, 0.3, E_)
+    E1, _, _ = sch.solve(x, y, z, m, v0, np.zeros(fixed.size), fixed, 4)
+    E3, _, _ = sch.solve(x, y, z, np.stack([m, m, m]), v0, np.zeros(fixed.size), fixed, 4)
+    assert np.array_equal(E1, E3)
+    with pytest.raises(ValueError, match="inv_mass"):
+        sch.solve(x, y, z, np.stack([m, m]), v0, np.zeros(fixed.size), fixed, 4)
 
 
 def test_harmonic_oscillator():
