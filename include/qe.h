@@ -345,13 +345,17 @@ qe_status qe_time_jv(const qe_problem* p, const qe_physics* ph, const double* ph
 qe_status qe_ohmic_potential(const qe_physics* ph, double N_D, double N_A, double V_a, double* phi);
 
 /* Effective-mass Schrodinger eigenproblem on the same Q1 mesh (Sec. II.B,
- * Eqs. SchrodEqn, SchrodEqnWeakForm): H psi = E M psi with
- *   H_ij = sum_e (hbar^2/2m0)(m0/m*_e) int_e grad w_i . grad w_j + int V w_i w_j,
+ * Eqs. SchrodEqn, SchrodEqnWeakForm, and Eq. Schrodinger3D's per-axis masses,
+ * Sec. II.C): H psi = E M psi with
+ *   H_ij = sum_e (hbar^2/2m0) sum_a (m0/m*_e,a) int_e d_a w_i d_a w_j + int V w_i w_j,
  *   M_ij = int w_i w_j,  V = v0_e - phi (eV; phi interpolated to the Gauss
- * points), psi = 0 on the `fixed` nodes and natural (Neumann) conditions on
- * every other boundary.  Only nx, ny, nz, x, y, z of the qe_problem are read. */
+ * points), a over x, y, z (a diagonal mass tensor per element: m_t, m_t, m_l
+ * for the Delta_2 valleys of a Si dot), psi = 0 on the `fixed` nodes and
+ * natural (Neumann) conditions on every other boundary.  Only nx, ny, nz,
+ * x, y, z of the qe_problem are read. */
 typedef struct {
-  const double* inv_mass;        /* DEVICE [E] m0 / m*_e, finite, > 0 */
+  const double* inv_mass;        /* DEVICE [3][E] m0 / m*_e along x, then y, then z
+                                    (three planes of E), finite, > 0 */
   const double* v0;              /* DEVICE [E] conduction-band edge at phi = 0 relative
                                     to E_F, eV, finite (Ec0 in Si, plus the band
                                     offset in an insulator) */

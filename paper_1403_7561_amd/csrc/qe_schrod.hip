@@ -43,7 +43,11 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_validate(long E, long N, co
                                                              const double* __restrict__ phi, int* flags) {
   int f = 0;
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (long)gridDim.x * blockDim.x) {
-    if (!(inv_mass[e] > 0.0) || !isfinite(inv_mass[e])) f |= 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double m = inv_mass[a * E + e];
+      if (!(m > 0.0) || !isfinite(m)) f |= 1;
+    }
     if (!isfinite(v0[e])) f |= 2;
   }
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x)
@@ -90,8 +94,9 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_vmin(Geom g, const double* 
   }
 }
 
-// Tile-major operator data: kinetic weight (hbar^2/2m0)(m0/m*) and the
-// Gauss-point coefficients W (V_q - sigma) of H', W of M.
+// Tile-major operator data: kinetic weights (hbar^2/2m0)(m0/m*_a) along
+// a = x, y, z (three planes of nslots) and the Gauss-point coefficients
+// W (V_q - sigma) of H', W of M.
 __global__ __launch_bounds__(kVecThreads) void k_sch_coef(Geom g, const double* __restrict__ inv_mass,
                                                          const double* __restrict__ v0,
                                                          const double* __restrict__ phi, double sigma, double hb2m,
@@ -112,7 +117,9 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_coef(Geom g, const double* 
 #pragma unroll
     for (int t = 0; t < 8; ++t) ch[t] = W * (ve - q[t] - sigma);
     const long sl = tile_slot(i, j, k, tgx, tgy);
-    eH[sl] = hb2m * inv_mass[e];
+    const long nslots = (long)tgx * tgy * 49 * (g.nz - 1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) eH[a * nslots + sl] = hb2m * inv_mass[a * E + e];
     store8(cH + 8 * sl, ch);
   }
 }
@@ -161,7 +168,7 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_diag(Geom g, const double* 
                                                          const double* __restrict__ phi,
                                                          const uint8_t* __restrict__ mask, double sigma,
                                                          double hb2m, double* __restrict__ dinv) {
-  const long N = (long)g.nx * g.ny * g.nz;
+  const long N = (long)g.nx * g.ny * g.nz, Ecount = (long)(g.nx - 1) * (g.ny - 1) * (g.nz - 1);
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
     if (mask[n]) {
       dinv[n] = 0.0;
@@ -176,7 +183,8 @@ __global__ __launch_bounds__(kVecThreads) void k_sch_diag(Geom g, const double* 
           if (ei < 0 || ei >= g.nx - 1 || ej < 0 || ej >= g.ny - 1 || ek < 0 || ek >= g.nz - 1) continue;
           const long e = (long)ei + (long)(g.nx - 1) * ((long)ej + (long)(g.ny - 1) * ek);
           const double hx = g.x[ei + 1] - g.x[ei], hy = g.y[ej + 1] - g.y[ej], hz = g.z[ek + 1] - g.z[ek];
-          d += hb2m * inv_mass[e] * (hy * hz / hx + hx * hz / hy + hx * hy / hz) * (1.0 / 9.0);
+          d += hb2m * (inv_mass[e] * (hy * hz / hx) + inv_mass[Ecount + e] * (hx * hz / hy) +
+                       inv_mass[2 * Ecount + e] * (hx * hy / hz)) * (1.0 / 9.0);
           d += hx * hy * hz * (1.0 / 27.0) * fmax(v0[e] - phi[n] - sigma, 0.0);
         }
     dinv[n] = d > 0.0 ? 1.0 / d : 0.0;
@@ -650,10 +658,18 @@ static void sym_eig(int k, std::vector<double>& A, std::vector<double>& V, std::
 
 // Rayleigh-Ritz on the k x k pencil (GA, GB) (column-major, symmetric):
 // the nb lowest eigenvalues into lam and the coefficient matrix C (k x nb,
-// column-major) with C^T GB C = I.  False if GB is not numerically SPD.
+// column-major) with C^T GB C = I.  The basis [X W P] loses rank as the
+// iteration converges (a residual direction falls into the span of the
+// others), so GB, scaled to a unit diagonal, is diagonalised and only its
+// eigendirections above kRankTol of the largest are kept (the SVQB basis of
+// Stathopoulos and Wu, SIAM J. Sci. Comput. 23, 2002): the pencil reduced
+// to that range is a standard symmetric eigenproblem.  False if fewer than
+// nb directions remain (or GB has a diagonal entry that is not positive).
+constexpr double kRankTol = 1e-12;
+
 static bool rayleigh_ritz(int k, int nb, const double* GA, const double* GB, std::vector<double>& lam,
                           std::vector<double>& C) {
-  std::vector<double> d(k), B((size_t)k * k), A((size_t)k * k), L((size_t)k * k, 0.0);
+  std::vector<double> d(k), B((size_t)k * k), A((size_t)k * k);
   for (int i = 0; i < k; ++i) {
     const double b = GB[(size_t)i * k + i];
     if (!(b > 0.0) || !std::isfinite(b)) return false;
@@ -665,53 +681,54 @@ static bool rayleigh_ritz(int k, int nb, const double* GA, const double* GB, std
       B[(size_t)i * k + j] = 0.5 * (GB[(size_t)j * k + i] + GB[(size_t)i * k + j]) * d[i] * d[j];
       A[(size_t)i * k + j] = 0.5 * (GA[(size_t)j * k + i] + GA[(size_t)i * k + j]) * d[i] * d[j];
     }
-  for (int j = 0; j < k; ++j) {   // B = L L^T
-    double s = B[(size_t)j * k + j];
-    for (int t = 0; t < j; ++t) s -= L[(size_t)j * k + t] * L[(size_t)j * k + t];
-    if (!(s > 1e-13)) return false;
-    L[(size_t)j * k + j] = std::sqrt(s);
-    for (int i = j + 1; i < k; ++i) {
-      double r = B[(size_t)i * k + j];
-      for (int t = 0; t < j; ++t) r -= L[(size_t)i * k + t] * L[(size_t)j * k + t];
-      L[(size_t)i * k + j] = r / L[(size_t)j * k + j];
-    }
-  }
-  // A' = L^-1 A L^-T: solve L Y = A, then L A'^T = Y^T
-  std::vector<double> Y((size_t)k * k);
-  for (int c = 0; c < k; ++c)
-    for (int i = 0; i < k; ++i) {
-      double r = A[(size_t)i * k + c];
-      for (int t = 0; t < i; ++t) r -= L[(size_t)i * k + t] * Y[(size_t)t * k + c];
-      Y[(size_t)i * k + c] = r / L[(size_t)i * k + i];
-    }
-  std::vector<double> Ap((size_t)k * k);
-  for (int c = 0; c < k; ++c)
-    for (int i = 0; i < k; ++i) {
-      double r = Y[(size_t)c * k + i];
-      for (int t = 0; t < i; ++t) r -= L[(size_t)i * k + t] * Ap[(size_t)c * k + t];
-      Ap[(size_t)c * k + i] = r / L[(size_t)i * k + i];
-    }
+  // B = U diag(mu) U^T; T = U_r diag(mu_r)^-1/2 over the kept directions
+  std::vector<double> U, mu;
+  sym_eig(k, B, U, mu);
+  double mu_max = 0.0;
+  for (int i = 0; i < k; ++i) mu_max = std::max(mu_max, mu[i]);
+  std::vector<int> keep;
   for (int i = 0; i < k; ++i)
-    for (int j = i + 1; j < k; ++j) {
-      const double m = 0.5 * (Ap[(size_t)i * k + j] + Ap[(size_t)j * k + i]);
-      Ap[(size_t)i * k + j] = Ap[(size_t)j * k + i] = m;
+    if (mu[i] > kRankTol * mu_max) keep.push_back(i);
+  const int r = (int)keep.size();
+  if (r < nb || !(mu_max > 0.0) || !std::isfinite(mu_max)) return false;
+  std::vector<double> T((size_t)k * r);   // row-major k x r
+  for (int j = 0; j < r; ++j) {
+    const double sc = 1.0 / std::sqrt(mu[keep[j]]);
+    for (int i = 0; i < k; ++i) T[(size_t)i * r + j] = U[(size_t)i * k + keep[j]] * sc;
+  }
+  // A_r = T^T A T (r x r), symmetrised
+  std::vector<double> AT((size_t)k * r, 0.0), Ar((size_t)r * r, 0.0);
+  for (int i = 0; i < k; ++i)
+    for (int t = 0; t < k; ++t) {
+      const double a = A[(size_t)i * k + t];
+      for (int j = 0; j < r; ++j) AT[(size_t)i * r + j] += a * T[(size_t)t * r + j];
+    }
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) {
+      double acc = 0.0;
+      for (int t = 0; t < k; ++t) acc += T[(size_t)t * r + i] * AT[(size_t)t * r + j];
+      Ar[(size_t)i * r + j] = acc;
+    }
+  for (int i = 0; i < r; ++i)
+    for (int j = i + 1; j < r; ++j) {
+      const double m = 0.5 * (Ar[(size_t)i * r + j] + Ar[(size_t)j * r + i]);
+      Ar[(size_t)i * r + j] = Ar[(size_t)j * r + i] = m;
     }
   std::vector<double> V, w;
-  sym_eig(k, Ap, V, w);
-  std::vector<int> ord(k);
-  for (int i = 0; i < k; ++i) ord[i] = i;
+  sym_eig(r, Ar, V, w);
+  std::vector<int> ord(r);
+  for (int i = 0; i < r; ++i) ord[i] = i;
   std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a] < w[b]; });
   lam.resize(nb);
   C.assign((size_t)k * nb, 0.0);
   for (int c = 0; c < nb; ++c) {
     lam[c] = w[ord[c]];
-    // C = D L^-T v: back substitution with L^T
-    for (int i = k - 1; i >= 0; --i) {
-      double r = V[(size_t)i * k + ord[c]];
-      for (int t = i + 1; t < k; ++t) r -= L[(size_t)t * k + i] * C[(size_t)c * k + t];
-      C[(size_t)c * k + i] = r / L[(size_t)i * k + i];
+    // C = D T v
+    for (int i = 0; i < k; ++i) {
+      double acc = 0.0;
+      for (int j = 0; j < r; ++j) acc += T[(size_t)i * r + j] * V[(size_t)j * r + ord[c]];
+      C[(size_t)c * k + i] = acc * d[i];
     }
-    for (int i = 0; i < k; ++i) C[(size_t)c * k + i] *= d[i];
   }
   return true;
 }
@@ -730,7 +747,7 @@ static SchLayout sch_layout(long N, long nslots, int nz, long nwaves, int nb) {
     return o;
   };
   const int K = 3 * nb;
-  L.eH = take(nslots * 8);
+  L.eH = take(3 * nslots * 8);
   L.cH = take(nslots * 64);
   L.rdz = take((size_t)(nz - 1) * 16);
   L.mbits = take(nwaves * 64 * 4);
@@ -984,7 +1001,7 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
       off = (off + b + 255) & ~size_t(255);
       return o;
     };
-    const size_t o_psi = take((size_t)n_states * Nb * 8), o_im = take(Eb * 8), o_v0 = take(Eb * 8),
+    const size_t o_psi = take((size_t)n_states * Nb * 8), o_im = take(3 * Eb * 8), o_v0 = take(Eb * 8),
                  o_phi = take(Nb * 8), o_fx = take(Nb);
     const WaveMap wmb = make_wavemap(bm.bx, bm.by, bm.bz, 0);
     const size_t need = off + sch_layout(Nb, tile_slots(bm.bx, bm.by, bm.bz), bm.bz, wmb.nwaves, nb).total;
@@ -1001,7 +1018,7 @@ qe_status qe_schrodinger_solve(const qe_problem* p, const qe_schrodinger* sp, co
              *v0b = reinterpret_cast<double*>(ws + o_v0), *phib = reinterpret_cast<double*>(ws + o_phi);
       uint8_t* fxb = reinterpret_cast<uint8_t*>(ws + o_fx);
       const int gb = vec_blocks(Nb);
-      hipLaunchKernelGGL(k_sch_box_gather<double>, dim3(gb), dim3(kVecThreads), 0, s, em, 1, Ecount, sp->inv_mass, imb);
+      hipLaunchKernelGGL(k_sch_box_gather<double>, dim3(gb), dim3(kVecThreads), 0, s, em, 3, Ecount, sp->inv_mass, imb);
       hipLaunchKernelGGL(k_sch_box_gather<double>, dim3(gb), dim3(kVecThreads), 0, s, em, 1, Ecount, sp->v0, v0b);
       hipLaunchKernelGGL(k_sch_box_gather<double>, dim3(gb), dim3(kVecThreads), 0, s, bm, 1, N, phi, phib);
       hipLaunchKernelGGL(k_sch_box_gather<uint8_t>, dim3(gb), dim3(kVecThreads), 0, s, bm, 1, N, sp->fixed, fxb);

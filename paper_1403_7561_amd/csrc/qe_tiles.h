@@ -573,8 +573,9 @@ __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int
 // ---------------------------------------------------------------------------
 // H v and M v of the generalized Schrodinger eigenproblem for two columns at
 // once, on raw buffer resources like jv_tile_cg.  H's element operator is the
-// stiffness with per-element weight eH plus the Gauss-point coefficients cH
-// (eight per element); M's is the consistent mass matrix, which in the Haar
+// stiffness with per-element weights eH along x, y and z (a diagonal mass
+// tensor, Eq. Schrodinger3D) plus the Gauss-point coefficients cH (eight per
+// element); M's is the consistent mass matrix, which in the Haar
 // basis is diagonal, (V / 64) (1/3)^(number of difference axes) for an
 // element of volume V, so it costs eight products and no memory.  Both share
 // the face loads, the forward transforms and the first Gauss-point transform;
@@ -586,7 +587,7 @@ __device__ __forceinline__ bool jv_tile_cg(const Geom& g, const WaveTile& w, int
 // the second column is absent (its resources are empty: zeros in, no stores).
 struct HmStage {
   double f[2][4];
-  double e;
+  double e[3];   // kinetic weights along x, y, z
   double c[8];
 };
 
@@ -606,7 +607,11 @@ __device__ __forceinline__ void jv_tile_hm(const Geom& g, const WaveTile& w, int
     rh[c] = buf_res(yh[c] + sxy * Pb, col_ok[c] ? vbytes : 0);
     rm[c] = buf_res(ym[c] + sxy * Pb, col_ok[c] ? vbytes : 0);
   }
-  const __amdgpu_buffer_rsrc_t re = buf_res(eH + sl * Pb, (long)(g.nz - 1 - Pb) * sl * B);
+  // eH holds three planes of tile-major weights (x, y, z), nslots apart
+  const long nslots = sl * (g.nz - 1);
+  __amdgpu_buffer_rsrc_t re[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) re[a] = buf_res(eH + a * nslots + sl * Pb, (long)(g.nz - 1 - Pb) * sl * B);
   const __amdgpu_buffer_rsrc_t rc = buf_res(cH + 8 * sl * Pb, (long)(g.nz - 1 - Pb) * sl * 8 * B);
   const long nxy = (long)w.gi + (long)g.nx * w.gj;
   const unsigned int o_f[4] = {w.col_ok ? (unsigned int)(w.n00 * B) : kBufOob,
@@ -638,7 +643,8 @@ __device__ __forceinline__ void jv_tile_hm(const Geom& g, const WaveTile& w, int
       fb[c][k] = IO::ld(rz[c], o_f[k], s_node(w.Lbeg));
       A.f[c][k] = IO::ld(rz[c], o_f[k], s_node(w.Lbeg + 1));
     }
-  A.e = IO::ld(re, o_e, s_elem(w.Lbeg));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) A.e[a] = IO::ld(re[a], o_e, s_elem(w.Lbeg));
   IO::ld8(rc, o_cl(w.Lbeg), 8 * s_elem(w.Lbeg), A.c);
   double ahx, ahy, axy;
   w.weights(ahx, ahy, axy);
@@ -650,7 +656,8 @@ __device__ __forceinline__ void jv_tile_hm(const Geom& g, const WaveTile& w, int
       asm("" : "+v"(fb[c][k]));
       asm("" : "+v"(A.f[c][k]));
     }
-  asm("" : "+v"(A.e));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) asm("" : "+v"(A.e[a]));
 #pragma unroll
   for (int k = 0; k < 8; ++k) asm("" : "+v"(A.c[k]));
   double Tb[2][4], carH[2][4], carM[2][4];
@@ -670,12 +677,13 @@ __device__ __forceinline__ void jv_tile_hm(const Geom& g, const WaveTile& w, int
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int k = 0; k < 4; ++k) nxt.f[c][k] = IO::ld(rz[c], o_f[k], s_node(L + 2));
-      nxt.e = IO::ld(re, o_e, s_elem(L + 1));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) nxt.e[a] = IO::ld(re[a], o_e, s_elem(L + 1));
       __builtin_amdgcn_sched_barrier(0);
     }
     const bool lay_ok = L >= 0 && L <= g.nz - 2;
     const double hz = lay_ok ? lane_value(hzl, j) : 0.0, rhz = lay_ok ? lane_value(rdzl, j) : 0.0;
-    const double sx = cur.e * (ahx * hz), sy = cur.e * (ahy * hz), sz = cur.e * (axy * rhz);
+    const double sx = cur.e[0] * (ahx * hz), sy = cur.e[1] * (ahy * hz), sz = cur.e[2] * (axy * rhz);
     const double k2 = 1.0 / 16.0, k6 = 1.0 / 48.0, k18 = 1.0 / 144.0;
     const double d1 = sx * k2, d2 = sy * k2, d3 = (sx + sy) * k6, d4 = sz * k2, d5 = (sx + sz) * k6,
                  d6 = (sy + sz) * k6, d7 = (sx + sy + sz) * k18;

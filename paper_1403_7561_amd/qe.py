@@ -543,19 +543,25 @@ def qe_ohmic_potential(phys, N_D, N_A, V_a=0.0):
 def qe_schrodinger_solve(prob, inv_mass, v0, phi, n_states, fixed=None, tol=1e-8, maxit=500, seed=1,
                          want_psi2=True, ws=None, check=True, guess=None):
     """Lowest eigenpairs of the effective-mass Schrodinger problem on the
-    problem's mesh: V = v0_e - phi.  inv_mass, v0: per element (m0/m*, eV);
-    fixed: per node booleans (psi = 0) or None; guess: device [n, N] starting
-    vectors or None.  Returns (E [n] eV, psi [n, N], psi2 [n, N] or None,
-    iterations)."""
+    problem's mesh: V = v0_e - phi.  inv_mass: m0/m* per element, [E]
+    (isotropic) or [3, E] (along x, y, z: a diagonal mass tensor); v0: per
+    element (eV); fixed: per node booleans (psi = 0) or None; guess: device
+    [n, N] starting vectors or None.  Returns (E [n] eV, psi [n, N], psi2
+    [n, N] or None, iterations)."""
+    im_h = np.asarray(inv_mass, dtype=np.float64)
+    if im_h.shape == (prob.E,):
+        im_h = np.stack([im_h, im_h, im_h])
+    if im_h.shape != (3, prob.E):
+        raise ValueError(f"inv_mass: shape {im_h.shape}, expected ({prob.E},) or (3, {prob.E})")
     torch = _torch()
     lib = load_library()
     f64 = dict(dtype=torch.float64, device=prob.device)
-    im = torch.as_tensor(np.ascontiguousarray(inv_mass, dtype=np.float64), **f64)
+    im = torch.as_tensor(np.ascontiguousarray(im_h), **f64)
     vv = torch.as_tensor(np.ascontiguousarray(v0, dtype=np.float64), **f64)
     fx = None if fixed is None else torch.as_tensor(np.ascontiguousarray(fixed, dtype=np.uint8), device=prob.device)
     ph = phi if hasattr(phi, "data_ptr") else torch.as_tensor(np.ascontiguousarray(phi, dtype=np.float64), **f64)
     _dev(ph, torch.float64, prob.N, prob.device, "phi")
-    _dev(im, torch.float64, prob.E, prob.device, "inv_mass")
+    _dev(im, torch.float64, 3 * prob.E, prob.device, "inv_mass [3, E]")
     _dev(vv, torch.float64, prob.E, prob.device, "v0")
     if fx is not None:
         _dev(fx, torch.uint8, prob.N, prob.device, "fixed")

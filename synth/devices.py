@@ -425,19 +425,23 @@ def with_quantum(dev, states):
 
 
 SIO2_CB_OFFSET_EV = 3.1          # Si/SiO2 conduction-band offset
-M_SI_T, M_OX = 0.19, 0.5         # effective masses (m0): Si transverse, SiO2
+M_SI_T, M_SI_L, M_OX = 0.19, 0.98, 0.5   # effective masses (m0): Si transverse and longitudinal, SiO2
 
 
-def quantum_region(dev, box):
+def quantum_region(dev, box, isotropic=False):
     """Inputs of the Schrodinger step for a quantum region `box` (x0, x1, y0,
-    y1, z0, z1) nm of a gate stack: per-element m0/m* and conduction-band
-    edge at phi = 0 (Ec0 in Si, Ec0 + the band offset in the oxide), the
-    fixed nodes (psi = 0: every node not strictly inside the box) and the
-    region's elements (centroid strictly inside)."""
+    y1, z0, z1) nm of a gate stack: per-element m0/m* along x, y, z ([3, E]:
+    the Delta_2 valleys' m_t, m_t, m_l in Si with the interface normal to z,
+    isotropic in the oxide), the conduction-band edge at phi = 0 (Ec0 in Si,
+    Ec0 + the band offset in the oxide), the fixed nodes (psi = 0: every
+    node not strictly inside the box) and the region's elements (centroid
+    strictly inside).  isotropic=True gives m_t along every axis."""
     x0, x1, y0, y1, z0, z1 = box
     ox = np.asarray(dev.semi) == 0
     v0 = np.where(ox, dev.Ec0_eV + SIO2_CB_OFFSET_EV, dev.Ec0_eV).astype(np.float64)
-    inv_mass = np.where(ox, 1.0 / M_OX, 1.0 / M_SI_T).astype(np.float64)
+    m_z = M_SI_T if isotropic else M_SI_L
+    inv_mass = np.stack([np.where(ox, 1.0 / M_OX, 1.0 / M_SI_T), np.where(ox, 1.0 / M_OX, 1.0 / M_SI_T),
+                         np.where(ox, 1.0 / M_OX, 1.0 / m_z)]).astype(np.float64)
     Z, Y, X = np.meshgrid(dev.z, dev.y, dev.x, indexing="ij")
     inside = (X > x0) & (X < x1) & (Y > y0) & (Y < y1) & (Z > z0) & (Z < z1)
     xc, yc, zc = [0.5 * (c[1:] + c[:-1]) for c in (dev.x, dev.y, dev.z)]

@@ -321,3 +321,15 @@ def test_static_solve_rejects_a_problem_too_large_before_device_work():
     st = lib.qe_solve_static(ctypes.byref(p), ctypes.byref(qe.Physics().c()), ctypes.byref(o),
                              ctypes.c_void_p(8), None, None, ctypes.byref(rep))
     assert st == -3 and rep.status == -3 and "static workspace" in qe.qe_last_error()
+
+
+def test_schrodinger_masses_take_one_or_three_axes():
+    """qe_schrodinger_solve takes m0/m* as [E] (isotropic) or [3, E] (per
+    axis) and rejects any other shape before the library is called."""
+    import numpy as np
+    import torch
+    from types import SimpleNamespace
+    P = SimpleNamespace(E=10, N=30, device=torch.device("cpu"))
+    for bad in (np.ones((2, 10)), np.ones(30), np.ones((10, 3))):
+        with pytest.raises(ValueError, match="inv_mass"):
+            qe.qe_schrodinger_solve(P, bad, np.zeros(10), np.zeros(30), 2)

@@ -1,9 +1,12 @@
 """GPU parity of the effective-mass Schrodinger eigensolver (Sec. II.B, Eqs.
-SchrodEqn, SchrodEqnWeakForm) through the C ABI against the oracle's dense /
-shift-invert generalized eigenproblem on the same mesh and inputs: the 1D
-infinite well (exact discrete levels), an anisotropic 3D box, the finite
-well with unequal masses, and the gate-stack dot in the semiclassical
-potential; eigenvalues to 1e-9 relative, eigenvectors (up to sign, or their
+SchrodEqn, SchrodEqnWeakForm, with Eq. Schrodinger3D's per-axis masses)
+through the C ABI against the oracle's dense / shift-invert generalized
+eigenproblem on the same mesh and inputs: the 1D infinite well (exact
+discrete levels), a 3D box with isotropic, Si Delta_2 (m_t, m_t, m_l) and
+three distinct masses (also against the closed-form levels), the finite
+well with unequal masses, random per-axis masses on a corner of free nodes,
+and the gate-stack dot (Si masses m_t = 0.19, m_l = 0.98) in the
+semiclassical potential; eigenvalues to 1e-9 relative, eigenvectors (up to sign, or their
 projector within a cluster of equal levels) to 1e-8.  Then one closed
 predictor-corrector loop, run with the GPU solvers and with the oracle's,
 which must agree to 1e-9 relative in phi, the levels and the electrons.""" 
@@ -73,13 +76,26 @@ def test_infinite_well_column():
     compare(P, np.full(n, 1 / 0.19), np.zeros(n), np.zeros(P.N), fixed, 4)
 
 
-def test_three_dimensional_box():
+def lam1d(k, n, h):
+    # generalized eigenvalue k of the 1D linear-element well on n uniform
+    # elements of size h, both ends fixed
+    t = k * np.pi / n
+    return 6.0 * (1.0 - np.cos(t)) / (h * h * (2.0 + np.cos(t)))
+
+
+@pytest.mark.parametrize("masses", [(1.0, 1.0, 1.0), (0.19, 0.19, 0.98), (0.3, 0.5, 0.9)])
+def test_three_dimensional_box(masses):
     x, y, z = np.linspace(0, 12, 13), np.linspace(0, 8, 10), np.linspace(0, 6, 8)
     P = mesh_problem(x, y, z)
     Z, Y, X = np.meshgrid(np.arange(8), np.arange(10), np.arange(13), indexing="ij")
     fixed = ((X == 0) | (X == 12) | (Y == 0) | (Y == 9) | (Z == 0) | (Z == 7)).ravel()
     E_ = 12 * 9 * 7
-    compare(P, np.full(E_, 1.0), np.zeros(E_), np.zeros(P.N), fixed, 5)
+    im = np.stack([np.full(E_, 1.0 / m) for m in masses])
+    E, _, _ = compare(P, im, np.zeros(E_), np.zeros(P.N), fixed, 5)
+    levels = sorted(sch.HB2M * (lam1d(a, 12, 1.0) / masses[0] + lam1d(b, 9, 8.0 / 9) / masses[1]
+                                + lam1d(c, 7, 6.0 / 7) / masses[2])
+                    for a in range(1, 12) for b in range(1, 9) for c in range(1, 7))
+    assert np.allclose(E, levels[:5], rtol=1e-9)
 
 
 def test_finite_well_unequal_masses():
@@ -107,7 +123,7 @@ def test_free_nodes_in_a_corner():
     fixed = ~((X <= 6) & (Y >= 3) & (Z >= 1) & (Z <= 5)).ravel()
     E_ = 12 * 9 * 7
     rng = np.random.default_rng(3)
-    compare(P, 1.0 + rng.random(E_), 0.2 * rng.random(E_), 0.05 * rng.standard_normal(P.N), fixed, 4)
+    compare(P, 1.0 + rng.random((3, E_)), 0.2 * rng.random(E_), 0.05 * rng.standard_normal(P.N), fixed, 4)
 
 
 QBOX = (0.0, 70.0, 60.0, 140.0, 40.0, 100.0)   # quantum region around the plunger P1
@@ -150,12 +166,16 @@ def test_unconverged_solve_still_writes_the_states():
 def test_predictor_corrector_loop_closes():
     """The S-P loop of the predictor-corrector method (the four steps listed
     in Sec. II.C) on the GPU: semiclassical start, then alternately the
-    lowest states in V = E_C(phi^(k)) inside a quantum region around the
+    lowest states of Eq. Schrodinger3D (Si m_t = 0.19 along x and y, m_l =
+    0.98 along z) in V = E_C(phi^(k)) inside a quantum region around the
     plunger P1 (psi = 0 on its boundary, the semiclassical electrons outside
     it) and the predictor Poisson step with their density, until
     max |phi^(k) - phi^(k-1)| < 1e-5 V.  The same loop run with the oracle's
     eigenproblem and Newton solve reaches the same fixed point."""
-    volts = (1.5, 1.2, 0.6, 0.7, 0.5)           # a few electrons in the dot
+    # a few electrons in the dot, its lowest level 5 kT below E_F; the loop
+    # converges here (nearer a level crossing E_F, at 1.5 V on P1, both
+    # loops settle into the same two-cycle instead)
+    volts = (1.55, 1.2, 0.6, 0.7, 0.5)
     dev, phi0, inv_mass, v0, fixed = stack_dot(volts)
     reg = dot_region(dev)
     box = (0, 70, 60, 140, 40, 100)
