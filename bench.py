@@ -55,35 +55,116 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(dev, gpu_newton, budget_s=25.0):
-    """The oracle on the host: linear initial guess plus as many Newton steps
-    as fit in the budget (at least one), extrapolated to a full solve with the
-    GPU run's Newton step count."""
-    import numpy as np
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def _oracle_c3(k):
+    """One instance of the batched sweep solved by the oracle, single-threaded
+    (a pool worker)."""
+    from threadpoolctl import threadpool_limits
+    import synth
     from oracle import solver
-    t0 = time.perf_counter()
-    prob = solver.make_problem(dev)
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    phi = solver.initial_guess(prob, method="cg")
-    t_init = time.perf_counter() - t0
-    steps, t_steps = 0, 0.0
-    phi_k = phi
-    while steps < max(gpu_newton, 1):
+    with threadpool_limits(1):
+        dev = synth.config3_instance(k)
         t0 = time.perf_counter()
-        r = solver.newton(prob, phi0=phi_k, atol=1e-8, maxit=1, method="cg")
-        print(f"[bench] oracle Newton step {steps + 1}: {time.perf_counter() - t0:.1f} s",
-              file=sys.stderr, flush=True)
-        t_steps += time.perf_counter() - t0
-        phi_k = r.phi
-        steps += 1
-        if t_init + t_steps > budget_s:
-            break
-    est = t_setup + t_init + t_steps / steps * max(gpu_newton, 1)
-    return {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"c2 device: assembly + linear initial guess + {steps} Newton step(s) timed "
-                      f"({t_setup + t_init + t_steps:.1f} s), full solve extrapolated to "
-                      f"{gpu_newton} Newton steps = {est:.1f} s (scipy CSR/CG, single-threaded)"}
+        _, res = solver.solve(dev, atol=1e-8, method="cg")
+        return k, time.perf_counter() - t0, res.status, dev.n_nodes
+
+
+def cpu_measure(budget_s=25.0, full=False, c3_workers=None):
+    """The oracle on the host, before the GPU is initialised (the sweep's pool
+    forks): single-threaded c2 solve (a bounded sample unless full), its CSR
+    J.v, the small c1 solve, and a 16-instance subset of the c3 sweep over a
+    pool of worker processes."""
+    import multiprocessing as mp
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import synth
+    from oracle import solver
+    out = cpu_info()
+    with threadpool_limits(1):
+        dev1 = synth.config1()
+        t0 = time.perf_counter()
+        _, r1 = solver.solve(dev1, atol=1e-10)
+        out["c1_solve_s"] = time.perf_counter() - t0
+        dev = synth.config2()
+        t0 = time.perf_counter()
+        prob = solver.make_problem(dev)
+        t_setup = time.perf_counter() - t0
+        if full:
+            t0 = time.perf_counter()
+            r = solver.newton(prob, atol=1e-8, method="cg")
+            out.update(c2_setup_s=t_setup, c2_solve_s=time.perf_counter() - t0, c2_newton_steps=r.iters,
+                       c2_full=True)
+            phi_k = r.phi
+        else:
+            t0 = time.perf_counter()
+            phi_k = solver.initial_guess(prob, method="cg")
+            t_init = time.perf_counter() - t0
+            steps, t_steps = 0, 0.0
+            while True:
+                t0 = time.perf_counter()
+                r = solver.newton(prob, phi0=phi_k, atol=1e-8, maxit=1, method="cg")
+                dt = time.perf_counter() - t0
+                log(f"oracle Newton step {steps + 1}: {dt:.1f} s")
+                t_steps += dt
+                phi_k = r.phi
+                steps += 1
+                if r.status == "ok" or t_setup + t_init + t_steps > budget_s:
+                    break
+            out.update(c2_setup_s=t_setup, c2_init_s=t_init, c2_step_s=t_steps / steps, c2_steps_timed=steps,
+                       c2_full=False)
+        # the assembled Jacobian's CSR product (scipy), median of three
+        J = prob.jacobian_full(phi_k)
+        v = np.random.default_rng(0).standard_normal(J.shape[0])
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            J @ v
+            ts.append(time.perf_counter() - t0)
+        out["jv_csr_ms"] = [t * 1e3 for t in ts]
+        out["jv_csr_gdof_s"] = J.shape[0] / sorted(ts)[1] / 1e9
+        out["jv_csr_nnz"] = int(J.nnz)
+        del J, prob
+    workers = c3_workers or min(16, os.cpu_count() or 1)
+    ks = [17 * j for j in range(16)]          # the sweep's diagonal: P1 = P2 on the 16 grid points
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        done = pool.map(_oracle_c3, ks, chunksize=1)
+    wall = time.perf_counter() - t0
+    out["c3_subset"] = {"instances": ks, "workers": workers, "wall_s": wall, "solves_per_s": len(ks) / wall,
+                        "instance_s": [d[1] for d in done], "nodes": [d[3] for d in done],
+                        "all_ok": all(d[2] == "ok" for d in done)}
+    return out
+
+
+def cpu_baseline(m, gpu_newton):
+    """The c2 rate from the host measurement: a full solve, or the sample's
+    setup + initial guess + per-step time scaled to the GPU run's Newton
+    steps."""
+    if m["c2_full"]:
+        est = m["c2_setup_s"] + m["c2_solve_s"]
+        sample = (f"c2 device: full oracle solve, assembly {m['c2_setup_s']:.1f} s + {m['c2_newton_steps']} "
+                  f"Newton steps {m['c2_solve_s']:.1f} s")
+    else:
+        est = m["c2_setup_s"] + m["c2_init_s"] + m["c2_step_s"] * max(gpu_newton, 1)
+        sample = (f"c2 device: assembly {m['c2_setup_s']:.1f} s + linear initial guess {m['c2_init_s']:.1f} s + "
+                  f"{m['c2_steps_timed']} Newton step(s) timed at {m['c2_step_s']:.1f} s each, scaled to the "
+                  f"GPU run's {gpu_newton} Newton steps = {est:.1f} s (scipy CSR / Jacobi-CG)")
+    out = {"value": 1.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle", "sample": sample}
+    out.update({k: m[k] for k in ("cpu_count", "cpu_model", "c1_solve_s", "jv_csr_gdof_s", "jv_csr_ms",
+                                  "jv_csr_nnz", "c3_subset")})
+    return out
 
 
 def full_charge_run(synth, qe, torch, dev, opts, ws, boxes, jv_reps):
@@ -193,8 +274,16 @@ def schrodinger_run(synth, qe, torch, dev, P, opts, phi_sc):
     n_dot = qe.qe_count_electrons(Pq, phi_k, [box])[0]
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
+    # the loop's end state: converged, or settled into a two-cycle (every
+    # other outer step repeats: successive max |dphi| equal to 1e-3 over the
+    # last ten steps), or neither
+    tail = hist[-10:]
+    two_cycle = (hist[-1] >= 1e-5 and len(tail) == 10 and
+                 all(abs(tail[i] - tail[i + 2]) <= 1e-3 * tail[i] for i in range(8)))
+    state = "converged" if hist[-1] < 1e-5 else ("two-cycle" if two_cycle else "not converged")
     return {"eig8_ms": t_eig * 1e3, "eig8_lobpcg_iters": it, "E8_meV": [float(e * 1e3) for e in E],
-            "sp_loop_s": t_loop, "sp_outer_iters": len(hist), "sp_final_dphi_V": hist[-1],
+            "sp_loop_s": t_loop, "sp_outer_iters": len(hist), "sp_final_dphi_V": hist[-1], "sp_state": state,
+            "sp_dphi_history_V": hist,
             "sp_lobpcg_iters": lob, "sp_dot_electrons": float(n_dot),
             "sp_levels_meV": [float(e * 1e3) for e in E16[:4]]}
 
@@ -210,6 +299,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--jv-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true", help="time the whole c2 oracle solve (minutes)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -224,6 +314,12 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (before the GPU is initialised)")
+        cpu = cpu_measure(full=args.cpu_full)
+
     import torch
 
     import synth
@@ -290,6 +386,9 @@ def main():
                       "ms_fp64": ms64, "ms_fp32": ms32},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "cache_assisted": True,
+                     "note": "the 129x129x65 CG working set (~74 MB) fits in the 256 MB Infinity Cache; "
+                             "roofline_c5 (257x257x129, ~700 MB) is the HBM-bound figure",
                      "kernel": "k_cg_jv<double> (FP64 J.v of the CG loop with the direction update and the solution step)",
                      "bytes_per_launch": b64, "ms_per_launch": ms64,
                      "coef_elems": ncoef, "elems": dev.n_elems},
@@ -327,12 +426,37 @@ def main():
         _, cnt3, reps3 = qe.qe_solve_batch(P3, opts=opts, boxes=boxes, tune_cache=cache)
         torch.cuda.synchronize()
         tb3 = time.perf_counter() - t0
+        # the same 256 instances by the single-instance FP64 path, one after
+        # another (one workspace sized for the largest)
+        wsb = qe.Workspace(max(qe.qe_workspace_bytes(p, opts) for p in P3), P3[0].device)
+        qe.qe_solve(P3[0], opts=opts, ws=wsb, want_density=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cnt_seq = []
+        for p in P3:
+            ph, _, _ = qe.qe_solve(p, opts=opts, ws=wsb, want_density=False)
+            cnt_seq.append(qe.qe_count_electrons(p, ph, boxes, ws=wsb))
+        torch.cuda.synchronize()
+        ts3 = time.perf_counter() - t0
+        cnt3 = np.asarray(cnt3, dtype=np.float64)
+        cnt_seq = np.asarray(cnt_seq, dtype=np.float64)
+        grid = cnt3.reshape(16, 16, 2)            # [P1 index, P2 index, dot]
         out["batch_c3"] = {"solves_per_s": len(P3) / tb3, "ms": tb3 * 1e3, "n_inst": len(P3),
                            "dof_total": int(sum(p.N for p in P3)),
                            "all_converged": all(r["status"] == 0 for r in reps3),
                            "max_res_final": max(r["res_final"] for r in reps3),
-                           "dot_electrons_first": [float(x) for x in cnt3[0]]}
-        del P3, devs3
+                           "sequential_solves_per_s": len(P3) / ts3, "sequential_ms": ts3 * 1e3,
+                           "speedup_vs_sequential": ts3 / tb3,
+                           "counts_max_rel_diff_vs_sequential":
+                               float(np.abs(cnt3 - cnt_seq).max() / max(np.abs(cnt_seq).max(), 1e-300)),
+                           "dot_electrons": {
+                               "plunger_grid_V": [float(v) for v in synth.PLUNGER_GRID],
+                               "D1_by_P1": [float(x) for x in grid[:, :, 0].mean(axis=1)],
+                               "D2_by_P2": [float(x) for x in grid[:, :, 1].mean(axis=0)],
+                               "max": [float(cnt3[:, 0].max()), float(cnt3[:, 1].max())],
+                               "instances_with_an_electron": [int((cnt3[:, 0] > 0.5).sum()),
+                                                              int((cnt3[:, 1] > 0.5).sum())]}}
+        del P3, devs3, wsb
     if not args.no_mixed:
         log("mixed precision at 257x257x129")
         dev5 = synth.config5()
@@ -381,9 +505,8 @@ def main():
     if not args.no_schrodinger:
         log("Schrodinger states and the predictor-corrector loop")
         out["schrodinger_c2"] = schrodinger_run(synth, qe, torch, dev, P, opts, phi)
-    log("cpu baseline")
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(dev, reps[-1]["newton_iters"])
+    if cpu is not None:
+        out["cpu_baseline"] = cpu_baseline(cpu, reps[-1]["newton_iters"])
     print(json.dumps(out), flush=True)
 
 

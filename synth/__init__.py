@@ -18,6 +18,7 @@ from .devices import (  # noqa: F401
     stack_z,
     make_stack_device,
     double_dot_gates,
+    PLUNGER_GRID,
     double_dot_device,
     config1,
     config2,
