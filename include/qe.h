@@ -197,7 +197,7 @@ typedef struct {
   int32_t init_guess;            /* 0: linear (charge-free) Poisson solve;
                                     1: start from the phi passed in */
   int32_t check_every;           /* CG iterations the host keeps queued beyond
-                                    those known to have finished (0 = 12;
+                                    those known to have finished (0 = 9;
                                     clamped to [9, 56]) */
 } qe_options;
 
