@@ -64,12 +64,16 @@ void launch_cast_d2f(hipStream_t s, int nblocks, long n, const double* a, float*
 void launch_masked_copy_d2d(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, double* b);
 void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, float* b);
 WaveMap make_wavemap(int nx, int ny, int nz, int kz);
-void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
-                          const uint8_t* semi, const Doping& dop, const uint8_t* mask, const double* phi,
-                          const double* delta64, const float* delta32, double lam, const double* fsheet,
-                          const double* fdiag, double* F, double* invdiag, double* diag_out, double* cq, float* cq32,
-                          uint8_t* cflag, unsigned int* cbits, float* invdiag32, double* partial, double* norm2,
-                          const Quantum& qm);
+// The residual with eigenstates (qm.n > 0) runs on the wave map wmq (shorter
+// chunks: the states' loop makes the waves over the dot the slowest) and
+// leaves the J.v lanes' coefficient flags (cbits, wave map wm) to a pass
+// over the owners' element flags.
+void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const WaveMap& wmq, const Charge& ch,
+                          const double* eps, const uint8_t* semi, const Doping& dop, const uint8_t* mask,
+                          const double* phi, const double* delta64, const float* delta32, double lam,
+                          const double* fsheet, const double* fdiag, double* F, double* invdiag, double* diag_out,
+                          double* cq, float* cq32, uint8_t* cflag, unsigned int* cbits, float* invdiag32,
+                          double* partial, double* norm2, const Quantum& qm);
 // y = J v with v read as 0 on Dirichlet nodes (identity_rows: y_i = v_i there).
 void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const unsigned int* cbits,
                       const double* cq, const uint8_t* mask, const double* v, double* y, int identity_rows);

@@ -228,10 +228,19 @@ __device__ __forceinline__ void residual_wave(
   int wx, wy, wz, wid;
   bool active;
   wave_coords(wm, wx, wy, wz, active, wid);
+  if constexpr (kQ) {
+    // the waves whose chunks hold the states' support loop over the states
+    // and take longest: the chunk order is rotated so that they come first
+    // in block order and start at once
+    int zlo = 0x7fffffff;
+    for (int i = 0; i < qm.n; ++i) zlo = min(zlo, qm.sbox[6 * i + 4]);
+    if (zlo != 0x7fffffff) wz = (wz + max(zlo - 1, 0) / wm.kz) % wm.gz;
+  }
   const WaveTile w(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   double acc = 0.0;
   residual_tile<TD, kQ>(g, w, ch, eps, semi, dop, mask, phi, delta, lam, fsheet, fdiag, F, invdiag, diag_out, cq, cq32,
-                        cflag, active ? cbits + 64L * wid + (threadIdx.x & 63) : nullptr, invdiag32, acc, &qm);
+                        cflag, (active && cbits) ? cbits + 64L * wid + (threadIdx.x & 63) : nullptr, invdiag32,
+                        acc, &qm);
   const double d = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = d;
   __syncthreads();
@@ -945,40 +954,73 @@ __global__ __launch_bounds__(64) void k_state_boxes_init(int n, int* __restrict_
   }
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_state_boxes(Geom g, Quantum qm, int* __restrict__ box) {
-  const long N = (long)g.nx * g.ny * g.nz;
-  for (int st = 0; st < qm.n; ++st) {
-    int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
-    for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
-      if (qm.psi2[qm.N * st + n] != 0.0) {
-        const int c[3] = {(int)(n % g.nx), (int)((n / g.nx) % g.ny), (int)(n / ((long)g.nx * g.ny))};
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          lo[a] = min(lo[a], c[a]);
-          hi[a] = max(hi[a], c[a]);
-        }
+__global__ __launch_bounds__(256) void k_state_boxes(Geom g, Quantum qm, int* __restrict__ box) {
+  // one wave per x row (j, k) of state blockIdx.y, rows strided over the
+  // grid's waves; lanes step along x, so the reads are coalesced and the
+  // only index arithmetic is per row
+  const int st = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const long rows = (long)g.ny * g.nz;
+  const long wave0 = (long)blockIdx.x * 4 + (threadIdx.x >> 6), nwav = (long)gridDim.x * 4;
+  const double* ps = qm.psi2 + qm.N * st;
+  int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
+  for (long r = wave0; r < rows; r += nwav) {
+    const int j = (int)(r % g.ny), k = (int)(r / g.ny);
+    const double* row = ps + r * g.nx;
+    bool any = false;
+    for (int i = lane; i < g.nx; i += 64) {
+      if (row[i] != 0.0) {
+        lo[0] = min(lo[0], i);
+        hi[0] = max(hi[0], i);
+        any = true;
       }
     }
+    if (any) {
+      lo[1] = min(lo[1], j);
+      hi[1] = max(hi[1], j);
+      lo[2] = min(lo[2], k);
+      hi[2] = max(hi[2], k);
+    }
+  }
+  // wave, then block minima / maxima; one set of atomics per block (the
+  // grid keeps few blocks per state, so they do not queue on one address)
+  __shared__ int sb[4][6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[a] = min(lo[a], __shfl_down(lo[a], off, 64));
+      hi[a] = max(hi[a], __shfl_down(hi[a], off, 64));
+    }
+  }
+  if (lane == 0)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      for (int off = 32; off > 0; off >>= 1) {
-        lo[a] = min(lo[a], __shfl_down(lo[a], off, 64));
-        hi[a] = max(hi[a], __shfl_down(hi[a], off, 64));
-      }
+      sb[threadIdx.x >> 6][2 * a] = lo[a];
+      sb[threadIdx.x >> 6][2 * a + 1] = hi[a];
     }
-    if ((threadIdx.x & 63) == 0 && hi[0] >= 0) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = min(min(sb[0][2 * a], sb[1][2 * a]), min(sb[2][2 * a], sb[3][2 * a]));
+      hi[a] = max(max(sb[0][2 * a + 1], sb[1][2 * a + 1]), max(sb[2][2 * a + 1], sb[3][2 * a + 1]));
+    }
+    if (hi[0] >= 0)
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         atomicMin(box + 6 * st + 2 * a, lo[a]);
         atomicMax(box + 6 * st + 2 * a + 1, hi[a]);
       }
-    }
   }
 }
 
 void launch_state_boxes(hipStream_t s, int nblocks, const Geom& g, const Quantum& qm, int* box) {
   QE_LAUNCH(k_state_boxes_init, 1, 64, s, qm.n, box);
-  QE_LAUNCH(k_state_boxes, nblocks, kVecThreads, s, g, qm, box);
+  // 64 blocks per state: 256 waves over the state's rows
+  const long rows = (long)g.ny * g.nz;
+  const int bx = (int)std::max(1L, std::min((rows + 3) / 4, 64L));
+  (void)nblocks;
+  hipLaunchKernelGGL(k_state_boxes, dim3(bx, qm.n), dim3(256), 0, s, g, qm, box);
 }
 
 void launch_validate_quantum(hipStream_t s, int nblocks, const Quantum& qm, int* flags) {
@@ -1011,26 +1053,45 @@ void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* m
   QE_LAUNCH((k_masked_copy<double, float>), nblocks, kVecThreads, s, n, mask, a, b);
 }
 
-void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const Charge& ch, const double* eps,
-                          const uint8_t* semi, const Doping& dop, const uint8_t* mask, const double* phi,
-                          const double* delta64, const float* delta32, double lam, const double* fsheet,
-                          const double* fdiag, double* F, double* invdiag, double* diag_out, double* cq, float* cq32,
-                          uint8_t* cflag, unsigned int* cbits, float* invdiag32, double* partial, double* norm2,
-                          const Quantum& qm) {
+// J.v lanes' coefficient flags from the owners' element flags: bit L - Lbeg
+// of a lane is set when its column's element of layer L has a nonzero c_q.
+__global__ __launch_bounds__(256) void k_cbits_from_cflag(Geom g, WaveMap wm, const uint8_t* __restrict__ cflag,
+                                                         unsigned int* __restrict__ cbits) {
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= wm.nwaves) return;
+  int wx, wy, wz;
+  wave_tile_of(w, wm, wx, wy, wz);
+  const WaveTile t(g, wx, wy, wz, wm.kz, threadIdx.x & 63, true);
+  unsigned int b = 0;
+  if (t.col_ok) {
+    const int lo = max(t.Lbeg, 0), hi = min(t.Lend, g.nz - 2);
+    for (int L = lo; L <= hi; ++L)
+      if (cflag[t.slot(L)]) b |= 1u << (L - t.Lbeg);
+  }
+  cbits[64L * w + (threadIdx.x & 63)] = b;
+}
+
+void launch_residual_wave(hipStream_t s, const Geom& g, const WaveMap& wm, const WaveMap& wmq, const Charge& ch,
+                          const double* eps, const uint8_t* semi, const Doping& dop, const uint8_t* mask,
+                          const double* phi, const double* delta64, const float* delta32, double lam,
+                          const double* fsheet, const double* fdiag, double* F, double* invdiag, double* diag_out,
+                          double* cq, float* cq32, uint8_t* cflag, unsigned int* cbits, float* invdiag32,
+                          double* partial, double* norm2, const Quantum& qm) {
   const bool q = qm.n > 0;
   if (delta32 && q)
-    QE_LAUNCH((k_residual_wave_q<float>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam,
-              fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
+    QE_LAUNCH((k_residual_wave_q<float>), wmq.nblocks, 256, s, g, wmq, ch, eps, semi, dop, mask, phi, delta32, lam,
+              fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, nullptr, invdiag32, partial, qm);
   else if (delta32)
     QE_LAUNCH((k_residual_wave<float>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta32, lam,
               fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
   else if (q)
-    QE_LAUNCH((k_residual_wave_q<double>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam,
-              fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
+    QE_LAUNCH((k_residual_wave_q<double>), wmq.nblocks, 256, s, g, wmq, ch, eps, semi, dop, mask, phi, delta64, lam,
+              fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, nullptr, invdiag32, partial, qm);
   else
     QE_LAUNCH((k_residual_wave<double>), wm.nblocks, 256, s, g, wm, ch, eps, semi, dop, mask, phi, delta64, lam,
               fsheet, fdiag, F, invdiag, diag_out, cq, cq32, cflag, cbits, invdiag32, partial, qm);
-  QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, wm.nblocks, norm2);
+  if (q) QE_LAUNCH(k_cbits_from_cflag, wm.nblocks, 256, s, g, wm, cflag, cbits);
+  QE_LAUNCH(k_sum_partials, 1, kVecThreads, s, partial, q ? wmq.nblocks : wm.nblocks, norm2);
 }
 
 void launch_jv_wave64(hipStream_t s, const Geom& g, const WaveMap& wm, const double* eps, const unsigned int* cbits,

@@ -48,7 +48,7 @@ struct Layout {
   size_t total;
 };
 Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int nblocks_tile, int vblocks,
-                   int n_dir, long sheet_slots);
+                   int n_dir, long sheet_slots, long nwaves_q);
 long sheet_slots(const qe_problem* p);
 qe_status make_quantum(const qe_problem* p, const Charge& ch, Quantum& Q);
 SheetSet make_sheets(const qe_problem* p, std::vector<int4>& items);
@@ -59,6 +59,7 @@ struct Context {
   Geom g;
   TileMap tm;
   WaveMap wm;
+  WaveMap wmq;   // the residual with eigenstates (wm without them)
   SheetSet sheets{};
   Quantum quantum{};
   static constexpr int kEventRing = 8;

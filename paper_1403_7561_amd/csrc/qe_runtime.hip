@@ -181,10 +181,16 @@ static int env_int(const char* name, int dflt) {
 }
 
 static const int kCountBlocks = 256;
+
+// Chunk height of the residual with eigenstates (QE_Q_KZ overrides it).
+static const int kQResidualKz = 4;
+static WaveMap quantum_wavemap(const qe_problem* p) {
+  return make_wavemap(p->nx, p->ny, p->nz, std::max(1, env_int("QE_Q_KZ", kQResidualKz)));
+}
 static const int kContactBlocks = 256;
 
 Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int nblocks_tile, int vblocks,
-                   int n_dir, long sheet_slots) {
+                   int n_dir, long sheet_slots, long nwaves_q) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -220,6 +226,7 @@ Layout make_layout(long N, long E, long nslots, long nz_elems, long nwaves, int 
   long np = std::max<long>(nblocks_tile, 2L * vblocks);
   np = std::max<long>(np, (long)N / 64 + 64);   // wave-tiled J.v: one partial per block
   np = std::max<long>(np, (nwaves + 3) / 4 + kSheetBlocks);   // ... then the Robin faces' partials
+  np = std::max<long>(np, (nwaves_q + 3) / 4);                 // the residual with eigenstates
   np = std::max<long>(np, (long)kCountBlocks * kMaxBoxes);
   np = std::max<long>(np, (long)kContactBlocks * std::max(1, n_dir));
   L.n_partial = np;
@@ -449,9 +456,13 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   g.z = p->z;
   tm = make_tilemap(p->nx, p->ny, p->nz, kz);
   wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
+  // with eigenstates the waves over the dot loop over every state on each of
+  // their layers; chunks of kQResidualKz layers shorten that critical path
+  wmq = quantum.n > 0 ? quantum_wavemap(p) : wm;
   vblocks = vec_blocks(N);
   nslots = tile_slots(p->nx, p->ny, p->nz);
-  lay = make_layout(N, E, nslots, p->nz - 1, wm.nwaves, tm.nblocks, vblocks, p->n_dir, sheet_slots(p));
+  lay = make_layout(N, E, nslots, p->nz - 1, wm.nwaves, tm.nblocks, vblocks, p->n_dir, sheet_slots(p),
+                    quantum.n > 0 ? wmq.nwaves : 0);
   if (!ws_) return fail(QE_ERR_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws_) & 255) return fail(QE_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (ws_bytes < lay.total)
@@ -536,7 +547,7 @@ qe_status Context::residual(const Charge& ch, const double* phi, const double* d
                             bool mixed, double* diag_out, double* norm2_host) {
   const bool sh = sheets.n > 0;
   if (sh) launch_sheet_residual(s, sheets, sheet_items(), ch.kappa, u8(lay.mask), phi, d64, d32, lam, f64(lay.fsheet), f64(lay.fdiag));
-  launch_residual_wave(s, g, wm, ch, prob.eps_r, prob.semi, doping(), u8(lay.mask), phi, d64, d32, lam,
+  launch_residual_wave(s, g, wm, wmq, ch, prob.eps_r, prob.semi, doping(), u8(lay.mask), phi, d64, d32, lam,
                        sh ? f64(lay.fsheet) : nullptr, sh ? f64(lay.fdiag) : nullptr, f64(lay.F), f64(lay.invdiag), diag_out, f64(lay.c), mixed ? f32(lay.c32) : nullptr,
                        u8(lay.cflag), u32(lay.cbits), mixed ? f32(lay.invdiag32) : nullptr, f64(lay.partial),
                        f64(lay.scal), quantum);
@@ -739,8 +750,9 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
   // the tile map with the smallest chunk height has the most blocks
   TileMap tm = make_tilemap(p->nx, p->ny, p->nz, 1);
   const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
+  const long nwq = p->quantum ? quantum_wavemap(p).nwaves : 0;
   return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), p->nz - 1, wm.nwaves, tm.nblocks, vec_blocks(N),
-                     p->n_dir, sheet_slots(p)).total;
+                     p->n_dir, sheet_slots(p), nwq).total;
 }
 
 const char* qe_last_error(void) { return g_last_error.c_str(); }
