@@ -19,7 +19,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1403_7561_amd/csrc/qe_device.h", "paper_1403_7561_amd/csrc/qe_tiles.h",
                   "paper_1403_7561_amd/csrc/qe_kernels.hip"]
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cg_jv_c2_hbm_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cg_loop_traffic.md")
 METRIC = "GDOF/s of nonlinear-Poisson J·v; solves/s at ‖F‖<1e-8; adjoint/forward time"
 
 
@@ -42,17 +42,19 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per J.v launch from the committed counter summary, or None if
-    the kernel sources changed since the counters were taken."""
+def measured_traffic(key):
+    """Counter-measured bytes per launch of a CG-loop kernel (key such as
+    "k_cg_jv<double>.c5") from the committed summary, or None if the kernel
+    sources changed since the counters were taken."""
     try:
         text = open(TRAFFIC_SUMMARY).read()
     except OSError:
         return None
-    fields = dict(ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("source_hash:", "traffic_bytes_per_launch:")))
-    if fields.get("source_hash", "").strip() != kernel_source_hash():
+    fields = dict((a.strip(), b.strip()) for a, b in
+                  (ln.split(":", 1) for ln in text.splitlines() if ln.startswith(("source_hash:", "traffic."))))
+    if fields.get("source_hash") != kernel_source_hash() or "traffic." + key not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields["traffic." + key])
 
 
 def cpu_info():
@@ -385,7 +387,7 @@ def main():
         "jv_gdof_s": {"fp64": P.N / (ms64 * 1e-3) / 1e9, "fp32": P.N / (ms32 * 1e-3) / 1e9,
                       "ms_fp64": ms64, "ms_fp32": ms32},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("k_cg_jv<double>.c2"),
                      "cache_assisted": True,
                      "note": "the 129x129x65 CG working set (~74 MB) fits in the 256 MB Infinity Cache; "
                              "roofline_c5 (257x257x129, ~700 MB) is the HBM-bound figure",
@@ -477,12 +479,19 @@ def main():
         ms5_64, nc5_64 = qe.qe_time_jv(P5, res["fp64"][1], v5, "fp64", args.jv_reps, ws=ws5)
         ms5_32, nc5_32 = qe.qe_time_jv(P5, res["fp64"][1], v5, "mixed", args.jv_reps, ws=ws5)
         b5_64, b5_32 = jv_bytes(dev5, 8, nc5_64), jv_bytes(dev5, 4, nc5_32)
+        t5_64, t5_32 = measured_traffic("k_cg_jv<double>.c5"), measured_traffic("k_cg_jv<float>.c5")
         out["roofline_c5"] = {"bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "achieved": b5_64 / (ms5_64 * 1e-3) / 1e9,
                               "frac": b5_64 / (ms5_64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "bytes_per_launch": b5_64, "ms_per_launch": ms5_64, "coef_elems": nc5_64,
-                              "fp32": {"achieved": b5_32 / (ms5_32 * 1e-3) / 1e9,
+                              "traffic": t5_64,
+                              "traffic_frac": None if t5_64 is None else t5_64 / (ms5_64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "kernel": "k_cg_jv<double>", "bytes_per_launch": b5_64, "ms_per_launch": ms5_64,
+                              "coef_elems": nc5_64,
+                              "fp32": {"kernel": "k_cg_jv<float>", "achieved": b5_32 / (ms5_32 * 1e-3) / 1e9,
                                        "frac": b5_32 / (ms5_32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                       "traffic": t5_32,
+                                       "traffic_frac": None if t5_32 is None else
+                                       t5_32 / (ms5_32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                        "bytes_per_launch": b5_32, "ms_per_launch": ms5_32},
                               "gdof_s": {"fp64": P5.N / (ms5_64 * 1e-3) / 1e9, "fp32": P5.N / (ms5_32 * 1e-3) / 1e9}}
         d = (res["mixed"][1] - res["fp64"][1]).abs().max().item() / res["fp64"][1].abs().max().item()
