@@ -195,7 +195,8 @@ typedef struct {
   int32_t krylov_maxit;          /* CG iterations per linear solve, >= 1 */
   int32_t precision;             /* qe_precision */
   int32_t init_guess;            /* 0: linear (charge-free) Poisson solve;
-                                    1: start from the phi passed in */
+                                    1: start from the phi passed in;
+                                    2: coarse-mesh sequence (see qe_solve) */
   int32_t check_every;           /* CG iterations the host keeps queued beyond
                                     those known to have finished (0 = 9;
                                     clamped to [9, 56]) */
@@ -210,10 +211,12 @@ typedef struct {
   int32_t n_residual_evals;
   double res0;                   /* ||F_free|| at the first Newton iterate */
   double res_final;              /* ||F_free|| at the returned phi */
+  int32_t seq_levels;            /* coarse meshes solved for the initial guess
+                                    (init_guess = 2), 0 for the linear guess */
 } qe_report;
 
 /* Fill `o` with defaults (atol 1e-8, 100 Newton steps, 30 halvings, forcing
- * cap 0.3, 20000 CG iterations, FP64, linear initial guess).  The forcing
+ * cap 0.3, 20000 CG iterations, FP64, coarse-mesh sequence).  The forcing
  * term is eta_k = min(cap, 0.9 (|F_k| / |F_k-1|)^2) (Eisenstat-Walker), and
  * the linear initial guess is solved to a relative CG residual of 1e-2. */
 void qe_default_options(qe_options* o);
@@ -225,7 +228,19 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o);
  * search, Newton update).  phi: device [N]; on entry the guess when
  * init_guess = 1 (its Dirichlet entries are overwritten), on return the
  * solution.  n_nodal: device [N] or NULL; receives n(phi_i) at nodes that
- * touch a semiconductor element, 0 elsewhere.  rep: host, may be NULL. */
+ * touch a semiconductor element, 0 elsewhere.  rep: host, may be NULL.
+ * The paper leaves Newton's start open (Sec. II.A.3).  With init_guess = 2
+ * a mesh of at least 400000 nodes without sheets or eigenstates is first
+ * coarsened (every other node along each axis, the last one kept; each
+ * coarse element takes the materials of its first fine element), that
+ * problem is solved from the linear guess until ||F|| falls to a fraction
+ * 1e-3 (139425 / N_coarse)^(2/3) of its initial value (the coarse mesh's
+ * error against this one falls as h^2), and its potential, interpolated
+ * trilinearly, starts Newton here; the solution is the same (the discrete problem has one
+ * solution), only the iteration counts change.  Smaller meshes, sheets,
+ * eigenstates, a coarse solve that fails, or a workspace without room for
+ * the coarse levels (qe_workspace_bytes counts them) take the linear
+ * guess. */
 qe_status qe_solve(const qe_problem* p, const qe_physics* ph, const qe_options* o,
                    double* phi, double* n_nodal, void* ws, size_t ws_bytes,
                    void* stream, qe_report* rep);

@@ -462,7 +462,9 @@ qe_status qe_solve_batch(int32_t n_inst, const qe_problem* probs, const qe_physi
   qe_status st;
   if ((st = check_options(o)) != QE_OK) return st;
   if (o->precision != QE_PREC_FP64) return fail(QE_ERR_INVALID_ARG, "the batched solve runs in FP64");
-  if (o->init_guess != 0) return fail(QE_ERR_INVALID_ARG, "the batched solve starts from the linear guess");
+  // every instance starts from the linear guess (a coarse-mesh sequence is
+  // for meshes far larger than the sweep's)
+  if (o->init_guess == 1) return fail(QE_ERR_INVALID_ARG, "the batched solve starts from the linear guess");
   Charge ch;
   if ((st = make_charge(ph, ch)) != QE_OK) return st;
   if (n_boxes < 0 || n_boxes > kMaxBoxes) return fail(QE_ERR_INVALID_ARG, "n_boxes must be in [0, %d]", kMaxBoxes);

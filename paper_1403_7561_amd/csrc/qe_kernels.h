@@ -1,6 +1,7 @@
 // Kernel-side types and host launchers of the Q1 nonlinear-Poisson path.
 #pragma once
 
+#include "../../include/qe.h"
 #include "qe_device.h"
 
 namespace qe {
@@ -63,6 +64,11 @@ void launch_stage_rdz(hipStream_t s, int nz, const double* z, double* rdz);
 void launch_cast_d2f(hipStream_t s, int nblocks, long n, const double* a, float* b);
 void launch_masked_copy_d2d(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, double* b);
 void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* mask, const double* a, float* b);
+// Coarse-mesh sequence: the coarse problem's coordinates, materials and
+// Dirichlet ids from the fine one (c's arrays are device memory the caller
+// owns), and the coarse potential interpolated onto the fine nodes.
+void launch_seq_coarsen(hipStream_t s, const qe_problem* f, const qe_problem* c);
+void launch_seq_prolong(hipStream_t s, const qe_problem* f, const qe_problem* c, const double* phic, double* phif);
 WaveMap make_wavemap(int nx, int ny, int nz, int kz);
 // The residual with eigenstates (qm.n > 0) runs on the wave map wmq (shorter
 // chunks: the states' loop makes the waves over the dot the slowest) and

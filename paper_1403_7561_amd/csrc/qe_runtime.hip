@@ -179,6 +179,14 @@ static int env_int(const char* name, int dflt) {
   const char* v = getenv(name);
   return v ? atoi(v) : dflt;
 }
+static long env_long(const char* name, long dflt) {
+  const char* v = getenv(name);
+  return v ? atol(v) : dflt;
+}
+static double env_double(const char* name, double dflt) {
+  const char* v = getenv(name);
+  return v ? atof(v) : dflt;
+}
 
 static const int kCountBlocks = 256;
 
@@ -385,7 +393,7 @@ qe_status check_options(const qe_options* o) {
   if (!(o->krylov_rtol_max > 0 && o->krylov_rtol_max < 1)) return fail(QE_ERR_INVALID_ARG, "krylov_rtol_max not in (0,1)");
   if (o->krylov_maxit < 1) return fail(QE_ERR_INVALID_ARG, "krylov_maxit < 1");
   if (o->precision != QE_PREC_FP64 && o->precision != QE_PREC_MIXED) return fail(QE_ERR_INVALID_ARG, "bad precision");
-  if (o->init_guess != 0 && o->init_guess != 1) return fail(QE_ERR_INVALID_ARG, "bad init_guess");
+  if (o->init_guess < 0 || o->init_guess > 2) return fail(QE_ERR_INVALID_ARG, "bad init_guess");
   if (o->check_every < 0) return fail(QE_ERR_INVALID_ARG, "check_every < 0");
   return QE_OK;
 }
@@ -701,6 +709,10 @@ qe_status Context::pcg_polled(bool mixed, const double* b, double sign, double r
 
 using namespace qe;
 
+static size_t fine_layout_bytes(const qe_problem* p);
+static size_t seq_extra_bytes(const qe_problem* p, int levels);
+static int seq_levels_wanted();
+
 // ====================================================================== C ABI
 // ------------------------------------------------------------------ contacts
 // eta with F_1/2(eta) ~= u: the Nilsson inverse of Eq. FDintInverse (the
@@ -738,13 +750,20 @@ void qe_default_options(qe_options* o) {
   o->krylov_rtol_max = 0.3;
   o->krylov_maxit = 20000;
   o->precision = QE_PREC_FP64;
-  o->init_guess = 0;
+  o->init_guess = 2;
   o->check_every = 0;
 }
 
 size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
   (void)o;
   if (check_problem(p) != QE_OK) return 0;
+  return fine_layout_bytes(p) + seq_extra_bytes(p, seq_levels_wanted());
+}
+
+}  // extern "C"
+
+// The largest layout any Context::init takes for this problem (checked).
+static size_t fine_layout_bytes(const qe_problem* p) {
   const long N = (long)p->nx * p->ny * p->nz;
   const long E = (long)(p->nx - 1) * (p->ny - 1) * (p->nz - 1);
   // the tile map with the smallest chunk height has the most blocks
@@ -754,6 +773,82 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
   return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), p->nz - 1, wm.nwaves, tm.nblocks, vec_blocks(N),
                      p->n_dir, sheet_slots(p), nwq).total;
 }
+
+// ---------------------------------------------------------------------------
+// Coarse-mesh sequence (init_guess = 2).  The problem coarsened by taking
+// every other node along each axis (the last node kept) is solved first, to
+// the relative residual seq_rtol (from its linear guess, or a further level
+// when QE_SEQ_LEVELS asks for more than one), and its potential, interpolated
+// trilinearly, starts Newton here.  Only for
+// meshes of at least kSeqMinNodes nodes (below, a solve is launch- rather
+// than bandwidth-bound and the coarse solve costs about as much as it saves)
+// without sheets or eigenstates; otherwise, or when the workspace has no room
+// for the coarse levels, the linear guess.  The coarse arrays and the coarse
+// solve's workspace follow the fine layout in the caller's workspace.
+static const long kSeqMinNodes = 400000;
+static const int kSeqLevels = 1;
+
+// The coarse solve need not be more accurate than the coarse mesh's own
+// error against the fine one, which falls as h^2: 1e-3 for a coarse mesh of
+// 139,425 nodes (the 129x129x65 problem's), scaled by (139425 / N_c)^(2/3).
+// Measured at 129x129x65: 1e-2 / 3e-3 / 1e-3 / 1e-4 gave 20.1 / 19.2 / 17.9 /
+// 18.7 ms; at 257x257x129 (coarse 1.08M nodes): 1e-3 / 1e-4 gave 269 / 245 ms.
+static double seq_rtol(long n_coarse) {
+  const double r = 1e-3 * std::pow(139425.0 / (double)n_coarse, 2.0 / 3.0);
+  return env_double("QE_SEQ_RTOL", std::min(1e-2, std::max(1e-5, r)));
+}
+
+struct SeqPlan {
+  qe_problem pc;       // the coarse problem (device pointers into the plan's region)
+  size_t o_phi, o_ws, total;
+};
+
+static bool seq_plan(const qe_problem* p, char* base, SeqPlan& sp, int levels) {
+  if (levels < 1 || p->n_sheets > 0 || p->quantum) return false;
+  const long N = (long)p->nx * p->ny * p->nz;
+  if (N < env_long("QE_SEQ_MIN_NODES", kSeqMinNodes)) return false;
+  qe_problem& c = sp.pc;
+  c = *p;
+  c.nx = p->nx / 2 + 1;
+  c.ny = p->ny / 2 + 1;
+  c.nz = p->nz / 2 + 1;
+  if (c.nx < 3 || c.ny < 3 || c.nz < 3 || c.nx >= p->nx || c.ny >= p->ny || c.nz >= p->nz) return false;
+  const long Nc = (long)c.nx * c.ny * c.nz, Ec = (long)(c.nx - 1) * (c.ny - 1) * (c.nz - 1);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off = align256(off + b);
+    return o;
+  };
+  c.x = reinterpret_cast<const double*>(base + take(c.nx * 8));
+  c.y = reinterpret_cast<const double*>(base + take(c.ny * 8));
+  c.z = reinterpret_cast<const double*>(base + take(c.nz * 8));
+  c.eps_r = reinterpret_cast<const double*>(base + take(Ec * 8));
+  c.semi = reinterpret_cast<const uint8_t*>(base + take(Ec));
+  c.net_doping = p->net_doping ? reinterpret_cast<const double*>(base + take(Ec * 8)) : nullptr;
+  c.donors = p->donors ? reinterpret_cast<const double*>(base + take(Ec * 8)) : nullptr;
+  c.acceptors = p->acceptors ? reinterpret_cast<const double*>(base + take(Ec * 8)) : nullptr;
+  c.dir_id = reinterpret_cast<const int32_t*>(base + take(Nc * 4));
+  c.n_sheets = 0;
+  c.sheets = nullptr;
+  c.quantum = nullptr;
+  sp.o_phi = take(Nc * 8);
+  sp.o_ws = off;
+  if (check_problem(&c) != QE_OK) return false;
+  off += fine_layout_bytes(&c) + seq_extra_bytes(&c, levels - 1);
+  sp.total = off;
+  return true;
+}
+
+static int seq_levels_wanted() { return env_int("QE_SEQ_LEVELS", kSeqLevels); }
+
+static size_t seq_extra_bytes(const qe_problem* p, int levels) {
+  SeqPlan sp;
+  // sizes only: a dummy base that no pointer derived from it is read through
+  return seq_plan(p, reinterpret_cast<char*>(size_t(1) << 20), sp, levels) ? sp.total : 0;
+}
+
+extern "C" {
 
 const char* qe_last_error(void) { return g_last_error.c_str(); }
 
@@ -770,9 +865,12 @@ static qe_status finish(qe_status st, qe_report& r, qe_report* rep) {
 }  // extern "C"
 
 // qe_solve's body; no_alloc: host read-backs in static storage and the CG
-// polled without events (qe_solve_static).
+// polled without events (qe_solve_static).  newton_rtol > 0 (the coarse
+// levels of a sequence) also stops Newton once ||F|| falls below that
+// fraction of its initial value.
 static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_options* o, double* phi,
-                            double* n_nodal, void* ws, size_t ws_bytes, void* stream, qe_report* rep, bool no_alloc) {
+                            double* n_nodal, void* ws, size_t ws_bytes, void* stream, qe_report* rep, bool no_alloc,
+                            double newton_rtol = 0.0, int seq_levels = -1) {
   clear_error();
   qe_report r;
   std::memset(&r, 0, sizeof(r));
@@ -785,14 +883,41 @@ static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_
   if ((st = cx.init(p, ch, ws, ws_bytes, stream, 0, no_alloc)) != QE_OK) return finish(st, r, rep);
   const bool mixed = o->precision == QE_PREC_MIXED;
   if ((st = cx.validate(o->init_guess == 1 ? phi : nullptr)) != QE_OK) return finish(st, r, rep);
-  if ((st = cx.stage(phi, 1, o->init_guess == 0 ? 1 : 0)) != QE_OK) return finish(st, r, rep);
+  // coarse-mesh sequence: the coarse problem's arrays are built from this
+  // one's (validated above), solved, and its potential interpolated into phi
+  bool linear = o->init_guess == 0;
+  if (o->init_guess == 2) {
+    SeqPlan sp;
+    const size_t fine = align256(fine_layout_bytes(p));
+    char* base = reinterpret_cast<char*>(ws) + fine;
+    const int levels = seq_levels < 0 ? seq_levels_wanted() : seq_levels;
+    if (ws_bytes >= fine && seq_plan(p, base, sp, levels) && ws_bytes - fine >= sp.total) {
+      launch_seq_coarsen(cx.s, p, &sp.pc);
+      if (hipGetLastError() != hipSuccess) return finish(fail(QE_ERR_HIP, "coarsening launch failed"), r, rep);
+      qe_report rc;
+      double* phic = reinterpret_cast<double*>(base + sp.o_phi);
+      const qe_status sc = solve_impl(&sp.pc, ph, o, phic, nullptr, base + sp.o_ws, sp.total - sp.o_ws, stream, &rc,
+                                      no_alloc, seq_rtol((long)sp.pc.nx * sp.pc.ny * sp.pc.nz), levels - 1);
+      if (sc == QE_ERR_HIP) return finish(sc, r, rep);
+      if (sc == QE_OK || sc == QE_ERR_NOT_CONVERGED) {
+        launch_seq_prolong(cx.s, p, &sp.pc, phic, phi);
+        if (hipGetLastError() != hipSuccess) return finish(fail(QE_ERR_HIP, "interpolation launch failed"), r, rep);
+        r.seq_levels = rc.seq_levels + 1;
+        r.init_krylov_iters = rc.krylov_iters;
+        r.krylov_iters += rc.krylov_iters;
+      }
+      clear_error();   // a coarse solve that failed leaves the linear guess, not an error
+    }
+    linear = r.seq_levels == 0;
+  }
+  if ((st = cx.stage(phi, 1, linear ? 1 : 0)) != QE_OK) return finish(st, r, rep);
   if (mixed) {
     launch_stage_eps32(cx.s, cx.vblocks, cx.g, p->eps_r, cx.f32(cx.lay.eps32), cx.nslots);
     if (hipGetLastError() != hipSuccess) return finish(fail(QE_ERR_HIP, "cast launch failed"), r, rep);
   }
   const int check = o->check_every;
   int pst = 0, its = 0;
-  if (o->init_guess == 0) {
+  if (linear) {
     // charge-free linear Poisson with the doping kept: one Newton step from
     // phi = (Dirichlet values, 0) on the linear problem
     lin = linear_charge(ch);
@@ -821,7 +946,7 @@ static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_
   if (!std::isfinite(nrm)) return finish(fail(QE_ERR_NONFINITE, "residual not finite at the initial guess"), r, rep);
   st = QE_ERR_NOT_CONVERGED;
   for (int it = 0; it <= o->newton_maxit; ++it) {
-    if (nrm <= o->newton_atol) {
+    if (nrm <= o->newton_atol || nrm <= newton_rtol * r.res0) {
       st = QE_OK;
       break;
     }
@@ -909,7 +1034,9 @@ qe_status qe_solve_static(const qe_problem* p, const qe_physics* ph, const qe_op
   std::memset(&r, 0, sizeof(r));
   qe_status st;
   if ((st = check_problem(p)) != QE_OK) return finish(st, r, rep);
-  const size_t need = qe_workspace_bytes(p, o);
+  // the coarse levels of a sequence are used when the static array has room
+  // for them as well, the linear guess otherwise
+  const size_t need = fine_layout_bytes(p);
   if (need > (size_t)QE_STATIC_WS_BYTES)
     return finish(fail(QE_ERR_WORKSPACE, "the problem needs %zu bytes of workspace, more than the %zu of the static "
                                          "workspace (use qe_solve with a caller workspace)",

@@ -94,7 +94,7 @@ class CReport(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
                 ("krylov_iters", ctypes.c_int32), ("ls_halvings", ctypes.c_int32),
                 ("init_krylov_iters", ctypes.c_int32), ("n_residual_evals", ctypes.c_int32),
-                ("res0", ctypes.c_double), ("res_final", ctypes.c_double)]
+                ("res0", ctypes.c_double), ("res_final", ctypes.c_double), ("seq_levels", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

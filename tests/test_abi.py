@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options():
     o = qe.qe_default_options()
     assert o.newton_atol == 1e-8 and o.newton_maxit == 100 and o.ls_max_halvings == 30
-    assert o.precision == 0 and o.init_guess == 0
+    assert o.precision == 0 and o.init_guess == 2
 
 
 def fake_problem(nx=4, ny=3, nz=2, n_dir=1):
@@ -116,15 +116,21 @@ def test_workspace_checks():
         assert st == -3 and msg in qe.qe_last_error()
 
 
-def test_workspace_scales_with_mesh():
+def test_workspace_scales_with_mesh(monkeypatch):
     lib = qe.load_library()
     o = qe.qe_default_options()
     small = lib.qe_workspace_bytes(ctypes.byref(fake_problem(17, 17, 9)), ctypes.byref(o))
     big = lib.qe_workspace_bytes(ctypes.byref(fake_problem(129, 129, 65)), ctypes.byref(o))
     N = 129 * 129 * 65
     assert big > small
-    # about 7 FP64 + 5 FP32 nodal vectors, FP64 + FP32 Gauss-point coefficients
-    assert 150 * N < big < 230 * N
+    # without the coarse-mesh sequence: about 7 FP64 + 5 FP32 nodal vectors,
+    # FP64 + FP32 Gauss-point coefficients
+    monkeypatch.setenv("QE_SEQ_MIN_NODES", str(10 ** 12))
+    fine = lib.qe_workspace_bytes(ctypes.byref(fake_problem(129, 129, 65)), ctypes.byref(o))
+    assert 150 * N < fine < 230 * N
+    # the sequence's coarse level (65 x 65 x 33, an eighth of the nodes) adds
+    # its arrays and its own layout
+    assert fine / 10 < big - fine < fine / 6
 
 
 def test_count_and_adjoint_argument_checks():
