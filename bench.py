@@ -249,8 +249,9 @@ def schrodinger_run(synth, qe, torch, dev, P, opts, phi_sc):
     """The Schrodinger step on the same stack: the 8 lowest states of a
     quantum region around the plunger P1 (x 0..70, y 60..140, z 40..100 nm)
     in V = E_C(phi_sc), from a random start to a relative residual of 1e-8;
-    then the predictor-corrector loop with 16 states (warm starts) until
-    max |phi^(k) - phi^(k-1)| < 1e-5 V or 60 outer iterations."""
+    then the predictor-corrector loop with 16 states (the eigensolver warm
+    started from the previous states, the predictor's Newton from phi^(k))
+    until max |phi^(k) - phi^(k-1)| < 1e-5 V or 60 outer iterations."""
     inv_mass, v0, fixed, region = synth.quantum_region(dev, (0.0, 70.0, 60.0, 140.0, 40.0, 100.0))
     ws = qe.Workspace(qe.load_library().qe_schrodinger_workspace_bytes(qe.ctypes.byref(P.c()), 16), P.device)
     qe.qe_schrodinger_solve(P, inv_mass, v0, phi_sc, 8, fixed=fixed, tol=1e-8, maxit=3000, ws=ws)   # warm-up
@@ -263,6 +264,9 @@ def schrodinger_run(synth, qe, torch, dev, P, opts, phi_sc):
     region_t = torch.as_tensor(region.astype("uint8"), device=P.device)
     t0 = time.perf_counter()
     phi_k, guess, hist, lob = phi_sc.clone(), None, [], []
+    # each predictor solve starts from phi^(k), the previous outer step's potential
+    opts_warm = qe.qe_default_options(newton_atol=opts.newton_atol, init_guess=1)
+    newton = []
     for _ in range(60):
         E16, psi16, psi2, it16 = qe.qe_schrodinger_solve(P, inv_mass, v0, phi_k, 16, fixed=fixed, tol=1e-8,
                                                          maxit=3000, ws=ws, guess=guess)
@@ -270,7 +274,8 @@ def schrodinger_run(synth, qe, torch, dev, P, opts, phi_sc):
         lob.append(it16)
         # the states stay on the device; the problem's other arrays are shared
         Pq = P.with_quantum(synth.QuantumStates(psi2=psi2, phi_k=phi_k, E_i=E16, region=region_t))
-        new, _, rep = qe.qe_solve(Pq, opts=opts, want_density=False)
+        new, _, rep = qe.qe_solve(Pq, opts=opts_warm, phi=phi_k.clone(), want_density=False)
+        newton.append(rep["newton_iters"])
         hist.append(float((new - phi_k).abs().max()))
         phi_k = new
         if hist[-1] < 1e-5:
@@ -288,7 +293,7 @@ def schrodinger_run(synth, qe, torch, dev, P, opts, phi_sc):
     return {"eig8_ms": t_eig * 1e3, "eig8_lobpcg_iters": it, "E8_meV": [float(e * 1e3) for e in E],
             "sp_loop_s": t_loop, "sp_outer_iters": len(hist), "sp_final_dphi_V": hist[-1], "sp_state": state,
             "sp_dphi_history_V": hist,
-            "sp_lobpcg_iters": lob, "sp_dot_electrons": float(n_dot),
+            "sp_lobpcg_iters": lob, "sp_newton_iters": newton, "sp_dot_electrons": float(n_dot),
             "sp_levels_meV": [float(e * 1e3) for e in E16[:4]]}
 
 

@@ -193,7 +193,7 @@ def test_predictor_corrector_loop_closes():
         return phi, E, count, hist
 
     base = qe.Problem(dev)
-    opts = qe.qe_default_options(newton_atol=1e-10)
+    opts_warm = qe.qe_default_options(newton_atol=1e-10, init_guess=1)
 
     prev = {}
 
@@ -206,8 +206,10 @@ def test_predictor_corrector_loop_closes():
         return E, psi2.cpu().numpy()
 
     def poisson_gpu(qdev):
+        # Newton from phi^(k), the previous outer step's potential
         P = qe.Problem(qdev)
-        phi, _, _ = qe.qe_solve(P, opts=opts)
+        start = torch.as_tensor(qdev.quantum.phi_k, dtype=torch.float64, device="cuda")
+        phi, _, _ = qe.qe_solve(P, opts=opts_warm, phi=start)
         return phi.cpu().numpy(), qe.qe_count_electrons(P, phi, [box])[0]
 
     def eig_oracle(phi):

@@ -53,3 +53,21 @@ def test_static_workspace_rejects_problems_that_need_more():
                              ctypes.c_void_p(big.data_ptr()), None, None, ctypes.byref(rep))
     assert st == -3 and "static workspace" in qe.qe_last_error() and rep.status == -3
     assert N > 0
+
+
+def test_static_workspace_sequenced_solve_at_the_benchmark_size():
+    """129x129x65: the static array also holds the coarse level of the
+    default coarse-mesh sequence, which then runs without allocating; the
+    solve matches qe_solve's."""
+    dev = synth.config2()
+    P = qe.Problem(dev)
+    opts = qe.qe_default_options(newton_atol=1e-10)
+    phi_ref, _, rep_ref = qe.qe_solve(P, opts=opts, want_density=False)
+    phi = torch.zeros(P.N, dtype=torch.float64, device=P.device)
+    rep = qe.qe_solve_static(P, phi, None, opts=opts)
+    torch.cuda.synchronize()
+    print("static", rep, "workspace", rep_ref)
+    assert rep["status"] == 0 and rep["res_final"] <= 1e-10
+    assert rep["seq_levels"] == 1 and rep_ref["seq_levels"] == 1
+    assert rep["newton_iters"] == rep_ref["newton_iters"]
+    assert rel_max(phi.cpu().numpy(), phi_ref.cpu().numpy()) <= 1e-12
