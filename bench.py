@@ -394,7 +394,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "double-dot Si/SiO2 stack 129x129x65 nodes (1081665 DOF), 5 gates, "
-                               "Fermi-Dirac 4 K, FP64 Newton + Jacobi-PCG to ||F||<1e-8",
+                               "Fermi-Dirac 4 K, FP64 Newton + Jacobi-PCG to ||F||<1e-8 from the default "
+                               "start (65x65x33 coarse-mesh sequence)",
                    "global_batch": 1, "parallelism": "single GPU"},
         "newton_iters": reps[-1]["newton_iters"],
         "krylov_iters": reps[-1]["krylov_iters"],
