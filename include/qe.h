@@ -230,7 +230,7 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o);
  * solution.  n_nodal: device [N] or NULL; receives n(phi_i) at nodes that
  * touch a semiconductor element, 0 elsewhere.  rep: host, may be NULL.
  * The paper leaves Newton's start open (Sec. II.A.3).  With init_guess = 2
- * a mesh of at least 400000 nodes without sheets or eigenstates is first
+ * a mesh of at least 250000 nodes without sheets or eigenstates is first
  * coarsened (every other node along each axis, the last one kept; each
  * coarse element takes the materials of its first fine element), that
  * problem is solved from the linear guess until ||F|| falls to a fraction

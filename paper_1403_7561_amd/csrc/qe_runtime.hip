@@ -779,13 +779,12 @@ static size_t fine_layout_bytes(const qe_problem* p) {
 // every other node along each axis (the last node kept) is solved first, to
 // the relative residual seq_rtol (from its linear guess, or a further level
 // when QE_SEQ_LEVELS asks for more than one), and its potential, interpolated
-// trilinearly, starts Newton here.  Only for
-// meshes of at least kSeqMinNodes nodes (below, a solve is launch- rather
-// than bandwidth-bound and the coarse solve costs about as much as it saves)
-// without sheets or eigenstates; otherwise, or when the workspace has no room
-// for the coarse levels, the linear guess.  The coarse arrays and the coarse
+// trilinearly, starts Newton here.  Only for meshes of at least
+// kSeqMinNodes nodes (measured faster from 269k nodes up; smaller solves are
+// launch-bound) without sheets or eigenstates; otherwise, or when the
+// workspace has no room for the coarse levels, the linear guess.  The coarse arrays and the coarse
 // solve's workspace follow the fine layout in the caller's workspace.
-static const long kSeqMinNodes = 400000;
+static const long kSeqMinNodes = 250000;
 static const int kSeqLevels = 1;
 
 // The coarse solve need not be more accurate than the coarse mesh's own

@@ -68,7 +68,7 @@ def test_fallbacks_to_the_linear_guess(monkeypatch):
     dev = double_dot(33, 33, 17)
     P = qe.Problem(dev)
     opts = qe.qe_default_options(newton_atol=1e-10)
-    # below the size threshold (the library's own, 400000 nodes)
+    # below the size threshold (the library's own, 250000 nodes)
     _, _, rep = qe.qe_solve(P, opts=opts)
     assert rep["seq_levels"] == 0
     # a workspace without room for the coarse level
