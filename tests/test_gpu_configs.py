@@ -2,9 +2,11 @@
 gradient of the 129 x 129 x 65 five-gate stack (Sec. III, C = q dN/dV)
 against central differences of the GPU solve, and the 256-instance plunger
 sweep, whose smallest and largest meshes must equal their single-instance
-solves.  (The oracle cannot solve these sizes in a test's time; the
-gradient is pinned by differences, the sweep by the single-instance path,
-which the oracle pins at smaller sizes.)"""
+solves, and the 257 x 257 x 129 stack's FP64 and mixed-precision solves.
+(The oracle cannot solve these sizes in a test's time; the gradient is
+pinned by differences, the sweep by the single-instance path, which the
+oracle pins at smaller sizes, and the large solves by the oracle's residual
+and Jacobian on sampled nodes.)"""
 import numpy as np
 import pytest
 
@@ -127,3 +129,50 @@ def test_c3_smallest_and_largest_instances_match_single_solves(tmp_path):
               "counts", counts[k], c1)
         assert err <= 1e-12
         assert np.allclose(counts[k], c1, rtol=1e-10, atol=1e-12 * max(c1.max(), 1e-30))
+
+
+def test_c5_fp64_and_mixed_solves_at_full_size():
+    """257 x 257 x 129 stack with eight random gates over a rough oxide, in the
+    launch configuration the benchmark times (coarse-mesh start, default
+    options): the FP64 and mixed-precision solves both reach ||F|| < 1e-8;
+    the oracle's residual at the returned potentials is at the FP64 floor on
+    sampled nodes (half of them where the electron density is largest, so the
+    charge terms are exercised); the mixed potential and dot counts agree with
+    the FP64 ones to 1e-6; sampled J.v values (FP64 and FP32 operands) at a
+    perturbed potential match the oracle's element-by-element Jacobian."""
+    from tests import gpu_support as gs
+    dev = synth.config5()
+    P = qe.Problem(dev)
+    boxes = [dev.boxes["D1"], dev.boxes["D2"]]
+    opts64 = qe.qe_default_options(newton_atol=1e-8)
+    optsm = qe.qe_default_options(newton_atol=1e-8, precision=1)
+    ws = qe.workspace_for(P, opts64)
+    phi64, n64, rep64 = qe.qe_solve(P, opts=opts64, ws=ws, want_density=True)
+    phim, _, repm = qe.qe_solve(P, opts=optsm, ws=ws, want_density=False)
+    print("fp64", rep64, "\nmixed", repm)
+    assert rep64["status"] == 0 and rep64["res_final"] <= 1e-8 and rep64["seq_levels"] == 1
+    assert repm["status"] == 0 and repm["res_final"] <= 1e-8
+    ph64, phm = phi64.cpu().numpy(), phim.cpu().numpy()
+    err = rel_max(phm, ph64)
+    c64 = qe.qe_count_electrons(P, phi64, boxes, ws=ws)
+    cm = qe.qe_count_electrons(P, phim, boxes, ws=ws)
+    print("mixed vs fp64", err, "counts", c64, cm)
+    assert err <= 1e-6
+    assert np.allclose(cm, c64, rtol=1e-6, atol=1e-6 * max(c64.max(), 1e-30))
+    rng = np.random.default_rng(55)
+    dens = n64.cpu().numpy()
+    nodes = np.concatenate([rng.choice(dev.n_nodes, 150, replace=False), np.argsort(dens)[-150:]])
+    for name, ph in (("fp64", ph64), ("mixed", phm)):
+        Fs = gs.sampled_residual(dev, ph, nodes)
+        print(name, "sampled oracle |F| max", np.abs(Fs).max())
+        assert np.abs(Fs).max() < 1e-8
+    pert = ph64 + 0.01 * rng.standard_normal(ph64.size)
+    pert[dev.dir_id >= 0] = dev.dir_val[dev.dir_id[dev.dir_id >= 0]]
+    v = rng.standard_normal(ph64.size)
+    pt = torch.as_tensor(pert, device="cuda")
+    yo = gs.sampled_jv(dev, pert, v, nodes)
+    y = qe.qe_jv(P, pt, torch.as_tensor(v, device="cuda"), ws=ws).cpu().numpy()[nodes]
+    y32 = qe.qe_jv(P, pt, torch.as_tensor(v, dtype=torch.float32, device="cuda"), ws=ws).cpu().numpy()[nodes]
+    print("jv64", np.abs(y - yo).max() / np.abs(yo).max(), "jv32", np.abs(y32 - yo).max() / np.abs(yo).max())
+    assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
+    assert np.abs(y32 - yo).max() <= 2e-5 * np.abs(yo).max()
