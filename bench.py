@@ -372,6 +372,14 @@ def main():
     _, _, rep_lin = qe.qe_solve(P, opts=opts_lin, phi=phi, want_density=False, ws=ws)
     torch.cuda.synchronize()
     t_lin = time.perf_counter() - t0
+    # and with the Jacobi preconditioner on every CG (no multigrid)
+    opts_jac = qe.qe_default_options(newton_atol=1e-8, precond=1)
+    qe.qe_solve(P, opts=opts_jac, phi=phi, want_density=False, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, rep_jac = qe.qe_solve(P, opts=opts_jac, phi=phi, want_density=False, ws=ws)
+    torch.cuda.synchronize()
+    t_jac = time.perf_counter() - t0
     log(f"{value:.3f} solves/s; timing J.v")
     # J.v kernel alone (HIP events on the library's stream)
     v = torch.randn(P.N, dtype=torch.float64, device="cuda")
@@ -394,15 +402,20 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "double-dot Si/SiO2 stack 129x129x65 nodes (1081665 DOF), 5 gates, "
-                               "Fermi-Dirac 4 K, FP64 Newton + Jacobi-PCG to ||F||<1e-8 from the default "
-                               "start (65x65x33 coarse-mesh sequence)",
+                               "Fermi-Dirac 4 K, FP64 Newton + PCG (Jacobi; multigrid V-cycle on the steps with CG "
+                               "tolerance <= 3e-2) to ||F||<1e-8 from the default start (65x65x33 "
+                               "coarse-mesh sequence)",
                    "global_batch": 1, "parallelism": "single GPU"},
         "newton_iters": reps[-1]["newton_iters"],
         "krylov_iters": reps[-1]["krylov_iters"],
         "init_krylov_iters": reps[-1]["init_krylov_iters"],
         "seq_levels": reps[-1]["seq_levels"],
+        "mg_levels": reps[-1]["mg_levels"],
+        "mg_krylov_iters": reps[-1]["mg_krylov_iters"],
         "linear_guess": {"ms": t_lin * 1e3, "newton_iters": rep_lin["newton_iters"],
                          "krylov_iters": rep_lin["krylov_iters"]},
+        "jacobi_only": {"ms": t_jac * 1e3, "newton_iters": rep_jac["newton_iters"],
+                        "krylov_iters": rep_jac["krylov_iters"]},
         "res_final": reps[-1]["res_final"],
         "dot_electrons": [float(c) for c in counts],
         "jv_gdof_s": {"fp64": P.N / (ms64 * 1e-3) / 1e9, "fp32": P.N / (ms32 * 1e-3) / 1e9,
@@ -422,21 +435,31 @@ def main():
         dev4 = synth.config4()
         P4 = qe.Problem(dev4)
         ws4 = qe.workspace_for(P4, opts)
+        # differentiate the dot under the more positive plunger (the other is empty)
+        box_name = "D1" if dev4.dir_val[0] >= dev4.dir_val[1] else "D2"
+        ph4, _, _ = qe.qe_solve(P4, opts=opts, ws=ws4, want_density=False)      # warm-up
+        qe.qe_adjoint(P4, ph4, dev4.boxes[box_name], opts=opts, ws=ws4)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         ph4, _, rep4 = qe.qe_solve(P4, opts=opts, ws=ws4, want_density=False)
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        # differentiate the dot under the more positive plunger (the other is empty)
-        box_name = "D1" if dev4.dir_val[0] >= dev4.dir_val[1] else "D2"
         Q, dV, deps, _, arep = qe.qe_adjoint(P4, ph4, dev4.boxes[box_name], opts=opts, ws=ws4)
         torch.cuda.synchronize()
         tc = time.perf_counter()
+        # the adjoint CG with Jacobi instead of the V-cycle, for comparison
+        _, dVj, _, _, arepj = qe.qe_adjoint(P4, ph4, dev4.boxes[box_name], opts=opts_jac, ws=ws4)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
         out["adjoint"] = {"forward_ms": (tb - ta) * 1e3, "adjoint_ms": (tc - tb) * 1e3,
                           "ratio": (tc - tb) / (tb - ta), "box": box_name, "Q": Q,
                           "dQ_dV": [float(x) for x in dV],
                           "C_aF": [float(1.602176634e-19 * x * 1e18) for x in dV],
-                          "forward_cg_iters": rep4["krylov_iters"], "adjoint_cg_iters": arep["krylov_iters"]}
+                          "forward_cg_iters": rep4["krylov_iters"], "adjoint_cg_iters": arep["krylov_iters"],
+                          "adjoint_mg_levels": arep["mg_levels"],
+                          "jacobi": {"adjoint_ms": (td - tc) * 1e3, "cg_iters": arepj["krylov_iters"],
+                                     "dQ_dV_max_rel_diff": float(np.abs(np.asarray(dV) - np.asarray(dVj)).max()
+                                                                 / np.abs(np.asarray(dVj)).max())}}
     if not args.no_batch:
         log("batched sweep (256 instances)")
         spec = synth.config3_spec()

@@ -87,6 +87,26 @@ typedef enum {
                                     Newton update in FP64 */
 } qe_precision;
 
+/* Preconditioner of the FP64 CG (the paper's solver library leaves it to
+ * the user; Sec. II.A.3).  Jacobi: z = D^-1 r.  Multigrid: a symmetric
+ * V-cycle on the meshes of the coarse-mesh sequence (every other node along
+ * each axis, the last kept, while the coarser mesh keeps at least 2000
+ * nodes), each with the coarse problem's own Jacobian at the injected
+ * potential; trilinear prolongation P, restriction P^T, one l1-Jacobi
+ * smoothing step (S = 1 / sum_j |J_ij|) before and one after the coarse
+ * correction, four on the coarsest mesh.  It is symmetric positive definite,
+ * so the CG stays plain CG.  AUTO takes multigrid for the Newton steps whose
+ * CG tolerance is at most 3e-2 and for the adjoint, where one V-cycle (the
+ * cost of about seven Jacobi iterations at 129 x 129 x 65) saves more
+ * iterations than it costs, and Jacobi otherwise.  Multigrid needs a mesh of at least 250000 nodes
+ * without sheets or eigenstates, FP64, and an entry point that allocates;
+ * elsewhere every choice runs Jacobi. */
+typedef enum {
+  QE_PC_AUTO = 0,
+  QE_PC_JACOBI = 1,
+  QE_PC_MULTIGRID = 2            /* multigrid for every CG solve it can serve */
+} qe_precond;
+
 /* A rectangle of mesh faces carrying a surface charge and / or a Robin
  * condition (Sec. II.A.4).  The sheet lies in the node plane
  * x_axis = coordinate[plane] (axis 0: x, 1: y, 2: z) and covers faces a0..a1-1
@@ -200,6 +220,7 @@ typedef struct {
   int32_t check_every;           /* CG iterations the host keeps queued beyond
                                     those known to have finished (0 = 9;
                                     clamped to [9, 56]) */
+  int32_t precond;               /* CG preconditioner (qe_precond) */
 } qe_options;
 
 typedef struct {
@@ -213,10 +234,14 @@ typedef struct {
   double res_final;              /* ||F_free|| at the returned phi */
   int32_t seq_levels;            /* coarse meshes solved for the initial guess
                                     (init_guess = 2), 0 for the linear guess */
+  int32_t mg_levels;             /* meshes of the multigrid preconditioner when
+                                    it served a CG solve of the call, else 0 */
+  int32_t mg_krylov_iters;       /* CG iterations preconditioned by multigrid
+                                    (part of krylov_iters) */
 } qe_report;
 
 /* Fill `o` with defaults (atol 1e-8, 100 Newton steps, 30 halvings, forcing
- * cap 0.3, 20000 CG iterations, FP64, coarse-mesh sequence).  The forcing
+ * cap 0.3, 20000 CG iterations, FP64, coarse-mesh sequence, QE_PC_AUTO).  The forcing
  * term is eta_k = min(cap, 0.9 (|F_k| / |F_k-1|)^2) (Eisenstat-Walker), and
  * the linear initial guess is solved to a relative CG residual of 1e-2. */
 void qe_default_options(qe_options* o);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqe.so")
-SOURCES = ["qe_kernels.hip", "qe_sheets.hip", "qe_runtime.hip", "qe_batch.hip", "qe_schrod.hip", "qe_seq.hip"]
+SOURCES = ["qe_kernels.hip", "qe_sheets.hip", "qe_runtime.hip", "qe_batch.hip", "qe_schrod.hip", "qe_seq.hip", "qe_mg.hip"]
 ARCH = os.environ.get("QE_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -1,0 +1,337 @@
+// Geometric multigrid preconditioner of the FP64 CG (kernels and host
+// launchers).  The paper solves each Newton step with a preconditioned
+// Krylov method from its solver library and names no preconditioner
+// (Sec. II.A.3 and II.C); this one is a symmetric V-cycle on the meshes of
+// the coarse-mesh sequence:
+//
+//   level l + 1 keeps the fine nodes f(I) = min(2 I, n - 1) of level l along
+//   each axis; its Jacobian is the coarse problem's own (rediscretised) at
+//   the potential injected from level l;
+//   prolongation P: trilinear interpolation in the fine coordinates;
+//   restriction: exactly P^T;
+//   smoother: x += S (b - J x) with S = 1 / sum_j |J_ij| (l1-Jacobi), the
+//   same before and after the coarse correction;
+//   coarsest level: a fixed number of smoother steps from x = S b.
+//
+// With R = P^T, one smoother S on both sides and an SPD coarse operator, the
+// V-cycle is symmetric, and 2 S^-1 - J is diagonally dominant (S^-1 bounds
+// the row's absolute sum), so the V-cycle is positive definite: plain CG
+// with it stays CG (no flexible variant).  The l1 sums are formed element by
+// element: sum_j |Khat_ij| of the box element from its three stiffness
+// weights, and for the Gauss-point coefficient term, whose entries are all
+// >= 0 and whose trilinear weights sum to 1, the row sum B^T c.  Both bound
+// the assembled row's absolute sum from above.
+//
+// Every kernel here returns at once when the CG it serves has stopped
+// (ctx->done), like the CG loop's own kernels, so launches queued after the
+// stop cost only their dispatch.
+#include <algorithm>
+
+#include "qe_kernels.h"
+#include "qe_tiles.h"
+
+namespace qe {
+
+#define QE_LAUNCH(kernel, grid, block, stream, ...) \
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, (hipStream_t)(stream), __VA_ARGS__)
+
+__device__ __forceinline__ int mg_fine(int I, int n) { return min(2 * I, n - 1); }
+
+// One axis of the interpolation: the coarse interval holding fine node i and
+// the weight of its upper end (fine node i takes (1 - w) of coarse I and w
+// of coarse I + 1).
+__device__ __forceinline__ void mg_weight(int i, int nf, int nc, const double* __restrict__ xf, int& I, double& w) {
+  I = min(i >> 1, nc - 2);
+  const double a = xf[mg_fine(I, nf)], b = xf[mg_fine(I + 1, nf)];
+  w = (xf[i] - a) / (b - a);
+}
+
+// One axis of the restriction: the fine nodes f(I) - 1, f(I), f(I) + 1 and
+// their weights on coarse node I, the transpose of mg_weight's (a fine node
+// strictly inside the coarse interval [I - 1, I] takes w of coarse I, one
+// inside [I, I + 1] takes 1 - w).  A missing neighbour (the mesh's end, or
+// a fine node that is itself a coarse node, as at the even count's last
+// interval) gets weight 0 and the centre's index.
+__device__ __forceinline__ void mg_taps(int I, int nf, int nc, const double* __restrict__ xf, int idx[3], double wt[3]) {
+  const int c = mg_fine(I, nf);
+  const double X = xf[c];
+  idx[0] = idx[1] = idx[2] = c;
+  wt[0] = wt[2] = 0.0;
+  wt[1] = 1.0;
+  if (I > 0) {
+    const int lo = mg_fine(I - 1, nf);
+    if (c - 1 > lo) {
+      const double a = xf[lo];
+      idx[0] = c - 1;
+      wt[0] = (xf[c - 1] - a) / (X - a);
+    }
+  }
+  if (I < nc - 1) {
+    const int hi = mg_fine(I + 1, nf);
+    if (c + 1 < hi) {
+      const double b = xf[hi];
+      idx[2] = c + 1;
+      wt[2] = (b - xf[c + 1]) / (b - X);
+    }
+  }
+}
+
+// y = J v on one level, as the library's plain J.v (v read as 0 on Dirichlet
+// nodes; their rows are left as computed and masked by the consumers).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_mg_jv(
+    Geom g, WaveMap wm, const double* __restrict__ eps, const unsigned int* __restrict__ cbits,
+    const double* __restrict__ cq, const uint8_t* __restrict__ mask, const double* __restrict__ v,
+    double* __restrict__ y, const PcgCtx* __restrict__ ctx) {
+  if (ctx->done) return;
+  const int w = __builtin_amdgcn_readfirstlane(wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6));
+  const bool active = w < wm.nwaves;
+  int wx, wy, wz;
+  wave_tile_of(w, wm, wx, wy, wz);
+  const WaveTile t(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
+  const unsigned int cb = active ? cbits[64L * w + (threadIdx.x & 63)] : 0u;
+  double dot = 0.0;
+  jv_tile<double, JV_PLAIN>(g, t, eps, cb, cq, mask, v, y, 0, dot);
+}
+
+// Coarse node (I, J, K): b_c = sum over fine nodes of P_fine,coarse *
+// (r - ys * y) (fine Dirichlet nodes count as 0), 0 on coarse Dirichlet
+// nodes; x_c = S_c b_c (the pre-smoothing step from zero).
+__global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
+                                                              const double* __restrict__ xf,
+                                                              const double* __restrict__ yf,
+                                                              const double* __restrict__ zf,
+                                                              const uint8_t* __restrict__ maskf,
+                                                              const double* __restrict__ r,
+                                                              const double* __restrict__ y, double ys,
+                                                              const uint8_t* __restrict__ maskc,
+                                                              const double* __restrict__ Sc, double* __restrict__ bc,
+                                                              double* __restrict__ xc, const PcgCtx* __restrict__ ctx) {
+  if (ctx->done) return;
+  const long Nc = (long)nxc * nyc * nzc;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < Nc; t += (long)gridDim.x * blockDim.x) {
+    double b = 0.0;
+    if (!maskc[t]) {
+      const int I = (int)(t % nxc), J = (int)((t / nxc) % nyc), K = (int)(t / ((long)nxc * nyc));
+      int ix[3], iy[3], iz[3];
+      double wx[3], wy[3], wz[3];
+      mg_taps(I, nxf, nxc, xf, ix, wx);
+      mg_taps(J, nyf, nyc, yf, iy, wy);
+      mg_taps(K, nzf, nzc, zf, iz, wz);
+      // 27 taps, every load issued before the sums (zero-weight taps read the
+      // centre again)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int bq = 0; bq < 3; ++bq) {
+          const long row = (long)nxf * ((long)iy[bq] + (long)nyf * iz[c]);
+          const double wyz = wy[bq] * wz[c];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const long n = row + ix[a];
+            const double v = maskf[n] ? 0.0 : r[n] - ys * y[n];
+            b += (wyz * wx[a]) * v;
+          }
+        }
+    }
+    bc[t] = b;
+    xc[t] = Sc[t] * b;
+  }
+}
+
+// Fine node: x = xs * x + (P x_c) on free nodes, 0 on Dirichlet nodes.
+__global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
+                                                             const double* __restrict__ xf,
+                                                             const double* __restrict__ yf,
+                                                             const double* __restrict__ zf,
+                                                             const uint8_t* __restrict__ maskf,
+                                                             const double* __restrict__ xcv, double xs,
+                                                             double* __restrict__ x, const PcgCtx* __restrict__ ctx) {
+  if (ctx->done) return;
+  const long Nf = (long)nxf * nyf * nzf;
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < Nf; n += (long)gridDim.x * blockDim.x) {
+    if (maskf[n]) {
+      x[n] = 0.0;
+      continue;
+    }
+    const int i = (int)(n % nxf), j = (int)((n / nxf) % nyf), k = (int)(n / ((long)nxf * nyf));
+    int I, J, K;
+    double wx, wy, wz;
+    mg_weight(i, nxf, nxc, xf, I, wx);
+    mg_weight(j, nyf, nyc, yf, J, wy);
+    mg_weight(k, nzf, nzc, zf, K, wz);
+    const long c0 = (long)I + (long)nxc * ((long)J + (long)nyc * K), sy = nxc, sz = (long)nxc * nyc;
+    const double v00 = xcv[c0] + wx * (xcv[c0 + 1] - xcv[c0]);
+    const double v10 = xcv[c0 + sy] + wx * (xcv[c0 + sy + 1] - xcv[c0 + sy]);
+    const double v01 = xcv[c0 + sz] + wx * (xcv[c0 + sz + 1] - xcv[c0 + sz]);
+    const double v11 = xcv[c0 + sz + sy] + wx * (xcv[c0 + sz + sy + 1] - xcv[c0 + sz + sy]);
+    const double v0 = v00 + wy * (v10 - v00), v1 = v01 + wy * (v11 - v01);
+    x[n] = xs * x[n] + (v0 + wz * (v1 - v0));
+  }
+}
+
+// x += S (b - y) (S is 0 on Dirichlet nodes); with part, one partial of
+// b^T x per block (the CG's r^T z after the fine level's last step).
+__global__ __launch_bounds__(kVecThreads) void k_mg_smooth(long N, const double* __restrict__ b,
+                                                            const double* __restrict__ y,
+                                                            const double* __restrict__ S, double* __restrict__ x,
+                                                            double* __restrict__ part, const PcgCtx* __restrict__ ctx) {
+  if (ctx->done) return;
+  __shared__ double sred[kVecThreads / 64];
+  double bz = 0.0;
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
+    const double bn = b[n];
+    const double xn = x[n] + S[n] * (bn - y[n]);
+    x[n] = xn;
+    bz += bn * xn;
+  }
+  if (part) {
+    const double s1 = block_sum(bz, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = s1;
+  }
+}
+
+// After the V-cycle on the CG's starting residual: r_0^T z_0 from its
+// partials replaces the Jacobi one (the tolerance keeps its ratio rtol^2).
+__global__ __launch_bounds__(kVecThreads) void k_mg_start_fin(PcgCtx* ctx, const double* __restrict__ part, int n) {
+  if (ctx->done) return;
+  __shared__ double sred[kVecThreads / 64];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += kVecThreads) a += part[i];
+  const double RZ = block_sum(a, sred);   // complete in thread 0
+  if (threadIdx.x == 0) {
+    const double ratio = ctx->tol2 / ctx->rzs[0];   // rtol^2 (rzs[0] > 0: the start did not stop)
+    ctx->rzs[0] = RZ;
+    ctx->tol2 = ratio * RZ;
+    if (!isfinite(RZ)) {
+      ctx->done = 1;
+      ctx->status = PCG_NONFINITE;
+    } else if (RZ <= 0.0) {
+      // r != 0 (the start did not stop) and the V-cycle is positive definite:
+      // r^T z <= 0 can only come from a broken linearisation
+      ctx->done = 1;
+      ctx->status = PCG_BREAKDOWN;
+    }
+  }
+}
+
+// Coarse potential by injection: phi_c(I, J, K) = phi_f(f(I), f(J), f(K)).
+__global__ __launch_bounds__(kVecThreads) void k_mg_inject(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
+                                                            const double* __restrict__ phif,
+                                                            double* __restrict__ phic) {
+  const long Nc = (long)nxc * nyc * nzc;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < Nc; t += (long)gridDim.x * blockDim.x) {
+    const int I = (int)(t % nxc), J = (int)((t / nxc) % nyc), K = (int)(t / ((long)nxc * nyc));
+    phic[t] = phif[(long)mg_fine(I, nxf) + (long)nxf * ((long)mg_fine(J, nyf) + (long)nyf * mg_fine(K, nzf))];
+  }
+}
+
+// Smoother weights S_i = 1 / (sum over the elements of node i of
+// sum_j |Khat_ij| + (B^T c)_i) on free nodes, 0 on Dirichlet nodes.
+// Khat's entry between local nodes that differ along the axes in d is
+// sx kx(dx) my(dy) mz(dz) + sy mx(dx) ky(dy) mz(dz) + sz mx(dx) my(dy) kz(dz)
+// with k(same) = 1, k(diff) = -1, m(same) = 1/3, m(diff) = 1/6 (the box
+// element's stiffness in the weights sx = eps h_y h_z / h_x, ...).  B^T c is
+// the coefficient term's product with the all-ones vector (the stiffness
+// rows sum to zero), so jv_element gives it.
+__global__ __launch_bounds__(kVecThreads) void k_mg_l1(Geom g, const double* __restrict__ eps,
+                                                        const uint8_t* __restrict__ cflag,
+                                                        const double* __restrict__ cq,
+                                                        const uint8_t* __restrict__ mask, double* __restrict__ S) {
+  const long N = (long)g.nx * g.ny * g.nz;
+  const int gx = (g.nx + 6) / 7, gy = (g.ny + 6) / 7;
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
+    if (mask[n]) {
+      S[n] = 0.0;
+      continue;
+    }
+    const int i = (int)(n % g.nx), j = (int)((n / g.nx) % g.ny), k = (int)(n / ((long)g.nx * g.ny));
+    double sum = 0.0;
+    for (int ez = max(k - 1, 0); ez <= min(k, g.nz - 2); ++ez)
+      for (int ey = max(j - 1, 0); ey <= min(j, g.ny - 2); ++ey)
+        for (int ex = max(i - 1, 0); ex <= min(i, g.nx - 2); ++ex) {
+          const double hx = g.x[ex + 1] - g.x[ex], hy = g.y[ey + 1] - g.y[ey], hz = g.z[ez + 1] - g.z[ez];
+          const double e = eps[(long)ex + (long)(g.nx - 1) * ((long)ey + (long)(g.ny - 1) * ez)];
+          const double sx = e * hy * hz / hx, sy = e * hx * hz / hy, sz = e * hx * hy / hz;
+          double st = 0.0;
+#pragma unroll
+          for (int d = 0; d < 8; ++d) {
+            const bool dx = d & 1, dy = d & 2, dz = d & 4;
+            const double kx = dx ? -1.0 : 1.0, ky = dy ? -1.0 : 1.0, kz = dz ? -1.0 : 1.0;
+            const double mx = dx ? 1.0 / 6.0 : 1.0 / 3.0, my = dy ? 1.0 / 6.0 : 1.0 / 3.0,
+                         mz = dz ? 1.0 / 6.0 : 1.0 / 3.0;
+            st += fabs(sx * kx * my * mz + sy * mx * ky * mz + sz * mx * my * kz);
+          }
+          sum += st;
+          const long sl = tile_slot(ex, ey, ez, gx, gy);
+          if (cflag[sl]) {
+            double c[8], ones[8], out[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              c[q] = cq[8 * sl + q];
+              ones[q] = 1.0;
+            }
+            jv_element<double, false>(ones, 0.0, 0.0, 0.0, c, true, out);
+            sum += out[(i - ex) + 2 * (j - ey) + 4 * (k - ez)];
+          }
+        }
+    S[n] = sum > 0.0 ? 1.0 / sum : 0.0;
+  }
+}
+
+static int mg_blocks(long n, long cap) {
+  return (int)std::max(1L, std::min((n + kVecThreads - 1) / kVecThreads, cap));
+}
+
+void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic) {
+  QE_LAUNCH(k_mg_inject, mg_blocks(c.N, 4096), kVecThreads, s, f.g.nx, f.g.ny, f.g.nz, c.g.nx, c.g.ny, c.g.nz, phif,
+            phic);
+}
+
+void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, double* S) {
+  QE_LAUNCH(k_mg_l1, mg_blocks(L.N, 8192), kVecThreads, s, L.g, eps_natural, cflag, L.cq, L.mask, S);
+}
+
+void launch_mg_start_fin(hipStream_t s, PcgCtx* ctx, const double* part, int n) {
+  QE_LAUNCH(k_mg_start_fin, 1, kVecThreads, s, ctx, part, n);
+}
+
+// The V-cycle below level l (levels l .. nlev-1).  On entry level l holds
+// b (its right-hand side) and x = S b; on return x = B_l b.  Level 0's last
+// smoothing step writes one b^T x partial per block into part (cgblocks
+// blocks).
+static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, int cgblocks, double* part,
+                   const PcgCtx* ctx) {
+  const MgGrid& A = L[l];
+  auto jv = [&](const double* v, double* y) {
+    QE_LAUNCH(k_mg_jv, A.wm.nblocks, 256, s, A.g, A.wm, A.eps_t, A.cbits, A.cq, A.mask, v, y, ctx);
+  };
+  auto smooth = [&](double* p, int nb) {
+    QE_LAUNCH(k_mg_smooth, nb, kVecThreads, s, A.N, A.b, A.y, A.S, A.x, p, ctx);
+  };
+  if (l == nlev - 1) {
+    for (int k = 1; k < sweeps; ++k) {
+      jv(A.x, A.y);
+      smooth(nullptr, mg_blocks(A.N, 4096));
+    }
+    return;
+  }
+  const MgGrid& C = L[l + 1];
+  jv(A.x, A.y);
+  QE_LAUNCH(k_mg_restrict, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny, C.g.nz,
+            A.g.x, A.g.y, A.g.z, A.mask, A.b, A.y, 1.0, C.mask, C.S, C.b, C.x, ctx);
+  vcycle(s, L, l + 1, nlev, sweeps, cgblocks, part, ctx);
+  QE_LAUNCH(k_mg_prolong, mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny, C.g.nz,
+            A.g.x, A.g.y, A.g.z, A.mask, C.x, 1.0, A.x, ctx);
+  jv(A.x, A.y);
+  if (l == 0)
+    smooth(part, cgblocks);
+  else
+    smooth(nullptr, mg_blocks(A.N, 4096));
+}
+
+void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, int cgblocks, double* part_rz,
+                      const PcgCtx* ctx) {
+  vcycle(s, levels, 0, nlev, sweeps, cgblocks, part_rz, ctx);
+}
+
+}  // namespace qe

@@ -53,6 +53,14 @@ long sheet_slots(const qe_problem* p);
 qe_status make_quantum(const qe_problem* p, const Charge& ch, Quantum& Q);
 SheetSet make_sheets(const qe_problem* p, std::vector<int4>& items);
 
+// The multigrid preconditioner as the CG loop sees it: the levels (0 = the
+// Context's own mesh) and the coarsest level's smoothing steps.
+struct MgRun {
+  const MgGrid* lv;
+  int nlev;
+  int sweeps;
+};
+
 // One call's view of a problem, its workspace and its stream.
 struct Context {
   qe_problem prob;
@@ -82,15 +90,18 @@ struct Context {
 
   bool no_alloc = false;                // host read-backs in static storage, no events
   HostMirror* hm = nullptr;
+  // wave_kz > 0: the J.v / residual wave tiles' chunk height (else the
+  // library's choice for the mesh)
   qe_status init(const qe_problem* p, const Charge& ch, void* ws, size_t ws_bytes, void* stream, int kz = 0,
-                 bool no_alloc = false);
+                 bool no_alloc = false, int wave_kz = 0);
   Doping doping() const;
   qe_status validate(const double* phi);
   qe_status stage(double* phi, int apply, int zero_free);
   qe_status residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam, bool mixed,
                      double* diag_out, double* norm2_host);
+  // mg: the multigrid preconditioner (FP64 only), or nullptr for Jacobi
   qe_status pcg(bool mixed, const double* b, double sign, double rtol, int maxit, int check_every, int* pcg_status,
-                int* iters);
+                int* iters, const MgRun* mg = nullptr);
   qe_status pcg_polled(bool mixed, const double* b, double sign, double rtol, int maxit, int* pcg_status,
                        int* iters);
 };

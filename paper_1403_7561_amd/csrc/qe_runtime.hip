@@ -395,6 +395,7 @@ qe_status check_options(const qe_options* o) {
   if (o->precision != QE_PREC_FP64 && o->precision != QE_PREC_MIXED) return fail(QE_ERR_INVALID_ARG, "bad precision");
   if (o->init_guess < 0 || o->init_guess > 2) return fail(QE_ERR_INVALID_ARG, "bad init_guess");
   if (o->check_every < 0) return fail(QE_ERR_INVALID_ARG, "check_every < 0");
+  if (o->precond < QE_PC_AUTO || o->precond > QE_PC_MULTIGRID) return fail(QE_ERR_INVALID_ARG, "bad precond");
   return QE_OK;
 }
 
@@ -446,7 +447,7 @@ static HostMirror& plain_mirror() {
 }
 
 qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t ws_bytes, void* stream_, int kz,
-                        bool no_alloc_) {
+                        bool no_alloc_, int wave_kz) {
   no_alloc = no_alloc_;
   QE_TRY(check_problem(p));
   if (ch.incomplete && !p->donors)
@@ -463,7 +464,7 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   g.y = p->y;
   g.z = p->z;
   tm = make_tilemap(p->nx, p->ny, p->nz, kz);
-  wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
+  wm = make_wavemap(p->nx, p->ny, p->nz, wave_kz > 0 ? wave_kz : env_int("QE_JV_KZ", 0));
   // with eigenstates the waves over the dot loop over every state on each of
   // their layers; chunks of kQResidualKz layers shorten that critical path
   wmq = quantum.n > 0 ? quantum_wavemap(p) : wm;
@@ -571,29 +572,41 @@ qe_status Context::residual(const Charge& ch, const double* phi, const double* d
 // Jacobi-PCG on J x = sign*b (free rows).  Returns the CG status through
 // *pcg_status and the iteration count through *iters.
 qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, int maxit, int check_every,
-                       int* pcg_status, int* iters) {
+                       int* pcg_status, int* iters, const MgRun* mg) {
   PcgCtx* dctx = reinterpret_cast<PcgCtx*>(ws + lay.ctx);
   if (no_alloc) return pcg_polled(mixed, b, sign, rtol, maxit, pcg_status, iters);
+  if (mg && (mixed || mg->nlev < 2)) mg = nullptr;
   HostMirror& hm = *this->hm;
   volatile CgProgress* hp = hm.prog;
   hp->word = 0;  // the last decision of an earlier solve has been read: no write is pending
   const int cgb = cg_blocks(N);
-  if (mixed)
+  // with multigrid the CG kernels' z = D^-1 r becomes the V-cycle's first
+  // smoothing step z = S r; the V-cycle then turns z into B r and replaces
+  // the r^T z partials
+  const double* dinv = mg ? mg->lv[0].S : f64(lay.invdiag);
+  if (mixed) {
     launch_pcg_start32(s, cgb, N, sign, b, u8(lay.mask), f32(lay.invdiag32), f32(lay.x32), f32(lay.r32),
                        f32(lay.z32), dctx, f64(lay.partial2), rtol, maxit);
-  else
-    launch_pcg_start64(s, cgb, N, sign, b, u8(lay.mask), f64(lay.invdiag), f64(lay.x), f64(lay.r), f64(lay.z),
-                       dctx, f64(lay.partial2), rtol, maxit);
+  } else {
+    launch_pcg_start64(s, cgb, N, sign, b, u8(lay.mask), dinv, f64(lay.x), f64(lay.r), f64(lay.z), dctx,
+                       f64(lay.partial2), rtol, maxit);
+    if (mg) {
+      launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, cgb, f64(lay.partial2), dctx);
+      launch_mg_start_fin(s, dctx, f64(lay.partial2), cgb);
+    }
+  }
   QE_HIP(hipGetLastError());
   auto queue_iter = [&](int k) {
-    if (mixed)
+    if (mixed) {
       launch_pcg_iter32(s, g, wm, cgb, N, k & 1, f32(lay.eps32), u32(lay.cbits), f32(lay.c32), f32(lay.invdiag32),
                         f32(lay.x32), f32(lay.r32), f32(lay.z32), f32(lay.p32), f32(lay.y32), dctx, hm.prog_dev,
                         f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
-    else
-      launch_pcg_iter64(s, g, wm, cgb, N, k & 1, f64(lay.eps_t), u32(lay.cbits), f64(lay.c), f64(lay.invdiag),
-                        f64(lay.x), f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, hm.prog_dev,
-                        f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
+    } else {
+      launch_pcg_iter64(s, g, wm, cgb, N, k & 1, f64(lay.eps_t), u32(lay.cbits), f64(lay.c), dinv, f64(lay.x),
+                        f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, hm.prog_dev, f64(lay.partial),
+                        f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
+      if (mg) launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, cgb, f64(lay.partial2), dctx);
+    }
   };
   // The host keeps `ahead` iterations queued beyond those it knows have
   // finished (an event is recorded after every kEv-th iteration), so the
@@ -604,7 +617,11 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
 #ifndef QE_CG_EVENT_EVERY
 #define QE_CG_EVENT_EVERY 8
 #endif
-  constexpr int kEv = QE_CG_EVENT_EVERY, kRing = kEventRing;
+  constexpr int kRing = kEventRing;
+  // a multigrid iteration (~25 launches) outlasts the host's reaction to an
+  // event several times over: an event after each, two iterations ahead
+  // (three measured no faster)
+  const int kEv = mg ? 1 : QE_CG_EVENT_EVERY;
   hipEvent_t* ring = events;
   for (int e = 0; e < kRing; ++e)
     if (!ring[e]) QE_HIP(hipEventCreateWithFlags(&ring[e], hipEventDisableTiming));
@@ -612,7 +629,8 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
   // host's reaction to an event, and fewer launches return at once after
   // the stop (measured: 0.5 % faster solves than kEv + 4; events every 4 or
   // 2 iterations cost more than they save)
-  const int ahead = std::min(std::max(check_every > 0 ? check_every : kEv + 1, kEv + 1), kEv * (kRing - 1));
+  const int ahead =
+      mg ? std::min(std::max(1, env_int("QE_MG_AHEAD", 2)), kRing - 1) : std::min(std::max(check_every > 0 ? check_every : kEv + 1, kEv + 1), kEv * (kRing - 1));
   int queued = 0, finished = 0, head = 0, tail = 0;  // events [head, tail) pending, in ring order
   // FP64: the last x += alpha p, queued after every launch of the loop
   auto finish = [&]() -> qe_status {
@@ -711,6 +729,7 @@ using namespace qe;
 
 static size_t fine_layout_bytes(const qe_problem* p);
 static size_t seq_extra_bytes(const qe_problem* p, int levels);
+static size_t extra_bytes(const qe_problem* p, int seq_levels);
 static int seq_levels_wanted();
 
 // ====================================================================== C ABI
@@ -752,27 +771,31 @@ void qe_default_options(qe_options* o) {
   o->precision = QE_PREC_FP64;
   o->init_guess = 2;
   o->check_every = 0;
+  o->precond = QE_PC_AUTO;
 }
 
 size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o) {
   (void)o;
   if (check_problem(p) != QE_OK) return 0;
-  return fine_layout_bytes(p) + seq_extra_bytes(p, seq_levels_wanted());
+  return fine_layout_bytes(p) + extra_bytes(p, seq_levels_wanted());
 }
 
 }  // extern "C"
 
-// The largest layout any Context::init takes for this problem (checked).
-static size_t fine_layout_bytes(const qe_problem* p) {
+// The largest layout Context::init takes for this problem with this wave
+// chunk height (0: the library's choice), checked there.
+static size_t layout_bytes(const qe_problem* p, int wave_kz) {
   const long N = (long)p->nx * p->ny * p->nz;
   const long E = (long)(p->nx - 1) * (p->ny - 1) * (p->nz - 1);
   // the tile map with the smallest chunk height has the most blocks
   TileMap tm = make_tilemap(p->nx, p->ny, p->nz, 1);
-  const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, env_int("QE_JV_KZ", 0));
+  const WaveMap wm = make_wavemap(p->nx, p->ny, p->nz, wave_kz > 0 ? wave_kz : env_int("QE_JV_KZ", 0));
   const long nwq = p->quantum ? quantum_wavemap(p).nwaves : 0;
   return make_layout(N, E, tile_slots(p->nx, p->ny, p->nz), p->nz - 1, wm.nwaves, tm.nblocks, vec_blocks(N),
                      p->n_dir, sheet_slots(p), nwq).total;
 }
+
+static size_t fine_layout_bytes(const qe_problem* p) { return layout_bytes(p, 0); }
 
 // ---------------------------------------------------------------------------
 // Coarse-mesh sequence (init_guess = 2).  The problem coarsened by taking
@@ -802,18 +825,16 @@ struct SeqPlan {
   size_t o_phi, o_ws, total;
 };
 
-static bool seq_plan(const qe_problem* p, char* base, SeqPlan& sp, int levels) {
-  if (levels < 1 || p->n_sheets > 0 || p->quantum) return false;
-  const long N = (long)p->nx * p->ny * p->nz;
-  if (N < env_long("QE_SEQ_MIN_NODES", kSeqMinNodes)) return false;
-  qe_problem& c = sp.pc;
+// The problem coarsened by every other node along each axis (the last node
+// kept): its arrays are carved from base + off (off advances, 256-aligned);
+// false if a dimension would not shrink or would fall below 3 nodes.
+static bool carve_coarse(const qe_problem* p, char* base, size_t& off, qe_problem& c) {
   c = *p;
   c.nx = p->nx / 2 + 1;
   c.ny = p->ny / 2 + 1;
   c.nz = p->nz / 2 + 1;
   if (c.nx < 3 || c.ny < 3 || c.nz < 3 || c.nx >= p->nx || c.ny >= p->ny || c.nz >= p->nz) return false;
   const long Nc = (long)c.nx * c.ny * c.nz, Ec = (long)(c.nx - 1) * (c.ny - 1) * (c.nz - 1);
-  size_t off = 0;
   auto take = [&](size_t b) {
     const size_t o = off;
     off = align256(off + b);
@@ -831,10 +852,23 @@ static bool seq_plan(const qe_problem* p, char* base, SeqPlan& sp, int levels) {
   c.n_sheets = 0;
   c.sheets = nullptr;
   c.quantum = nullptr;
-  sp.o_phi = take(Nc * 8);
+  return check_problem(&c) == QE_OK;
+}
+
+static bool seq_plan(const qe_problem* p, char* base, SeqPlan& sp, int levels) {
+  if (levels < 1 || p->n_sheets > 0 || p->quantum) return false;
+  const long N = (long)p->nx * p->ny * p->nz;
+  if (N < env_long("QE_SEQ_MIN_NODES", kSeqMinNodes)) return false;
+  qe_problem& c = sp.pc;
+  size_t off = 0;
+  if (!carve_coarse(p, base, off, c)) return false;
+  const long Nc = (long)c.nx * c.ny * c.nz;
+  sp.o_phi = off;
+  off = align256(off + Nc * 8);
   sp.o_ws = off;
-  if (check_problem(&c) != QE_OK) return false;
-  off += fine_layout_bytes(&c) + seq_extra_bytes(&c, levels - 1);
+  // the coarse solve's workspace: its own layout and room for its own
+  // sequence or multigrid levels
+  off += fine_layout_bytes(&c) + extra_bytes(&c, levels - 1);
   sp.total = off;
   return true;
 }
@@ -846,6 +880,165 @@ static size_t seq_extra_bytes(const qe_problem* p, int levels) {
   // sizes only: a dummy base that no pointer derived from it is read through
   return seq_plan(p, reinterpret_cast<char*>(size_t(1) << 20), sp, levels) ? sp.total : 0;
 }
+
+// ---------------------------------------------------------------------------
+// Multigrid preconditioner of the FP64 CG (qe_precond; kernels in
+// qe_mg.hip).  The levels are the meshes of the coarse-mesh sequence, down
+// to the last one with at least kMgMinCoarse nodes; each coarse level has
+// its problem arrays, its potential, its smoother weights and a Context
+// layout (whose r, x and y hold the V-cycle's b, x and J x), after the fine
+// layout in the caller's workspace (the region the sequence's coarse solve
+// used before Newton started).  Level 0 adds its smoother weights and a J x
+// vector there; its b and x are the CG's r and z.
+static const long kMgMinNodes = 250000;
+static const long kMgMinCoarse = 2000;
+static const int kMgMaxLevels = 6;
+// AUTO: multigrid for CG tolerances at or below this one.  At the
+// 129x129x65 stack a V-cycle costs ~7 Jacobi iterations (its small levels
+// are launch- and latency-bound) and saves ~10x the iterations on the last
+// Newton steps; measured there, 1e-2 / 3e-2 / 1e-1 / every step gave
+// 13.4 / 13.4 / 13.5 / 15.0 ms per solve against 17.8 ms with Jacobi only.
+static const double kMgEta = 3e-2;
+// Smoothing steps on the coarsest mesh (4 measured faster than 2: 40 against
+// 49 iterations in the adjoint, 8.8 against 9.8 ms).
+static const int kMgSweeps = 4;
+// Chunk height of the coarse levels' wave tiles: their meshes are small, so
+// short chunks give the J.v and the residual more waves (latency, not
+// bandwidth, bounds them there; 1 / 2 / 4 measured 8.8 / 9.0 / 9.5 ms for
+// the adjoint above).
+static const int kMgCoarseKz = 1;
+static int mg_coarse_kz() { return std::max(1, env_int("QE_MG_KZ", kMgCoarseKz)); }
+
+struct MgPlan {
+  int nlev = 0;
+  qe_problem pc[kMgMaxLevels];
+  size_t o_y0 = 0, o_S[kMgMaxLevels] = {}, o_phi[kMgMaxLevels] = {}, o_ws[kMgMaxLevels] = {},
+         ws_bytes[kMgMaxLevels] = {};
+  size_t total = 0;
+};
+
+static bool mg_plan(const qe_problem* p, char* base, MgPlan& mp) {
+  mp.nlev = 0;
+  if (p->n_sheets > 0 || p->quantum) return false;
+  const long N = (long)p->nx * p->ny * p->nz;
+  if (N < env_long("QE_MG_MIN_NODES", kMgMinNodes)) return false;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off = align256(off + b);
+    return o;
+  };
+  mp.pc[0] = *p;
+  mp.o_S[0] = take(N * 8);
+  mp.o_y0 = take(N * 8);
+  int L = 1;
+  while (L < kMgMaxLevels) {
+    qe_problem c;
+    size_t o2 = off;
+    if (!carve_coarse(&mp.pc[L - 1], base, o2, c)) break;
+    const long Nc = (long)c.nx * c.ny * c.nz;
+    if (Nc < kMgMinCoarse) break;
+    off = o2;
+    mp.pc[L] = c;
+    mp.o_phi[L] = take(Nc * 8);
+    mp.o_S[L] = take(Nc * 8);
+    mp.ws_bytes[L] = layout_bytes(&c, mg_coarse_kz());
+    mp.o_ws[L] = take(mp.ws_bytes[L]);
+    ++L;
+  }
+  if (L < 2) return false;
+  mp.nlev = L;
+  mp.total = off;
+  return true;
+}
+
+static size_t mg_extra_bytes(const qe_problem* p) {
+  MgPlan mp;
+  return mg_plan(p, reinterpret_cast<char*>(size_t(1) << 20), mp) ? mp.total : 0;
+}
+
+// Room after the fine layout: the sequence's coarse solve before Newton and
+// the multigrid levels during it use the same region.
+static size_t extra_bytes(const qe_problem* p, int seq_levels) {
+  return std::max(seq_extra_bytes(p, seq_levels), mg_extra_bytes(p));
+}
+
+static double mg_eta() { return env_double("QE_MG_ETA", kMgEta); }
+
+// One call's multigrid levels: planned when the call may use them, set up
+// on first use, linearised at each potential a CG solve with them starts
+// from.
+struct MgState {
+  MgPlan plan;
+  char* base = nullptr;
+  bool possible = false, ready = false;
+  Context cx[kMgMaxLevels];   // levels 1 .. nlev - 1
+  MgGrid lv[kMgMaxLevels];
+  MgRun run{};
+
+  // Whether multigrid can serve this call (FP64, an allocating entry point,
+  // a large enough plain mesh, room in the workspace).
+  void plan_for(const qe_problem* p, const qe_options* o, void* ws, size_t ws_bytes, bool mixed, bool no_alloc) {
+    possible = false;
+    if (mixed || no_alloc || o->precond == QE_PC_JACOBI) return;
+    const size_t fine = align256(fine_layout_bytes(p));
+    if (ws_bytes < fine) return;
+    base = reinterpret_cast<char*>(ws) + fine;
+    possible = mg_plan(p, base, plan) && ws_bytes - fine >= plan.total;
+  }
+  bool wanted(const qe_options* o, double eta) const {
+    return possible && (o->precond == QE_PC_MULTIGRID || eta <= mg_eta());
+  }
+  qe_status setup(Context& fine, const Charge& ch) {
+    for (int l = 1; l < plan.nlev; ++l) {
+      launch_seq_coarsen(fine.s, &plan.pc[l - 1], &plan.pc[l]);
+      QE_HIP(hipGetLastError());
+      QE_TRY(cx[l].init(&plan.pc[l], ch, base + plan.o_ws[l], plan.ws_bytes[l], fine.s, 0, false, mg_coarse_kz()));
+      QE_TRY(cx[l].stage(nullptr, 0, 0));
+    }
+    for (int l = 0; l < plan.nlev; ++l) {
+      Context& c = l == 0 ? fine : cx[l];
+      MgGrid& G = lv[l];
+      G.g = c.g;
+      G.wm = c.wm;
+      G.N = c.N;
+      G.eps_t = c.f64(c.lay.eps_t);
+      G.cbits = c.u32(c.lay.cbits);
+      G.cq = c.f64(c.lay.c);
+      G.mask = c.u8(c.lay.mask);
+      G.S = reinterpret_cast<double*>(base + plan.o_S[l]);
+      G.b = c.f64(c.lay.r);
+      G.x = l == 0 ? c.f64(c.lay.z) : c.f64(c.lay.x);
+      G.y = l == 0 ? reinterpret_cast<double*>(base + plan.o_y0) : c.f64(c.lay.y);
+    }
+    run = MgRun{lv, plan.nlev, std::max(1, env_int("QE_MG_SWEEPS", kMgSweeps))};
+    ready = true;
+    return QE_OK;
+  }
+  // The coarse levels' Jacobians at the potential injected from phi (the
+  // fine level's was formed by the caller's last residual at phi), then
+  // every level's smoother weights.
+  qe_status linearize(Context& fine, const Charge& ch, const double* phi) {
+    const double* src = phi;
+    for (int l = 1; l < plan.nlev; ++l) {
+      double* ph = reinterpret_cast<double*>(base + plan.o_phi[l]);
+      launch_mg_inject(fine.s, lv[l - 1], lv[l], src, ph);
+      QE_TRY(cx[l].residual(ch, ph, nullptr, nullptr, 0.0, false, nullptr, nullptr));
+      src = ph;
+    }
+    for (int l = 0; l < plan.nlev; ++l) {
+      Context& c = l == 0 ? fine : cx[l];
+      launch_mg_l1(fine.s, lv[l], c.prob.eps_r, c.u8(c.lay.cflag), lv[l].S);
+    }
+    QE_HIP(hipGetLastError());
+    return QE_OK;
+  }
+  // Ready to serve a CG solve at phi (set up on first use).
+  qe_status prepare(Context& fine, const Charge& ch, const double* phi) {
+    if (!ready) QE_TRY(setup(fine, ch));
+    return linearize(fine, ch, phi);
+  }
+};
 
 extern "C" {
 
@@ -916,6 +1109,8 @@ static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_
   }
   const int check = o->check_every;
   int pst = 0, its = 0;
+  MgState mg;
+  mg.plan_for(p, o, ws, ws_bytes, mixed, no_alloc);
   if (linear) {
     // charge-free linear Poisson with the doping kept: one Newton step from
     // phi = (Dirichlet values, 0) on the linear problem
@@ -955,9 +1150,16 @@ static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_
     eta = std::max(eta, 0.5 * o->newton_atol / nrm);
     eta = std::min(eta, o->krylov_rtol_max);
     eta = std::max(eta, mixed ? 1e-6 : 1e-13);
-    qe_status s2 = cx.pcg(mixed, cx.f64(cx.lay.F), -1.0, eta, o->krylov_maxit, check, &pst, &its);
+    const bool use_mg = mg.wanted(o, eta);
+    if (use_mg && (st = mg.prepare(cx, ch, phi)) != QE_OK) return finish(st, r, rep);
+    qe_status s2 = cx.pcg(mixed, cx.f64(cx.lay.F), -1.0, eta, o->krylov_maxit, check, &pst, &its,
+                          use_mg ? &mg.run : nullptr);
     if (s2 != QE_OK) return finish(s2, r, rep);
     r.krylov_iters += its;
+    if (use_mg) {
+      r.mg_krylov_iters += its;
+      r.mg_levels = mg.plan.nlev;
+    }
     if (pst == PCG_BREAKDOWN || pst == PCG_NONFINITE) {
       st = fail(pst == PCG_BREAKDOWN ? QE_ERR_KRYLOV_BREAKDOWN : QE_ERR_NONFINITE, "Newton step %d: CG failed (status %d)",
                 it, pst);
@@ -1256,9 +1458,18 @@ qe_status qe_adjoint(const qe_problem* p, const qe_physics* ph, const qe_options
   launch_adj_rhs(cx.s, cx.g, cx.tm, ch, bx, p->semi, phi, cx.f64(cx.lay.gvec), cx.f64(cx.lay.partial), counters + 2,
                  cx.f64(cx.lay.scal) + 1);
   int pst = 0, its = 0;
-  if ((st = cx.pcg(false, cx.f64(cx.lay.gvec), 1.0, 1e-12, o->krylov_maxit, o->check_every, &pst, &its)) != QE_OK)
+  MgState mg;
+  mg.plan_for(p, o, ws, ws_bytes, false, false);
+  const bool use_mg = mg.wanted(o, 1e-12);
+  if (use_mg && (st = mg.prepare(cx, ch, phi)) != QE_OK) return finish(st, r, rep);
+  if ((st = cx.pcg(false, cx.f64(cx.lay.gvec), 1.0, 1e-12, o->krylov_maxit, o->check_every, &pst, &its,
+                   use_mg ? &mg.run : nullptr)) != QE_OK)
     return finish(st, r, rep);
   r.krylov_iters = its;
+  if (use_mg) {
+    r.mg_krylov_iters = its;
+    r.mg_levels = mg.plan.nlev;
+  }
   if (pst == PCG_BREAKDOWN || pst == PCG_NONFINITE)
     return finish(fail(pst == PCG_BREAKDOWN ? QE_ERR_KRYLOV_BREAKDOWN : QE_ERR_NONFINITE, "adjoint CG failed (status %d)",
                        pst), r, rep);

@@ -87,14 +87,16 @@ class COptions(ctypes.Structure):
     _fields_ = [("newton_atol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
                 ("ls_max_halvings", ctypes.c_int32), ("krylov_rtol_max", ctypes.c_double),
                 ("krylov_maxit", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("init_guess", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("init_guess", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("precond", ctypes.c_int32)]
 
 
 class CReport(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("newton_iters", ctypes.c_int32),
                 ("krylov_iters", ctypes.c_int32), ("ls_halvings", ctypes.c_int32),
                 ("init_krylov_iters", ctypes.c_int32), ("n_residual_evals", ctypes.c_int32),
-                ("res0", ctypes.c_double), ("res_final", ctypes.c_double), ("seq_levels", ctypes.c_int32)]
+                ("res0", ctypes.c_double), ("res_final", ctypes.c_double), ("seq_levels", ctypes.c_int32),
+                ("mg_levels", ctypes.c_int32), ("mg_krylov_iters", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -123,14 +123,23 @@ def test_workspace_scales_with_mesh(monkeypatch):
     big = lib.qe_workspace_bytes(ctypes.byref(fake_problem(129, 129, 65)), ctypes.byref(o))
     N = 129 * 129 * 65
     assert big > small
-    # without the coarse-mesh sequence: about 7 FP64 + 5 FP32 nodal vectors,
-    # FP64 + FP32 Gauss-point coefficients
-    monkeypatch.setenv("QE_SEQ_MIN_NODES", str(10 ** 12))
-    fine = lib.qe_workspace_bytes(ctypes.byref(fake_problem(129, 129, 65)), ctypes.byref(o))
+    def size(seq, mg):
+        monkeypatch.setenv("QE_SEQ_MIN_NODES", "1" if seq else str(10 ** 12))
+        monkeypatch.setenv("QE_MG_MIN_NODES", "1" if mg else str(10 ** 12))
+        return lib.qe_workspace_bytes(ctypes.byref(fake_problem(129, 129, 65)), ctypes.byref(o))
+    # without the coarse-mesh sequence and multigrid: about 7 FP64 + 5 FP32
+    # nodal vectors, FP64 + FP32 Gauss-point coefficients
+    fine = size(False, False)
     assert 150 * N < fine < 230 * N
     # the sequence's coarse level (65 x 65 x 33, an eighth of the nodes) adds
     # its arrays and its own layout
-    assert fine / 10 < big - fine < fine / 6
+    assert fine / 10 < size(True, False) - fine < fine / 6
+    # multigrid: the fine level's smoother weights and J x (16 B per node)
+    # plus three coarse levels (an eighth, a 64th, a 512th of the nodes)
+    mg = size(False, True) - fine
+    assert 16 * N + fine / 10 < mg < 16 * N + fine / 5
+    # both share one region after the fine layout
+    assert size(True, True) - fine == max(size(True, False) - fine, mg) == big - fine
 
 
 def test_count_and_adjoint_argument_checks():

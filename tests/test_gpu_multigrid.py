@@ -1,0 +1,144 @@
+"""The multigrid preconditioner of the FP64 CG (qe_options.precond): a
+symmetric V-cycle on the meshes of the coarse-mesh sequence, so the CG it
+preconditions still converges to the one discrete solution.  These tests
+lower the size threshold (QE_MG_MIN_NODES) so that meshes the oracle solves
+quickly run it: solves and the adjoint against the oracle with multigrid on
+every CG (odd and even node counts: the restriction's clamped last coarse
+interval), far fewer iterations than Jacobi, the fallbacks to Jacobi, and
+the 129 x 129 x 65 stack's default solve and adjoint against the Jacobi
+ones."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import solver
+from paper_1403_7561_amd import qe
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+JACOBI, MULTIGRID = 1, 2
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def double_dot(nx, ny, nz, volts=(1.5, 1.4, 0.5, 0.7, 0.3)):
+    return synth.double_dot_device(f"mg{nx}x{ny}x{nz}", nx, ny, nz, np.array(volts))
+
+
+@pytest.mark.parametrize("dims,levels", [
+    ((33, 33, 17), 2),      # odd counts: 17x17x9 (9x9x5 has fewer than 2000 nodes)
+    ((36, 30, 20), 2),      # even counts: 19x16x11, the last coarse interval spans one fine one
+    ((65, 57, 33), 3),      # 33x29x17, 17x15x9
+])
+def test_multigrid_solve_matches_oracle(monkeypatch, dims, levels):
+    monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
+    dev = double_dot(*dims)
+    P = qe.Problem(dev)
+    phi, _, rep = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-10, precond=MULTIGRID))
+    phj, _, repj = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-10, precond=JACOBI))
+    print(dims, "multigrid", rep, "\njacobi", repj)
+    assert rep["status"] == 0 and rep["res_final"] <= 1e-10
+    assert rep["mg_levels"] == levels and repj["mg_levels"] == 0
+    # every Newton step's CG ran with the V-cycle; the linear guess with Jacobi
+    assert rep["mg_krylov_iters"] == rep["krylov_iters"] - rep["init_krylov_iters"] > 0
+    assert rep["mg_krylov_iters"] * 2 < repj["krylov_iters"] - repj["init_krylov_iters"]
+    _, res = solver.solve(dev, atol=1e-10)
+    assert rel_max(phi.cpu().numpy(), res.phi) <= 1e-9
+    assert rel_max(phi.cpu().numpy(), phj.cpu().numpy()) <= 1e-9
+
+
+def test_multigrid_full_charge_and_sequence(monkeypatch):
+    """Donor and acceptor arrays and hole charge on the coarse levels, with
+    the coarse-mesh sequence's start (both use the region after the fine
+    layout, one after the other)."""
+    monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
+    monkeypatch.setenv("QE_SEQ_MIN_NODES", "1000")
+    from tests import gpu_support as gs
+    dev = gs.full_charge_device("incomplete")
+    P = qe.Problem(dev)
+    phi, _, rep = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-10, precond=MULTIGRID))
+    print(rep)
+    assert rep["status"] == 0 and rep["seq_levels"] == 1 and rep["mg_levels"] >= 2 and rep["mg_krylov_iters"] > 0
+    _, res = solver.solve(dev, atol=1e-10)
+    assert rel_max(phi.cpu().numpy(), res.phi) <= 1e-9
+
+
+def test_multigrid_adjoint_matches_oracle(monkeypatch):
+    """dQ/dV, dQ/deps and lambda with the V-cycle in the adjoint CG against
+    the oracle's adjoint at the oracle's potential (1e-10, as Jacobi)."""
+    monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
+    dev = double_dot(33, 33, 17, volts=(1.6, 1.5, 0.5, 0.8, 0.4))
+    box = dev.boxes["D1"]
+    po, res = solver.solve(dev, atol=1e-11)
+    adj = solver.adjoint(po, res.phi, box)
+    P = qe.Problem(dev)
+    ph = torch.as_tensor(res.phi, device="cuda")
+    Q, dV, deps, lam, rep = qe.qe_adjoint(P, ph, box, want_lam=True)
+    Qj, dVj, _, _, repj = qe.qe_adjoint(P, ph, box, opts=qe.qe_default_options(precond=JACOBI))
+    print("multigrid", rep, "jacobi", repj)
+    print("rel dV", rel_max(np.asarray(dV), adj.dQ_ddir), "deps", rel_max(deps.cpu().numpy(), adj.dQ_deps),
+          "lam", rel_max(lam.cpu().numpy(), adj.lam))
+    assert Q == pytest.approx(adj.Q, rel=1e-12)
+    assert rel_max(np.asarray(dV), adj.dQ_ddir) <= 1e-10
+    assert rel_max(deps.cpu().numpy(), adj.dQ_deps) <= 1e-10
+    assert rel_max(lam.cpu().numpy(), adj.lam) <= 1e-10
+    assert rep["mg_levels"] == 2 and rep["mg_krylov_iters"] == rep["krylov_iters"] > 0
+    assert rep["krylov_iters"] * 2 < repj["krylov_iters"]
+
+
+def test_multigrid_fallbacks(monkeypatch):
+    """Jacobi runs instead below the size threshold, in mixed precision, with
+    sheets, with eigenstates, in a workspace without room for the levels and
+    in the static entry point."""
+    dev = double_dot(33, 33, 17)
+    P = qe.Problem(dev)
+    mg = qe.qe_default_options(newton_atol=1e-10, precond=MULTIGRID)
+    _, _, rep = qe.qe_solve(P, opts=mg)                 # 18513 nodes < 250000
+    assert rep["status"] == 0 and rep["mg_levels"] == 0 and rep["mg_krylov_iters"] == 0
+    monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
+    _, _, rep = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-10, precond=MULTIGRID, precision="mixed"))
+    assert rep["status"] == 0 and rep["mg_levels"] == 0
+    monkeypatch.setenv("QE_MG_MIN_NODES", str(10 ** 12))
+    fine_only = qe.qe_workspace_bytes(P, mg)
+    monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
+    assert qe.qe_workspace_bytes(P, mg) > fine_only
+    _, _, rep = qe.qe_solve(P, opts=mg, ws=qe.Workspace(fine_only, P.device))
+    assert rep["status"] == 0 and rep["mg_levels"] == 0
+    sdev = synth.with_interface_charge(dev, 1e-3, seed=5, spread=0.5)
+    _, _, rep = qe.qe_solve(qe.Problem(sdev), opts=mg)
+    assert rep["status"] == 0 and rep["mg_levels"] == 0
+    _, res = solver.solve(dev, atol=1e-10)
+    st = synth.box_states(dev, (10.0, 60.0, 80.0, 120.0, 75.0, 90.0), 4, res.phi, seed=3, e0=-0.003, spacing=0.0006)
+    _, _, rep = qe.qe_solve(qe.Problem(synth.with_quantum(dev, st)), opts=mg)
+    assert rep["status"] == 0 and rep["mg_levels"] == 0
+    phi = torch.zeros(P.N, dtype=torch.float64, device=P.device)
+    rep = qe.qe_solve_static(P, phi, None, opts=mg)
+    torch.cuda.synchronize()
+    assert rep["status"] == 0 and rep["mg_levels"] == 0
+
+
+def test_benchmark_mesh_default_uses_multigrid():
+    """129 x 129 x 65: the default options run the V-cycle on the Newton
+    steps with tight CG tolerances and in the adjoint; the potential and the
+    gradient equal the Jacobi-only ones (both CGs converge to the one
+    discrete solution, to their tolerances)."""
+    dev = synth.config2()
+    P = qe.Problem(dev)
+    phi, _, rep = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-10))
+    phj, _, repj = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-10, precond=JACOBI))
+    print("default", rep, "\njacobi", repj)
+    assert rep["mg_levels"] == 4 and 0 < rep["mg_krylov_iters"] and repj["mg_levels"] == 0
+    assert rep["krylov_iters"] < repj["krylov_iters"]
+    assert rel_max(phi.cpu().numpy(), phj.cpu().numpy()) <= 1e-11
+    box = dev.boxes["D1"]
+    Q, dV, deps, _, arep = qe.qe_adjoint(P, phj, box)
+    Qj, dVj, depsj, _, arepj = qe.qe_adjoint(P, phj, box, opts=qe.qe_default_options(precond=JACOBI))
+    print("adjoint", arep, arepj)
+    assert arep["mg_levels"] == 4 and arep["krylov_iters"] * 5 < arepj["krylov_iters"]
+    assert Q == pytest.approx(Qj, rel=1e-13)
+    assert rel_max(np.asarray(dV), np.asarray(dVj)) <= 1e-9
+    assert rel_max(deps.cpu().numpy(), depsj.cpu().numpy()) <= 1e-9

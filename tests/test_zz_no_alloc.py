@@ -58,10 +58,11 @@ def test_static_workspace_rejects_problems_that_need_more():
 def test_static_workspace_sequenced_solve_at_the_benchmark_size():
     """129x129x65: the static array also holds the coarse level of the
     default coarse-mesh sequence, which then runs without allocating; the
-    solve matches qe_solve's."""
+    solve matches qe_solve's (with the Jacobi preconditioner, the only one
+    the static entry point runs)."""
     dev = synth.config2()
     P = qe.Problem(dev)
-    opts = qe.qe_default_options(newton_atol=1e-10)
+    opts = qe.qe_default_options(newton_atol=1e-10, precond=1)
     phi_ref, _, rep_ref = qe.qe_solve(P, opts=opts, want_density=False)
     phi = torch.zeros(P.N, dtype=torch.float64, device=P.device)
     rep = qe.qe_solve_static(P, phi, None, opts=opts)
