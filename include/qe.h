@@ -87,7 +87,7 @@ typedef enum {
                                     Newton update in FP64 */
 } qe_precision;
 
-/* Preconditioner of the FP64 CG (the paper's solver library leaves it to
+/* Preconditioner of the CG (the paper's solver library leaves it to
  * the user; Sec. II.A.3).  Jacobi: z = D^-1 r.  Multigrid: a symmetric
  * V-cycle on the meshes of the coarse-mesh sequence (every other node along
  * each axis, the last kept, while the coarser mesh keeps at least 2000
@@ -98,9 +98,10 @@ typedef enum {
  * so the CG stays plain CG.  AUTO takes multigrid for the Newton steps whose
  * CG tolerance is at most 3e-2 and for the adjoint, where one V-cycle (the
  * cost of about seven Jacobi iterations at 129 x 129 x 65) saves more
- * iterations than it costs, and Jacobi otherwise.  Multigrid needs a mesh of at least 250000 nodes
- * without sheets or eigenstates, FP64, and an entry point that allocates;
- * elsewhere every choice runs Jacobi. */
+ * iterations than it costs, and Jacobi otherwise.  In mixed precision the
+ * V-cycle runs in FP32 like the CG it serves.  Multigrid needs a mesh of at
+ * least 250000 nodes without sheets or eigenstates and an entry point that
+ * allocates; elsewhere every choice runs Jacobi. */
 typedef enum {
   QE_PC_AUTO = 0,
   QE_PC_JACOBI = 1,

@@ -69,29 +69,35 @@ void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* m
 // owns), and the coarse potential interpolated onto the fine nodes.
 void launch_seq_coarsen(hipStream_t s, const qe_problem* f, const qe_problem* c);
 void launch_seq_prolong(hipStream_t s, const qe_problem* f, const qe_problem* c, const double* phic, double* phif);
-// Multigrid preconditioner of the FP64 CG (qe_mg.hip): one level's mesh,
-// linearisation (the arrays of its residual) and vectors.  On level 0, b is
-// the CG's r, x its z and S the array the CG kernels use in place of D^-1.
+// Multigrid preconditioner of the CG (qe_mg.hip): one level's mesh,
+// linearisation (the arrays of its residual) and vectors, in FP64 and, for
+// the mixed-precision CG, FP32.  On level 0, b is the CG's r, x its z and S
+// the array the CG kernels use in place of D^-1.
 struct MgGrid {
   Geom g;
   WaveMap wm;
   long N;
-  const double* eps_t;         // tile-major permittivity
   const unsigned int* cbits;   // J.v lanes' coefficient flags
-  const double* cq;            // tile-major Gauss-point coefficients
   const uint8_t* mask;         // Dirichlet nodes
+  const double* eps_t;         // tile-major permittivity
+  const double* cq;            // tile-major Gauss-point coefficients
   double* S;                   // l1-Jacobi smoother weights (0 on Dirichlet nodes)
   double *b, *x, *y;           // right-hand side, iterate, J x
+  const float* eps32;          // the same in FP32
+  const float* cq32;
+  float* S32;
+  float *b32, *x32, *y32;
 };
 // phi_c = phi_f at the coarse level's nodes f(I) = min(2 I, n - 1).
 void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic);
-// L.S from the level's permittivity (natural element order), coefficient
-// flags and coefficients.
-void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, double* S);
-// z = B r on level 0 (x = S r on entry); one r^T z partial per block of the
-// last kernel (cgblocks blocks) into part_rz.  Skipped once ctx->done.
+// L.S (and L.S32 with fp32) from the level's permittivity (natural element
+// order), coefficient flags and FP64 coefficients.
+void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, bool fp32);
+// z = B r on level 0 (x = S r on entry), in FP32 with fp32; one r^T z
+// partial per block of the last kernel (cgblocks blocks) into part_rz.
+// Skipped once ctx->done.
 void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, int cgblocks, double* part_rz,
-                      const PcgCtx* ctx);
+                      const PcgCtx* ctx, bool fp32);
 // After a CG start with z = S r and the V-cycle: r_0^T z_0 and the
 // tolerance from the V-cycle's partials.
 void launch_mg_start_fin(hipStream_t s, PcgCtx* ctx, const double* part, int n);

@@ -1,4 +1,4 @@
-// Geometric multigrid preconditioner of the FP64 CG (kernels and host
+// Geometric multigrid preconditioner of the CG (kernels and host
 // launchers).  The paper solves each Newton step with a preconditioned
 // Krylov method from its solver library and names no preconditioner
 // (Sec. II.A.3 and II.C); this one is a symmetric V-cycle on the meshes of
@@ -21,6 +21,10 @@
 // weights, and for the Gauss-point coefficient term, whose entries are all
 // >= 0 and whose trilinear weights sum to 1, the row sum B^T c.  Both bound
 // the assembled row's absolute sum from above.
+//
+// The V-cycle runs in the CG's own precision: FP64, or FP32 inside the
+// mixed-precision Newton (FP32 coefficients, permittivities, smoother
+// weights and vectors; restriction sums and the r^T z partials in FP64).
 //
 // Every kernel here returns at once when the CG it serves has stopped
 // (ctx->done), like the CG loop's own kernels, so launches queued after the
@@ -78,10 +82,11 @@ __device__ __forceinline__ void mg_taps(int I, int nf, int nc, const double* __r
 
 // y = J v on one level, as the library's plain J.v (v read as 0 on Dirichlet
 // nodes; their rows are left as computed and masked by the consumers).
+template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_mg_jv(
-    Geom g, WaveMap wm, const double* __restrict__ eps, const unsigned int* __restrict__ cbits,
-    const double* __restrict__ cq, const uint8_t* __restrict__ mask, const double* __restrict__ v,
-    double* __restrict__ y, const PcgCtx* __restrict__ ctx) {
+    Geom g, WaveMap wm, const T* __restrict__ eps, const unsigned int* __restrict__ cbits,
+    const T* __restrict__ cq, const uint8_t* __restrict__ mask, const T* __restrict__ v,
+    T* __restrict__ y, const PcgCtx* __restrict__ ctx) {
   if (ctx->done) return;
   const int w = __builtin_amdgcn_readfirstlane(wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6));
   const bool active = w < wm.nwaves;
@@ -90,22 +95,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const WaveTile t(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   const unsigned int cb = active ? cbits[64L * w + (threadIdx.x & 63)] : 0u;
   double dot = 0.0;
-  jv_tile<double, JV_PLAIN>(g, t, eps, cb, cq, mask, v, y, 0, dot);
+  jv_tile<T, JV_PLAIN>(g, t, eps, cb, cq, mask, v, y, 0, dot);
 }
 
 // Coarse node (I, J, K): b_c = sum over fine nodes of P_fine,coarse *
-// (r - ys * y) (fine Dirichlet nodes count as 0), 0 on coarse Dirichlet
+// (r - y) (fine Dirichlet nodes count as 0), 0 on coarse Dirichlet
 // nodes; x_c = S_c b_c (the pre-smoothing step from zero).
+template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
                                                               const double* __restrict__ xf,
                                                               const double* __restrict__ yf,
                                                               const double* __restrict__ zf,
                                                               const uint8_t* __restrict__ maskf,
-                                                              const double* __restrict__ r,
-                                                              const double* __restrict__ y, double ys,
+                                                              const T* __restrict__ r, const T* __restrict__ y,
                                                               const uint8_t* __restrict__ maskc,
-                                                              const double* __restrict__ Sc, double* __restrict__ bc,
-                                                              double* __restrict__ xc, const PcgCtx* __restrict__ ctx) {
+                                                              const T* __restrict__ Sc, T* __restrict__ bc,
+                                                              T* __restrict__ xc, const PcgCtx* __restrict__ ctx) {
   if (ctx->done) return;
   const long Nc = (long)nxc * nyc * nzc;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < Nc; t += (long)gridDim.x * blockDim.x) {
@@ -128,29 +133,31 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, i
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const long n = row + ix[a];
-            const double v = maskf[n] ? 0.0 : r[n] - ys * y[n];
+            const double v = maskf[n] ? 0.0 : (double)r[n] - (double)y[n];
             b += (wyz * wx[a]) * v;
           }
         }
     }
-    bc[t] = b;
-    xc[t] = Sc[t] * b;
+    const T bt = (T)b;
+    bc[t] = bt;
+    xc[t] = Sc[t] * bt;
   }
 }
 
-// Fine node: x = xs * x + (P x_c) on free nodes, 0 on Dirichlet nodes.
+// Fine node: x += P x_c on free nodes, 0 on Dirichlet nodes.
+template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
                                                              const double* __restrict__ xf,
                                                              const double* __restrict__ yf,
                                                              const double* __restrict__ zf,
                                                              const uint8_t* __restrict__ maskf,
-                                                             const double* __restrict__ xcv, double xs,
-                                                             double* __restrict__ x, const PcgCtx* __restrict__ ctx) {
+                                                             const T* __restrict__ xcv, T* __restrict__ x,
+                                                             const PcgCtx* __restrict__ ctx) {
   if (ctx->done) return;
   const long Nf = (long)nxf * nyf * nzf;
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < Nf; n += (long)gridDim.x * blockDim.x) {
     if (maskf[n]) {
-      x[n] = 0.0;
+      x[n] = T(0);
       continue;
     }
     const int i = (int)(n % nxf), j = (int)((n / nxf) % nyf), k = (int)(n / ((long)nxf * nyf));
@@ -160,29 +167,30 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, in
     mg_weight(j, nyf, nyc, yf, J, wy);
     mg_weight(k, nzf, nzc, zf, K, wz);
     const long c0 = (long)I + (long)nxc * ((long)J + (long)nyc * K), sy = nxc, sz = (long)nxc * nyc;
-    const double v00 = xcv[c0] + wx * (xcv[c0 + 1] - xcv[c0]);
-    const double v10 = xcv[c0 + sy] + wx * (xcv[c0 + sy + 1] - xcv[c0 + sy]);
-    const double v01 = xcv[c0 + sz] + wx * (xcv[c0 + sz + 1] - xcv[c0 + sz]);
-    const double v11 = xcv[c0 + sz + sy] + wx * (xcv[c0 + sz + sy + 1] - xcv[c0 + sz + sy]);
+    double c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c[q] = (double)xcv[c0 + (q & 1) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0)];
+    const double v00 = c[0] + wx * (c[1] - c[0]), v10 = c[2] + wx * (c[3] - c[2]);
+    const double v01 = c[4] + wx * (c[5] - c[4]), v11 = c[6] + wx * (c[7] - c[6]);
     const double v0 = v00 + wy * (v10 - v00), v1 = v01 + wy * (v11 - v01);
-    x[n] = xs * x[n] + (v0 + wz * (v1 - v0));
+    x[n] = (T)((double)x[n] + (v0 + wz * (v1 - v0)));
   }
 }
 
 // x += S (b - y) (S is 0 on Dirichlet nodes); with part, one partial of
 // b^T x per block (the CG's r^T z after the fine level's last step).
-__global__ __launch_bounds__(kVecThreads) void k_mg_smooth(long N, const double* __restrict__ b,
-                                                            const double* __restrict__ y,
-                                                            const double* __restrict__ S, double* __restrict__ x,
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_mg_smooth(long N, const T* __restrict__ b, const T* __restrict__ y,
+                                                            const T* __restrict__ S, T* __restrict__ x,
                                                             double* __restrict__ part, const PcgCtx* __restrict__ ctx) {
   if (ctx->done) return;
   __shared__ double sred[kVecThreads / 64];
   double bz = 0.0;
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
-    const double bn = b[n];
-    const double xn = x[n] + S[n] * (bn - y[n]);
+    const T bn = b[n];
+    const T xn = x[n] + S[n] * (bn - y[n]);
     x[n] = xn;
-    bz += bn * xn;
+    bz += (double)bn * (double)xn;
   }
   if (part) {
     const double s1 = block_sum(bz, sred);
@@ -236,12 +244,14 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_inject(int nxf, int nyf, int
 __global__ __launch_bounds__(kVecThreads) void k_mg_l1(Geom g, const double* __restrict__ eps,
                                                         const uint8_t* __restrict__ cflag,
                                                         const double* __restrict__ cq,
-                                                        const uint8_t* __restrict__ mask, double* __restrict__ S) {
+                                                        const uint8_t* __restrict__ mask, double* __restrict__ S,
+                                                        float* __restrict__ S32) {
   const long N = (long)g.nx * g.ny * g.nz;
   const int gx = (g.nx + 6) / 7, gy = (g.ny + 6) / 7;
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
     if (mask[n]) {
       S[n] = 0.0;
+      if (S32) S32[n] = 0.0f;
       continue;
     }
     const int i = (int)(n % g.nx), j = (int)((n / g.nx) % g.ny), k = (int)(n / ((long)g.nx * g.ny));
@@ -275,6 +285,7 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_l1(Geom g, const double* __r
           }
         }
     S[n] = sum > 0.0 ? 1.0 / sum : 0.0;
+    if (S32) S32[n] = (float)S[n];
   }
 }
 
@@ -287,42 +298,62 @@ void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const dou
             phic);
 }
 
-void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, double* S) {
-  QE_LAUNCH(k_mg_l1, mg_blocks(L.N, 8192), kVecThreads, s, L.g, eps_natural, cflag, L.cq, L.mask, S);
+void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, bool fp32) {
+  QE_LAUNCH(k_mg_l1, mg_blocks(L.N, 8192), kVecThreads, s, L.g, eps_natural, cflag, L.cq, L.mask, L.S,
+            fp32 ? L.S32 : nullptr);
 }
 
 void launch_mg_start_fin(hipStream_t s, PcgCtx* ctx, const double* part, int n) {
   QE_LAUNCH(k_mg_start_fin, 1, kVecThreads, s, ctx, part, n);
 }
 
+// A level's arrays in the V-cycle's precision.
+template <typename T>
+struct MgView;
+template <>
+struct MgView<double> {
+  const double *eps, *cq, *S;
+  double *b, *x, *y;
+  explicit MgView(const MgGrid& G) : eps(G.eps_t), cq(G.cq), S(G.S), b(G.b), x(G.x), y(G.y) {}
+};
+template <>
+struct MgView<float> {
+  const float *eps, *cq, *S;
+  float *b, *x, *y;
+  explicit MgView(const MgGrid& G) : eps(G.eps32), cq(G.cq32), S(G.S32), b(G.b32), x(G.x32), y(G.y32) {}
+};
+
 // The V-cycle below level l (levels l .. nlev-1).  On entry level l holds
 // b (its right-hand side) and x = S b; on return x = B_l b.  Level 0's last
 // smoothing step writes one b^T x partial per block into part (cgblocks
 // blocks).
+template <typename T>
 static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, int cgblocks, double* part,
                    const PcgCtx* ctx) {
   const MgGrid& A = L[l];
-  auto jv = [&](const double* v, double* y) {
-    QE_LAUNCH(k_mg_jv, A.wm.nblocks, 256, s, A.g, A.wm, A.eps_t, A.cbits, A.cq, A.mask, v, y, ctx);
+  const MgView<T> a(A);
+  auto jv = [&]() {
+    QE_LAUNCH(k_mg_jv<T>, A.wm.nblocks, 256, s, A.g, A.wm, a.eps, A.cbits, a.cq, A.mask, a.x, a.y, ctx);
   };
   auto smooth = [&](double* p, int nb) {
-    QE_LAUNCH(k_mg_smooth, nb, kVecThreads, s, A.N, A.b, A.y, A.S, A.x, p, ctx);
+    QE_LAUNCH(k_mg_smooth<T>, nb, kVecThreads, s, A.N, a.b, a.y, a.S, a.x, p, ctx);
   };
   if (l == nlev - 1) {
     for (int k = 1; k < sweeps; ++k) {
-      jv(A.x, A.y);
+      jv();
       smooth(nullptr, mg_blocks(A.N, 4096));
     }
     return;
   }
   const MgGrid& C = L[l + 1];
-  jv(A.x, A.y);
-  QE_LAUNCH(k_mg_restrict, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny, C.g.nz,
-            A.g.x, A.g.y, A.g.z, A.mask, A.b, A.y, 1.0, C.mask, C.S, C.b, C.x, ctx);
-  vcycle(s, L, l + 1, nlev, sweeps, cgblocks, part, ctx);
-  QE_LAUNCH(k_mg_prolong, mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny, C.g.nz,
-            A.g.x, A.g.y, A.g.z, A.mask, C.x, 1.0, A.x, ctx);
-  jv(A.x, A.y);
+  const MgView<T> c(C);
+  jv();
+  QE_LAUNCH(k_mg_restrict<T>, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny,
+            C.g.nz, A.g.x, A.g.y, A.g.z, A.mask, a.b, a.y, C.mask, c.S, c.b, c.x, ctx);
+  vcycle<T>(s, L, l + 1, nlev, sweeps, cgblocks, part, ctx);
+  QE_LAUNCH(k_mg_prolong<T>, mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny,
+            C.g.nz, A.g.x, A.g.y, A.g.z, A.mask, c.x, a.x, ctx);
+  jv();
   if (l == 0)
     smooth(part, cgblocks);
   else
@@ -330,8 +361,11 @@ static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, 
 }
 
 void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, int cgblocks, double* part_rz,
-                      const PcgCtx* ctx) {
-  vcycle(s, levels, 0, nlev, sweeps, cgblocks, part_rz, ctx);
+                      const PcgCtx* ctx, bool fp32) {
+  if (fp32)
+    vcycle<float>(s, levels, 0, nlev, sweeps, cgblocks, part_rz, ctx);
+  else
+    vcycle<double>(s, levels, 0, nlev, sweeps, cgblocks, part_rz, ctx);
 }
 
 }  // namespace qe

@@ -99,7 +99,7 @@ struct Context {
   qe_status stage(double* phi, int apply, int zero_free);
   qe_status residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam, bool mixed,
                      double* diag_out, double* norm2_host);
-  // mg: the multigrid preconditioner (FP64 only), or nullptr for Jacobi
+  // mg: the multigrid preconditioner, or nullptr for Jacobi
   qe_status pcg(bool mixed, const double* b, double sign, double rtol, int maxit, int check_every, int* pcg_status,
                 int* iters, const MgRun* mg = nullptr);
   qe_status pcg_polled(bool mixed, const double* b, double sign, double rtol, int maxit, int* pcg_status,

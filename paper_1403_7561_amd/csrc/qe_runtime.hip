@@ -575,7 +575,7 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
                        int* pcg_status, int* iters, const MgRun* mg) {
   PcgCtx* dctx = reinterpret_cast<PcgCtx*>(ws + lay.ctx);
   if (no_alloc) return pcg_polled(mixed, b, sign, rtol, maxit, pcg_status, iters);
-  if (mg && (mixed || mg->nlev < 2)) mg = nullptr;
+  if (mg && mg->nlev < 2) mg = nullptr;
   HostMirror& hm = *this->hm;
   volatile CgProgress* hp = hm.prog;
   hp->word = 0;  // the last decision of an earlier solve has been read: no write is pending
@@ -584,29 +584,28 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
   // smoothing step z = S r; the V-cycle then turns z into B r and replaces
   // the r^T z partials
   const double* dinv = mg ? mg->lv[0].S : f64(lay.invdiag);
-  if (mixed) {
-    launch_pcg_start32(s, cgb, N, sign, b, u8(lay.mask), f32(lay.invdiag32), f32(lay.x32), f32(lay.r32),
-                       f32(lay.z32), dctx, f64(lay.partial2), rtol, maxit);
-  } else {
+  const float* dinv32 = mg ? mg->lv[0].S32 : f32(lay.invdiag32);
+  if (mixed)
+    launch_pcg_start32(s, cgb, N, sign, b, u8(lay.mask), dinv32, f32(lay.x32), f32(lay.r32), f32(lay.z32), dctx,
+                       f64(lay.partial2), rtol, maxit);
+  else
     launch_pcg_start64(s, cgb, N, sign, b, u8(lay.mask), dinv, f64(lay.x), f64(lay.r), f64(lay.z), dctx,
                        f64(lay.partial2), rtol, maxit);
-    if (mg) {
-      launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, cgb, f64(lay.partial2), dctx);
-      launch_mg_start_fin(s, dctx, f64(lay.partial2), cgb);
-    }
+  if (mg) {
+    launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, cgb, f64(lay.partial2), dctx, mixed);
+    launch_mg_start_fin(s, dctx, f64(lay.partial2), cgb);
   }
   QE_HIP(hipGetLastError());
   auto queue_iter = [&](int k) {
-    if (mixed) {
-      launch_pcg_iter32(s, g, wm, cgb, N, k & 1, f32(lay.eps32), u32(lay.cbits), f32(lay.c32), f32(lay.invdiag32),
-                        f32(lay.x32), f32(lay.r32), f32(lay.z32), f32(lay.p32), f32(lay.y32), dctx, hm.prog_dev,
-                        f64(lay.partial), f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
-    } else {
+    if (mixed)
+      launch_pcg_iter32(s, g, wm, cgb, N, k & 1, f32(lay.eps32), u32(lay.cbits), f32(lay.c32), dinv32, f32(lay.x32),
+                        f32(lay.r32), f32(lay.z32), f32(lay.p32), f32(lay.y32), dctx, hm.prog_dev, f64(lay.partial),
+                        f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
+    else
       launch_pcg_iter64(s, g, wm, cgb, N, k & 1, f64(lay.eps_t), u32(lay.cbits), f64(lay.c), dinv, f64(lay.x),
                         f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, hm.prog_dev, f64(lay.partial),
                         f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
-      if (mg) launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, cgb, f64(lay.partial2), dctx);
-    }
+    if (mg) launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, cgb, f64(lay.partial2), dctx, mixed);
   };
   // The host keeps `ahead` iterations queued beyond those it knows have
   // finished (an event is recorded after every kEv-th iteration), so the
@@ -882,7 +881,7 @@ static size_t seq_extra_bytes(const qe_problem* p, int levels) {
 }
 
 // ---------------------------------------------------------------------------
-// Multigrid preconditioner of the FP64 CG (qe_precond; kernels in
+// Multigrid preconditioner of the CG (qe_precond; kernels in
 // qe_mg.hip).  The levels are the meshes of the coarse-mesh sequence, down
 // to the last one with at least kMgMinCoarse nodes; each coarse level has
 // its problem arrays, its potential, its smoother weights and a Context
@@ -912,8 +911,8 @@ static int mg_coarse_kz() { return std::max(1, env_int("QE_MG_KZ", kMgCoarseKz))
 struct MgPlan {
   int nlev = 0;
   qe_problem pc[kMgMaxLevels];
-  size_t o_y0 = 0, o_S[kMgMaxLevels] = {}, o_phi[kMgMaxLevels] = {}, o_ws[kMgMaxLevels] = {},
-         ws_bytes[kMgMaxLevels] = {};
+  size_t o_y0 = 0, o_y0_32 = 0, o_S[kMgMaxLevels] = {}, o_S32[kMgMaxLevels] = {}, o_phi[kMgMaxLevels] = {},
+         o_ws[kMgMaxLevels] = {}, ws_bytes[kMgMaxLevels] = {};
   size_t total = 0;
 };
 
@@ -931,6 +930,8 @@ static bool mg_plan(const qe_problem* p, char* base, MgPlan& mp) {
   mp.pc[0] = *p;
   mp.o_S[0] = take(N * 8);
   mp.o_y0 = take(N * 8);
+  mp.o_S32[0] = take(N * 4);
+  mp.o_y0_32 = take(N * 4);
   int L = 1;
   while (L < kMgMaxLevels) {
     qe_problem c;
@@ -942,6 +943,7 @@ static bool mg_plan(const qe_problem* p, char* base, MgPlan& mp) {
     mp.pc[L] = c;
     mp.o_phi[L] = take(Nc * 8);
     mp.o_S[L] = take(Nc * 8);
+    mp.o_S32[L] = take(Nc * 4);
     mp.ws_bytes[L] = layout_bytes(&c, mg_coarse_kz());
     mp.o_ws[L] = take(mp.ws_bytes[L]);
     ++L;
@@ -976,11 +978,14 @@ struct MgState {
   MgGrid lv[kMgMaxLevels];
   MgRun run{};
 
-  // Whether multigrid can serve this call (FP64, an allocating entry point,
-  // a large enough plain mesh, room in the workspace).
+  bool fp32 = false;   // the CG it serves runs in FP32 (mixed precision)
+
+  // Whether multigrid can serve this call (an allocating entry point, a
+  // large enough plain mesh, room in the workspace).
   void plan_for(const qe_problem* p, const qe_options* o, void* ws, size_t ws_bytes, bool mixed, bool no_alloc) {
     possible = false;
-    if (mixed || no_alloc || o->precond == QE_PC_JACOBI) return;
+    fp32 = mixed;
+    if (no_alloc || o->precond == QE_PC_JACOBI) return;
     const size_t fine = align256(fine_layout_bytes(p));
     if (ws_bytes < fine) return;
     base = reinterpret_cast<char*>(ws) + fine;
@@ -995,6 +1000,8 @@ struct MgState {
       QE_HIP(hipGetLastError());
       QE_TRY(cx[l].init(&plan.pc[l], ch, base + plan.o_ws[l], plan.ws_bytes[l], fine.s, 0, false, mg_coarse_kz()));
       QE_TRY(cx[l].stage(nullptr, 0, 0));
+      if (fp32) launch_stage_eps32(fine.s, cx[l].vblocks, cx[l].g, plan.pc[l].eps_r, cx[l].f32(cx[l].lay.eps32),
+                                   cx[l].nslots);
     }
     for (int l = 0; l < plan.nlev; ++l) {
       Context& c = l == 0 ? fine : cx[l];
@@ -1010,6 +1017,12 @@ struct MgState {
       G.b = c.f64(c.lay.r);
       G.x = l == 0 ? c.f64(c.lay.z) : c.f64(c.lay.x);
       G.y = l == 0 ? reinterpret_cast<double*>(base + plan.o_y0) : c.f64(c.lay.y);
+      G.eps32 = c.f32(c.lay.eps32);
+      G.cq32 = c.f32(c.lay.c32);
+      G.S32 = reinterpret_cast<float*>(base + plan.o_S32[l]);
+      G.b32 = c.f32(c.lay.r32);
+      G.x32 = l == 0 ? c.f32(c.lay.z32) : c.f32(c.lay.x32);
+      G.y32 = l == 0 ? reinterpret_cast<float*>(base + plan.o_y0_32) : c.f32(c.lay.y32);
     }
     run = MgRun{lv, plan.nlev, std::max(1, env_int("QE_MG_SWEEPS", kMgSweeps))};
     ready = true;
@@ -1023,12 +1036,12 @@ struct MgState {
     for (int l = 1; l < plan.nlev; ++l) {
       double* ph = reinterpret_cast<double*>(base + plan.o_phi[l]);
       launch_mg_inject(fine.s, lv[l - 1], lv[l], src, ph);
-      QE_TRY(cx[l].residual(ch, ph, nullptr, nullptr, 0.0, false, nullptr, nullptr));
+      QE_TRY(cx[l].residual(ch, ph, nullptr, nullptr, 0.0, fp32, nullptr, nullptr));
       src = ph;
     }
     for (int l = 0; l < plan.nlev; ++l) {
       Context& c = l == 0 ? fine : cx[l];
-      launch_mg_l1(fine.s, lv[l], c.prob.eps_r, c.u8(c.lay.cflag), lv[l].S);
+      launch_mg_l1(fine.s, lv[l], c.prob.eps_r, c.u8(c.lay.cflag), fp32);
     }
     QE_HIP(hipGetLastError());
     return QE_OK;

@@ -134,10 +134,11 @@ def test_workspace_scales_with_mesh(monkeypatch):
     # the sequence's coarse level (65 x 65 x 33, an eighth of the nodes) adds
     # its arrays and its own layout
     assert fine / 10 < size(True, False) - fine < fine / 6
-    # multigrid: the fine level's smoother weights and J x (16 B per node)
-    # plus three coarse levels (an eighth, a 64th, a 512th of the nodes)
+    # multigrid: the fine level's smoother weights and J x in FP64 and FP32
+    # (24 B per node) plus three coarse levels (an eighth, a 64th, a 512th of
+    # the nodes)
     mg = size(False, True) - fine
-    assert 16 * N + fine / 10 < mg < 16 * N + fine / 5
+    assert 24 * N + fine / 10 < mg < 24 * N + fine / 5
     # both share one region after the fine layout
     assert size(True, True) - fine == max(size(True, False) - fine, mg) == big - fine
 
