@@ -882,7 +882,11 @@ static size_t seq_extra_bytes(const qe_problem* p, int levels) {
 
 // ---------------------------------------------------------------------------
 // Multigrid preconditioner of the CG (qe_precond; kernels in
-// qe_mg.hip).  The levels are the meshes of the coarse-mesh sequence, down
+// qe_mg.hip).  With sheets or eigenstates the fine level is the problem's
+// own Jacobian without the Robin face term (the V-cycle stays positive
+// definite, it only approximates J less closely) and the coarse levels
+// carry neither (their Jacobians use the statistics where the fine one has
+// the states' density).  The levels are the meshes of the coarse-mesh sequence, down
 // to the last one with at least kMgMinCoarse nodes; each coarse level has
 // its problem arrays, its potential, its smoother weights and a Context
 // layout (whose r, x and y hold the V-cycle's b, x and J x), after the fine
@@ -918,7 +922,6 @@ struct MgPlan {
 
 static bool mg_plan(const qe_problem* p, char* base, MgPlan& mp) {
   mp.nlev = 0;
-  if (p->n_sheets > 0 || p->quantum) return false;
   const long N = (long)p->nx * p->ny * p->nz;
   if (N < env_long("QE_MG_MIN_NODES", kMgMinNodes)) return false;
   size_t off = 0;
@@ -979,20 +982,25 @@ struct MgState {
   MgRun run{};
 
   bool fp32 = false;   // the CG it serves runs in FP32 (mixed precision)
+  bool states = false; // the problem has eigenstates (AUTO leaves the V-cycle off)
 
   // Whether multigrid can serve this call (an allocating entry point, a
   // large enough plain mesh, room in the workspace).
   void plan_for(const qe_problem* p, const qe_options* o, void* ws, size_t ws_bytes, bool mixed, bool no_alloc) {
     possible = false;
     fp32 = mixed;
+    states = p->quantum != nullptr;
     if (no_alloc || o->precond == QE_PC_JACOBI) return;
     const size_t fine = align256(fine_layout_bytes(p));
     if (ws_bytes < fine) return;
     base = reinterpret_cast<char*>(ws) + fine;
     possible = mg_plan(p, base, plan) && ws_bytes - fine >= plan.total;
   }
+  // AUTO: not with eigenstates, where the coarse levels lack the states'
+  // density (the 129x129x65 predictor step with 16 states measured 30.1
+  // against 39.1 solves/s with Jacobi); QE_PC_MULTIGRID still takes it.
   bool wanted(const qe_options* o, double eta) const {
-    return possible && (o->precond == QE_PC_MULTIGRID || eta <= mg_eta());
+    return possible && (o->precond == QE_PC_MULTIGRID || (!states && eta <= mg_eta()));
   }
   qe_status setup(Context& fine, const Charge& ch) {
     for (int l = 1; l < plan.nlev; ++l) {

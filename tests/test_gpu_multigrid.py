@@ -4,7 +4,8 @@ preconditions still converges to the one discrete solution.  These tests
 lower the size threshold (QE_MG_MIN_NODES) so that meshes the oracle solves
 quickly run it: solves and the adjoint against the oracle with multigrid on
 every CG (odd and even node counts: the restriction's clamped last coarse
-interval), far fewer iterations than Jacobi, the fallbacks to Jacobi, and
+interval; sheets and eigenstates; mixed precision), far fewer iterations
+than Jacobi, the fallbacks to Jacobi, and
 the 129 x 129 x 65 stack's default solve and adjoint against the Jacobi
 ones."""
 import numpy as np
@@ -108,10 +109,39 @@ def test_multigrid_adjoint_matches_oracle(monkeypatch):
     assert rep["krylov_iters"] * 2 < repj["krylov_iters"]
 
 
+def test_multigrid_with_sheets_and_eigenstates(monkeypatch):
+    """The V-cycle (without the Robin face term on the fine level; the
+    statistics on the coarse levels where the fine one has the states'
+    density) still preconditions the exact Jacobian: interface charge with
+    charged plungers (Robin), and the predictor step with 12 states in D1,
+    against the oracle."""
+    monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
+    from tests import gpu_support as gs
+    mg = qe.qe_default_options(newton_atol=1e-10, precond=MULTIGRID)
+    jac = qe.qe_default_options(newton_atol=1e-10, precond=JACOBI)
+    base = gs.ragged_device(volts=(2.6, 2.4, 1.0, 1.3, 0.9))
+    sdev = synth.with_interface_charge(base, 1e-3, seed=11, spread=0.5)
+    sdev = synth.with_charged_gates(sdev, synth.double_dot_gates()[:2], sigma_nm2=-2e-3)
+    qbase = gs.ragged_device(volts=(2.0, 1.8, 0.9, 1.1, 0.7))
+    _, res0 = solver.solve(qbase, atol=1e-10)
+    st = synth.box_states(qbase, (0.0, 60.0, 70.0, 130.0, 70.0, 90.0), 12, res0.phi, seed=3, e0=-0.003,
+                          spacing=0.0006)
+    qdev = synth.with_quantum(qbase, st)
+    for name, dev in (("sheets", sdev), ("eigenstates", qdev)):
+        P = qe.Problem(dev)
+        phi, _, rep = qe.qe_solve(P, opts=mg)
+        _, _, repj = qe.qe_solve(P, opts=jac)
+        _, res = solver.solve(dev, atol=1e-10)
+        err = rel_max(phi.cpu().numpy(), res.phi)
+        print(name, "multigrid", rep, "\njacobi", repj, "\nrel err", err)
+        assert rep["status"] == 0 and rep["res_final"] <= 1e-10 and err <= 1e-9
+        assert rep["mg_levels"] == 2 and rep["mg_krylov_iters"] > 0
+        assert rep["mg_krylov_iters"] < repj["krylov_iters"] - repj["init_krylov_iters"]
+
+
 def test_multigrid_fallbacks(monkeypatch):
-    """Jacobi runs instead below the size threshold, with sheets, with
-    eigenstates, in a workspace without room for the levels and in the
-    static entry point."""
+    """Jacobi runs instead below the size threshold, in a workspace without
+    room for the levels and in the static entry point."""
     dev = double_dot(33, 33, 17)
     P = qe.Problem(dev)
     mg = qe.qe_default_options(newton_atol=1e-10, precond=MULTIGRID)
@@ -122,13 +152,6 @@ def test_multigrid_fallbacks(monkeypatch):
     monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
     assert qe.qe_workspace_bytes(P, mg) > fine_only
     _, _, rep = qe.qe_solve(P, opts=mg, ws=qe.Workspace(fine_only, P.device))
-    assert rep["status"] == 0 and rep["mg_levels"] == 0
-    sdev = synth.with_interface_charge(dev, 1e-3, seed=5, spread=0.5)
-    _, _, rep = qe.qe_solve(qe.Problem(sdev), opts=mg)
-    assert rep["status"] == 0 and rep["mg_levels"] == 0
-    _, res = solver.solve(dev, atol=1e-10)
-    st = synth.box_states(dev, (10.0, 60.0, 80.0, 120.0, 75.0, 90.0), 4, res.phi, seed=3, e0=-0.003, spacing=0.0006)
-    _, _, rep = qe.qe_solve(qe.Problem(synth.with_quantum(dev, st)), opts=mg)
     assert rep["status"] == 0 and rep["mg_levels"] == 0
     phi = torch.zeros(P.N, dtype=torch.float64, device=P.device)
     rep = qe.qe_solve_static(P, phi, None, opts=mg)
