@@ -94,7 +94,7 @@ typedef enum {
  * nodes), each with the coarse problem's own Jacobian at the injected
  * potential; trilinear prolongation P, restriction P^T, one l1-Jacobi
  * smoothing step (S = 1 / sum_j |J_ij|) before and one after the coarse
- * correction, four on the coarsest mesh.  It is symmetric positive definite,
+ * correction, eight on the coarsest mesh.  It is symmetric positive definite,
  * so the CG stays plain CG.  AUTO takes multigrid for the Newton steps whose
  * CG tolerance is at most 3e-2 and for the adjoint, where one V-cycle (the
  * cost of about seven Jacobi iterations at 129 x 129 x 65) saves more

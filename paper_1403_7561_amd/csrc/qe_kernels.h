@@ -69,6 +69,15 @@ void launch_masked_copy_d2f(hipStream_t s, int nblocks, long n, const uint8_t* m
 // owns), and the coarse potential interpolated onto the fine nodes.
 void launch_seq_coarsen(hipStream_t s, const qe_problem* f, const qe_problem* c);
 void launch_seq_prolong(hipStream_t s, const qe_problem* f, const qe_problem* c, const double* phic, double* phif);
+// Per-axis tables between a level and the next finer one: for each fine
+// index its coarse interval pI and upper-end weight pw (interpolation), for
+// each coarse index its three fine taps rI and weights rw (restriction).
+struct MgAxes {
+  int* pI[3];
+  double* pw[3];
+  int* rI[3];
+  double* rw[3];
+};
 // Multigrid preconditioner of the CG (qe_mg.hip): one level's mesh,
 // linearisation (the arrays of its residual) and vectors, in FP64 and, for
 // the mixed-precision CG, FP32.  On level 0, b is the CG's r, x its z and S
@@ -87,7 +96,10 @@ struct MgGrid {
   const float* cq32;
   float* S32;
   float *b32, *x32, *y32;
+  MgAxes tab;                  // tables to the next finer level (levels >= 1)
 };
+// The tables of the level pair (f finer, c coarser) into c.tab.
+void launch_mg_tables(hipStream_t s, const MgGrid& f, const MgGrid& c);
 // phi_c = phi_f at the coarse level's nodes f(I) = min(2 I, n - 1).
 void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic);
 // L.S (and L.S32 with fp32) from the level's permittivity (natural element

@@ -81,7 +81,7 @@ __device__ __forceinline__ void mg_taps(int I, int nf, int nc, const double* __r
 }
 
 // y = J v on one level, as the library's plain J.v (v read as 0 on Dirichlet
-// nodes; their rows are left as computed and masked by the consumers).
+// nodes, y = 0 on their rows).
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_mg_jv(
     Geom g, WaveMap wm, const T* __restrict__ eps, const unsigned int* __restrict__ cbits,
@@ -95,33 +95,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   const WaveTile t(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
   const unsigned int cb = active ? cbits[64L * w + (threadIdx.x & 63)] : 0u;
   double dot = 0.0;
-  jv_tile<T, JV_PLAIN>(g, t, eps, cb, cq, mask, v, y, 0, dot);
+  jv_tile<T, JV_PLAIN>(g, t, eps, cb, cq, mask, v, y, 2, dot);
 }
 
-// Coarse node (I, J, K): b_c = sum over fine nodes of P_fine,coarse *
-// (r - y) (fine Dirichlet nodes count as 0), 0 on coarse Dirichlet
-// nodes; x_c = S_c b_c (the pre-smoothing step from zero).
+// Coarse node (I, J, K): b_c = sum over fine nodes of P_fine,coarse (r - y)
+// with fine Dirichlet nodes counted as 0 (the CG's own r is not zero on
+// their rows: its J.v writes them), 0 on coarse Dirichlet nodes; x_c =
+// S_c b_c (the pre-smoothing step from zero).  The taps and weights per axis
+// come from the level's tables (mg_taps, formed once per setup).
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
-                                                              const double* __restrict__ xf,
-                                                              const double* __restrict__ yf,
-                                                              const double* __restrict__ zf,
-                                                              const uint8_t* __restrict__ maskf,
+__global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, int nxc, int nyc, long Nc,
+                                                              MgAxes tab, const uint8_t* __restrict__ maskf,
                                                               const T* __restrict__ r, const T* __restrict__ y,
                                                               const uint8_t* __restrict__ maskc,
                                                               const T* __restrict__ Sc, T* __restrict__ bc,
                                                               T* __restrict__ xc, const PcgCtx* __restrict__ ctx) {
   if (ctx->done) return;
-  const long Nc = (long)nxc * nyc * nzc;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < Nc; t += (long)gridDim.x * blockDim.x) {
     double b = 0.0;
     if (!maskc[t]) {
       const int I = (int)(t % nxc), J = (int)((t / nxc) % nyc), K = (int)(t / ((long)nxc * nyc));
       int ix[3], iy[3], iz[3];
       double wx[3], wy[3], wz[3];
-      mg_taps(I, nxf, nxc, xf, ix, wx);
-      mg_taps(J, nyf, nyc, yf, iy, wy);
-      mg_taps(K, nzf, nzc, zf, iz, wz);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ix[k] = tab.rI[0][3 * I + k];
+        iy[k] = tab.rI[1][3 * J + k];
+        iz[k] = tab.rI[2][3 * K + k];
+        wx[k] = tab.rw[0][3 * I + k];
+        wy[k] = tab.rw[1][3 * J + k];
+        wz[k] = tab.rw[2][3 * K + k];
+      }
       // 27 taps, every load issued before the sums (zero-weight taps read the
       // centre again)
 #pragma unroll
@@ -144,28 +148,22 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, i
   }
 }
 
-// Fine node: x += P x_c on free nodes, 0 on Dirichlet nodes.
+// Fine node: x += P x_c on free nodes, 0 on Dirichlet nodes (the coarse
+// interval and weight per axis from the level's tables).
 template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
-                                                             const double* __restrict__ xf,
-                                                             const double* __restrict__ yf,
-                                                             const double* __restrict__ zf,
+__global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, long Nf, int nxc, int nyc, MgAxes tab,
                                                              const uint8_t* __restrict__ maskf,
                                                              const T* __restrict__ xcv, T* __restrict__ x,
                                                              const PcgCtx* __restrict__ ctx) {
   if (ctx->done) return;
-  const long Nf = (long)nxf * nyf * nzf;
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < Nf; n += (long)gridDim.x * blockDim.x) {
     if (maskf[n]) {
       x[n] = T(0);
       continue;
     }
     const int i = (int)(n % nxf), j = (int)((n / nxf) % nyf), k = (int)(n / ((long)nxf * nyf));
-    int I, J, K;
-    double wx, wy, wz;
-    mg_weight(i, nxf, nxc, xf, I, wx);
-    mg_weight(j, nyf, nyc, yf, J, wy);
-    mg_weight(k, nzf, nzc, zf, K, wz);
+    const int I = tab.pI[0][i], J = tab.pI[1][j], K = tab.pI[2][k];
+    const double wx = tab.pw[0][i], wy = tab.pw[1][j], wz = tab.pw[2][k];
     const long c0 = (long)I + (long)nxc * ((long)J + (long)nyc * K), sy = nxc, sz = (long)nxc * nyc;
     double c[8];
 #pragma unroll
@@ -174,6 +172,35 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, in
     const double v01 = c[4] + wx * (c[5] - c[4]), v11 = c[6] + wx * (c[7] - c[6]);
     const double v0 = v00 + wy * (v10 - v00), v1 = v01 + wy * (v11 - v01);
     x[n] = (T)((double)x[n] + (v0 + wz * (v1 - v0)));
+  }
+}
+
+// The interpolation and restriction tables of a level pair, per axis: for
+// each fine index its coarse interval and upper-end weight (mg_weight), for
+// each coarse index its three fine taps and weights (mg_taps).
+__global__ __launch_bounds__(kVecThreads) void k_mg_tables(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
+                                                            const double* __restrict__ xf,
+                                                            const double* __restrict__ yf,
+                                                            const double* __restrict__ zf, MgAxes tab) {
+  const int nf[3] = {nxf, nyf, nzf}, nc[3] = {nxc, nyc, nzc};
+  const double* co[3] = {xf, yf, zf};
+  for (int a = 0; a < 3; ++a) {
+    for (int i = threadIdx.x; i < nf[a]; i += blockDim.x) {
+      int I;
+      double w;
+      mg_weight(i, nf[a], nc[a], co[a], I, w);
+      tab.pI[a][i] = I;
+      tab.pw[a][i] = w;
+    }
+    for (int I = threadIdx.x; I < nc[a]; I += blockDim.x) {
+      int idx[3];
+      double wt[3];
+      mg_taps(I, nf[a], nc[a], co[a], idx, wt);
+      for (int k = 0; k < 3; ++k) {
+        tab.rI[a][3 * I + k] = idx[k];
+        tab.rw[a][3 * I + k] = wt[k];
+      }
+    }
   }
 }
 
@@ -303,6 +330,10 @@ void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, con
             fp32 ? L.S32 : nullptr);
 }
 
+void launch_mg_tables(hipStream_t s, const MgGrid& f, const MgGrid& c) {
+  QE_LAUNCH(k_mg_tables, 1, kVecThreads, s, f.g.nx, f.g.ny, f.g.nz, c.g.nx, c.g.ny, c.g.nz, f.g.x, f.g.y, f.g.z, c.tab);
+}
+
 void launch_mg_start_fin(hipStream_t s, PcgCtx* ctx, const double* part, int n) {
   QE_LAUNCH(k_mg_start_fin, 1, kVecThreads, s, ctx, part, n);
 }
@@ -348,11 +379,11 @@ static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, 
   const MgGrid& C = L[l + 1];
   const MgView<T> c(C);
   jv();
-  QE_LAUNCH(k_mg_restrict<T>, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny,
-            C.g.nz, A.g.x, A.g.y, A.g.z, A.mask, a.b, a.y, C.mask, c.S, c.b, c.x, ctx);
+  QE_LAUNCH(k_mg_restrict<T>, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab,
+            A.mask, a.b, a.y, C.mask, c.S, c.b, c.x, ctx);
   vcycle<T>(s, L, l + 1, nlev, sweeps, cgblocks, part, ctx);
-  QE_LAUNCH(k_mg_prolong<T>, mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny,
-            C.g.nz, A.g.x, A.g.y, A.g.z, A.mask, c.x, a.x, ctx);
+  QE_LAUNCH(k_mg_prolong<T>, mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.N, C.g.nx, C.g.ny, C.tab,
+            A.mask, c.x, a.x, ctx);
   jv();
   if (l == 0)
     smooth(part, cgblocks);

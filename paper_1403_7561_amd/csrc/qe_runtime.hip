@@ -902,9 +902,10 @@ static const int kMgMaxLevels = 6;
 // Newton steps; measured there, 1e-2 / 3e-2 / 1e-1 / every step gave
 // 13.4 / 13.4 / 13.5 / 15.0 ms per solve against 17.8 ms with Jacobi only.
 static const double kMgEta = 3e-2;
-// Smoothing steps on the coarsest mesh (4 measured faster than 2: 40 against
-// 49 iterations in the adjoint, 8.8 against 9.8 ms).
-static const int kMgSweeps = 4;
+// Smoothing steps on the coarsest mesh (at 129x129x65, 2 / 4 / 8 / 16 gave
+// 49 / 40 / 34 / 32 adjoint iterations in 9.8 / 8.9 / 8.7 / 10.1 ms; a fifth
+// level, down to 9x9x5, measured slower: 9.9 ms).
+static const int kMgSweeps = 8;
 // Chunk height of the coarse levels' wave tiles: their meshes are small, so
 // short chunks give the J.v and the residual more waves (latency, not
 // bandwidth, bounds them there; 1 / 2 / 4 measured 8.8 / 9.0 / 9.5 ms for
@@ -917,6 +918,8 @@ struct MgPlan {
   qe_problem pc[kMgMaxLevels];
   size_t o_y0 = 0, o_y0_32 = 0, o_S[kMgMaxLevels] = {}, o_S32[kMgMaxLevels] = {}, o_phi[kMgMaxLevels] = {},
          o_ws[kMgMaxLevels] = {}, ws_bytes[kMgMaxLevels] = {};
+  size_t o_pI[kMgMaxLevels][3] = {}, o_pw[kMgMaxLevels][3] = {}, o_rI[kMgMaxLevels][3] = {},
+         o_rw[kMgMaxLevels][3] = {};
   size_t total = 0;
 };
 
@@ -941,12 +944,19 @@ static bool mg_plan(const qe_problem* p, char* base, MgPlan& mp) {
     size_t o2 = off;
     if (!carve_coarse(&mp.pc[L - 1], base, o2, c)) break;
     const long Nc = (long)c.nx * c.ny * c.nz;
-    if (Nc < kMgMinCoarse) break;
+    if (Nc < env_long("QE_MG_MIN_COARSE", kMgMinCoarse)) break;
     off = o2;
     mp.pc[L] = c;
     mp.o_phi[L] = take(Nc * 8);
     mp.o_S[L] = take(Nc * 8);
     mp.o_S32[L] = take(Nc * 4);
+    const int nf[3] = {mp.pc[L - 1].nx, mp.pc[L - 1].ny, mp.pc[L - 1].nz}, nc[3] = {c.nx, c.ny, c.nz};
+    for (int a = 0; a < 3; ++a) {
+      mp.o_pI[L][a] = take(nf[a] * 4);
+      mp.o_pw[L][a] = take(nf[a] * 8);
+      mp.o_rI[L][a] = take(nc[a] * 3 * 4);
+      mp.o_rw[L][a] = take(nc[a] * 3 * 8);
+    }
     mp.ws_bytes[L] = layout_bytes(&c, mg_coarse_kz());
     mp.o_ws[L] = take(mp.ws_bytes[L]);
     ++L;
@@ -1031,7 +1041,15 @@ struct MgState {
       G.b32 = c.f32(c.lay.r32);
       G.x32 = l == 0 ? c.f32(c.lay.z32) : c.f32(c.lay.x32);
       G.y32 = l == 0 ? reinterpret_cast<float*>(base + plan.o_y0_32) : c.f32(c.lay.y32);
+      for (int a = 0; a < 3 && l > 0; ++a) {
+        G.tab.pI[a] = reinterpret_cast<int*>(base + plan.o_pI[l][a]);
+        G.tab.pw[a] = reinterpret_cast<double*>(base + plan.o_pw[l][a]);
+        G.tab.rI[a] = reinterpret_cast<int*>(base + plan.o_rI[l][a]);
+        G.tab.rw[a] = reinterpret_cast<double*>(base + plan.o_rw[l][a]);
+      }
     }
+    for (int l = 1; l < plan.nlev; ++l) launch_mg_tables(fine.s, lv[l - 1], lv[l]);
+    QE_HIP(hipGetLastError());
     run = MgRun{lv, plan.nlev, std::max(1, env_int("QE_MG_SWEEPS", kMgSweeps))};
     ready = true;
     return QE_OK;
