@@ -171,7 +171,7 @@ def cpu_baseline(m, gpu_newton):
     return out
 
 
-def full_charge_run(synth, qe, torch, dev, opts, ws, boxes, jv_reps):
+def full_charge_run(synth, qe, torch, dev, opts, boxes, jv_reps):
     """The same stack with the full space charge: holes, a 1e15 cm^-3 boron
     substrate with incomplete ionization, the bottom contact at the library's
     Ohmic potential of that substrate.  One warm-up and two timed solves,
@@ -182,6 +182,8 @@ def full_charge_run(synth, qe, torch, dev, opts, ws, boxes, jv_reps):
     vb = qe.qe_ohmic_potential(phys, 0.0, float(fdev.acceptors.max()))
     fdev.dir_val[fdev.contacts.index("bottom")] = vb
     P = qe.Problem(fdev)
+    # its own workspace: the coarse levels carry the donor and acceptor arrays
+    ws = qe.workspace_for(P, opts)
     qe.qe_solve(P, opts=opts, ws=ws, want_density=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -196,6 +198,7 @@ def full_charge_run(synth, qe, torch, dev, opts, ws, boxes, jv_reps):
     ach = b64 / (ms64 * 1e-3) / 1e9
     return {"solves_per_s": 1.0 / dt, "ms": dt * 1e3, "ohmic_bottom_V": vb,
             "newton_iters": rep["newton_iters"], "krylov_iters": rep["krylov_iters"],
+            "mg_krylov_iters": rep["mg_krylov_iters"],
             "res_final": rep["res_final"], "dot_electrons": [float(x) for x in c],
             "jv": {"ms": ms64, "coef_elems": ncoef, "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}}
 
@@ -218,8 +221,8 @@ def sheets_run(synth, qe, torch, dev, opts, ws, boxes):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / 2
     return {"solves_per_s": 1.0 / dt, "ms": dt * 1e3, "newton_iters": rep["newton_iters"],
-            "krylov_iters": rep["krylov_iters"], "res_final": rep["res_final"],
-            "dot_electrons": [float(x) for x in c], "n_sheets": len(sdev.sheets)}
+            "krylov_iters": rep["krylov_iters"], "mg_krylov_iters": rep["mg_krylov_iters"],
+            "res_final": rep["res_final"], "dot_electrons": [float(x) for x in c], "n_sheets": len(sdev.sheets)}
 
 
 def predictor_run(synth, qe, torch, dev, P, opts, ws, boxes, phi_sc):
@@ -548,7 +551,7 @@ def main():
         del P5, ws5, res
     if not args.no_full_charge:
         log("full space charge on the same stack")
-        out["full_charge_c2"] = full_charge_run(synth, qe, torch, dev, opts, ws, boxes, args.jv_reps)
+        out["full_charge_c2"] = full_charge_run(synth, qe, torch, dev, opts, boxes, args.jv_reps)
     if not args.no_sheets:
         log("interface charge and charged plunger gates on the same stack")
         out["sheets_c2"] = sheets_run(synth, qe, torch, dev, opts, ws, boxes)

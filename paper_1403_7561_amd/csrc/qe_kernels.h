@@ -104,7 +104,8 @@ void launch_mg_tables(hipStream_t s, const MgGrid& f, const MgGrid& c);
 void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic);
 // L.S (and L.S32 with fp32) from the level's permittivity (natural element
 // order), coefficient flags and FP64 coefficients.
-void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, bool fp32);
+void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, double omega,
+                  bool fp32);
 // z = B r on level 0 (x = S r on entry), in FP32 with fp32; one r^T z
 // partial per block of the last kernel (cgblocks blocks) into part_rz.
 // Skipped once ctx->done.

@@ -271,8 +271,8 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_inject(int nxf, int nyf, int
 __global__ __launch_bounds__(kVecThreads) void k_mg_l1(Geom g, const double* __restrict__ eps,
                                                         const uint8_t* __restrict__ cflag,
                                                         const double* __restrict__ cq,
-                                                        const uint8_t* __restrict__ mask, double* __restrict__ S,
-                                                        float* __restrict__ S32) {
+                                                        const uint8_t* __restrict__ mask, double omega,
+                                                        double* __restrict__ S, float* __restrict__ S32) {
   const long N = (long)g.nx * g.ny * g.nz;
   const int gx = (g.nx + 6) / 7, gy = (g.ny + 6) / 7;
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_l1(Geom g, const double* __r
             sum += out[(i - ex) + 2 * (j - ey) + 4 * (k - ez)];
           }
         }
-    S[n] = sum > 0.0 ? 1.0 / sum : 0.0;
+    S[n] = sum > 0.0 ? omega / sum : 0.0;
     if (S32) S32[n] = (float)S[n];
   }
 }
@@ -325,8 +325,9 @@ void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const dou
             phic);
 }
 
-void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, bool fp32) {
-  QE_LAUNCH(k_mg_l1, mg_blocks(L.N, 8192), kVecThreads, s, L.g, eps_natural, cflag, L.cq, L.mask, L.S,
+void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, double omega,
+                  bool fp32) {
+  QE_LAUNCH(k_mg_l1, mg_blocks(L.N, 8192), kVecThreads, s, L.g, eps_natural, cflag, L.cq, L.mask, omega, L.S,
             fp32 ? L.S32 : nullptr);
 }
 

@@ -902,16 +902,30 @@ static const int kMgMaxLevels = 6;
 // Newton steps; measured there, 1e-2 / 3e-2 / 1e-1 / every step gave
 // 13.4 / 13.4 / 13.5 / 15.0 ms per solve against 17.8 ms with Jacobi only.
 static const double kMgEta = 3e-2;
-// Smoothing steps on the coarsest mesh (at 129x129x65, 2 / 4 / 8 / 16 gave
-// 49 / 40 / 34 / 32 adjoint iterations in 9.8 / 8.9 / 8.7 / 10.1 ms; a fifth
-// level, down to 9x9x5, measured slower: 9.9 ms).
-static const int kMgSweeps = 8;
+// Smoothing steps on the coarsest mesh (at 129x129x65 with the weight below,
+// 2 / 4 / 6 gave 37 / 30 / 28 adjoint iterations in 7.6 / 6.9 / 6.9 ms and
+// solves of 12.0 / 11.0 / 11.3 ms; a fifth level, down to 9x9x5, measured
+// slower).
+static const int kMgSweeps = 4;
 // Chunk height of the coarse levels' wave tiles: their meshes are small, so
 // short chunks give the J.v and the residual more waves (latency, not
 // bandwidth, bounds them there; 1 / 2 / 4 measured 8.8 / 9.0 / 9.5 ms for
 // the adjoint above).
 static const int kMgCoarseKz = 1;
 static int mg_coarse_kz() { return std::max(1, env_int("QE_MG_KZ", kMgCoarseKz)); }
+// Smoother weight: S = omega / (row's absolute-sum bound).  Since that bound
+// puts every eigenvalue of S J / omega in (0, 1], any omega < 2 keeps
+// 2 S^-1 - J positive definite, hence the V-cycle; for the stiffness rows the
+// bound is about twice the diagonal, so omega = 1 would damp like Jacobi
+// with 0.5.  Measured at 129x129x65: omega 1.0 / 1.2 / 1.4 / 1.6 / 1.8 / 1.9
+// gave solves of 13.3 / 12.9 / 11.8 / 12.0 / 11.0 / 10.9 ms and adjoints of
+// 8.6 / 8.2 / 7.7 / 7.3 / 6.9 / 6.9 ms; at 257x257x129 1.8 against 1.0 took
+// 88 against 104 ms.
+static const double kMgOmega = 1.8;
+static double mg_omega() {
+  const double w = env_double("QE_MG_OMEGA", kMgOmega);
+  return (w > 0.0 && w < 2.0) ? w : kMgOmega;
+}
 
 struct MgPlan {
   int nlev = 0;
@@ -1067,7 +1081,7 @@ struct MgState {
     }
     for (int l = 0; l < plan.nlev; ++l) {
       Context& c = l == 0 ? fine : cx[l];
-      launch_mg_l1(fine.s, lv[l], c.prob.eps_r, c.u8(c.lay.cflag), fp32);
+      launch_mg_l1(fine.s, lv[l], c.prob.eps_r, c.u8(c.lay.cflag), mg_omega(), fp32);
     }
     QE_HIP(hipGetLastError());
     return QE_OK;
