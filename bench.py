@@ -225,7 +225,7 @@ def sheets_run(synth, qe, torch, dev, opts, ws, boxes):
             "res_final": rep["res_final"], "dot_electrons": [float(x) for x in c], "n_sheets": len(sdev.sheets)}
 
 
-def predictor_run(synth, qe, torch, dev, P, opts, ws, boxes, phi_sc):
+def predictor_run(synth, qe, torch, dev, P, opts, boxes, phi_sc):
     """The predictor step of the predictor-corrector loop on the same stack:
     16 synthetic 3D-confined states in the D1 dot (hard-wall box modes,
     seeded levels from -3 meV around E_F) computed in the semiclassical
@@ -234,6 +234,8 @@ def predictor_run(synth, qe, torch, dev, P, opts, ws, boxes, phi_sc):
     st = synth.box_states(dev, (10.0, 60.0, 80.0, 120.0, 75.0, 90.0), 16, phi_sc.cpu().numpy(), seed=7564,
                           e0=-0.003, spacing=0.0006)
     Pq = qe.Problem(synth.with_quantum(dev, st))
+    # its own workspace: the V-cycle's coarse levels carry the states
+    ws = qe.workspace_for(Pq, opts)
     qe.qe_solve(Pq, opts=opts, ws=ws, want_density=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -243,7 +245,7 @@ def predictor_run(synth, qe, torch, dev, P, opts, ws, boxes, phi_sc):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / 2
     return {"solves_per_s": 1.0 / dt, "ms": dt * 1e3, "n_states": 16, "newton_iters": rep["newton_iters"],
-            "krylov_iters": rep["krylov_iters"], "res_final": rep["res_final"],
+            "krylov_iters": rep["krylov_iters"], "mg_krylov_iters": rep["mg_krylov_iters"], "res_final": rep["res_final"],
             "dot_electrons": [float(x) for x in c],
             "max_dphi_vs_phi_k": float((ph - phi_sc).abs().max())}
 
@@ -557,7 +559,7 @@ def main():
         out["sheets_c2"] = sheets_run(synth, qe, torch, dev, opts, ws, boxes)
     if not args.no_predictor:
         log("predictor step with 16 synthetic dot states")
-        out["predictor_c2"] = predictor_run(synth, qe, torch, dev, P, opts, ws, boxes, phi)
+        out["predictor_c2"] = predictor_run(synth, qe, torch, dev, P, opts, boxes, phi)
     if not args.no_schrodinger:
         log("Schrodinger states and the predictor-corrector loop")
         out["schrodinger_c2"] = schrodinger_run(synth, qe, torch, dev, P, opts, phi)

@@ -100,11 +100,10 @@ typedef enum {
  * cost of about seven Jacobi iterations at 129 x 129 x 65) saves more
  * iterations than it costs, and Jacobi otherwise.  In mixed precision the
  * V-cycle runs in FP32 like the CG it serves.  With sheets the V-cycle
- * leaves out the Robin face term, and with eigenstates its coarse meshes use
- * the statistics; it stays positive definite, but with eigenstates it saves
- * too little, so AUTO runs Jacobi there.  Multigrid needs a mesh of at least
- * 250000 nodes and an entry point that allocates; elsewhere every choice
- * runs Jacobi. */
+ * leaves out the Robin face term (it stays positive definite); with
+ * eigenstates every coarse mesh carries them, injected like the potential.
+ * Multigrid needs a mesh of at least 250000 nodes and an entry point that
+ * allocates; elsewhere every choice runs Jacobi. */
 typedef enum {
   QE_PC_AUTO = 0,
   QE_PC_JACOBI = 1,

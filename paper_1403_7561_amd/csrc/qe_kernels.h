@@ -100,6 +100,10 @@ struct MgGrid {
 };
 // The tables of the level pair (f finer, c coarser) into c.tab.
 void launch_mg_tables(hipStream_t s, const MgGrid& f, const MgGrid& c);
+// The coarse problem's eigenstate arrays from the fine one's (|psi|^2 and
+// phi^(k) at the coarse nodes, each coarse element's region flag from its
+// first fine element); c->quantum's arrays are device memory the caller owns.
+void launch_mg_coarsen_states(hipStream_t s, const qe_problem* f, const qe_problem* c);
 // phi_c = phi_f at the coarse level's nodes f(I) = min(2 I, n - 1).
 void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic);
 // L.S (and L.S32 with fp32) from the level's permittivity (natural element

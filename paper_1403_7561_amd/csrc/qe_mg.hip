@@ -249,6 +249,32 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_start_fin(PcgCtx* ctx, const
   }
 }
 
+// A coarse level's eigenstates by injection (n_states planes of |psi|^2 and
+// phi^(k)); each coarse element takes the region flag of its first fine
+// element, as the coarse problem takes its materials.
+__global__ __launch_bounds__(kVecThreads) void k_mg_coarsen_states(int nxf, int nyf, int nzf, int nxc, int nyc,
+                                                                    int nzc, int n_states,
+                                                                    const double* __restrict__ psi2f,
+                                                                    const double* __restrict__ phikf,
+                                                                    const uint8_t* __restrict__ regf,
+                                                                    double* __restrict__ psi2c,
+                                                                    double* __restrict__ phikc,
+                                                                    uint8_t* __restrict__ regc) {
+  const long Nf = (long)nxf * nyf * nzf, Nc = (long)nxc * nyc * nzc;
+  const long Ec = (long)(nxc - 1) * (nyc - 1) * (nzc - 1);
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < Nc; t += (long)gridDim.x * blockDim.x) {
+    const int I = (int)(t % nxc), J = (int)((t / nxc) % nyc), K = (int)(t / ((long)nxc * nyc));
+    const long f = (long)mg_fine(I, nxf) + (long)nxf * ((long)mg_fine(J, nyf) + (long)nyf * mg_fine(K, nzf));
+    phikc[t] = phikf[f];
+    for (int st = 0; st < n_states; ++st) psi2c[(long)st * Nc + t] = psi2f[(long)st * Nf + f];
+    if (regc && t < Ec) {
+      const int ei = (int)(t % (nxc - 1)), ej = (int)((t / (nxc - 1)) % (nyc - 1)),
+                ek = (int)(t / ((long)(nxc - 1) * (nyc - 1)));
+      regc[t] = regf[(long)(2 * ei) + (long)(nxf - 1) * ((long)(2 * ej) + (long)(nyf - 1) * (2 * ek))];
+    }
+  }
+}
+
 // Coarse potential by injection: phi_c(I, J, K) = phi_f(f(I), f(J), f(K)).
 __global__ __launch_bounds__(kVecThreads) void k_mg_inject(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
                                                             const double* __restrict__ phif,
@@ -329,6 +355,15 @@ void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, con
                   bool fp32) {
   QE_LAUNCH(k_mg_l1, mg_blocks(L.N, 8192), kVecThreads, s, L.g, eps_natural, cflag, L.cq, L.mask, omega, L.S,
             fp32 ? L.S32 : nullptr);
+}
+
+void launch_mg_coarsen_states(hipStream_t s, const qe_problem* f, const qe_problem* c) {
+  const long Nc = (long)c->nx * c->ny * c->nz;
+  const qe_quantum& qf = *f->quantum;
+  const qe_quantum& qc = *c->quantum;
+  QE_LAUNCH(k_mg_coarsen_states, mg_blocks(Nc, 4096), kVecThreads, s, f->nx, f->ny, f->nz, c->nx, c->ny, c->nz,
+            qf.n_states, qf.psi2, qf.phi_k, qf.region, const_cast<double*>(qc.psi2), const_cast<double*>(qc.phi_k),
+            const_cast<uint8_t*>(qc.region));
 }
 
 void launch_mg_tables(hipStream_t s, const MgGrid& f, const MgGrid& c) {

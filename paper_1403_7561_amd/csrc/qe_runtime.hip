@@ -882,11 +882,12 @@ static size_t seq_extra_bytes(const qe_problem* p, int levels) {
 
 // ---------------------------------------------------------------------------
 // Multigrid preconditioner of the CG (qe_precond; kernels in
-// qe_mg.hip).  With sheets or eigenstates the fine level is the problem's
-// own Jacobian without the Robin face term (the V-cycle stays positive
-// definite, it only approximates J less closely) and the coarse levels
-// carry neither (their Jacobians use the statistics where the fine one has
-// the states' density).  The levels are the meshes of the coarse-mesh sequence, down
+// qe_mg.hip).  With sheets the fine level is the problem's own Jacobian
+// without the Robin face term (the V-cycle stays positive definite, it only
+// approximates J less closely) and the coarse levels carry no sheets; with
+// eigenstates every coarse level has them too, injected like the potential
+// (|psi|^2 and phi^(k) at its nodes, each coarse element the region flag
+// of its first fine element).  The levels are the meshes of the coarse-mesh sequence, down
 // to the last one with at least kMgMinCoarse nodes; each coarse level has
 // its problem arrays, its potential, its smoother weights and a Context
 // layout (whose r, x and y hold the V-cycle's b, x and J x), after the fine
@@ -934,6 +935,9 @@ struct MgPlan {
          o_ws[kMgMaxLevels] = {}, ws_bytes[kMgMaxLevels] = {};
   size_t o_pI[kMgMaxLevels][3] = {}, o_pw[kMgMaxLevels][3] = {}, o_rI[kMgMaxLevels][3] = {},
          o_rw[kMgMaxLevels][3] = {};
+  // with eigenstates: each coarse level's states (|psi|^2 and phi^(k) at its
+  // nodes, the region flag of its elements; the levels E_i are shared)
+  qe_quantum qc[kMgMaxLevels] = {};
   size_t total = 0;
 };
 
@@ -960,6 +964,16 @@ static bool mg_plan(const qe_problem* p, char* base, MgPlan& mp) {
     const long Nc = (long)c.nx * c.ny * c.nz;
     if (Nc < env_long("QE_MG_MIN_COARSE", kMgMinCoarse)) break;
     off = o2;
+    if (p->quantum) {
+      const qe_quantum& qf = *mp.pc[L - 1].quantum;
+      qe_quantum& q = mp.qc[L];
+      q = qf;
+      const long Ec = (long)(c.nx - 1) * (c.ny - 1) * (c.nz - 1);
+      q.psi2 = reinterpret_cast<const double*>(base + take((size_t)qf.n_states * Nc * 8));
+      q.phi_k = reinterpret_cast<const double*>(base + take(Nc * 8));
+      q.region = qf.region ? reinterpret_cast<const uint8_t*>(base + take(Ec)) : nullptr;
+      c.quantum = &q;
+    }
     mp.pc[L] = c;
     mp.o_phi[L] = take(Nc * 8);
     mp.o_S[L] = take(Nc * 8);
@@ -1006,29 +1020,25 @@ struct MgState {
   MgRun run{};
 
   bool fp32 = false;   // the CG it serves runs in FP32 (mixed precision)
-  bool states = false; // the problem has eigenstates (AUTO leaves the V-cycle off)
 
   // Whether multigrid can serve this call (an allocating entry point, a
   // large enough plain mesh, room in the workspace).
   void plan_for(const qe_problem* p, const qe_options* o, void* ws, size_t ws_bytes, bool mixed, bool no_alloc) {
     possible = false;
     fp32 = mixed;
-    states = p->quantum != nullptr;
     if (no_alloc || o->precond == QE_PC_JACOBI) return;
     const size_t fine = align256(fine_layout_bytes(p));
     if (ws_bytes < fine) return;
     base = reinterpret_cast<char*>(ws) + fine;
     possible = mg_plan(p, base, plan) && ws_bytes - fine >= plan.total;
   }
-  // AUTO: not with eigenstates, where the coarse levels lack the states'
-  // density (the 129x129x65 predictor step with 16 states measured 30.1
-  // against 39.1 solves/s with Jacobi); QE_PC_MULTIGRID still takes it.
   bool wanted(const qe_options* o, double eta) const {
-    return possible && (o->precond == QE_PC_MULTIGRID || (!states && eta <= mg_eta()));
+    return possible && (o->precond == QE_PC_MULTIGRID || eta <= mg_eta());
   }
   qe_status setup(Context& fine, const Charge& ch) {
     for (int l = 1; l < plan.nlev; ++l) {
       launch_seq_coarsen(fine.s, &plan.pc[l - 1], &plan.pc[l]);
+      if (plan.pc[l].quantum) launch_mg_coarsen_states(fine.s, &plan.pc[l - 1], &plan.pc[l]);
       QE_HIP(hipGetLastError());
       QE_TRY(cx[l].init(&plan.pc[l], ch, base + plan.o_ws[l], plan.ws_bytes[l], fine.s, 0, false, mg_coarse_kz()));
       QE_TRY(cx[l].stage(nullptr, 0, 0));

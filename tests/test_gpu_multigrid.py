@@ -110,11 +110,10 @@ def test_multigrid_adjoint_matches_oracle(monkeypatch):
 
 
 def test_multigrid_with_sheets_and_eigenstates(monkeypatch):
-    """The V-cycle (without the Robin face term on the fine level; the
-    statistics on the coarse levels where the fine one has the states'
-    density) still preconditions the exact Jacobian: interface charge with
-    charged plungers (Robin), and the predictor step with 12 states in D1,
-    against the oracle."""
+    """The V-cycle (without the Robin face term on the fine level; with the
+    states injected onto every coarse level) still preconditions the exact
+    Jacobian: interface charge with charged plungers (Robin), and the
+    predictor step with 12 states in D1, against the oracle."""
     monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
     from tests import gpu_support as gs
     mg = qe.qe_default_options(newton_atol=1e-10, precond=MULTIGRID)
