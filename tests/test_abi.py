@@ -33,6 +33,25 @@ def test_default_options():
     o = qe.qe_default_options()
     assert o.newton_atol == 1e-8 and o.newton_maxit == 100 and o.ls_max_halvings == 30
     assert o.precision == 0 and o.init_guess == 2
+    assert o.precond == 0          # QE_PC_AUTO
+
+
+def test_report_layout_matches_the_header():
+    """The binding's report struct ends with the fields include/qe.h declares
+    last (the multigrid counts after the sequence's level count)."""
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qe.h")).read()
+
+    def fields(struct):
+        body = hdr[:hdr.index("} %s;" % struct)]
+        body = body[body.rindex("typedef struct {"):]
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        return re.findall(r"\b(\w+)\s*;", body)
+
+    assert [f for f, _ in qe.CReport._fields_] == fields("qe_report")
+    assert [f for f, _ in qe.COptions._fields_] == fields("qe_options")
+    assert fields("qe_report")[-2:] == ["mg_levels", "mg_krylov_iters"]
 
 
 def fake_problem(nx=4, ny=3, nz=2, n_dir=1):
@@ -72,6 +91,8 @@ def test_invalid_problem_rejected(mut, needle):
     ("krylov_maxit", 0, "krylov_maxit"),
     ("precision", 7, "precision"),
     ("init_guess", 3, "init_guess"),
+    ("precond", 3, "precond"),
+    ("precond", -1, "precond"),
 ])
 def test_invalid_options_rejected(field, val, needle):
     lib = qe.load_library()
