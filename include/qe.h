@@ -94,8 +94,10 @@ typedef enum {
  * nodes), each with the coarse problem's own Jacobian at the injected
  * potential; trilinear prolongation P, restriction P^T, one weighted
  * l1-Jacobi smoothing step (S = 1.8 / sum_j |J_ij|) before and one after the
- * coarse correction, four on the coarsest mesh.  It is symmetric positive
- * definite (any weight below 2 keeps it so), so the CG stays plain CG.  AUTO takes multigrid for the Newton steps whose
+ * coarse correction, four on the coarsest mesh; on meshes of 4M nodes and
+ * more the finest level only adds its correction (z = S r + P B_1 P^T r).
+ * It is symmetric positive definite (any weight below 2 keeps it so), so
+ * the CG stays plain CG.  AUTO takes multigrid for the Newton steps whose
  * CG tolerance is at most 3e-2 and for the adjoint, where one V-cycle (the
  * cost of about seven Jacobi iterations at 129 x 129 x 65) saves more
  * iterations than it costs, and Jacobi otherwise.  In mixed precision the

@@ -112,9 +112,10 @@ void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, con
                   bool fp32);
 // z = B r on level 0 (x = S r on entry), in FP32 with fp32; one r^T z
 // partial per block of the last kernel (cgblocks blocks) into part_rz.
-// Skipped once ctx->done.
-void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, int cgblocks, double* part_rz,
-                      const PcgCtx* ctx, bool fp32);
+// add_top: the finest level adds the coarse correction to S r instead of
+// smoothing around it.  Skipped once ctx->done.
+void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, bool add_top, int cgblocks,
+                      double* part_rz, const PcgCtx* ctx, bool fp32);
 // After a CG start with z = S r and the V-cycle: r_0^T z_0 and the
 // tolerance from the V-cycle's partials.
 void launch_mg_start_fin(hipStream_t s, PcgCtx* ctx, const double* part, int n);

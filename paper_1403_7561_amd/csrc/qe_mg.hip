@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 }
 
 // Coarse node (I, J, K): b_c = sum over fine nodes of P_fine,coarse (r - y)
-// with fine Dirichlet nodes counted as 0 (the CG's own r is not zero on
+// (y = NULL: r alone) with fine Dirichlet nodes counted as 0 (the CG's own r is not zero on
 // their rows: its J.v writes them), 0 on coarse Dirichlet nodes; x_c =
 // S_c b_c (the pre-smoothing step from zero).  The taps and weights per axis
 // come from the level's tables (mg_taps, formed once per setup).
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, i
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const long n = row + ix[a];
-            const double v = maskf[n] ? 0.0 : (double)r[n] - (double)y[n];
+            const double v = maskf[n] ? 0.0 : (double)r[n] - (y ? (double)y[n] : 0.0);
             b += (wyz * wx[a]) * v;
           }
         }
@@ -149,13 +149,17 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, i
 }
 
 // Fine node: x += P x_c on free nodes, 0 on Dirichlet nodes (the coarse
-// interval and weight per axis from the level's tables).
+// interval and weight per axis from the level's tables); with part, one
+// partial of bdot^T x per block.
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, long Nf, int nxc, int nyc, MgAxes tab,
                                                              const uint8_t* __restrict__ maskf,
                                                              const T* __restrict__ xcv, T* __restrict__ x,
+                                                             const T* __restrict__ bdot, double* __restrict__ part,
                                                              const PcgCtx* __restrict__ ctx) {
   if (ctx->done) return;
+  __shared__ double sred[kVecThreads / 64];
+  double bz = 0.0;
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < Nf; n += (long)gridDim.x * blockDim.x) {
     if (maskf[n]) {
       x[n] = T(0);
@@ -171,7 +175,13 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, lo
     const double v00 = c[0] + wx * (c[1] - c[0]), v10 = c[2] + wx * (c[3] - c[2]);
     const double v01 = c[4] + wx * (c[5] - c[4]), v11 = c[6] + wx * (c[7] - c[6]);
     const double v0 = v00 + wy * (v10 - v00), v1 = v01 + wy * (v11 - v01);
-    x[n] = (T)((double)x[n] + (v0 + wz * (v1 - v0)));
+    const T xn = (T)((double)x[n] + (v0 + wz * (v1 - v0)));
+    x[n] = xn;
+    if (part) bz += (double)bdot[n] * (double)xn;
+  }
+  if (part) {
+    const double s1 = block_sum(bz, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = s1;
   }
 }
 
@@ -395,8 +405,8 @@ struct MgView<float> {
 // smoothing step writes one b^T x partial per block into part (cgblocks
 // blocks).
 template <typename T>
-static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, int cgblocks, double* part,
-                   const PcgCtx* ctx) {
+static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bool add_top, int cgblocks,
+                   double* part, const PcgCtx* ctx) {
   const MgGrid& A = L[l];
   const MgView<T> a(A);
   auto jv = [&]() {
@@ -414,12 +424,23 @@ static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, 
   }
   const MgGrid& C = L[l + 1];
   const MgView<T> c(C);
+  if (l == 0 && add_top) {
+    // additive top level: z = S r + P B_1 P^T r, no smoothing products on
+    // the finest mesh (positive definite as a sum of positive definite and
+    // semidefinite parts)
+    QE_LAUNCH(k_mg_restrict<T>, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab,
+              A.mask, a.b, (const T*)nullptr, C.mask, c.S, c.b, c.x, ctx);
+    vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
+    QE_LAUNCH(k_mg_prolong<T>, cgblocks, kVecThreads, s, A.g.nx, A.g.ny, A.N, C.g.nx, C.g.ny, C.tab, A.mask, c.x,
+              a.x, (const T*)a.b, part, ctx);
+    return;
+  }
   jv();
   QE_LAUNCH(k_mg_restrict<T>, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab,
             A.mask, a.b, a.y, C.mask, c.S, c.b, c.x, ctx);
-  vcycle<T>(s, L, l + 1, nlev, sweeps, cgblocks, part, ctx);
+  vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
   QE_LAUNCH(k_mg_prolong<T>, mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.N, C.g.nx, C.g.ny, C.tab,
-            A.mask, c.x, a.x, ctx);
+            A.mask, c.x, a.x, (const T*)nullptr, (double*)nullptr, ctx);
   jv();
   if (l == 0)
     smooth(part, cgblocks);
@@ -427,12 +448,12 @@ static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, 
     smooth(nullptr, mg_blocks(A.N, 4096));
 }
 
-void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, int cgblocks, double* part_rz,
-                      const PcgCtx* ctx, bool fp32) {
+void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, bool add_top, int cgblocks,
+                      double* part_rz, const PcgCtx* ctx, bool fp32) {
   if (fp32)
-    vcycle<float>(s, levels, 0, nlev, sweeps, cgblocks, part_rz, ctx);
+    vcycle<float>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, ctx);
   else
-    vcycle<double>(s, levels, 0, nlev, sweeps, cgblocks, part_rz, ctx);
+    vcycle<double>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, ctx);
 }
 
 }  // namespace qe

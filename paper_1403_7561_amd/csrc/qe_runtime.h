@@ -59,6 +59,7 @@ struct MgRun {
   const MgGrid* lv;
   int nlev;
   int sweeps;
+  bool add_top;   // additive finest level (no smoothing products there)
 };
 
 // One call's view of a problem, its workspace and its stream.

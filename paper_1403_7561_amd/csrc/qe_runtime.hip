@@ -592,7 +592,7 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
     launch_pcg_start64(s, cgb, N, sign, b, u8(lay.mask), dinv, f64(lay.x), f64(lay.r), f64(lay.z), dctx,
                        f64(lay.partial2), rtol, maxit);
   if (mg) {
-    launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, cgb, f64(lay.partial2), dctx, mixed);
+    launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, mg->add_top, cgb, f64(lay.partial2), dctx, mixed);
     launch_mg_start_fin(s, dctx, f64(lay.partial2), cgb);
   }
   QE_HIP(hipGetLastError());
@@ -605,7 +605,7 @@ qe_status Context::pcg(bool mixed, const double* b, double sign, double rtol, in
       launch_pcg_iter64(s, g, wm, cgb, N, k & 1, f64(lay.eps_t), u32(lay.cbits), f64(lay.c), dinv, f64(lay.x),
                         f64(lay.r), f64(lay.z), f64(lay.p), f64(lay.y), dctx, hm.prog_dev, f64(lay.partial),
                         f64(lay.partial2), sheets.any_robin ? &sheets : nullptr, sheet_items(), u8(lay.mask));
-    if (mg) launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, cgb, f64(lay.partial2), dctx, mixed);
+    if (mg) launch_mg_vcycle(s, mg->lv, mg->nlev, mg->sweeps, mg->add_top, cgb, f64(lay.partial2), dctx, mixed);
   };
   // The host keeps `ahead` iterations queued beyond those it knows have
   // finished (an event is recorded after every kEv-th iteration), so the
@@ -923,6 +923,11 @@ static int mg_coarse_kz() { return std::max(1, env_int("QE_MG_KZ", kMgCoarseKz))
 // 8.6 / 8.2 / 7.7 / 7.3 / 6.9 / 6.9 ms; at 257x257x129 1.8 against 1.0 took
 // 88 against 104 ms.
 static const double kMgOmega = 1.8;
+// From this many nodes the finest level is additive (z = S r + P B_1 P^T r):
+// there its two smoothing J.v products cost more than the iterations they
+// save (257x257x129: solve 88 -> 76 ms, adjoint 39 -> 34 ms; at 129x129x65
+// the multiplicative form is faster, 11.3 against 11.9 ms).
+static const long kMgAddTopNodes = 4000000;
 static double mg_omega() {
   const double w = env_double("QE_MG_OMEGA", kMgOmega);
   return (w > 0.0 && w < 2.0) ? w : kMgOmega;
@@ -1074,7 +1079,8 @@ struct MgState {
     }
     for (int l = 1; l < plan.nlev; ++l) launch_mg_tables(fine.s, lv[l - 1], lv[l]);
     QE_HIP(hipGetLastError());
-    run = MgRun{lv, plan.nlev, std::max(1, env_int("QE_MG_SWEEPS", kMgSweeps))};
+    run = MgRun{lv, plan.nlev, std::max(1, env_int("QE_MG_SWEEPS", kMgSweeps)),
+                fine.N >= env_long("QE_MG_ADD_NODES", kMgAddTopNodes)};
     ready = true;
     return QE_OK;
   }

@@ -52,6 +52,28 @@ def test_multigrid_solve_matches_oracle(monkeypatch, dims, levels):
     assert rel_max(phi.cpu().numpy(), phj.cpu().numpy()) <= 1e-9
 
 
+def test_multigrid_additive_top_level(monkeypatch):
+    """The additive finest level (z = S r + P B_1 P^T r, the default from 4M
+    nodes; forced here through QE_MG_ADD_NODES): the solve and the adjoint
+    still match the oracle."""
+    monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
+    monkeypatch.setenv("QE_MG_ADD_NODES", "1000")
+    dev = double_dot(36, 30, 20, volts=(1.6, 1.5, 0.5, 0.8, 0.4))
+    P = qe.Problem(dev)
+    phi, _, rep = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-10, precond=MULTIGRID))
+    po, res = solver.solve(dev, atol=1e-11)
+    print("additive top", rep, "rel err", rel_max(phi.cpu().numpy(), res.phi))
+    assert rep["status"] == 0 and rep["mg_levels"] == 2 and rep["mg_krylov_iters"] > 0
+    assert rel_max(phi.cpu().numpy(), res.phi) <= 1e-9
+    box = dev.boxes["D1"]
+    adj = solver.adjoint(po, res.phi, box)
+    Q, dV, deps, lam, arep = qe.qe_adjoint(P, torch.as_tensor(res.phi, device="cuda"), box, want_lam=True)
+    print("adjoint", arep, rel_max(np.asarray(dV), adj.dQ_ddir))
+    assert arep["mg_levels"] == 2
+    assert rel_max(np.asarray(dV), adj.dQ_ddir) <= 1e-10
+    assert rel_max(deps.cpu().numpy(), adj.dQ_deps) <= 1e-10
+
+
 def test_multigrid_full_charge_and_sequence(monkeypatch):
     """Donor and acceptor arrays and hole charge on the coarse levels, with
     the coarse-mesh sequence's start (both use the region after the fine
