@@ -9,18 +9,23 @@
 //   the potential injected from level l;
 //   prolongation P: trilinear interpolation in the fine coordinates;
 //   restriction: exactly P^T;
-//   smoother: x += S (b - J x) with S = 1 / sum_j |J_ij| (l1-Jacobi), the
-//   same before and after the coarse correction;
-//   coarsest level: a fixed number of smoother steps from x = S b.
+//   smoother: x += S (b - J x) with S = omega / sum_j |J_ij| (weighted
+//   l1-Jacobi, 0 < omega < 2), the same before and after the coarse
+//   correction;
+//   coarsest level: a fixed number of smoother steps from x = S b;
+//   on very large meshes the finest level only adds its correction,
+//   z = S r + P B_1 P^T r (no smoothing products there).
 //
 // With R = P^T, one smoother S on both sides and an SPD coarse operator, the
-// V-cycle is symmetric, and 2 S^-1 - J is diagonally dominant (S^-1 bounds
-// the row's absolute sum), so the V-cycle is positive definite: plain CG
-// with it stays CG (no flexible variant).  The l1 sums are formed element by
-// element: sum_j |Khat_ij| of the box element from its three stiffness
-// weights, and for the Gauss-point coefficient term, whose entries are all
-// >= 0 and whose trilinear weights sum to 1, the row sum B^T c.  Both bound
-// the assembled row's absolute sum from above.
+// V-cycle is symmetric; the row bound puts every eigenvalue of S J / omega
+// in (0, 1], so 2 S^-1 - J is positive definite for omega < 2, and so is
+// the V-cycle (and the additive form, a sum of positive definite and
+// semidefinite parts): plain CG with it stays CG (no flexible variant).
+// The l1 sums are formed element by element: sum_j |Khat_ij| of the box
+// element from its three stiffness weights, and for the Gauss-point
+// coefficient term, whose entries are all >= 0 and whose trilinear weights
+// sum to 1, the row sum B^T c.  Both bound the assembled row's absolute sum
+// from above.
 //
 // The V-cycle runs in the CG's own precision: FP64, or FP32 inside the
 // mixed-precision Newton (FP32 coefficients, permittivities, smoother
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_inject(int nxf, int nyf, int
   }
 }
 
-// Smoother weights S_i = 1 / (sum over the elements of node i of
+// Smoother weights S_i = omega / (sum over the elements of node i of
 // sum_j |Khat_ij| + (B^T c)_i) on free nodes, 0 on Dirichlet nodes.
 // Khat's entry between local nodes that differ along the axes in d is
 // sx kx(dx) my(dy) mz(dz) + sy mx(dx) ky(dy) mz(dz) + sz mx(dx) my(dy) kz(dz)
