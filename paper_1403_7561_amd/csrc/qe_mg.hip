@@ -153,6 +153,50 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, i
   }
 }
 
+// The same with a group of 16 lanes per coarse node, for small levels
+// (with one thread per node they run a few waves, each a chain of 27
+// gathers).
+template <typename T>
+__global__ __launch_bounds__(kVecThreads) void k_mg_restrict16(int nxf, int nyf, int nxc, int nyc, long Nc,
+                                                                MgAxes tab, const uint8_t* __restrict__ maskf,
+                                                                const T* __restrict__ r, const T* __restrict__ y,
+                                                                const uint8_t* __restrict__ maskc,
+                                                                const T* __restrict__ Sc, T* __restrict__ bc,
+                                                                T* __restrict__ xc, const PcgCtx* __restrict__ ctx) {
+  if (ctx->done) return;
+  // a group of 16 lanes per coarse node: lane j < 9 takes the y tap j % 3
+  // and the z tap j / 3 with their three x taps, so the 27 gathers run on 9
+  // lanes at once; the partial sums meet in a fixed order (shuffles)
+  constexpr int G = 16;
+  const int j = threadIdx.x & (G - 1);
+  const long groups = (long)gridDim.x * (kVecThreads / G);
+  for (long t = (long)blockIdx.x * (kVecThreads / G) + (threadIdx.x / G); t < Nc; t += groups) {
+    double b = 0.0;
+    const bool free_c = !maskc[t];
+    if (free_c && j < 9) {
+      const int I = (int)(t % nxc), J = (int)((t / nxc) % nyc), K = (int)(t / ((long)nxc * nyc));
+      const int bq = j % 3, c = j / 3;
+      const long row = (long)nxf * ((long)tab.rI[1][3 * J + bq] + (long)nyf * tab.rI[2][3 * K + c]);
+      const double wyz = tab.rw[1][3 * J + bq] * tab.rw[2][3 * K + c];
+      double v[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const long n = row + tab.rI[0][3 * I + a];
+        v[a] = maskf[n] ? 0.0 : (double)r[n] - (y ? (double)y[n] : 0.0);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) b += (wyz * tab.rw[0][3 * I + a]) * v[a];
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) b += __shfl_xor(b, off, G);
+    if (j == 0) {
+      const T bt = free_c ? (T)b : T(0);
+      bc[t] = bt;
+      xc[t] = Sc[t] * bt;
+    }
+  }
+}
+
 // Fine node: x += P x_c on free nodes, 0 on Dirichlet nodes (the coarse
 // interval and weight per axis from the level's tables); with part, one
 // partial of bdot^T x per block.
@@ -361,6 +405,11 @@ static int mg_blocks(long n, long cap) {
   return (int)std::max(1L, std::min((n + kVecThreads - 1) / kVecThreads, cap));
 }
 
+// Coarse levels below this many nodes take the restriction with 16 lanes per
+// node (at 129x129x65: 12 -> 6.8 us onto 33x33x17 and 11 -> 4.6 us onto
+// 17x17x9, but 17.6 -> 27.2 us onto 65x65x33).
+static const long kMgRestrictGroupMax = 65536;
+
 void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic) {
   QE_LAUNCH(k_mg_inject, mg_blocks(c.N, 4096), kVecThreads, s, f.g.nx, f.g.ny, f.g.nz, c.g.nx, c.g.ny, c.g.nz, phif,
             phic);
@@ -405,6 +454,22 @@ struct MgView<float> {
   explicit MgView(const MgGrid& G) : eps(G.eps32), cq(G.cq32), S(G.S32), b(G.b32), x(G.x32), y(G.y32) {}
 };
 
+// b_c = P^T (b - y) and x_c = S_c b_c from level A onto level C (y = NULL:
+// P^T b).
+template <typename T>
+static void restrict_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T* b, const T* y, const MgView<T>& c,
+                        const PcgCtx* ctx) {
+  if (C.N < kMgRestrictGroupMax) {
+    constexpr long per = kVecThreads / 16;
+    const int nb = (int)std::max(1L, std::min((C.N + per - 1) / per, 16384L));
+    QE_LAUNCH(k_mg_restrict16<T>, nb, kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab, A.mask, b, y,
+              C.mask, c.S, c.b, c.x, ctx);
+  } else {
+    QE_LAUNCH(k_mg_restrict<T>, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab,
+              A.mask, b, y, C.mask, c.S, c.b, c.x, ctx);
+  }
+}
+
 // The V-cycle below level l (levels l .. nlev-1).  On entry level l holds
 // b (its right-hand side) and x = S b; on return x = B_l b.  Level 0's last
 // smoothing step writes one b^T x partial per block into part (cgblocks
@@ -433,16 +498,14 @@ static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, 
     // additive top level: z = S r + P B_1 P^T r, no smoothing products on
     // the finest mesh (positive definite as a sum of positive definite and
     // semidefinite parts)
-    QE_LAUNCH(k_mg_restrict<T>, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab,
-              A.mask, a.b, (const T*)nullptr, C.mask, c.S, c.b, c.x, ctx);
+    restrict_to(s, A, C, a.b, (const T*)nullptr, c, ctx);
     vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
     QE_LAUNCH(k_mg_prolong<T>, cgblocks, kVecThreads, s, A.g.nx, A.g.ny, A.N, C.g.nx, C.g.ny, C.tab, A.mask, c.x,
               a.x, (const T*)a.b, part, ctx);
     return;
   }
   jv();
-  QE_LAUNCH(k_mg_restrict<T>, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab,
-            A.mask, a.b, a.y, C.mask, c.S, c.b, c.x, ctx);
+  restrict_to(s, A, C, a.b, (const T*)a.y, c, ctx);
   vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
   QE_LAUNCH(k_mg_prolong<T>, mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.N, C.g.nx, C.g.ny, C.tab,
             A.mask, c.x, a.x, (const T*)nullptr, (double*)nullptr, ctx);
