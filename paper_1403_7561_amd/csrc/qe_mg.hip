@@ -103,59 +103,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   jv_tile<T, JV_PLAIN>(g, t, eps, cb, cq, mask, v, y, 2, dot);
 }
 
-// Coarse node (I, J, K): b_c = sum over fine nodes of P_fine,coarse (r - y)
-// (y = NULL: r alone) with fine Dirichlet nodes counted as 0 (the CG's own r is not zero on
-// their rows: its J.v writes them), 0 on coarse Dirichlet nodes; x_c =
-// S_c b_c (the pre-smoothing step from zero).  The taps and weights per axis
-// come from the level's tables (mg_taps, formed once per setup).
-template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_mg_restrict(int nxf, int nyf, int nxc, int nyc, long Nc,
-                                                              MgAxes tab, const uint8_t* __restrict__ maskf,
-                                                              const T* __restrict__ r, const T* __restrict__ y,
-                                                              const uint8_t* __restrict__ maskc,
-                                                              const T* __restrict__ Sc, T* __restrict__ bc,
-                                                              T* __restrict__ xc, const PcgCtx* __restrict__ ctx) {
-  if (ctx->done) return;
-  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < Nc; t += (long)gridDim.x * blockDim.x) {
-    double b = 0.0;
-    if (!maskc[t]) {
-      const int I = (int)(t % nxc), J = (int)((t / nxc) % nyc), K = (int)(t / ((long)nxc * nyc));
-      int ix[3], iy[3], iz[3];
-      double wx[3], wy[3], wz[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        ix[k] = tab.rI[0][3 * I + k];
-        iy[k] = tab.rI[1][3 * J + k];
-        iz[k] = tab.rI[2][3 * K + k];
-        wx[k] = tab.rw[0][3 * I + k];
-        wy[k] = tab.rw[1][3 * J + k];
-        wz[k] = tab.rw[2][3 * K + k];
-      }
-      // 27 taps, every load issued before the sums (zero-weight taps read the
-      // centre again)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int bq = 0; bq < 3; ++bq) {
-          const long row = (long)nxf * ((long)iy[bq] + (long)nyf * iz[c]);
-          const double wyz = wy[bq] * wz[c];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const long n = row + ix[a];
-            const double v = maskf[n] ? 0.0 : (double)r[n] - (y ? (double)y[n] : 0.0);
-            b += (wyz * wx[a]) * v;
-          }
-        }
-    }
-    const T bt = (T)b;
-    bc[t] = bt;
-    xc[t] = Sc[t] * bt;
-  }
-}
-
-// The same with a group of 16 lanes per coarse node, for small levels
-// (with one thread per node they run a few waves, each a chain of 27
-// gathers).
+// The restriction onto small levels, with a group of 16 lanes per coarse
+// node (coarse node (I, J, K): b_c = sum over fine nodes of P_fine,coarse
+// (r - y), y = NULL: r alone, with fine Dirichlet nodes counted as 0 (the
+// CG's own r is not zero on their rows: its J.v writes them), 0 on coarse
+// Dirichlet nodes; x_c = S_c b_c, the pre-smoothing step from zero; the
+// taps and weights per axis come from the level's tables, formed once per
+// setup by mg_taps).
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_mg_restrict16(int nxf, int nyf, int nxc, int nyc, long Nc,
                                                                 MgAxes tab, const uint8_t* __restrict__ maskf,
@@ -195,6 +149,130 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict16(int nxf, int nyf,
       xc[t] = Sc[t] * bt;
     }
   }
+}
+
+// Tiles of the tiled restriction.  Along each axis a mesh of n nodes is cut
+// into ceil((n - 1) / w) tiles of w nodes, the last taking the rest (w + 1
+// at most), so 2^k + 1 meshes get no one-node tiles.
+__device__ __forceinline__ void mg_tile(int t, int tn, int n, int w, int& lo, int& hi) {
+  lo = t * w;
+  hi = (t == tn - 1) ? n : lo + w;
+}
+static inline int mg_ntiles(int n, int w) { return n > 1 ? (n - 1 + w - 1) / w : 1; }
+
+// Restriction tiles of 32 x 4 x 2 coarse nodes, one per thread.  The taps of
+// coarse node I lie in [f(I) - 1, f(I) + 1] and move forward with I, so a
+// tile of w coarse nodes reads a window of at most 2 w + 1 fine nodes, from
+// the first tap of its first node to the last tap of its last.
+constexpr int kRtX = 32, kRtY = 4, kRtZ = 2;
+constexpr int kRwX = 2 * (kRtX + 1) + 1, kRwY = 2 * (kRtY + 1) + 1, kRwZ = 2 * (kRtZ + 1) + 1;
+constexpr int kRowsPer = (kRwY * kRwZ + 3) / 4;
+
+// The restriction onto larger levels (what k_mg_restrict16 computes), one
+// thread per coarse node: the block's fine window of r - y (0 on fine
+// Dirichlet nodes) is staged in LDS by coalesced loads, and the 27 taps
+// then read LDS.  Every load is issued before its first use (lanes past the
+// window read a node inside it; the masks are applied as selects), so a
+// block waits for memory twice, not once per element.
+template <typename T, bool HAS_Y>
+__global__ __launch_bounds__(kVecThreads) void k_mg_restrict_tile(int nxf, int nyf, int nzf, int nxc, int nyc, int nzc,
+                                                                   int tnx, int tny, int tnz, MgAxes tab,
+                                                                   const uint8_t* __restrict__ maskf,
+                                                                   const T* __restrict__ r, const T* __restrict__ y,
+                                                                   const uint8_t* __restrict__ maskc,
+                                                                   const T* __restrict__ Sc, T* __restrict__ bc,
+                                                                   T* __restrict__ xc, const PcgCtx* __restrict__ ctx) {
+  if (ctx->done) return;
+  __shared__ double sv[kRwX * kRwY * kRwZ];
+  const int tx = blockIdx.x % tnx, ty = (blockIdx.x / tnx) % tny, tz = blockIdx.x / (tnx * tny);
+  int I0, I1, J0, J1, K0, K1;
+  mg_tile(tx, tnx, nxc, kRtX, I0, I1);
+  mg_tile(ty, tny, nyc, kRtY, J0, J1);
+  mg_tile(tz, tnz, nzc, kRtZ, K0, K1);
+  // window [f(I0) - 1, f(I1 - 1) + 1] clipped to the mesh: it holds every
+  // tap of the tile (a tap that is no neighbour of a coarse node is staged
+  // but not read)
+  const int fx = max(mg_fine(I0, nxf) - 1, 0), fy = max(mg_fine(J0, nyf) - 1, 0), fz = max(mg_fine(K0, nzf) - 1, 0);
+  const int wx = min(mg_fine(I1 - 1, nxf) + 1, nxf - 1) - fx + 1;
+  const int wy = min(mg_fine(J1 - 1, nyf) + 1, nyf - 1) - fy + 1;
+  const int rows = wy * (min(mg_fine(K1 - 1, nzf) + 1, nzf - 1) - fz + 1);
+  const long base = (long)fx + (long)nxf * ((long)fy + (long)nyf * fz);
+  // one window row per wave and step (lanes along x), all loads issued
+  // before the first use; columns past 64 (only in the wider last tiles)
+  // follow, one per thread
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int ex = min(lane, wx - 1);
+  uint8_t m[kRowsPer];
+  T rv[kRowsPer], yv[kRowsPer];
+#pragma unroll
+  for (int p = 0; p < kRowsPer; ++p) {
+    const int row = min(wv + 4 * p, rows - 1), ez = row / wy, ey = row - ez * wy;
+    const long n = base + ex + (long)nxf * ((long)ey + (long)nyf * ez);
+    m[p] = maskf[n];
+    rv[p] = r[n];
+    if (HAS_Y) yv[p] = y[n];
+  }
+  const int extra = wx > 64 ? (wx - 64) * rows : 0;
+  const int xe = threadIdx.x < extra ? threadIdx.x : 0;
+  const int xrow = xe / max(wx - 64, 1), xcol = 64 + xe - xrow * max(wx - 64, 1);
+  const int xez = xrow / wy, xey = xrow - xez * wy;
+  const long xn = base + (threadIdx.x < extra ? xcol + (long)nxf * ((long)xey + (long)nyf * xez) : 0);
+  const uint8_t xm = maskf[xn];
+  const T xr = r[xn], xy = HAS_Y ? y[xn] : T(0);
+#pragma unroll
+  for (int p = 0; p < kRowsPer; ++p) {
+    const int row = wv + 4 * p;
+    if (row < rows && lane < wx) {
+      const int ez = row / wy, ey = row - ez * wy;
+      const double v = (double)rv[p] - (HAS_Y ? (double)yv[p] : 0.0);
+      sv[(ez * kRwY + ey) * kRwX + lane] = m[p] ? 0.0 : v;
+    }
+  }
+  if (threadIdx.x < extra) {
+    const double v = (double)xr - (HAS_Y ? (double)xy : 0.0);
+    sv[(xez * kRwY + xey) * kRwX + xcol] = xm ? 0.0 : v;
+  }
+  __syncthreads();
+  const int li = threadIdx.x % kRtX, lj = (threadIdx.x / kRtX) % kRtY, lk = threadIdx.x / (kRtX * kRtY);
+  for (int K = K0 + lk; K < K1; K += kRtZ)
+    for (int J = J0 + lj; J < J1; J += kRtY)
+      for (int I = I0 + li; I < I1; I += kRtX) {
+        const long t = (long)I + (long)nxc * ((long)J + (long)nyc * K);
+        const uint8_t mc = maskc[t];
+        const T st = Sc[t];
+        int ix[3], iy[3], iz[3];
+        double wxs[3], wys[3], wzs[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          ix[k] = tab.rI[0][3 * I + k] - fx;
+          iy[k] = tab.rI[1][3 * J + k] - fy;
+          iz[k] = tab.rI[2][3 * K + k] - fz;
+          wxs[k] = tab.rw[0][3 * I + k];
+          wys[k] = tab.rw[1][3 * J + k];
+          wzs[k] = tab.rw[2][3 * K + k];
+        }
+        double v[27];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int bq = 0; bq < 3; ++bq) {
+            const double* row = sv + (iz[c] * kRwY + iy[bq]) * kRwX;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[(c * 3 + bq) * 3 + a] = row[ix[a]];
+          }
+        double b = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int bq = 0; bq < 3; ++bq) {
+            const double wyz = wys[bq] * wzs[c];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) b += (wyz * wxs[a]) * v[(c * 3 + bq) * 3 + a];
+          }
+        const T bt = mc ? T(0) : (T)b;
+        bc[t] = bt;
+        xc[t] = st * bt;
+      }
 }
 
 // Fine node: x += P x_c on free nodes, 0 on Dirichlet nodes (the coarse
@@ -406,8 +484,11 @@ static int mg_blocks(long n, long cap) {
 }
 
 // Coarse levels below this many nodes take the restriction with 16 lanes per
-// node (at 129x129x65: 12 -> 6.8 us onto 33x33x17 and 11 -> 4.6 us onto
-// 17x17x9, but 17.6 -> 27.2 us onto 65x65x33).
+// node, larger ones the tiled one.  Under 129x129x65: onto 33x33x17 and
+// 17x17x9 the 16-lane form took 6.8 and 4.6 us (one thread per node: 12 and
+// 11 us), and the tiled one everywhere made the solve 2.5 % slower; onto
+// 65x65x33 one thread per node took 17.3 us, 16 lanes 27.2, the tiled form
+// 14.9 (and onto 129x129x65 under 257x257x129, 52 against 79 us).
 static const long kMgRestrictGroupMax = 65536;
 
 void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic) {
@@ -464,10 +545,24 @@ static void restrict_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T
     const int nb = (int)std::max(1L, std::min((C.N + per - 1) / per, 16384L));
     QE_LAUNCH(k_mg_restrict16<T>, nb, kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab, A.mask, b, y,
               C.mask, c.S, c.b, c.x, ctx);
-  } else {
-    QE_LAUNCH(k_mg_restrict<T>, mg_blocks(C.N, 4096), kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab,
-              A.mask, b, y, C.mask, c.S, c.b, c.x, ctx);
+    return;
   }
+  const int tnx = mg_ntiles(C.g.nx, kRtX), tny = mg_ntiles(C.g.ny, kRtY), tnz = mg_ntiles(C.g.nz, kRtZ);
+  if (y)
+    QE_LAUNCH((k_mg_restrict_tile<T, true>), tnx * tny * tnz, kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny,
+              C.g.nz, tnx, tny, tnz, C.tab, A.mask, b, y, C.mask, c.S, c.b, c.x, ctx);
+  else
+    QE_LAUNCH((k_mg_restrict_tile<T, false>), tnx * tny * tnz, kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx,
+              C.g.ny, C.g.nz, tnx, tny, tnz, C.tab, A.mask, b, y, C.mask, c.S, c.b, c.x, ctx);
+}
+
+// x += P x_c from level C onto level A; with part (grid = nb blocks), one
+// b^T x partial per block.
+template <typename T>
+static void prolong_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T* xc, T* x, const T* bdot,
+                       double* part, int nb, const PcgCtx* ctx) {
+  QE_LAUNCH(k_mg_prolong<T>, part ? nb : mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.N, C.g.nx, C.g.ny,
+            C.tab, A.mask, xc, x, bdot, part, ctx);
 }
 
 // The V-cycle below level l (levels l .. nlev-1).  On entry level l holds
@@ -500,15 +595,13 @@ static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, 
     // semidefinite parts)
     restrict_to(s, A, C, a.b, (const T*)nullptr, c, ctx);
     vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
-    QE_LAUNCH(k_mg_prolong<T>, cgblocks, kVecThreads, s, A.g.nx, A.g.ny, A.N, C.g.nx, C.g.ny, C.tab, A.mask, c.x,
-              a.x, (const T*)a.b, part, ctx);
+    prolong_to<T>(s, A, C, c.x, a.x, (const T*)a.b, part, cgblocks, ctx);
     return;
   }
   jv();
   restrict_to(s, A, C, a.b, (const T*)a.y, c, ctx);
   vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
-  QE_LAUNCH(k_mg_prolong<T>, mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.N, C.g.nx, C.g.ny, C.tab,
-            A.mask, c.x, a.x, (const T*)nullptr, (double*)nullptr, ctx);
+  prolong_to<T>(s, A, C, c.x, a.x, (const T*)nullptr, (double*)nullptr, 0, ctx);
   jv();
   if (l == 0)
     smooth(part, cgblocks);

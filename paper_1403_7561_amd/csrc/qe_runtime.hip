@@ -913,7 +913,14 @@ static const int kMgSweeps = 4;
 // bandwidth, bounds them there; 1 / 2 / 4 measured 8.8 / 9.0 / 9.5 ms for
 // the adjoint above).
 static const int kMgCoarseKz = 1;
-static int mg_coarse_kz() { return std::max(1, env_int("QE_MG_KZ", kMgCoarseKz)); }
+// Coarse levels of this many nodes and more keep the default chunks (a
+// 129x129x65 level under 257x257x129: its J.v took 34.8 us with chunks of
+// 1, against ~19 us with the default).
+static const long kMgCoarseKzMaxNodes = 500000;
+static int mg_coarse_kz(long nodes) {
+  if (nodes >= env_long("QE_MG_KZ_MAX_NODES", kMgCoarseKzMaxNodes)) return 0;
+  return std::max(1, env_int("QE_MG_KZ", kMgCoarseKz));
+}
 // Smoother weight: S = omega / (row's absolute-sum bound).  Since that bound
 // puts every eigenvalue of S J / omega in (0, 1], any omega < 2 keeps
 // 2 S^-1 - J positive definite, hence the V-cycle; for the stiffness rows the
@@ -990,7 +997,7 @@ static bool mg_plan(const qe_problem* p, char* base, MgPlan& mp) {
       mp.o_rI[L][a] = take(nc[a] * 3 * 4);
       mp.o_rw[L][a] = take(nc[a] * 3 * 8);
     }
-    mp.ws_bytes[L] = layout_bytes(&c, mg_coarse_kz());
+    mp.ws_bytes[L] = layout_bytes(&c, mg_coarse_kz(Nc));
     mp.o_ws[L] = take(mp.ws_bytes[L]);
     ++L;
   }
@@ -1045,7 +1052,8 @@ struct MgState {
       launch_seq_coarsen(fine.s, &plan.pc[l - 1], &plan.pc[l]);
       if (plan.pc[l].quantum) launch_mg_coarsen_states(fine.s, &plan.pc[l - 1], &plan.pc[l]);
       QE_HIP(hipGetLastError());
-      QE_TRY(cx[l].init(&plan.pc[l], ch, base + plan.o_ws[l], plan.ws_bytes[l], fine.s, 0, false, mg_coarse_kz()));
+      const long nl = (long)plan.pc[l].nx * plan.pc[l].ny * plan.pc[l].nz;
+      QE_TRY(cx[l].init(&plan.pc[l], ch, base + plan.o_ws[l], plan.ws_bytes[l], fine.s, 0, false, mg_coarse_kz(nl)));
       QE_TRY(cx[l].stage(nullptr, 0, 0));
       if (fp32) launch_stage_eps32(fine.s, cx[l].vblocks, cx[l].g, plan.pc[l].eps_r, cx[l].f32(cx[l].lay.eps32),
                                    cx[l].nslots);
