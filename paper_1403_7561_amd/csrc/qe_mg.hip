@@ -103,6 +103,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   jv_tile<T, JV_PLAIN>(g, t, eps, cb, cq, mask, v, y, 2, dot);
 }
 
+// One smoothing step in one launch: xo = x + S (b - J x) on every node (J x
+// as k_mg_jv's, S = 0 on Dirichlet nodes), xo a buffer other than x.  It
+// runs on the coarse levels, whose meshes give about 3 waves per SIMD or
+// fewer, so it may take the registers of 3 (with 4 the FP64 form spills).
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_mg_jv_smooth(
+    Geom g, WaveMap wm, const T* __restrict__ eps, const unsigned int* __restrict__ cbits,
+    const T* __restrict__ cq, const uint8_t* __restrict__ mask, const T* __restrict__ x,
+    const T* __restrict__ b, const T* __restrict__ S, T* __restrict__ xo, const PcgCtx* __restrict__ ctx) {
+  if (ctx->done) return;
+  const int w = __builtin_amdgcn_readfirstlane(wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6));
+  const bool active = w < wm.nwaves;
+  int wx, wy, wz;
+  wave_tile_of(w, wm, wx, wy, wz);
+  const WaveTile t(g, wx, wy, wz, wm.kz, threadIdx.x & 63, active);
+  const unsigned int cb = active ? cbits[64L * w + (threadIdx.x & 63)] : 0u;
+  double dot = 0.0;
+  jv_tile<T, JV_SMOOTH>(g, t, eps, cb, cq, mask, x, xo, 2, dot, b, S);
+}
+
 // The restriction onto small levels, with a group of 16 lanes per coarse
 // node (coarse node (I, J, K): b_c = sum over fine nodes of P_fine,coarse
 // (r - y), y = NULL: r alone, with fine Dirichlet nodes counted as 0 (the
@@ -566,26 +586,30 @@ static void prolong_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T*
 }
 
 // The V-cycle below level l (levels l .. nlev-1).  On entry level l holds
-// b (its right-hand side) and x = S b; on return x = B_l b.  Level 0's last
-// smoothing step writes one b^T x partial per block into part (cgblocks
-// blocks).
+// b (its right-hand side) and x = S b; returns the array that holds B_l b
+// (x or y: below the finest level a smoothing step writes the other one).
+// Level 0's last smoothing step writes one b^T x partial per block into part
+// (cgblocks blocks), and its result is always x.
 template <typename T>
-static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bool add_top, int cgblocks,
-                   double* part, const PcgCtx* ctx) {
+static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bool add_top, int cgblocks,
+                 double* part, const PcgCtx* ctx) {
   const MgGrid& A = L[l];
   const MgView<T> a(A);
   auto jv = [&]() {
     QE_LAUNCH(k_mg_jv<T>, A.wm.nblocks, 256, s, A.g, A.wm, a.eps, A.cbits, a.cq, A.mask, a.x, a.y, ctx);
   };
-  auto smooth = [&](double* p, int nb) {
-    QE_LAUNCH(k_mg_smooth<T>, nb, kVecThreads, s, A.N, a.b, a.y, a.S, a.x, p, ctx);
+  auto jv_smooth = [&](const T* xin, T* xout) {
+    QE_LAUNCH(k_mg_jv_smooth<T>, A.wm.nblocks, 256, s, A.g, A.wm, a.eps, A.cbits, a.cq, A.mask, xin, (const T*)a.b,
+              a.S, xout, ctx);
   };
   if (l == nlev - 1) {
+    T* cur = a.x;
+    T* nxt = a.y;
     for (int k = 1; k < sweeps; ++k) {
-      jv();
-      smooth(nullptr, mg_blocks(A.N, 4096));
+      jv_smooth(cur, nxt);
+      std::swap(cur, nxt);
     }
-    return;
+    return cur;
   }
   const MgGrid& C = L[l + 1];
   const MgView<T> c(C);
@@ -594,19 +618,21 @@ static void vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, 
     // the finest mesh (positive definite as a sum of positive definite and
     // semidefinite parts)
     restrict_to(s, A, C, a.b, (const T*)nullptr, c, ctx);
-    vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
-    prolong_to<T>(s, A, C, c.x, a.x, (const T*)a.b, part, cgblocks, ctx);
-    return;
+    const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
+    prolong_to<T>(s, A, C, xc, a.x, (const T*)a.b, part, cgblocks, ctx);
+    return a.x;
   }
   jv();
   restrict_to(s, A, C, a.b, (const T*)a.y, c, ctx);
-  vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
-  prolong_to<T>(s, A, C, c.x, a.x, (const T*)nullptr, (double*)nullptr, 0, ctx);
+  const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
+  prolong_to<T>(s, A, C, xc, a.x, (const T*)nullptr, (double*)nullptr, 0, ctx);
+  if (l > 0) {
+    jv_smooth(a.x, a.y);
+    return a.y;
+  }
   jv();
-  if (l == 0)
-    smooth(part, cgblocks);
-  else
-    smooth(nullptr, mg_blocks(A.N, 4096));
+  QE_LAUNCH(k_mg_smooth<T>, cgblocks, kVecThreads, s, A.N, a.b, a.y, a.S, a.x, part, ctx);
+  return a.x;
 }
 
 void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, bool add_top, int cgblocks,

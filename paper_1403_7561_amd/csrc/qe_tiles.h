@@ -143,10 +143,13 @@ struct WaveTile {
 //             (1: y = v on Dirichlet rows, 2: y = 0 there).
 //   JV_DOT    v = a CG direction (zero on Dirichlet nodes); y = J v on every
 //             owned row; dot += v^T J v over the elements this wave owns.
+//   JV_SMOOTH as JV_PLAIN with identity_rows = 2, then a smoothing step:
+//             y = v + S (b - J v) on every owned node (S is 0 on Dirichlet
+//             nodes), y a buffer other than v.
 // In the CG mode the Dirichlet flag is not read at all: the vectors vanish
 // on Dirichlet nodes and D^-1 is 0 there, so whatever y holds on those rows
 // never reaches z, p or x.  (The single-instance CG uses jv_tile_cg below.)
-enum JvMode { JV_PLAIN = 0, JV_DOT = 1 };
+enum JvMode { JV_PLAIN = 0, JV_DOT = 1, JV_SMOOTH = 2 };
 
 // cbits: this lane's coefficient flags over the chunk (bit L - Lbeg), as
 // written by residual_tile for the same wave tile.
@@ -154,8 +157,10 @@ template <typename T, int kMode>
 __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const T* __restrict__ eps_t,
                                         unsigned int cbits, const T* __restrict__ cq,
                                         const uint8_t* __restrict__ mask, const T* __restrict__ v,
-                                        T* __restrict__ y, int identity_rows, double& dot) {
-  constexpr bool kPlain = kMode == JV_PLAIN;
+                                        T* __restrict__ y, int identity_rows, double& dot,
+                                        const T* __restrict__ sm_b = nullptr, const T* __restrict__ sm_S = nullptr) {
+  constexpr bool kPlain = kMode != JV_DOT;
+  constexpr bool kSmooth = kMode == JV_SMOOTH;
   const unsigned int sbits = cbits;
   auto face = [&](int P, T f[4]) {
     const long b = w.n00 + w.sxy * P;
@@ -174,6 +179,7 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
   T fb[4], ft[4], fn[4];
   T cc[8], cn[8], ee = T(0), en = T(0);
   uint8_t mk = 0, mkn = 0;
+  T xs = T(0), bs = T(0), ss = T(0), xsn = T(0), bsn = T(0), ssn = T(0);  // JV_SMOOTH: v, b, S at the owned node
 #pragma unroll
   for (int k = 0; k < 4; ++k) fb[k] = ft[k] = fn[k] = T(0);
 #pragma unroll
@@ -227,6 +233,12 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
       if ((sbits >> (L1 - w.Lbeg)) & 1u) load8(cq + 8 * sl, cn);
     }
     if (kPlain && w.node_ok && L1 <= w.Lend) mkn = mask[w.node(g, L1)];
+    if (kSmooth && w.node_ok && L1 <= w.Lend) {
+      const long n1 = w.node(g, L1);
+      xsn = v[n1];
+      bsn = sm_b[n1];
+      ssn = sm_S[n1];
+    }
     T out[8];
     if (w.col_ok && layer_ok) {
       const T sx = ee * T(ahx * hz), sy = ee * T(ahy * hz), sz = ee * T(axy * rhz);
@@ -244,6 +256,7 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
       const long n = w.node(g, L);
       T val = carry + bot;
       if (kPlain && mk && identity_rows) val = identity_rows == 1 ? v[n] : T(0);
+      if (kSmooth) val = xs + ss * (bs - val);
       y[n] = val;
     }
     carry = top;
@@ -256,6 +269,9 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
     for (int k = 0; k < 8; ++k) cc[k] = cn[k];
     ee = en;
     mk = mkn;
+    xs = xsn;
+    bs = bsn;
+    ss = ssn;
   }
 }
 
