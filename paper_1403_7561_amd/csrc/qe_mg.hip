@@ -104,15 +104,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 }
 
 // One smoothing step in one launch: xo = x + S (b - J x) on every node (J x
-// as k_mg_jv's, S = 0 on Dirichlet nodes), xo a buffer other than x.  It
-// runs on the coarse levels, whose meshes give about 3 waves per SIMD or
-// fewer, so it may take the registers of 3 (with 4 the FP64 form spills).
+// as k_mg_jv's, S = 0 on Dirichlet nodes), xo a buffer other than x; with
+// part, one b^T xo partial per block, and blocks past the wave map's (the
+// grid may be larger, to give the count a reader expects) write 0.  Its
+// meshes give about 3 waves per SIMD or fewer, so it may take the registers
+// of 3 (with 4 the FP64 form spills).
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_mg_jv_smooth(
     Geom g, WaveMap wm, const T* __restrict__ eps, const unsigned int* __restrict__ cbits,
     const T* __restrict__ cq, const uint8_t* __restrict__ mask, const T* __restrict__ x,
-    const T* __restrict__ b, const T* __restrict__ S, T* __restrict__ xo, const PcgCtx* __restrict__ ctx) {
+    const T* __restrict__ b, const T* __restrict__ S, T* __restrict__ xo, double* __restrict__ part,
+    const PcgCtx* __restrict__ ctx) {
   if (ctx->done) return;
+  if ((int)blockIdx.x >= wm.nblocks) {
+    if (part && threadIdx.x == 0) part[blockIdx.x] = 0.0;
+    return;
+  }
+  __shared__ double sred[4];
   const int w = __builtin_amdgcn_readfirstlane(wave_of_block(blockIdx.x, wm) * 4 + (threadIdx.x >> 6));
   const bool active = w < wm.nwaves;
   int wx, wy, wz;
@@ -121,6 +129,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   const unsigned int cb = active ? cbits[64L * w + (threadIdx.x & 63)] : 0u;
   double dot = 0.0;
   jv_tile<T, JV_SMOOTH>(g, t, eps, cb, cq, mask, x, xo, 2, dot, b, S);
+  if (part) {
+    const double s1 = block_sum(dot, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = s1;
+  }
 }
 
 // The restriction onto small levels, with a group of 16 lanes per coarse
@@ -295,13 +307,13 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict_tile(int nxf, int n
       }
 }
 
-// Fine node: x += P x_c on free nodes, 0 on Dirichlet nodes (the coarse
-// interval and weight per axis from the level's tables); with part, one
-// partial of bdot^T x per block.
+// Fine node: xo = x + P x_c on free nodes, 0 on Dirichlet nodes (the
+// coarse interval and weight per axis from the level's tables; xo may be
+// x); with part, one partial of bdot^T xo per block.
 template <typename T>
 __global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, long Nf, int nxc, int nyc, MgAxes tab,
                                                              const uint8_t* __restrict__ maskf,
-                                                             const T* __restrict__ xcv, T* __restrict__ x,
+                                                             const T* __restrict__ xcv, const T* x, T* xo,
                                                              const T* __restrict__ bdot, double* __restrict__ part,
                                                              const PcgCtx* __restrict__ ctx) {
   if (ctx->done) return;
@@ -309,7 +321,7 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, lo
   double bz = 0.0;
   for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < Nf; n += (long)gridDim.x * blockDim.x) {
     if (maskf[n]) {
-      x[n] = T(0);
+      xo[n] = T(0);
       continue;
     }
     const int i = (int)(n % nxf), j = (int)((n / nxf) % nyf), k = (int)(n / ((long)nxf * nyf));
@@ -323,7 +335,7 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_prolong(int nxf, int nyf, lo
     const double v01 = c[4] + wx * (c[5] - c[4]), v11 = c[6] + wx * (c[7] - c[6]);
     const double v0 = v00 + wy * (v10 - v00), v1 = v01 + wy * (v11 - v01);
     const T xn = (T)((double)x[n] + (v0 + wz * (v1 - v0)));
-    x[n] = xn;
+    xo[n] = xn;
     if (part) bz += (double)bdot[n] * (double)xn;
   }
   if (part) {
@@ -576,20 +588,20 @@ static void restrict_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T
               C.g.ny, C.g.nz, tnx, tny, tnz, C.tab, A.mask, b, y, C.mask, c.S, c.b, c.x, ctx);
 }
 
-// x += P x_c from level C onto level A; with part (grid = nb blocks), one
-// b^T x partial per block.
+// xo = x + P x_c from level C onto level A (xo may be x); with part (grid
+// = nb blocks), one b^T xo partial per block.
 template <typename T>
-static void prolong_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T* xc, T* x, const T* bdot,
-                       double* part, int nb, const PcgCtx* ctx) {
+static void prolong_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T* xc, const T* x, T* xo,
+                       const T* bdot, double* part, int nb, const PcgCtx* ctx) {
   QE_LAUNCH(k_mg_prolong<T>, part ? nb : mg_blocks(A.N, 8192), kVecThreads, s, A.g.nx, A.g.ny, A.N, C.g.nx, C.g.ny,
-            C.tab, A.mask, xc, x, bdot, part, ctx);
+            C.tab, A.mask, xc, x, xo, bdot, part, ctx);
 }
 
 // The V-cycle below level l (levels l .. nlev-1).  On entry level l holds
 // b (its right-hand side) and x = S b; returns the array that holds B_l b
-// (x or y: below the finest level a smoothing step writes the other one).
-// Level 0's last smoothing step writes one b^T x partial per block into part
-// (cgblocks blocks), and its result is always x.
+// (x or y: a smoothing step writes the other one).  Level 0's last
+// smoothing step writes one b^T x partial per block into part (cgblocks
+// blocks), and its result is always x.
 template <typename T>
 static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bool add_top, int cgblocks,
                  double* part, const PcgCtx* ctx) {
@@ -598,15 +610,15 @@ static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bo
   auto jv = [&]() {
     QE_LAUNCH(k_mg_jv<T>, A.wm.nblocks, 256, s, A.g, A.wm, a.eps, A.cbits, a.cq, A.mask, a.x, a.y, ctx);
   };
-  auto jv_smooth = [&](const T* xin, T* xout) {
-    QE_LAUNCH(k_mg_jv_smooth<T>, A.wm.nblocks, 256, s, A.g, A.wm, a.eps, A.cbits, a.cq, A.mask, xin, (const T*)a.b,
-              a.S, xout, ctx);
+  auto jv_smooth = [&](const T* xin, T* xout, double* p, int nb) {
+    QE_LAUNCH(k_mg_jv_smooth<T>, nb, 256, s, A.g, A.wm, a.eps, A.cbits, a.cq, A.mask, xin, (const T*)a.b, a.S, xout,
+              p, ctx);
   };
   if (l == nlev - 1) {
     T* cur = a.x;
     T* nxt = a.y;
     for (int k = 1; k < sweeps; ++k) {
-      jv_smooth(cur, nxt);
+      jv_smooth(cur, nxt, nullptr, A.wm.nblocks);
       std::swap(cur, nxt);
     }
     return cur;
@@ -619,17 +631,26 @@ static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bo
     // semidefinite parts)
     restrict_to(s, A, C, a.b, (const T*)nullptr, c, ctx);
     const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
-    prolong_to<T>(s, A, C, xc, a.x, (const T*)a.b, part, cgblocks, ctx);
+    prolong_to<T>(s, A, C, xc, a.x, a.x, (const T*)a.b, part, cgblocks, ctx);
     return a.x;
   }
   jv();
   restrict_to(s, A, C, a.b, (const T*)a.y, c, ctx);
   const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
-  prolong_to<T>(s, A, C, xc, a.x, (const T*)nullptr, (double*)nullptr, 0, ctx);
   if (l > 0) {
-    jv_smooth(a.x, a.y);
+    prolong_to<T>(s, A, C, xc, a.x, a.x, (const T*)nullptr, (double*)nullptr, 0, ctx);
+    jv_smooth(a.x, a.y, nullptr, A.wm.nblocks);
     return a.y;
   }
+  if (A.wm.nblocks <= cgblocks) {
+    // the finest level's last step in one launch too: interpolate into y,
+    // smooth from y into x (the CG's z), with the r^T z partials in the
+    // CG's block count
+    prolong_to<T>(s, A, C, xc, a.x, a.y, (const T*)nullptr, (double*)nullptr, 0, ctx);
+    jv_smooth(a.y, a.x, part, cgblocks);
+    return a.x;
+  }
+  prolong_to<T>(s, A, C, xc, a.x, a.x, (const T*)nullptr, (double*)nullptr, 0, ctx);
   jv();
   QE_LAUNCH(k_mg_smooth<T>, cgblocks, kVecThreads, s, A.N, a.b, a.y, a.S, a.x, part, ctx);
   return a.x;

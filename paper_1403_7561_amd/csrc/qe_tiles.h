@@ -145,7 +145,7 @@ struct WaveTile {
 //             owned row; dot += v^T J v over the elements this wave owns.
 //   JV_SMOOTH as JV_PLAIN with identity_rows = 2, then a smoothing step:
 //             y = v + S (b - J v) on every owned node (S is 0 on Dirichlet
-//             nodes), y a buffer other than v.
+//             nodes), y a buffer other than v; dot += b^T y over them.
 // In the CG mode the Dirichlet flag is not read at all: the vectors vanish
 // on Dirichlet nodes and D^-1 is 0 there, so whatever y holds on those rows
 // never reaches z, p or x.  (The single-instance CG uses jv_tile_cg below.)
@@ -256,7 +256,10 @@ __device__ __forceinline__ void jv_tile(const Geom& g, const WaveTile& w, const 
       const long n = w.node(g, L);
       T val = carry + bot;
       if (kPlain && mk && identity_rows) val = identity_rows == 1 ? v[n] : T(0);
-      if (kSmooth) val = xs + ss * (bs - val);
+      if (kSmooth) {
+        val = xs + ss * (bs - val);
+        dot += (double)bs * (double)val;
+      }
       y[n] = val;
     }
     carry = top;
