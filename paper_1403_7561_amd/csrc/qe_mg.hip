@@ -251,6 +251,58 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict_tile(int nxf, int n
   const long xn = base + (threadIdx.x < extra ? xcol + (long)nxf * ((long)xey + (long)nyf * xez) : 0);
   const uint8_t xm = maskf[xn];
   const T xr = r[xn], xy = HAS_Y ? y[xn] : T(0);
+  // the taps, weights, flag and S of a coarse node, and its sum from LDS
+  struct Taps {
+    int ix[3], iy[3], iz[3];
+    double wx[3], wy[3], wz[3];
+    uint8_t mc;
+    T st;
+  };
+  auto load_taps = [&](int I, int J, int K, Taps& q) {
+    const long t = (long)I + (long)nxc * ((long)J + (long)nyc * K);
+    q.mc = maskc[t];
+    q.st = Sc[t];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      q.ix[k] = tab.rI[0][3 * I + k] - fx;
+      q.iy[k] = tab.rI[1][3 * J + k] - fy;
+      q.iz[k] = tab.rI[2][3 * K + k] - fz;
+      q.wx[k] = tab.rw[0][3 * I + k];
+      q.wy[k] = tab.rw[1][3 * J + k];
+      q.wz[k] = tab.rw[2][3 * K + k];
+    }
+  };
+  auto sum_taps = [&](int I, int J, int K, const Taps& q) {
+    double v[27];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int bq = 0; bq < 3; ++bq) {
+        const double* row = sv + (q.iz[c] * kRwY + q.iy[bq]) * kRwX;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[(c * 3 + bq) * 3 + a] = row[q.ix[a]];
+      }
+    double b = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int bq = 0; bq < 3; ++bq) {
+        const double wyz = q.wy[bq] * q.wz[c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) b += (wyz * q.wx[a]) * v[(c * 3 + bq) * 3 + a];
+      }
+    const long t = (long)I + (long)nxc * ((long)J + (long)nyc * K);
+    const T bt = q.mc ? T(0) : (T)b;
+    bc[t] = bt;
+    xc[t] = q.st * bt;
+  };
+  // this thread's first coarse node (most threads have no other) is loaded
+  // with the window
+  const int li = threadIdx.x % kRtX, lj = (threadIdx.x / kRtX) % kRtY, lk = threadIdx.x / (kRtX * kRtY);
+  const int Io = I0 + li, Jo = J0 + lj, Ko = K0 + lk;
+  const bool own = Io < I1 && Jo < J1 && Ko < K1;
+  Taps qo;
+  load_taps(min(Io, I1 - 1), min(Jo, J1 - 1), min(Ko, K1 - 1), qo);
 #pragma unroll
   for (int p = 0; p < kRowsPer; ++p) {
     const int row = wv + 4 * p;
@@ -265,45 +317,15 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict_tile(int nxf, int n
     sv[(xez * kRwY + xey) * kRwX + xcol] = xm ? 0.0 : v;
   }
   __syncthreads();
-  const int li = threadIdx.x % kRtX, lj = (threadIdx.x / kRtX) % kRtY, lk = threadIdx.x / (kRtX * kRtY);
-  for (int K = K0 + lk; K < K1; K += kRtZ)
-    for (int J = J0 + lj; J < J1; J += kRtY)
-      for (int I = I0 + li; I < I1; I += kRtX) {
-        const long t = (long)I + (long)nxc * ((long)J + (long)nyc * K);
-        const uint8_t mc = maskc[t];
-        const T st = Sc[t];
-        int ix[3], iy[3], iz[3];
-        double wxs[3], wys[3], wzs[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          ix[k] = tab.rI[0][3 * I + k] - fx;
-          iy[k] = tab.rI[1][3 * J + k] - fy;
-          iz[k] = tab.rI[2][3 * K + k] - fz;
-          wxs[k] = tab.rw[0][3 * I + k];
-          wys[k] = tab.rw[1][3 * J + k];
-          wzs[k] = tab.rw[2][3 * K + k];
-        }
-        double v[27];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int bq = 0; bq < 3; ++bq) {
-            const double* row = sv + (iz[c] * kRwY + iy[bq]) * kRwX;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) v[(c * 3 + bq) * 3 + a] = row[ix[a]];
-          }
-        double b = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int bq = 0; bq < 3; ++bq) {
-            const double wyz = wys[bq] * wzs[c];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) b += (wyz * wxs[a]) * v[(c * 3 + bq) * 3 + a];
-          }
-        const T bt = mc ? T(0) : (T)b;
-        bc[t] = bt;
-        xc[t] = st * bt;
+  if (own) sum_taps(Io, Jo, Ko, qo);
+  // the rest of a wider last tile (a 33rd column, a 5th row, a 3rd layer)
+  for (int K = Ko; K < K1; K += kRtZ)
+    for (int J = Jo; J < J1; J += kRtY)
+      for (int I = Io; I < I1; I += kRtX) {
+        if (I == Io && J == Jo && K == Ko) continue;
+        Taps q;
+        load_taps(I, J, K, q);
+        sum_taps(I, J, K, q);
       }
 }
 
@@ -520,7 +542,7 @@ static int mg_blocks(long n, long cap) {
 // 17x17x9 the 16-lane form took 6.8 and 4.6 us (one thread per node: 12 and
 // 11 us), and the tiled one everywhere made the solve 2.5 % slower; onto
 // 65x65x33 one thread per node took 17.3 us, 16 lanes 27.2, the tiled form
-// 14.9 (and onto 129x129x65 under 257x257x129, 52 against 79 us).
+// 14.1 (and onto 129x129x65 under 257x257x129, 50 against 79 us).
 static const long kMgRestrictGroupMax = 65536;
 
 void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic) {
