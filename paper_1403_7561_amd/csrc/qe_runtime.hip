@@ -447,7 +447,7 @@ static HostMirror& plain_mirror() {
 }
 
 qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t ws_bytes, void* stream_, int kz,
-                        bool no_alloc_, int wave_kz) {
+                        bool no_alloc_, int wave_kz, bool trusted) {
   no_alloc = no_alloc_;
   QE_TRY(check_problem(p));
   if (ch.incomplete && !p->donors)
@@ -483,7 +483,7 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   std::vector<double> c(std::max({p->nx, p->ny, p->nz}));
   const double* arrs[3] = {p->x, p->y, p->z};
   const int lens[3] = {p->nx, p->ny, p->nz};
-  for (int a = 0; a < 3; ++a) {
+  for (int a = 0; a < 3 && !trusted; ++a) {
     QE_HIP(hipMemcpyAsync(c.data(), arrs[a], lens[a] * sizeof(double), hipMemcpyDeviceToHost, s));
     QE_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < lens[a]; ++i)
@@ -491,7 +491,7 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
     for (int i = 1; i < lens[a]; ++i)
       if (!(c[i] > c[i - 1])) return fail(QE_ERR_INVALID_ARG, "coordinates %c not strictly increasing at %d", "xyz"[a], i);
   }
-  if (p->n_dir > 0) {
+  if (p->n_dir > 0 && !trusted) {
     std::vector<double> dv(p->n_dir);
     QE_HIP(hipMemcpyAsync(dv.data(), p->dir_val, p->n_dir * sizeof(double), hipMemcpyDeviceToHost, s));
     QE_HIP(hipStreamSynchronize(s));
@@ -1053,7 +1053,8 @@ struct MgState {
       if (plan.pc[l].quantum) launch_mg_coarsen_states(fine.s, &plan.pc[l - 1], &plan.pc[l]);
       QE_HIP(hipGetLastError());
       const long nl = (long)plan.pc[l].nx * plan.pc[l].ny * plan.pc[l].nz;
-      QE_TRY(cx[l].init(&plan.pc[l], ch, base + plan.o_ws[l], plan.ws_bytes[l], fine.s, 0, false, mg_coarse_kz(nl)));
+      QE_TRY(cx[l].init(&plan.pc[l], ch, base + plan.o_ws[l], plan.ws_bytes[l], fine.s, 0, false, mg_coarse_kz(nl),
+                        true));
       QE_TRY(cx[l].stage(nullptr, 0, 0));
       if (fp32) launch_stage_eps32(fine.s, cx[l].vblocks, cx[l].g, plan.pc[l].eps_r, cx[l].f32(cx[l].lay.eps32),
                                    cx[l].nslots);
@@ -1139,7 +1140,7 @@ static qe_status finish(qe_status st, qe_report& r, qe_report* rep) {
 // fraction of its initial value.
 static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_options* o, double* phi,
                             double* n_nodal, void* ws, size_t ws_bytes, void* stream, qe_report* rep, bool no_alloc,
-                            double newton_rtol = 0.0, int seq_levels = -1) {
+                            double newton_rtol = 0.0, int seq_levels = -1, bool trusted = false) {
   clear_error();
   qe_report r;
   std::memset(&r, 0, sizeof(r));
@@ -1149,9 +1150,10 @@ static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_
   if ((st = make_charge(ph, ch)) != QE_OK) return finish(st, r, rep);
   if (!phi) return finish(fail(QE_ERR_INVALID_ARG, "phi is NULL"), r, rep);
   Context cx;
-  if ((st = cx.init(p, ch, ws, ws_bytes, stream, 0, no_alloc)) != QE_OK) return finish(st, r, rep);
+  if ((st = cx.init(p, ch, ws, ws_bytes, stream, 0, no_alloc, 0, trusted)) != QE_OK) return finish(st, r, rep);
   const bool mixed = o->precision == QE_PREC_MIXED;
-  if ((st = cx.validate(o->init_guess == 1 ? phi : nullptr)) != QE_OK) return finish(st, r, rep);
+  // (a coarse problem built here from this one needs no checks of its own)
+  if (!trusted && (st = cx.validate(o->init_guess == 1 ? phi : nullptr)) != QE_OK) return finish(st, r, rep);
   // coarse-mesh sequence: the coarse problem's arrays are built from this
   // one's (validated above), solved, and its potential interpolated into phi
   bool linear = o->init_guess == 0;
@@ -1166,7 +1168,7 @@ static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_
       qe_report rc;
       double* phic = reinterpret_cast<double*>(base + sp.o_phi);
       const qe_status sc = solve_impl(&sp.pc, ph, o, phic, nullptr, base + sp.o_ws, sp.total - sp.o_ws, stream, &rc,
-                                      no_alloc, seq_rtol((long)sp.pc.nx * sp.pc.ny * sp.pc.nz), levels - 1);
+                                      no_alloc, seq_rtol((long)sp.pc.nx * sp.pc.ny * sp.pc.nz), levels - 1, true);
       if (sc == QE_ERR_HIP) return finish(sc, r, rep);
       if (sc == QE_OK || sc == QE_ERR_NOT_CONVERGED) {
         launch_seq_prolong(cx.s, p, &sp.pc, phic, phi);
