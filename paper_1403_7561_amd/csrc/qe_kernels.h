@@ -57,6 +57,10 @@ void launch_state_boxes(hipStream_t s, int nblocks, const Geom& g, const Quantum
 void launch_validate_quantum(hipStream_t s, int nblocks, const Quantum& qm, int* flags);
 void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const Doping& dop,
                      const int32_t* dir_id, const double* phi, int* flags);
+// Coordinates finite and strictly increasing, Dirichlet values finite
+// (flag bits 128 / 256 / 512 for x / y / z, 1024 for the values).
+void launch_validate_mesh(hipStream_t s, int nx, int ny, int nz, const double* x, const double* y, const double* z,
+                          int n_dir, const double* dir_val, int* flags);
 void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, const double* dir_val, uint8_t* mask,
                   double* phi, int apply, int zero_free);
 // Inverse z spacings, then the spacings, into g.rdz's buffer (2 (nz - 1) values).

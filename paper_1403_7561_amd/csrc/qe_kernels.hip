@@ -606,6 +606,26 @@ __global__ __launch_bounds__(kVecThreads) void k_validate(long N, long E, int n_
   if (f) atomicOr(flags, f);
 }
 
+// Mesh coordinates and Dirichlet values: bits 128 / 256 / 512 of *flags when
+// x / y / z has a value that is not finite or not above the one before it,
+// 1024 when a Dirichlet value is not finite.
+__global__ __launch_bounds__(kVecThreads) void k_validate_mesh(int nx, int ny, int nz, const double* __restrict__ x,
+                                                              const double* __restrict__ y,
+                                                              const double* __restrict__ z, int n_dir,
+                                                              const double* __restrict__ dir_val, int* flags) {
+  const int n[3] = {nx, ny, nz};
+  const double* c[3] = {x, y, z};
+  int f = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n[a]; i += gridDim.x * blockDim.x) {
+      const double v = c[a][i];
+      if (!isfinite(v) || (i > 0 && !(v > c[a][i - 1]))) f |= 128 << a;
+    }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_dir; i += gridDim.x * blockDim.x)
+    if (!isfinite(dir_val[i])) f |= 1024;
+  if (f) atomicOr(flags, f);
+}
+
 // mask[i] = node i is Dirichlet.  Optionally sets phi on Dirichlet nodes to
 // its value and (zero_free) free nodes to 0.
 __global__ __launch_bounds__(kVecThreads) void k_stage(long N, const int32_t* __restrict__ dir_id,
@@ -1030,6 +1050,13 @@ void launch_validate_quantum(hipStream_t s, int nblocks, const Quantum& qm, int*
 void launch_validate(hipStream_t s, int nblocks, long N, long E, int n_dir, const double* eps, const Doping& dop,
                      const int32_t* dir_id, const double* phi, int* flags) {
   QE_LAUNCH(k_validate, nblocks, kVecThreads, s, N, E, n_dir, eps, dop, dir_id, phi, flags);
+}
+
+void launch_validate_mesh(hipStream_t s, int nx, int ny, int nz, const double* x, const double* y, const double* z,
+                          int n_dir, const double* dir_val, int* flags) {
+  const int longest = std::max(std::max(nx, ny), std::max(nz, n_dir));
+  QE_LAUNCH(k_validate_mesh, std::max(1, std::min((longest + kVecThreads - 1) / kVecThreads, 64)), kVecThreads, s, nx,
+            ny, nz, x, y, z, n_dir, dir_val, flags);
 }
 
 void launch_stage(hipStream_t s, int nblocks, long N, const int32_t* dir_id, const double* dir_val, uint8_t* mask,

@@ -93,12 +93,11 @@ struct Context {
   HostMirror* hm = nullptr;
   // wave_kz > 0: the J.v / residual wave tiles' chunk height (else the
   // library's choice for the mesh)
-  // trusted: a problem the library built from one it has checked (a coarse
-  // level): the host checks of its coordinates and Dirichlet values, each a
-  // round trip to the device, are skipped.
   qe_status init(const qe_problem* p, const Charge& ch, void* ws, size_t ws_bytes, void* stream, int kz = 0,
-                 bool no_alloc = false, int wave_kz = 0, bool trusted = false);
+                 bool no_alloc = false, int wave_kz = 0);
   Doping doping() const;
+  // Device-side checks of the problem's arrays (coordinates, Dirichlet ids
+  // and values, eps_r, doping, sheets, states) and of phi: one round trip.
   qe_status validate(const double* phi);
   qe_status stage(double* phi, int apply, int zero_free);
   qe_status residual(const Charge& ch, const double* phi, const double* d64, const float* d32, double lam, bool mixed,

@@ -447,7 +447,7 @@ static HostMirror& plain_mirror() {
 }
 
 qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t ws_bytes, void* stream_, int kz,
-                        bool no_alloc_, int wave_kz, bool trusted) {
+                        bool no_alloc_, int wave_kz) {
   no_alloc = no_alloc_;
   QE_TRY(check_problem(p));
   if (ch.incomplete && !p->donors)
@@ -479,25 +479,6 @@ qe_status Context::init(const qe_problem* p, const Charge& ch, void* ws_, size_t
   ws = reinterpret_cast<char*>(ws_);
   hm = no_alloc ? &plain_mirror() : &mirror();
   if (!hm->ok) return fail(QE_ERR_HIP, "pinned host buffer allocation failed");
-  // coordinates: strictly increasing (host copy; a few KB)
-  std::vector<double> c(std::max({p->nx, p->ny, p->nz}));
-  const double* arrs[3] = {p->x, p->y, p->z};
-  const int lens[3] = {p->nx, p->ny, p->nz};
-  for (int a = 0; a < 3 && !trusted; ++a) {
-    QE_HIP(hipMemcpyAsync(c.data(), arrs[a], lens[a] * sizeof(double), hipMemcpyDeviceToHost, s));
-    QE_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < lens[a]; ++i)
-      if (!std::isfinite(c[i])) return fail(QE_ERR_INVALID_ARG, "coordinate %c[%d] not finite", "xyz"[a], i);
-    for (int i = 1; i < lens[a]; ++i)
-      if (!(c[i] > c[i - 1])) return fail(QE_ERR_INVALID_ARG, "coordinates %c not strictly increasing at %d", "xyz"[a], i);
-  }
-  if (p->n_dir > 0 && !trusted) {
-    std::vector<double> dv(p->n_dir);
-    QE_HIP(hipMemcpyAsync(dv.data(), p->dir_val, p->n_dir * sizeof(double), hipMemcpyDeviceToHost, s));
-    QE_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < p->n_dir; ++i)
-      if (!std::isfinite(dv[i])) return fail(QE_ERR_NONFINITE, "dir_val[%d] not finite", i);
-  }
   g.rdz = f64(lay.rdz);
   g.hz = g.rdz + (p->nz - 1);
   launch_stage_rdz(s, p->nz, p->z, f64(lay.rdz));
@@ -525,9 +506,11 @@ Doping Context::doping() const {
   return Doping{prob.net_doping, prob.donors, prob.acceptors};
 }
 
-// Device-side checks of eps_r, doping, dir_id and (optionally) phi.
+// Device-side checks of the coordinates, Dirichlet ids and values, eps_r,
+// doping, sheets, states and (optionally) phi.
 qe_status Context::validate(const double* phi) {
   int* dflags = reinterpret_cast<int*>(ws + lay.flags);
+  launch_validate_mesh(s, prob.nx, prob.ny, prob.nz, prob.x, prob.y, prob.z, prob.n_dir, prob.dir_val, dflags);
   launch_validate(s, vblocks, N, E, prob.n_dir, prob.eps_r, doping(), prob.dir_id, phi, dflags);
   if (sheets.n > 0) launch_validate_sheets(s, sheets, dflags);
   if (quantum.n > 0) launch_validate_quantum(s, vblocks, quantum, dflags);
@@ -535,6 +518,9 @@ qe_status Context::validate(const double* phi) {
   QE_HIP(hipMemcpyAsync(hm->flags, dflags, sizeof(int), hipMemcpyDeviceToHost, s));
   QE_HIP(hipStreamSynchronize(s));
   const int f = *hm->flags;
+  for (int a = 0; a < 3; ++a)
+    if (f & (128 << a)) return fail(QE_ERR_INVALID_ARG, "coordinates %c not finite or not strictly increasing", "xyz"[a]);
+  if (f & 1024) return fail(QE_ERR_NONFINITE, "dir_val not finite");
   if (f & 1) return fail(QE_ERR_INVALID_ARG, "eps_r must be finite and > 0");
   if (f & 2) return fail(QE_ERR_NONFINITE, "net_doping not finite or donors / acceptors not finite and >= 0");
   if (f & 4) return fail(QE_ERR_INVALID_ARG, "dir_id outside [-1, n_dir)");
@@ -1053,8 +1039,7 @@ struct MgState {
       if (plan.pc[l].quantum) launch_mg_coarsen_states(fine.s, &plan.pc[l - 1], &plan.pc[l]);
       QE_HIP(hipGetLastError());
       const long nl = (long)plan.pc[l].nx * plan.pc[l].ny * plan.pc[l].nz;
-      QE_TRY(cx[l].init(&plan.pc[l], ch, base + plan.o_ws[l], plan.ws_bytes[l], fine.s, 0, false, mg_coarse_kz(nl),
-                        true));
+      QE_TRY(cx[l].init(&plan.pc[l], ch, base + plan.o_ws[l], plan.ws_bytes[l], fine.s, 0, false, mg_coarse_kz(nl)));
       QE_TRY(cx[l].stage(nullptr, 0, 0));
       if (fp32) launch_stage_eps32(fine.s, cx[l].vblocks, cx[l].g, plan.pc[l].eps_r, cx[l].f32(cx[l].lay.eps32),
                                    cx[l].nslots);
@@ -1150,9 +1135,10 @@ static qe_status solve_impl(const qe_problem* p, const qe_physics* ph, const qe_
   if ((st = make_charge(ph, ch)) != QE_OK) return finish(st, r, rep);
   if (!phi) return finish(fail(QE_ERR_INVALID_ARG, "phi is NULL"), r, rep);
   Context cx;
-  if ((st = cx.init(p, ch, ws, ws_bytes, stream, 0, no_alloc, 0, trusted)) != QE_OK) return finish(st, r, rep);
+  if ((st = cx.init(p, ch, ws, ws_bytes, stream, 0, no_alloc)) != QE_OK) return finish(st, r, rep);
   const bool mixed = o->precision == QE_PREC_MIXED;
-  // (a coarse problem built here from this one needs no checks of its own)
+  // (trusted: a coarse problem built here from a checked one needs no
+  // checks, each a round trip to the device)
   if (!trusted && (st = cx.validate(o->init_guess == 1 ? phi : nullptr)) != QE_OK) return finish(st, r, rep);
   // coarse-mesh sequence: the coarse problem's arrays are built from this
   // one's (validated above), solved, and its potential interpolated into phi

@@ -243,6 +243,22 @@ def test_device_side_validation():
     dev.net_doping[3] = np.nan
     with pytest.raises(qe.QeError, match="NONFINITE"):
         qe.qe_solve(qe.Problem(dev))
+    # mesh coordinates and Dirichlet values, checked on the device as well
+    dev = synth.config1()
+    dev.x = dev.x.copy()
+    dev.x[4] = dev.x[3]
+    with pytest.raises(qe.QeError, match="coordinates x"):
+        qe.qe_solve(qe.Problem(dev))
+    dev = synth.config1()
+    dev.z = dev.z.copy()
+    dev.z[-1] = np.inf
+    with pytest.raises(qe.QeError, match="coordinates z"):
+        qe.qe_solve(qe.Problem(dev))
+    dev = synth.config1()
+    dev.dir_val = np.array(dev.dir_val, dtype=np.float64)
+    dev.dir_val[0] = np.nan
+    with pytest.raises(qe.QeError, match="dir_val"):
+        qe.qe_solve(qe.Problem(dev))
 
 
 def test_newton_status_codes():
