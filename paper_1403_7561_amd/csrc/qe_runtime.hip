@@ -164,9 +164,11 @@ WaveMap make_wavemap(int nx, int ny, int nz, int kz) {
     // taller chunks recompute fewer halo layers and, at 9, put a
     // 129x129x65 mesh's CG sweep in one round of 3 waves per SIMD
     // (measured fastest there and at 257x257x129); a small mesh gets
-    // shorter chunks, hence more waves
+    // shorter chunks, hence more waves, down to 3 (the 65x65x33 coarse
+    // start: 1100 waves; its solve with chunks of 4 / 3 / 2 / 1 made the
+    // 129x129x65 solve 9.69 / 9.57 / 9.75 / 9.90 ms)
     kz = 9;
-    while (kz > 4 && (long)wm.gx * wm.gy * ((nz + kz - 1) / kz) < 2048) --kz;
+    while (kz > 3 && (long)wm.gx * wm.gy * ((nz + kz - 1) / kz) < 2048) --kz;
   }
   wm.kz = std::max(1, std::min(kz, 31));
   wm.gz = (nz + wm.kz - 1) / wm.kz;
