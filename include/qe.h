@@ -98,9 +98,10 @@ typedef enum {
  * more the finest level only adds its correction (z = S r + P B_1 P^T r).
  * It is symmetric positive definite (any weight below 2 keeps it so), so
  * the CG stays plain CG.  AUTO takes multigrid for the Newton steps whose
- * CG tolerance is at most 3e-2 and for the adjoint, where one V-cycle (the
- * cost of about seven Jacobi iterations at 129 x 129 x 65) saves more
- * iterations than it costs, and Jacobi otherwise.  In mixed precision the
+ * CG tolerance is at most 3e-2 (1e-1 on meshes of 4M nodes and more, where
+ * a V-cycle costs less relative to a Jacobi iteration) and for the adjoint,
+ * where one V-cycle saves more iterations than it costs, and Jacobi
+ * otherwise.  In mixed precision the
  * V-cycle runs in FP32 like the CG it serves.  With sheets the V-cycle
  * leaves out the Robin face term (it stays positive definite); with
  * eigenstates every coarse mesh carries them, injected like the potential.

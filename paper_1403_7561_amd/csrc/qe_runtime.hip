@@ -923,6 +923,13 @@ static const double kMgOmega = 1.8;
 // save (257x257x129: solve 88 -> 76 ms, adjoint 39 -> 34 ms; at 129x129x65
 // the multiplicative form is faster, 11.3 against 11.9 ms).
 static const long kMgAddTopNodes = 4000000;
+// On those meshes a V-cycle costs about two Jacobi iterations, so the AUTO
+// rule takes it from this CG tolerance on (257x257x129: 3e-2 / 5e-2 / 1e-1
+// / 2e-1 gave FP64 solves of 71.5 / 48.0 / 46.8 / 46.8 ms, mixed 50.4 /
+// 37.3 / 37.3 / 37.3; the same on its 129x129x65 coarse start as well
+// measured slower, 47.7, and at 129x129x65 itself 1e-1 made the solve 3 %
+// slower).
+static const double kMgEtaLarge = 1e-1;
 static double mg_omega() {
   const double w = env_double("QE_MG_OMEGA", kMgOmega);
   return (w > 0.0 && w < 2.0) ? w : kMgOmega;
@@ -1006,7 +1013,13 @@ static size_t extra_bytes(const qe_problem* p, int seq_levels) {
   return std::max(seq_extra_bytes(p, seq_levels), mg_extra_bytes(p));
 }
 
-static double mg_eta() { return env_double("QE_MG_ETA", kMgEta); }
+// The AUTO threshold for a mesh of this many nodes (QE_MG_ETA overrides it
+// for every mesh).
+static double mg_eta(long nodes) {
+  const char* v = getenv("QE_MG_ETA");
+  if (v) return atof(v);
+  return nodes >= env_long("QE_MG_ADD_NODES", kMgAddTopNodes) ? kMgEtaLarge : kMgEta;
+}
 
 // One call's multigrid levels: planned when the call may use them, set up
 // on first use, linearised at each potential a CG solve with them starts
@@ -1033,7 +1046,7 @@ struct MgState {
     possible = mg_plan(p, base, plan) && ws_bytes - fine >= plan.total;
   }
   bool wanted(const qe_options* o, double eta) const {
-    return possible && (o->precond == QE_PC_MULTIGRID || eta <= mg_eta());
+    return possible && (o->precond == QE_PC_MULTIGRID || eta <= mg_eta(plan.pc[0].nx * (long)plan.pc[0].ny * plan.pc[0].nz));
   }
   qe_status setup(Context& fine, const Charge& ch) {
     for (int l = 1; l < plan.nlev; ++l) {
