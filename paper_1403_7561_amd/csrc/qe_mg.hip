@@ -35,6 +35,7 @@
 // (ctx->done), like the CG loop's own kernels, so launches queued after the
 // stop cost only their dispatch.
 #include <algorithm>
+#include <cstdlib>
 
 #include "qe_kernels.h"
 #include "qe_tiles.h"
@@ -537,13 +538,17 @@ static int mg_blocks(long n, long cap) {
   return (int)std::max(1L, std::min((n + kVecThreads - 1) / kVecThreads, cap));
 }
 
-// Coarse levels below this many nodes take the restriction with 16 lanes per
-// node, larger ones the tiled one.  Under 129x129x65: onto 33x33x17 and
+// Coarse levels below this many nodes (QE_MG_RGROUP_MAX overrides it) take
+// the restriction with 16 lanes per node, larger ones the tiled one.  Under 129x129x65: onto 33x33x17 and
 // 17x17x9 the 16-lane form took 6.8 and 4.6 us (one thread per node: 12 and
 // 11 us), and the tiled one everywhere made the solve 2.5 % slower; onto
 // 65x65x33 one thread per node took 17.3 us, 16 lanes 27.2, the tiled form
 // 14.1 (and onto 129x129x65 under 257x257x129, 50 against 79 us).
 static const long kMgRestrictGroupMax = 65536;
+static long mg_group_max() {
+  const char* v = getenv("QE_MG_RGROUP_MAX");
+  return v ? atol(v) : kMgRestrictGroupMax;
+}
 
 void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic) {
   QE_LAUNCH(k_mg_inject, mg_blocks(c.N, 4096), kVecThreads, s, f.g.nx, f.g.ny, f.g.nz, c.g.nx, c.g.ny, c.g.nz, phif,
@@ -593,8 +598,8 @@ struct MgView<float> {
 // P^T b).
 template <typename T>
 static void restrict_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T* b, const T* y, const MgView<T>& c,
-                        const PcgCtx* ctx) {
-  if (C.N < kMgRestrictGroupMax) {
+                        long group_max, const PcgCtx* ctx) {
+  if (C.N < group_max) {
     constexpr long per = kVecThreads / 16;
     const int nb = (int)std::max(1L, std::min((C.N + per - 1) / per, 16384L));
     QE_LAUNCH(k_mg_restrict16<T>, nb, kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab, A.mask, b, y,
@@ -626,7 +631,7 @@ static void prolong_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T*
 // blocks), and its result is always x.
 template <typename T>
 static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bool add_top, int cgblocks,
-                 double* part, const PcgCtx* ctx) {
+                 double* part, long group_max, const PcgCtx* ctx) {
   const MgGrid& A = L[l];
   const MgView<T> a(A);
   auto jv = [&]() {
@@ -651,14 +656,14 @@ static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bo
     // additive top level: z = S r + P B_1 P^T r, no smoothing products on
     // the finest mesh (positive definite as a sum of positive definite and
     // semidefinite parts)
-    restrict_to(s, A, C, a.b, (const T*)nullptr, c, ctx);
-    const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
+    restrict_to(s, A, C, a.b, (const T*)nullptr, c, group_max, ctx);
+    const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, group_max, ctx);
     prolong_to<T>(s, A, C, xc, a.x, a.x, (const T*)a.b, part, cgblocks, ctx);
     return a.x;
   }
   jv();
-  restrict_to(s, A, C, a.b, (const T*)a.y, c, ctx);
-  const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
+  restrict_to(s, A, C, a.b, (const T*)a.y, c, group_max, ctx);
+  const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, group_max, ctx);
   if (l > 0) {
     prolong_to<T>(s, A, C, xc, a.x, a.x, (const T*)nullptr, (double*)nullptr, 0, ctx);
     jv_smooth(a.x, a.y, nullptr, A.wm.nblocks);
@@ -680,10 +685,11 @@ static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bo
 
 void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, bool add_top, int cgblocks,
                       double* part_rz, const PcgCtx* ctx, bool fp32) {
+  const long group_max = mg_group_max();
   if (fp32)
-    vcycle<float>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, ctx);
+    vcycle<float>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, group_max, ctx);
   else
-    vcycle<double>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, ctx);
+    vcycle<double>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, group_max, ctx);
 }
 
 }  // namespace qe

@@ -4,8 +4,8 @@ preconditions still converges to the one discrete solution.  These tests
 lower the size threshold (QE_MG_MIN_NODES) so that meshes the oracle solves
 quickly run it: solves and the adjoint against the oracle with multigrid on
 every CG (odd and even node counts: the restriction's clamped last coarse
-interval; sheets and eigenstates; mixed precision), far fewer iterations
-than Jacobi, the fallbacks to Jacobi, and
+interval; sheets and eigenstates; mixed precision; the tiled restriction
+on ragged tiles), far fewer iterations than Jacobi, the fallbacks to Jacobi, and
 the 129 x 129 x 65 stack's default solve and adjoint against the Jacobi
 ones."""
 import numpy as np
@@ -50,6 +50,33 @@ def test_multigrid_solve_matches_oracle(monkeypatch, dims, levels):
     _, res = solver.solve(dev, atol=1e-10)
     assert rel_max(phi.cpu().numpy(), res.phi) <= 1e-9
     assert rel_max(phi.cpu().numpy(), phj.cpu().numpy()) <= 1e-9
+
+
+@pytest.mark.parametrize("dims,add_top,precision", [
+    ((33, 33, 17), False, 0),   # tiles of 17x17x9 coarse nodes: one short tile per axis
+    ((36, 30, 20), False, 0),   # even counts: 19x16x11
+    ((65, 57, 33), False, 0),   # two levels below: 33x29x17 (tiles 32+1 wide), 17x15x9
+    ((36, 30, 20), True, 0),    # the additive finest level restricts r alone
+    ((65, 57, 33), False, 1),   # the FP32 V-cycle
+])
+def test_multigrid_tiled_restriction_matches_oracle(monkeypatch, dims, add_top, precision):
+    """The tiled restriction (the default onto levels of 65536 nodes and
+    more, forced onto every level here through QE_MG_RGROUP_MAX): ragged
+    tiles of odd and even meshes, with and without J x, in FP64 and FP32."""
+    monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
+    monkeypatch.setenv("QE_MG_RGROUP_MAX", "0")
+    if add_top:
+        monkeypatch.setenv("QE_MG_ADD_NODES", "1000")
+    dev = double_dot(*dims)
+    P = qe.Problem(dev)
+    phi, _, rep = qe.qe_solve(P, opts=qe.qe_default_options(newton_atol=1e-10, precond=MULTIGRID,
+                                                             precision=precision))
+    print(dims, add_top, precision, rep)
+    assert rep["status"] == 0 and rep["res_final"] <= 1e-10
+    assert rep["mg_levels"] >= 2 and rep["mg_krylov_iters"] == rep["krylov_iters"] - rep["init_krylov_iters"] > 0
+    _, res = solver.solve(dev, atol=1e-10)
+    # FP64: the solve's bound; mixed: the mixed path's (as in the test above)
+    assert rel_max(phi.cpu().numpy(), res.phi) <= (1e-9 if precision == 0 else 1e-6)
 
 
 def test_multigrid_additive_top_level(monkeypatch):
