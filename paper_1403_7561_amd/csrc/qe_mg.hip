@@ -31,6 +31,11 @@
 // mixed-precision Newton (FP32 coefficients, permittivities, smoother
 // weights and vectors; restriction sums and the r^T z partials in FP64).
 //
+// A smoothing step after the coarse correction, and each of the coarsest
+// level's, is one launch: the level's wave-tiled J.v in a smoothing mode
+// writes x + S (b - J x) into the level's other vector as each row
+// completes, so a level's x and y take turns holding its iterate.
+//
 // Every kernel here returns at once when the CG it serves has stopped
 // (ctx->done), like the CG loop's own kernels, so launches queued after the
 // stop cost only their dispatch.
