@@ -491,51 +491,85 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_inject(int nxf, int nyf, int
 // element's stiffness in the weights sx = eps h_y h_z / h_x, ...).  B^T c is
 // the coefficient term's product with the all-ones vector (the stiffness
 // rows sum to zero), so jv_element gives it.
+// One thread per node column (i, j) and chunk of kc node layers: it walks
+// up the column, and each element layer's (up to) four elements around the
+// column give the row sums of the node below them and of the node above
+// (carried to the next layer).  The box element's stiffness rows all have the
+// same absolute sum, so that part is formed once per element.
 __global__ __launch_bounds__(kVecThreads) void k_mg_l1(Geom g, const double* __restrict__ eps,
                                                         const uint8_t* __restrict__ cflag,
                                                         const double* __restrict__ cq,
-                                                        const uint8_t* __restrict__ mask, double omega,
+                                                        const uint8_t* __restrict__ mask, double omega, int kc,
                                                         double* __restrict__ S, float* __restrict__ S32) {
-  const long N = (long)g.nx * g.ny * g.nz;
+  const int nchunks = (g.nz + kc - 1) / kc;
   const int gx = (g.nx + 6) / 7, gy = (g.ny + 6) / 7;
-  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (long)gridDim.x * blockDim.x) {
-    if (mask[n]) {
-      S[n] = 0.0;
-      if (S32) S32[n] = 0.0f;
-      continue;
+  const int ncols = g.nx * g.ny;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ncols * nchunks; t += gridDim.x * blockDim.x) {
+    const int i = t % g.nx, r = t / g.nx, j = r % g.ny, ch = r / g.ny;
+    const int k0 = ch * kc, k1 = min(k0 + kc, g.nz);
+    // the four element columns around node column (i, j): ex = i - 1 + a,
+    // ey = j - 1 + b; this node is their local corner (1 - a, 1 - b)
+    bool ok[4];
+    double ahx[4], ahy[4], axy[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ex = i - 1 + (q & 1), ey = j - 1 + (q >> 1);
+      ok[q] = ex >= 0 && ex <= g.nx - 2 && ey >= 0 && ey <= g.ny - 2;
+      const int cx = min(max(ex, 0), g.nx - 2), cy = min(max(ey, 0), g.ny - 2);
+      const double hx = g.x[cx + 1] - g.x[cx], hy = g.y[cy + 1] - g.y[cy];
+      ahx[q] = hy / hx;
+      ahy[q] = hx / hy;
+      axy[q] = hx * hy;
     }
-    const int i = (int)(n % g.nx), j = (int)((n / g.nx) % g.ny), k = (int)(n / ((long)g.nx * g.ny));
-    double sum = 0.0;
-    for (int ez = max(k - 1, 0); ez <= min(k, g.nz - 2); ++ez)
-      for (int ey = max(j - 1, 0); ey <= min(j, g.ny - 2); ++ey)
-        for (int ex = max(i - 1, 0); ex <= min(i, g.nx - 2); ++ex) {
-          const double hx = g.x[ex + 1] - g.x[ex], hy = g.y[ey + 1] - g.y[ey], hz = g.z[ez + 1] - g.z[ez];
-          const double e = eps[(long)ex + (long)(g.nx - 1) * ((long)ey + (long)(g.ny - 1) * ez)];
-          const double sx = e * hy * hz / hx, sy = e * hx * hz / hy, sz = e * hx * hy / hz;
-          double st = 0.0;
+    // the row sums layer ez gives the node column's nodes at ez (bottom) and
+    // ez + 1 (top)
+    auto layer = [&](int ez, double& bot, double& top) {
+      bot = top = 0.0;
+      const double hz = g.z[ez + 1] - g.z[ez];
 #pragma unroll
-          for (int d = 0; d < 8; ++d) {
-            const bool dx = d & 1, dy = d & 2, dz = d & 4;
-            const double kx = dx ? -1.0 : 1.0, ky = dy ? -1.0 : 1.0, kz = dz ? -1.0 : 1.0;
-            const double mx = dx ? 1.0 / 6.0 : 1.0 / 3.0, my = dy ? 1.0 / 6.0 : 1.0 / 3.0,
-                         mz = dz ? 1.0 / 6.0 : 1.0 / 3.0;
-            st += fabs(sx * kx * my * mz + sy * mx * ky * mz + sz * mx * my * kz);
-          }
-          sum += st;
-          const long sl = tile_slot(ex, ey, ez, gx, gy);
-          if (cflag[sl]) {
-            double c[8], ones[8], out[8];
+      for (int q = 0; q < 4; ++q) {
+        if (!ok[q]) continue;
+        const int ex = i - 1 + (q & 1), ey = j - 1 + (q >> 1);
+        const double e = eps[(long)ex + (long)(g.nx - 1) * ((long)ey + (long)(g.ny - 1) * ez)];
+        const double sx = e * ahx[q] * hz, sy = e * ahy[q] * hz, sz = e * axy[q] / hz;
+        double st = 0.0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              c[q] = cq[8 * sl + q];
-              ones[q] = 1.0;
-            }
-            jv_element<double, false>(ones, 0.0, 0.0, 0.0, c, true, out);
-            sum += out[(i - ex) + 2 * (j - ey) + 4 * (k - ez)];
-          }
+        for (int d = 0; d < 8; ++d) {
+          const bool dx = d & 1, dy = d & 2, dz = d & 4;
+          const double kx = dx ? -1.0 : 1.0, ky = dy ? -1.0 : 1.0, kz = dz ? -1.0 : 1.0;
+          const double mx = dx ? 1.0 / 6.0 : 1.0 / 3.0, my = dy ? 1.0 / 6.0 : 1.0 / 3.0,
+                       mz = dz ? 1.0 / 6.0 : 1.0 / 3.0;
+          st += fabs(sx * kx * my * mz + sy * mx * ky * mz + sz * mx * my * kz);
         }
-    S[n] = sum > 0.0 ? omega / sum : 0.0;
-    if (S32) S32[n] = (float)S[n];
+        bot += st;
+        top += st;
+        const long sl = tile_slot(ex, ey, ez, gx, gy);
+        if (cflag[sl]) {
+          double c[8], ones[8], out[8];
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            c[m] = cq[8 * sl + m];
+            ones[m] = 1.0;
+          }
+          jv_element<double, false>(ones, 0.0, 0.0, 0.0, c, true, out);
+          const int li = (1 - (q & 1)) + 2 * (1 - (q >> 1));
+          bot += out[li];
+          top += out[li + 4];
+        }
+      }
+    };
+    double carry = 0.0, bot, top;
+    if (k0 > 0) layer(k0 - 1, bot, carry);
+    for (int k = k0; k < k1; ++k) {
+      bot = top = 0.0;
+      if (k <= g.nz - 2) layer(k, bot, top);
+      const double sum = carry + bot;
+      carry = top;
+      const long n = (long)i + (long)g.nx * ((long)j + (long)g.ny * k);
+      const double sn = mask[n] || !(sum > 0.0) ? 0.0 : omega / sum;
+      S[n] = sn;
+      if (S32) S32[n] = (float)sn;
+    }
   }
 }
 
@@ -562,7 +596,10 @@ void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const dou
 
 void launch_mg_l1(hipStream_t s, const MgGrid& L, const double* eps_natural, const uint8_t* cflag, double omega,
                   bool fp32) {
-  QE_LAUNCH(k_mg_l1, mg_blocks(L.N, 8192), kVecThreads, s, L.g, eps_natural, cflag, L.cq, L.mask, omega, L.S,
+  // chunks of 8 layers on large meshes, shorter (more threads) on small ones
+  const int kc = (int)std::max(1L, std::min(8L, L.N / 262144));
+  const long threads = (long)L.g.nx * L.g.ny * ((L.g.nz + kc - 1) / kc);
+  QE_LAUNCH(k_mg_l1, mg_blocks(threads, 8192), kVecThreads, s, L.g, eps_natural, cflag, L.cq, L.mask, omega, kc, L.S,
             fp32 ? L.S32 : nullptr);
 }
 
