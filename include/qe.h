@@ -265,8 +265,8 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o);
  * coarsened (every other node along each axis, the last one kept; each
  * coarse element takes the materials of its first fine element), that
  * problem is solved from the linear guess until ||F|| falls to a fraction
- * 1e-3 (139425 / N_coarse)^(2/3) of its initial value (the coarse mesh's
- * error against this one falls as h^2), and its potential, interpolated
+ * 1e-3 (139425 / N_coarse)^(1/3) of its initial value (a finer coarse mesh
+ * is worth solving further; measured), and its potential, interpolated
  * trilinearly, starts Newton here; the solution is the same (the discrete problem has one
  * solution), only the iteration counts change.  Smaller meshes, sheets,
  * eigenstates, a coarse solve that fails, or a workspace without room for

@@ -798,12 +798,15 @@ static const long kSeqMinNodes = 250000;
 static const int kSeqLevels = 1;
 
 // The coarse solve need not be more accurate than the coarse mesh's own
-// error against the fine one, which falls as h^2: 1e-3 for a coarse mesh of
-// 139,425 nodes (the 129x129x65 problem's), scaled by (139425 / N_c)^(2/3).
+// error against the fine one, which falls with h: 1e-3 for a coarse mesh of
+// 139,425 nodes (the 129x129x65 problem's), scaled by (139425 / N_c)^(1/3).
 // Measured at 129x129x65: 1e-2 / 3e-3 / 1e-3 / 1e-4 gave 20.1 / 19.2 / 17.9 /
-// 18.7 ms; at 257x257x129 (coarse 1.08M nodes): 1e-3 / 1e-4 gave 269 / 245 ms.
+// 18.7 ms (with the V-cycle: 3e-3 / 1e-3 / 3e-4 gave 10.6 / 9.4 / 10.5 ms);
+// at 257x257x129 (coarse 1.08M nodes), with the V-cycle, 1e-3 / 5e-4 / 2.6e-4
+// / 1e-4 gave 46.2 / 43.1 / 46.0 / 50.2 ms (the scaling was (.)^(2/3), giving
+// 2.6e-4, before the V-cycle took the fine Newton's last steps).
 static double seq_rtol(long n_coarse) {
-  const double r = 1e-3 * std::pow(139425.0 / (double)n_coarse, 2.0 / 3.0);
+  const double r = 1e-3 * std::pow(139425.0 / (double)n_coarse, 1.0 / 3.0);
   return env_double("QE_SEQ_RTOL", std::min(1e-2, std::max(1e-5, r)));
 }
 
