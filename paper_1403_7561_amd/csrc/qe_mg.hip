@@ -189,21 +189,22 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict16(int nxf, int nyf,
   }
 }
 
-// Tiles of the tiled restriction.  Along each axis a mesh of n nodes is cut
-// into ceil((n - 1) / w) tiles of w nodes, the last taking the rest (w + 1
-// at most), so 2^k + 1 meshes get no one-node tiles.
-__device__ __forceinline__ void mg_tile(int t, int tn, int n, int w, int& lo, int& hi) {
+// Tiles of the tiled restriction: along each axis ceil(n / w) tiles of w
+// nodes, the last one shorter.  (Letting the last tile take one node more,
+// so that 2^k + 1 meshes get no one-node tiles, needs a larger LDS window:
+// 3 blocks per CU instead of 6, measured slower.)
+__device__ __forceinline__ void mg_tile(int t, int n, int w, int& lo, int& hi) {
   lo = t * w;
-  hi = (t == tn - 1) ? n : lo + w;
+  hi = min(lo + w, n);
 }
-static inline int mg_ntiles(int n, int w) { return n > 1 ? (n - 1 + w - 1) / w : 1; }
+static inline int mg_ntiles(int n, int w) { return (n + w - 1) / w; }
 
 // Restriction tiles of 32 x 4 x 2 coarse nodes, one per thread.  The taps of
 // coarse node I lie in [f(I) - 1, f(I) + 1] and move forward with I, so a
 // tile of w coarse nodes reads a window of at most 2 w + 1 fine nodes, from
 // the first tap of its first node to the last tap of its last.
 constexpr int kRtX = 32, kRtY = 4, kRtZ = 2;
-constexpr int kRwX = 2 * (kRtX + 1) + 1, kRwY = 2 * (kRtY + 1) + 1, kRwZ = 2 * (kRtZ + 1) + 1;
+constexpr int kRwX = 2 * kRtX + 1, kRwY = 2 * kRtY + 1, kRwZ = 2 * kRtZ + 1;
 constexpr int kRowsPer = (kRwY * kRwZ + 3) / 4;
 
 // The restriction onto larger levels (what k_mg_restrict16 computes), one
@@ -224,9 +225,9 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict_tile(int nxf, int n
   __shared__ double sv[kRwX * kRwY * kRwZ];
   const int tx = blockIdx.x % tnx, ty = (blockIdx.x / tnx) % tny, tz = blockIdx.x / (tnx * tny);
   int I0, I1, J0, J1, K0, K1;
-  mg_tile(tx, tnx, nxc, kRtX, I0, I1);
-  mg_tile(ty, tny, nyc, kRtY, J0, J1);
-  mg_tile(tz, tnz, nzc, kRtZ, K0, K1);
+  mg_tile(tx, nxc, kRtX, I0, I1);
+  mg_tile(ty, nyc, kRtY, J0, J1);
+  mg_tile(tz, nzc, kRtZ, K0, K1);
   // window [f(I0) - 1, f(I1 - 1) + 1] clipped to the mesh: it holds every
   // tap of the tile (a tap that is no neighbour of a coarse node is staged
   // but not read)
@@ -236,8 +237,8 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict_tile(int nxf, int n
   const int rows = wy * (min(mg_fine(K1 - 1, nzf) + 1, nzf - 1) - fz + 1);
   const long base = (long)fx + (long)nxf * ((long)fy + (long)nyf * fz);
   // one window row per wave and step (lanes along x), all loads issued
-  // before the first use; columns past 64 (only in the wider last tiles)
-  // follow, one per thread
+  // before the first use; the 65th column of a full tile's window follows,
+  // one node per thread
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ex = min(lane, wx - 1);
   uint8_t m[kRowsPer];
@@ -302,8 +303,8 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict_tile(int nxf, int n
     bc[t] = bt;
     xc[t] = q.st * bt;
   };
-  // this thread's first coarse node (most threads have no other) is loaded
-  // with the window
+  // this thread's coarse node (one per thread: a tile has at most 256) is
+  // loaded with the window
   const int li = threadIdx.x % kRtX, lj = (threadIdx.x / kRtX) % kRtY, lk = threadIdx.x / (kRtX * kRtY);
   const int Io = I0 + li, Jo = J0 + lj, Ko = K0 + lk;
   const bool own = Io < I1 && Jo < J1 && Ko < K1;
@@ -324,15 +325,6 @@ __global__ __launch_bounds__(kVecThreads) void k_mg_restrict_tile(int nxf, int n
   }
   __syncthreads();
   if (own) sum_taps(Io, Jo, Ko, qo);
-  // the rest of a wider last tile (a 33rd column, a 5th row, a 3rd layer)
-  for (int K = Ko; K < K1; K += kRtZ)
-    for (int J = Jo; J < J1; J += kRtY)
-      for (int I = Io; I < I1; I += kRtX) {
-        if (I == Io && J == Jo && K == Ko) continue;
-        Taps q;
-        load_taps(I, J, K, q);
-        sum_taps(I, J, K, q);
-      }
 }
 
 // Fine node: xo = x + P x_c on free nodes, 0 on Dirichlet nodes (the
