@@ -40,7 +40,6 @@
 // (ctx->done), like the CG loop's own kernels, so launches queued after the
 // stop cost only their dispatch.
 #include <algorithm>
-#include <cstdlib>
 
 #include "qe_kernels.h"
 #include "qe_tiles.h"
@@ -141,54 +140,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   }
 }
 
-// The restriction onto small levels, with a group of 16 lanes per coarse
-// node (coarse node (I, J, K): b_c = sum over fine nodes of P_fine,coarse
-// (r - y), y = NULL: r alone, with fine Dirichlet nodes counted as 0 (the
-// CG's own r is not zero on their rows: its J.v writes them), 0 on coarse
-// Dirichlet nodes; x_c = S_c b_c, the pre-smoothing step from zero; the
-// taps and weights per axis come from the level's tables, formed once per
-// setup by mg_taps).
-template <typename T>
-__global__ __launch_bounds__(kVecThreads) void k_mg_restrict16(int nxf, int nyf, int nxc, int nyc, long Nc,
-                                                                MgAxes tab, const uint8_t* __restrict__ maskf,
-                                                                const T* __restrict__ r, const T* __restrict__ y,
-                                                                const uint8_t* __restrict__ maskc,
-                                                                const T* __restrict__ Sc, T* __restrict__ bc,
-                                                                T* __restrict__ xc, const PcgCtx* __restrict__ ctx) {
-  if (ctx->done) return;
-  // a group of 16 lanes per coarse node: lane j < 9 takes the y tap j % 3
-  // and the z tap j / 3 with their three x taps, so the 27 gathers run on 9
-  // lanes at once; the partial sums meet in a fixed order (shuffles)
-  constexpr int G = 16;
-  const int j = threadIdx.x & (G - 1);
-  const long groups = (long)gridDim.x * (kVecThreads / G);
-  for (long t = (long)blockIdx.x * (kVecThreads / G) + (threadIdx.x / G); t < Nc; t += groups) {
-    double b = 0.0;
-    const bool free_c = !maskc[t];
-    if (free_c && j < 9) {
-      const int I = (int)(t % nxc), J = (int)((t / nxc) % nyc), K = (int)(t / ((long)nxc * nyc));
-      const int bq = j % 3, c = j / 3;
-      const long row = (long)nxf * ((long)tab.rI[1][3 * J + bq] + (long)nyf * tab.rI[2][3 * K + c]);
-      const double wyz = tab.rw[1][3 * J + bq] * tab.rw[2][3 * K + c];
-      double v[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const long n = row + tab.rI[0][3 * I + a];
-        v[a] = maskf[n] ? 0.0 : (double)r[n] - (y ? (double)y[n] : 0.0);
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) b += (wyz * tab.rw[0][3 * I + a]) * v[a];
-    }
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) b += __shfl_xor(b, off, G);
-    if (j == 0) {
-      const T bt = free_c ? (T)b : T(0);
-      bc[t] = bt;
-      xc[t] = Sc[t] * bt;
-    }
-  }
-}
-
 // Tiles of the tiled restriction: along each axis ceil(n / w) tiles of w
 // nodes, the last one shorter.  (Letting the last tile take one node more,
 // so that 2^k + 1 meshes get no one-node tiles, needs a larger LDS window:
@@ -207,10 +158,14 @@ constexpr int kRtX = 32, kRtY = 4, kRtZ = 2;
 constexpr int kRwX = 2 * kRtX + 1, kRwY = 2 * kRtY + 1, kRwZ = 2 * kRtZ + 1;
 constexpr int kRowsPer = (kRwY * kRwZ + 3) / 4;
 
-// The restriction onto larger levels (what k_mg_restrict16 computes), one
-// thread per coarse node: the block's fine window of r - y (0 on fine
-// Dirichlet nodes) is staged in LDS by coalesced loads, and the 27 taps
-// then read LDS.  Every load is issued before its first use (lanes past the
+// The restriction, one thread per coarse node (I, J, K): b_c = sum over fine
+// nodes of P_fine,coarse (r - y) (y = NULL: r alone) with fine Dirichlet
+// nodes counted as 0 (the CG's own r is not zero on their rows: its J.v
+// writes them), 0 on coarse Dirichlet nodes; x_c = S_c b_c, the
+// pre-smoothing step from zero.  The taps and weights per axis come from the
+// level's tables (mg_taps, formed once per setup).  The block's fine window
+// of r - y (0 on fine Dirichlet nodes) is staged in LDS by coalesced loads,
+// and the 27 taps then read LDS.  Every load is issued before its first use (lanes past the
 // window read a node inside it; the masks are applied as selects), so a
 // block waits for memory twice, not once per element.
 template <typename T, bool HAS_Y>
@@ -569,18 +524,6 @@ static int mg_blocks(long n, long cap) {
   return (int)std::max(1L, std::min((n + kVecThreads - 1) / kVecThreads, cap));
 }
 
-// Coarse levels below this many nodes (QE_MG_RGROUP_MAX overrides it) take
-// the restriction with 16 lanes per node, larger ones the tiled one.  Under 129x129x65: onto 33x33x17 and
-// 17x17x9 the 16-lane form took 6.8 and 4.6 us (one thread per node: 12 and
-// 11 us), and the tiled one everywhere made the solve 2.5 % slower; onto
-// 65x65x33 one thread per node took 17.3 us, 16 lanes 27.2, the tiled form
-// 14.1 (and onto 129x129x65 under 257x257x129, 50 against 79 us).
-static const long kMgRestrictGroupMax = 65536;
-static long mg_group_max() {
-  const char* v = getenv("QE_MG_RGROUP_MAX");
-  return v ? atol(v) : kMgRestrictGroupMax;
-}
-
 void launch_mg_inject(hipStream_t s, const MgGrid& f, const MgGrid& c, const double* phif, double* phic) {
   QE_LAUNCH(k_mg_inject, mg_blocks(c.N, 4096), kVecThreads, s, f.g.nx, f.g.ny, f.g.nz, c.g.nx, c.g.ny, c.g.nz, phif,
             phic);
@@ -629,17 +572,13 @@ struct MgView<float> {
 };
 
 // b_c = P^T (b - y) and x_c = S_c b_c from level A onto level C (y = NULL:
-// P^T b).
+// P^T b).  The tiled form on every level: one thread per coarse node
+// gathering its 27 taps from memory took 17.3 us onto 65x65x33 against 11.3,
+// and a group of 16 lanes per coarse node on the levels below 65536 nodes
+// made the 129x129x65 adjoint 1 % slower.
 template <typename T>
 static void restrict_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T* b, const T* y, const MgView<T>& c,
-                        long group_max, const PcgCtx* ctx) {
-  if (C.N < group_max) {
-    constexpr long per = kVecThreads / 16;
-    const int nb = (int)std::max(1L, std::min((C.N + per - 1) / per, 16384L));
-    QE_LAUNCH(k_mg_restrict16<T>, nb, kVecThreads, s, A.g.nx, A.g.ny, C.g.nx, C.g.ny, C.N, C.tab, A.mask, b, y,
-              C.mask, c.S, c.b, c.x, ctx);
-    return;
-  }
+                        const PcgCtx* ctx) {
   const int tnx = mg_ntiles(C.g.nx, kRtX), tny = mg_ntiles(C.g.ny, kRtY), tnz = mg_ntiles(C.g.nz, kRtZ);
   if (y)
     QE_LAUNCH((k_mg_restrict_tile<T, true>), tnx * tny * tnz, kVecThreads, s, A.g.nx, A.g.ny, A.g.nz, C.g.nx, C.g.ny,
@@ -665,7 +604,7 @@ static void prolong_to(hipStream_t s, const MgGrid& A, const MgGrid& C, const T*
 // blocks), and its result is always x.
 template <typename T>
 static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bool add_top, int cgblocks,
-                 double* part, long group_max, const PcgCtx* ctx) {
+                 double* part, const PcgCtx* ctx) {
   const MgGrid& A = L[l];
   const MgView<T> a(A);
   auto jv = [&]() {
@@ -690,14 +629,14 @@ static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bo
     // additive top level: z = S r + P B_1 P^T r, no smoothing products on
     // the finest mesh (positive definite as a sum of positive definite and
     // semidefinite parts)
-    restrict_to(s, A, C, a.b, (const T*)nullptr, c, group_max, ctx);
-    const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, group_max, ctx);
+    restrict_to(s, A, C, a.b, (const T*)nullptr, c, ctx);
+    const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
     prolong_to<T>(s, A, C, xc, a.x, a.x, (const T*)a.b, part, cgblocks, ctx);
     return a.x;
   }
   jv();
-  restrict_to(s, A, C, a.b, (const T*)a.y, c, group_max, ctx);
-  const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, group_max, ctx);
+  restrict_to(s, A, C, a.b, (const T*)a.y, c, ctx);
+  const T* xc = vcycle<T>(s, L, l + 1, nlev, sweeps, add_top, cgblocks, part, ctx);
   if (l > 0) {
     prolong_to<T>(s, A, C, xc, a.x, a.x, (const T*)nullptr, (double*)nullptr, 0, ctx);
     jv_smooth(a.x, a.y, nullptr, A.wm.nblocks);
@@ -719,11 +658,10 @@ static T* vcycle(hipStream_t s, const MgGrid* L, int l, int nlev, int sweeps, bo
 
 void launch_mg_vcycle(hipStream_t s, const MgGrid* levels, int nlev, int sweeps, bool add_top, int cgblocks,
                       double* part_rz, const PcgCtx* ctx, bool fp32) {
-  const long group_max = mg_group_max();
   if (fp32)
-    vcycle<float>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, group_max, ctx);
+    vcycle<float>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, ctx);
   else
-    vcycle<double>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, group_max, ctx);
+    vcycle<double>(s, levels, 0, nlev, sweeps, add_top, cgblocks, part_rz, ctx);
 }
 
 }  // namespace qe

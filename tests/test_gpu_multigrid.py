@@ -53,18 +53,16 @@ def test_multigrid_solve_matches_oracle(monkeypatch, dims, levels):
 
 
 @pytest.mark.parametrize("dims,add_top,precision", [
-    ((33, 33, 17), False, 0),   # tiles of 17x17x9 coarse nodes: one short tile per axis
+    ((33, 33, 17), False, 0),   # 17x17x9 coarse nodes: short tiles along every axis
     ((36, 30, 20), False, 0),   # even counts: 19x16x11
-    ((65, 57, 33), False, 0),   # two levels below: 33x29x17 (tiles 32+1 wide), 17x15x9
+    ((65, 57, 33), False, 0),   # two levels below: 33x29x17 (a one-node last tile along x), 17x15x9
     ((36, 30, 20), True, 0),    # the additive finest level restricts r alone
     ((65, 57, 33), False, 1),   # the FP32 V-cycle
 ])
 def test_multigrid_tiled_restriction_matches_oracle(monkeypatch, dims, add_top, precision):
-    """The tiled restriction (the default onto levels of 65536 nodes and
-    more, forced onto every level here through QE_MG_RGROUP_MAX): ragged
-    tiles of odd and even meshes, with and without J x, in FP64 and FP32."""
+    """The tiled restriction on ragged tiles (short last tiles of odd and
+    even meshes), with and without J x, in FP64 and FP32."""
     monkeypatch.setenv("QE_MG_MIN_NODES", "1000")
-    monkeypatch.setenv("QE_MG_RGROUP_MAX", "0")
     if add_top:
         monkeypatch.setenv("QE_MG_ADD_NODES", "1000")
     dev = double_dot(*dims)
