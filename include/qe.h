@@ -266,7 +266,8 @@ size_t qe_workspace_bytes(const qe_problem* p, const qe_options* o);
  * coarse element takes the materials of its first fine element), that
  * problem is solved from the linear guess until ||F|| falls to a fraction
  * 1e-3 (139425 / N_coarse)^(1/3) of its initial value (a finer coarse mesh
- * is worth solving further; measured), and its potential, interpolated
+ * is worth solving further; measured; its CG runs in FP32 inside its FP64
+ * Newton, as in mixed precision), and its potential, interpolated
  * trilinearly, starts Newton here; the solution is the same (the discrete problem has one
  * solution), only the iteration counts change.  Smaller meshes, sheets,
  * eigenstates, a coarse solve that fails, or a workspace without room for
