@@ -409,7 +409,7 @@ def main():
         "config": {"workload": "double-dot Si/SiO2 stack 129x129x65 nodes (1081665 DOF), 5 gates, "
                                "Fermi-Dirac 4 K, FP64 Newton + PCG (Jacobi; multigrid V-cycle on the steps with CG "
                                "tolerance <= 3e-2) to ||F||<1e-8 from the default start (65x65x33 "
-                               "coarse-mesh sequence)",
+                               "coarse-mesh sequence, its inner CG in FP32)",
                    "global_batch": 1, "parallelism": "single GPU"},
         "newton_iters": reps[-1]["newton_iters"],
         "krylov_iters": reps[-1]["krylov_iters"],
