@@ -797,9 +797,10 @@ static size_t fine_layout_bytes(const qe_problem* p) { return layout_bytes(p, 0)
 static const long kSeqMinNodes = 250000;
 static const int kSeqLevels = 1;
 
-// The coarse solve need not be more accurate than the coarse mesh's own
-// error against the fine one, which falls with h: 1e-3 for a coarse mesh of
-// 139,425 nodes (the 129x129x65 problem's), scaled by (139425 / N_c)^(1/3).
+// The coarse solve need not be much more accurate than the coarse mesh's
+// own error against the fine one: 1e-3 for a coarse mesh of 139,425 nodes
+// (the 129x129x65 problem's), scaled by (139425 / N_c)^(1/3), the scaling
+// that fits the optima measured on the two stacks below.
 // Measured at 129x129x65: 1e-2 / 3e-3 / 1e-3 / 1e-4 gave 20.1 / 19.2 / 17.9 /
 // 18.7 ms (with the V-cycle: 3e-3 / 1e-3 / 3e-4 gave 10.6 / 9.4 / 10.5 ms);
 // at 257x257x129 (coarse 1.08M nodes), with the V-cycle, 1e-3 / 5e-4 / 2.6e-4
